@@ -1,0 +1,1047 @@
+/*
+ * FP64 CPU oracle for one coupled RW-MI-DELBM time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant generator
+ * with the HIP path: both are written independently from the paper
+ * (arXiv 2308.05007) and from the readings of it recorded in the design notes.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -fPIC -shared
+ * (no FMA contraction, no fast-math, IEEE double on x86-64 SSE2).
+ *
+ * What is computed (paper sections in brackets):
+ *   fluid    : D3Q19 BGK lattice Boltzmann (Sec. 2.3, Eq. 12-15), collide then
+ *              stream; the moving-wall term of the bounce-back rule has the
+ *              form of Eq. 23 (with C = 1).  Particles enter through the
+ *              partially saturated cell method (named in Sec. 1) with the
+ *              Noble-Torczynski weighting; a uniform body force enters by the
+ *              Guo forcing scheme.  Neither PSM's formula nor the forcing is
+ *              printed in the paper: both are readings.
+ *   particles: metaball function and gradient (Eq. 3, Eq. 17), prescribed
+ *              rigid motion (the oscillator of Sec. 4, Eq. 37 read as a
+ *              displacement sinusoid), rigid surface velocity (Sec. 2.4.3).
+ *   solute   : random-walk update (Eq. 2) with trilinear velocity
+ *              interpolation (Sec. 2.4.1), walker/particle types I-IV
+ *              (Sec. 2.4.2), binary search for the intersection (Algorithm 1),
+ *              specular reflection (Algorithm 2, Eq. 18-22), refill of type II
+ *              walkers and return-to-origin in narrow gaps (Sec. 2.4.2),
+ *              concentration as a node count (Eq. 16).
+ *   random   : Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the
+ *              seed, counter (walker, step, purpose, 0); Box-Muller normals
+ *              built from our own LN and SINCOS2PI that use only +,-,*,/,sqrt
+ *              so that any IEEE machine reproduces them bit for bit.
+ *   reports  : occupancy n_s (Eq. 16), FP64 moments feeding Eq. 38-40.
+ *
+ * Every sum is taken left to right in the order stated next to it.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXP 64
+#define ORC_NCNT 8
+
+/* ---------------------------------------------------------------- D3Q19 */
+/* Textbook D3Q19 (Qian, d'Humieres, Lallemand 1992); the paper names the
+ * model (Sec. 2.3) but prints neither the velocities nor the weights.
+ * Order: rest, the six axis directions (+x,-x,+y,-y,+z,-z), then the twelve
+ * diagonals in opposite pairs.  c_s^2 = 1/3. */
+static const int EV[19][3] = {
+    {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+    {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+    {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+static double WT[19];
+
+static int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+static void init_weights(void) {
+  WT[0] = 1.0 / 3.0;
+  for (int i = 1; i <= 6; i++) WT[i] = 1.0 / 18.0;
+  for (int i = 7; i <= 18; i++) WT[i] = 1.0 / 36.0;
+}
+
+/* e_i . v summed over x, y, z; a zero component contributes nothing. */
+static double edot(int i, const double v[3]) {
+  double s = 0.0;
+  for (int a = 0; a < 3; a++) {
+    if (EV[i][a] == 1) s = s + v[a];
+    else if (EV[i][a] == -1) s = s - v[a];
+  }
+  return s;
+}
+
+/* Eq. 13 with c_s^2 = 1/3:  w_i rho [1 + 3 eu + 4.5 eu^2 - 1.5 u.u]. */
+static double feq(int i, double rho, const double u[3]) {
+  double eu = edot(i, u);
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return (WT[i] * rho) * (((1.0 + 3.0 * eu) + 4.5 * (eu * eu)) - 1.5 * uu);
+}
+
+/* ------------------------------------------------------------ Philox */
+/* Philox4x32-10 as published: ten rounds of the 4x32 S-box
+ * (hi(M0 c0), lo(M0 c0), hi(M1 c2), lo(M1 c2)) mixed with the key, the key
+ * bumped by the Weyl constants between rounds. */
+static void philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; r++) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* (r + 1/2) 2^-32: exact in double, strictly inside (0, 1). */
+static double u01(uint32_t r) { return ((double)r + 0.5) * (1.0 / 4294967296.0); }
+
+/* Natural log of a positive normal double: u = m 2^e with m in (sqrt(1/2),
+ * sqrt(2)], ln m = 2 atanh(s) = 2s (1 + s^2/3 + s^4/5 + ...), s = (m-1)/(m+1),
+ * eleven terms (|s| < 0.1716, truncation below 1e-17), then e ln2 with ln2
+ * split in a high part with trailing zeros and a low remainder. */
+static double orc_ln(double u) {
+  uint64_t bits;
+  memcpy(&bits, &u, 8);
+  int e = (int)((bits >> 52) & 0x7ff) - 1023;
+  uint64_t mb = (bits & 0x000fffffffffffffULL) | 0x3ff0000000000000ULL;
+  double m;
+  memcpy(&m, &mb, 8);
+  if (m > 0x1.6a09e667f3bcdp+0) { /* sqrt(2) rounded */
+    m = m * 0.5;
+    e = e + 1;
+  }
+  double s = (m - 1.0) / (m + 1.0);
+  double s2 = s * s;
+  double p = 1.0 / 21.0;
+  p = p * s2 + 1.0 / 19.0;
+  p = p * s2 + 1.0 / 17.0;
+  p = p * s2 + 1.0 / 15.0;
+  p = p * s2 + 1.0 / 13.0;
+  p = p * s2 + 1.0 / 11.0;
+  p = p * s2 + 1.0 / 9.0;
+  p = p * s2 + 1.0 / 7.0;
+  p = p * s2 + 1.0 / 5.0;
+  p = p * s2 + 1.0 / 3.0;
+  double t = 2.0 * s;
+  double lnm = t + (t * s2) * p;
+  double de = (double)e;
+  return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + lnm);
+}
+
+/* Taylor polynomials of sin and cos on [0, pi/4]: degree 17 and 16. */
+static double sin_poly(double x) {
+  double x2 = x * x;
+  double p = 1.0 / 355687428096000.0;
+  p = p * x2 - 1.0 / 1307674368000.0;
+  p = p * x2 + 1.0 / 6227020800.0;
+  p = p * x2 - 1.0 / 39916800.0;
+  p = p * x2 + 1.0 / 362880.0;
+  p = p * x2 - 1.0 / 5040.0;
+  p = p * x2 + 1.0 / 120.0;
+  p = p * x2 - 1.0 / 6.0;
+  return x + (x * x2) * p;
+}
+static double cos_poly(double x) {
+  double x2 = x * x;
+  double p = 1.0 / 20922789888000.0;
+  p = p * x2 - 1.0 / 87178291200.0;
+  p = p * x2 + 1.0 / 479001600.0;
+  p = p * x2 - 1.0 / 3628800.0;
+  p = p * x2 + 1.0 / 40320.0;
+  p = p * x2 - 1.0 / 720.0;
+  p = p * x2 + 1.0 / 24.0;
+  p = p * x2 - 1.0 / 2.0;
+  return 1.0 + x2 * p;
+}
+
+/* sin(2 pi u), cos(2 pi u) for u in [0, 1): exact quadrant split q = floor(4u),
+ * f = 4u - q; reduce to [0, pi/4] by f -> 1 - f (both exact), then rotate by
+ * q quarter turns. */
+static void sincos2pi(double u, double* s, double* c) {
+  double t4 = 4.0 * u;
+  double qd = floor(t4);
+  double f = t4 - qd;
+  int q = (int)qd & 3;
+  double s0, c0;
+  if (f <= 0.5) {
+    double x = f * 0x1.921fb54442d18p+0; /* pi/2 */
+    s0 = sin_poly(x);
+    c0 = cos_poly(x);
+  } else {
+    double x = (1.0 - f) * 0x1.921fb54442d18p+0;
+    s0 = cos_poly(x);
+    c0 = sin_poly(x);
+  }
+  switch (q) {
+    case 0: *s = s0; *c = c0; break;
+    case 1: *s = c0; *c = -s0; break;
+    case 2: *s = -s0; *c = -c0; break;
+    default: *s = -c0; *c = s0; break;
+  }
+}
+
+/* Box-Muller on the four words of one Philox block: z0, z1 from (r0, r1),
+ * z2 from (r2, r3).  The paper asks only for zero-mean unit-variance
+ * Gaussian z (Eq. 2). */
+static void normals3(const uint32_t r[4], double z[3]) {
+  double R0 = sqrt(-2.0 * orc_ln(u01(r[0])));
+  double s, c;
+  sincos2pi(u01(r[1]), &s, &c);
+  z[0] = R0 * c;
+  z[1] = R0 * s;
+  double R2 = sqrt(-2.0 * orc_ln(u01(r[2])));
+  sincos2pi(u01(r[3]), &s, &c);
+  z[2] = R2 * c;
+}
+
+/* ----------------------------------------------------------- domain */
+typedef struct {
+  int nc;
+  double* b; /* 3*nc offsets of the control points from the centre (world frame) */
+  double* k; /* nc positive weights */
+  double c0[3];
+  int motion; /* 0 static, 1 sinusoid, 2 constant velocity */
+  double amp[3], period, phase, vel[3];
+  double rb;    /* bounding radius: M <= 1 beyond it */
+  double cutsq; /* (rb + 2)^2: support of the solid fraction */
+} OPart;
+
+typedef struct {
+  int n[3];
+  int bc[3];           /* 0 periodic, 1 wall pair */
+  double wu[3][2][3];  /* velocity of the lo / hi wall of each wall axis */
+  double tau, F[3], D, rho0, u0[3], sD;
+  uint32_t key[2];
+  int64_t N;
+  double *f, *fs;                   /* [19][N] pre-collision, post-collision */
+  double *rho, *u, *eps, *us;       /* rho[N], u[3][N], eps[N], us[3][N] */
+  unsigned char* wall;              /* 1 on wall nodes */
+  double* wallu;                    /* [3][N] wall velocity on wall nodes */
+  OPart P[ORC_MAXP];
+  int np;
+  int64_t nw;
+  int32_t *cell, *img; /* cell index; image counts [3][nw] */
+  double* off;         /* [3][nw] offsets in [0,1) */
+  double ref[3];
+  int64_t t;
+  uint64_t cnt[ORC_NCNT];
+  int max_bisect;
+  int seeded;
+} orc_domain;
+
+enum { C_TYPE2 = 0, C_TYPE4, C_BISECT_FAIL, C_REFILL_FALLBACK, C_RETURNED, C_WALL_REFLECT };
+
+static int64_t nidx(const orc_domain* d, int x, int y, int z) {
+  return (int64_t)x + (int64_t)d->n[0] * ((int64_t)y + (int64_t)d->n[1] * (int64_t)z);
+}
+
+orc_domain* orc_create(const int n[3], const int bc[3], const double wall_lo[9],
+                       const double wall_hi[9], double tau, const double F[3], double D,
+                       double rho0, const double u0[3], uint64_t seed) {
+  init_weights();
+  orc_domain* d = (orc_domain*)calloc(1, sizeof(orc_domain));
+  for (int a = 0; a < 3; a++) {
+    d->n[a] = n[a];
+    d->bc[a] = bc[a];
+    for (int c = 0; c < 3; c++) {
+      d->wu[a][0][c] = wall_lo[3 * a + c];
+      d->wu[a][1][c] = wall_hi[3 * a + c];
+    }
+    d->F[a] = F[a];
+    d->u0[a] = u0[a];
+  }
+  d->tau = tau;
+  d->D = D;
+  d->sD = sqrt(2.0 * D);
+  d->rho0 = rho0;
+  d->key[0] = (uint32_t)seed;
+  d->key[1] = (uint32_t)(seed >> 32);
+  d->max_bisect = 200;
+  d->N = (int64_t)n[0] * n[1] * n[2];
+  int64_t N = d->N;
+  d->f = (double*)malloc(sizeof(double) * 19 * N);
+  d->fs = (double*)malloc(sizeof(double) * 19 * N);
+  d->rho = (double*)malloc(sizeof(double) * N);
+  d->u = (double*)malloc(sizeof(double) * 3 * N);
+  d->eps = (double*)calloc(N, sizeof(double));
+  d->us = (double*)calloc(3 * N, sizeof(double));
+  d->wall = (unsigned char*)calloc(N, 1);
+  d->wallu = (double*)calloc(3 * N, sizeof(double));
+  for (int z = 0; z < n[2]; z++)
+    for (int y = 0; y < n[1]; y++)
+      for (int x = 0; x < n[0]; x++) {
+        int64_t id = nidx(d, x, y, z);
+        int co[3] = {x, y, z};
+        for (int a = 0; a < 3 && !d->wall[id]; a++) {
+          if (!bc[a]) continue;
+          int side = co[a] == 0 ? 0 : (co[a] == n[a] - 1 ? 1 : -1);
+          if (side < 0) continue;
+          d->wall[id] = 1;
+          for (int c = 0; c < 3; c++) d->wallu[c * N + id] = d->wu[a][side][c];
+        }
+        for (int i = 0; i < 19; i++) d->f[i * N + id] = feq(i, rho0, u0);
+        d->rho[id] = rho0;
+        for (int c = 0; c < 3; c++)
+          d->u[c * N + id] = d->wall[id] ? d->wallu[c * N + id] : u0[c];
+      }
+  return d;
+}
+
+void orc_destroy(orc_domain* d) {
+  if (!d) return;
+  free(d->f); free(d->fs); free(d->rho); free(d->u); free(d->eps); free(d->us);
+  free(d->wall); free(d->wallu);
+  for (int p = 0; p < d->np; p++) { free(d->P[p].b); free(d->P[p].k); }
+  free(d->cell); free(d->img); free(d->off);
+  free(d);
+}
+
+void orc_set_max_bisect(orc_domain* d, int m) { d->max_bisect = m; }
+
+/* Bounding radius: with K = sum k_i and R_b = max |b_i| + sqrt(K), every
+ * control point is at least sqrt(K) away from any x with |x - c| >= R_b, so
+ * M(x) <= sum k_i / K = 1 there. */
+int orc_add_particle(orc_domain* d, int nc, const double* b, const double* k,
+                     const double c0[3], int motion, const double amp[3], double period,
+                     double phase, const double vel[3]) {
+  if (d->np >= ORC_MAXP || nc < 1) return -1;
+  OPart* p = &d->P[d->np];
+  p->nc = nc;
+  p->b = (double*)malloc(sizeof(double) * 3 * nc);
+  p->k = (double*)malloc(sizeof(double) * nc);
+  memcpy(p->b, b, sizeof(double) * 3 * nc);
+  memcpy(p->k, k, sizeof(double) * nc);
+  double K = 0.0, bmax = 0.0;
+  for (int i = 0; i < nc; i++) {
+    K = K + k[i];
+    double r = sqrt(b[3 * i] * b[3 * i] + b[3 * i + 1] * b[3 * i + 1] + b[3 * i + 2] * b[3 * i + 2]);
+    if (r > bmax) bmax = r;
+  }
+  p->rb = bmax + sqrt(K);
+  p->cutsq = (p->rb + 2.0) * (p->rb + 2.0);
+  for (int a = 0; a < 3; a++) {
+    p->c0[a] = c0[a];
+    p->amp[a] = amp ? amp[a] : 0.0;
+    p->vel[a] = vel ? vel[a] : 0.0;
+  }
+  p->motion = motion;
+  p->period = period;
+  p->phase = phase;
+  return d->np++;
+}
+
+/* Prescribed rigid motion.  Sinusoid: c(t) = c0 + A sin(2 pi (t/T + phase)),
+ * v(t) = A (2 pi / T) cos(...), phase in cycles; constant velocity:
+ * c(t) = c0 + v t.  Orientation is fixed (no rotation), so the rigid surface
+ * velocity v_p + w x (x - x_p) of Sec. 2.4.3 reduces to v_p. */
+static void pose(const OPart* p, int64_t t, double c[3], double v[3]) {
+  if (p->motion == 1) {
+    double ph = (double)t / p->period + p->phase;
+    ph = ph - floor(ph);
+    double s, co;
+    sincos2pi(ph, &s, &co);
+    double w = 0x1.921fb54442d18p+2 / p->period; /* 2 pi / T */
+    for (int a = 0; a < 3; a++) {
+      c[a] = p->c0[a] + p->amp[a] * s;
+      v[a] = (p->amp[a] * w) * co;
+    }
+  } else if (p->motion == 2) {
+    for (int a = 0; a < 3; a++) {
+      c[a] = p->c0[a] + p->vel[a] * (double)t;
+      v[a] = p->vel[a];
+    }
+  } else {
+    for (int a = 0; a < 3; a++) { c[a] = p->c0[a]; v[a] = 0.0; }
+  }
+}
+
+typedef struct { double c[ORC_MAXP][3], v[ORC_MAXP][3]; } Poses;
+
+static void all_poses(const orc_domain* d, int64_t t, Poses* P) {
+  for (int p = 0; p < d->np; p++) pose(&d->P[p], t, P->c[p], P->v[p]);
+}
+
+/* Displacement from a particle centre to the point (cell + x) along axis a,
+ * minimum image on periodic axes. */
+static double rel(const orc_domain* d, int a, int cell_a, double cp, double x) {
+  double r = ((double)cell_a - cp) + x;
+  if (!d->bc[a]) {
+    double L = (double)d->n[a];
+    r = r - L * floor(r / L + 0.5);
+  }
+  return r;
+}
+
+/* Eq. 3: M = sum_i k_i / |x - x_i|^2, in control-point order. */
+static double mb_M(const OPart* p, const double dl[3]) {
+  double M = 0.0;
+  for (int i = 0; i < p->nc; i++) {
+    double rx = dl[0] - p->b[3 * i], ry = dl[1] - p->b[3 * i + 1], rz = dl[2] - p->b[3 * i + 2];
+    double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 == 0.0) return INFINITY;
+    M = M + p->k[i] / r2;
+  }
+  return M;
+}
+
+/* Eq. 17: grad M = sum_i -2 k_i (x - x_i) / |x - x_i|^4. */
+static void mb_grad(const OPart* p, const double dl[3], double g[3]) {
+  g[0] = g[1] = g[2] = 0.0;
+  for (int i = 0; i < p->nc; i++) {
+    double r[3] = {dl[0] - p->b[3 * i], dl[1] - p->b[3 * i + 1], dl[2] - p->b[3 * i + 2]};
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double q = (-2.0 * p->k[i]) / (r2 * r2);
+    for (int a = 0; a < 3; a++) g[a] = g[a] + q * r[a];
+  }
+}
+
+static void delta_to(const orc_domain* d, const Poses* P, int p, const int cell[3],
+                     const double x[3], double dl[3]) {
+  for (int a = 0; a < 3; a++) dl[a] = rel(d, a, cell[a], P->c[p][a], x[a]);
+}
+
+static double M_at(const orc_domain* d, const Poses* P, int p, const int cell[3], const double x[3]) {
+  double dl[3];
+  delta_to(d, P, p, cell, x, dl);
+  return mb_M(&d->P[p], dl);
+}
+
+/* Inside a particle <=> its own M >= 1 (each particle has its own function);
+ * returns the lowest such particle index, or -1. */
+static int inside_any(const orc_domain* d, const Poses* P, const int cell[3], const double x[3]) {
+  for (int p = 0; p < d->np; p++)
+    if (M_at(d, P, p, cell, x) >= 1.0) return p;
+  return -1;
+}
+
+/* Solid fraction of one particle at a node: 1/2 + d clamped to [0,1], with d
+ * the signed distance (positive inside) to the surface estimated from the
+ * field M^(-1/2), whose level 1 is the surface:
+ *   d = (1 - M^(-1/2)) / |grad M^(-1/2)| = 2 M (sqrt(M) - 1) / |grad M|.
+ * Near the surface this is the first-order estimate (M - 1)/|grad M|; for a
+ * single control point it is the exact distance sqrt(k) - r.  Zero outside
+ * the support |x - c| > R_b + 2. */
+static double eps_one(const orc_domain* d, const Poses* P, int p, const int nd[3]) {
+  const OPart* q = &d->P[p];
+  double dl[3];
+  for (int a = 0; a < 3; a++) dl[a] = rel(d, a, nd[a], P->c[p][a], 0.5);
+  double r2c = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+  if (r2c > q->cutsq) return 0.0;
+  double M = mb_M(q, dl);
+  if (M == INFINITY) return 1.0;
+  double g[3];
+  mb_grad(q, dl, g);
+  double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  double e;
+  if (gn == 0.0) {
+    e = M >= 1.0 ? 1.0 : 0.0;
+  } else {
+    double dist = ((2.0 * M) * (sqrt(M) - 1.0)) / gn;
+    e = dist == dist ? 0.5 + dist : (M >= 1.0 ? 1.0 : 0.0);
+  }
+  if (e < 0.0) e = 0.0;
+  if (e > 1.0) e = 1.0;
+  return e;
+}
+
+/* ------------------------------------------------------------ fluid */
+/* Collision at one node (pre-collision f[19] in, post-collision out[19]).
+ * rho = sum f_i, j = sum f_i e_i (Eq. 14-15), u = (j + F/2)/rho (Guo).
+ * B = eps (tau - 1/2) / ((1 - eps) + (tau - 1/2));
+ * Om_i = [f_opp - feq_opp(rho,u)] - [f_i - feq_i(rho,us)];
+ * S_i = w_i [3 (e_i - u).F + 9 (e_i.u)(e_i.F)];
+ * f*_i = f_i - (1-B)/tau (f_i - feq_i(rho,u)) + B Om_i + (1-B)(1 - 1/(2 tau)) S_i. */
+static void collide_node(const orc_domain* d, const double f[19], double eps, const double us[3],
+                         double out[19], double* rho_out, double u_out[3]) {
+  double rho = 0.0;
+  for (int i = 0; i < 19; i++) rho = rho + f[i];
+  double j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 19; i++)
+    for (int a = 0; a < 3; a++) {
+      if (EV[i][a] == 1) j[a] = j[a] + f[i];
+      else if (EV[i][a] == -1) j[a] = j[a] - f[i];
+    }
+  double u[3];
+  for (int a = 0; a < 3; a++) u[a] = (j[a] + 0.5 * d->F[a]) / rho;
+  double omega = 1.0 / d->tau;
+  double tm = d->tau - 0.5;
+  double B = (eps * tm) / ((1.0 - eps) + tm);
+  double A = (1.0 - B) * omega;
+  double Cf = (1.0 - B) * (1.0 - 0.5 * omega);
+  double fe[19], fes[19];
+  for (int i = 0; i < 19; i++) {
+    fe[i] = feq(i, rho, u);
+    fes[i] = feq(i, rho, us);
+  }
+  for (int i = 0; i < 19; i++) {
+    int o = opp(i);
+    double Om = (f[o] - fe[o]) - (f[i] - fes[i]);
+    double eu = edot(i, u);
+    double eF = edot(i, d->F);
+    double emF = 0.0;
+    for (int a = 0; a < 3; a++) emF = emF + ((double)EV[i][a] - u[a]) * d->F[a];
+    double S = WT[i] * (3.0 * emF + (9.0 * eu) * eF);
+    out[i] = ((f[i] - A * (f[i] - fe[i])) + B * Om) + Cf * S;
+  }
+  *rho_out = rho;
+  for (int a = 0; a < 3; a++) u_out[a] = u[a];
+}
+
+static void fluid_step(orc_domain* d, const Poses* Pt) {
+  const int64_t N = d->N;
+  const int nx = d->n[0], ny = d->n[1], nz = d->n[2];
+#pragma omp parallel for schedule(static)
+  for (int64_t id = 0; id < N; id++) {
+    if (d->wall[id]) continue;
+    int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
+    /* solid fraction and solid velocity: eps = min(1, sum eps_p),
+     * us = sum eps_p v_p / sum eps_p (particle order) */
+    double es = 0.0, un[3] = {0.0, 0.0, 0.0};
+    for (int p = 0; p < d->np; p++) {
+      double e = eps_one(d, Pt, p, nd);
+      es = es + e;
+      for (int a = 0; a < 3; a++) un[a] = un[a] + e * Pt->v[p][a];
+    }
+    double eps = es < 1.0 ? es : 1.0;
+    double us[3];
+    for (int a = 0; a < 3; a++) us[a] = es > 0.0 ? un[a] / es : 0.0;
+    double f[19], out[19], rho, u[3];
+    for (int i = 0; i < 19; i++) f[i] = d->f[i * N + id];
+    collide_node(d, f, eps, us, out, &rho, u);
+    for (int i = 0; i < 19; i++) d->fs[i * N + id] = out[i];
+    d->rho[id] = rho;
+    d->eps[id] = eps;
+    for (int a = 0; a < 3; a++) {
+      d->u[a * N + id] = u[a];
+      d->us[a * N + id] = us[a];
+    }
+  }
+  /* streaming: f_i(x, t+1) = f*_i(x - e_i); from a wall node the population
+   * is the bounced one, f*_opp(i)(x) + 6 w_i rho(x) (e_i . u_w) (Eq. 23 form) */
+#pragma omp parallel for schedule(static)
+  for (int64_t id = 0; id < N; id++) {
+    if (d->wall[id]) continue;
+    int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
+    for (int i = 0; i < 19; i++) {
+      int s[3];
+      for (int a = 0; a < 3; a++) {
+        s[a] = nd[a] - EV[i][a];
+        if (s[a] < 0) s[a] += d->n[a];
+        if (s[a] >= d->n[a]) s[a] -= d->n[a];
+      }
+      int64_t sid = nidx(d, s[0], s[1], s[2]);
+      (void)nz;
+      if (d->wall[sid]) {
+        double uw[3] = {d->wallu[sid], d->wallu[N + sid], d->wallu[2 * N + sid]};
+        double term = ((6.0 * WT[i]) * d->rho[id]) * edot(i, uw);
+        d->f[i * N + id] = d->fs[opp(i) * N + id] + term;
+      } else {
+        d->f[i * N + id] = d->fs[i * N + sid];
+      }
+    }
+  }
+}
+
+/* ----------------------------------------------------------- walkers */
+/* Algorithm 1 on the straight segment x(s) = a + s dir, s from s_out (M<1)
+ * to s_in (M>=1): midpoint in s, stop when |M - 1| < 1e-3, at most imax
+ * evaluations.  Returns 1 and the converged s on success. */
+static int bisect(const orc_domain* d, const Poses* P, int p, const int cell[3], const double a0[3],
+                  const double dir[3], double s_out, double s_in, int imax, double* s_res) {
+  for (int it = 1; it <= imax; it++) {
+    double sm = 0.5 * (s_out + s_in);
+    double x[3];
+    for (int a = 0; a < 3; a++) x[a] = a0[a] + sm * dir[a];
+    double m = M_at(d, P, p, cell, x);
+    if (fabs(m - 1.0) < 1e-3) {
+      *s_res = sm;
+      return 1;
+    }
+    if (m < 1.0) s_out = sm;
+    else s_in = sm;
+  }
+  return 0;
+}
+
+static double prev_double(double x) { /* x > 0 */
+  uint64_t b;
+  memcpy(&b, &x, 8);
+  b -= 1;
+  memcpy(&x, &b, 8);
+  return x;
+}
+
+typedef struct { uint64_t c[ORC_NCNT]; } Cnt;
+
+/* One walker, one step.  cell/x are the walker's cell and offset (updated in
+ * place, with image counts), u(t) is the fluid velocity of this step, Pn the
+ * particle poses at t+1. */
+static void walker_step(const orc_domain* d, const Poses* Pn, int64_t w, int cell[3], double o[3],
+                        int img[3], Cnt* cn) {
+  const int64_t N = d->N;
+  const int* n = d->n;
+  /* 1. trilinear interpolation between node centres, x then y then z */
+  int b0[3], b1[3];
+  double wt[3];
+  for (int a = 0; a < 3; a++) {
+    int b;
+    if (o[a] >= 0.5) { b = cell[a]; wt[a] = o[a] - 0.5; }
+    else { b = cell[a] - 1; wt[a] = o[a] + 0.5; }
+    int c1 = b + 1;
+    if (b < 0) b += n[a];
+    if (c1 >= n[a]) c1 -= n[a];
+    b0[a] = b;
+    b1[a] = c1;
+  }
+  double U[3];
+  for (int c = 0; c < 3; c++) {
+    const double* uc = d->u + c * N;
+    double v[2][2];
+    for (int zz = 0; zz < 2; zz++)
+      for (int yy = 0; yy < 2; yy++) {
+        int y = yy ? b1[1] : b0[1], z = zz ? b1[2] : b0[2];
+        double lo = uc[nidx(d, b0[0], y, z)], hi = uc[nidx(d, b1[0], y, z)];
+        v[zz][yy] = (1.0 - wt[0]) * lo + wt[0] * hi;
+      }
+    double v0 = (1.0 - wt[1]) * v[0][0] + wt[1] * v[0][1];
+    double v1 = (1.0 - wt[1]) * v[1][0] + wt[1] * v[1][1];
+    U[c] = (1.0 - wt[2]) * v0 + wt[2] * v1;
+  }
+  /* 2-3. Eq. 2 with dt = 1: x_f = x_p + u + z sqrt(2D) */
+  uint32_t ctr[4] = {(uint32_t)w, (uint32_t)d->t, 0u, 0u}, r[4];
+  philox(ctr, d->key, r);
+  double z[3], dl[3], xf[3];
+  normals3(r, z);
+  for (int a = 0; a < 3; a++) {
+    dl[a] = U[a] + z[a] * d->sD;
+    xf[a] = o[a] + dl[a];
+  }
+  /* 4. walker/particle relation at the next pose (types I-IV) */
+  double xn[3];
+  for (int a = 0; a < 3; a++) xn[a] = xf[a];
+  int jb = inside_any(d, Pn, cell, xf);
+  if (jb >= 0) {
+    int ja = inside_any(d, Pn, cell, o);
+    if (ja < 0) {
+      /* type IV: no-flux, Algorithm 1 then Algorithm 2 */
+      cn->c[C_TYPE4]++;
+      double s;
+      int ok = bisect(d, Pn, jb, cell, o, dl, 0.0, 1.0, d->max_bisect, &s);
+      int done = 0;
+      if (ok) {
+        double xi[3], dv[3], g[3];
+        for (int a = 0; a < 3; a++) xi[a] = o[a] + s * dl[a];
+        delta_to(d, Pn, jb, cell, xi, dv);
+        mb_grad(&d->P[jb], dv, g);
+        double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        if (gn > 0.0) {
+          double nv[3], ti[3];
+          for (int a = 0; a < 3; a++) {
+            nv[a] = g[a] / gn;
+            ti[a] = xf[a] - xi[a];
+          }
+          double dt = ti[0] * nv[0] + ti[1] * nv[1] + ti[2] * nv[2];
+          for (int a = 0; a < 3; a++) xn[a] = xi[a] + (ti[a] - (2.0 * dt) * nv[a]);
+          if (inside_any(d, Pn, cell, xn) >= 0) {
+            cn->c[C_RETURNED]++;
+            for (int a = 0; a < 3; a++) xn[a] = o[a];
+          }
+          done = 1;
+        }
+      }
+      if (!done) {
+        cn->c[C_BISECT_FAIL]++;
+        for (int a = 0; a < 3; a++) xn[a] = o[a];
+      }
+    } else {
+      /* type II: refill -- push out along -grad M, place at random within
+       * the sqrt(2D) half-ball outside the surface */
+      cn->c[C_TYPE2]++;
+      double dv[3], g[3];
+      delta_to(d, Pn, jb, cell, xf, dv);
+      mb_grad(&d->P[jb], dv, g);
+      double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+      int fallback = 1;
+      if (gn > 0.0) {
+        double no[3];
+        for (int a = 0; a < 3; a++) no[a] = (-g[a]) / gn;
+        double s = 0.5, lim = 2.0 * d->P[jb].rb;
+        double xe[3];
+        for (;;) {
+          for (int a = 0; a < 3; a++) xe[a] = xf[a] + s * no[a];
+          if (!(M_at(d, Pn, jb, cell, xe) >= 1.0) || !(s < lim)) break;
+          s = 2.0 * s;
+        }
+        if (M_at(d, Pn, jb, cell, xe) < 1.0) {
+          double ss;
+          int ok = bisect(d, Pn, jb, cell, xf, no, s, 0.0, d->max_bisect, &ss);
+          double xs[3];
+          if (ok) {
+            for (int a = 0; a < 3; a++) xs[a] = xf[a] + ss * no[a];
+            uint32_t c1[4] = {(uint32_t)w, (uint32_t)d->t, 1u, 0u}, r1[4];
+            uint32_t c2[4] = {(uint32_t)w, (uint32_t)d->t, 2u, 0u}, r2[4];
+            philox(c1, d->key, r1);
+            philox(c2, d->key, r2);
+            double v[3];
+            normals3(r1, v);
+            double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            for (int a = 0; a < 3; a++) v[a] = v[a] / vn;
+            if (v[0] * no[0] + v[1] * no[1] + v[2] * no[2] < 0.0)
+              for (int a = 0; a < 3; a++) v[a] = -v[a];
+            double mx = u01(r2[0]);
+            if (u01(r2[1]) > mx) mx = u01(r2[1]);
+            if (u01(r2[2]) > mx) mx = u01(r2[2]);
+            double rr = d->sD * mx;
+            for (int a = 0; a < 3; a++) xn[a] = xs[a] + rr * v[a];
+          } else {
+            cn->c[C_BISECT_FAIL]++;
+            for (int a = 0; a < 3; a++) xn[a] = xe[a];
+          }
+          int bad = inside_any(d, Pn, cell, xn) >= 0;
+          for (int a = 0; a < 3 && !bad; a++) {
+            if (!d->bc[a]) continue;
+            double lo = 1.0 - (double)cell[a], hi = (double)(n[a] - 1) - (double)cell[a];
+            if (xn[a] < lo || xn[a] >= hi) bad = 1;
+          }
+          if (bad)
+            for (int a = 0; a < 3; a++) xn[a] = xe[a];
+          fallback = inside_any(d, Pn, cell, xn) >= 0;
+        }
+      }
+      if (fallback) {
+        cn->c[C_REFILL_FALLBACK]++;
+        for (int a = 0; a < 3; a++) xn[a] = xf[a];
+      }
+    }
+  }
+  /* 5. walls: halfway planes at 1 and n-1 on wall axes, one specular
+   * reflection per axis; a reflected point inside a particle returns the
+   * walker to where it started (narrow gaps) */
+  int refl = 0;
+  for (int a = 0; a < 3; a++) {
+    if (!d->bc[a]) continue;
+    double lo = 1.0 - (double)cell[a], hi = (double)(n[a] - 1) - (double)cell[a];
+    if (xn[a] < lo) {
+      xn[a] = 2.0 * lo - xn[a];
+      refl = 1;
+    } else if (xn[a] >= hi) {
+      xn[a] = 2.0 * hi - xn[a];
+      if (xn[a] == hi) xn[a] = prev_double(hi);
+      refl = 1;
+    }
+  }
+  if (refl) {
+    cn->c[C_WALL_REFLECT]++;
+    if (inside_any(d, Pn, cell, xn) >= 0) {
+      cn->c[C_RETURNED]++;
+      for (int a = 0; a < 3; a++) xn[a] = o[a];
+    }
+  }
+  /* 6. back to (cell, offset in [0,1)), periodic wrap with image counts */
+  for (int a = 0; a < 3; a++) {
+    double k = floor(xn[a]);
+    double of = xn[a] - k;
+    if (of == 1.0) {
+      of = 0.0;
+      k = k + 1.0;
+    }
+    int c = cell[a] + (int)k;
+    if (!d->bc[a]) {
+      if (c < 0) { c += n[a]; img[a] -= 1; }
+      else if (c >= n[a]) { c -= n[a]; img[a] += 1; }
+    }
+    cell[a] = c;
+    o[a] = of;
+  }
+}
+
+static void walkers_step(orc_domain* d, const Poses* Pn) {
+  const int64_t nw = d->nw;
+  const int nx = d->n[0], ny = d->n[1];
+  uint64_t tot[ORC_NCNT] = {0};
+#pragma omp parallel
+  {
+    Cnt cn;
+    memset(&cn, 0, sizeof(cn));
+#pragma omp for schedule(static)
+    for (int64_t w = 0; w < nw; w++) {
+      int32_t lc = d->cell[w];
+      int cell[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
+      double o[3] = {d->off[w], d->off[nw + w], d->off[2 * nw + w]};
+      int img[3] = {d->img[w], d->img[nw + w], d->img[2 * nw + w]};
+      walker_step(d, Pn, w, cell, o, img, &cn);
+      d->cell[w] = (int32_t)nidx(d, cell[0], cell[1], cell[2]);
+      for (int a = 0; a < 3; a++) {
+        d->off[a * nw + w] = o[a];
+        d->img[a * nw + w] = img[a];
+      }
+    }
+#pragma omp critical
+    for (int c = 0; c < ORC_NCNT; c++) tot[c] += cn.c[c];
+  }
+  for (int c = 0; c < ORC_NCNT; c++) d->cnt[c] += tot[c];
+}
+
+/* One coupled step t -> t+1: fluid at P(t), walkers with u(t) against P(t+1). */
+void orc_step(orc_domain* d, int nsteps) {
+  for (int s = 0; s < nsteps; s++) {
+    Poses Pt, Pn;
+    all_poses(d, d->t, &Pt);
+    all_poses(d, d->t + 1, &Pn);
+    fluid_step(d, &Pt);
+    if (d->nw) walkers_step(d, &Pn);
+    d->t++;
+  }
+}
+
+/* ----------------------------------------------------------- seeding */
+/* kind 0 uniform over the fluid box, 1 Gaussian (centre, sigma), 2 band along
+ * one axis, 3 explicit positions.  Attempt a of walker w draws Philox counter
+ * (w, 0xFFFFFFFF, 16 + a, 0); positions inside a particle at P(0) or outside
+ * the fluid range of a wall axis are rejected and redrawn.  remove_inside = 1
+ * instead drops such walkers after one draw (the paper's removal at the first
+ * step) and renumbers the survivors in order.  Returns the number placed, or
+ * -1 if a walker exhausted its attempts. */
+int64_t orc_seed(orc_domain* d, int kind, const double centre[3], double sigma, int band_axis,
+                 double band_lo, double band_hi, const double* xyz, int64_t n, int max_attempts,
+                 int remove_inside, const double ref[3]) {
+  Poses P0;
+  all_poses(d, 0, &P0);
+  free(d->cell); free(d->off); free(d->img);
+  d->cell = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+  d->off = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+  d->img = (int32_t*)calloc(3 * (n > 0 ? n : 1), sizeof(int32_t));
+  double* tmp = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+  int32_t* tcell = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+  unsigned char* okv = (unsigned char*)calloc(n > 0 ? n : 1, 1);
+  int attempts = remove_inside ? 1 : max_attempts;
+  if (kind == 3) attempts = 1;
+  int fail = 0;
+#pragma omp parallel for schedule(static) reduction(| : fail)
+  for (int64_t w = 0; w < n; w++) {
+    int placed = 0;
+    for (int at = 0; at < attempts && !placed; at++) {
+      double X[3];
+      if (kind == 3) {
+        for (int a = 0; a < 3; a++) X[a] = xyz[3 * w + a];
+      } else {
+        uint32_t ctr[4] = {(uint32_t)w, 0xFFFFFFFFu, 16u + (uint32_t)at, 0u}, r[4];
+        philox(ctr, d->key, r);
+        if (kind == 1) {
+          double z[3];
+          normals3(r, z);
+          for (int a = 0; a < 3; a++) X[a] = centre[a] + sigma * z[a];
+        } else {
+          for (int a = 0; a < 3; a++) {
+            double lo = d->bc[a] ? 1.0 : 0.0, hi = d->bc[a] ? (double)(d->n[a] - 1) : (double)d->n[a];
+            if (kind == 2 && a == band_axis) { lo = band_lo; hi = band_hi; }
+            X[a] = lo + u01(r[a]) * (hi - lo);
+          }
+        }
+      }
+      int cell[3], okp = 1;
+      double o[3];
+      for (int a = 0; a < 3; a++) {
+        double L = (double)d->n[a];
+        double x = X[a];
+        if (!d->bc[a]) {
+          x = x - L * floor(x / L);
+          if (x >= L) x = 0.0;
+        } else if (x < 1.0 || x >= L - 1.0) {
+          okp = 0;
+        }
+        double k = floor(x);
+        cell[a] = (int)k;
+        o[a] = x - k;
+      }
+      if (!okp) continue;
+      if (inside_any(d, &P0, cell, o) >= 0) continue;
+      tcell[w] = (int32_t)nidx(d, cell[0], cell[1], cell[2]);
+      for (int a = 0; a < 3; a++) tmp[3 * w + a] = o[a];
+      placed = 1;
+    }
+    okv[w] = (unsigned char)placed;
+    if (!placed && !remove_inside) fail = 1;
+  }
+  int64_t m = 0;
+  for (int64_t w = 0; w < n; w++) {
+    if (!okv[w]) continue;
+    d->cell[m] = tcell[w];
+    m++;
+  }
+  /* offsets in SoA order */
+  double* off = d->off;
+  int64_t k = 0;
+  for (int64_t w = 0; w < n; w++) {
+    if (!okv[w]) continue;
+    for (int a = 0; a < 3; a++) off[a * m + k] = tmp[3 * w + a];
+    k++;
+  }
+  free(tmp); free(tcell); free(okv);
+  d->nw = m;
+  for (int a = 0; a < 3; a++) d->ref[a] = ref[a];
+  d->seeded = 1;
+  if (fail) return -1;
+  return m;
+}
+
+/* ----------------------------------------------------------- reports */
+/* Eq. 16: n_s = number of walkers whose cell is the node. */
+void orc_occupancy(const orc_domain* d, uint32_t* ns) {
+  memset(ns, 0, sizeof(uint32_t) * d->N);
+  for (int64_t w = 0; w < d->nw; w++) ns[d->cell[w]]++;
+}
+
+/* Moments (sequential sums in index order):
+ * out[0]   walker count
+ * out[1-3] sum (X - ref), X unwrapped with image counts
+ * out[4-6] sum (X - ref)^2
+ * out[7]   sum rho over fluid nodes       out[8-10] sum rho u over fluid nodes
+ * out[11-13] sum (1-eps) u / sum (1-eps)  (fluid-volume average)
+ * out[14-16] sum eps us / sum eps         (particle-volume average; 0 if none)
+ * out[17]  sum eps                        out[18] step */
+void orc_moments(const orc_domain* d, double* out) {
+  const int64_t N = d->N, nw = d->nw;
+  const int nx = d->n[0], ny = d->n[1];
+  memset(out, 0, sizeof(double) * 19);
+  out[0] = (double)nw;
+  for (int64_t w = 0; w < nw; w++) {
+    int32_t lc = d->cell[w];
+    int cell[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
+    for (int a = 0; a < 3; a++) {
+      int64_t X = (int64_t)cell[a] + (int64_t)d->img[a * nw + w] * (int64_t)d->n[a];
+      double dv = ((double)X - d->ref[a]) + d->off[a * nw + w];
+      out[1 + a] = out[1 + a] + dv;
+      out[4 + a] = out[4 + a] + dv * dv;
+    }
+  }
+  double s1e = 0.0, se = 0.0, fu[3] = {0, 0, 0}, pv[3] = {0, 0, 0};
+  for (int64_t id = 0; id < N; id++) {
+    if (d->wall[id]) continue;
+    double r = d->rho[id], e = d->eps[id];
+    out[7] = out[7] + r;
+    for (int a = 0; a < 3; a++) {
+      double ua = d->u[a * N + id];
+      out[8 + a] = out[8 + a] + r * ua;
+      fu[a] = fu[a] + (1.0 - e) * ua;
+      pv[a] = pv[a] + e * d->us[a * N + id];
+    }
+    s1e = s1e + (1.0 - e);
+    se = se + e;
+  }
+  for (int a = 0; a < 3; a++) {
+    out[11 + a] = s1e > 0.0 ? fu[a] / s1e : 0.0;
+    out[14 + a] = se > 0.0 ? pv[a] / se : 0.0;
+  }
+  out[17] = se;
+  out[18] = (double)d->t;
+}
+
+/* ----------------------------------------------------------- accessors */
+int64_t orc_num_nodes(const orc_domain* d) { return d->N; }
+int64_t orc_num_walkers(const orc_domain* d) { return d->nw; }
+int64_t orc_time(const orc_domain* d) { return d->t; }
+void orc_counters(const orc_domain* d, uint64_t* c) { memcpy(c, d->cnt, sizeof(d->cnt)); }
+void orc_get_f(const orc_domain* d, double* f) { memcpy(f, d->f, sizeof(double) * 19 * d->N); }
+void orc_set_f(orc_domain* d, const double* f) { memcpy(d->f, f, sizeof(double) * 19 * d->N); }
+void orc_get_fields(const orc_domain* d, double* rho, double* u, double* eps, double* us) {
+  if (rho) memcpy(rho, d->rho, sizeof(double) * d->N);
+  if (u) memcpy(u, d->u, sizeof(double) * 3 * d->N);
+  if (eps) memcpy(eps, d->eps, sizeof(double) * d->N);
+  if (us) memcpy(us, d->us, sizeof(double) * 3 * d->N);
+}
+void orc_get_walkers(const orc_domain* d, int32_t* cell, double* off, int32_t* img) {
+  if (cell) memcpy(cell, d->cell, sizeof(int32_t) * d->nw);
+  if (off) memcpy(off, d->off, sizeof(double) * 3 * d->nw);
+  if (img) memcpy(img, d->img, sizeof(int32_t) * 3 * d->nw);
+}
+/* Replace the walker set (positions as cell index + offset); for tests. */
+void orc_set_walkers(orc_domain* d, int64_t nw, const int32_t* cell, const double* off,
+                     const double ref[3]) {
+  free(d->cell); free(d->off); free(d->img);
+  d->nw = nw;
+  d->cell = (int32_t*)malloc(sizeof(int32_t) * (nw > 0 ? nw : 1));
+  d->off = (double*)malloc(sizeof(double) * 3 * (nw > 0 ? nw : 1));
+  d->img = (int32_t*)calloc(3 * (nw > 0 ? nw : 1), sizeof(int32_t));
+  memcpy(d->cell, cell, sizeof(int32_t) * nw);
+  memcpy(d->off, off, sizeof(double) * 3 * nw);
+  for (int a = 0; a < 3; a++) d->ref[a] = ref[a];
+}
+
+/* ------------------------------------------ exported pieces for the pins */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox(ctr, key, out); }
+double orc_ln_export(double u) { return orc_ln(u); }
+void orc_sincos2pi(double u, double* s, double* c) { sincos2pi(u, s, c); }
+void orc_normals(const uint32_t ctr[4], const uint32_t key[2], double z[3]) {
+  uint32_t r[4];
+  philox(ctr, key, r);
+  normals3(r, z);
+}
+/* normals for counters (id, t, purpose, 0), id = 0..n-1 */
+void orc_normals_batch(uint32_t t, uint32_t purpose, const uint32_t key[2], int64_t n, double* z) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    uint32_t ctr[4] = {(uint32_t)i, t, purpose, 0u}, r[4];
+    philox(ctr, key, r);
+    normals3(r, z + 3 * i);
+  }
+}
+void orc_feq(double rho, const double u[3], double out[19]) {
+  init_weights();
+  for (int i = 0; i < 19; i++) out[i] = feq(i, rho, u);
+}
+void orc_lattice(int32_t e[57], double w[19]) {
+  init_weights();
+  for (int i = 0; i < 19; i++) {
+    w[i] = WT[i];
+    for (int a = 0; a < 3; a++) e[3 * i + a] = EV[i][a];
+  }
+}
+void orc_collide_node(orc_domain* d, const double f[19], double eps, const double us[3],
+                      double out[19], double* rho, double u[3]) {
+  collide_node(d, f, eps, us, out, rho, u);
+}
+double orc_particle_M(const orc_domain* d, int p, int64_t t, const int cell[3], const double x[3]) {
+  Poses P;
+  all_poses(d, t, &P);
+  return M_at(d, &P, p, cell, x);
+}
+void orc_particle_grad(const orc_domain* d, int p, int64_t t, const int cell[3], const double x[3],
+                       double g[3]) {
+  Poses P;
+  all_poses(d, t, &P);
+  double dl[3];
+  delta_to(d, &P, p, cell, x, dl);
+  mb_grad(&d->P[p], dl, g);
+}
+void orc_particle_pose(const orc_domain* d, int p, int64_t t, double c[3], double v[3]) {
+  pose(&d->P[p], t, c, v);
+}
+double orc_particle_rb(const orc_domain* d, int p) { return d->P[p].rb; }
+/* Algorithm 1 on a caller-given segment; returns iterations used encoded as
+ * success flag in *ok. */
+double orc_bisect_segment(const orc_domain* d, int p, int64_t t, const int cell[3], const double a0[3],
+                          const double dir[3], double s_out, double s_in, int imax, int* ok) {
+  Poses P;
+  all_poses(d, t, &P);
+  double s = -1.0;
+  *ok = bisect(d, &P, p, cell, a0, dir, s_out, s_in, imax, &s);
+  return s;
+}
+/* Eq. 19 with the normal normalised: t_r = t_i - 2 (t_i . n) n. */
+void orc_reflect(const double ti[3], const double g[3], double tr[3]) {
+  double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  double nv[3];
+  for (int a = 0; a < 3; a++) nv[a] = g[a] / gn;
+  double dt = ti[0] * nv[0] + ti[1] * nv[1] + ti[2] * nv[2];
+  for (int a = 0; a < 3; a++) tr[a] = ti[a] - (2.0 * dt) * nv[a];
+}

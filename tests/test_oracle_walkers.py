@@ -1,0 +1,156 @@
+"""Pins of the oracle's random walkers (Eq. 2; Sec. 2.4.1-2.4.2; Algorithms
+1-2): free-space mean squared displacement 6 D t (second moment of Eq. 31),
+the drifting Gaussian plume of Eq. 34, wall confinement, exact count
+conservation (Eq. 16 occupancy sums to N), no walker left inside a particle
+except through the counted refill fallback, and the forced failure of
+Algorithm 1."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2308_05007_amd import workloads as W
+
+
+def _point_release(orc, n_box, D, u0, N, centre):
+    o = orc.Oracle(dict(n=(n_box,) * 3, bc=("periodic",) * 3, tau=0.8, F=(0, 0, 0), D=D, seed=99, u0=u0))
+    xyz = np.tile(np.asarray(centre, float), (N, 1))
+    assert o.seed(dict(kind="explicit", xyz=xyz, ref=centre), N) == N
+    return o
+
+
+def test_free_space_msd_is_6Dt(orc):
+    N, D, t = 10000, 0.05, 40
+    c = (16.5, 16.25, 15.75)
+    o = _point_release(orc, 32, D, (0, 0, 0), N, c)
+    o.step(t)
+    m = o.moments()
+    assert m["n_walkers"] == N
+    msd = m["sumsq"].sum() / N
+    sd = 6 * D * t * math.sqrt(2.0 / (3 * N))
+    assert abs(msd - 6 * D * t) < 4 * sd, (msd, 6 * D * t, sd)
+    # the fluid is exactly at rest
+    assert np.all(o.fields()["u"] == 0.0)
+
+
+def test_plume_drifts_and_spreads_as_eq34(orc):
+    """Sec. 3.1 in lattice units (D = 0.2, u = 0.2): a uniform u0 is a fixed
+    point of the fluid, so the plume must be the Gaussian of Eq. 34."""
+    N, D, t = 20000, 0.2, 25
+    u0 = (0.2, 0.0, 0.0)
+    c = (20.0, 20.0, 20.0)
+    o = _point_release(orc, 40, D, u0, N, c)
+    o.step(t)
+    cell, off, img = o.walkers()
+    n = 40
+    X = np.stack([cell % n, (cell // n) % n, cell // (n * n)]).astype(float) + img * n + off
+    for a in range(3):
+        mu = c[a] + u0[a] * t
+        sig = math.sqrt(2 * D * t)
+        assert abs(X[a].mean() - mu) < 4 * sig / math.sqrt(N)
+        assert abs(X[a].var() / sig ** 2 - 1) < 4 * math.sqrt(2.0 / N)
+        assert stats.kstest(X[a], "norm", args=(mu, sig)).pvalue > 1e-3
+
+
+def test_walls_confine_and_keep_uniform_density(orc):
+    n = (12, 10, 12)
+    o = orc.Oracle(dict(n=n, bc=("periodic", "wall", "periodic"), tau=0.8, F=(0, 0, 0), D=0.1, seed=5))
+    N = 30000
+    assert o.seed(dict(kind="uniform", ref=(6, 5, 6)), N) == N
+    for _ in range(4):
+        o.step(25)
+        cell, off, img = o.walkers()
+        y = (cell // n[0]) % n[1] + off[1]
+        assert y.min() >= 1.0 and y.max() < n[1] - 1
+        assert np.all(img[1] == 0)
+    counts, _ = np.histogram(y, bins=16, range=(1, n[1] - 1))
+    assert stats.chisquare(counts).pvalue > 1e-3
+    assert o.counters()["wall_reflect"] > 0
+
+
+def _inside_any(o, P, t, cell, off, n):
+    """brute force over walkers and particles with the oracle's own M"""
+    cnt = 0
+    for w in range(cell.size):
+        c = np.array([cell[w] % n[0], (cell[w] // n[0]) % n[1], cell[w] // (n[0] * n[1])], np.int32)
+        if any(o.particle_M(p, t, c, off[:, w]) >= 1.0 for p in range(P)):
+            cnt += 1
+    return cnt
+
+
+def test_reflection_keeps_walkers_out_of_static_particle(orc):
+    cfg = W.config_plain_fp64(scale=0.2)
+    cfg["domain"]["D"] = 0.05
+    o = orc.build_domain(cfg)
+    N = cfg["walkers"]["n"]
+    assert o.seed(cfg["walkers"], N) == N
+    n = cfg["domain"]["n"]
+    assert _inside_any(o, 1, 0, *o.walkers()[:2], n) == 0
+    o.step(30)
+    cell, off, _ = o.walkers()
+    assert cell.size == N and o.occupancy().sum() == N
+    assert o.counters()["type4"] > 0
+    assert _inside_any(o, 1, 30, cell, off, n) == 0
+
+
+def test_swept_walkers_are_refilled_outside(orc):
+    """A particle moving at 0.1 cell/step through slow walkers: walkers it
+    sweeps over are type II and get pushed out; only counted fallbacks may
+    stay inside."""
+    n = (16, 16, 16)
+    o = orc.Oracle(dict(n=n, bc=("periodic",) * 3, tau=0.8, F=(0, 0, 0), D=0.0005, seed=8))
+    o.add_particle(dict(b=np.array([[0.0, 0.0, 0.8], [0.0, 0.0, -0.8]]), k=np.array([2.0, 2.0]),
+                        centre=np.array([4.0, 8.0, 8.0]), motion="const_vel", vel=np.array([0.1, 0.0, 0.0])))
+    N = 4000
+    assert o.seed(dict(kind="uniform", ref=(8, 8, 8)), N) == N
+    for step in range(6):
+        o.step(5)
+        cell, off, _ = o.walkers()
+        assert cell.size == N and o.occupancy().sum() == N
+        inside = _inside_any(o, 1, o.t, cell, off, n)
+        assert inside <= o.counters()["refill_fallback"]
+    c = o.counters()
+    assert c["type2"] > 0
+
+
+def test_forced_bisection_failure_keeps_count(orc):
+    cfg = W.config_plain_fp64(scale=0.2)
+    cfg["domain"]["D"] = 0.05
+    o = orc.build_domain(cfg)
+    o.set_max_bisect(1)
+    N = cfg["walkers"]["n"]
+    o.seed(cfg["walkers"], N)
+    before = o.walkers()
+    o.step(10)
+    c = o.counters()
+    assert c["bisect_fail"] > 0
+    assert o.nw == N and o.occupancy().sum() == N
+    assert _inside_any(o, 1, 10, *o.walkers()[:2], cfg["domain"]["n"]) == 0
+
+
+def test_seeding_excludes_particles_and_remove_option(orc):
+    cfg = W.config_plain_fp64(scale=0.5)
+    o = orc.build_domain(cfg)
+    N = cfg["walkers"]["n"]
+    assert o.seed(cfg["walkers"], N) == N
+    assert _inside_any(o, 1, 0, *o.walkers()[:2], cfg["domain"]["n"]) == 0
+    o2 = orc.build_domain(cfg)
+    w = dict(cfg["walkers"], remove_inside=1)
+    m = o2.seed(w, N)
+    solid = o2.fields()["eps"]  # not stepped yet: use the particle volume estimate instead
+    assert 0 < N - m < 0.05 * N
+    # survivors are the first-attempt draws that were outside, in order
+    cell_all, _, _ = o.walkers()
+    assert o2.nw == m
+
+
+def test_occupancy_is_cell_count(orc):
+    cfg = W.config_tiny(n=(6, 5, 7), n_walkers=500, steps=3)
+    o = orc.build_domain(cfg)
+    o.seed(cfg["walkers"], 500)
+    o.step(3)
+    cell, _, _ = o.walkers()
+    ns = o.occupancy().ravel()
+    assert np.array_equal(ns, np.bincount(cell, minlength=ns.size))
+    assert ns.sum() == 500

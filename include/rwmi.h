@@ -1,0 +1,271 @@
+/*
+ * rwmi.h -- C ABI of the MI355X (gfx950) library for one coupled time step of
+ * the random-walk / metaball / lattice-Boltzmann method of arXiv 2308.05007
+ * ("RW-MI-DELBM").
+ *
+ * The library advances, entirely in hand-written HIP kernels:
+ *   - a D3Q19 BGK lattice Boltzmann fluid (Sec. 2.3, Eq. 12-15) coupled to
+ *     moving metaball particles (Eq. 3) through partially saturated cells
+ *     (named in Sec. 1), with Guo body forcing and halfway bounce-back walls
+ *     carrying the moving-wall term of Eq. 23;
+ *   - N solute random walkers (Eq. 2): trilinear velocity interpolation
+ *     (Sec. 2.4.1), Gaussian steps from Philox4x32-10, the four
+ *     walker/particle types of Sec. 2.4.2 with Algorithm 1 (intersection by
+ *     binary search), Algorithm 2 (specular reflection, Eq. 18-22) and the
+ *     refill of swept walkers, reflection at walls.  The walker count is
+ *     conserved exactly.
+ *
+ * Conventions shared by every call
+ *   - Lattice units: dx = dt = 1.  Node (i,j,k) is centred at
+ *     (i+1/2, j+1/2, k+1/2); its cell is [i,i+1) x [j,j+1) x [k,k+1).
+ *     Linear node index = i + nx (j + ny k).  Arrays over nodes are SoA with x
+ *     fastest.
+ *   - D3Q19 direction order: rest; +x,-x,+y,-y,+z,-z; then (1,1,0),(-1,-1,0),
+ *     (1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),(0,1,1),
+ *     (0,-1,-1),(0,1,-1),(0,-1,1).  Weights 1/3, 1/18, 1/36; c_s^2 = 1/3.
+ *   - A wall axis has solid wall nodes at index 0 and n-1; the halfway
+ *     bounce-back planes sit at continuous coordinates 1 and n-1.
+ *   - Every call returns an rwmi_status.  rwmi_last_error() gives a message
+ *     owned by the library, valid until the next call on the same domain.
+ *   - A domain is not thread-safe; distinct domains may be used from
+ *     distinct threads.  Device work is enqueued on the domain's stream
+ *     (the caller's hipStream_t, or one the library creates); calls named
+ *     read_* synchronise that stream, rwmi_step does not.
+ *   - Host pointers passed in are read during the call only; the caller keeps
+ *     ownership.  Host output buffers are caller-allocated with the sizes
+ *     from rwmi_query_sizes().
+ */
+#ifndef RWMI_H
+#define RWMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RWMI_OK = 0,
+  RWMI_EINVAL = -1,  /* an argument is out of range; nothing was changed */
+  RWMI_ENOMEM = -2,  /* device allocation failed */
+  RWMI_EDEVICE = -3, /* a HIP call failed (message in rwmi_last_error) */
+  RWMI_ESTATE = -4,  /* call not allowed in the current state */
+  RWMI_ESEED = -5    /* a walker found no admissible position */
+} rwmi_status;
+
+typedef enum { RWMI_BC_PERIODIC = 0, RWMI_BC_WALL = 1 } rwmi_bc;
+
+/* Storage/compute modes.  FP64: distributions, velocity and walker offsets in
+ * double, arithmetic in double with no contraction (reproduces the FP64
+ * reference bit for bit).  FP32 / FP16_STORE / BF16_STORE: distributions
+ * stored as deviations f_i - w_i rho0 in float / half / bfloat16, collision
+ * in float, velocity field in float, walker offsets in float; Gaussian
+ * normals are always drawn in double so every mode sees the same noise. */
+typedef enum { RWMI_FP64 = 0, RWMI_FP32 = 1, RWMI_FP16_STORE = 2, RWMI_BF16_STORE = 3 } rwmi_precision;
+
+/* Prescribed rigid motion of a particle (fixed orientation; the oscillator of
+ * Sec. 4 read as a displacement sinusoid):
+ *   STATIC   c(t) = c0
+ *   SINUSOID c(t) = c0 + A sin(2 pi (t / period + phase)),  phase in cycles
+ *   CONST_VEL c(t) = c0 + v t
+ * The surface velocity seen by the fluid is dc/dt (Sec. 2.4.3 with w = 0). */
+typedef enum { RWMI_MOTION_STATIC = 0, RWMI_MOTION_SINUSOID = 1, RWMI_MOTION_CONST_VEL = 2 } rwmi_motion;
+
+/* Walker release (Sec. 3.1 point source, Sec. 4 solute band):
+ *   UNIFORM  uniform over the fluid box
+ *   GAUSSIAN centre + sigma z, z standard normal
+ *   BAND     uniform, except axis band_axis uniform in [band_lo, band_hi)
+ *   EXPLICIT the host positions xyz (3 per walker, continuous coordinates) */
+typedef enum { RWMI_SEED_UNIFORM = 0, RWMI_SEED_GAUSSIAN = 1, RWMI_SEED_BAND = 2, RWMI_SEED_EXPLICIT = 3 } rwmi_seed_kind;
+
+typedef void* (*rwmi_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*rwmi_free_fn)(void* ptr, void* ctx);
+
+typedef struct {
+  int32_t n[3];             /* lattice nodes per axis (>= 1; >= 3 on a wall axis) */
+  int32_t bc[3];            /* rwmi_bc per axis */
+  double wall_u_lo[3][3];   /* [axis][component] velocity of the wall at index 0 */
+  double wall_u_hi[3][3];   /* [axis][component] velocity of the wall at index n-1 */
+  double tau;               /* BGK relaxation time, > 0.5 (Eq. 12) */
+  double force[3];          /* uniform body force per unit volume (Guo forcing) */
+  double diffusivity;       /* solute D >= 0 (Eq. 1-2) */
+  double rho0;              /* initial density (0 means 1) */
+  double u0[3];             /* initial uniform velocity */
+  uint64_t seed;            /* Philox key = (seed mod 2^32, seed >> 32) */
+  int32_t precision;        /* rwmi_precision */
+  int32_t device;           /* HIP device ordinal */
+  void* stream;             /* hipStream_t to enqueue on, or NULL for a library stream */
+  rwmi_alloc_fn alloc;      /* optional device allocator (e.g. the torch caching */
+  rwmi_free_fn free;        /*   allocator); NULL pair means hipMalloc / hipFree  */
+  void* alloc_ctx;
+} rwmi_domain_desc;
+
+typedef struct {
+  int32_t n_ctrl;           /* control points, 1..RWMI_MAX_CTRL */
+  const double* offsets;    /* 3*n_ctrl: control point - centre, world frame (Eq. 3 x_i) */
+  const double* weights;    /* n_ctrl: k_i > 0 (Eq. 3) */
+  double centre[3];         /* c0 */
+  int32_t motion;           /* rwmi_motion */
+  double amplitude[3];      /* SINUSOID amplitude vector A */
+  double period;            /* SINUSOID period in steps (> 0) */
+  double phase;             /* SINUSOID phase in cycles */
+  double velocity[3];       /* CONST_VEL velocity */
+} rwmi_metaball_desc;
+
+typedef struct {
+  int32_t kind;             /* rwmi_seed_kind */
+  double centre[3];         /* GAUSSIAN centre */
+  double sigma;             /* GAUSSIAN standard deviation */
+  int32_t band_axis;        /* BAND axis (0..2) */
+  double band_lo, band_hi;  /* BAND range along that axis */
+  const double* xyz;        /* EXPLICIT positions, 3 per walker (host) */
+  double ref[3];            /* reference point for the position moments */
+  int32_t max_attempts;     /* redraws per walker (0 means 64) */
+  int32_t remove_inside;    /* 1: drop (not redraw) walkers inside a particle, the
+                               paper's removal at the first step (Sec. 2.4.2) */
+} rwmi_seed_desc;
+
+/* FP64 moments of the state after the last completed step (Eq. 16, Eq. 38-40
+ * inputs).  Walker positions are unwrapped with their periodic image counts;
+ * sums run over walkers, field sums over fluid (non-wall) nodes, with eps the
+ * solid fraction of the last fluid update. */
+typedef struct {
+  uint64_t step;            /* completed coupled steps */
+  uint64_t n_walkers;       /* exact walker count */
+  double sum[3];            /* sum (X - ref) */
+  double sumsq[3];          /* sum (X - ref)^2 */
+  double mass;              /* sum rho */
+  double momentum[3];       /* sum rho u */
+  double fluid_u[3];        /* sum (1-eps) u / sum (1-eps) */
+  double particle_v[3];     /* sum eps u_s / sum eps (0 without solid) */
+  double solid_volume;      /* sum eps */
+  uint64_t type2;           /* walkers inside a particle at both ends (refilled) */
+  uint64_t type4;           /* walkers entering a particle (reflected, Alg. 1-2) */
+  uint64_t bisect_fail;     /* Algorithm 1 reached its iteration cap */
+  uint64_t refill_fallback; /* refill found no admissible point */
+  uint64_t returned_to_origin; /* narrow-gap rule: walker kept its position */
+  uint64_t wall_reflect;    /* walkers reflected at a wall */
+} rwmi_moments;
+
+typedef struct rwmi_domain rwmi_domain;
+typedef struct rwmi_batch rwmi_batch;
+
+#define RWMI_MAX_PARTICLES 64
+#define RWMI_MAX_CTRL 64
+
+/* Create a domain: allocates the lattice state on the device and sets every
+ * distribution to the equilibrium of (rho0, u0) (Eq. 13).  *out owns the
+ * device memory until rwmi_destroy_domain.  EINVAL on bad sizes, tau <= 0.5,
+ * D < 0, unknown precision; ENOMEM / EDEVICE on device failure. */
+rwmi_status rwmi_create_domain(const rwmi_domain_desc* desc, rwmi_domain** out);
+
+/* Release every device buffer of the domain (after synchronising its stream).
+ * NULL is ignored.  The domain must not be in a batch. */
+void rwmi_destroy_domain(rwmi_domain* dom);
+
+/* Add a metaball particle (Eq. 3) with prescribed motion.  The host arrays are
+ * copied.  *out_id receives its index (0-based, in call order; lower indices
+ * win where particles overlap).  ESTATE once walkers are seeded or a step has
+ * run; EINVAL on n_ctrl out of range, a weight <= 0, period <= 0, or more
+ * than RWMI_MAX_PARTICLES particles. */
+rwmi_status rwmi_add_metaball_particle(rwmi_domain* dom, const rwmi_metaball_desc* p, int32_t* out_id);
+
+/* Seed n walkers (ids 0..n-1) at step 0, on the device.  Attempt a of walker
+ * w draws the Philox block with counter (w, 0xFFFFFFFF, 16 + a, 0); positions
+ * inside a particle at t = 0 or outside the fluid range of a wall axis are
+ * redrawn up to max_attempts times (remove_inside = 1: dropped instead, the
+ * survivors keep their order and are renumbered).  *out_seeded receives the
+ * number placed.  ESEED if a walker ran out of attempts (the placed walkers
+ * are kept); ESTATE after the first step or a second call; EINVAL for a bad
+ * kind or n > 2^31 - 1. */
+rwmi_status rwmi_seed_walkers(rwmi_domain* dom, const rwmi_seed_desc* s, uint64_t n, uint64_t* out_seeded);
+
+/* Enqueue n_steps coupled steps t -> t+1 on the domain's stream and return.
+ * Each step: particle poses at t and t+1; fluid update at P(t) writing u(t);
+ * walkers moved with u(t) and classified against P(t+1); walker counter
+ * (w, t, purpose, 0) with purpose 0 Brownian, 1 refill direction, 2 refill
+ * radius.  Device-side anomalies are counted (see rwmi_moments), never
+ * returned. */
+rwmi_status rwmi_step(rwmi_domain* dom, uint32_t n_steps);
+
+/* Compute and copy the FP64 moments (synchronises). */
+rwmi_status rwmi_read_moments(rwmi_domain* dom, rwmi_moments* out);
+
+/* Occupancy n_s per node (Eq. 16: walkers whose cell is the node), exact
+ * uint32, nx*ny*nz entries (synchronises). */
+rwmi_status rwmi_read_occupancy(rwmi_domain* dom, uint32_t* ns);
+
+/* Velocity u(t) of the last fluid update, SoA [3][nodes] as double, and the
+ * density of that update (rho may be NULL).  Wall nodes carry the wall
+ * velocity.  Before any step: u0 and rho0. */
+rwmi_status rwmi_read_velocity(rwmi_domain* dom, double* u, double* rho);
+
+/* Walker state: cell index (int32, n entries), offsets in [0,1) SoA [3][n]
+ * as double, periodic image counts SoA [3][n] (any pointer may be NULL). */
+rwmi_status rwmi_read_walkers(rwmi_domain* dom, int32_t* cell, double* off, int32_t* img);
+
+/* Pre-collision distributions f_i(x, t) at the current step, SoA [19][nodes]
+ * as double (wall nodes: unspecified).  Diagnostic. */
+rwmi_status rwmi_read_distributions(rwmi_domain* dom, double* f);
+
+/* Sizes for the read buffers and the number of steps enqueued so far. */
+rwmi_status rwmi_query_sizes(const rwmi_domain* dom, uint64_t* n_nodes, uint64_t* n_walkers, uint64_t* step);
+
+/* Device bytes a domain with these parameters holds (for admission by HBM
+ * footprint).  Does not touch the device. */
+uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles, uint32_t n_ctrl_total,
+                              uint64_t n_walkers);
+
+/* Debug and tuning knobs (EINVAL on an unknown key):
+ *   RWMI_KEY_MAX_BISECT      iteration cap of Algorithm 1 (default 200, >= 1)
+ *   RWMI_KEY_USE_GRAPH       0/1: replay steps from a captured hipGraph
+ *   RWMI_KEY_LBM_BLOCK       threads per block of the fluid kernel (64..1024, multiple of 64)
+ *   RWMI_KEY_WALK_BLOCK      threads per block of the walker kernel
+ *   RWMI_KEY_TIMING          0/1: record HIP events around every kernel of a step */
+enum {
+  RWMI_KEY_MAX_BISECT = 1,
+  RWMI_KEY_USE_GRAPH = 2,
+  RWMI_KEY_LBM_BLOCK = 3,
+  RWMI_KEY_WALK_BLOCK = 4,
+  RWMI_KEY_TIMING = 5
+};
+rwmi_status rwmi_debug_set(rwmi_domain* dom, int32_t key, int64_t value);
+
+/* Kernel timing recorded while RWMI_KEY_TIMING is on (synchronises, then
+ * clears the record).  Index k: 0 poses+mask, 1 fluid, 2 walkers (main),
+ * 3 walkers near particles.  ms[k] total milliseconds, launches[k] count. */
+rwmi_status rwmi_read_kernel_times(rwmi_domain* dom, double ms[4], uint64_t launches[4]);
+
+/* Block until all work enqueued for the domain has finished. */
+rwmi_status rwmi_synchronize(rwmi_domain* dom);
+
+/* Message of the last failing call on dom (dom NULL: of the last failing
+ * create / batch call on this thread).  Never NULL. */
+const char* rwmi_last_error(const rwmi_domain* dom);
+
+/* ---------------------------------------------------------------- batch
+ * A batch steps many domains with one launch per kernel per step (work
+ * lists over all member domains) on the batch stream, optionally replayed
+ * from a hipGraph.  Members keep their state and ownership; results of a
+ * domain are bit-identical to stepping it alone (same arithmetic per node and
+ * per walker).  Members must live on the batch device; their own streams are
+ * synchronised before each batch step. */
+rwmi_status rwmi_batch_create(int32_t device, void* stream, rwmi_batch** out);
+rwmi_status rwmi_batch_add(rwmi_batch* b, rwmi_domain* dom);
+rwmi_status rwmi_batch_remove(rwmi_batch* b, rwmi_domain* dom);
+/* Enqueue n_steps steps of every member on the batch stream. */
+rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps);
+rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value);
+rwmi_status rwmi_batch_synchronize(rwmi_batch* b);
+void rwmi_batch_destroy(rwmi_batch* b);
+
+/* ---------------------------------------------------------------- diagnostics
+ * The Gaussian triples the walker kernels draw for counters (id, t, purpose,
+ * 0), id = 0..n-1, under key seed, written as n x 3 doubles to host z. */
+rwmi_status rwmi_device_normals(int32_t device, uint64_t seed, uint32_t t, uint32_t purpose, uint64_t n, double* z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RWMI_H */

@@ -111,6 +111,7 @@ class Oracle:
         bc = np.asarray([BC_WALL if b in ("wall", 1) else BC_PERIODIC for b in dom.get("bc", ["periodic"] * 3)],
                         dtype=np.int32)
         self.n = tuple(int(v) for v in n)
+        self.bc = tuple("wall" if b == BC_WALL else "periodic" for b in bc)
         self.N = int(np.prod(self.n))
         self.h = self.L.orc_create(n, bc, _d(dom.get("wall_lo", np.zeros(9)), 9), _d(dom.get("wall_hi", np.zeros(9)), 9),
                                    float(dom["tau"]), _d(dom.get("F", (0, 0, 0)), 3), float(dom.get("D", 0.0)),

@@ -723,9 +723,15 @@ static void walker_step(const orc_domain* d, const Poses* Pn, int64_t w, int cel
       }
     }
   }
+  /* a non-finite position (only from an unstable flow) keeps the walker
+   * where it was */
+  if (!(isfinite(xn[0]) && isfinite(xn[1]) && isfinite(xn[2]))) {
+    cn->c[C_RETURNED]++;
+    for (int a = 0; a < 3; a++) xn[a] = o[a];
+  }
   /* 5. walls: halfway planes at 1 and n-1 on wall axes, one specular
-   * reflection per axis; a reflected point inside a particle returns the
-   * walker to where it started (narrow gaps) */
+   * reflection per axis; a reflected point still outside the fluid range, or
+   * inside a particle, returns the walker to where it started (narrow gaps) */
   int refl = 0;
   for (int a = 0; a < 3; a++) {
     if (!d->bc[a]) continue;
@@ -741,7 +747,13 @@ static void walker_step(const orc_domain* d, const Poses* Pn, int64_t w, int cel
   }
   if (refl) {
     cn->c[C_WALL_REFLECT]++;
-    if (inside_any(d, Pn, cell, xn) >= 0) {
+    int out = 0;
+    for (int a = 0; a < 3; a++) {
+      if (!d->bc[a]) continue;
+      double lo = 1.0 - (double)cell[a], hi = (double)(n[a] - 1) - (double)cell[a];
+      if (xn[a] < lo || xn[a] >= hi) out = 1;
+    }
+    if (out || inside_any(d, Pn, cell, xn) >= 0) {
       cn->c[C_RETURNED]++;
       for (int a = 0; a < 3; a++) xn[a] = o[a];
     }
@@ -756,8 +768,9 @@ static void walker_step(const orc_domain* d, const Poses* Pn, int64_t w, int cel
     }
     int c = cell[a] + (int)k;
     if (!d->bc[a]) {
-      if (c < 0) { c += n[a]; img[a] -= 1; }
-      else if (c >= n[a]) { c -= n[a]; img[a] += 1; }
+      int q = c >= 0 ? c / n[a] : -((-c + n[a] - 1) / n[a]); /* floor(c / n) */
+      c -= q * n[a];
+      img[a] += q;
     }
     cell[a] = c;
     o[a] = of;

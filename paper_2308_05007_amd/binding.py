@@ -1,0 +1,409 @@
+"""ctypes binding of librwmi (include/rwmi.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels.  PyTorch, when
+present with a GPU, supplies device memory (its caching allocator, through
+the library's allocation callbacks) and the stream each domain runs on.
+Loading fails loudly if librwmi.so has not been built: there is no CPU path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librwmi.so")
+
+RWMI_OK, RWMI_EINVAL, RWMI_ENOMEM, RWMI_EDEVICE, RWMI_ESTATE, RWMI_ESEED = 0, -1, -2, -3, -4, -5
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ESEED"}
+PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+MOTION = {"static": 0, "sinusoid": 1, "const_vel": 2}
+SEED_KIND = {"uniform": 0, "gaussian": 1, "band": 2, "explicit": 3}
+KEY = {"max_bisect": 1, "use_graph": 2, "lbm_block": 3, "walk_block": 4, "timing": 5}
+MAX_PARTICLES = 64
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class DomainDesc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("bc", C.c_int32 * 3), ("wall_u_lo", (C.c_double * 3) * 3),
+                ("wall_u_hi", (C.c_double * 3) * 3), ("tau", C.c_double), ("force", C.c_double * 3),
+                ("diffusivity", C.c_double), ("rho0", C.c_double), ("u0", C.c_double * 3), ("seed", C.c_uint64),
+                ("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+class MetaballDesc(C.Structure):
+    _fields_ = [("n_ctrl", C.c_int32), ("offsets", C.POINTER(C.c_double)), ("weights", C.POINTER(C.c_double)),
+                ("centre", C.c_double * 3), ("motion", C.c_int32), ("amplitude", C.c_double * 3),
+                ("period", C.c_double), ("phase", C.c_double), ("velocity", C.c_double * 3)]
+
+
+class SeedDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("centre", C.c_double * 3), ("sigma", C.c_double), ("band_axis", C.c_int32),
+                ("band_lo", C.c_double), ("band_hi", C.c_double), ("xyz", C.POINTER(C.c_double)),
+                ("ref", C.c_double * 3), ("max_attempts", C.c_int32), ("remove_inside", C.c_int32)]
+
+
+class Moments(C.Structure):
+    _fields_ = [("step", C.c_uint64), ("n_walkers", C.c_uint64), ("sum", C.c_double * 3), ("sumsq", C.c_double * 3),
+                ("mass", C.c_double), ("momentum", C.c_double * 3), ("fluid_u", C.c_double * 3),
+                ("particle_v", C.c_double * 3), ("solid_volume", C.c_double), ("type2", C.c_uint64),
+                ("type4", C.c_uint64), ("bisect_fail", C.c_uint64), ("refill_fallback", C.c_uint64),
+                ("returned_to_origin", C.c_uint64), ("wall_reflect", C.c_uint64)]
+
+
+# name -> (restype, argtypes); the full exported surface of include/rwmi.h
+SIGNATURES = {
+    "rwmi_create_domain": (C.c_int, [C.POINTER(DomainDesc), C.POINTER(C.c_void_p)]),
+    "rwmi_destroy_domain": (None, [C.c_void_p]),
+    "rwmi_add_metaball_particle": (C.c_int, [C.c_void_p, C.POINTER(MetaballDesc), C.POINTER(C.c_int32)]),
+    "rwmi_seed_walkers": (C.c_int, [C.c_void_p, C.POINTER(SeedDesc), C.c_uint64, C.POINTER(C.c_uint64)]),
+    "rwmi_step": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "rwmi_read_moments": (C.c_int, [C.c_void_p, C.POINTER(Moments)]),
+    "rwmi_read_occupancy": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rwmi_read_velocity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rwmi_read_walkers": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rwmi_read_distributions": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rwmi_query_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "rwmi_footprint_bytes": (C.c_uint64, [C.POINTER(DomainDesc), C.c_uint32, C.c_uint32, C.c_uint64]),
+    "rwmi_debug_set": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64]),
+    "rwmi_read_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "rwmi_synchronize": (C.c_int, [C.c_void_p]),
+    "rwmi_last_error": (C.c_char_p, [C.c_void_p]),
+    "rwmi_batch_create": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "rwmi_batch_add": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rwmi_batch_remove": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rwmi_batch_step": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "rwmi_batch_set": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64]),
+    "rwmi_batch_synchronize": (C.c_int, [C.c_void_p]),
+    "rwmi_batch_destroy": (None, [C.c_void_p]),
+    "rwmi_device_normals": (C.c_int, [C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p]),
+}
+
+_lib = None
+
+
+class RwmiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+def _hip_runtimes():
+    """Distinct HIP runtime files mapped into this process."""
+    try:
+        with open("/proc/self/maps") as fh:
+            return sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln and "/" in ln})
+    except OSError:
+        return []
+
+
+def lib():
+    """Load librwmi.so (raises if it has not been built).
+
+    torch (when installed) is imported first: it brings its own HIP runtime
+    under the soname libamdhip64.so.7, and librwmi.so must bind to that same
+    runtime rather than load a second one."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librwmi.so is not built (%s); run python -m paper_2308_05007_amd.build" % LIB_PATH)
+        try:
+            import torch  # noqa: F401
+        except Exception:
+            pass
+        L = C.CDLL(LIB_PATH)
+        rts = _hip_runtimes()
+        if len(rts) > 1:
+            raise RuntimeError("two HIP runtimes are loaded (%s); import torch before librwmi.so" % ", ".join(rts))
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st, handle=None):
+    if st != RWMI_OK:
+        msg = lib().rwmi_last_error(handle)
+        raise RwmiError(st, msg.decode() if msg else "")
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _torch_gpu():
+    try:
+        import torch
+        return torch if torch.cuda.is_available() else None
+    except Exception:
+        return None
+
+
+class _TorchAllocator:
+    """Device memory from torch's caching allocator on a given stream."""
+
+    def __init__(self, torch, device, stream):
+        self.torch = torch
+        self.device = device
+        self.stream = stream
+
+        def _alloc(nbytes, ctx):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream))
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                pass
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+
+def make_desc(dom, device=0, stream=None, allocator=None):
+    d = DomainDesc()
+    n = dom["n"]
+    bc = dom.get("bc", ("periodic",) * 3)
+    for a in range(3):
+        d.n[a] = int(n[a])
+        d.bc[a] = 1 if bc[a] in ("wall", 1) else 0
+    wl = np.asarray(dom.get("wall_lo", np.zeros(9)), float).reshape(3, 3)
+    wh = np.asarray(dom.get("wall_hi", np.zeros(9)), float).reshape(3, 3)
+    for a in range(3):
+        for c in range(3):
+            d.wall_u_lo[a][c] = wl[a, c]
+            d.wall_u_hi[a][c] = wh[a, c]
+    d.tau = float(dom["tau"])
+    F = dom.get("F", (0, 0, 0))
+    u0 = dom.get("u0", (0, 0, 0))
+    for a in range(3):
+        d.force[a] = float(F[a])
+        d.u0[a] = float(u0[a])
+    d.diffusivity = float(dom.get("D", 0.0))
+    d.rho0 = float(dom.get("rho0", 1.0))
+    d.seed = int(dom.get("seed", 0)) & (2**64 - 1)
+    d.precision = PRECISION[dom.get("precision", "fp64")]
+    d.device = int(device)
+    d.stream = stream
+    if allocator is not None:
+        d.alloc = allocator.alloc
+        d.free = allocator.free
+    return d
+
+
+def footprint_bytes(dom, n_particles=0, n_ctrl_total=0, n_walkers=0):
+    d = make_desc(dom)
+    return int(lib().rwmi_footprint_bytes(C.byref(d), int(n_particles), int(n_ctrl_total), int(n_walkers)))
+
+
+class Domain:
+    """One simulation domain on the GPU (mirrors the C ABI)."""
+
+    def __init__(self, dom, device=0, use_torch=True):
+        L = lib()
+        self.L = L
+        self.n = tuple(int(v) for v in dom["n"])
+        self.N = int(np.prod(self.n))
+        self.precision = dom.get("precision", "fp64")
+        torch = _torch_gpu() if use_torch else None
+        self._torch_stream = None
+        self._alloc = None
+        stream = None
+        if torch is not None:
+            self._torch_stream = torch.cuda.Stream(device=device)
+            stream = C.c_void_p(self._torch_stream.cuda_stream)
+            self._alloc = _TorchAllocator(torch, device, self._torch_stream.cuda_stream)
+        self._desc = make_desc(dom, device, stream, self._alloc)
+        h = C.c_void_p()
+        _check(L.rwmi_create_domain(C.byref(self._desc), C.byref(h)))
+        self.h = h
+        self.nparticles = 0
+        self.nw = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.rwmi_destroy_domain(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ck(self, st):
+        _check(st, self.h)
+
+    def add_particle(self, p):
+        b = np.ascontiguousarray(np.asarray(p["b"], float).ravel())
+        k = np.ascontiguousarray(np.asarray(p["k"], float).ravel())
+        m = MetaballDesc()
+        m.n_ctrl = k.size
+        m.offsets = _dptr(b)
+        m.weights = _dptr(k)
+        c = p["centre"]
+        amp = p.get("amp", (0, 0, 0))
+        vel = p.get("vel", (0, 0, 0))
+        for a in range(3):
+            m.centre[a] = float(c[a])
+            m.amplitude[a] = float(amp[a])
+            m.velocity[a] = float(vel[a])
+        m.motion = MOTION[p.get("motion", "static")]
+        m.period = float(p.get("period", 1.0))
+        m.phase = float(p.get("phase", 0.0))
+        out = C.c_int32()
+        self._ck(self.L.rwmi_add_metaball_particle(self.h, C.byref(m), C.byref(out)))
+        self.nparticles += 1
+        return out.value
+
+    def seed(self, s, n, check=True):
+        sd = SeedDesc()
+        sd.kind = SEED_KIND[s["kind"]]
+        c = s.get("centre", (0, 0, 0))
+        ref = s.get("ref", [0.5 * v for v in self.n])
+        for a in range(3):
+            sd.centre[a] = float(c[a])
+            sd.ref[a] = float(ref[a])
+        sd.sigma = float(s.get("sigma", 1.0))
+        band = s.get("band", (2, 0.0, 1.0))
+        sd.band_axis, sd.band_lo, sd.band_hi = int(band[0]), float(band[1]), float(band[2])
+        xyz = None
+        if sd.kind == 3:
+            xyz = np.ascontiguousarray(np.asarray(s["xyz"], float).reshape(-1))
+            sd.xyz = _dptr(xyz)
+        sd.max_attempts = int(s.get("max_attempts", 64))
+        sd.remove_inside = int(s.get("remove_inside", 0))
+        out = C.c_uint64()
+        st = self.L.rwmi_seed_walkers(self.h, C.byref(sd), int(n), C.byref(out))
+        self.nw = int(out.value)
+        if check:
+            self._ck(st)
+        return self.nw
+
+    def step(self, n=1):
+        self._ck(self.L.rwmi_step(self.h, int(n)))
+
+    def sync(self):
+        self._ck(self.L.rwmi_synchronize(self.h))
+
+    def set(self, key, value):
+        self._ck(self.L.rwmi_debug_set(self.h, KEY[key], int(value)))
+
+    def sizes(self):
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        self._ck(self.L.rwmi_query_sizes(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return int(a.value), int(b.value), int(c.value)
+
+    def moments(self):
+        m = Moments()
+        self._ck(self.L.rwmi_read_moments(self.h, C.byref(m)))
+        return dict(step=int(m.step), n_walkers=int(m.n_walkers), sum=np.array(m.sum[:]), sumsq=np.array(m.sumsq[:]),
+                    mass=m.mass, momentum=np.array(m.momentum[:]), fluid_u=np.array(m.fluid_u[:]),
+                    particle_v=np.array(m.particle_v[:]), solid_volume=m.solid_volume,
+                    counters=dict(type2=int(m.type2), type4=int(m.type4), bisect_fail=int(m.bisect_fail),
+                                  refill_fallback=int(m.refill_fallback),
+                                  returned_to_origin=int(m.returned_to_origin), wall_reflect=int(m.wall_reflect)))
+
+    def occupancy(self):
+        ns = np.empty(self.N, np.uint32)
+        self._ck(self.L.rwmi_read_occupancy(self.h, ns.ctypes.data_as(C.c_void_p)))
+        return ns.reshape(self.n[::-1])
+
+    def velocity(self):
+        u = np.empty(3 * self.N)
+        rho = np.empty(self.N)
+        self._ck(self.L.rwmi_read_velocity(self.h, u.ctypes.data_as(C.c_void_p), rho.ctypes.data_as(C.c_void_p)))
+        sh = self.n[::-1]
+        return u.reshape(3, *sh), rho.reshape(sh)
+
+    def walkers(self):
+        _, m, _ = self.sizes()
+        cell = np.empty(max(m, 1), np.int32)
+        off = np.empty(max(3 * m, 1))
+        img = np.empty(max(3 * m, 1), np.int32)
+        vp = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._ck(self.L.rwmi_read_walkers(self.h, vp(cell), vp(off), vp(img)))
+        return cell[:m].copy(), off[:3 * m].reshape(3, m).copy(), img[:3 * m].reshape(3, m).copy()
+
+    def distributions(self):
+        f = np.empty(19 * self.N)
+        self._ck(self.L.rwmi_read_distributions(self.h, f.ctypes.data_as(C.c_void_p)))
+        return f.reshape(19, *self.n[::-1])
+
+    def kernel_times(self):
+        ms = (C.c_double * 4)()
+        cnt = (C.c_uint64 * 4)()
+        self._ck(self.L.rwmi_read_kernel_times(self.h, ms, cnt))
+        names = ("prologue", "fluid", "walk", "walk_slow")
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(names)}
+
+
+def build_domain(cfg, device=0, use_torch=True, seed_walkers=True):
+    """Domain with the particles (and walkers) of a generated configuration."""
+    d = Domain(cfg["domain"], device=device, use_torch=use_torch)
+    for p in cfg.get("particles", []):
+        d.add_particle(p)
+    if seed_walkers and cfg.get("walkers") and cfg["walkers"].get("n", 0) > 0:
+        d.seed(cfg["walkers"], cfg["walkers"]["n"])
+    return d
+
+
+class Batch:
+    """Many domains stepped together (one launch per kernel per step)."""
+
+    def __init__(self, device=0, use_torch=True):
+        L = lib()
+        self.L = L
+        torch = _torch_gpu() if use_torch else None
+        self._torch_stream = torch.cuda.Stream(device=device) if torch is not None else None
+        stream = C.c_void_p(self._torch_stream.cuda_stream) if self._torch_stream is not None else None
+        h = C.c_void_p()
+        _check(L.rwmi_batch_create(int(device), stream, C.byref(h)))
+        self.h = h
+        self.members = []
+
+    def _ck(self, st):
+        _check(st, None)
+
+    def add(self, dom):
+        self._ck(self.L.rwmi_batch_add(self.h, dom.h))
+        self.members.append(dom)
+
+    def remove(self, dom):
+        self._ck(self.L.rwmi_batch_remove(self.h, dom.h))
+        self.members.remove(dom)
+
+    def step(self, n=1):
+        self._ck(self.L.rwmi_batch_step(self.h, int(n)))
+
+    def set(self, key, value):
+        self._ck(self.L.rwmi_batch_set(self.h, KEY[key], int(value)))
+
+    def sync(self):
+        self._ck(self.L.rwmi_batch_synchronize(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.rwmi_batch_destroy(self.h)
+            self.h = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_normals(seed, t, purpose, n, device=0):
+    z = np.empty(3 * n)
+    _check(lib().rwmi_device_normals(int(device), int(seed), int(t), int(purpose), int(n),
+                                     z.ctypes.data_as(C.c_void_p)))
+    return z.reshape(n, 3)

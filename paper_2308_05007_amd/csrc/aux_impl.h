@@ -1,0 +1,339 @@
+// Per-step prologue (particle poses, walker cull mask), walker seeding,
+// occupancy (Eq. 16) and the FP64 moment reductions.
+#pragma once
+#include "dev_common.h"
+#include "lbm_impl.h"
+#include "walk_impl.h"
+
+namespace rwmi {
+
+// Circular or plain gap between coordinate c and the interval [a, b].
+__device__ __forceinline__ double gap_to(int periodic, int L, double a, double b, double c) {
+  if (!periodic) {
+    if (c < a) return a - c;
+    if (c > b) return c - b;
+    return 0.0;
+  }
+  const double hw = 0.5 * (b - a);
+  if (2.0 * hw >= (double)L) return 0.0;
+  double m = c - 0.5 * (a + b);
+  m = m - (double)L * floor(m / (double)L + 0.5);
+  const double g = fabs(m) - hw;
+  return g > 0.0 ? g : 0.0;
+}
+
+// Block 0 writes the poses P(t), P(t+1) of step t = tstep[0], records t in
+// tstep[1] and empties the near-surface queue; every block then builds its
+// share of the coarse mask at P(t+1): bit p of a block is set when the sphere
+// (c_p(t+1), rb_p + 1/2) meets the block (extended to infinity beyond wall
+// planes).
+__global__ void k_prologue(const DomView* __restrict__ views, const int32_t* __restrict__ boff, int nd_count) {
+  __shared__ double sc[kMaxParticles][3];
+  __shared__ double sr[kMaxParticles];
+  const int d = find_domain(boff, nd_count, blockIdx.x);
+  const DomView& V = views[d];
+  const int lb = blockIdx.x - boff[d];
+  const uint64_t t = V.tstep[0];
+  const int tid = threadIdx.x;
+  if (tid < V.np) {
+    const DevParticle& P = V.parts[tid];
+    double c0[3], v0[3], c1[3], v1[3];
+    particle_pose(P, t, c0, v0);
+    particle_pose(P, t + 1, c1, v1);
+    if (lb == 0) {
+      double* pt = V.pose + 6 * tid;
+      double* pn = V.pose + 6 * (V.np + tid);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pt[a] = c0[a];
+        pt[3 + a] = v0[a];
+        pn[a] = c1[a];
+        pn[3 + a] = v1[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sc[tid][a] = c1[a];
+    sr[tid] = P.maskr;
+  }
+  if (lb == 0 && tid == 0) {
+    V.tstep[1] = t;
+    if (V.qcount) *V.qcount = 0u;  // allocated with the walkers
+  }
+  __syncthreads();
+  if (V.nw == 0 || V.np == 0) return;
+  const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
+  const int64_t cb = (int64_t)lb * blockDim.x + tid;
+  if (cb >= nmb) return;
+  const int bidx[3] = {(int)(cb % V.mb[0]), (int)((cb / V.mb[0]) % V.mb[1]), (int)(cb / ((int64_t)V.mb[0] * V.mb[1]))};
+  double lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = (double)(bidx[a] * kMaskBlock);
+    const int e = (bidx[a] + 1) * kMaskBlock;
+    hi[a] = (double)(e < V.n[a] ? e : V.n[a]);
+    if (V.bc[a]) {
+      if (bidx[a] == 0) lo[a] = -1e300;
+      if (bidx[a] == V.mb[a] - 1) hi[a] = 1e300;
+    }
+  }
+  unsigned long long bits = 0ull;
+  for (int p = 0; p < V.np; ++p) {
+    double g2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double g = gap_to(!V.bc[a], V.n[a], lo[a], hi[a], sc[p][a]);
+      g2 += g * g;
+    }
+    const double r = sr[p];
+    if (g2 <= r * r * (1.0 + 1e-9) + 1e-9) bits |= (1ull << p);
+  }
+  V.mask[cb] = bits;
+}
+
+// Seeding at t = 0: walker w tries Philox blocks (w, 0xFFFFFFFF, 16 + a, 0).
+// Writes cell, offsets (in the walker precision) and flag[w] = 1 if placed.
+template <typename R>
+__global__ void k_seed(const DomView* __restrict__ views, int dom, int kind, double cx, double cy, double cz,
+                       double sigma, int band_axis, double band_lo, double band_hi, const double* __restrict__ xyz,
+                       int64_t n, int attempts, int32_t* __restrict__ cell_out, R* __restrict__ off_out,
+                       uint8_t* __restrict__ flag) {
+  const DomView& V = views[dom];
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n) return;
+  // particle centres at t = 0
+  const double centre[3] = {cx, cy, cz};
+  bool placed = false;
+  int cell[3] = {0, 0, 0};
+  double o[3] = {0, 0, 0};
+  for (int at = 0; at < attempts && !placed; ++at) {
+    double X[3];
+    if (kind == 3) {
+      X[0] = xyz[3 * w];
+      X[1] = xyz[3 * w + 1];
+      X[2] = xyz[3 * w + 2];
+    } else {
+      const U4 r = philox4x32_10((uint32_t)w, 0xFFFFFFFFu, 16u + (uint32_t)at, 0u, V.key0, V.key1);
+      if (kind == 1) {
+        double z0, z1, z2;
+        gauss3(r, z0, z1, z2);
+        X[0] = centre[0] + sigma * z0;
+        X[1] = centre[1] + sigma * z1;
+        X[2] = centre[2] + sigma * z2;
+      } else {
+        const uint32_t rr[3] = {r.x, r.y, r.z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          double lo = V.bc[a] ? 1.0 : 0.0, hi = V.bc[a] ? (double)(V.n[a] - 1) : (double)V.n[a];
+          if (kind == 2 && a == band_axis) {
+            lo = band_lo;
+            hi = band_hi;
+          }
+          X[a] = lo + unit_open(rr[a]) * (hi - lo);
+        }
+      }
+    }
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double L = (double)V.n[a];
+      double x = X[a];
+      if (!V.bc[a]) {
+        x = x - L * floor(x / L);
+        if (x >= L) x = 0.0;
+      } else if (x < 1.0 || x >= L - 1.0) {
+        ok = false;
+      }
+      const double k = floor(x);
+      cell[a] = (int)k;
+      o[a] = (double)(R)(x - k);
+    }
+    if (!ok) continue;
+    // inside a particle at t = 0?
+    bool inside = false;
+    for (int p = 0; p < V.np && !inside; ++p) {
+      const DevParticle& P = V.parts[p];
+      double pc[3], pv[3];
+      particle_pose(P, 0, pc, pv);
+      const double dx = axis_disp<double>(!V.bc[0], V.n[0], cell[0], pc[0], o[0]);
+      const double dy = axis_disp<double>(!V.bc[1], V.n[1], cell[1], pc[1], o[1]);
+      const double dz = axis_disp<double>(!V.bc[2], V.n[2], cell[2], pc[2], o[2]);
+      if ((dx * dx + dy * dy) + dz * dz >= P.maskr * P.maskr) continue;
+      if (metaball_value<double>(V.ctrl + 4 * P.ctrl0, P.nc, dx, dy, dz) >= 1.0) inside = true;
+    }
+    if (inside) continue;
+    placed = true;
+  }
+  flag[w] = placed ? 1 : 0;
+  cell_out[w] = (int32_t)lin(V, cell[0], cell[1], cell[2]);
+  off_out[w] = (R)o[0];
+  off_out[n + w] = (R)o[1];
+  off_out[2 * n + w] = (R)o[2];
+}
+
+// Scatter the placed walkers (exclusive prefix pos of flag) into the walker
+// arrays, keeping their order.
+template <typename R>
+__global__ void k_seed_scatter(const DomView* __restrict__ views, int dom, int64_t n, const int32_t* __restrict__ cell_in,
+                               const R* __restrict__ off_in, const uint8_t* __restrict__ flag,
+                               const int32_t* __restrict__ pos, int64_t m) {
+  const DomView& V = views[dom];
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n || !flag[w]) return;
+  const int64_t k = pos[w];
+  R* off = (R*)V.woff;
+  V.wcell[k] = cell_in[w];
+  off[k] = off_in[w];
+  off[m + k] = off_in[n + w];
+  off[2 * m + k] = off_in[2 * n + w];
+  V.wimg[k] = 0;
+  V.wimg[m + k] = 0;
+  V.wimg[2 * m + k] = 0;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_occupancy(const DomView* __restrict__ views, int dom) {
+  const DomView& V = views[dom];
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < V.nw) atomicAdd(&V.occ[V.wcell[w]], 1u);
+}
+
+// ---------------------------------------------------------------- moments
+// Deterministic FP64 reductions: chunk k covers elements [k*4096, (k+1)*4096);
+// thread j of the 256-thread block adds elements j, j+256, ... in order, the
+// block then folds the 256 partials by halving; the final kernel adds the
+// chunk partials in chunk order.  The result does not depend on the launch
+// configuration of the stepping kernels.
+constexpr int kRedChunk = 4096;
+constexpr int kRedThreads = 256;
+constexpr int kWalkMom = 6;   // sum d[3], sum d^2[3]
+constexpr int kNodeMom = 12;  // rho, rho u[3], (1-eps) u[3], (1-eps), eps us[3], eps
+
+template <int K>
+__device__ __forceinline__ void block_fold(double (*sh)[kRedThreads], double acc[K], double* out) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) sh[k][tid] = acc[k];
+  __syncthreads();
+  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) sh[k][tid] = sh[k][tid] + sh[k][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid < K) out[tid] = sh[tid][0];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_mom_walkers(const DomView* __restrict__ views, int dom,
+                                                             const double* __restrict__ ref, double* __restrict__ part) {
+  __shared__ double sh[kWalkMom][kRedThreads];
+  const DomView& V = views[dom];
+  const R* off = (const R*)V.woff;
+  const int64_t base = (int64_t)blockIdx.x * kRedChunk;
+  double acc[kWalkMom] = {0, 0, 0, 0, 0, 0};
+  const int nx = V.n[0], ny = V.n[1];
+  for (int j = threadIdx.x; j < kRedChunk; j += kRedThreads) {
+    const int64_t w = base + j;
+    if (w >= V.nw) break;
+    const int32_t lc = V.wcell[w];
+    const int c[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int64_t X = (int64_t)c[a] + (int64_t)V.wimg[a * V.nw + w] * (int64_t)V.n[a];
+      const double dv = ((double)X - ref[a]) + (double)off[a * V.nw + w];
+      acc[a] = acc[a] + dv;
+      acc[3 + a] = acc[3 + a] + dv * dv;
+    }
+  }
+  block_fold<kWalkMom>(sh, acc, part + (int64_t)blockIdx.x * kWalkMom);
+}
+
+template <typename U>
+__global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __restrict__ views, int dom,
+                                                           double* __restrict__ part) {
+  __shared__ double sh[kNodeMom][kRedThreads];
+  __shared__ BlockParticles sp;
+  const DomView& V = views[dom];
+  const int64_t base = (int64_t)blockIdx.x * kRedChunk;
+  const int64_t last = (base + kRedChunk - 1 < V.N) ? base + kRedChunk - 1 : V.N - 1;
+  const bool stepped = V.tstep[0] > 0;
+  if (stepped && V.np > 0) cull_block(V, base, last, sp);
+  else if (threadIdx.x == 0) sp.cnt = 0;
+  __syncthreads();
+  double acc[kNodeMom];
+#pragma unroll
+  for (int k = 0; k < kNodeMom; ++k) acc[k] = 0.0;
+  const U* u4 = (const U*)V.u4;
+  const int nx = V.n[0], ny = V.n[1];
+  for (int j = threadIdx.x; j < kRedChunk; j += kRedThreads) {
+    const int64_t id = base + j;
+    if (id >= V.N) break;
+    const int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
+    bool wall = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (V.bc[a] && (nd[a] == 0 || nd[a] == V.n[a] - 1)) wall = true;
+    if (wall) continue;
+    double es = 0.0, un[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < sp.cnt; ++k) {
+      const double e = (double)node_eps<typename Store<sizeof(U) == 8 ? P64 : P32>::C>(V, sp, k, nd);
+      es = es + e;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) un[a] = un[a] + e * sp.v[k][a];
+    }
+    const double eps = es < 1.0 ? es : 1.0;
+    const double r = (double)u4[4 * id + 3];
+    acc[0] = acc[0] + r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double ua = (double)u4[4 * id + a];
+      const double usa = es > 0.0 ? un[a] / es : 0.0;
+      acc[1 + a] = acc[1 + a] + r * ua;
+      acc[4 + a] = acc[4 + a] + (1.0 - eps) * ua;
+      acc[8 + a] = acc[8 + a] + eps * usa;
+    }
+    acc[7] = acc[7] + (1.0 - eps);
+    acc[11] = acc[11] + eps;
+  }
+  block_fold<kNodeMom>(sh, acc, part + (int64_t)blockIdx.x * kNodeMom);
+}
+
+// out: [0..5] walker sums, [6..17] node sums, [18..25] counters, [26] step
+__global__ void k_mom_final(const DomView* __restrict__ views, int dom, const double* __restrict__ pw, int64_t nbw,
+                            const double* __restrict__ pn, int64_t nbn, double* __restrict__ out) {
+  const DomView& V = views[dom];
+  const int tid = threadIdx.x;
+  if (tid < kWalkMom) {
+    double s = 0.0;
+    for (int64_t b = 0; b < nbw; ++b) s = s + pw[b * kWalkMom + tid];
+    out[tid] = s;
+  } else if (tid < kWalkMom + kNodeMom) {
+    const int k = tid - kWalkMom;
+    double s = 0.0;
+    for (int64_t b = 0; b < nbn; ++b) s = s + pn[b * kNodeMom + k];
+    out[tid] = s;
+  } else if (tid < kWalkMom + kNodeMom + kCounters) {
+    const int k = tid - kWalkMom - kNodeMom;
+    out[tid] = __longlong_as_double((long long)V.counters[k]);
+  } else if (tid == kWalkMom + kNodeMom + kCounters) {
+    out[tid] = __longlong_as_double((long long)V.tstep[0]);
+  }
+}
+
+__global__ void k_normals(uint32_t k0, uint32_t k1, uint32_t t, uint32_t purpose, int64_t n, double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const U4 r = philox4x32_10((uint32_t)i, t, purpose, 0u, k0, k1);
+  double a, b, c;
+  gauss3(r, a, b, c);
+  z[3 * i] = a;
+  z[3 * i + 1] = b;
+  z[3 * i + 2] = c;
+}
+
+}  // namespace rwmi

@@ -1,0 +1,1047 @@
+// Host side of the rwmi C ABI (include/rwmi.h): domain and batch state,
+// device memory, launch sequencing, graph capture, readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rwmi.h"
+#include "dev_common.h"
+#include "launch.h"
+
+using rwmi::DevParticle;
+using rwmi::DomView;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+struct HostParticle {
+  std::vector<double> b, k;
+  double c0[3], amp[3], vel[3], period, phase;
+  int motion;
+};
+
+struct Alloc {
+  rwmi_alloc_fn fa = nullptr;
+  rwmi_free_fn ff = nullptr;
+  void* ctx = nullptr;
+};
+
+size_t elem_size(int prec) { return prec == RWMI_FP64 ? 8 : (prec == RWMI_FP32 ? 4 : 2); }
+size_t u_size(int prec) { return prec == RWMI_FP64 ? 8 : 4; }
+size_t off_size(int prec) { return prec == RWMI_FP64 ? 8 : 4; }
+
+enum { KT_PRO = 0, KT_FLUID = 1, KT_WALK = 2, KT_SLOW = 3, KT_N = 4 };
+
+}  // namespace
+
+struct rwmi_domain {
+  rwmi_domain_desc desc{};
+  int prec = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Alloc al;
+  std::string err = "no error";
+  std::vector<HostParticle> parts;
+  std::vector<void*> owned;  // device allocations to release
+  DomView hv{};
+  DomView* dv = nullptr;    // device copy of hv
+  int32_t* dboff = nullptr; // 4 work maps of 2 entries each
+  bool particles_uploaded = false;
+  bool seeded = false;
+  bool stepped = false;
+  uint64_t steps = 0;
+  double ref[3] = {0, 0, 0};
+  int lbm_bs = 256, walk_bs = 256;
+  bool use_graph = false;
+  bool timing = false;
+  hipGraphExec_t gexec = nullptr;
+  uint32_t gsteps = 0;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  std::vector<std::pair<int, size_t>> evrec;  // (kernel type, index of start event)
+  // lazily allocated readback scratch
+  uint32_t* occ = nullptr;
+  double* mom_part = nullptr;
+  size_t mom_part_n = 0;
+  double* mom_out = nullptr;
+  double* dref = nullptr;
+  rwmi_batch* batch = nullptr;
+};
+
+struct rwmi_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<rwmi_domain*> members;
+  bool dirty = true;
+  // per precision group: device arrays of views and work maps
+  struct Group {
+    int prec;
+    std::vector<rwmi_domain*> doms;
+    DomView* views = nullptr;
+    int32_t* boff = nullptr;  // 4 maps x (nd + 1)
+    int blocks[KT_N] = {0, 0, 0, 0};
+    bool any_walkers = false;
+  };
+  std::vector<Group> groups;
+  std::vector<void*> owned;
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  uint32_t gsteps = 0;
+  int lbm_bs = 256, walk_bs = 256;
+};
+
+namespace {
+
+rwmi_status fail(rwmi_domain* d, rwmi_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (d) d->err = buf;
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(d, call)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail((d), RWMI_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+void* dev_alloc(const Alloc& al, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (al.fa) return al.fa(bytes, al.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+void dev_free(const Alloc& al, void* p) {
+  if (!p) return;
+  if (al.ff) al.ff(p, al.ctx);
+  else (void)hipFree(p);
+}
+
+template <typename T>
+rwmi_status alloc_into(rwmi_domain* d, T*& out, size_t bytes) {
+  void* p = dev_alloc(d->al, bytes);
+  if (!p) return fail(d, RWMI_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  d->owned.push_back(p);
+  out = (T*)p;
+  return RWMI_OK;
+}
+
+void release(rwmi_domain* d, void* p) {
+  if (!p) return;
+  auto it = std::find(d->owned.begin(), d->owned.end(), p);
+  if (it != d->owned.end()) d->owned.erase(it);
+  dev_free(d->al, p);
+}
+
+int64_t mask_blocks(const rwmi_domain_desc& s, int32_t mb[3]) {
+  int64_t t = 1;
+  for (int a = 0; a < 3; ++a) {
+    mb[a] = (s.n[a] + rwmi::kMaskBlock - 1) / rwmi::kMaskBlock;
+    t *= mb[a];
+  }
+  return t;
+}
+
+rwmi_status upload_view(rwmi_domain* d) {
+  HIPCHK(d, hipMemcpyAsync(d->dv, &d->hv, sizeof(DomView), hipMemcpyHostToDevice, d->stream));
+  return RWMI_OK;
+}
+
+int blocks_for(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
+
+int slow_blocks(int64_t nw) {
+  return (int)std::min<int64_t>(std::max<int64_t>(1, (nw + rwmi::kSlowThreads - 1) / rwmi::kSlowThreads), 512);
+}
+
+void kernel_blocks(const rwmi_domain* d, int b[KT_N]) {
+  const int64_t nmb = (int64_t)d->hv.mb[0] * d->hv.mb[1] * d->hv.mb[2];
+  b[KT_PRO] = (d->hv.nw > 0 && d->hv.np > 0) ? blocks_for(nmb, 256) : 1;
+  b[KT_FLUID] = blocks_for(d->hv.N, d->lbm_bs);
+  b[KT_WALK] = blocks_for(d->hv.nw, d->walk_bs);
+  b[KT_SLOW] = slow_blocks(d->hv.nw);
+}
+
+rwmi_status upload_workmaps(rwmi_domain* d) {
+  int b[KT_N];
+  kernel_blocks(d, b);
+  int32_t h[2 * KT_N];
+  for (int k = 0; k < KT_N; ++k) {
+    h[2 * k] = 0;
+    h[2 * k + 1] = b[k];
+  }
+  HIPCHK(d, hipMemcpyAsync(d->dboff, h, sizeof h, hipMemcpyHostToDevice, d->stream));
+  return RWMI_OK;
+}
+
+void drop_graph(rwmi_domain* d) {
+  if (d->gexec) {
+    (void)hipGraphExecDestroy(d->gexec);
+    d->gexec = nullptr;
+    d->gsteps = 0;
+  }
+}
+
+// Upload the particle table and control points (once, before seeding or the
+// first step).
+rwmi_status finalize_particles(rwmi_domain* d) {
+  if (d->particles_uploaded) return RWMI_OK;
+  const int np = (int)d->parts.size();
+  std::vector<DevParticle> hp(std::max(np, 1));
+  std::vector<double> ctrl;
+  for (int p = 0; p < np; ++p) {
+    const HostParticle& q = d->parts[p];
+    DevParticle& r = hp[p];
+    std::memset(&r, 0, sizeof r);
+    const int nc = (int)q.k.size();
+    double K = 0.0, bmax = 0.0;
+    for (int i = 0; i < nc; ++i) {
+      K = K + q.k[i];
+      const double* b = &q.b[3 * i];
+      const double rr = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      if (rr > bmax) bmax = rr;
+    }
+    r.rb = bmax + std::sqrt(K);
+    r.cutsq = (r.rb + 2.0) * (r.rb + 2.0);
+    r.maskr = r.rb + 0.5;
+    for (int a = 0; a < 3; ++a) {
+      r.c0[a] = q.c0[a];
+      r.amp[a] = q.amp[a];
+      r.vel[a] = q.vel[a];
+    }
+    r.period = q.period;
+    r.phase = q.phase;
+    r.motion = q.motion;
+    r.nc = nc;
+    r.ctrl0 = (int)(ctrl.size() / 4);
+    for (int i = 0; i < nc; ++i) {
+      ctrl.push_back(q.b[3 * i]);
+      ctrl.push_back(q.b[3 * i + 1]);
+      ctrl.push_back(q.b[3 * i + 2]);
+      ctrl.push_back(q.k[i]);
+    }
+  }
+  DevParticle* dp;
+  double* dc;
+  double* dpose;
+  rwmi_status st;
+  if ((st = alloc_into(d, dp, sizeof(DevParticle) * hp.size())) != RWMI_OK) return st;
+  if ((st = alloc_into(d, dc, sizeof(double) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
+  if ((st = alloc_into(d, dpose, sizeof(double) * 12 * std::max(np, 1))) != RWMI_OK) return st;
+  HIPCHK(d, hipMemcpyAsync(dp, hp.data(), sizeof(DevParticle) * hp.size(), hipMemcpyHostToDevice, d->stream));
+  if (!ctrl.empty())
+    HIPCHK(d, hipMemcpyAsync(dc, ctrl.data(), sizeof(double) * ctrl.size(), hipMemcpyHostToDevice, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));  // host vectors go out of scope
+  d->hv.parts = dp;
+  d->hv.ctrl = dc;
+  d->hv.pose = dpose;
+  d->hv.np = np;
+  if (np > 0) {
+    unsigned long long* mask;
+    int32_t mb[3];
+    const int64_t nmb = mask_blocks(d->desc, mb);
+    if ((st = alloc_into(d, mask, 8 * nmb)) != RWMI_OK) return st;
+    d->hv.mask = mask;
+  }
+  d->particles_uploaded = true;
+  if ((st = upload_view(d)) != RWMI_OK) return st;
+  return upload_workmaps(d);
+}
+
+hipEvent_t take_event(rwmi_domain* d) {
+  if (d->evused == d->evpool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    d->evpool.push_back(e);
+  }
+  return d->evpool[d->evused++];
+}
+
+// One coupled step for a single domain (eager launches).
+rwmi_status enqueue_step(rwmi_domain* d, bool record) {
+  const DomView* v = d->dv;
+  int b[KT_N];
+  kernel_blocks(d, b);
+  const rwmi::Work wpro{v, d->dboff + 0, 1, b[KT_PRO]};
+  const rwmi::Work wflu{v, d->dboff + 2, 1, b[KT_FLUID]};
+  const rwmi::Work wwal{v, d->dboff + 4, 1, b[KT_WALK]};
+  const rwmi::Work wslo{v, d->dboff + 6, 1, b[KT_SLOW]};
+  auto timed = [&](int kt, auto&& launch) -> rwmi_status {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    size_t i0 = 0;
+    if (record) {
+      i0 = d->evused;
+      e0 = take_event(d);
+      e1 = take_event(d);
+      if (!e0 || !e1) return fail(d, RWMI_EDEVICE, "hipEventCreate failed");
+      HIPCHK(d, hipEventRecord(e0, d->stream));
+    }
+    HIPCHK(d, launch());
+    if (record) {
+      HIPCHK(d, hipEventRecord(e1, d->stream));
+      d->evrec.push_back({kt, i0});
+    }
+    return RWMI_OK;
+  };
+  rwmi_status st;
+  if ((st = timed(KT_PRO, [&] { return rwmi::launch_prologue(wpro, d->stream); })) != RWMI_OK) return st;
+  if ((st = timed(KT_FLUID, [&] { return rwmi::launch_fluid(d->prec, d->lbm_bs, wflu, d->stream); })) != RWMI_OK)
+    return st;
+  if (d->hv.nw > 0) {
+    if ((st = timed(KT_WALK, [&] { return rwmi::launch_walk(d->prec, d->walk_bs, wwal, d->stream); })) != RWMI_OK)
+      return st;
+    if (d->hv.np > 0 &&
+        (st = timed(KT_SLOW, [&] { return rwmi::launch_walk_slow(d->prec, wslo, d->stream); })) != RWMI_OK)
+      return st;
+  }
+  return RWMI_OK;
+}
+
+bool valid_prec(int p) { return p >= RWMI_FP64 && p <= RWMI_BF16_STORE; }
+
+}  // namespace
+
+extern "C" {
+
+uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, uint32_t n_ctrl_total,
+                              uint64_t n_walkers) {
+  if (!s) return 0;
+  const uint64_t N = (uint64_t)s->n[0] * s->n[1] * s->n[2];
+  const int p = s->precision;
+  int32_t mb[3];
+  const uint64_t nmb = (uint64_t)mask_blocks(*s, mb);
+  uint64_t b = 0;
+  b += 2 * 19 * N * elem_size(p) + 4 * N * u_size(p);
+  b += sizeof(DomView) + 64 + 16;
+  b += n_particles * sizeof(DevParticle) + 32 * n_ctrl_total + 96 * n_particles + (n_particles ? 8 * nmb : 0);
+  // walkers: cell, offsets, images, queue (id + step), moment partials
+  b += n_walkers * (4 + 3 * off_size(p) + 12 + 4 + 3 * off_size(p));
+  b += 4 * N;  // occupancy
+  b += 8 * (6 * ((n_walkers + 4095) / 4096) + 12 * ((N + 4095) / 4096) + 64);
+  return b;
+}
+
+rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
+  if (!s || !out) return fail(nullptr, RWMI_EINVAL, "null argument");
+  *out = nullptr;
+  for (int a = 0; a < 3; ++a) {
+    if (s->n[a] < 1) return fail(nullptr, RWMI_EINVAL, "n[%d] = %d must be >= 1", a, s->n[a]);
+    if (s->bc[a] != RWMI_BC_PERIODIC && s->bc[a] != RWMI_BC_WALL)
+      return fail(nullptr, RWMI_EINVAL, "bc[%d] = %d unknown", a, s->bc[a]);
+    if (s->bc[a] == RWMI_BC_WALL && s->n[a] < 3)
+      return fail(nullptr, RWMI_EINVAL, "a wall axis needs at least 3 nodes (axis %d)", a);
+  }
+  const int64_t N = (int64_t)s->n[0] * s->n[1] * s->n[2];
+  if (N > ((int64_t)1 << 31) - 1) return fail(nullptr, RWMI_EINVAL, "lattice of %lld nodes too large", (long long)N);
+  if (!(s->tau > 0.5)) return fail(nullptr, RWMI_EINVAL, "tau = %g must be > 0.5", s->tau);
+  if (!(s->diffusivity >= 0.0)) return fail(nullptr, RWMI_EINVAL, "diffusivity must be >= 0");
+  if (!valid_prec(s->precision)) return fail(nullptr, RWMI_EINVAL, "precision %d unknown", s->precision);
+  if ((s->alloc == nullptr) != (s->free == nullptr))
+    return fail(nullptr, RWMI_EINVAL, "alloc and free callbacks must be given together");
+  {
+    const hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return fail(nullptr, RWMI_EDEVICE, "hipSetDevice(%d) failed: %s", s->device, hipGetErrorString(e));
+  }
+
+  rwmi_domain* d = new rwmi_domain();
+  d->desc = *s;
+  d->prec = s->precision;
+  d->device = s->device;
+  d->al.fa = s->alloc;
+  d->al.ff = s->free;
+  d->al.ctx = s->alloc_ctx;
+  if (s->stream) {
+    d->stream = (hipStream_t)s->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete d;
+      return fail(nullptr, RWMI_EDEVICE, "hipStreamCreate failed");
+    }
+    d->own_stream = true;
+  }
+  DomView& v = d->hv;
+  std::memset(&v, 0, sizeof v);
+  for (int a = 0; a < 3; ++a) {
+    v.n[a] = s->n[a];
+    v.bc[a] = s->bc[a];
+  }
+  mask_blocks(*s, v.mb);
+  v.N = N;
+  v.prec = d->prec;
+  const double rho0 = s->rho0 > 0 ? s->rho0 : 1.0;
+  v.tau = s->tau;
+  v.omega = 1.0 / s->tau;
+  v.tm = s->tau - 0.5;
+  v.cfree = 1.0 - 0.5 * v.omega;
+  v.rho0 = rho0;
+  v.sD = std::sqrt(2.0 * s->diffusivity);
+  v.omega_f = (float)v.omega;
+  v.tm_f = (float)v.tm;
+  v.cfree_f = (float)v.cfree;
+  v.rho0_f = (float)rho0;
+  v.sD_f = (float)v.sD;
+  v.has_force = 0;
+  for (int a = 0; a < 3; ++a) {
+    v.F[a] = s->force[a];
+    v.F_f[a] = (float)s->force[a];
+    v.halfF_f[a] = (float)(0.5 * s->force[a]);
+    if (s->force[a] != 0.0) v.has_force = 1;
+    for (int c = 0; c < 3; ++c) {
+      v.wu[a][0][c] = s->wall_u_lo[a][c];
+      v.wu[a][1][c] = s->wall_u_hi[a][c];
+      v.wu_f[a][0][c] = (float)s->wall_u_lo[a][c];
+      v.wu_f[a][1][c] = (float)s->wall_u_hi[a][c];
+    }
+  }
+  v.key0 = (uint32_t)s->seed;
+  v.key1 = (uint32_t)(s->seed >> 32);
+  v.max_bisect = 200;
+
+  rwmi_status st = RWMI_OK;
+  void *fA, *fB, *u4;
+  uint64_t* tstep;
+  unsigned long long* cnt;
+  if ((st = alloc_into(d, fA, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
+      (st = alloc_into(d, fB, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
+      (st = alloc_into(d, u4, 4 * (size_t)N * u_size(d->prec))) != RWMI_OK ||
+      (st = alloc_into(d, tstep, 16)) != RWMI_OK || (st = alloc_into(d, cnt, 8 * rwmi::kCounters)) != RWMI_OK ||
+      (st = alloc_into(d, d->dv, sizeof(DomView))) != RWMI_OK ||
+      (st = alloc_into(d, d->dboff, sizeof(int32_t) * 2 * KT_N)) != RWMI_OK) {
+    rwmi_destroy_domain(d);
+    return fail(nullptr, st, "%s", g_err.c_str());
+  }
+  v.fA = fA;
+  v.fB = fB;
+  v.u4 = u4;
+  v.tstep = tstep;
+  v.counters = cnt;
+  uint64_t zeros[rwmi::kCounters] = {0};
+  if (hipMemcpyAsync(tstep, zeros, 16, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
+      hipMemcpyAsync(cnt, zeros, sizeof zeros, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
+      upload_view(d) != RWMI_OK || upload_workmaps(d) != RWMI_OK ||
+      rwmi::launch_init(d->prec, d->dv, 0, N, s->u0, d->stream) != hipSuccess ||
+      hipStreamSynchronize(d->stream) != hipSuccess) {
+    rwmi_destroy_domain(d);
+    return fail(nullptr, RWMI_EDEVICE, "device initialisation failed");
+  }
+  *out = d;
+  return RWMI_OK;
+}
+
+void rwmi_destroy_domain(rwmi_domain* d) {
+  if (!d) return;
+  (void)hipSetDevice(d->device);
+  if (d->stream) (void)hipStreamSynchronize(d->stream);
+  drop_graph(d);
+  for (hipEvent_t e : d->evpool) (void)hipEventDestroy(e);
+  for (void* p : d->owned) dev_free(d->al, p);
+  if (d->own_stream) (void)hipStreamDestroy(d->stream);
+  delete d;
+}
+
+rwmi_status rwmi_add_metaball_particle(rwmi_domain* d, const rwmi_metaball_desc* p, int32_t* out_id) {
+  if (!d || !p) return fail(d, RWMI_EINVAL, "null argument");
+  if (d->seeded || d->stepped || d->particles_uploaded)
+    return fail(d, RWMI_ESTATE, "particles must be added before seeding and stepping");
+  if ((int)d->parts.size() >= RWMI_MAX_PARTICLES) return fail(d, RWMI_EINVAL, "at most %d particles", RWMI_MAX_PARTICLES);
+  if (p->n_ctrl < 1 || p->n_ctrl > RWMI_MAX_CTRL || !p->offsets || !p->weights)
+    return fail(d, RWMI_EINVAL, "n_ctrl = %d out of range", p->n_ctrl);
+  if (p->motion < RWMI_MOTION_STATIC || p->motion > RWMI_MOTION_CONST_VEL) return fail(d, RWMI_EINVAL, "bad motion");
+  if (p->motion == RWMI_MOTION_SINUSOID && !(p->period > 0.0)) return fail(d, RWMI_EINVAL, "period must be > 0");
+  HostParticle h;
+  h.b.assign(p->offsets, p->offsets + 3 * p->n_ctrl);
+  h.k.assign(p->weights, p->weights + p->n_ctrl);
+  for (double k : h.k)
+    if (!(k > 0.0)) return fail(d, RWMI_EINVAL, "control-point weights must be > 0");
+  for (int a = 0; a < 3; ++a) {
+    h.c0[a] = p->centre[a];
+    h.amp[a] = p->amplitude[a];
+    h.vel[a] = p->velocity[a];
+  }
+  h.period = p->motion == RWMI_MOTION_SINUSOID ? p->period : 1.0;
+  h.phase = p->phase;
+  h.motion = p->motion;
+  d->parts.push_back(h);
+  if (out_id) *out_id = (int32_t)d->parts.size() - 1;
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_seed_walkers(rwmi_domain* d, const rwmi_seed_desc* s, uint64_t n, uint64_t* out_seeded) {
+  if (!d || !s) return fail(d, RWMI_EINVAL, "null argument");
+  if (out_seeded) *out_seeded = 0;
+  if (d->seeded || d->stepped) return fail(d, RWMI_ESTATE, "walkers can be seeded once, before the first step");
+  if (n > (uint64_t)INT32_MAX) return fail(d, RWMI_EINVAL, "too many walkers");
+  if (s->kind < RWMI_SEED_UNIFORM || s->kind > RWMI_SEED_EXPLICIT) return fail(d, RWMI_EINVAL, "bad seed kind");
+  if (s->kind == RWMI_SEED_EXPLICIT && n > 0 && !s->xyz) return fail(d, RWMI_EINVAL, "explicit seeding needs xyz");
+  if (s->kind == RWMI_SEED_BAND && (s->band_axis < 0 || s->band_axis > 2 || !(s->band_hi > s->band_lo)))
+    return fail(d, RWMI_EINVAL, "bad band");
+  HIPCHK(d, hipSetDevice(d->device));
+  rwmi_status st;
+  if ((st = finalize_particles(d)) != RWMI_OK) return st;
+  const size_t osz = off_size(d->prec);
+  const int64_t nn = (int64_t)n;
+  int32_t* tcell = nullptr;
+  void* toff = nullptr;
+  uint8_t* flag = nullptr;
+  int32_t* pos = nullptr;
+  double* dxyz = nullptr;
+  std::vector<void*> tmp;
+  auto cleanup = [&] {
+    for (void* p : tmp) release(d, p);
+  };
+  if (nn > 0) {
+    if ((st = alloc_into(d, tcell, 4 * nn)) != RWMI_OK) return st;
+    tmp.push_back(tcell);
+    if ((st = alloc_into(d, toff, 3 * osz * nn)) != RWMI_OK) return cleanup(), st;
+    tmp.push_back(toff);
+    if ((st = alloc_into(d, flag, nn)) != RWMI_OK) return cleanup(), st;
+    tmp.push_back(flag);
+    if ((st = alloc_into(d, pos, 4 * nn)) != RWMI_OK) return cleanup(), st;
+    tmp.push_back(pos);
+    if (s->kind == RWMI_SEED_EXPLICIT) {
+      if ((st = alloc_into(d, dxyz, 24 * nn)) != RWMI_OK) return cleanup(), st;
+      tmp.push_back(dxyz);
+      if (hipMemcpyAsync(dxyz, s->xyz, 24 * nn, hipMemcpyHostToDevice, d->stream) != hipSuccess)
+        return cleanup(), fail(d, RWMI_EDEVICE, "copy of explicit positions failed");
+    }
+  }
+  const int attempts = s->kind == RWMI_SEED_EXPLICIT || s->remove_inside ? 1 : (s->max_attempts > 0 ? s->max_attempts : 64);
+  std::vector<uint8_t> hflag(nn);
+  if (nn > 0) {
+    if (rwmi::launch_seed(d->prec, d->dv, 0, s->kind, s->centre, s->sigma, s->band_axis, s->band_lo, s->band_hi, dxyz,
+                          nn, attempts, tcell, toff, flag, d->stream) != hipSuccess ||
+        hipMemcpyAsync(hflag.data(), flag, nn, hipMemcpyDeviceToHost, d->stream) != hipSuccess ||
+        hipStreamSynchronize(d->stream) != hipSuccess)
+      return cleanup(), fail(d, RWMI_EDEVICE, "seeding kernel failed");
+  }
+  std::vector<int32_t> hpos(nn);
+  int64_t m = 0;
+  for (int64_t w = 0; w < nn; ++w) {
+    hpos[w] = (int32_t)m;
+    m += hflag[w];
+  }
+  // walker arrays of the final size
+  int32_t *wcell, *wimg, *qid;
+  void *woff, *qdl;
+  uint32_t* qcount;
+  if ((st = alloc_into(d, wcell, 4 * std::max<int64_t>(m, 1))) != RWMI_OK ||
+      (st = alloc_into(d, woff, 3 * osz * std::max<int64_t>(m, 1))) != RWMI_OK ||
+      (st = alloc_into(d, wimg, 12 * std::max<int64_t>(m, 1))) != RWMI_OK ||
+      (st = alloc_into(d, qid, 4 * std::max<int64_t>(m, 1))) != RWMI_OK ||
+      (st = alloc_into(d, qdl, 3 * osz * std::max<int64_t>(m, 1))) != RWMI_OK ||
+      (st = alloc_into(d, qcount, 16)) != RWMI_OK)
+    return cleanup(), st;
+  d->hv.wcell = wcell;
+  d->hv.woff = woff;
+  d->hv.wimg = wimg;
+  d->hv.qid = qid;
+  d->hv.qdl = qdl;
+  d->hv.qcount = qcount;
+  d->hv.nw = m;
+  d->hv.qcap = std::max<int64_t>(m, 1);
+  if ((st = upload_view(d)) != RWMI_OK) return cleanup(), st;
+  if (m > 0) {
+    if (hipMemcpyAsync(pos, hpos.data(), 4 * nn, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
+        rwmi::launch_seed_scatter(d->prec, d->dv, 0, nn, tcell, toff, flag, pos, m, d->stream) != hipSuccess)
+      return cleanup(), fail(d, RWMI_EDEVICE, "seed scatter failed");
+  }
+  if (hipStreamSynchronize(d->stream) != hipSuccess) return cleanup(), fail(d, RWMI_EDEVICE, "seeding failed");
+  cleanup();
+  for (int a = 0; a < 3; ++a) d->ref[a] = s->ref[a];
+  d->seeded = true;
+  if ((st = upload_workmaps(d)) != RWMI_OK) return st;
+  drop_graph(d);
+  if (out_seeded) *out_seeded = (uint64_t)m;
+  if (m < nn && !s->remove_inside)
+    return fail(d, RWMI_ESEED, "%lld of %lld walkers found no admissible position", (long long)(nn - m), (long long)nn);
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_step(rwmi_domain* d, uint32_t n_steps) {
+  if (!d) return fail(d, RWMI_EINVAL, "null domain");
+  if (d->batch) return fail(d, RWMI_ESTATE, "domain is stepped by its batch");
+  HIPCHK(d, hipSetDevice(d->device));
+  rwmi_status st;
+  if ((st = finalize_particles(d)) != RWMI_OK) return st;
+  d->stepped = true;
+  uint32_t left = n_steps;
+  if (d->use_graph && !d->timing && n_steps >= 2) {
+    const uint32_t k = std::min<uint32_t>(n_steps, 64);
+    if (!d->gexec || d->gsteps != k) {
+      drop_graph(d);
+      hipGraph_t g;
+      HIPCHK(d, hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal));
+      for (uint32_t i = 0; i < k; ++i) {
+        if ((st = enqueue_step(d, false)) != RWMI_OK) {
+          hipGraph_t junk;
+          (void)hipStreamEndCapture(d->stream, &junk);
+          if (junk) (void)hipGraphDestroy(junk);
+          return st;
+        }
+      }
+      HIPCHK(d, hipStreamEndCapture(d->stream, &g));
+      hipError_t e = hipGraphInstantiate(&d->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(d, RWMI_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+      d->gsteps = k;
+    }
+    while (left >= d->gsteps) {
+      HIPCHK(d, hipGraphLaunch(d->gexec, d->stream));
+      left -= d->gsteps;
+      d->steps += d->gsteps;
+    }
+  }
+  for (; left > 0; --left) {
+    if ((st = enqueue_step(d, d->timing)) != RWMI_OK) return st;
+    d->steps++;
+  }
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_synchronize(rwmi_domain* d) {
+  if (!d) return fail(d, RWMI_EINVAL, "null domain");
+  HIPCHK(d, hipSetDevice(d->device));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_query_sizes(const rwmi_domain* d, uint64_t* n_nodes, uint64_t* n_walkers, uint64_t* step) {
+  if (!d) return fail(nullptr, RWMI_EINVAL, "null domain");
+  if (n_nodes) *n_nodes = (uint64_t)d->hv.N;
+  if (n_walkers) *n_walkers = (uint64_t)d->hv.nw;
+  if (step) *step = d->steps;
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_read_velocity(rwmi_domain* d, double* u, double* rho) {
+  if (!d) return fail(d, RWMI_EINVAL, "null domain");
+  HIPCHK(d, hipSetDevice(d->device));
+  const int64_t N = d->hv.N;
+  const size_t us = u_size(d->prec);
+  std::vector<unsigned char> h(4 * N * us);
+  HIPCHK(d, hipMemcpyAsync(h.data(), d->hv.u4, h.size(), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  for (int64_t i = 0; i < N; ++i) {
+    for (int c = 0; c < 4; ++c) {
+      double v;
+      if (us == 8) v = ((const double*)h.data())[4 * i + c];
+      else v = ((const float*)h.data())[4 * i + c];
+      if (c < 3) {
+        if (u) u[c * N + i] = v;
+      } else if (rho) {
+        rho[i] = v;
+      }
+    }
+  }
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_read_walkers(rwmi_domain* d, int32_t* cell, double* off, int32_t* img) {
+  if (!d) return fail(d, RWMI_EINVAL, "null domain");
+  HIPCHK(d, hipSetDevice(d->device));
+  const int64_t m = d->hv.nw;
+  if (m == 0) return RWMI_OK;
+  if (cell) HIPCHK(d, hipMemcpyAsync(cell, d->hv.wcell, 4 * m, hipMemcpyDeviceToHost, d->stream));
+  if (img) HIPCHK(d, hipMemcpyAsync(img, d->hv.wimg, 12 * m, hipMemcpyDeviceToHost, d->stream));
+  std::vector<float> hf;
+  if (off) {
+    if (d->prec == RWMI_FP64) {
+      HIPCHK(d, hipMemcpyAsync(off, d->hv.woff, 24 * m, hipMemcpyDeviceToHost, d->stream));
+    } else {
+      hf.resize(3 * m);
+      HIPCHK(d, hipMemcpyAsync(hf.data(), d->hv.woff, 12 * m, hipMemcpyDeviceToHost, d->stream));
+    }
+  }
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  if (off && d->prec != RWMI_FP64)
+    for (int64_t i = 0; i < 3 * m; ++i) off[i] = hf[i];
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_read_distributions(rwmi_domain* d, double* f) {
+  if (!d || !f) return fail(d, RWMI_EINVAL, "null argument");
+  HIPCHK(d, hipSetDevice(d->device));
+  const int64_t N = d->hv.N;
+  double* tmp;
+  rwmi_status st;
+  if ((st = alloc_into(d, tmp, 8 * 19 * (size_t)N)) != RWMI_OK) return st;
+  hipError_t e = rwmi::launch_read_f(d->prec, d->dv, 0, N, tmp, d->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, 8 * 19 * (size_t)N, hipMemcpyDeviceToHost, d->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
+  release(d, tmp);
+  if (e != hipSuccess) return fail(d, RWMI_EDEVICE, "read_distributions: %s", hipGetErrorString(e));
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_read_occupancy(rwmi_domain* d, uint32_t* ns) {
+  if (!d || !ns) return fail(d, RWMI_EINVAL, "null argument");
+  HIPCHK(d, hipSetDevice(d->device));
+  rwmi_status st;
+  if (!d->occ && (st = alloc_into(d, d->occ, 4 * (size_t)d->hv.N)) != RWMI_OK) return st;
+  if (!d->hv.occ) {
+    d->hv.occ = d->occ;
+    if ((st = upload_view(d)) != RWMI_OK) return st;
+    drop_graph(d);
+  }
+  HIPCHK(d, rwmi::launch_occupancy(d->dv, 0, d->occ, d->hv.N, d->hv.nw, d->stream));
+  HIPCHK(d, hipMemcpyAsync(ns, d->occ, 4 * (size_t)d->hv.N, hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_read_moments(rwmi_domain* d, rwmi_moments* out) {
+  if (!d || !out) return fail(d, RWMI_EINVAL, "null argument");
+  HIPCHK(d, hipSetDevice(d->device));
+  rwmi_status st;
+  if ((st = finalize_particles(d)) != RWMI_OK) return st;
+  const int64_t N = d->hv.N, nw = d->hv.nw;
+  const size_t need = 6 * ((nw + 4095) / 4096) + 12 * ((N + 4095) / 4096) + 8;
+  if (d->mom_part_n < need) {
+    release(d, d->mom_part);
+    d->mom_part = nullptr;
+    if ((st = alloc_into(d, d->mom_part, 8 * need)) != RWMI_OK) return st;
+    d->mom_part_n = need;
+  }
+  if (!d->mom_out && (st = alloc_into(d, d->mom_out, 8 * 32)) != RWMI_OK) return st;
+  if (!d->dref && (st = alloc_into(d, d->dref, 8 * 4)) != RWMI_OK) return st;
+  HIPCHK(d, hipMemcpyAsync(d->dref, d->ref, 24, hipMemcpyHostToDevice, d->stream));
+  double* pw = d->mom_part;
+  double* pn = d->mom_part + 6 * ((nw + 4095) / 4096);
+  HIPCHK(d, rwmi::launch_moments(d->prec, d->dv, 0, N, nw, d->dref, pw, pn, d->mom_out, d->stream));
+  double h[32];
+  HIPCHK(d, hipMemcpyAsync(h, d->mom_out, sizeof h, hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  std::memset(out, 0, sizeof *out);
+  uint64_t u64[rwmi::kCounters + 1];
+  std::memcpy(u64, h + 18, sizeof u64);
+  out->step = u64[rwmi::kCounters];
+  out->n_walkers = (uint64_t)nw;
+  for (int a = 0; a < 3; ++a) {
+    out->sum[a] = h[a];
+    out->sumsq[a] = h[3 + a];
+    out->momentum[a] = h[7 + a];
+    out->fluid_u[a] = h[13] > 0.0 ? h[10 + a] / h[13] : 0.0;
+    out->particle_v[a] = h[17] > 0.0 ? h[14 + a] / h[17] : 0.0;
+  }
+  out->mass = h[6];
+  out->solid_volume = h[17];
+  out->type2 = u64[rwmi::kType2];
+  out->type4 = u64[rwmi::kType4];
+  out->bisect_fail = u64[rwmi::kBisectFail];
+  out->refill_fallback = u64[rwmi::kRefillFallback];
+  out->returned_to_origin = u64[rwmi::kReturned];
+  out->wall_reflect = u64[rwmi::kWallReflect];
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
+  if (!d) return fail(d, RWMI_EINVAL, "null domain");
+  HIPCHK(d, hipSetDevice(d->device));
+  switch (key) {
+    case RWMI_KEY_MAX_BISECT:
+      if (value < 1 || value > 100000) return fail(d, RWMI_EINVAL, "max_bisect out of range");
+      d->hv.max_bisect = (int32_t)value;
+      drop_graph(d);
+      return upload_view(d);
+    case RWMI_KEY_USE_GRAPH:
+      d->use_graph = value != 0;
+      if (!d->use_graph) drop_graph(d);
+      return RWMI_OK;
+    case RWMI_KEY_LBM_BLOCK:
+      if (value != 128 && value != 256 && value != 512) return fail(d, RWMI_EINVAL, "fluid block must be 128, 256 or 512");
+      d->lbm_bs = (int)value;
+      drop_graph(d);
+      return upload_workmaps(d);
+    case RWMI_KEY_WALK_BLOCK:
+      if (value != 128 && value != 256) return fail(d, RWMI_EINVAL, "walker block must be 128 or 256");
+      d->walk_bs = (int)value;
+      drop_graph(d);
+      return upload_workmaps(d);
+    case RWMI_KEY_TIMING:
+      d->timing = value != 0;
+      return RWMI_OK;
+    default:
+      return fail(d, RWMI_EINVAL, "unknown key %d", key);
+  }
+}
+
+rwmi_status rwmi_read_kernel_times(rwmi_domain* d, double ms[4], uint64_t launches[4]) {
+  if (!d || !ms || !launches) return fail(d, RWMI_EINVAL, "null argument");
+  HIPCHK(d, hipSetDevice(d->device));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  for (int k = 0; k < KT_N; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (auto& r : d->evrec) {
+    float t = 0.0f;
+    HIPCHK(d, hipEventElapsedTime(&t, d->evpool[r.second], d->evpool[r.second + 1]));
+    ms[r.first] += t;
+    launches[r.first]++;
+  }
+  d->evrec.clear();
+  d->evused = 0;
+  return RWMI_OK;
+}
+
+const char* rwmi_last_error(const rwmi_domain* d) { return d ? d->err.c_str() : g_err.c_str(); }
+
+rwmi_status rwmi_device_normals(int32_t device, uint64_t seed, uint32_t t, uint32_t purpose, uint64_t n, double* z) {
+  if (!z && n) return fail(nullptr, RWMI_EINVAL, "null output");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, RWMI_EDEVICE, "hipSetDevice failed");
+  if (n == 0) return RWMI_OK;
+  double* dz = nullptr;
+  if (hipMalloc(&dz, 24 * n) != hipSuccess) return fail(nullptr, RWMI_ENOMEM, "hipMalloc failed");
+  hipError_t e = rwmi::launch_normals(seed, t, purpose, (int64_t)n, dz, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(z, dz, 24 * n, hipMemcpyDeviceToHost);
+  (void)hipFree(dz);
+  if (e != hipSuccess) return fail(nullptr, RWMI_EDEVICE, "normals: %s", hipGetErrorString(e));
+  return RWMI_OK;
+}
+
+// ---------------------------------------------------------------- batch
+
+static rwmi_status bfail(rwmi_batch* b, rwmi_status st, const char* msg) {
+  if (b) b->err = msg;
+  g_err = msg;
+  return st;
+}
+
+rwmi_status rwmi_batch_create(int32_t device, void* stream, rwmi_batch** out) {
+  if (!out) return bfail(nullptr, RWMI_EINVAL, "null argument");
+  if (hipSetDevice(device) != hipSuccess) return bfail(nullptr, RWMI_EDEVICE, "hipSetDevice failed");
+  rwmi_batch* b = new rwmi_batch();
+  b->device = device;
+  if (stream) {
+    b->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return bfail(nullptr, RWMI_EDEVICE, "hipStreamCreate failed");
+    }
+    b->own_stream = true;
+  }
+  *out = b;
+  return RWMI_OK;
+}
+
+static void batch_drop_graph(rwmi_batch* b) {
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->gsteps = 0;
+  }
+}
+
+static void batch_free_groups(rwmi_batch* b) {
+  for (void* p : b->owned) (void)hipFree(p);
+  b->owned.clear();
+  b->groups.clear();
+}
+
+rwmi_status rwmi_batch_add(rwmi_batch* b, rwmi_domain* d) {
+  if (!b || !d) return bfail(b, RWMI_EINVAL, "null argument");
+  if (d->batch) return bfail(b, RWMI_ESTATE, "domain already in a batch");
+  if (d->device != b->device) return bfail(b, RWMI_EINVAL, "domain lives on another device");
+  if (hipSetDevice(d->device) != hipSuccess) return bfail(b, RWMI_EDEVICE, "hipSetDevice failed");
+  if (finalize_particles(d) != RWMI_OK) return bfail(b, RWMI_EDEVICE, d->err.c_str());
+  d->batch = b;
+  b->members.push_back(d);
+  b->dirty = true;
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_batch_remove(rwmi_batch* b, rwmi_domain* d) {
+  if (!b || !d) return bfail(b, RWMI_EINVAL, "null argument");
+  auto it = std::find(b->members.begin(), b->members.end(), d);
+  if (it == b->members.end()) return bfail(b, RWMI_EINVAL, "domain not in this batch");
+  if (hipSetDevice(b->device) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)
+    return bfail(b, RWMI_EDEVICE, "batch synchronisation failed");
+  b->members.erase(it);
+  d->batch = nullptr;
+  b->dirty = true;
+  return RWMI_OK;
+}
+
+// Rebuild the per-precision view arrays and work maps of the batch.
+static rwmi_status batch_rebuild(rwmi_batch* b) {
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, RWMI_EDEVICE, "batch sync failed");
+  batch_drop_graph(b);
+  batch_free_groups(b);
+  for (int prec = 0; prec < 4; ++prec) {
+    rwmi_batch::Group g;
+    g.prec = prec;
+    for (rwmi_domain* d : b->members)
+      if (d->prec == prec) g.doms.push_back(d);
+    if (g.doms.empty()) continue;
+    const int nd = (int)g.doms.size();
+    std::vector<DomView> hv(nd);
+    std::vector<int32_t> boff(KT_N * (nd + 1));
+    for (int k = 0; k < KT_N; ++k) {
+      int acc = 0;
+      for (int i = 0; i < nd; ++i) {
+        rwmi_domain* d = g.doms[i];
+        const int lbs = d->lbm_bs, wbs = d->walk_bs;
+        d->lbm_bs = b->lbm_bs;
+        d->walk_bs = b->walk_bs;
+        int bl[KT_N];
+        kernel_blocks(d, bl);
+        d->lbm_bs = lbs;
+        d->walk_bs = wbs;
+        boff[k * (nd + 1) + i] = acc;
+        int nb = bl[k];
+        if ((k == KT_WALK || k == KT_SLOW) && d->hv.nw == 0) nb = 0;
+        if (k == KT_SLOW && d->hv.np == 0) nb = 0;
+        acc += nb;
+      }
+      boff[k * (nd + 1) + nd] = acc;
+      g.blocks[k] = acc;
+    }
+    for (int i = 0; i < nd; ++i) {
+      hv[i] = g.doms[i]->hv;
+      if (g.doms[i]->hv.nw > 0) g.any_walkers = true;
+    }
+    if (hipMalloc(&g.views, sizeof(DomView) * nd) != hipSuccess ||
+        hipMalloc(&g.boff, sizeof(int32_t) * boff.size()) != hipSuccess)
+      return bfail(b, RWMI_ENOMEM, "batch allocation failed");
+    b->owned.push_back(g.views);
+    b->owned.push_back(g.boff);
+    if (hipMemcpy(g.views, hv.data(), sizeof(DomView) * nd, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.boff, boff.data(), sizeof(int32_t) * boff.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return bfail(b, RWMI_EDEVICE, "batch upload failed");
+    b->groups.push_back(g);
+  }
+  b->dirty = false;
+  return RWMI_OK;
+}
+
+static rwmi_status batch_enqueue_step(rwmi_batch* b) {
+  for (auto& g : b->groups) {
+    const int nd = (int)g.doms.size();
+    const rwmi::Work wpro{g.views, g.boff + 0 * (nd + 1), nd, g.blocks[KT_PRO]};
+    const rwmi::Work wflu{g.views, g.boff + 1 * (nd + 1), nd, g.blocks[KT_FLUID]};
+    const rwmi::Work wwal{g.views, g.boff + 2 * (nd + 1), nd, g.blocks[KT_WALK]};
+    const rwmi::Work wslo{g.views, g.boff + 3 * (nd + 1), nd, g.blocks[KT_SLOW]};
+    if (rwmi::launch_prologue(wpro, b->stream) != hipSuccess ||
+        rwmi::launch_fluid(g.prec, b->lbm_bs, wflu, b->stream) != hipSuccess)
+      return bfail(b, RWMI_EDEVICE, "batch launch failed");
+    if (g.blocks[KT_WALK] > 0 && rwmi::launch_walk(g.prec, b->walk_bs, wwal, b->stream) != hipSuccess)
+      return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
+    if (g.blocks[KT_SLOW] > 0 && rwmi::launch_walk_slow(g.prec, wslo, b->stream) != hipSuccess)
+      return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
+  }
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps) {
+  if (!b) return bfail(b, RWMI_EINVAL, "null batch");
+  if (hipSetDevice(b->device) != hipSuccess) return bfail(b, RWMI_EDEVICE, "hipSetDevice failed");
+  for (rwmi_domain* d : b->members)
+    if (d->stream != b->stream && hipStreamSynchronize(d->stream) != hipSuccess)
+      return bfail(b, RWMI_EDEVICE, "member synchronisation failed");
+  if (b->dirty) {
+    rwmi_status st = batch_rebuild(b);
+    if (st != RWMI_OK) return st;
+  }
+  if (b->members.empty()) return RWMI_OK;
+  uint32_t left = n_steps;
+  if (b->use_graph && n_steps >= 2) {
+    const uint32_t k = std::min<uint32_t>(n_steps, 32);
+    if (!b->gexec || b->gsteps != k) {
+      batch_drop_graph(b);
+      hipGraph_t g;
+      if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bfail(b, RWMI_EDEVICE, "capture failed");
+      for (uint32_t i = 0; i < k; ++i) {
+        if (batch_enqueue_step(b) != RWMI_OK) {
+          hipGraph_t junk;
+          (void)hipStreamEndCapture(b->stream, &junk);
+          if (junk) (void)hipGraphDestroy(junk);
+          return RWMI_EDEVICE;
+        }
+      }
+      if (hipStreamEndCapture(b->stream, &g) != hipSuccess) return bfail(b, RWMI_EDEVICE, "end capture failed");
+      hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return bfail(b, RWMI_EDEVICE, "graph instantiate failed");
+      b->gsteps = k;
+    }
+    while (left >= b->gsteps) {
+      if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return bfail(b, RWMI_EDEVICE, "graph launch failed");
+      left -= b->gsteps;
+      for (rwmi_domain* d : b->members) d->steps += b->gsteps;
+    }
+  }
+  for (; left > 0; --left) {
+    rwmi_status st = batch_enqueue_step(b);
+    if (st != RWMI_OK) return st;
+    for (rwmi_domain* d : b->members) d->steps++;
+  }
+  for (rwmi_domain* d : b->members) d->stepped = true;
+  // member reads run on the members' streams: order them after this work
+  hipEvent_t ev;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+    (void)hipEventRecord(ev, b->stream);
+    for (rwmi_domain* d : b->members)
+      if (d->stream != b->stream) (void)hipStreamWaitEvent(d->stream, ev, 0);
+    (void)hipEventDestroy(ev);
+  }
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value) {
+  if (!b) return bfail(b, RWMI_EINVAL, "null batch");
+  switch (key) {
+    case RWMI_KEY_USE_GRAPH:
+      b->use_graph = value != 0;
+      if (!b->use_graph) batch_drop_graph(b);
+      return RWMI_OK;
+    case RWMI_KEY_LBM_BLOCK:
+      if (value != 128 && value != 256 && value != 512) return bfail(b, RWMI_EINVAL, "bad fluid block");
+      b->lbm_bs = (int)value;
+      b->dirty = true;
+      return RWMI_OK;
+    case RWMI_KEY_WALK_BLOCK:
+      if (value != 128 && value != 256) return bfail(b, RWMI_EINVAL, "bad walker block");
+      b->walk_bs = (int)value;
+      b->dirty = true;
+      return RWMI_OK;
+    default:
+      return bfail(b, RWMI_EINVAL, "unknown batch key");
+  }
+}
+
+rwmi_status rwmi_batch_synchronize(rwmi_batch* b) {
+  if (!b) return bfail(b, RWMI_EINVAL, "null batch");
+  if (hipSetDevice(b->device) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)
+    return bfail(b, RWMI_EDEVICE, "batch synchronisation failed");
+  return RWMI_OK;
+}
+
+void rwmi_batch_destroy(rwmi_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  for (rwmi_domain* d : b->members) d->batch = nullptr;
+  batch_drop_graph(b);
+  batch_free_groups(b);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,305 @@
+// Device-side building blocks shared by the kernels of librwmi.
+//
+// Every double-precision routine here follows one fixed sequence of IEEE
+// operations (compiled with -ffp-contract=off for the FP64 path), so that the
+// FP64 mode reproduces any other IEEE implementation of the same sequence bit
+// for bit.  The low-precision modes reuse the routines templated on float.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace rwmi {
+
+// ------------------------------------------------------------------ lattice
+// D3Q19 (Sec. 2.3): rest, +-x, +-y, +-z, then the twelve edge diagonals in
+// opposite pairs.  Opposite of i > 0 is i + 1 for odd i, i - 1 for even i.
+constexpr int kQ = 19;
+constexpr int kEx[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kEy[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kEz[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+__host__ __device__ constexpr int opp_dir(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr int comp(int i, int a) { return a == 0 ? kEx[i] : (a == 1 ? kEy[i] : kEz[i]); }
+template <typename R>
+__host__ __device__ constexpr R weight(int i) {
+  return i == 0 ? R(1.0) / R(3.0) : (i <= 6 ? R(1.0) / R(18.0) : R(1.0) / R(36.0));
+}
+
+constexpr int kMaxParticles = 64;
+constexpr int kCounters = 8;
+enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect };
+constexpr int kMaskBlock = 4;  // edge of a coarse block of the walker cull mask
+
+// Precision tags
+enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
+
+// Per-particle record in device memory.
+struct DevParticle {
+  double c0[3], amp[3], vel[3];
+  double period, phase;
+  double rb;      // bounding radius: M <= 1 beyond it
+  double cutsq;   // (rb + 2)^2, support of the solid fraction
+  double maskr;   // rb + 0.5, radius used to build the walker cull mask
+  int32_t motion, nc, ctrl0, pad;
+};
+
+// Everything a kernel needs to know about one domain.  Lives in device memory
+// (one per domain, or an array for a batch); constant across steps.
+struct DomView {
+  int32_t n[3];
+  int32_t bc[3];
+  int32_t mb[3];     // coarse mask blocks per axis
+  int32_t np;        // particles
+  int64_t N;         // nodes
+  int64_t nw;        // walkers
+  int64_t qcap;      // near-surface queue capacity
+  int32_t prec;
+  int32_t has_force;
+  int32_t max_bisect;
+  uint32_t key0, key1;
+  double tau, omega, tm, cfree;   // 1/tau, tau - 1/2, 1 - 1/(2 tau)
+  double F[3], rho0, sD;          // force, initial density, sqrt(2D)
+  float omega_f, tm_f, cfree_f, rho0_f, sD_f, F_f[3], halfF_f[3];
+  double wu[3][2][3];             // wall velocity [axis][lo/hi][component]
+  float wu_f[3][2][3];
+  void* fA;                       // distributions, parity 0 source
+  void* fB;                       // distributions, parity 1 source
+  void* u4;                       // (ux, uy, uz, rho) per node
+  const DevParticle* parts;
+  const double* ctrl;             // 4 per control point: bx, by, bz, k
+  double* pose;                   // [2][np][6]: (c, v) at t and t+1
+  uint64_t* tstep;                // [0] steps started, [1] step being computed
+  unsigned long long* mask;       // coarse cull mask, one bit per particle
+  int32_t* wcell;                 // walker cell index
+  void* woff;                     // walker offsets SoA [3][nw] (double or float)
+  int32_t* wimg;                  // walker image counts SoA [3][nw]
+  int32_t* qid;                   // near-surface queue: walker id
+  void* qdl;                      // near-surface queue: step vector SoA [3][qcap]
+  uint32_t* qcount;
+  unsigned long long* counters;   // kCounters
+  uint32_t* occ;                  // occupancy per node
+};
+
+// Work map of a multi-domain launch: block b of the grid belongs to domain d
+// with boff[d] <= b < boff[d + 1].
+__device__ __forceinline__ int find_domain(const int32_t* __restrict__ boff, int nd, int b) {
+  int lo = 0, hi = nd;  // invariant boff[lo] <= b < boff[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (boff[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// Uniform in (0, 1): (r + 1/2) 2^-32, exact in double.
+__device__ __forceinline__ double unit_open(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
+
+// ln(u) for normal u in (0, 1] using only +,-,*,/ on exactly split
+// mantissa/exponent: m in (sqrt(1/2), sqrt(2)], s = (m-1)/(m+1),
+// ln m = 2s + 2s s^2 (1/3 + s^2/5 + ... + s^20/21), then e ln 2 in two parts.
+__device__ __forceinline__ double log_unit(double u) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(u);
+  int e = (int)((bits >> 52) & 0x7ffull) - 1023;
+  double m = __longlong_as_double((long long)((bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
+  if (m > 0x1.6a09e667f3bcdp+0) {
+    m = m * 0.5;
+    e = e + 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  constexpr double c[10] = {1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0,
+                            1.0 / 11.0, 1.0 / 9.0,  1.0 / 7.0,  1.0 / 5.0,  1.0 / 3.0};
+  double p = c[0];
+#pragma unroll
+  for (int j = 1; j < 10; ++j) p = p * z + c[j];
+  const double t = 2.0 * s;
+  const double lm = t + (t * z) * p;
+  const double de = (double)e;
+  return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + lm);
+}
+
+// Taylor polynomials on [0, pi/4] (degree 17 for sine, 16 for cosine), Horner
+// in x^2 with the signed reciprocal factorials.
+__device__ __forceinline__ double sin_taylor(double x) {
+  const double z = x * x;
+  constexpr double c[8] = {1.0 / 355687428096000.0, -1.0 / 1307674368000.0, 1.0 / 6227020800.0,
+                           -1.0 / 39916800.0,       1.0 / 362880.0,          -1.0 / 5040.0,
+                           1.0 / 120.0,             -1.0 / 6.0};
+  double p = c[0];
+#pragma unroll
+  for (int j = 1; j < 8; ++j) p = p * z + c[j];
+  return x + (x * z) * p;
+}
+__device__ __forceinline__ double cos_taylor(double x) {
+  const double z = x * x;
+  constexpr double c[8] = {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
+                           -1.0 / 3628800.0,       1.0 / 40320.0,        -1.0 / 720.0,
+                           1.0 / 24.0,             -1.0 / 2.0};
+  double p = c[0];
+#pragma unroll
+  for (int j = 1; j < 8; ++j) p = p * z + c[j];
+  return 1.0 + z * p;
+}
+
+// sin and cos of 2 pi u, u in [0, 1): quarter-turn q = floor(4u) and the
+// fraction f = 4u - q are exact; f > 1/2 is folded to 1 - f (exact) with sine
+// and cosine swapped; the quarter turns are applied by sign/swap.
+__device__ __forceinline__ void sincos_turns(double u, double& s, double& c) {
+  const double t4 = 4.0 * u;
+  const double qd = floor(t4);
+  const double f = t4 - qd;
+  const int q = ((int)qd) & 3;
+  double a, b;  // sin, cos of the folded angle
+  if (f <= 0.5) {
+    const double x = f * 0x1.921fb54442d18p+0;
+    a = sin_taylor(x);
+    b = cos_taylor(x);
+  } else {
+    const double x = (1.0 - f) * 0x1.921fb54442d18p+0;
+    a = cos_taylor(x);
+    b = sin_taylor(x);
+  }
+  if (q == 0) { s = a; c = b; }
+  else if (q == 1) { s = b; c = -a; }
+  else if (q == 2) { s = -a; c = -b; }
+  else { s = -b; c = a; }
+}
+
+// Three standard normals from one Philox block (Box-Muller on (r0, r1) and
+// (r2, r3)).
+__device__ __forceinline__ void gauss3(const U4& r, double& z0, double& z1, double& z2) {
+  const double R0 = sqrt(-2.0 * log_unit(unit_open(r.x)));
+  double s, c;
+  sincos_turns(unit_open(r.y), s, c);
+  z0 = R0 * c;
+  z1 = R0 * s;
+  const double R2 = sqrt(-2.0 * log_unit(unit_open(r.z)));
+  sincos_turns(unit_open(r.w), s, c);
+  z2 = R2 * c;
+}
+
+// ------------------------------------------------------------------ motion
+// Pose (centre, velocity) of particle p at integer step t.
+__device__ __forceinline__ void particle_pose(const DevParticle& p, uint64_t t, double c[3], double v[3]) {
+  if (p.motion == 1) {
+    double ph = (double)t / p.period + p.phase;
+    ph = ph - floor(ph);
+    double s, co;
+    sincos_turns(ph, s, co);
+    const double w = 0x1.921fb54442d18p+2 / p.period;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c[a] = p.c0[a] + p.amp[a] * s;
+      v[a] = (p.amp[a] * w) * co;
+    }
+  } else if (p.motion == 2) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c[a] = p.c0[a] + p.vel[a] * (double)t;
+      v[a] = p.vel[a];
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c[a] = p.c0[a];
+      v[a] = 0.0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ geometry
+// Displacement from a particle centre cp to (cell + x) along one axis, with
+// the minimum image r - L floor(r / L + 1/2) on periodic axes.
+template <typename R>
+__device__ __forceinline__ R axis_disp(int periodic, int L, int cell, double cp, R x) {
+  R r = (R)((double)cell - cp) + x;
+  if (periodic) {
+    const R Lr = (R)L;
+    r = r - Lr * floor(r / Lr + (R)0.5);
+  }
+  return r;
+}
+template <>
+__device__ __forceinline__ double axis_disp<double>(int periodic, int L, int cell, double cp, double x) {
+  double r = ((double)cell - cp) + x;
+  if (periodic) {
+    const double Lr = (double)L;
+    r = r - Lr * floor(r / Lr + 0.5);
+  }
+  return r;
+}
+
+// Metaball value M = sum k_i / |d - b_i|^2 in control-point order (Eq. 3);
+// +inf at a control point.
+template <typename R>
+__device__ __forceinline__ R metaball_value(const double* __restrict__ ctrl, int nc, R dx, R dy, R dz) {
+  R M = (R)0;
+  for (int i = 0; i < nc; ++i) {
+    const double* q = ctrl + 4 * i;
+    const R rx = dx - (R)q[0], ry = dy - (R)q[1], rz = dz - (R)q[2];
+    const R r2 = (rx * rx + ry * ry) + rz * rz;
+    if (r2 == (R)0) return (R)INFINITY;
+    M = M + (R)q[3] / r2;
+  }
+  return M;
+}
+
+// Gradient of M (Eq. 17): sum -2 k_i (d - b_i) / |d - b_i|^4.
+template <typename R>
+__device__ __forceinline__ void metaball_grad(const double* __restrict__ ctrl, int nc, R dx, R dy, R dz, R g[3]) {
+  g[0] = g[1] = g[2] = (R)0;
+  for (int i = 0; i < nc; ++i) {
+    const double* q = ctrl + 4 * i;
+    const R rx = dx - (R)q[0], ry = dy - (R)q[1], rz = dz - (R)q[2];
+    const R r2 = (rx * rx + ry * ry) + rz * rz;
+    const R f = ((R)-2 * (R)q[3]) / (r2 * r2);
+    g[0] = g[0] + f * rx;
+    g[1] = g[1] + f * ry;
+    g[2] = g[2] + f * rz;
+  }
+}
+
+// ------------------------------------------------------------------ storage
+template <int P> struct Store;
+template <> struct Store<P64> { using S = double; using C = double; using U = double; using O = double; };
+template <> struct Store<P32> { using S = float; using C = float; using U = float; using O = float; };
+template <> struct Store<P16> { using S = __half; using C = float; using U = float; using O = float; };
+template <> struct Store<PB16> { using S = __hip_bfloat16; using C = float; using U = float; using O = float; };
+
+__device__ __forceinline__ float to_c(__half h) { return __half2float(h); }
+__device__ __forceinline__ float to_c(__hip_bfloat16 h) { return __bfloat162float(h); }
+__device__ __forceinline__ float to_c(float h) { return h; }
+__device__ __forceinline__ double to_c(double h) { return h; }
+template <typename S> __device__ __forceinline__ S from_c(float v);
+template <> __device__ __forceinline__ __half from_c<__half>(float v) { return __float2half_rn(v); }
+template <> __device__ __forceinline__ __hip_bfloat16 from_c<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+template <> __device__ __forceinline__ float from_c<float>(float v) { return v; }
+template <typename S> __device__ __forceinline__ S from_d(double v) { return (S)v; }
+
+}  // namespace rwmi

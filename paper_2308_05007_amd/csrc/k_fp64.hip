@@ -1,0 +1,93 @@
+// FP64 kernels (compiled with -ffp-contract=off: every double operation is
+// a separately rounded IEEE operation) and the precision-independent ones.
+#include "aux_impl.h"
+#include "launch.h"
+
+namespace rwmi {
+
+hipError_t launch_prologue(const Work& w, hipStream_t s) {
+  k_prologue<<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd);
+  return hipGetLastError();
+}
+
+hipError_t launch_fluid_p64(int bs, const Work& w, hipStream_t s) {
+  switch (bs) {
+    case 128: k_fluid<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd); break;
+    case 512: k_fluid<P64, 512><<<w.blocks, 512, 0, s>>>(w.views, w.boff, w.nd); break;
+    default: k_fluid<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_p64(int bs, const Work& w, hipStream_t s) {
+  switch (bs) {
+    case 128: k_walk<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd); break;
+    default: k_walk<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_slow_p64(const Work& w, hipStream_t s) {
+  k_walk_slow<P64><<<w.blocks, kSlowThreads, 0, s>>>(w.views, w.boff, w.nd);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_p64(const DomView* v, int dom, int64_t N, const double u0[3], hipStream_t s) {
+  k_init<P64><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(v, dom, u0[0], u0[1], u0[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_f_p64(const DomView* v, int dom, int64_t N, double* out, hipStream_t s) {
+  k_read_f<P64><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(v, dom, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(int prec, const DomView* v, int dom, int kind, const double c[3], double sigma, int axis,
+                       double lo, double hi, const double* xyz, int64_t n, int attempts, int32_t* cell, void* off,
+                       uint8_t* flag, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (prec == P64)
+    k_seed<double><<<g, 256, 0, s>>>(v, dom, kind, c[0], c[1], c[2], sigma, axis, lo, hi, xyz, n, attempts, cell,
+                                     (double*)off, flag);
+  else
+    k_seed<float><<<g, 256, 0, s>>>(v, dom, kind, c[0], c[1], c[2], sigma, axis, lo, hi, xyz, n, attempts, cell,
+                                    (float*)off, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_scatter(int prec, const DomView* v, int dom, int64_t n, const int32_t* cell, const void* off,
+                               const uint8_t* flag, const int32_t* pos, int64_t m, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (prec == P64)
+    k_seed_scatter<double><<<g, 256, 0, s>>>(v, dom, n, cell, (const double*)off, flag, pos, m);
+  else
+    k_seed_scatter<float><<<g, 256, 0, s>>>(v, dom, n, cell, (const float*)off, flag, pos, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_occupancy(const DomView* v, int dom, uint32_t* occ, int64_t N, int64_t nw, hipStream_t s) {
+  k_fill_u32<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(occ, N, 0u);
+  if (nw > 0) k_occupancy<<<(unsigned)((nw + 255) / 256), 256, 0, s>>>(v, dom);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_t nw, const double* ref, double* pw,
+                          double* pn, double* out, hipStream_t s) {
+  const int64_t nbw = (nw + kRedChunk - 1) / kRedChunk;
+  const int64_t nbn = (N + kRedChunk - 1) / kRedChunk;
+  if (nbw > 0) {
+    if (prec == P64) k_mom_walkers<double><<<(unsigned)nbw, kRedThreads, 0, s>>>(v, dom, ref, pw);
+    else k_mom_walkers<float><<<(unsigned)nbw, kRedThreads, 0, s>>>(v, dom, ref, pw);
+  }
+  if (prec == P64) k_mom_nodes<double><<<(unsigned)nbn, kRedThreads, 0, s>>>(v, dom, pn);
+  else k_mom_nodes<float><<<(unsigned)nbn, kRedThreads, 0, s>>>(v, dom, pn);
+  k_mom_final<<<1, 64, 0, s>>>(v, dom, pw, nbw, pn, nbn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals(uint64_t seed, uint32_t t, uint32_t purpose, int64_t n, double* z, hipStream_t s) {
+  k_normals<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((uint32_t)seed, (uint32_t)(seed >> 32), t, purpose, n, z);
+  return hipGetLastError();
+}
+
+}  // namespace rwmi

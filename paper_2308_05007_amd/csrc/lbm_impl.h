@@ -1,0 +1,416 @@
+// D3Q19 partially-saturated-cell BGK collide + pull-stream, one thread per
+// node, one block per run of consecutive nodes (x fastest).
+//
+// Stored state between steps is the post-collision distribution f*(t-1),
+// SoA [19][nodes], with the moving-wall term of Eq. 23 already added to every
+// population that will bounce off a wall node.  A step gathers
+// f_i(x, t) = f*_i(x - e_i, t-1) (or the bounced f*_opp(i)(x) when x - e_i is
+// a wall node), computes rho, u (Eq. 14-15, Guo half-force velocity), the
+// solid fraction eps and solid velocity u_s of the metaballs culled for the
+// block (Eq. 3, Eq. 17), collides (BGK, Eq. 12-13, Noble-Torczynski
+// weighting, Guo source) and writes f*(t) in place of the node's own slots of
+// the other buffer, plus (u, rho).
+#pragma once
+#include "dev_common.h"
+
+namespace rwmi {
+
+constexpr int kLdsCtrl = 384;  // control points staged in LDS per block
+
+struct BlockParticles {
+  int cnt;
+  int id[kMaxParticles];
+  int ctrl_off[kMaxParticles];  // offset in s_ctrl, or -1 to read global memory
+  int nc[kMaxParticles];
+  double c[kMaxParticles][3];
+  double v[kMaxParticles][3];
+  double cutsq[kMaxParticles];
+  double ctrl[4 * kLdsCtrl];
+};
+
+// Circular (periodic) or plain distance from coordinate c to the node-centre
+// interval [lo + 1/2, hi + 1/2].
+__device__ __forceinline__ double interval_gap(int periodic, int L, int lo, int hi, double c) {
+  const double a = (double)lo + 0.5, b = (double)hi + 0.5;
+  if (!periodic) {
+    if (c < a) return a - c;
+    if (c > b) return c - b;
+    return 0.0;
+  }
+  const double hw = 0.5 * (b - a);
+  if (2.0 * hw >= (double)L - 1.0) return 0.0;
+  double m = c - 0.5 * (a + b);
+  m = m - (double)L * floor(m / (double)L + 0.5);
+  const double g = fabs(m) - hw;
+  return g > 0.0 ? g : 0.0;
+}
+
+// Cull the particles for the node range [n0, n1] of a block and stage their
+// poses and control points in LDS.  Called by every thread of the block.
+__device__ __forceinline__ void cull_block(const DomView& V, int64_t n0, int64_t n1, BlockParticles& sp) {
+  const int nx = V.n[0], ny = V.n[1];
+  const int64_t nxy = (int64_t)nx * ny;
+  int lo[3], hi[3];
+  {
+    const int x0 = (int)(n0 % nx), y0 = (int)((n0 / nx) % ny), z0 = (int)(n0 / nxy);
+    const int x1 = (int)(n1 % nx), y1 = (int)((n1 / nx) % ny), z1 = (int)(n1 / nxy);
+    lo[2] = z0; hi[2] = z1;
+    if (z0 == z1 && y0 == y1) { lo[0] = x0; hi[0] = x1; lo[1] = y0; hi[1] = y0; }
+    else if (z0 == z1) { lo[0] = 0; hi[0] = nx - 1; lo[1] = y0; hi[1] = y1; }
+    else { lo[0] = 0; hi[0] = nx - 1; lo[1] = 0; hi[1] = ny - 1; }
+  }
+  const double* pose = V.pose;  // P(t) at index 0
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    bool keep = false;
+    if (tid < V.np) {
+      const double* pc = pose + 6 * tid;
+      double g2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double g = interval_gap(!V.bc[a], V.n[a], lo[a], hi[a], pc[a]);
+        g2 += g * g;
+      }
+      const double cs = V.parts[tid].cutsq;
+      keep = g2 <= cs * (1.0 + 1e-9) + 1e-9;
+    }
+    const unsigned long long m = __ballot(keep);
+    if (keep) {
+      const int r = __popcll(m & ((1ull << tid) - 1ull));
+      sp.id[r] = tid;
+    }
+    if (tid == 0) sp.cnt = __popcll(m);
+  }
+  __syncthreads();
+  const int cnt = sp.cnt;
+  if (cnt == 0) return;
+  if (tid == 0) {
+    int off = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int nc = V.parts[sp.id[k]].nc;
+      sp.nc[k] = nc;
+      if (off + nc <= kLdsCtrl) {
+        sp.ctrl_off[k] = off;
+        off += nc;
+      } else {
+        sp.ctrl_off[k] = -1;
+      }
+    }
+  }
+  if (tid < cnt) {
+    const int p = sp.id[tid];
+    const double* pc = pose + 6 * p;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      sp.c[tid][a] = pc[a];
+      sp.v[tid][a] = pc[3 + a];
+    }
+    sp.cutsq[tid] = V.parts[p].cutsq;
+  }
+  __syncthreads();
+  for (int k = 0; k < cnt; ++k) {
+    const int off = sp.ctrl_off[k];
+    if (off < 0) continue;
+    const double* src = V.ctrl + 4 * V.parts[sp.id[k]].ctrl0;
+    for (int j = tid; j < 4 * sp.nc[k]; j += blockDim.x) sp.ctrl[4 * off + j] = src[j];
+  }
+  __syncthreads();
+}
+
+// Solid fraction of one particle at node nd (1/2 + signed distance estimate
+// 2 M (sqrt M - 1) / |grad M|, clamped; 0 beyond sqrt(cutsq)).
+template <typename R>
+__device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles& sp, int k, const int nd[3]) {
+  const R dx = axis_disp<R>(!V.bc[0], V.n[0], nd[0], sp.c[k][0], (R)0.5);
+  const R dy = axis_disp<R>(!V.bc[1], V.n[1], nd[1], sp.c[k][1], (R)0.5);
+  const R dz = axis_disp<R>(!V.bc[2], V.n[2], nd[2], sp.c[k][2], (R)0.5);
+  const R r2c = (dx * dx + dy * dy) + dz * dz;
+  if (r2c > (R)sp.cutsq[k]) return (R)0;
+  const double* ctrl = sp.ctrl_off[k] >= 0 ? sp.ctrl + 4 * sp.ctrl_off[k] : V.ctrl + 4 * V.parts[sp.id[k]].ctrl0;
+  const int nc = sp.nc[k];
+  const R M = metaball_value<R>(ctrl, nc, dx, dy, dz);
+  if (M == (R)INFINITY) return (R)1;
+  R g[3];
+  metaball_grad<R>(ctrl, nc, dx, dy, dz, g);
+  const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+  R e;
+  if (gn == (R)0) {
+    e = M >= (R)1 ? (R)1 : (R)0;
+  } else {
+    const R dist = (((R)2 * M) * (sqrt(M) - (R)1)) / gn;
+    e = dist == dist ? (R)0.5 + dist : (M >= (R)1 ? (R)1 : (R)0);
+  }
+  if (e < (R)0) e = (R)0;
+  if (e > (R)1) e = (R)1;
+  return e;
+}
+
+// e_i . v with zero components contributing nothing (left to right over x, y, z).
+template <typename R>
+__device__ __forceinline__ R edot(int i, R vx, R vy, R vz) {
+  R s = (R)0;
+  if (kEx[i] == 1) s = s + vx; else if (kEx[i] == -1) s = s - vx;
+  if (kEy[i] == 1) s = s + vy; else if (kEy[i] == -1) s = s - vy;
+  if (kEz[i] == 1) s = s + vz; else if (kEz[i] == -1) s = s - vz;
+  return s;
+}
+
+// Wall node test for a neighbour at coordinate offsets (dx,dy,dz) of a fluid
+// node at (x,y,z): returns the wall velocity slot (axis*2 + side) of the first
+// wall axis on which the neighbour lies at index 0 or n-1, or -1.
+__device__ __forceinline__ int wall_slot(const DomView& V, const int nd[3], int dx, int dy, int dz) {
+  const int dd[3] = {dx, dy, dz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!V.bc[a] || dd[a] == 0) continue;
+    const int c = nd[a] + dd[a];
+    if (c == 0) return 2 * a;
+    if (c == V.n[a] - 1) return 2 * a + 1;
+  }
+  return -1;
+}
+
+template <int P, int BS>
+__global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
+                                              int nd_count) {
+  using S = typename Store<P>::S;
+  using R = typename Store<P>::C;
+  constexpr bool exact = (P == P64);
+  __shared__ BlockParticles sp;
+  const int d = find_domain(boff, nd_count, blockIdx.x);
+  const DomView& V = views[d];
+  const int64_t lb = (int64_t)blockIdx.x - boff[d];
+  const uint64_t t = V.tstep[1];
+  if (lb == 0 && threadIdx.x == 0) V.tstep[0] = t + 1;
+  const S* __restrict__ src = (const S*)((t & 1ull) ? V.fB : V.fA);
+  S* __restrict__ dst = (S*)((t & 1ull) ? V.fA : V.fB);
+  const int64_t N = V.N;
+  const int64_t n0 = lb * BS;
+  const int64_t n1 = (n0 + BS - 1 < N) ? n0 + BS - 1 : N - 1;
+  if (V.np > 0) cull_block(V, n0, n1, sp);
+  else if (threadIdx.x == 0) sp.cnt = 0;
+  __syncthreads();
+
+  const int64_t id = n0 + threadIdx.x;
+  if (id >= N) return;
+  const int nx = V.n[0], ny = V.n[1], nz = V.n[2];
+  const int64_t nxy = (int64_t)nx * ny;
+  const int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / nxy)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (V.bc[a] && (nd[a] == 0 || nd[a] == V.n[a] - 1)) return;  // wall node: never updated
+
+  // ---- solid fraction and solid velocity
+  R es = (R)0, unx = (R)0, uny = (R)0, unz = (R)0;
+  for (int k = 0; k < sp.cnt; ++k) {
+    const R e = node_eps<R>(V, sp, k, nd);
+    es = es + e;
+    unx = unx + e * (R)sp.v[k][0];
+    uny = uny + e * (R)sp.v[k][1];
+    unz = unz + e * (R)sp.v[k][2];
+  }
+  const R eps = es < (R)1 ? es : (R)1;
+  const R usx = es > (R)0 ? unx / es : (R)0;
+  const R usy = es > (R)0 ? uny / es : (R)0;
+  const R usz = es > (R)0 ? unz / es : (R)0;
+
+  // ---- gather (pull-stream with bounce-back from wall nodes)
+  R f[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int ex = kEx[i], ey = kEy[i], ez = kEz[i];
+    int sx = nd[0] - ex, sy = nd[1] - ey, sz = nd[2] - ez;
+    bool wall = false;
+    if (V.bc[0]) wall |= (ex != 0) && (sx == 0 || sx == nx - 1);
+    else sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+    if (V.bc[1]) wall |= (ey != 0) && (sy == 0 || sy == ny - 1);
+    else sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+    if (V.bc[2]) wall |= (ez != 0) && (sz == 0 || sz == nz - 1);
+    else sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+    const int64_t sidx = wall ? (int64_t)opp_dir(i) * N + id : (int64_t)i * N + (sx + nx * ((int64_t)sy + (int64_t)ny * sz));
+    f[i] = (R)to_c(src[sidx]);
+  }
+
+  // ---- moments
+  R rho, drho;
+  if constexpr (exact) {
+    rho = (R)0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) rho = rho + f[i];
+    drho = rho;
+  } else {
+    drho = (R)0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) drho = drho + f[i];
+    rho = V.rho0_f + drho;
+  }
+  R jx = (R)0, jy = (R)0, jz = (R)0;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    if (kEx[i] == 1) jx = jx + f[i]; else if (kEx[i] == -1) jx = jx - f[i];
+    if (kEy[i] == 1) jy = jy + f[i]; else if (kEy[i] == -1) jy = jy - f[i];
+    if (kEz[i] == 1) jz = jz + f[i]; else if (kEz[i] == -1) jz = jz - f[i];
+  }
+  R ux, uy, uz;
+  if constexpr (exact) {
+    ux = (jx + 0.5 * V.F[0]) / rho;
+    uy = (jy + 0.5 * V.F[1]) / rho;
+    uz = (jz + 0.5 * V.F[2]) / rho;
+  } else {
+    ux = (jx + V.halfF_f[0]) / rho;
+    uy = (jy + V.halfF_f[1]) / rho;
+    uz = (jz + V.halfF_f[2]) / rho;
+  }
+
+  // ---- collision
+  R omega, tm, cfree;
+  R Fx, Fy, Fz;
+  if constexpr (exact) { omega = V.omega; tm = V.tm; cfree = V.cfree; Fx = V.F[0]; Fy = V.F[1]; Fz = V.F[2]; }
+  else { omega = V.omega_f; tm = V.tm_f; cfree = V.cfree_f; Fx = V.F_f[0]; Fy = V.F_f[1]; Fz = V.F_f[2]; }
+  const R uu = (ux * ux + uy * uy) + uz * uz;
+  const R uu15 = (R)1.5 * uu;
+  const bool solid = eps > (R)0;
+  R B = (R)0, A = omega, Cf = cfree;
+  if (solid) {
+    B = (eps * tm) / (((R)1 - eps) + tm);
+    A = ((R)1 - B) * omega;
+    Cf = ((R)1 - B) * ((R)1 - (R)0.5 * omega);
+  }
+  R uss15 = (R)0;
+  if (solid) uss15 = (R)1.5 * ((usx * usx + usy * usy) + usz * usz);
+
+  // equilibria: exact form (w rho)(((1 + 3 eu) + 4.5 eu^2) - 1.5 uu); the
+  // shifted form returns feq - w rho0 = w (drho + rho (3 eu + 4.5 eu^2 - 1.5 uu))
+  auto feq = [&](int i, R eu, R u15) -> R {
+    if constexpr (exact) {
+      return (weight<R>(i) * rho) * ((((R)1 + (R)3 * eu) + (R)4.5 * (eu * eu)) - u15);
+    } else {
+      return weight<R>(i) * (drho + rho * (((R)3 * eu + (R)4.5 * (eu * eu)) - u15));
+    }
+  };
+  R fe[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) fe[i] = feq(i, edot<R>(i, ux, uy, uz), uu15);
+
+  R out[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    R v = f[i] - A * (f[i] - fe[i]);
+    if (solid) {
+      const int o = opp_dir(i);
+      const R fes = feq(i, edot<R>(i, usx, usy, usz), uss15);
+      const R Om = (f[o] - fe[o]) - (f[i] - fes);
+      v = v + B * Om;
+    }
+    if (V.has_force) {
+      const R eu = edot<R>(i, ux, uy, uz);
+      const R eF = edot<R>(i, Fx, Fy, Fz);
+      R emF = (R)0;
+      emF = emF + ((R)kEx[i] - ux) * Fx;
+      emF = emF + ((R)kEy[i] - uy) * Fy;
+      emF = emF + ((R)kEz[i] - uz) * Fz;
+      const R Si = weight<R>(i) * ((R)3 * emF + ((R)9 * eu) * eF);
+      v = v + Cf * Si;
+    }
+    out[i] = v;
+  }
+
+  // ---- store f*(t), pre-adding the moving-wall term for populations that
+  // will bounce off a wall node at the next step
+#pragma unroll
+  for (int j = 0; j < kQ; ++j) {
+    R v = out[j];
+    const int ws = wall_slot(V, nd, kEx[j], kEy[j], kEz[j]);
+    if (ws >= 0) {
+      const int i = opp_dir(j);
+      const int a = ws >> 1, side = ws & 1;
+      R wx, wy, wz;
+      if constexpr (exact) { wx = V.wu[a][side][0]; wy = V.wu[a][side][1]; wz = V.wu[a][side][2]; }
+      else { wx = V.wu_f[a][side][0]; wy = V.wu_f[a][side][1]; wz = V.wu_f[a][side][2]; }
+      v = v + (((R)6 * weight<R>(i)) * rho) * edot<R>(i, wx, wy, wz);
+    }
+    if constexpr (exact) dst[(int64_t)j * N + id] = v;
+    else dst[(int64_t)j * N + id] = from_c<S>(v);
+  }
+  using U = typename Store<P>::U;
+  U* __restrict__ u4 = (U*)V.u4;
+  u4[4 * id + 0] = (U)ux;
+  u4[4 * id + 1] = (U)uy;
+  u4[4 * id + 2] = (U)uz;
+  u4[4 * id + 3] = (U)rho;
+}
+
+// Initial stored state: streaming it reproduces f = feq(rho0, u0) at every
+// fluid node (populations that bounce are set to the value they must arrive
+// with); (u, rho) = (u0, rho0), wall nodes carry the wall velocity.
+template <int P>
+__global__ void k_init(const DomView* __restrict__ views, int dom, double u0x, double u0y, double u0z) {
+  using S = typename Store<P>::S;
+  using U = typename Store<P>::U;
+  const DomView& V = views[dom];
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= V.N) return;
+  const int nx = V.n[0], ny = V.n[1];
+  const int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
+  int wslot = -1;
+  for (int a = 0; a < 3 && wslot < 0; ++a)
+    if (V.bc[a] && (nd[a] == 0 || nd[a] == V.n[a] - 1)) wslot = 2 * a + (nd[a] == 0 ? 0 : 1);
+  const double rho0 = V.rho0;
+  const double uu15 = 1.5 * ((u0x * u0x + u0y * u0y) + u0z * u0z);
+  S* fA = (S*)V.fA;
+  S* fB = (S*)V.fB;
+  for (int j = 0; j < kQ; ++j) {
+    int i = j;
+    if (wslot < 0 && wall_slot(V, nd, kEx[j], kEy[j], kEz[j]) >= 0) i = opp_dir(j);
+    const double eu = edot<double>(i, u0x, u0y, u0z);
+    double fe = (weight<double>(i) * rho0) * (((1.0 + 3.0 * eu) + 4.5 * (eu * eu)) - uu15);
+    if (P != P64) fe = fe - weight<double>(i) * rho0;
+    fA[(int64_t)j * V.N + id] = from_d<S>(fe);
+    fB[(int64_t)j * V.N + id] = from_d<S>(fe);
+  }
+  U* u4 = (U*)V.u4;
+  if (wslot >= 0) {
+    const int a = wslot >> 1, side = wslot & 1;
+    u4[4 * id + 0] = (U)V.wu[a][side][0];
+    u4[4 * id + 1] = (U)V.wu[a][side][1];
+    u4[4 * id + 2] = (U)V.wu[a][side][2];
+  } else {
+    u4[4 * id + 0] = (U)u0x;
+    u4[4 * id + 1] = (U)u0y;
+    u4[4 * id + 2] = (U)u0z;
+  }
+  u4[4 * id + 3] = (U)rho0;
+}
+
+// Pre-collision f(x, t) for diagnostics, as double SoA [19][nodes].
+template <int P>
+__global__ void k_read_f(const DomView* __restrict__ views, int dom, double* __restrict__ out) {
+  using S = typename Store<P>::S;
+  const DomView& V = views[dom];
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= V.N) return;
+  const uint64_t t = V.tstep[0];
+  const S* src = (const S*)((t & 1ull) ? V.fB : V.fA);
+  const int nx = V.n[0], ny = V.n[1], nz = V.n[2];
+  const int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
+  for (int a = 0; a < 3; ++a)
+    if (V.bc[a] && (nd[a] == 0 || nd[a] == V.n[a] - 1)) {
+      for (int i = 0; i < kQ; ++i) out[(int64_t)i * V.N + id] = 0.0;
+      return;
+    }
+  for (int i = 0; i < kQ; ++i) {
+    int s[3] = {nd[0] - kEx[i], nd[1] - kEy[i], nd[2] - kEz[i]};
+    bool wall = false;
+    for (int a = 0; a < 3; ++a) {
+      if (V.bc[a]) wall |= (comp(i, a) != 0) && (s[a] == 0 || s[a] == V.n[a] - 1);
+      else s[a] = s[a] < 0 ? s[a] + V.n[a] : (s[a] >= V.n[a] ? s[a] - V.n[a] : s[a]);
+    }
+    const int64_t sidx = wall ? (int64_t)opp_dir(i) * V.N + id : (int64_t)i * V.N + (s[0] + nx * ((int64_t)s[1] + (int64_t)ny * s[2]));
+    double v = (double)to_c(src[sidx]);
+    if (P != P64) v = v + weight<double>(i) * V.rho0;
+    out[(int64_t)i * V.N + id] = v;
+  }
+  (void)nz;
+}
+
+}  // namespace rwmi

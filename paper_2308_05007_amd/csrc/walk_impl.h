@@ -1,0 +1,457 @@
+// Random walkers (Eq. 2) on the lattice velocity field.
+//
+// k_walk (one thread per walker): trilinear interpolation of u(t) between
+// node centres (x, then y, then z), three normals from the Philox block
+// (w, t, 0, 0), step dl = u + z sqrt(2D).  The coarse cull mask of the
+// particles at t+1 is looked up at the start and end cells; a walker with no
+// candidate particle at either end can be neither type II nor IV (Sec.
+// 2.4.2), so it is moved here (walls, renormalisation).  Walkers with a
+// candidate are compacted into the near-surface queue with a wavefront ballot.
+//
+// k_walk_slow (grid-stride over the queue): the full classification against
+// the particles at t+1 (types I-IV), Algorithm 1 and Algorithm 2 for type IV,
+// the refill of type II, then walls and renormalisation.
+#pragma once
+#include "dev_common.h"
+
+namespace rwmi {
+
+template <typename R> __device__ __forceinline__ R prev_value(R x);
+template <> __device__ __forceinline__ double prev_value<double>(double x) {
+  return __longlong_as_double(__double_as_longlong(x) - 1);  // x > 0
+}
+template <> __device__ __forceinline__ float prev_value<float>(float x) {
+  return __int_as_float(__float_as_int(x) - 1);
+}
+
+__device__ __forceinline__ int64_t lin(const DomView& V, int x, int y, int z) {
+  return (int64_t)x + (int64_t)V.n[0] * ((int64_t)y + (int64_t)V.n[1] * z);
+}
+
+// Coarse mask block of the cell that contains cell c + offset x (x need not be
+// in [0,1)); periodic wrap, clamped at wall axes (the boundary blocks of the
+// mask extend to infinity there).
+template <typename R>
+__device__ __forceinline__ int64_t mask_index(const DomView& V, const int c[3], const R x[3]) {
+  int b[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int k = c[a] + (int)floor(x[a]);
+    const int n = V.n[a];
+    if (!V.bc[a]) {
+      k %= n;
+      if (k < 0) k += n;
+    } else {
+      k = k < 0 ? 0 : (k >= n ? n - 1 : k);
+    }
+    b[a] = k / kMaskBlock;
+  }
+  return (int64_t)b[0] + (int64_t)V.mb[0] * ((int64_t)b[1] + (int64_t)V.mb[1] * b[2]);
+}
+
+// Particle pose at t+1 from the pose table.
+__device__ __forceinline__ const double* pose_next(const DomView& V, int p) { return V.pose + 6 * (V.np + p); }
+
+template <typename R>
+__device__ __forceinline__ R particle_M_at(const DomView& V, int p, const int c[3], const R x[3]) {
+  const double* pc = pose_next(V, p);
+  const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
+  const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
+  const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
+  const DevParticle& P = V.parts[p];
+  return metaball_value<R>(V.ctrl + 4 * P.ctrl0, P.nc, dx, dy, dz);
+}
+
+template <typename R>
+__device__ __forceinline__ void particle_grad_at(const DomView& V, int p, const int c[3], const R x[3], R g[3]) {
+  const double* pc = pose_next(V, p);
+  const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
+  const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
+  const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
+  const DevParticle& P = V.parts[p];
+  metaball_grad<R>(V.ctrl + 4 * P.ctrl0, P.nc, dx, dy, dz, g);
+}
+
+// Lowest index of a particle whose own M >= 1 at (c + x), or -1.  Particles
+// whose bounding sphere (rb + 1/2) is farther than the point are skipped: M < 1
+// there (bounding-radius lemma), so the result is that of testing all.
+template <typename R>
+__device__ __forceinline__ int inside_any(const DomView& V, const int c[3], const R x[3]) {
+  for (int p = 0; p < V.np; ++p) {
+    const double* pc = pose_next(V, p);
+    const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
+    const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
+    const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
+    const DevParticle& P = V.parts[p];
+    const R r2 = (dx * dx + dy * dy) + dz * dz;
+    if (r2 >= (R)(P.maskr * P.maskr)) continue;
+    if (metaball_value<R>(V.ctrl + 4 * P.ctrl0, P.nc, dx, dy, dz) >= (R)1) return p;
+  }
+  return -1;
+}
+
+// Algorithm 1 on x(s) = a0 + s dir between s_out (M < 1) and s_in (M >= 1):
+// midpoint in s, converged when |M - 1| < 1e-3, at most imax evaluations.
+template <typename R>
+__device__ __forceinline__ bool bisect(const DomView& V, int p, const int c[3], const R a0[3], const R dir[3],
+                                       R s_out, R s_in, int imax, R& s_res) {
+  for (int it = 1; it <= imax; ++it) {
+    const R sm = (R)0.5 * (s_out + s_in);
+    const R x[3] = {a0[0] + sm * dir[0], a0[1] + sm * dir[1], a0[2] + sm * dir[2]};
+    const R m = particle_M_at<R>(V, p, c, x);
+    if (fabs(m - (R)1) < (R)1e-3) {
+      s_res = sm;
+      return true;
+    }
+    if (m < (R)1) s_out = sm;
+    else s_in = sm;
+  }
+  return false;
+}
+
+// Wall reflection on wall axes (halfway planes at 1 and n-1, one reflection
+// per axis).  Returns true if any coordinate was reflected.
+template <typename R>
+__device__ __forceinline__ bool reflect_walls(const DomView& V, const int c[3], R xn[3]) {
+  bool refl = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!V.bc[a]) continue;
+    const R lo = (R)(1.0 - (double)c[a]);
+    const R hi = (R)((double)(V.n[a] - 1) - (double)c[a]);
+    if (xn[a] < lo) {
+      xn[a] = (R)2 * lo - xn[a];
+      refl = true;
+    } else if (xn[a] >= hi) {
+      xn[a] = (R)2 * hi - xn[a];
+      if (xn[a] == hi) xn[a] = prev_value<R>(hi);
+      refl = true;
+    }
+  }
+  return refl;
+}
+
+template <typename R>
+__device__ __forceinline__ bool outside_walls(const DomView& V, const int c[3], const R xn[3]) {
+  bool out = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!V.bc[a]) continue;
+    const R lo = (R)(1.0 - (double)c[a]);
+    const R hi = (R)((double)(V.n[a] - 1) - (double)c[a]);
+    if (xn[a] < lo || xn[a] >= hi) out = true;
+  }
+  return out;
+}
+
+template <typename R>
+__device__ __forceinline__ bool finite3(const R x[3]) {
+  return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
+}
+
+// Write back (cell, offset in [0,1), image counts on periodic wrap).
+template <typename R>
+__device__ __forceinline__ void store_walker(const DomView& V, int64_t w, int c[3], const R xn[3]) {
+  R* __restrict__ off = (R*)V.woff;
+  const int64_t nw = V.nw;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R k = floor(xn[a]);
+    R of = xn[a] - k;
+    if (of == (R)1) {
+      of = (R)0;
+      k = k + (R)1;
+    }
+    int cc = c[a] + (int)k;
+    if (!V.bc[a]) {
+      const int n = V.n[a];
+      if (cc < 0 || cc >= n) {
+        const int q = cc >= 0 ? cc / n : -((-cc + n - 1) / n);  // floor(cc / n)
+        cc -= q * n;
+        V.wimg[a * nw + w] += q;
+      }
+    }
+    c[a] = cc;
+    off[a * nw + w] = of;
+  }
+  V.wcell[w] = (int32_t)lin(V, c[0], c[1], c[2]);
+}
+
+template <int P, int BS>
+__global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
+                                             int nd_count) {
+  using R = typename Store<P>::O;
+  using U = typename Store<P>::U;
+  const int d = find_domain(boff, nd_count, blockIdx.x);
+  const DomView& V = views[d];
+  const int64_t w = ((int64_t)blockIdx.x - boff[d]) * BS + threadIdx.x;
+  const bool active = w < V.nw;
+  bool queue = false;
+  bool refl = false;
+  R dl[3] = {(R)0, (R)0, (R)0};
+  if (active) {
+    const uint64_t t = V.tstep[1];
+    const int nx = V.n[0], ny = V.n[1];
+    const int32_t lc = V.wcell[w];
+    int c[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
+    const R* __restrict__ off = (const R*)V.woff;
+    const R o[3] = {off[w], off[V.nw + w], off[2 * V.nw + w]};
+    // trilinear interpolation between node centres
+    int b0[3], b1[3];
+    R wt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      int b;
+      if (o[a] >= (R)0.5) {
+        b = c[a];
+        wt[a] = o[a] - (R)0.5;
+      } else {
+        b = c[a] - 1;
+        wt[a] = o[a] + (R)0.5;
+      }
+      int b1a = b + 1;
+      if (b < 0) b += V.n[a];
+      if (b1a >= V.n[a]) b1a -= V.n[a];
+      b0[a] = b;
+      b1[a] = b1a;
+    }
+    const U* __restrict__ u4 = (const U*)V.u4;
+    R Ui[3];
+    {
+      R v[2][2][3];
+#pragma unroll
+      for (int zz = 0; zz < 2; ++zz)
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy) {
+          const int y = yy ? b1[1] : b0[1], z = zz ? b1[2] : b0[2];
+          const int64_t i0 = lin(V, b0[0], y, z), i1 = lin(V, b1[0], y, z);
+#pragma unroll
+          for (int cpt = 0; cpt < 3; ++cpt) {
+            const R lo = (R)u4[4 * i0 + cpt], hi = (R)u4[4 * i1 + cpt];
+            v[zz][yy][cpt] = ((R)1 - wt[0]) * lo + wt[0] * hi;
+          }
+        }
+#pragma unroll
+      for (int cpt = 0; cpt < 3; ++cpt) {
+        const R v0 = ((R)1 - wt[1]) * v[0][0][cpt] + wt[1] * v[0][1][cpt];
+        const R v1 = ((R)1 - wt[1]) * v[1][0][cpt] + wt[1] * v[1][1][cpt];
+        Ui[cpt] = ((R)1 - wt[2]) * v0 + wt[2] * v1;
+      }
+    }
+    // Brownian step (Eq. 2 with dt = 1)
+    const U4 r = philox4x32_10((uint32_t)w, (uint32_t)t, 0u, 0u, V.key0, V.key1);
+    double z0, z1, z2;
+    gauss3(r, z0, z1, z2);
+    R xf[3];
+    if constexpr (P == P64) {
+      dl[0] = Ui[0] + z0 * V.sD;
+      dl[1] = Ui[1] + z1 * V.sD;
+      dl[2] = Ui[2] + z2 * V.sD;
+    } else {
+      dl[0] = Ui[0] + (R)z0 * V.sD_f;
+      dl[1] = Ui[1] + (R)z1 * V.sD_f;
+      dl[2] = Ui[2] + (R)z2 * V.sD_f;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xf[a] = o[a] + dl[a];
+    if (V.np > 0) {
+      const R zero3[3] = {(R)0, (R)0, (R)0};
+      const unsigned long long mA = V.mask[mask_index<R>(V, c, zero3)];
+      const unsigned long long mB = V.mask[mask_index<R>(V, c, xf)];
+      queue = (mA | mB) != 0ull;
+    }
+    if (!queue) {
+      R xn[3] = {xf[0], xf[1], xf[2]};
+      if (!finite3<R>(xn)) {
+        atomicAdd(&V.counters[kReturned], 1ull);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xn[a] = o[a];
+      } else {
+        refl = reflect_walls<R>(V, c, xn);
+        if (refl) {
+          if (outside_walls<R>(V, c, xn)) {
+            atomicAdd(&V.counters[kReturned], 1ull);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xn[a] = o[a];
+          } else if (V.np > 0 && V.mask[mask_index<R>(V, c, xn)] != 0ull) {
+            queue = true;  // the reflected point may be inside a particle
+            refl = false;
+          }
+        }
+      }
+      if (!queue) store_walker<R>(V, w, c, xn);
+    }
+  }
+  // wavefront-ballot compaction into the near-surface queue
+  const unsigned long long qm = __ballot(queue);
+  if (qm) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)qm) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(V.qcount, (uint32_t)__popcll(qm));
+    base = __shfl(base, leader);
+    if (queue) {
+      const uint32_t slot = base + (uint32_t)__popcll(qm & ((1ull << lane) - 1ull));
+      V.qid[slot] = (int32_t)w;
+      R* qdl = (R*)V.qdl;
+      qdl[slot] = dl[0];
+      qdl[V.qcap + slot] = dl[1];
+      qdl[2 * V.qcap + slot] = dl[2];
+    }
+  }
+  const unsigned long long rm = __ballot(refl);
+  if (rm && (threadIdx.x & 63) == __ffsll((long long)rm) - 1)
+    atomicAdd(&V.counters[kWallReflect], (unsigned long long)__popcll(rm));
+}
+
+template <int P>
+__global__ void k_walk_slow(const DomView* __restrict__ views, const int32_t* __restrict__ boff, int nd_count) {
+  using R = typename Store<P>::O;
+  const int d = find_domain(boff, nd_count, blockIdx.x);
+  const DomView& V = views[d];
+  const int nblk = boff[d + 1] - boff[d];
+  const int64_t stride = (int64_t)nblk * blockDim.x;
+  const uint32_t nq = *V.qcount;
+  const uint64_t t = V.tstep[1];
+  const int nx = V.n[0], ny = V.n[1];
+  const R* __restrict__ off = (const R*)V.woff;
+  const R* __restrict__ qdl = (const R*)V.qdl;
+  for (int64_t q = ((int64_t)blockIdx.x - boff[d]) * blockDim.x + threadIdx.x; q < (int64_t)nq; q += stride) {
+    const int64_t w = V.qid[q];
+    const R dl[3] = {qdl[q], qdl[V.qcap + q], qdl[2 * V.qcap + q]};
+    const int32_t lc = V.wcell[w];
+    int c[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
+    const R o[3] = {off[w], off[V.nw + w], off[2 * V.nw + w]};
+    R xf[3], xn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      xf[a] = o[a] + dl[a];
+      xn[a] = xf[a];
+    }
+    const int jb = inside_any<R>(V, c, xf);
+    if (jb >= 0) {
+      const int ja = inside_any<R>(V, c, o);
+      if (ja < 0) {
+        // type IV: no-flux boundary, Algorithm 1 then Algorithm 2
+        atomicAdd(&V.counters[kType4], 1ull);
+        R s;
+        bool done = false;
+        if (bisect<R>(V, jb, c, o, dl, (R)0, (R)1, V.max_bisect, s)) {
+          R xi[3], g[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) xi[a] = o[a] + s * dl[a];
+          particle_grad_at<R>(V, jb, c, xi, g);
+          const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+          if (gn > (R)0) {
+            R nv[3], ti[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              nv[a] = g[a] / gn;
+              ti[a] = xf[a] - xi[a];
+            }
+            const R dt = (ti[0] * nv[0] + ti[1] * nv[1]) + ti[2] * nv[2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xn[a] = xi[a] + (ti[a] - ((R)2 * dt) * nv[a]);
+            if (inside_any<R>(V, c, xn) >= 0) {
+              atomicAdd(&V.counters[kReturned], 1ull);
+#pragma unroll
+              for (int a = 0; a < 3; ++a) xn[a] = o[a];
+            }
+            done = true;
+          }
+        }
+        if (!done) {
+          atomicAdd(&V.counters[kBisectFail], 1ull);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) xn[a] = o[a];
+        }
+      } else {
+        // type II: refill (push out along -grad M, random point in the
+        // sqrt(2D) half-ball on the outer side of the surface)
+        atomicAdd(&V.counters[kType2], 1ull);
+        R g[3];
+        particle_grad_at<R>(V, jb, c, xf, g);
+        const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+        bool fallback = true;
+        if (gn > (R)0) {
+          const R no[3] = {(-g[0]) / gn, (-g[1]) / gn, (-g[2]) / gn};
+          R s = (R)0.5;
+          const R lim = (R)(2.0 * V.parts[jb].rb);
+          R xe[3];
+          for (;;) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xe[a] = xf[a] + s * no[a];
+            if (!(particle_M_at<R>(V, jb, c, xe) >= (R)1) || !(s < lim)) break;
+            s = (R)2 * s;
+          }
+          if (particle_M_at<R>(V, jb, c, xe) < (R)1) {
+            R ss;
+            if (bisect<R>(V, jb, c, xf, no, s, (R)0, V.max_bisect, ss)) {
+              R xs[3];
+#pragma unroll
+              for (int a = 0; a < 3; ++a) xs[a] = xf[a] + ss * no[a];
+              const U4 r1 = philox4x32_10((uint32_t)w, (uint32_t)t, 1u, 0u, V.key0, V.key1);
+              const U4 r2 = philox4x32_10((uint32_t)w, (uint32_t)t, 2u, 0u, V.key0, V.key1);
+              double v0, v1, v2;
+              gauss3(r1, v0, v1, v2);
+              R v[3] = {(R)v0, (R)v1, (R)v2};
+              const R vn = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+#pragma unroll
+              for (int a = 0; a < 3; ++a) v[a] = v[a] / vn;
+              if ((v[0] * no[0] + v[1] * no[1]) + v[2] * no[2] < (R)0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) v[a] = -v[a];
+              }
+              double mx = unit_open(r2.x);
+              if (unit_open(r2.y) > mx) mx = unit_open(r2.y);
+              if (unit_open(r2.z) > mx) mx = unit_open(r2.z);
+              R rr;
+              if constexpr (P == P64) rr = V.sD * mx;
+              else rr = V.sD_f * (R)mx;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) xn[a] = xs[a] + rr * v[a];
+            } else {
+              atomicAdd(&V.counters[kBisectFail], 1ull);
+#pragma unroll
+              for (int a = 0; a < 3; ++a) xn[a] = xe[a];
+            }
+            bool bad = inside_any<R>(V, c, xn) >= 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              if (bad || !V.bc[a]) continue;
+              const R lo = (R)(1.0 - (double)c[a]);
+              const R hi = (R)((double)(V.n[a] - 1) - (double)c[a]);
+              if (xn[a] < lo || xn[a] >= hi) bad = true;
+            }
+            if (bad) {
+#pragma unroll
+              for (int a = 0; a < 3; ++a) xn[a] = xe[a];
+            }
+            fallback = inside_any<R>(V, c, xn) >= 0;
+          }
+        }
+        if (fallback) {
+          atomicAdd(&V.counters[kRefillFallback], 1ull);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) xn[a] = xf[a];
+        }
+      }
+    }
+    if (!finite3<R>(xn)) {
+      atomicAdd(&V.counters[kReturned], 1ull);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xn[a] = o[a];
+    }
+    if (reflect_walls<R>(V, c, xn)) {
+      atomicAdd(&V.counters[kWallReflect], 1ull);
+      if (outside_walls<R>(V, c, xn) || inside_any<R>(V, c, xn) >= 0) {
+        atomicAdd(&V.counters[kReturned], 1ull);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xn[a] = o[a];
+      }
+    }
+    store_walker<R>(V, w, c, xn);
+  }
+}
+
+}  // namespace rwmi

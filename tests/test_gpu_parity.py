@@ -1,0 +1,244 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 mode: walker counts, cells, image counts and occupancy must match
+exactly; velocities, densities, distributions and walker offsets within 1e-10
+(relative to the field's scale), as the FP64 contract states.  The kernels
+follow the oracle's operation order, so in practice they agree bit for bit;
+the tests report the number of non-identical elements.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_05007_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2308_05007_amd import binding
+    binding.lib()
+    return binding
+
+
+def _pair(orc, B, cfg, seed=True):
+    o = orc.build_domain(cfg)
+    g = B.build_domain(cfg, seed_walkers=False)
+    w = cfg.get("walkers")
+    if seed and w and w.get("n", 0):
+        no = o.seed(w, w["n"])
+        ng = g.seed(w, w["n"], check=False)
+        assert no == ng
+    return o, g
+
+
+def _close(a, b, tol, what):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert a.shape == b.shape, what
+    scale = max(1.0, float(np.max(np.abs(b)))) if b.size else 1.0
+    err = float(np.max(np.abs(a - b))) if a.size else 0.0
+    assert err <= tol * scale, "%s: max diff %.3e (scale %.3e, %d of %d differ)" % (
+        what, err, scale, int(np.count_nonzero(a != b)), a.size)
+
+
+def o_bc(o):
+    return o.bc
+
+
+def _fluid_mask(n, bc):
+    m = np.ones(n[::-1], bool)
+    for a in range(3):
+        if bc[a] == "wall":
+            idx = [slice(None)] * 3
+            idx[2 - a] = 0
+            m[tuple(idx)] = False
+            idx[2 - a] = n[a] - 1
+            m[tuple(idx)] = False
+    return m
+
+
+def compare(o, g, fields=True, f=True, walkers=True, mom=True, tol=TOL):
+    if fields:
+        fo = o.fields()
+        ug, rg = g.velocity()
+        _close(ug, fo["u"], tol, "velocity")
+        _close(rg, fo["rho"], tol, "density")
+    if f:
+        # wall nodes hold no distributions (unspecified by the ABI)
+        fluid = _fluid_mask(o.n, o_bc(o))
+        _close(g.distributions()[:, fluid], o.f()[:, fluid], tol, "distributions")
+    if walkers:
+        co, oo, io = o.walkers()
+        cg, og, ig = g.walkers()
+        assert cg.size == co.size
+        assert np.array_equal(cg, co), "cells differ for %d walkers" % int(np.count_nonzero(cg != co))
+        assert np.array_equal(ig, io), "image counts differ"
+        _close(og, oo, tol, "offsets")
+        assert np.array_equal(g.occupancy(), o.occupancy()), "occupancy differs"
+    if mom:
+        mo = o.moments()
+        mg = g.moments()
+        assert mg["n_walkers"] == int(mo["n_walkers"])
+        for k in ("sum", "sumsq", "momentum", "fluid_u", "particle_v"):
+            _close(mg[k], mo[k], 1e-9, "moment " + k)
+        for k in ("mass", "solid_volume"):
+            assert abs(mg[k] - mo[k]) <= 1e-9 * max(1.0, abs(mo[k])), k
+        assert mg["counters"] == o.counters()
+
+
+def test_normals_bitwise(orc, B):
+    n = 200_000
+    for t, purpose, seed in ((0, 0, 0), (7, 0, 12345), (123, 1, 2**40 + 3), (4999, 2, 2)):
+        zg = B.device_normals(seed, t, purpose, n)
+        zo = orc.normals(t, purpose, seed, n)
+        assert np.array_equal(zg, zo), "normals differ at %d of %d" % (int(np.count_nonzero(zg != zo)), zg.size)
+
+
+def test_initial_state(orc, B):
+    cfg = W.config_tiny(n=(5, 6, 4), bc=("periodic", "wall", "periodic"), n_walkers=0,
+                        wall_u=([[0, 0, 0], [0.01, 0, 0], [0, 0, 0]], [[0, 0, 0], [-0.02, 0, 0.01], [0, 0, 0]]),
+                        u0=(0.01, 0.0, -0.005))
+    o, g = _pair(orc, B, cfg)
+    compare(o, g, walkers=False)
+
+
+TINY = [
+    dict(n=(6, 5, 7), bc=("periodic",) * 3, motion="static", n_walkers=200),
+    dict(n=(9, 4, 11), bc=("periodic", "wall", "periodic"), motion="sinusoid", n_walkers=300),
+    dict(n=(7, 6, 5), bc=("wall", "periodic", "wall"), motion="const_vel", n_walkers=250, spread=0.8),
+    dict(n=(8, 8, 8), bc=("wall", "wall", "wall"), motion="sinusoid", n_walkers=400, n_particles=2, spread=1.2),
+    dict(n=(10, 7, 9), bc=("periodic", "wall", "periodic"), motion="sinusoid", n_walkers=500, n_particles=3,
+         wall_u=([[0, 0, 0], [-0.01, 0, 0], [0, 0, 0]], [[0, 0, 0], [0.02, 0, 0.0], [0, 0, 0]]), D=0.05),
+    dict(n=(5, 5, 5), bc=("periodic",) * 3, motion="sinusoid", n_walkers=300, n_particles=2, amp=2.5, period=12.0,
+         D=0.002, spread=1.0),
+    dict(n=(3, 9, 1), bc=("periodic", "wall", "periodic"), motion="static", n_walkers=50, n_particles=0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(TINY)))
+def test_tiny_fp64_parity(orc, B, case):
+    kw = dict(TINY[case])
+    steps = kw.pop("steps", 12)
+    cfg = W.config_tiny(steps=steps, seed=100 + case, **kw)
+    o, g = _pair(orc, B, cfg)
+    compare(o, g)
+    for chunk in (1, 3, steps - 4):
+        o.step(chunk)
+        g.step(chunk)
+        compare(o, g)
+
+
+def test_sweeping_particle_types_2_and_4(orc, B):
+    """A particle moving at 0.1 cell/step through slow walkers exercises the
+    refill (type II) and the reflection (type IV) paths."""
+    cfg = W.config_tiny(n=(16, 12, 12), bc=("periodic",) * 3, n_particles=1, n_walkers=3000, motion="const_vel",
+                        D=0.0005, spread=0.8, seed=3, F=(0, 0, 0))
+    cfg["particles"][0]["vel"] = np.array([0.1, 0.0, 0.02])
+    o, g = _pair(orc, B, cfg)
+    for _ in range(4):
+        o.step(5)
+        g.step(5)
+        compare(o, g, f=False)
+    c = o.counters()
+    assert c["type2"] > 0 and c["type4"] > 0
+
+
+def test_forced_bisection_failure(orc, B):
+    cfg = W.config_plain_fp64(scale=0.2)
+    cfg["domain"]["D"] = 0.05
+    o, g = _pair(orc, B, cfg)
+    o.set_max_bisect(1)
+    g.set("max_bisect", 1)
+    o.step(10)
+    g.step(10)
+    compare(o, g, f=False)
+    assert o.counters()["bisect_fail"] > 0
+
+
+def test_plain_fp64_32cubed_full_run(orc, B):
+    """The 32^3 configuration (static metaball, body force, 1e4 walkers,
+    200 steps) element by element at several points of the run."""
+    cfg = W.config_plain_fp64()
+    o, g = _pair(orc, B, cfg)
+    done = 0
+    for chunk in (1, 49, 150):
+        o.step(chunk)
+        g.step(chunk)
+        done += chunk
+        compare(o, g)
+    assert done == cfg["steps"]
+
+
+def test_channel_128_fp64_prefix(orc, B):
+    """Full-size 128^3 channel (walls, 20 oscillating metaballs, 1e6
+    walkers) in FP64 mode: first steps compared element by element."""
+    cfg = W.config_channel(precision="fp64")
+    o, g = _pair(orc, B, cfg)
+    for chunk in (1, 2):
+        o.step(chunk)
+        g.step(chunk)
+        compare(o, g, f=False)
+
+
+def test_graph_replay_equals_eager(B):
+    cfg = W.config_tiny(n=(9, 4, 11), bc=("periodic", "wall", "periodic"), n_walkers=500, n_particles=2, seed=5)
+    a = B.build_domain(cfg)
+    b = B.build_domain(cfg)
+    b.set("use_graph", 1)
+    a.step(37)
+    b.step(37)
+    ua, ra = a.velocity()
+    ub, rb = b.velocity()
+    assert np.array_equal(ua, ub) and np.array_equal(ra, rb)
+    assert all(np.array_equal(x, y) for x, y in zip(a.walkers(), b.walkers()))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_batch_equals_alone(B, prec):
+    cfgs = [W.config_tiny(n=n, bc=bc, n_walkers=nw, n_particles=npart, seed=s, precision=prec)
+            for n, bc, nw, npart, s in (((9, 4, 11), ("periodic", "wall", "periodic"), 300, 2, 1),
+                                         ((6, 6, 6), ("periodic",) * 3, 0, 1, 2),
+                                         ((12, 5, 7), ("periodic",) * 3, 700, 3, 3))]
+    alone = [B.build_domain(c) for c in cfgs]
+    mixed = [B.build_domain(c) for c in cfgs]
+    for d in alone:
+        d.step(15)
+    bt = B.Batch()
+    for d in mixed:
+        bt.add(d)
+    bt.set("use_graph", 1)
+    bt.step(15)
+    bt.sync()
+    for a, m in zip(alone, mixed):
+        ua, ra = a.velocity()
+        um, rm = m.velocity()
+        assert np.array_equal(ua, um) and np.array_equal(ra, rm)
+        for x, y in zip(a.walkers(), m.walkers()):
+            assert np.array_equal(x, y)
+        assert a.moments()["counters"] == m.moments()["counters"]
+    bt.close()
+
+
+def test_fp32_mode_against_oracle(orc, B):
+    """FP32 storage of deviations, float collision and float walker offsets
+    with the same normals: stated bounds after 50 steps of the 32^3 case."""
+    cfg = W.config_plain_fp64()
+    cfg["domain"]["precision"] = "fp32"
+    o, g = _pair(orc, B, cfg)
+    o.step(50)
+    g.step(50)
+    ug, _ = g.velocity()
+    uo = o.fields()["u"]
+    rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    assert rel < 1e-4, rel
+    co, oo, _ = o.walkers()
+    cg, og, _ = g.walkers()
+    n = cfg["domain"]["n"]
+    X = lambda c, off: np.stack([c % n[0], (c // n[0]) % n[1], c // (n[0] * n[1])]) + off
+    d = np.abs(X(cg, og) - X(co, oo))
+    d = np.minimum(d, n[0] - d)
+    assert np.quantile(d.max(0), 0.999) < 1e-4
+    assert g.moments()["n_walkers"] == cfg["walkers"]["n"]

@@ -1,0 +1,192 @@
+"""Benchmark of the coupled RW-MI-DELBM step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Default workload: the 128^3 FP32 channel (walls at y = 0 / 127, periodic x
+and z, tau 0.7, body force 5e-6, 20 oscillating metaballs of 8-16 control
+points, 1e6 walkers released as a Gaussian pulse of sigma 4, D = 0.005,
+2000 steps).  One step = one coupled step: particle poses + walker cull mask,
+PSM-BGK collide-stream (writes u), walker advection/diffusion with the
+near-surface queue.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line with MLUPS (all lattice nodes per second), walker-steps
+per second, the fluid kernel's achieved HBM bandwidth against the 8 TB/s peak
+(algorithmic bytes over its average duration from HIP events recorded around
+every launch of the timed region) and the FP64 CPU oracle timed on a bounded
+sample of the same workload on this host.
+
+Other workloads (own JSON line each, not the headline):
+  --workload oscillator --precision fp16|bf16|fp32|fp64   256^3 oscillator
+  --workload batch                                        64-simulation sweep
+  --workload serve                                        Poisson request stream
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+ELEM = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+UELEM = {"fp64": 8, "fp32": 4, "fp16": 4, "bf16": 4}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f16-store/f32", "bf16": "bf16-store/f32"}
+METRIC = "MLUPS + walker-steps/s (1 GPU, % HBM roofline); batched/served vs plain at tol"
+
+
+def fluid_nodes(cfg):
+    n = cfg["domain"]["n"]
+    bc = cfg["domain"]["bc"]
+    m = 1
+    for a in range(3):
+        m *= n[a] - 2 if bc[a] == "wall" else n[a]
+    return m
+
+
+def fluid_bytes_per_node(prec):
+    """Algorithmic bytes of the collide-stream per fluid node: 19 reads and 19
+    writes of the stored distribution plus the velocity the walkers need
+    (3 components); the density the kernel also writes is not credited."""
+    return 38 * ELEM[prec] + 3 * UELEM[prec]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_impl.h", "dev_common.h", "k_lowp.hip", "k_fp64.hip"):
+        with open(os.path.join(ROOT, "paper_2308_05007_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(workload_key):
+    """HBM bytes per launch of the fluid kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "fluid_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload_key)
+    if not e or e.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cfg, seconds=15.0, max_steps=200):
+    """The FP64 oracle on this host's cores: first steps of the same workload
+    (seeding excluded), as many as fit in about `seconds`."""
+    import oracle
+    o = oracle.build_domain(cfg)
+    w = cfg["walkers"]
+    o.seed(w, w["n"])
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < max_steps:
+        o.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    N = int(np.prod(cfg["domain"]["n"]))
+    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "walker_steps_per_s": w["n"] * steps / dt,
+            "sample": "FP64 oracle, first %d coupled steps of %s (%d nodes, %d walkers), %.1f s"
+                      % (steps, cfg["name"], N, w["n"], dt)}
+
+
+def run_plain(cfg, steps, warmup, prec, timing=True, graph=False):
+    from paper_2308_05007_amd import binding as B
+    import torch
+    dom = B.build_domain(cfg, device=0)
+    if graph:
+        dom.set("use_graph", 1)
+    dom.step(warmup)
+    dom.sync()
+    torch.cuda.synchronize()
+    if timing:
+        dom.set("timing", 1)
+        dom.kernel_times()  # clear
+    t0 = time.perf_counter()
+    dom.step(steps)
+    dom.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = dom.kernel_times() if timing else {}
+    mom = dom.moments()
+    return dom, dt, kt, mom
+
+
+def bench_plain(args):
+    from paper_2308_05007_amd import workloads as W
+    if args.workload == "channel":
+        cfg = W.config_channel(precision=args.precision or "fp32")
+        key = "channel_128_" + (args.precision or "fp32")
+    else:
+        cfg = W.config_oscillator(precision=args.precision or "fp16", n_walkers=args.walkers or 10_000_000)
+        key = "oscillator_256_" + (args.precision or "fp16")
+    prec = cfg["domain"]["precision"]
+    steps, warmup = args.steps, args.warmup
+    dom, dt, kt, mom = run_plain(cfg, steps, warmup, prec, timing=True, graph=False)
+    N = int(np.prod(cfg["domain"]["n"]))
+    nw = cfg["walkers"]["n"]
+    assert mom["n_walkers"] == nw, "walker count not conserved"
+    mlups = N * steps / dt / 1e6
+    fl_ms, fl_n = kt["fluid"]
+    fl_avg_s = fl_ms / 1e3 / max(fl_n, 1)
+    bytes_launch = fluid_nodes(cfg) * fluid_bytes_per_node(prec)
+    achieved = bytes_launch / fl_avg_s / 1e9
+    traffic = pmc_traffic(key)
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(dt / steps * 1e3, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[prec], "data": "synthetic (seeded metaballs and walkers; no datasets)",
+        "config": {"workload": key, "lattice": list(cfg["domain"]["n"]), "bc": list(cfg["domain"]["bc"]),
+                   "particles": len(cfg["particles"]), "walkers": nw, "precision": prec,
+                   "steps_per_run": cfg["steps"]},
+        "walker_steps_per_s": round(nw * steps / dt, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_fluid (PSM-BGK collide + pull-stream)",
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(fl_avg_s * 1e6, 2)},
+        "kernels_us": {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in kt.items()},
+        "counters": mom["counters"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, seconds=args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="channel", choices=["channel", "oscillator", "batch", "serve"])
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--walkers", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("channel", "oscillator"):
+        bench_plain(args)
+    elif args.workload == "batch":
+        from paper_2308_05007_amd import batchbench
+        batchbench.main(args)
+    else:
+        from paper_2308_05007_amd import serve
+        serve.bench(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,10 +55,7 @@ __global__ void k_prologue(const DomView* __restrict__ views, const int32_t* __r
     for (int a = 0; a < 3; ++a) sc[tid][a] = c1[a];
     sr[tid] = P.maskr;
   }
-  if (lb == 0 && tid == 0) {
-    V.tstep[1] = t;
-    if (V.qcount) *V.qcount = 0u;  // allocated with the walkers
-  }
+  if (lb == 0 && tid == 0) V.tstep[1] = t;
   __syncthreads();
   if (V.nw == 0 || V.np == 0) return;
   const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
@@ -158,7 +155,7 @@ __global__ void k_seed(const DomView* __restrict__ views, int dom, int kind, dou
       const double dy = axis_disp<double>(!V.bc[1], V.n[1], cell[1], pc[1], o[1]);
       const double dz = axis_disp<double>(!V.bc[2], V.n[2], cell[2], pc[2], o[2]);
       if ((dx * dx + dy * dy) + dz * dz >= P.maskr * P.maskr) continue;
-      if (metaball_value<double>(V.ctrl + 4 * P.ctrl0, P.nc, dx, dy, dz) >= 1.0) inside = true;
+      if (metaball_value<double>(gp(V.ctrl) + 4 * P.ctrl0, P.nc, dx, dy, dz) >= 1.0) inside = true;
     }
     if (inside) continue;
     placed = true;

@@ -165,16 +165,12 @@ rwmi_status upload_view(rwmi_domain* d) {
 
 int blocks_for(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
-int slow_blocks(int64_t nw) {
-  return (int)std::min<int64_t>(std::max<int64_t>(1, (nw + rwmi::kSlowThreads - 1) / rwmi::kSlowThreads), 512);
-}
-
 void kernel_blocks(const rwmi_domain* d, int b[KT_N]) {
   const int64_t nmb = (int64_t)d->hv.mb[0] * d->hv.mb[1] * d->hv.mb[2];
   b[KT_PRO] = (d->hv.nw > 0 && d->hv.np > 0) ? blocks_for(nmb, 256) : 1;
   b[KT_FLUID] = blocks_for(d->hv.N, d->lbm_bs);
   b[KT_WALK] = blocks_for(d->hv.nw, d->walk_bs);
-  b[KT_SLOW] = slow_blocks(d->hv.nw);
+  b[KT_SLOW] = b[KT_WALK];
 }
 
 rwmi_status upload_workmaps(rwmi_domain* d) {
@@ -238,17 +234,23 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   }
   DevParticle* dp;
   double* dc;
+  float* dcf;
   double* dpose;
   rwmi_status st;
+  std::vector<float> ctrl_f(ctrl.begin(), ctrl.end());
   if ((st = alloc_into(d, dp, sizeof(DevParticle) * hp.size())) != RWMI_OK) return st;
   if ((st = alloc_into(d, dc, sizeof(double) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
+  if ((st = alloc_into(d, dcf, sizeof(float) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
   if ((st = alloc_into(d, dpose, sizeof(double) * 12 * std::max(np, 1))) != RWMI_OK) return st;
   HIPCHK(d, hipMemcpyAsync(dp, hp.data(), sizeof(DevParticle) * hp.size(), hipMemcpyHostToDevice, d->stream));
-  if (!ctrl.empty())
+  if (!ctrl.empty()) {
     HIPCHK(d, hipMemcpyAsync(dc, ctrl.data(), sizeof(double) * ctrl.size(), hipMemcpyHostToDevice, d->stream));
+    HIPCHK(d, hipMemcpyAsync(dcf, ctrl_f.data(), sizeof(float) * ctrl_f.size(), hipMemcpyHostToDevice, d->stream));
+  }
   HIPCHK(d, hipStreamSynchronize(d->stream));  // host vectors go out of scope
   d->hv.parts = dp;
   d->hv.ctrl = dc;
+  d->hv.ctrl_f = dcf;
   d->hv.pose = dpose;
   d->hv.np = np;
   if (np > 0) {
@@ -306,7 +308,7 @@ rwmi_status enqueue_step(rwmi_domain* d, bool record) {
     if ((st = timed(KT_WALK, [&] { return rwmi::launch_walk(d->prec, d->walk_bs, wwal, d->stream); })) != RWMI_OK)
       return st;
     if (d->hv.np > 0 &&
-        (st = timed(KT_SLOW, [&] { return rwmi::launch_walk_slow(d->prec, wslo, d->stream); })) != RWMI_OK)
+        (st = timed(KT_SLOW, [&] { return rwmi::launch_walk_slow(d->prec, d->walk_bs, wslo, d->stream); })) != RWMI_OK)
       return st;
   }
   return RWMI_OK;
@@ -328,7 +330,7 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   uint64_t b = 0;
   b += 2 * 19 * N * elem_size(p) + 4 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
-  b += n_particles * sizeof(DevParticle) + 32 * n_ctrl_total + 96 * n_particles + (n_particles ? 8 * nmb : 0);
+  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 96 * n_particles + (n_particles ? 8 * nmb : 0);
   // walkers: cell, offsets, images, queue (id + step), moment partials
   b += n_walkers * (4 + 3 * off_size(p) + 12 + 4 + 3 * off_size(p));
   b += 4 * N;  // occupancy
@@ -381,6 +383,10 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
     v.bc[a] = s->bc[a];
   }
   mask_blocks(*s, v.mb);
+  v.dx = rwmi::make_fastdiv(s->n[0]);
+  v.dy = rwmi::make_fastdiv(s->n[1]);
+  v.dmx = rwmi::make_fastdiv(v.mb[0]);
+  v.dmy = rwmi::make_fastdiv(v.mb[1]);
   v.N = N;
   v.prec = d->prec;
   const double rho0 = s->rho0 > 0 ? s->rho0 : 1.0;
@@ -544,7 +550,7 @@ rwmi_status rwmi_seed_walkers(rwmi_domain* d, const rwmi_seed_desc* s, uint64_t 
       (st = alloc_into(d, wimg, 12 * std::max<int64_t>(m, 1))) != RWMI_OK ||
       (st = alloc_into(d, qid, 4 * std::max<int64_t>(m, 1))) != RWMI_OK ||
       (st = alloc_into(d, qdl, 3 * osz * std::max<int64_t>(m, 1))) != RWMI_OK ||
-      (st = alloc_into(d, qcount, 16)) != RWMI_OK)
+      (st = alloc_into(d, qcount, 4 * ((std::max<int64_t>(m, 1) + 127) / 128))) != RWMI_OK)
     return cleanup(), st;
   d->hv.wcell = wcell;
   d->hv.woff = woff;
@@ -554,6 +560,7 @@ rwmi_status rwmi_seed_walkers(rwmi_domain* d, const rwmi_seed_desc* s, uint64_t 
   d->hv.qcount = qcount;
   d->hv.nw = m;
   d->hv.qcap = std::max<int64_t>(m, 1);
+  d->hv.qblock = d->walk_bs;
   if ((st = upload_view(d)) != RWMI_OK) return cleanup(), st;
   if (m > 0) {
     if (hipMemcpyAsync(pos, hpos.data(), 4 * nn, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
@@ -757,6 +764,7 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       if (value < 1 || value > 100000) return fail(d, RWMI_EINVAL, "max_bisect out of range");
       d->hv.max_bisect = (int32_t)value;
       drop_graph(d);
+      if (d->batch) d->batch->dirty = true;
       return upload_view(d);
     case RWMI_KEY_USE_GRAPH:
       d->use_graph = value != 0;
@@ -764,13 +772,17 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       return RWMI_OK;
     case RWMI_KEY_LBM_BLOCK:
       if (value != 128 && value != 256 && value != 512) return fail(d, RWMI_EINVAL, "fluid block must be 128, 256 or 512");
+      if (d->batch) return fail(d, RWMI_ESTATE, "the batch sets the fluid block of its members");
       d->lbm_bs = (int)value;
       drop_graph(d);
       return upload_workmaps(d);
     case RWMI_KEY_WALK_BLOCK:
       if (value != 128 && value != 256) return fail(d, RWMI_EINVAL, "walker block must be 128 or 256");
+      if (d->batch) return fail(d, RWMI_ESTATE, "the batch sets the walker block of its members");
       d->walk_bs = (int)value;
+      d->hv.qblock = (int)value;
       drop_graph(d);
+      if (upload_view(d) != RWMI_OK) return RWMI_EDEVICE;
       return upload_workmaps(d);
     case RWMI_KEY_TIMING:
       d->timing = value != 0;
@@ -914,6 +926,7 @@ static rwmi_status batch_rebuild(rwmi_batch* b) {
     }
     for (int i = 0; i < nd; ++i) {
       hv[i] = g.doms[i]->hv;
+      hv[i].qblock = b->walk_bs;
       if (g.doms[i]->hv.nw > 0) g.any_walkers = true;
     }
     if (hipMalloc(&g.views, sizeof(DomView) * nd) != hipSuccess ||
@@ -942,7 +955,7 @@ static rwmi_status batch_enqueue_step(rwmi_batch* b) {
       return bfail(b, RWMI_EDEVICE, "batch launch failed");
     if (g.blocks[KT_WALK] > 0 && rwmi::launch_walk(g.prec, b->walk_bs, wwal, b->stream) != hipSuccess)
       return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
-    if (g.blocks[KT_SLOW] > 0 && rwmi::launch_walk_slow(g.prec, wslo, b->stream) != hipSuccess)
+    if (g.blocks[KT_SLOW] > 0 && rwmi::launch_walk_slow(g.prec, b->walk_bs, wslo, b->stream) != hipSuccess)
       return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
   }
   return RWMI_OK;

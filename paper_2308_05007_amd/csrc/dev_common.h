@@ -34,6 +34,29 @@ constexpr int kMaskBlock = 4;  // edge of a coarse block of the walker cull mask
 // Precision tags
 enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
 
+// floor(n / d) for 0 <= n < 2^31 and 1 <= d < 2^31 by one 32x32->64 multiply
+// and a shift (Granlund-Montgomery, round-up multiplier with N = 31 bits):
+// l = ceil(log2 d), s = 31 + l, m = ceil(2^s / d) < 2^32.
+struct FastDiv {
+  uint32_t m;
+  uint32_t s;
+  int32_t d;
+  int32_t pad;
+};
+inline FastDiv make_fastdiv(int32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < (unsigned long long)d) ++l;
+  FastDiv f;
+  f.s = 31 + l;
+  f.m = (uint32_t)(((1ull << f.s) + (unsigned long long)d - 1ull) / (unsigned long long)d);
+  f.d = d;
+  f.pad = 0;
+  return f;
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return (uint32_t)(((unsigned long long)n * (unsigned long long)f.m) >> f.s);
+}
+
 // Per-particle record in device memory.
 struct DevParticle {
   double c0[3], amp[3], vel[3];
@@ -47,6 +70,7 @@ struct DevParticle {
 // Everything a kernel needs to know about one domain.  Lives in device memory
 // (one per domain, or an array for a batch); constant across steps.
 struct DomView {
+  FastDiv dx, dy, dmx, dmy;  // division by nx, ny, mb[0], mb[1]
   int32_t n[3];
   int32_t bc[3];
   int32_t mb[3];     // coarse mask blocks per axis
@@ -68,6 +92,7 @@ struct DomView {
   void* u4;                       // (ux, uy, uz, rho) per node
   const DevParticle* parts;
   const double* ctrl;             // 4 per control point: bx, by, bz, k
+  const float* ctrl_f;            // the same in float (low-precision modes)
   double* pose;                   // [2][np][6]: (c, v) at t and t+1
   uint64_t* tstep;                // [0] steps started, [1] step being computed
   unsigned long long* mask;       // coarse cull mask, one bit per particle
@@ -76,10 +101,18 @@ struct DomView {
   int32_t* wimg;                  // walker image counts SoA [3][nw]
   int32_t* qid;                   // near-surface queue: walker id
   void* qdl;                      // near-surface queue: step vector SoA [3][qcap]
-  uint32_t* qcount;
+  uint32_t* qcount;               // queued walkers per walker block (region of qblock slots)
+  int32_t qblock;                 // walkers per block of the walker kernel
   unsigned long long* counters;   // kCounters
   uint32_t* occ;                  // occupancy per node
 };
+
+// Global-address-space view of a pointer loaded from memory, so that accesses
+// compile to global_* (not flat_*) instructions.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
 
 // Work map of a multi-domain launch: block b of the grid belongs to domain d
 // with boff[d] <= b < boff[d + 1].
@@ -204,6 +237,25 @@ __device__ __forceinline__ void gauss3(const U4& r, double& z0, double& z1, doub
   z2 = R2 * c;
 }
 
+// Float normals for the low-precision modes: the same Philox words and the
+// same Box-Muller map, with the hardware base-2 log, turn-scaled sine/cosine
+// and square root (close to the double normals, not bit-identical).
+__device__ __forceinline__ float unit_open_f(uint32_t r) { return (float)unit_open(r); }
+__device__ __forceinline__ void gauss3_fast(const U4& r, float& z0, float& z1, float& z2) {
+  constexpr float m2ln2 = -1.3862943611198906f;  // -2 ln 2
+  const float R0 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(unit_open_f(r.x)));
+  const float a = unit_open_f(r.y);
+  z0 = R0 * __builtin_amdgcn_cosf(a);
+  z1 = R0 * __builtin_amdgcn_sinf(a);
+  const float R2 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(unit_open_f(r.z)));
+  z2 = R2 * __builtin_amdgcn_cosf(unit_open_f(r.w));
+}
+
+// a / b: IEEE division in double, hardware reciprocal in float.
+template <typename R> __device__ __forceinline__ R qdiv(R a, R b);
+template <> __device__ __forceinline__ double qdiv<double>(double a, double b) { return a / b; }
+template <> __device__ __forceinline__ float qdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // ------------------------------------------------------------------ motion
 // Pose (centre, velocity) of particle p at integer step t.
 __device__ __forceinline__ void particle_pose(const DevParticle& p, uint64_t t, double c[3], double v[3]) {
@@ -257,28 +309,28 @@ __device__ __forceinline__ double axis_disp<double>(int periodic, int L, int cel
 
 // Metaball value M = sum k_i / |d - b_i|^2 in control-point order (Eq. 3);
 // +inf at a control point.
-template <typename R>
-__device__ __forceinline__ R metaball_value(const double* __restrict__ ctrl, int nc, R dx, R dy, R dz) {
+template <typename R, typename PT>
+__device__ __forceinline__ R metaball_value(PT ctrl, int nc, R dx, R dy, R dz) {
   R M = (R)0;
   for (int i = 0; i < nc; ++i) {
-    const double* q = ctrl + 4 * i;
+    const auto q = ctrl + 4 * i;
     const R rx = dx - (R)q[0], ry = dy - (R)q[1], rz = dz - (R)q[2];
     const R r2 = (rx * rx + ry * ry) + rz * rz;
     if (r2 == (R)0) return (R)INFINITY;
-    M = M + (R)q[3] / r2;
+    M = M + qdiv<R>((R)q[3], r2);
   }
   return M;
 }
 
 // Gradient of M (Eq. 17): sum -2 k_i (d - b_i) / |d - b_i|^4.
-template <typename R>
-__device__ __forceinline__ void metaball_grad(const double* __restrict__ ctrl, int nc, R dx, R dy, R dz, R g[3]) {
+template <typename R, typename PT>
+__device__ __forceinline__ void metaball_grad(PT ctrl, int nc, R dx, R dy, R dz, R g[3]) {
   g[0] = g[1] = g[2] = (R)0;
   for (int i = 0; i < nc; ++i) {
-    const double* q = ctrl + 4 * i;
+    const auto q = ctrl + 4 * i;
     const R rx = dx - (R)q[0], ry = dy - (R)q[1], rz = dz - (R)q[2];
     const R r2 = (rx * rx + ry * ry) + rz * rz;
-    const R f = ((R)-2 * (R)q[3]) / (r2 * r2);
+    const R f = qdiv<R>((R)-2 * (R)q[3], r2 * r2);
     g[0] = g[0] + f * rx;
     g[1] = g[1] + f * ry;
     g[2] = g[2] + f * rz;
@@ -301,5 +353,34 @@ template <> __device__ __forceinline__ __half from_c<__half>(float v) { return _
 template <> __device__ __forceinline__ __hip_bfloat16 from_c<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
 template <> __device__ __forceinline__ float from_c<float>(float v) { return v; }
 template <typename S> __device__ __forceinline__ S from_d(double v) { return (S)v; }
+
+// Raw storage words: 16-bit modes are moved as unsigned short and converted
+// in registers (round to nearest even on the way out).
+template <typename S> struct Raw { using T = S; };
+template <> struct Raw<__half> { using T = unsigned short; };
+template <> struct Raw<__hip_bfloat16> { using T = unsigned short; };
+template <typename S> __device__ __forceinline__ typename Store<P32>::C raw_in(typename Raw<S>::T b);
+template <> __device__ __forceinline__ float raw_in<float>(float b) { return b; }
+template <> __device__ __forceinline__ float raw_in<__half>(unsigned short b) { return __half2float(__ushort_as_half(b)); }
+template <> __device__ __forceinline__ float raw_in<__hip_bfloat16>(unsigned short b) {
+  return __uint_as_float((uint32_t)b << 16);
+}
+template <typename S> __device__ __forceinline__ typename Raw<S>::T raw_out(float v);
+template <> __device__ __forceinline__ float raw_out<float>(float v) { return v; }
+template <> __device__ __forceinline__ unsigned short raw_out<__half>(float v) {
+  return __half_as_ushort(__float2half_rn(v));
+}
+template <> __device__ __forceinline__ unsigned short raw_out<__hip_bfloat16>(float v) {
+  // round to nearest even on the upper 16 bits (inputs are finite)
+  const uint32_t u = __float_as_uint(v);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Control points in the arithmetic precision of a mode.
+template <typename R> __device__ __forceinline__ const R* ctrl_of(const DomView& V);
+template <> __device__ __forceinline__ const double* ctrl_of<double>(const DomView& V) { return V.ctrl; }
+template <> __device__ __forceinline__ const float* ctrl_of<float>(const DomView& V) { return V.ctrl_f; }
+// metaball sums read control points through a global pointer
+template <typename T> using gconst = const __attribute__((address_space(1))) T*;
 
 }  // namespace rwmi

@@ -31,8 +31,9 @@ hipError_t launch_walk_lowp(int bs, const Work& w, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_walk_slow_lowp(const Work& w, hipStream_t s) {
-  k_walk_slow<P32><<<w.blocks, kSlowThreads, 0, s>>>(w.views, w.boff, w.nd);
+hipError_t launch_walk_slow_lowp(int bs, const Work& w, hipStream_t s) {
+  if (bs == 128) k_walk_slow<P32, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd);
+  else k_walk_slow<P32, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd);
   return hipGetLastError();
 }
 

@@ -20,8 +20,8 @@ hipError_t launch_fluid_p64(int bs, const Work& w, hipStream_t s);
 hipError_t launch_fluid_lowp(int prec, int bs, const Work& w, hipStream_t s);
 hipError_t launch_walk_p64(int bs, const Work& w, hipStream_t s);
 hipError_t launch_walk_lowp(int bs, const Work& w, hipStream_t s);
-hipError_t launch_walk_slow_p64(const Work& w, hipStream_t s);
-hipError_t launch_walk_slow_lowp(const Work& w, hipStream_t s);
+hipError_t launch_walk_slow_p64(int bs, const Work& w, hipStream_t s);
+hipError_t launch_walk_slow_lowp(int bs, const Work& w, hipStream_t s);
 hipError_t launch_init_p64(const DomView* v, int dom, int64_t N, const double u0[3], hipStream_t s);
 hipError_t launch_init_lowp(int prec, const DomView* v, int dom, int64_t N, const double u0[3], hipStream_t s);
 hipError_t launch_read_f_p64(const DomView* v, int dom, int64_t N, double* out, hipStream_t s);
@@ -34,8 +34,9 @@ inline hipError_t launch_fluid(int prec, int bs, const Work& w, hipStream_t s) {
 inline hipError_t launch_walk(int prec, int bs, const Work& w, hipStream_t s) {
   return prec == 0 ? launch_walk_p64(bs, w, s) : launch_walk_lowp(bs, w, s);
 }
-inline hipError_t launch_walk_slow(int prec, const Work& w, hipStream_t s) {
-  return prec == 0 ? launch_walk_slow_p64(w, s) : launch_walk_slow_lowp(w, s);
+// one block per walker block (queue region), same block size as the walker kernel
+inline hipError_t launch_walk_slow(int prec, int bs, const Work& w, hipStream_t s) {
+  return prec == 0 ? launch_walk_slow_p64(bs, w, s) : launch_walk_slow_lowp(bs, w, s);
 }
 inline hipError_t launch_init(int prec, const DomView* v, int dom, int64_t N, const double u0[3], hipStream_t s) {
   return prec == 0 ? launch_init_p64(v, dom, N, u0, s) : launch_init_lowp(prec, v, dom, N, u0, s);
@@ -54,5 +55,4 @@ hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_
                           double* pw, double* pn, double* out, hipStream_t s);
 hipError_t launch_normals(uint64_t seed, uint32_t t, uint32_t purpose, int64_t n, double* z, hipStream_t s);
 
-constexpr int kSlowThreads = 128;
 }  // namespace rwmi

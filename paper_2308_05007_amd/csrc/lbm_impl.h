@@ -11,11 +11,13 @@
 // weighting, Guo source) and writes f*(t) in place of the node's own slots of
 // the other buffer, plus (u, rho).
 #pragma once
+#include <type_traits>
+
 #include "dev_common.h"
 
 namespace rwmi {
 
-constexpr int kLdsCtrl = 384;  // control points staged in LDS per block
+constexpr int kLdsCtrl = 160;  // control points staged in LDS per block
 
 struct BlockParticles {
   int cnt;
@@ -47,31 +49,33 @@ __device__ __forceinline__ double interval_gap(int periodic, int L, int lo, int 
 
 // Cull the particles for the node range [n0, n1] of a block and stage their
 // poses and control points in LDS.  Called by every thread of the block.
-__device__ __forceinline__ void cull_block(const DomView& V, int64_t n0, int64_t n1, BlockParticles& sp) {
+__device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32_t n1, BlockParticles& sp) {
   const int nx = V.n[0], ny = V.n[1];
-  const int64_t nxy = (int64_t)nx * ny;
   int lo[3], hi[3];
   {
-    const int x0 = (int)(n0 % nx), y0 = (int)((n0 / nx) % ny), z0 = (int)(n0 / nxy);
-    const int x1 = (int)(n1 % nx), y1 = (int)((n1 / nx) % ny), z1 = (int)(n1 / nxy);
+    const uint32_t a0 = fdiv(n0, V.dx), a1 = fdiv(n1, V.dx);
+    const int z0 = (int)fdiv(a0, V.dy), z1 = (int)fdiv(a1, V.dy);
+    const int x0 = (int)(n0 - a0 * (uint32_t)nx), x1 = (int)(n1 - a1 * (uint32_t)nx);
+    const int y0 = (int)a0 - z0 * ny, y1 = (int)a1 - z1 * ny;
     lo[2] = z0; hi[2] = z1;
     if (z0 == z1 && y0 == y1) { lo[0] = x0; hi[0] = x1; lo[1] = y0; hi[1] = y0; }
     else if (z0 == z1) { lo[0] = 0; hi[0] = nx - 1; lo[1] = y0; hi[1] = y1; }
     else { lo[0] = 0; hi[0] = nx - 1; lo[1] = 0; hi[1] = ny - 1; }
   }
-  const double* pose = V.pose;  // P(t) at index 0
+  const auto pose = gp((const double*)V.pose);  // P(t) at index 0
+  const auto parts = gp(V.parts);
   const int tid = threadIdx.x;
   if (tid < 64) {
     bool keep = false;
     if (tid < V.np) {
-      const double* pc = pose + 6 * tid;
+      const auto pc = pose + 6 * tid;
       double g2 = 0.0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const double g = interval_gap(!V.bc[a], V.n[a], lo[a], hi[a], pc[a]);
         g2 += g * g;
       }
-      const double cs = V.parts[tid].cutsq;
+      const double cs = parts[tid].cutsq;
       keep = g2 <= cs * (1.0 + 1e-9) + 1e-9;
     }
     const unsigned long long m = __ballot(keep);
@@ -87,7 +91,7 @@ __device__ __forceinline__ void cull_block(const DomView& V, int64_t n0, int64_t
   if (tid == 0) {
     int off = 0;
     for (int k = 0; k < cnt; ++k) {
-      const int nc = V.parts[sp.id[k]].nc;
+      const int nc = parts[sp.id[k]].nc;
       sp.nc[k] = nc;
       if (off + nc <= kLdsCtrl) {
         sp.ctrl_off[k] = off;
@@ -99,19 +103,19 @@ __device__ __forceinline__ void cull_block(const DomView& V, int64_t n0, int64_t
   }
   if (tid < cnt) {
     const int p = sp.id[tid];
-    const double* pc = pose + 6 * p;
+    const auto pc = pose + 6 * p;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       sp.c[tid][a] = pc[a];
       sp.v[tid][a] = pc[3 + a];
     }
-    sp.cutsq[tid] = V.parts[p].cutsq;
+    sp.cutsq[tid] = parts[p].cutsq;
   }
   __syncthreads();
   for (int k = 0; k < cnt; ++k) {
     const int off = sp.ctrl_off[k];
     if (off < 0) continue;
-    const double* src = V.ctrl + 4 * V.parts[sp.id[k]].ctrl0;
+    const auto src = gp(V.ctrl) + 4 * parts[sp.id[k]].ctrl0;
     for (int j = tid; j < 4 * sp.nc[k]; j += blockDim.x) sp.ctrl[4 * off + j] = src[j];
   }
   __syncthreads();
@@ -126,12 +130,19 @@ __device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles& sp
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], nd[2], sp.c[k][2], (R)0.5);
   const R r2c = (dx * dx + dy * dy) + dz * dz;
   if (r2c > (R)sp.cutsq[k]) return (R)0;
-  const double* ctrl = sp.ctrl_off[k] >= 0 ? sp.ctrl + 4 * sp.ctrl_off[k] : V.ctrl + 4 * V.parts[sp.id[k]].ctrl0;
   const int nc = sp.nc[k];
-  const R M = metaball_value<R>(ctrl, nc, dx, dy, dz);
-  if (M == (R)INFINITY) return (R)1;
-  R g[3];
-  metaball_grad<R>(ctrl, nc, dx, dy, dz, g);
+  R M, g[3];
+  if (sp.ctrl_off[k] >= 0) {
+    const double* ctrl = sp.ctrl + 4 * sp.ctrl_off[k];
+    M = metaball_value<R>(ctrl, nc, dx, dy, dz);
+    if (M == (R)INFINITY) return (R)1;
+    metaball_grad<R>(ctrl, nc, dx, dy, dz, g);
+  } else {
+    const auto ctrl = gp(V.ctrl) + 4 * gp(V.parts)[sp.id[k]].ctrl0;
+    M = metaball_value<R>(ctrl, nc, dx, dy, dz);
+    if (M == (R)INFINITY) return (R)1;
+    metaball_grad<R>(ctrl, nc, dx, dy, dz, g);
+  }
   const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
   R e;
   if (gn == (R)0) {
@@ -170,6 +181,25 @@ __device__ __forceinline__ int wall_slot(const DomView& V, const int nd[3], int 
   return -1;
 }
 
+// Compile-time sum of the components of (ax, ay, az) picked by direction i
+// (e_i . a with zero components skipped, left to right).
+template <int i, typename R>
+__device__ __forceinline__ R edot_c(R ax, R ay, R az) {
+  R s = (R)0;
+  if constexpr (kEx[i] == 1) s = s + ax; else if constexpr (kEx[i] == -1) s = s - ax;
+  if constexpr (kEy[i] == 1) s = s + ay; else if constexpr (kEy[i] == -1) s = s - ay;
+  if constexpr (kEz[i] == 1) s = s + az; else if constexpr (kEz[i] == -1) s = s - az;
+  return s;
+}
+
+template <int I, int N_, typename F>
+__device__ __forceinline__ void unroll(F&& f) {
+  if constexpr (I < N_) {
+    f(std::integral_constant<int, I>{});
+    unroll<I + 1, N_>(f);
+  }
+}
+
 template <int P, int BS>
 __global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
                                               int nd_count) {
@@ -179,26 +209,41 @@ __global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views,
   __shared__ BlockParticles sp;
   const int d = find_domain(boff, nd_count, blockIdx.x);
   const DomView& V = views[d];
-  const int64_t lb = (int64_t)blockIdx.x - boff[d];
-  const uint64_t t = V.tstep[1];
-  if (lb == 0 && threadIdx.x == 0) V.tstep[0] = t + 1;
-  const S* __restrict__ src = (const S*)((t & 1ull) ? V.fB : V.fA);
-  S* __restrict__ dst = (S*)((t & 1ull) ? V.fA : V.fB);
-  const int64_t N = V.N;
-  const int64_t n0 = lb * BS;
-  const int64_t n1 = (n0 + BS - 1 < N) ? n0 + BS - 1 : N - 1;
+  const uint32_t lb = (uint32_t)((int)blockIdx.x - boff[d]);
+  const auto tstep = gp(V.tstep);
+  const uint64_t t = tstep[1];
+  if (lb == 0 && threadIdx.x == 0) tstep[0] = t + 1;
+  using SR = typename Raw<S>::T;
+  const auto src = gp((const SR*)((t & 1ull) ? V.fB : V.fA));
+  const auto dst = gp((SR*)((t & 1ull) ? V.fA : V.fB));
+  const uint32_t N = (uint32_t)V.N;
+  const uint32_t n0 = lb * BS;
+  const uint32_t n1 = (n0 + BS - 1 < N) ? n0 + BS - 1 : N - 1;
   if (V.np > 0) cull_block(V, n0, n1, sp);
   else if (threadIdx.x == 0) sp.cnt = 0;
   __syncthreads();
 
-  const int64_t id = n0 + threadIdx.x;
+  const uint32_t id = n0 + threadIdx.x;
   if (id >= N) return;
   const int nx = V.n[0], ny = V.n[1], nz = V.n[2];
-  const int64_t nxy = (int64_t)nx * ny;
-  const int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / nxy)};
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-    if (V.bc[a] && (nd[a] == 0 || nd[a] == V.n[a] - 1)) return;  // wall node: never updated
+  const int bx = V.bc[0], by = V.bc[1], bz = V.bc[2];
+  const uint32_t q1 = fdiv(id, V.dx);
+  const int x = (int)(id - q1 * (uint32_t)nx);
+  const int z = (int)fdiv(q1, V.dy);
+  const int y = (int)q1 - z * ny;
+  if ((bx && (x == 0 || x == nx - 1)) || (by && (y == 0 || y == ny - 1)) || (bz && (z == 0 || z == nz - 1)))
+    return;  // wall node: never updated
+  const int nd[3] = {x, y, z};
+  const int sxy = nx * ny;
+  // linear offsets to the six face neighbours (periodic wrap)
+  const int dxm = x > 0 ? -1 : nx - 1, dxp = x < nx - 1 ? 1 : -(nx - 1);
+  const int dym = y > 0 ? -nx : (ny - 1) * nx, dyp = y < ny - 1 ? nx : -(ny - 1) * nx;
+  const int dzm = z > 0 ? -sxy : (nz - 1) * sxy, dzp = z < nz - 1 ? sxy : -(nz - 1) * sxy;
+  // neighbour at -1 / +1 along an axis is a wall node
+  const bool wxl = bx && x == 1, wxh = bx && x == nx - 2;
+  const bool wyl = by && y == 1, wyh = by && y == ny - 2;
+  const bool wzl = bz && z == 1, wzh = bz && z == nz - 2;
+  const bool near_wall = wxl | wxh | wyl | wyh | wzl | wzh;
 
   // ---- solid fraction and solid velocity
   R es = (R)0, unx = (R)0, uny = (R)0, unz = (R)0;
@@ -210,28 +255,25 @@ __global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views,
     unz = unz + e * (R)sp.v[k][2];
   }
   const R eps = es < (R)1 ? es : (R)1;
-  const R usx = es > (R)0 ? unx / es : (R)0;
-  const R usy = es > (R)0 ? uny / es : (R)0;
-  const R usz = es > (R)0 ? unz / es : (R)0;
+  const bool solid = eps > (R)0;
 
-  // ---- gather (pull-stream with bounce-back from wall nodes)
+  // ---- gather (pull-stream; from a wall node the stored bounced population)
   R f[kQ];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const int ex = kEx[i], ey = kEy[i], ez = kEz[i];
-    int sx = nd[0] - ex, sy = nd[1] - ey, sz = nd[2] - ez;
+  unroll<0, kQ>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int ex = kEx[i], ey = kEy[i], ez = kEz[i];
     bool wall = false;
-    if (V.bc[0]) wall |= (ex != 0) && (sx == 0 || sx == nx - 1);
-    else sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-    if (V.bc[1]) wall |= (ey != 0) && (sy == 0 || sy == ny - 1);
-    else sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
-    if (V.bc[2]) wall |= (ez != 0) && (sz == 0 || sz == nz - 1);
-    else sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
-    const int64_t sidx = wall ? (int64_t)opp_dir(i) * N + id : (int64_t)i * N + (sx + nx * ((int64_t)sy + (int64_t)ny * sz));
-    f[i] = (R)to_c(src[sidx]);
-  }
+    int delta = 0;
+    if constexpr (ex == 1) { wall |= wxl; delta += dxm; } else if constexpr (ex == -1) { wall |= wxh; delta += dxp; }
+    if constexpr (ey == 1) { wall |= wyl; delta += dym; } else if constexpr (ey == -1) { wall |= wyh; delta += dyp; }
+    if constexpr (ez == 1) { wall |= wzl; delta += dzm; } else if constexpr (ez == -1) { wall |= wzh; delta += dzp; }
+    const auto base = src + (size_t)(wall ? opp_dir(i) : i) * N;
+    const SR raw = base[wall ? id : (uint32_t)((int)id + delta)];
+    if constexpr (exact) f[i] = raw;
+    else f[i] = raw_in<S>(raw);
+  });
 
-  // ---- moments
+  // ---- moments (Eq. 14-15; Guo half-force velocity)
   R rho, drho;
   if constexpr (exact) {
     rho = (R)0;
@@ -245,99 +287,145 @@ __global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views,
     rho = V.rho0_f + drho;
   }
   R jx = (R)0, jy = (R)0, jz = (R)0;
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    if (kEx[i] == 1) jx = jx + f[i]; else if (kEx[i] == -1) jx = jx - f[i];
-    if (kEy[i] == 1) jy = jy + f[i]; else if (kEy[i] == -1) jy = jy - f[i];
-    if (kEz[i] == 1) jz = jz + f[i]; else if (kEz[i] == -1) jz = jz - f[i];
-  }
+  unroll<0, kQ>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (kEx[i] == 1) jx = jx + f[i]; else if constexpr (kEx[i] == -1) jx = jx - f[i];
+    if constexpr (kEy[i] == 1) jy = jy + f[i]; else if constexpr (kEy[i] == -1) jy = jy - f[i];
+    if constexpr (kEz[i] == 1) jz = jz + f[i]; else if constexpr (kEz[i] == -1) jz = jz - f[i];
+  });
   R ux, uy, uz;
   if constexpr (exact) {
     ux = (jx + 0.5 * V.F[0]) / rho;
     uy = (jy + 0.5 * V.F[1]) / rho;
     uz = (jz + 0.5 * V.F[2]) / rho;
   } else {
-    ux = (jx + V.halfF_f[0]) / rho;
-    uy = (jy + V.halfF_f[1]) / rho;
-    uz = (jz + V.halfF_f[2]) / rho;
+    const R ir = (R)1 / rho;
+    ux = (jx + V.halfF_f[0]) * ir;
+    uy = (jy + V.halfF_f[1]) * ir;
+    uz = (jz + V.halfF_f[2]) * ir;
   }
 
-  // ---- collision
+  // ---- BGK relaxation (Eq. 12-13), Noble-Torczynski weighting where eps > 0
   R omega, tm, cfree;
-  R Fx, Fy, Fz;
-  if constexpr (exact) { omega = V.omega; tm = V.tm; cfree = V.cfree; Fx = V.F[0]; Fy = V.F[1]; Fz = V.F[2]; }
-  else { omega = V.omega_f; tm = V.tm_f; cfree = V.cfree_f; Fx = V.F_f[0]; Fy = V.F_f[1]; Fz = V.F_f[2]; }
-  const R uu = (ux * ux + uy * uy) + uz * uz;
-  const R uu15 = (R)1.5 * uu;
-  const bool solid = eps > (R)0;
+  if constexpr (exact) { omega = V.omega; tm = V.tm; cfree = V.cfree; }
+  else { omega = V.omega_f; tm = V.tm_f; cfree = V.cfree_f; }
+  const R uu15 = (R)1.5 * ((ux * ux + uy * uy) + uz * uz);
   R B = (R)0, A = omega, Cf = cfree;
   if (solid) {
     B = (eps * tm) / (((R)1 - eps) + tm);
     A = ((R)1 - B) * omega;
     Cf = ((R)1 - B) * ((R)1 - (R)0.5 * omega);
   }
-  R uss15 = (R)0;
-  if (solid) uss15 = (R)1.5 * ((usx * usx + usy * usy) + usz * usz);
+  R usx = (R)0, usy = (R)0, usz = (R)0, us15 = (R)0;
+  if (solid) {
+    usx = unx / es;
+    usy = uny / es;
+    usz = unz / es;
+    us15 = (R)1.5 * ((usx * usx + usy * usy) + usz * usz);
+  }
+  R Fx, Fy, Fz;
+  if constexpr (exact) { Fx = V.F[0]; Fy = V.F[1]; Fz = V.F[2]; }
+  else { Fx = V.F_f[0]; Fy = V.F_f[1]; Fz = V.F_f[2]; }
+  const R uF = (ux * Fx + uy * Fy) + uz * Fz;
+  const bool force = V.has_force != 0;
 
   // equilibria: exact form (w rho)(((1 + 3 eu) + 4.5 eu^2) - 1.5 uu); the
-  // shifted form returns feq - w rho0 = w (drho + rho (3 eu + 4.5 eu^2 - 1.5 uu))
-  auto feq = [&](int i, R eu, R u15) -> R {
-    if constexpr (exact) {
-      return (weight<R>(i) * rho) * ((((R)1 + (R)3 * eu) + (R)4.5 * (eu * eu)) - u15);
-    } else {
-      return weight<R>(i) * (drho + rho * (((R)3 * eu + (R)4.5 * (eu * eu)) - u15));
-    }
+  // shifted form feq - w rho0 = w (drho + rho (3 eu + 4.5 eu^2 - 1.5 uu))
+  auto feq = [&](auto ic, R eu, R u15) -> R {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (exact) return (weight<R>(i) * rho) * ((((R)1 + (R)3 * eu) + (R)4.5 * (eu * eu)) - u15);
+    else return weight<R>(i) * (drho + rho * (eu * ((R)3 + (R)4.5 * eu) - u15));
   };
-  R fe[kQ];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) fe[i] = feq(i, edot<R>(i, ux, uy, uz), uu15);
-
-  R out[kQ];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    R v = f[i] - A * (f[i] - fe[i]);
-    if (solid) {
-      const int o = opp_dir(i);
-      const R fes = feq(i, edot<R>(i, usx, usy, usz), uss15);
-      const R Om = (f[o] - fe[o]) - (f[i] - fes);
-      v = v + B * Om;
-    }
-    if (V.has_force) {
-      const R eu = edot<R>(i, ux, uy, uz);
-      const R eF = edot<R>(i, Fx, Fy, Fz);
+  // Guo source S_i = w_i [3 (e_i - u).F + 9 (e_i.u)(e_i.F)]
+  auto guo = [&](auto ic, R eu) -> R {
+    constexpr int i = decltype(ic)::value;
+    const R eF = edot_c<i, R>(Fx, Fy, Fz);
+    if constexpr (exact) {
       R emF = (R)0;
       emF = emF + ((R)kEx[i] - ux) * Fx;
       emF = emF + ((R)kEy[i] - uy) * Fy;
       emF = emF + ((R)kEz[i] - uz) * Fz;
-      const R Si = weight<R>(i) * ((R)3 * emF + ((R)9 * eu) * eF);
-      v = v + Cf * Si;
+      return weight<R>(i) * ((R)3 * emF + ((R)9 * eu) * eF);
+    } else {
+      return weight<R>(i) * ((R)3 * (eF - uF) + (R)9 * eu * eF);
     }
-    out[i] = v;
-  }
-
-  // ---- store f*(t), pre-adding the moving-wall term for populations that
-  // will bounce off a wall node at the next step
-#pragma unroll
-  for (int j = 0; j < kQ; ++j) {
-    R v = out[j];
-    const int ws = wall_slot(V, nd, kEx[j], kEy[j], kEz[j]);
+  };
+  // moving-wall term for a population headed for a wall node (Eq. 23 form),
+  // added now so that the next gather only has to bounce it
+  auto wall_term = [&](auto jc, R& v) {
+    constexpr int j = decltype(jc)::value;
+    constexpr int i = opp_dir(j);
+    constexpr int ex = kEx[j], ey = kEy[j], ez = kEz[j];
+    int ws = -1;  // wall slot of the first wall axis the neighbour x + e_j lies on
+    if constexpr (ex == -1) { if (wxl) ws = 0; } else if constexpr (ex == 1) { if (wxh) ws = 1; }
+    if constexpr (ey == -1) { if (ws < 0 && wyl) ws = 2; } else if constexpr (ey == 1) { if (ws < 0 && wyh) ws = 3; }
+    if constexpr (ez == -1) { if (ws < 0 && wzl) ws = 4; } else if constexpr (ez == 1) { if (ws < 0 && wzh) ws = 5; }
     if (ws >= 0) {
-      const int i = opp_dir(j);
       const int a = ws >> 1, side = ws & 1;
       R wx, wy, wz;
       if constexpr (exact) { wx = V.wu[a][side][0]; wy = V.wu[a][side][1]; wz = V.wu[a][side][2]; }
       else { wx = V.wu_f[a][side][0]; wy = V.wu_f[a][side][1]; wz = V.wu_f[a][side][2]; }
-      v = v + (((R)6 * weight<R>(i)) * rho) * edot<R>(i, wx, wy, wz);
+      v = v + (((R)6 * weight<R>(i)) * rho) * edot_c<i, R>(wx, wy, wz);
     }
-    if constexpr (exact) dst[(int64_t)j * N + id] = v;
-    else dst[(int64_t)j * N + id] = from_c<S>(v);
+  };
+  auto put = [&](auto jc, R v) {
+    constexpr int j = decltype(jc)::value;
+    if constexpr (exact) dst[(size_t)j * N + id] = v;
+    else dst[(size_t)j * N + id] = raw_out<S>(v);
+  };
+
+  // rest population
+  {
+    constexpr std::integral_constant<int, 0> i0{};
+    const R fe0 = feq(i0, (R)0, uu15);
+    R o0 = f[0] - A * (f[0] - fe0);
+    if (solid) o0 = o0 + B * ((f[0] - fe0) - (f[0] - feq(i0, (R)0, us15)));
+    if (force) o0 = o0 + Cf * guo(i0, (R)0);
+    put(i0, o0);
   }
-  using U = typename Store<P>::U;
-  U* __restrict__ u4 = (U*)V.u4;
-  u4[4 * id + 0] = (U)ux;
-  u4[4 * id + 1] = (U)uy;
-  u4[4 * id + 2] = (U)uz;
-  u4[4 * id + 3] = (U)rho;
+  // opposite pairs (i, i+1): each pair is relaxed, exchanged with the solid,
+  // forced and stored before the next, so few registers stay live
+  unroll<0, 9>([&](auto pc) {
+    constexpr int i = 1 + 2 * decltype(pc)::value;
+    constexpr int o = i + 1;
+    constexpr std::integral_constant<int, i> ic{};
+    constexpr std::integral_constant<int, o> oc{};
+    const R eui = edot_c<i, R>(ux, uy, uz);
+    const R euo = edot_c<o, R>(ux, uy, uz);
+    const R fei = feq(ic, eui, uu15);
+    const R feo = feq(oc, euo, uu15);
+    R vi = f[i] - A * (f[i] - fei);
+    R vo = f[o] - A * (f[o] - feo);
+    if (solid) {
+      const R fesi = feq(ic, edot_c<i, R>(usx, usy, usz), us15);
+      const R feso = feq(oc, edot_c<o, R>(usx, usy, usz), us15);
+      vi = vi + B * ((f[o] - feo) - (f[i] - fesi));
+      vo = vo + B * ((f[i] - fei) - (f[o] - feso));
+    }
+    if (force) {
+      vi = vi + Cf * guo(ic, eui);
+      vo = vo + Cf * guo(oc, euo);
+    }
+    if (near_wall) {
+      wall_term(ic, vi);
+      wall_term(oc, vo);
+    }
+    put(ic, vi);
+    put(oc, vo);
+  });
+  if constexpr (exact) {
+    const auto u = gp((double*)V.u4) + 4 * (size_t)id;
+    u[0] = ux;
+    u[1] = uy;
+    u[2] = uz;
+    u[3] = rho;
+  } else {
+    const auto u = gp((float*)V.u4) + 4 * (size_t)id;
+    u[0] = ux;
+    u[1] = uy;
+    u[2] = uz;
+    u[3] = rho;
+  }
 }
 
 // Initial stored state: streaming it reproduces f = feq(rho0, u0) at every

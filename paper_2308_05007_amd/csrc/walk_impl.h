@@ -39,53 +39,79 @@ __device__ __forceinline__ int64_t mask_index(const DomView& V, const int c[3], 
     int k = c[a] + (int)floor(x[a]);
     const int n = V.n[a];
     if (!V.bc[a]) {
-      k %= n;
-      if (k < 0) k += n;
+      if (k < 0 || k >= n) {
+        k %= n;
+        if (k < 0) k += n;
+      }
     } else {
       k = k < 0 ? 0 : (k >= n ? n - 1 : k);
     }
     b[a] = k / kMaskBlock;
   }
-  return (int64_t)b[0] + (int64_t)V.mb[0] * ((int64_t)b[1] + (int64_t)V.mb[1] * b[2]);
+  return b[0] + V.mb[0] * (b[1] + V.mb[1] * b[2]);
 }
 
 // Particle pose at t+1 from the pose table.
-__device__ __forceinline__ const double* pose_next(const DomView& V, int p) { return V.pose + 6 * (V.np + p); }
+__device__ __forceinline__ gconst<double> pose_next(const DomView& V, int p) {
+  return gp((const double*)V.pose) + 6 * (V.np + p);
+}
 
 template <typename R>
 __device__ __forceinline__ R particle_M_at(const DomView& V, int p, const int c[3], const R x[3]) {
-  const double* pc = pose_next(V, p);
+  const auto pc = pose_next(V, p);
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
-  const DevParticle& P = V.parts[p];
-  return metaball_value<R>(V.ctrl + 4 * P.ctrl0, P.nc, dx, dy, dz);
+  const auto P = gp(V.parts) + p;
+  return metaball_value<R>(gp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz);
 }
 
 template <typename R>
 __device__ __forceinline__ void particle_grad_at(const DomView& V, int p, const int c[3], const R x[3], R g[3]) {
-  const double* pc = pose_next(V, p);
+  const auto pc = pose_next(V, p);
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
-  const DevParticle& P = V.parts[p];
-  metaball_grad<R>(V.ctrl + 4 * P.ctrl0, P.nc, dx, dy, dz, g);
+  const auto P = gp(V.parts) + p;
+  metaball_grad<R>(gp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz, g);
 }
 
 // Lowest index of a particle whose own M >= 1 at (c + x), or -1.  Particles
 // whose bounding sphere (rb + 1/2) is farther than the point are skipped: M < 1
 // there (bounding-radius lemma), so the result is that of testing all.
+// Is (c + x) within the sphere (c_p(t+1), rb_p + 1/2) of particle p?
+template <typename R>
+__device__ __forceinline__ bool in_sphere(const DomView& V, int p, const int c[3], const R x[3]) {
+  const auto pc = pose_next(V, p);
+  const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
+  const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
+  const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
+  const double mr = gp(V.parts)[p].maskr;
+  return (dx * dx + dy * dy) + dz * dz < (R)(mr * mr);
+}
+
+template <typename R>
+__device__ __forceinline__ unsigned long long mask_at(const DomView& V, const int c[3], const R x[3]) {
+  return gp((const unsigned long long*)V.mask)[mask_index<R>(V, c, x)];
+}
+
 template <typename R>
 __device__ __forceinline__ int inside_any(const DomView& V, const int c[3], const R x[3]) {
-  for (int p = 0; p < V.np; ++p) {
-    const double* pc = pose_next(V, p);
+  // only the particles whose mask bit is set for the point's coarse block can
+  // contain it; visit them in ascending index order
+  unsigned long long bits = mask_at<R>(V, c, x);
+  while (bits) {
+    const int p = __ffsll((long long)bits) - 1;
+    bits &= bits - 1ull;
+    const auto pc = pose_next(V, p);
     const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
     const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
     const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
-    const DevParticle& P = V.parts[p];
+    const auto P = gp(V.parts) + p;
     const R r2 = (dx * dx + dy * dy) + dz * dz;
-    if (r2 >= (R)(P.maskr * P.maskr)) continue;
-    if (metaball_value<R>(V.ctrl + 4 * P.ctrl0, P.nc, dx, dy, dz) >= (R)1) return p;
+    const double mr = P->maskr;
+    if (r2 >= (R)(mr * mr)) continue;
+    if (metaball_value<R>(gp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz) >= (R)1) return p;
   }
   return -1;
 }
@@ -152,7 +178,8 @@ __device__ __forceinline__ bool finite3(const R x[3]) {
 // Write back (cell, offset in [0,1), image counts on periodic wrap).
 template <typename R>
 __device__ __forceinline__ void store_walker(const DomView& V, int64_t w, int c[3], const R xn[3]) {
-  R* __restrict__ off = (R*)V.woff;
+  const auto off = gp((R*)V.woff);
+  const auto img = gp(V.wimg);
   const int64_t nw = V.nw;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -168,13 +195,13 @@ __device__ __forceinline__ void store_walker(const DomView& V, int64_t w, int c[
       if (cc < 0 || cc >= n) {
         const int q = cc >= 0 ? cc / n : -((-cc + n - 1) / n);  // floor(cc / n)
         cc -= q * n;
-        V.wimg[a * nw + w] += q;
+        img[a * nw + w] += q;
       }
     }
     c[a] = cc;
     off[a * nw + w] = of;
   }
-  V.wcell[w] = (int32_t)lin(V, c[0], c[1], c[2]);
+  gp(V.wcell)[w] = (int32_t)lin(V, c[0], c[1], c[2]);
 }
 
 template <int P, int BS>
@@ -190,11 +217,13 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
   bool refl = false;
   R dl[3] = {(R)0, (R)0, (R)0};
   if (active) {
-    const uint64_t t = V.tstep[1];
+    const uint64_t t = gp(V.tstep)[1];
     const int nx = V.n[0], ny = V.n[1];
-    const int32_t lc = V.wcell[w];
-    int c[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
-    const R* __restrict__ off = (const R*)V.woff;
+    const uint32_t lc = (uint32_t)gp(V.wcell)[w];
+    const uint32_t q1 = fdiv(lc, V.dx);
+    const int cz = (int)fdiv(q1, V.dy);
+    int c[3] = {(int)(lc - q1 * (uint32_t)nx), (int)q1 - cz * ny, cz};
+    const auto off = gp((const R*)V.woff);
     const R o[3] = {off[w], off[V.nw + w], off[2 * V.nw + w]};
     // trilinear interpolation between node centres
     int b0[3], b1[3];
@@ -215,7 +244,7 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
       b0[a] = b;
       b1[a] = b1a;
     }
-    const U* __restrict__ u4 = (const U*)V.u4;
+    const auto u4 = gp((const U*)V.u4);
     R Ui[3];
     {
       R v[2][2][3];
@@ -240,25 +269,33 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
     }
     // Brownian step (Eq. 2 with dt = 1)
     const U4 r = philox4x32_10((uint32_t)w, (uint32_t)t, 0u, 0u, V.key0, V.key1);
-    double z0, z1, z2;
-    gauss3(r, z0, z1, z2);
     R xf[3];
     if constexpr (P == P64) {
+      double z0, z1, z2;
+      gauss3(r, z0, z1, z2);
       dl[0] = Ui[0] + z0 * V.sD;
       dl[1] = Ui[1] + z1 * V.sD;
       dl[2] = Ui[2] + z2 * V.sD;
     } else {
-      dl[0] = Ui[0] + (R)z0 * V.sD_f;
-      dl[1] = Ui[1] + (R)z1 * V.sD_f;
-      dl[2] = Ui[2] + (R)z2 * V.sD_f;
+      float z0, z1, z2;
+      gauss3_fast(r, z0, z1, z2);
+      dl[0] = Ui[0] + z0 * V.sD_f;
+      dl[1] = Ui[1] + z1 * V.sD_f;
+      dl[2] = Ui[2] + z2 * V.sD_f;
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) xf[a] = o[a] + dl[a];
     if (V.np > 0) {
+      // a walker that starts and ends outside every bounding sphere is
+      // neither type II nor IV (M < 1 outside rb); candidates come from the
+      // coarse mask, the exact sphere test decides
       const R zero3[3] = {(R)0, (R)0, (R)0};
-      const unsigned long long mA = V.mask[mask_index<R>(V, c, zero3)];
-      const unsigned long long mB = V.mask[mask_index<R>(V, c, xf)];
-      queue = (mA | mB) != 0ull;
+      unsigned long long bits = mask_at<R>(V, c, zero3) | mask_at<R>(V, c, xf);
+      while (bits && !queue) {
+        const int p = __ffsll((long long)bits) - 1;
+        bits &= bits - 1ull;
+        queue = in_sphere<R>(V, p, c, o) || in_sphere<R>(V, p, c, xf);
+      }
     }
     if (!queue) {
       R xn[3] = {xf[0], xf[1], xf[2]};
@@ -273,54 +310,75 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
             atomicAdd(&V.counters[kReturned], 1ull);
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] = o[a];
-          } else if (V.np > 0 && V.mask[mask_index<R>(V, c, xn)] != 0ull) {
-            queue = true;  // the reflected point may be inside a particle
-            refl = false;
+          } else if (V.np > 0) {
+            unsigned long long bits = mask_at<R>(V, c, xn);
+            while (bits && !queue) {
+              const int p = __ffsll((long long)bits) - 1;
+              bits &= bits - 1ull;
+              queue = in_sphere<R>(V, p, c, xn);  // the reflected point may be inside a particle
+            }
+            if (queue) refl = false;
           }
         }
       }
       if (!queue) store_walker<R>(V, w, c, xn);
     }
   }
-  // wavefront-ballot compaction into the near-surface queue
+  // wavefront-ballot compaction into this block's region of the queue (no
+  // global atomics): ballot and popcount per wave, prefix over the waves in
+  // LDS, one count per block
+  constexpr int kWaves = BS / 64;
+  __shared__ uint32_t s_q[kWaves], s_r[kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long qm = __ballot(queue);
-  if (qm) {
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)qm) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(V.qcount, (uint32_t)__popcll(qm));
-    base = __shfl(base, leader);
-    if (queue) {
-      const uint32_t slot = base + (uint32_t)__popcll(qm & ((1ull << lane) - 1ull));
-      V.qid[slot] = (int32_t)w;
-      R* qdl = (R*)V.qdl;
-      qdl[slot] = dl[0];
-      qdl[V.qcap + slot] = dl[1];
-      qdl[2 * V.qcap + slot] = dl[2];
-    }
-  }
   const unsigned long long rm = __ballot(refl);
-  if (rm && (threadIdx.x & 63) == __ffsll((long long)rm) - 1)
-    atomicAdd(&V.counters[kWallReflect], (unsigned long long)__popcll(rm));
+  if (lane == 0) {
+    s_q[wave] = (uint32_t)__popcll(qm);
+    s_r[wave] = (uint32_t)__popcll(rm);
+  }
+  __syncthreads();
+  uint32_t before = 0, total = 0, refl_total = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    before += k < wave ? s_q[k] : 0u;
+    total += s_q[k];
+    refl_total += s_r[k];
+  }
+  const int64_t lblock = (int64_t)blockIdx.x - boff[d];
+  if (queue) {
+    const int64_t slot = lblock * BS + before + (uint32_t)__popcll(qm & ((1ull << lane) - 1ull));
+    gp(V.qid)[slot] = (int32_t)w;
+    const auto qdl = gp((R*)V.qdl);
+    qdl[slot] = dl[0];
+    qdl[V.qcap + slot] = dl[1];
+    qdl[2 * V.qcap + slot] = dl[2];
+  }
+  if (threadIdx.x == 0) {
+    if (V.np > 0) gp(V.qcount)[lblock] = total;
+    if (refl_total) atomicAdd(&V.counters[kWallReflect], (unsigned long long)refl_total);
+  }
 }
 
-template <int P>
-__global__ void k_walk_slow(const DomView* __restrict__ views, const int32_t* __restrict__ boff, int nd_count) {
+template <int P, int BS>
+__global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
+                                                  int nd_count) {
   using R = typename Store<P>::O;
   const int d = find_domain(boff, nd_count, blockIdx.x);
   const DomView& V = views[d];
-  const int nblk = boff[d + 1] - boff[d];
-  const int64_t stride = (int64_t)nblk * blockDim.x;
-  const uint32_t nq = *V.qcount;
-  const uint64_t t = V.tstep[1];
+  const int64_t wb = (int64_t)blockIdx.x - boff[d];  // queue region of walker block wb
+  const uint64_t t = gp(V.tstep)[1];
   const int nx = V.n[0], ny = V.n[1];
-  const R* __restrict__ off = (const R*)V.woff;
-  const R* __restrict__ qdl = (const R*)V.qdl;
-  for (int64_t q = ((int64_t)blockIdx.x - boff[d]) * blockDim.x + threadIdx.x; q < (int64_t)nq; q += stride) {
-    const int64_t w = V.qid[q];
+  const auto off = gp((const R*)V.woff);
+  const auto qdl = gp((const R*)V.qdl);
+  const uint32_t nq = gp((const uint32_t*)V.qcount)[wb];
+  if (threadIdx.x < nq) {
+    const int64_t q = wb * BS + threadIdx.x;
+    const int64_t w = gp(V.qid)[q];
     const R dl[3] = {qdl[q], qdl[V.qcap + q], qdl[2 * V.qcap + q]};
-    const int32_t lc = V.wcell[w];
-    int c[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
+    const uint32_t lc = (uint32_t)gp(V.wcell)[w];
+    const uint32_t q1 = fdiv(lc, V.dx);
+    const int cz = (int)fdiv(q1, V.dy);
+    int c[3] = {(int)(lc - q1 * (uint32_t)nx), (int)q1 - cz * ny, cz};
     const R o[3] = {off[w], off[V.nw + w], off[2 * V.nw + w]};
     R xf[3], xn[3];
 #pragma unroll
@@ -376,7 +434,7 @@ __global__ void k_walk_slow(const DomView* __restrict__ views, const int32_t* __
         if (gn > (R)0) {
           const R no[3] = {(-g[0]) / gn, (-g[1]) / gn, (-g[2]) / gn};
           R s = (R)0.5;
-          const R lim = (R)(2.0 * V.parts[jb].rb);
+          const R lim = (R)(2.0 * gp(V.parts)[jb].rb);
           R xe[3];
           for (;;) {
 #pragma unroll
@@ -392,9 +450,16 @@ __global__ void k_walk_slow(const DomView* __restrict__ views, const int32_t* __
               for (int a = 0; a < 3; ++a) xs[a] = xf[a] + ss * no[a];
               const U4 r1 = philox4x32_10((uint32_t)w, (uint32_t)t, 1u, 0u, V.key0, V.key1);
               const U4 r2 = philox4x32_10((uint32_t)w, (uint32_t)t, 2u, 0u, V.key0, V.key1);
-              double v0, v1, v2;
-              gauss3(r1, v0, v1, v2);
-              R v[3] = {(R)v0, (R)v1, (R)v2};
+              R v[3];
+              if constexpr (P == P64) {
+                double v0, v1, v2;
+                gauss3(r1, v0, v1, v2);
+                v[0] = v0; v[1] = v1; v[2] = v2;
+              } else {
+                float v0, v1, v2;
+                gauss3_fast(r1, v0, v1, v2);
+                v[0] = v0; v[1] = v1; v[2] = v2;
+              }
               const R vn = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
 #pragma unroll
               for (int a = 0; a < 3; ++a) v[a] = v[a] / vn;

@@ -60,8 +60,10 @@ typedef enum { RWMI_BC_PERIODIC = 0, RWMI_BC_WALL = 1 } rwmi_bc;
  * double, arithmetic in double with no contraction (reproduces the FP64
  * reference bit for bit).  FP32 / FP16_STORE / BF16_STORE: distributions
  * stored as deviations f_i - w_i rho0 in float / half / bfloat16, collision
- * in float, velocity field in float, walker offsets in float; Gaussian
- * normals are always drawn in double so every mode sees the same noise. */
+ * in float, velocity field in float, walker offsets in float.  Every mode
+ * draws its Gaussian normals from the same Philox words (FP64 with an exact
+ * double Box-Muller, the others with the float hardware log / sin / cos), so
+ * the walkers of all modes see the same noise up to float rounding. */
 typedef enum { RWMI_FP64 = 0, RWMI_FP32 = 1, RWMI_FP16_STORE = 2, RWMI_BF16_STORE = 3 } rwmi_precision;
 
 /* Prescribed rigid motion of a particle (fixed orientation; the oscillator of
@@ -222,13 +224,18 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles
  *   RWMI_KEY_USE_GRAPH       0/1: replay steps from a captured hipGraph
  *   RWMI_KEY_LBM_BLOCK       threads per block of the fluid kernel (64..1024, multiple of 64)
  *   RWMI_KEY_WALK_BLOCK      threads per block of the walker kernel
- *   RWMI_KEY_TIMING          0/1: record HIP events around every kernel of a step */
+ *   RWMI_KEY_TIMING          0/1: record HIP events around every kernel of a step
+ *   RWMI_KEY_FLUID_FLAGS     launch options of the fluid kernel: bit 0 hands each of
+ *                            the 8 XCDs a contiguous range of blocks (default on),
+ *                            bit 1 writes f* and (u, rho) with non-temporal stores
+ * Results never depend on the block sizes or flags. */
 enum {
   RWMI_KEY_MAX_BISECT = 1,
   RWMI_KEY_USE_GRAPH = 2,
   RWMI_KEY_LBM_BLOCK = 3,
   RWMI_KEY_WALK_BLOCK = 4,
-  RWMI_KEY_TIMING = 5
+  RWMI_KEY_TIMING = 5,
+  RWMI_KEY_FLUID_FLAGS = 6
 };
 rwmi_status rwmi_debug_set(rwmi_domain* dom, int32_t key, int64_t value);
 
@@ -256,6 +263,8 @@ rwmi_status rwmi_batch_add(rwmi_batch* b, rwmi_domain* dom);
 rwmi_status rwmi_batch_remove(rwmi_batch* b, rwmi_domain* dom);
 /* Enqueue n_steps steps of every member on the batch stream. */
 rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps);
+/* Launch options of the batch (RWMI_KEY_USE_GRAPH, _LBM_BLOCK, _WALK_BLOCK,
+ * _FLUID_FLAGS); they replace the members' own for batch steps. */
 rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value);
 rwmi_status rwmi_batch_synchronize(rwmi_batch* b);
 void rwmi_batch_destroy(rwmi_batch* b);

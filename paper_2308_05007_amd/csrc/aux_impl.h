@@ -22,18 +22,20 @@ __device__ __forceinline__ double gap_to(int periodic, int L, double a, double b
   return g > 0.0 ? g : 0.0;
 }
 
-// Block 0 writes the poses P(t), P(t+1) of step t = tstep[0], records t in
-// tstep[1] and empties the near-surface queue; every block then builds its
-// share of the coarse mask at P(t+1): bit p of a block is set when the sphere
-// (c_p(t+1), rb_p + 1/2) meets the block (extended to infinity beyond wall
-// planes).
-__global__ void k_prologue(const DomView* __restrict__ views, const int32_t* __restrict__ boff, int nd_count) {
+// Walker-side prologue of step t (parity par = t & 1): block 0 writes the
+// poses P(t), P(t+1) into pose[par]; every block builds its share of the
+// coarse mask at P(t+1) in mask[par]: bit p of a coarse block is set when the
+// sphere (c_p(t+1), rb_p + 1/2) meets the block (extended to infinity beyond
+// wall planes).
+__global__ void k_prologue(const DomView* __restrict__ views, const int32_t* __restrict__ boff, int nd_count,
+                           uint32_t kstep) {
   __shared__ double sc[kMaxParticles][3];
   __shared__ double sr[kMaxParticles];
   const int d = find_domain(boff, nd_count, blockIdx.x);
   const DomView& V = views[d];
   const int lb = blockIdx.x - boff[d];
-  const uint64_t t = V.tstep[0];
+  const uint64_t t = step_of(V, kstep);
+  const int par = (int)(t & 1ull);
   const int tid = threadIdx.x;
   if (tid < V.np) {
     const DevParticle& P = V.parts[tid];
@@ -41,8 +43,8 @@ __global__ void k_prologue(const DomView* __restrict__ views, const int32_t* __r
     particle_pose(P, t, c0, v0);
     particle_pose(P, t + 1, c1, v1);
     if (lb == 0) {
-      double* pt = V.pose + 6 * tid;
-      double* pn = V.pose + 6 * (V.np + tid);
+      double* pt = V.pose[par] + 6 * tid;
+      double* pn = V.pose[par] + 6 * (V.np + tid);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         pt[a] = c0[a];
@@ -55,7 +57,6 @@ __global__ void k_prologue(const DomView* __restrict__ views, const int32_t* __r
     for (int a = 0; a < 3; ++a) sc[tid][a] = c1[a];
     sr[tid] = P.maskr;
   }
-  if (lb == 0 && tid == 0) V.tstep[1] = t;
   __syncthreads();
   if (V.nw == 0 || V.np == 0) return;
   const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
@@ -84,7 +85,7 @@ __global__ void k_prologue(const DomView* __restrict__ views, const int32_t* __r
     const double r = sr[p];
     if (g2 <= r * r * (1.0 + 1e-9) + 1e-9) bits |= (1ull << p);
   }
-  V.mask[cb] = bits;
+  V.mask[par][cb] = bits;
 }
 
 // Seeding at t = 0: walker w tries Philox blocks (w, 0xFFFFFFFF, 16 + a, 0).
@@ -258,14 +259,15 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
   const DomView& V = views[dom];
   const int64_t base = (int64_t)blockIdx.x * kRedChunk;
   const int64_t last = (base + kRedChunk - 1 < V.N) ? base + kRedChunk - 1 : V.N - 1;
-  const bool stepped = V.tstep[0] > 0;
-  if (stepped && V.np > 0) cull_block(V, base, last, sp);
+  const uint64_t done = V.tstep[0];  // steps completed
+  const bool stepped = done > 0;
+  if (stepped && V.np > 0) cull_block(V, (uint32_t)base, (uint32_t)last, done - 1, sp);
   else if (threadIdx.x == 0) sp.cnt = 0;
   __syncthreads();
   double acc[kNodeMom];
 #pragma unroll
   for (int k = 0; k < kNodeMom; ++k) acc[k] = 0.0;
-  const U* u4 = (const U*)V.u4;
+  const U* u4 = (const U*)V.u4[stepped ? ((done - 1) & 1ull) : 0];
   const int nx = V.n[0], ny = V.n[1];
   for (int j = threadIdx.x; j < kRedChunk; j += kRedThreads) {
     const int64_t id = base + j;
@@ -320,6 +322,12 @@ __global__ void k_mom_final(const DomView* __restrict__ views, int dom, const do
   } else if (tid == kWalkMom + kNodeMom + kCounters) {
     out[tid] = __longlong_as_double((long long)V.tstep[0]);
   }
+}
+
+// End of a launch group: every domain of the launch has completed n more steps.
+__global__ void k_advance(const DomView* __restrict__ views, int nd_count, uint32_t n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nd_count) views[i].tstep[0] += n;
 }
 
 __global__ void k_normals(uint32_t k0, uint32_t k1, uint32_t t, uint32_t purpose, int64_t n, double* __restrict__ z) {

@@ -41,12 +41,45 @@ enum { KT_PRO = 0, KT_FLUID = 1, KT_WALK = 2, KT_SLOW = 3, KT_N = 4 };
 
 }  // namespace
 
+// Two streams per domain (or batch): the fluid kernels run on `a`, the
+// walker side (prologue, walkers, near-surface walkers) on `b`, so that the
+// walkers of step t overlap the fluid update of step t+1.  Step t's walkers
+// wait for F[t] (u(t) written); the fluid update of step t+2, which rewrites
+// the same velocity buffer, waits for W[t] (walkers of step t done).
+struct Streams {
+  hipStream_t b = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t F[4] = {}, W[4] = {};
+  hipError_t create() {
+    hipError_t e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    for (hipEvent_t* ev : {&fork, &join})
+      if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
+    for (int i = 0; i < 4; ++i) {
+      if ((e = hipEventCreateWithFlags(&F[i], hipEventDisableTiming)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&W[i], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  void destroy() {
+    for (hipEvent_t e : {fork, join})
+      if (e) (void)hipEventDestroy(e);
+    for (int i = 0; i < 4; ++i) {
+      if (F[i]) (void)hipEventDestroy(F[i]);
+      if (W[i]) (void)hipEventDestroy(W[i]);
+    }
+    if (b) (void)hipStreamDestroy(b);
+    b = nullptr;
+  }
+};
+
 struct rwmi_domain {
   rwmi_domain_desc desc{};
   int prec = 0;
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  Streams ss;
   Alloc al;
   std::string err = "no error";
   std::vector<HostParticle> parts;
@@ -60,6 +93,7 @@ struct rwmi_domain {
   uint64_t steps = 0;
   double ref[3] = {0, 0, 0};
   int lbm_bs = 256, walk_bs = 256;
+  int fluid_flags = rwmi::kFlagXcd;
   bool use_graph = false;
   bool timing = false;
   hipGraphExec_t gexec = nullptr;
@@ -80,6 +114,7 @@ struct rwmi_batch {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  Streams ss;
   std::string err;
   std::vector<rwmi_domain*> members;
   bool dirty = true;
@@ -98,6 +133,7 @@ struct rwmi_batch {
   hipGraphExec_t gexec = nullptr;
   uint32_t gsteps = 0;
   int lbm_bs = 256, walk_bs = 256;
+  int fluid_flags = rwmi::kFlagXcd;
 };
 
 namespace {
@@ -241,7 +277,7 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   if ((st = alloc_into(d, dp, sizeof(DevParticle) * hp.size())) != RWMI_OK) return st;
   if ((st = alloc_into(d, dc, sizeof(double) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
   if ((st = alloc_into(d, dcf, sizeof(float) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
-  if ((st = alloc_into(d, dpose, sizeof(double) * 12 * std::max(np, 1))) != RWMI_OK) return st;
+  if ((st = alloc_into(d, dpose, sizeof(double) * 24 * std::max(np, 1))) != RWMI_OK) return st;
   HIPCHK(d, hipMemcpyAsync(dp, hp.data(), sizeof(DevParticle) * hp.size(), hipMemcpyHostToDevice, d->stream));
   if (!ctrl.empty()) {
     HIPCHK(d, hipMemcpyAsync(dc, ctrl.data(), sizeof(double) * ctrl.size(), hipMemcpyHostToDevice, d->stream));
@@ -251,14 +287,16 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   d->hv.parts = dp;
   d->hv.ctrl = dc;
   d->hv.ctrl_f = dcf;
-  d->hv.pose = dpose;
+  d->hv.pose[0] = dpose;
+  d->hv.pose[1] = dpose + 12 * std::max(np, 1);
   d->hv.np = np;
   if (np > 0) {
     unsigned long long* mask;
     int32_t mb[3];
     const int64_t nmb = mask_blocks(d->desc, mb);
-    if ((st = alloc_into(d, mask, 8 * nmb)) != RWMI_OK) return st;
-    d->hv.mask = mask;
+    if ((st = alloc_into(d, mask, 16 * nmb)) != RWMI_OK) return st;
+    d->hv.mask[0] = mask;
+    d->hv.mask[1] = mask + nmb;
   }
   d->particles_uploaded = true;
   if ((st = upload_view(d)) != RWMI_OK) return st;
@@ -274,16 +312,18 @@ hipEvent_t take_event(rwmi_domain* d) {
   return d->evpool[d->evused++];
 }
 
-// One coupled step for a single domain (eager launches).
-rwmi_status enqueue_step(rwmi_domain* d, bool record) {
+// A launch group of n coupled steps for one domain: step offsets k = 0..n-1
+// relative to the domain's device step counter, fluid on the domain stream,
+// walker side on the second stream, joined at the end, then the counter is
+// advanced by n.
+rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record) {
   const DomView* v = d->dv;
   int b[KT_N];
   kernel_blocks(d, b);
-  const rwmi::Work wpro{v, d->dboff + 0, 1, b[KT_PRO]};
-  const rwmi::Work wflu{v, d->dboff + 2, 1, b[KT_FLUID]};
-  const rwmi::Work wwal{v, d->dboff + 4, 1, b[KT_WALK]};
-  const rwmi::Work wslo{v, d->dboff + 6, 1, b[KT_SLOW]};
-  auto timed = [&](int kt, auto&& launch) -> rwmi_status {
+  const bool walkers = d->hv.nw > 0;
+  const bool parts = d->hv.np > 0;
+  hipStream_t A = d->stream, Bs = d->ss.b;
+  auto timed = [&](int kt, hipStream_t s, auto&& launch) -> rwmi_status {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     size_t i0 = 0;
     if (record) {
@@ -291,26 +331,44 @@ rwmi_status enqueue_step(rwmi_domain* d, bool record) {
       e0 = take_event(d);
       e1 = take_event(d);
       if (!e0 || !e1) return fail(d, RWMI_EDEVICE, "hipEventCreate failed");
-      HIPCHK(d, hipEventRecord(e0, d->stream));
+      HIPCHK(d, hipEventRecord(e0, s));
     }
     HIPCHK(d, launch());
     if (record) {
-      HIPCHK(d, hipEventRecord(e1, d->stream));
+      HIPCHK(d, hipEventRecord(e1, s));
       d->evrec.push_back({kt, i0});
     }
     return RWMI_OK;
   };
   rwmi_status st;
-  if ((st = timed(KT_PRO, [&] { return rwmi::launch_prologue(wpro, d->stream); })) != RWMI_OK) return st;
-  if ((st = timed(KT_FLUID, [&] { return rwmi::launch_fluid(d->prec, d->lbm_bs, wflu, d->stream); })) != RWMI_OK)
-    return st;
-  if (d->hv.nw > 0) {
-    if ((st = timed(KT_WALK, [&] { return rwmi::launch_walk(d->prec, d->walk_bs, wwal, d->stream); })) != RWMI_OK)
-      return st;
-    if (d->hv.np > 0 &&
-        (st = timed(KT_SLOW, [&] { return rwmi::launch_walk_slow(d->prec, d->walk_bs, wslo, d->stream); })) != RWMI_OK)
-      return st;
+  if (walkers) {
+    HIPCHK(d, hipEventRecord(d->ss.fork, A));
+    HIPCHK(d, hipStreamWaitEvent(Bs, d->ss.fork, 0));
   }
+  for (uint32_t k = 0; k < n; ++k) {
+    const rwmi::Work wpro{v, d->dboff + 0, 1, b[KT_PRO], 0, k};
+    const rwmi::Work wflu{v, d->dboff + 2, 1, b[KT_FLUID], d->fluid_flags, k};
+    const rwmi::Work wwal{v, d->dboff + 4, 1, b[KT_WALK], 0, k};
+    const rwmi::Work wslo{v, d->dboff + 6, 1, b[KT_SLOW], 0, k};
+    if (walkers && k >= 2) HIPCHK(d, hipStreamWaitEvent(A, d->ss.W[(k - 2) & 3], 0));
+    if ((st = timed(KT_FLUID, A, [&] { return rwmi::launch_fluid(d->prec, d->lbm_bs, wflu, A); })) != RWMI_OK)
+      return st;
+    if (!walkers) continue;
+    HIPCHK(d, hipEventRecord(d->ss.F[k & 3], A));
+    if (parts && (st = timed(KT_PRO, Bs, [&] { return rwmi::launch_prologue(wpro, Bs); })) != RWMI_OK) return st;
+    HIPCHK(d, hipStreamWaitEvent(Bs, d->ss.F[k & 3], 0));
+    if ((st = timed(KT_WALK, Bs, [&] { return rwmi::launch_walk(d->prec, d->walk_bs, wwal, Bs); })) != RWMI_OK)
+      return st;
+    if (parts &&
+        (st = timed(KT_SLOW, Bs, [&] { return rwmi::launch_walk_slow(d->prec, d->walk_bs, wslo, Bs); })) != RWMI_OK)
+      return st;
+    HIPCHK(d, hipEventRecord(d->ss.W[k & 3], Bs));
+  }
+  if (walkers) {
+    HIPCHK(d, hipEventRecord(d->ss.join, Bs));
+    HIPCHK(d, hipStreamWaitEvent(A, d->ss.join, 0));
+  }
+  HIPCHK(d, rwmi::launch_advance(v, 1, n, A));
   return RWMI_OK;
 }
 
@@ -328,9 +386,9 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   int32_t mb[3];
   const uint64_t nmb = (uint64_t)mask_blocks(*s, mb);
   uint64_t b = 0;
-  b += 2 * 19 * N * elem_size(p) + 4 * N * u_size(p);
+  b += 2 * 19 * N * elem_size(p) + 8 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
-  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 96 * n_particles + (n_particles ? 8 * nmb : 0);
+  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 192 * n_particles + (n_particles ? 16 * nmb : 0);
   // walkers: cell, offsets, images, queue (id + step), moment partials
   b += n_walkers * (4 + 3 * off_size(p) + 12 + 4 + 3 * off_size(p));
   b += 4 * N;  // occupancy
@@ -420,11 +478,17 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
 
   rwmi_status st = RWMI_OK;
   void *fA, *fB, *u4;
+  if (d->ss.create() != hipSuccess) {
+    d->ss.destroy();
+    if (d->own_stream) (void)hipStreamDestroy(d->stream);
+    delete d;
+    return fail(nullptr, RWMI_EDEVICE, "stream/event creation failed");
+  }
   uint64_t* tstep;
   unsigned long long* cnt;
   if ((st = alloc_into(d, fA, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
       (st = alloc_into(d, fB, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
-      (st = alloc_into(d, u4, 4 * (size_t)N * u_size(d->prec))) != RWMI_OK ||
+      (st = alloc_into(d, u4, 8 * (size_t)N * u_size(d->prec))) != RWMI_OK ||
       (st = alloc_into(d, tstep, 16)) != RWMI_OK || (st = alloc_into(d, cnt, 8 * rwmi::kCounters)) != RWMI_OK ||
       (st = alloc_into(d, d->dv, sizeof(DomView))) != RWMI_OK ||
       (st = alloc_into(d, d->dboff, sizeof(int32_t) * 2 * KT_N)) != RWMI_OK) {
@@ -433,7 +497,8 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
   }
   v.fA = fA;
   v.fB = fB;
-  v.u4 = u4;
+  v.u4[0] = u4;
+  v.u4[1] = (char*)u4 + 4 * (size_t)N * u_size(d->prec);
   v.tstep = tstep;
   v.counters = cnt;
   uint64_t zeros[rwmi::kCounters] = {0};
@@ -454,6 +519,8 @@ void rwmi_destroy_domain(rwmi_domain* d) {
   (void)hipSetDevice(d->device);
   if (d->stream) (void)hipStreamSynchronize(d->stream);
   drop_graph(d);
+  if (d->ss.b) (void)hipStreamSynchronize(d->ss.b);
+  d->ss.destroy();
   for (hipEvent_t e : d->evpool) (void)hipEventDestroy(e);
   for (void* p : d->owned) dev_free(d->al, p);
   if (d->own_stream) (void)hipStreamDestroy(d->stream);
@@ -593,13 +660,11 @@ rwmi_status rwmi_step(rwmi_domain* d, uint32_t n_steps) {
       drop_graph(d);
       hipGraph_t g;
       HIPCHK(d, hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal));
-      for (uint32_t i = 0; i < k; ++i) {
-        if ((st = enqueue_step(d, false)) != RWMI_OK) {
-          hipGraph_t junk;
-          (void)hipStreamEndCapture(d->stream, &junk);
-          if (junk) (void)hipGraphDestroy(junk);
-          return st;
-        }
+      if ((st = enqueue_group(d, k, false)) != RWMI_OK) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(d->stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        return st;
       }
       HIPCHK(d, hipStreamEndCapture(d->stream, &g));
       hipError_t e = hipGraphInstantiate(&d->gexec, g, nullptr, nullptr, 0);
@@ -613,9 +678,9 @@ rwmi_status rwmi_step(rwmi_domain* d, uint32_t n_steps) {
       d->steps += d->gsteps;
     }
   }
-  for (; left > 0; --left) {
-    if ((st = enqueue_step(d, d->timing)) != RWMI_OK) return st;
-    d->steps++;
+  if (left > 0) {
+    if ((st = enqueue_group(d, left, d->timing)) != RWMI_OK) return st;
+    d->steps += left;
   }
   return RWMI_OK;
 }
@@ -641,7 +706,8 @@ rwmi_status rwmi_read_velocity(rwmi_domain* d, double* u, double* rho) {
   const int64_t N = d->hv.N;
   const size_t us = u_size(d->prec);
   std::vector<unsigned char> h(4 * N * us);
-  HIPCHK(d, hipMemcpyAsync(h.data(), d->hv.u4, h.size(), hipMemcpyDeviceToHost, d->stream));
+  const void* ub = d->hv.u4[d->steps > 0 ? ((d->steps - 1) & 1) : 0];
+  HIPCHK(d, hipMemcpyAsync(h.data(), ub, h.size(), hipMemcpyDeviceToHost, d->stream));
   HIPCHK(d, hipStreamSynchronize(d->stream));
   for (int64_t i = 0; i < N; ++i) {
     for (int c = 0; c < 4; ++c) {
@@ -787,6 +853,11 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
     case RWMI_KEY_TIMING:
       d->timing = value != 0;
       return RWMI_OK;
+    case RWMI_KEY_FLUID_FLAGS:
+      if (value < 0 || value > 3) return fail(d, RWMI_EINVAL, "fluid flags must be in 0..3");
+      d->fluid_flags = (int)value;
+      drop_graph(d);
+      return RWMI_OK;
     default:
       return fail(d, RWMI_EINVAL, "unknown key %d", key);
   }
@@ -839,6 +910,11 @@ rwmi_status rwmi_batch_create(int32_t device, void* stream, rwmi_batch** out) {
   if (hipSetDevice(device) != hipSuccess) return bfail(nullptr, RWMI_EDEVICE, "hipSetDevice failed");
   rwmi_batch* b = new rwmi_batch();
   b->device = device;
+  if (b->ss.create() != hipSuccess) {
+    b->ss.destroy();
+    delete b;
+    return bfail(nullptr, RWMI_EDEVICE, "stream/event creation failed");
+  }
   if (stream) {
     b->stream = (hipStream_t)stream;
   } else {
@@ -943,21 +1019,47 @@ static rwmi_status batch_rebuild(rwmi_batch* b) {
   return RWMI_OK;
 }
 
-static rwmi_status batch_enqueue_step(rwmi_batch* b) {
-  for (auto& g : b->groups) {
-    const int nd = (int)g.doms.size();
-    const rwmi::Work wpro{g.views, g.boff + 0 * (nd + 1), nd, g.blocks[KT_PRO]};
-    const rwmi::Work wflu{g.views, g.boff + 1 * (nd + 1), nd, g.blocks[KT_FLUID]};
-    const rwmi::Work wwal{g.views, g.boff + 2 * (nd + 1), nd, g.blocks[KT_WALK]};
-    const rwmi::Work wslo{g.views, g.boff + 3 * (nd + 1), nd, g.blocks[KT_SLOW]};
-    if (rwmi::launch_prologue(wpro, b->stream) != hipSuccess ||
-        rwmi::launch_fluid(g.prec, b->lbm_bs, wflu, b->stream) != hipSuccess)
-      return bfail(b, RWMI_EDEVICE, "batch launch failed");
-    if (g.blocks[KT_WALK] > 0 && rwmi::launch_walk(g.prec, b->walk_bs, wwal, b->stream) != hipSuccess)
-      return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
-    if (g.blocks[KT_SLOW] > 0 && rwmi::launch_walk_slow(g.prec, b->walk_bs, wslo, b->stream) != hipSuccess)
-      return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
+// A launch group of n steps for every member: one launch per kernel per step
+// and precision group, the same two-stream schedule as a single domain.
+static rwmi_status batch_enqueue_group(rwmi_batch* b, uint32_t n) {
+  hipStream_t A = b->stream, Bs = b->ss.b;
+  bool walkers = false;
+  for (auto& g : b->groups) walkers |= g.blocks[KT_WALK] > 0;
+  auto ck = [&](hipError_t e) -> bool { return e == hipSuccess; };
+  if (walkers && (!ck(hipEventRecord(b->ss.fork, A)) || !ck(hipStreamWaitEvent(Bs, b->ss.fork, 0))))
+    return bfail(b, RWMI_EDEVICE, "batch fork failed");
+  for (uint32_t k = 0; k < n; ++k) {
+    if (walkers && k >= 2 && !ck(hipStreamWaitEvent(A, b->ss.W[(k - 2) & 3], 0)))
+      return bfail(b, RWMI_EDEVICE, "batch wait failed");
+    for (auto& g : b->groups) {
+      const int nd = (int)g.doms.size();
+      const rwmi::Work wflu{g.views, g.boff + 1 * (nd + 1), nd, g.blocks[KT_FLUID], b->fluid_flags, k};
+      if (!ck(rwmi::launch_fluid(g.prec, b->lbm_bs, wflu, A))) return bfail(b, RWMI_EDEVICE, "batch launch failed");
+    }
+    if (!walkers) continue;
+    if (!ck(hipEventRecord(b->ss.F[k & 3], A))) return bfail(b, RWMI_EDEVICE, "batch record failed");
+    for (auto& g : b->groups) {
+      const int nd = (int)g.doms.size();
+      const rwmi::Work wpro{g.views, g.boff + 0 * (nd + 1), nd, g.blocks[KT_PRO], 0, k};
+      if (g.blocks[KT_SLOW] > 0 && !ck(rwmi::launch_prologue(wpro, Bs)))
+        return bfail(b, RWMI_EDEVICE, "batch prologue failed");
+    }
+    if (!ck(hipStreamWaitEvent(Bs, b->ss.F[k & 3], 0))) return bfail(b, RWMI_EDEVICE, "batch wait failed");
+    for (auto& g : b->groups) {
+      const int nd = (int)g.doms.size();
+      const rwmi::Work wwal{g.views, g.boff + 2 * (nd + 1), nd, g.blocks[KT_WALK], 0, k};
+      const rwmi::Work wslo{g.views, g.boff + 3 * (nd + 1), nd, g.blocks[KT_SLOW], 0, k};
+      if (g.blocks[KT_WALK] > 0 && !ck(rwmi::launch_walk(g.prec, b->walk_bs, wwal, Bs)))
+        return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
+      if (g.blocks[KT_SLOW] > 0 && !ck(rwmi::launch_walk_slow(g.prec, b->walk_bs, wslo, Bs)))
+        return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
+    }
+    if (!ck(hipEventRecord(b->ss.W[k & 3], Bs))) return bfail(b, RWMI_EDEVICE, "batch record failed");
   }
+  if (walkers && (!ck(hipEventRecord(b->ss.join, Bs)) || !ck(hipStreamWaitEvent(A, b->ss.join, 0))))
+    return bfail(b, RWMI_EDEVICE, "batch join failed");
+  for (auto& g : b->groups)
+    if (!ck(rwmi::launch_advance(g.views, (int)g.doms.size(), n, A))) return bfail(b, RWMI_EDEVICE, "batch advance failed");
   return RWMI_OK;
 }
 
@@ -980,13 +1082,11 @@ rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps) {
       hipGraph_t g;
       if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, RWMI_EDEVICE, "capture failed");
-      for (uint32_t i = 0; i < k; ++i) {
-        if (batch_enqueue_step(b) != RWMI_OK) {
-          hipGraph_t junk;
-          (void)hipStreamEndCapture(b->stream, &junk);
-          if (junk) (void)hipGraphDestroy(junk);
-          return RWMI_EDEVICE;
-        }
+      if (batch_enqueue_group(b, k) != RWMI_OK) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(b->stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        return RWMI_EDEVICE;
       }
       if (hipStreamEndCapture(b->stream, &g) != hipSuccess) return bfail(b, RWMI_EDEVICE, "end capture failed");
       hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
@@ -1000,10 +1100,10 @@ rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps) {
       for (rwmi_domain* d : b->members) d->steps += b->gsteps;
     }
   }
-  for (; left > 0; --left) {
-    rwmi_status st = batch_enqueue_step(b);
+  if (left > 0) {
+    rwmi_status st = batch_enqueue_group(b, left);
     if (st != RWMI_OK) return st;
-    for (rwmi_domain* d : b->members) d->steps++;
+    for (rwmi_domain* d : b->members) d->steps += left;
   }
   for (rwmi_domain* d : b->members) d->stepped = true;
   // member reads run on the members' streams: order them after this work
@@ -1034,6 +1134,11 @@ rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value) {
       b->walk_bs = (int)value;
       b->dirty = true;
       return RWMI_OK;
+    case RWMI_KEY_FLUID_FLAGS:
+      if (value < 0 || value > 3) return bfail(b, RWMI_EINVAL, "fluid flags must be in 0..3");
+      b->fluid_flags = (int)value;
+      batch_drop_graph(b);
+      return RWMI_OK;
     default:
       return bfail(b, RWMI_EINVAL, "unknown batch key");
   }
@@ -1053,6 +1158,8 @@ void rwmi_batch_destroy(rwmi_batch* b) {
   for (rwmi_domain* d : b->members) d->batch = nullptr;
   batch_drop_graph(b);
   batch_free_groups(b);
+  if (b->ss.b) (void)hipStreamSynchronize(b->ss.b);
+  b->ss.destroy();
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }

@@ -89,13 +89,13 @@ struct DomView {
   float wu_f[3][2][3];
   void* fA;                       // distributions, parity 0 source
   void* fB;                       // distributions, parity 1 source
-  void* u4;                       // (ux, uy, uz, rho) per node
+  void* u4[2];                    // (ux, uy, uz, rho) per node, written by step t into [t & 1]
   const DevParticle* parts;
   const double* ctrl;             // 4 per control point: bx, by, bz, k
   const float* ctrl_f;            // the same in float (low-precision modes)
-  double* pose;                   // [2][np][6]: (c, v) at t and t+1
-  uint64_t* tstep;                // [0] steps started, [1] step being computed
-  unsigned long long* mask;       // coarse cull mask, one bit per particle
+  double* pose[2];                // per step parity: [2][np][6] (c, v) at t and t+1
+  uint64_t* tstep;                // [0] steps completed before the current launch group
+  unsigned long long* mask[2];    // per step parity: coarse cull mask at P(t+1)
   int32_t* wcell;                 // walker cell index
   void* woff;                     // walker offsets SoA [3][nw] (double or float)
   int32_t* wimg;                  // walker image counts SoA [3][nw]
@@ -113,6 +113,19 @@ template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
+
+// Block order for an 8-XCD part: workgroup i runs on XCD i mod 8, so give
+// XCD x the contiguous range of logical blocks [start(x), start(x+1)) with
+// start(x) = x floor(nb/8) + min(x, nb mod 8).  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_swizzle(int i, int nb) {
+  const int x = i & 7, local = i >> 3;
+  const int per = nb >> 3, extra = nb & 7;
+  return x * per + (x < extra ? x : extra) + local;
+}
+
+// Step t of a launch: the domain's step counter at the start of the launch
+// group plus the launch's offset k within the group.
+__device__ __forceinline__ uint64_t step_of(const DomView& V, uint32_t k) { return gp(V.tstep)[0] + k; }
 
 // Work map of a multi-domain launch: block b of the grid belongs to domain d
 // with boff[d] <= b < boff[d + 1].
@@ -255,6 +268,11 @@ __device__ __forceinline__ void gauss3_fast(const U4& r, float& z0, float& z1, f
 template <typename R> __device__ __forceinline__ R qdiv(R a, R b);
 template <> __device__ __forceinline__ double qdiv<double>(double a, double b) { return a / b; }
 template <> __device__ __forceinline__ float qdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// sqrt: IEEE in double, hardware square root in float.
+template <typename R> __device__ __forceinline__ R qsqrt(R a);
+template <> __device__ __forceinline__ double qsqrt<double>(double a) { return sqrt(a); }
+template <> __device__ __forceinline__ float qsqrt<float>(float a) { return __builtin_amdgcn_sqrtf(a); }
 
 // ------------------------------------------------------------------ motion
 // Pose (centre, velocity) of particle p at integer step t.

@@ -6,30 +6,30 @@
 namespace rwmi {
 
 hipError_t launch_prologue(const Work& w, hipStream_t s) {
-  k_prologue<<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd);
+  k_prologue<<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k);
   return hipGetLastError();
 }
 
 hipError_t launch_fluid_p64(int bs, const Work& w, hipStream_t s) {
   switch (bs) {
-    case 128: k_fluid<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd); break;
-    case 512: k_fluid<P64, 512><<<w.blocks, 512, 0, s>>>(w.views, w.boff, w.nd); break;
-    default: k_fluid<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd); break;
+    case 128: k_fluid<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
+    case 512: k_fluid<P64, 512><<<w.blocks, 512, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
+    default: k_fluid<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_walk_p64(int bs, const Work& w, hipStream_t s) {
   switch (bs) {
-    case 128: k_walk<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd); break;
-    default: k_walk<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd); break;
+    case 128: k_walk<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.k); break;
+    default: k_walk<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_walk_slow_p64(int bs, const Work& w, hipStream_t s) {
-  if (bs == 128) k_walk_slow<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd);
-  else k_walk_slow<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd);
+  if (bs == 128) k_walk_slow<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.k);
+  else k_walk_slow<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k);
   return hipGetLastError();
 }
 
@@ -83,6 +83,11 @@ hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_
   if (prec == P64) k_mom_nodes<double><<<(unsigned)nbn, kRedThreads, 0, s>>>(v, dom, pn);
   else k_mom_nodes<float><<<(unsigned)nbn, kRedThreads, 0, s>>>(v, dom, pn);
   k_mom_final<<<1, 64, 0, s>>>(v, dom, pw, nbw, pn, nbn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(const DomView* views, int nd, uint32_t n, hipStream_t s) {
+  k_advance<<<(nd + 63) / 64, 64, 0, s>>>(views, nd, n);
   return hipGetLastError();
 }
 

@@ -9,9 +9,9 @@ namespace rwmi {
 template <int P>
 static void fluid_bs(int bs, const Work& w, hipStream_t s) {
   switch (bs) {
-    case 128: k_fluid<P, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd); break;
-    case 512: k_fluid<P, 512><<<w.blocks, 512, 0, s>>>(w.views, w.boff, w.nd); break;
-    default: k_fluid<P, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd); break;
+    case 128: k_fluid<P, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
+    case 512: k_fluid<P, 512><<<w.blocks, 512, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
+    default: k_fluid<P, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
   }
 }
 
@@ -25,15 +25,15 @@ hipError_t launch_fluid_lowp(int prec, int bs, const Work& w, hipStream_t s) {
 hipError_t launch_walk_lowp(int bs, const Work& w, hipStream_t s) {
   // every low-precision mode keeps walker offsets and the velocity in float
   switch (bs) {
-    case 128: k_walk<P32, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd); break;
-    default: k_walk<P32, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd); break;
+    case 128: k_walk<P32, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.k); break;
+    default: k_walk<P32, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_walk_slow_lowp(int bs, const Work& w, hipStream_t s) {
-  if (bs == 128) k_walk_slow<P32, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd);
-  else k_walk_slow<P32, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd);
+  if (bs == 128) k_walk_slow<P32, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.k);
+  else k_walk_slow<P32, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k);
   return hipGetLastError();
 }
 

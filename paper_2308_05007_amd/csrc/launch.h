@@ -13,7 +13,11 @@ struct Work {
   const int32_t* boff;
   int nd;
   int blocks;
+  int flags;     // fluid kernel: kFlagXcd | kFlagNontemporal
+  uint32_t k;    // step offset within the launch group
 };
+constexpr int kFlagXcd = 1;          // XCD-contiguous block order
+constexpr int kFlagNontemporal = 2;  // non-temporal stores of f* and (u, rho)
 
 hipError_t launch_prologue(const Work& w, hipStream_t s);
 hipError_t launch_fluid_p64(int bs, const Work& w, hipStream_t s);
@@ -53,6 +57,7 @@ hipError_t launch_occupancy(const DomView* v, int dom, uint32_t* occ, int64_t N,
 // partial buffers: walkers ceil(nw/4096)*6, nodes ceil(N/4096)*12 doubles
 hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_t nw, const double* ref,
                           double* pw, double* pn, double* out, hipStream_t s);
+hipError_t launch_advance(const DomView* views, int nd, uint32_t n, hipStream_t s);
 hipError_t launch_normals(uint64_t seed, uint32_t t, uint32_t purpose, int64_t n, double* z, hipStream_t s);
 
 }  // namespace rwmi

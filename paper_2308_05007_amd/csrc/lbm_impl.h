@@ -47,9 +47,10 @@ __device__ __forceinline__ double interval_gap(int periodic, int L, int lo, int 
   return g > 0.0 ? g : 0.0;
 }
 
-// Cull the particles for the node range [n0, n1] of a block and stage their
-// poses and control points in LDS.  Called by every thread of the block.
-__device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32_t n1, BlockParticles& sp) {
+// Cull the particles at pose P(t) for the node range [n0, n1] of a block and
+// stage their poses and control points in LDS.  Called by every thread of
+// the block; wave 0 computes the poses.
+__device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32_t n1, uint64_t t, BlockParticles& sp) {
   const int nx = V.n[0], ny = V.n[1];
   int lo[3], hi[3];
   {
@@ -62,26 +63,31 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
     else if (z0 == z1) { lo[0] = 0; hi[0] = nx - 1; lo[1] = y0; hi[1] = y1; }
     else { lo[0] = 0; hi[0] = nx - 1; lo[1] = 0; hi[1] = ny - 1; }
   }
-  const auto pose = gp((const double*)V.pose);  // P(t) at index 0
   const auto parts = gp(V.parts);
   const int tid = threadIdx.x;
   if (tid < 64) {
     bool keep = false;
+    double pc[3] = {0, 0, 0}, pv[3] = {0, 0, 0};
     if (tid < V.np) {
-      const auto pc = pose + 6 * tid;
+      const DevParticle& P = V.parts[tid];
+      particle_pose(P, t, pc, pv);
       double g2 = 0.0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const double g = interval_gap(!V.bc[a], V.n[a], lo[a], hi[a], pc[a]);
         g2 += g * g;
       }
-      const double cs = parts[tid].cutsq;
-      keep = g2 <= cs * (1.0 + 1e-9) + 1e-9;
+      keep = g2 <= P.cutsq * (1.0 + 1e-9) + 1e-9;
     }
     const unsigned long long m = __ballot(keep);
     if (keep) {
       const int r = __popcll(m & ((1ull << tid) - 1ull));
       sp.id[r] = tid;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sp.c[r][a] = pc[a];
+        sp.v[r][a] = pv[a];
+      }
     }
     if (tid == 0) sp.cnt = __popcll(m);
   }
@@ -101,16 +107,7 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
       }
     }
   }
-  if (tid < cnt) {
-    const int p = sp.id[tid];
-    const auto pc = pose + 6 * p;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      sp.c[tid][a] = pc[a];
-      sp.v[tid][a] = pc[3 + a];
-    }
-    sp.cutsq[tid] = parts[p].cutsq;
-  }
+  if (tid < cnt) sp.cutsq[tid] = parts[sp.id[tid]].cutsq;
   __syncthreads();
   for (int k = 0; k < cnt; ++k) {
     const int off = sp.ctrl_off[k];
@@ -138,17 +135,17 @@ __device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles& sp
     if (M == (R)INFINITY) return (R)1;
     metaball_grad<R>(ctrl, nc, dx, dy, dz, g);
   } else {
-    const auto ctrl = gp(V.ctrl) + 4 * gp(V.parts)[sp.id[k]].ctrl0;
+    const auto ctrl = gp(ctrl_of<R>(V)) + 4 * gp(V.parts)[sp.id[k]].ctrl0;
     M = metaball_value<R>(ctrl, nc, dx, dy, dz);
     if (M == (R)INFINITY) return (R)1;
     metaball_grad<R>(ctrl, nc, dx, dy, dz, g);
   }
-  const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+  const R gn = qsqrt<R>((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
   R e;
   if (gn == (R)0) {
     e = M >= (R)1 ? (R)1 : (R)0;
   } else {
-    const R dist = (((R)2 * M) * (sqrt(M) - (R)1)) / gn;
+    const R dist = qdiv<R>(((R)2 * M) * (qsqrt<R>(M) - (R)1), gn);
     e = dist == dist ? (R)0.5 + dist : (M >= (R)1 ? (R)1 : (R)0);
   }
   if (e < (R)0) e = (R)0;
@@ -202,24 +199,24 @@ __device__ __forceinline__ void unroll(F&& f) {
 
 template <int P, int BS>
 __global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
-                                              int nd_count) {
+                                              int nd_count, int flags, uint32_t k) {
   using S = typename Store<P>::S;
   using R = typename Store<P>::C;
   constexpr bool exact = (P == P64);
   __shared__ BlockParticles sp;
-  const int d = find_domain(boff, nd_count, blockIdx.x);
+  const int gb = (flags & 1) ? xcd_swizzle((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const bool nt = (flags & 2) != 0;
+  const int d = find_domain(boff, nd_count, gb);
   const DomView& V = views[d];
-  const uint32_t lb = (uint32_t)((int)blockIdx.x - boff[d]);
-  const auto tstep = gp(V.tstep);
-  const uint64_t t = tstep[1];
-  if (lb == 0 && threadIdx.x == 0) tstep[0] = t + 1;
+  const uint32_t lb = (uint32_t)(gb - boff[d]);
+  const uint64_t t = step_of(V, k);
   using SR = typename Raw<S>::T;
   const auto src = gp((const SR*)((t & 1ull) ? V.fB : V.fA));
   const auto dst = gp((SR*)((t & 1ull) ? V.fA : V.fB));
   const uint32_t N = (uint32_t)V.N;
   const uint32_t n0 = lb * BS;
   const uint32_t n1 = (n0 + BS - 1 < N) ? n0 + BS - 1 : N - 1;
-  if (V.np > 0) cull_block(V, n0, n1, sp);
+  if (V.np > 0) cull_block(V, n0, n1, t, sp);
   else if (threadIdx.x == 0) sp.cnt = 0;
   __syncthreads();
 
@@ -370,8 +367,11 @@ __global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views,
   };
   auto put = [&](auto jc, R v) {
     constexpr int j = decltype(jc)::value;
-    if constexpr (exact) dst[(size_t)j * N + id] = v;
-    else dst[(size_t)j * N + id] = raw_out<S>(v);
+    SR w;
+    if constexpr (exact) w = v;
+    else w = raw_out<S>(v);
+    if (nt) __builtin_nontemporal_store(w, &dst[(size_t)j * N + id]);
+    else dst[(size_t)j * N + id] = w;
   };
 
   // rest population
@@ -413,18 +413,20 @@ __global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views,
     put(ic, vi);
     put(oc, vo);
   });
-  if constexpr (exact) {
-    const auto u = gp((double*)V.u4) + 4 * (size_t)id;
-    u[0] = ux;
-    u[1] = uy;
-    u[2] = uz;
-    u[3] = rho;
-  } else {
-    const auto u = gp((float*)V.u4) + 4 * (size_t)id;
-    u[0] = ux;
-    u[1] = uy;
-    u[2] = uz;
-    u[3] = rho;
+  {
+    using U = typename Store<P>::U;
+    const auto u = gp((U*)V.u4[t & 1ull]) + 4 * (size_t)id;
+    if (nt) {
+      __builtin_nontemporal_store((U)ux, &u[0]);
+      __builtin_nontemporal_store((U)uy, &u[1]);
+      __builtin_nontemporal_store((U)uz, &u[2]);
+      __builtin_nontemporal_store((U)rho, &u[3]);
+    } else {
+      u[0] = ux;
+      u[1] = uy;
+      u[2] = uz;
+      u[3] = rho;
+    }
   }
 }
 
@@ -456,18 +458,20 @@ __global__ void k_init(const DomView* __restrict__ views, int dom, double u0x, d
     fA[(int64_t)j * V.N + id] = from_d<S>(fe);
     fB[(int64_t)j * V.N + id] = from_d<S>(fe);
   }
-  U* u4 = (U*)V.u4;
-  if (wslot >= 0) {
-    const int a = wslot >> 1, side = wslot & 1;
-    u4[4 * id + 0] = (U)V.wu[a][side][0];
-    u4[4 * id + 1] = (U)V.wu[a][side][1];
-    u4[4 * id + 2] = (U)V.wu[a][side][2];
-  } else {
-    u4[4 * id + 0] = (U)u0x;
-    u4[4 * id + 1] = (U)u0y;
-    u4[4 * id + 2] = (U)u0z;
+  for (int b = 0; b < 2; ++b) {  // wall nodes keep these values in both buffers
+    U* u4 = (U*)V.u4[b];
+    if (wslot >= 0) {
+      const int a = wslot >> 1, side = wslot & 1;
+      u4[4 * id + 0] = (U)V.wu[a][side][0];
+      u4[4 * id + 1] = (U)V.wu[a][side][1];
+      u4[4 * id + 2] = (U)V.wu[a][side][2];
+    } else {
+      u4[4 * id + 0] = (U)u0x;
+      u4[4 * id + 1] = (U)u0y;
+      u4[4 * id + 2] = (U)u0z;
+    }
+    u4[4 * id + 3] = (U)rho0;
   }
-  u4[4 * id + 3] = (U)rho0;
 }
 
 // Pre-collision f(x, t) for diagnostics, as double SoA [19][nodes].
@@ -477,7 +481,7 @@ __global__ void k_read_f(const DomView* __restrict__ views, int dom, double* __r
   const DomView& V = views[dom];
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= V.N) return;
-  const uint64_t t = V.tstep[0];
+  const uint64_t t = V.tstep[0];  // steps completed
   const S* src = (const S*)((t & 1ull) ? V.fB : V.fA);
   const int nx = V.n[0], ny = V.n[1], nz = V.n[2];
   const int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};

@@ -52,13 +52,13 @@ __device__ __forceinline__ int64_t mask_index(const DomView& V, const int c[3], 
 }
 
 // Particle pose at t+1 from the pose table.
-__device__ __forceinline__ gconst<double> pose_next(const DomView& V, int p) {
-  return gp((const double*)V.pose) + 6 * (V.np + p);
+__device__ __forceinline__ gconst<double> pose_next(const DomView& V, int par, int p) {
+  return gp((const double*)V.pose[par]) + 6 * (V.np + p);
 }
 
 template <typename R>
-__device__ __forceinline__ R particle_M_at(const DomView& V, int p, const int c[3], const R x[3]) {
-  const auto pc = pose_next(V, p);
+__device__ __forceinline__ R particle_M_at(const DomView& V, int par, int p, const int c[3], const R x[3]) {
+  const auto pc = pose_next(V, par, p);
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
@@ -67,8 +67,8 @@ __device__ __forceinline__ R particle_M_at(const DomView& V, int p, const int c[
 }
 
 template <typename R>
-__device__ __forceinline__ void particle_grad_at(const DomView& V, int p, const int c[3], const R x[3], R g[3]) {
-  const auto pc = pose_next(V, p);
+__device__ __forceinline__ void particle_grad_at(const DomView& V, int par, int p, const int c[3], const R x[3], R g[3]) {
+  const auto pc = pose_next(V, par, p);
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
@@ -81,8 +81,8 @@ __device__ __forceinline__ void particle_grad_at(const DomView& V, int p, const 
 // there (bounding-radius lemma), so the result is that of testing all.
 // Is (c + x) within the sphere (c_p(t+1), rb_p + 1/2) of particle p?
 template <typename R>
-__device__ __forceinline__ bool in_sphere(const DomView& V, int p, const int c[3], const R x[3]) {
-  const auto pc = pose_next(V, p);
+__device__ __forceinline__ bool in_sphere(const DomView& V, int par, int p, const int c[3], const R x[3]) {
+  const auto pc = pose_next(V, par, p);
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
@@ -91,19 +91,19 @@ __device__ __forceinline__ bool in_sphere(const DomView& V, int p, const int c[3
 }
 
 template <typename R>
-__device__ __forceinline__ unsigned long long mask_at(const DomView& V, const int c[3], const R x[3]) {
-  return gp((const unsigned long long*)V.mask)[mask_index<R>(V, c, x)];
+__device__ __forceinline__ unsigned long long mask_at(const DomView& V, int par, const int c[3], const R x[3]) {
+  return gp((const unsigned long long*)V.mask[par])[mask_index<R>(V, c, x)];
 }
 
 template <typename R>
-__device__ __forceinline__ int inside_any(const DomView& V, const int c[3], const R x[3]) {
+__device__ __forceinline__ int inside_any(const DomView& V, int par, const int c[3], const R x[3]) {
   // only the particles whose mask bit is set for the point's coarse block can
   // contain it; visit them in ascending index order
-  unsigned long long bits = mask_at<R>(V, c, x);
+  unsigned long long bits = mask_at<R>(V, par, c, x);
   while (bits) {
     const int p = __ffsll((long long)bits) - 1;
     bits &= bits - 1ull;
-    const auto pc = pose_next(V, p);
+    const auto pc = pose_next(V, par, p);
     const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
     const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
     const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
@@ -119,12 +119,12 @@ __device__ __forceinline__ int inside_any(const DomView& V, const int c[3], cons
 // Algorithm 1 on x(s) = a0 + s dir between s_out (M < 1) and s_in (M >= 1):
 // midpoint in s, converged when |M - 1| < 1e-3, at most imax evaluations.
 template <typename R>
-__device__ __forceinline__ bool bisect(const DomView& V, int p, const int c[3], const R a0[3], const R dir[3],
+__device__ __forceinline__ bool bisect(const DomView& V, int par, int p, const int c[3], const R a0[3], const R dir[3],
                                        R s_out, R s_in, int imax, R& s_res) {
   for (int it = 1; it <= imax; ++it) {
     const R sm = (R)0.5 * (s_out + s_in);
     const R x[3] = {a0[0] + sm * dir[0], a0[1] + sm * dir[1], a0[2] + sm * dir[2]};
-    const R m = particle_M_at<R>(V, p, c, x);
+    const R m = particle_M_at<R>(V, par, p, c, x);
     if (fabs(m - (R)1) < (R)1e-3) {
       s_res = sm;
       return true;
@@ -206,7 +206,7 @@ __device__ __forceinline__ void store_walker(const DomView& V, int64_t w, int c[
 
 template <int P, int BS>
 __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
-                                             int nd_count) {
+                                             int nd_count, uint32_t kstep) {
   using R = typename Store<P>::O;
   using U = typename Store<P>::U;
   const int d = find_domain(boff, nd_count, blockIdx.x);
@@ -217,7 +217,8 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
   bool refl = false;
   R dl[3] = {(R)0, (R)0, (R)0};
   if (active) {
-    const uint64_t t = gp(V.tstep)[1];
+    const uint64_t t = step_of(V, kstep);
+    const int par = (int)(t & 1ull);
     const int nx = V.n[0], ny = V.n[1];
     const uint32_t lc = (uint32_t)gp(V.wcell)[w];
     const uint32_t q1 = fdiv(lc, V.dx);
@@ -244,7 +245,7 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
       b0[a] = b;
       b1[a] = b1a;
     }
-    const auto u4 = gp((const U*)V.u4);
+    const auto u4 = gp((const U*)V.u4[par]);
     R Ui[3];
     {
       R v[2][2][3];
@@ -290,11 +291,11 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
       // neither type II nor IV (M < 1 outside rb); candidates come from the
       // coarse mask, the exact sphere test decides
       const R zero3[3] = {(R)0, (R)0, (R)0};
-      unsigned long long bits = mask_at<R>(V, c, zero3) | mask_at<R>(V, c, xf);
+      unsigned long long bits = mask_at<R>(V, par, c, zero3) | mask_at<R>(V, par, c, xf);
       while (bits && !queue) {
         const int p = __ffsll((long long)bits) - 1;
         bits &= bits - 1ull;
-        queue = in_sphere<R>(V, p, c, o) || in_sphere<R>(V, p, c, xf);
+        queue = in_sphere<R>(V, par, p, c, o) || in_sphere<R>(V, par, p, c, xf);
       }
     }
     if (!queue) {
@@ -311,11 +312,11 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] = o[a];
           } else if (V.np > 0) {
-            unsigned long long bits = mask_at<R>(V, c, xn);
+            unsigned long long bits = mask_at<R>(V, par, c, xn);
             while (bits && !queue) {
               const int p = __ffsll((long long)bits) - 1;
               bits &= bits - 1ull;
-              queue = in_sphere<R>(V, p, c, xn);  // the reflected point may be inside a particle
+              queue = in_sphere<R>(V, par, p, c, xn);  // the reflected point may be inside a particle
             }
             if (queue) refl = false;
           }
@@ -361,12 +362,13 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
 
 template <int P, int BS>
 __global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
-                                                  int nd_count) {
+                                                  int nd_count, uint32_t kstep) {
   using R = typename Store<P>::O;
   const int d = find_domain(boff, nd_count, blockIdx.x);
   const DomView& V = views[d];
   const int64_t wb = (int64_t)blockIdx.x - boff[d];  // queue region of walker block wb
-  const uint64_t t = gp(V.tstep)[1];
+  const uint64_t t = step_of(V, kstep);
+  const int par = (int)(t & 1ull);
   const int nx = V.n[0], ny = V.n[1];
   const auto off = gp((const R*)V.woff);
   const auto qdl = gp((const R*)V.qdl);
@@ -386,19 +388,19 @@ __global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ vi
       xf[a] = o[a] + dl[a];
       xn[a] = xf[a];
     }
-    const int jb = inside_any<R>(V, c, xf);
+    const int jb = inside_any<R>(V, par, c, xf);
     if (jb >= 0) {
-      const int ja = inside_any<R>(V, c, o);
+      const int ja = inside_any<R>(V, par, c, o);
       if (ja < 0) {
         // type IV: no-flux boundary, Algorithm 1 then Algorithm 2
         atomicAdd(&V.counters[kType4], 1ull);
         R s;
         bool done = false;
-        if (bisect<R>(V, jb, c, o, dl, (R)0, (R)1, V.max_bisect, s)) {
+        if (bisect<R>(V, par, jb, c, o, dl, (R)0, (R)1, V.max_bisect, s)) {
           R xi[3], g[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) xi[a] = o[a] + s * dl[a];
-          particle_grad_at<R>(V, jb, c, xi, g);
+          particle_grad_at<R>(V, par, jb, c, xi, g);
           const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
           if (gn > (R)0) {
             R nv[3], ti[3];
@@ -410,7 +412,7 @@ __global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ vi
             const R dt = (ti[0] * nv[0] + ti[1] * nv[1]) + ti[2] * nv[2];
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] = xi[a] + (ti[a] - ((R)2 * dt) * nv[a]);
-            if (inside_any<R>(V, c, xn) >= 0) {
+            if (inside_any<R>(V, par, c, xn) >= 0) {
               atomicAdd(&V.counters[kReturned], 1ull);
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = o[a];
@@ -428,7 +430,7 @@ __global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ vi
         // sqrt(2D) half-ball on the outer side of the surface)
         atomicAdd(&V.counters[kType2], 1ull);
         R g[3];
-        particle_grad_at<R>(V, jb, c, xf, g);
+        particle_grad_at<R>(V, par, jb, c, xf, g);
         const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
         bool fallback = true;
         if (gn > (R)0) {
@@ -439,12 +441,12 @@ __global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ vi
           for (;;) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) xe[a] = xf[a] + s * no[a];
-            if (!(particle_M_at<R>(V, jb, c, xe) >= (R)1) || !(s < lim)) break;
+            if (!(particle_M_at<R>(V, par, jb, c, xe) >= (R)1) || !(s < lim)) break;
             s = (R)2 * s;
           }
-          if (particle_M_at<R>(V, jb, c, xe) < (R)1) {
+          if (particle_M_at<R>(V, par, jb, c, xe) < (R)1) {
             R ss;
-            if (bisect<R>(V, jb, c, xf, no, s, (R)0, V.max_bisect, ss)) {
+            if (bisect<R>(V, par, jb, c, xf, no, s, (R)0, V.max_bisect, ss)) {
               R xs[3];
 #pragma unroll
               for (int a = 0; a < 3; ++a) xs[a] = xf[a] + ss * no[a];
@@ -480,7 +482,7 @@ __global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ vi
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = xe[a];
             }
-            bool bad = inside_any<R>(V, c, xn) >= 0;
+            bool bad = inside_any<R>(V, par, c, xn) >= 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
               if (bad || !V.bc[a]) continue;
@@ -492,7 +494,7 @@ __global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ vi
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = xe[a];
             }
-            fallback = inside_any<R>(V, c, xn) >= 0;
+            fallback = inside_any<R>(V, par, c, xn) >= 0;
           }
         }
         if (fallback) {
@@ -509,7 +511,7 @@ __global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ vi
     }
     if (reflect_walls<R>(V, c, xn)) {
       atomicAdd(&V.counters[kWallReflect], 1ull);
-      if (outside_walls<R>(V, c, xn) || inside_any<R>(V, c, xn) >= 0) {
+      if (outside_walls<R>(V, c, xn) || inside_any<R>(V, par, c, xn) >= 0) {
         atomicAdd(&V.counters[kReturned], 1ull);
 #pragma unroll
         for (int a = 0; a < 3; ++a) xn[a] = o[a];

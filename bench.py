@@ -163,12 +163,28 @@ def bench_plain(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_precision(args):
+    """The oscillator in every storage mode against the FP64 GPU run."""
+    from paper_2308_05007_amd import precision, workloads as W
+    n = args.lattice or 256
+    cfg = W.config_oscillator(n=n, n_particles=args.particles or 64, n_walkers=args.walkers or 10_000_000,
+                              steps=args.steps)
+    rep = precision.report(cfg, steps=args.steps, every=max(1, args.steps // 100))
+    print(json.dumps({"metric": "precision modes vs FP64 (velocity L2, concentration L2, D_alpha)",
+                      "config": {"workload": cfg["name"].rsplit("_", 1)[0], "lattice": [n] * 3,
+                                 "particles": len(cfg["particles"]), "walkers": cfg["walkers"]["n"],
+                                 "steps": args.steps},
+                      "report": rep}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="channel", choices=["channel", "oscillator", "batch", "serve"])
+    ap.add_argument("--workload", default="channel", choices=["channel", "oscillator", "precision", "batch", "serve"])
+    ap.add_argument("--lattice", type=int, default=None)
+    ap.add_argument("--particles", type=int, default=None)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -180,6 +196,8 @@ def main():
         sys.exit(2)
     if args.workload in ("channel", "oscillator"):
         bench_plain(args)
+    elif args.workload == "precision":
+        bench_precision(args)
     elif args.workload == "batch":
         from paper_2308_05007_amd import batchbench
         batchbench.main(args)

@@ -269,6 +269,18 @@ rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value);
 rwmi_status rwmi_batch_synchronize(rwmi_batch* b);
 void rwmi_batch_destroy(rwmi_batch* b);
 
+/* ---------------------------------------------------------------- dispersion
+ * Dispersion coefficient from a series of solute moments (Sec. 4, Eq. 38-40):
+ * with s_i = sigma2[i] / two_r^2 the least-squares line s = a + b t over the
+ * samples i0..n-1 gives the slope b = K u_slip / two_r of Eq. 38, so
+ * K = b two_r / u_slip, and D_alpha = K / (1 - phi) (Eq. 40).  sigma2[i] is
+ * the variance of the walker positions along the dispersion axis at time
+ * t[i] (sumsq/N - (sum/N)^2 of rwmi_moments); u_slip = <u> - <u_p> (Eq. 39);
+ * phi the solid volume fraction.  Host-only arithmetic on caller arrays.
+ * EINVAL if fewer than 2 samples are used, u_slip == 0 or phi >= 1. */
+rwmi_status rwmi_dispersion_fit(const double* t, const double* sigma2, uint32_t n, uint32_t i0, double two_r,
+                                double u_slip, double phi, double* K, double* D_alpha, double* offset);
+
 /* ---------------------------------------------------------------- diagnostics
  * The Gaussian triples the walker kernels draw for counters (id, t, purpose,
  * 0), id = 0..n-1, under key seed, written as n x 3 doubles to host z. */

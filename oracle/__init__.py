@@ -82,6 +82,9 @@ def lib():
         L.orc_bisect_segment.argtypes = [P, C.c_int, C.c_int64, ip, dp, dp, C.c_double, C.c_double,
                                          C.c_int, C.POINTER(C.c_int)]
         L.orc_reflect.argtypes = [dp, dp, dp]
+        L.orc_dispersion_fit.restype = C.c_int
+        L.orc_dispersion_fit.argtypes = [dp, dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -287,6 +290,18 @@ def reflect(ti, g):
     tr = np.empty(3)
     lib().orc_reflect(_d(ti, 3), _d(g, 3), tr)
     return tr
+
+
+def dispersion_fit(t, sigma2, two_r, u_slip, phi, i0=0):
+    K = C.c_double()
+    Da = C.c_double()
+    t = _d(t)
+    s2 = _d(sigma2)
+    r = lib().orc_dispersion_fit(t, s2, t.size, int(i0), float(two_r), float(u_slip), float(phi), C.byref(K),
+                                 C.byref(Da))
+    if r != 0:
+        raise ValueError("oracle dispersion fit: invalid input")
+    return K.value, Da.value
 
 
 def build_domain(cfg):

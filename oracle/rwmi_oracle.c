@@ -1058,3 +1058,26 @@ void orc_reflect(const double ti[3], const double g[3], double tr[3]) {
   double dt = ti[0] * nv[0] + ti[1] * nv[1] + ti[2] * nv[2];
   for (int a = 0; a < 3; a++) tr[a] = ti[a] - (2.0 * dt) * nv[a];
 }
+
+/* Eq. 38-40: sigma^2/(2R)^2 = K (U_slip / 2R) t + offset fitted by ordinary
+ * least squares (normal equations) on samples i0..n-1, then D_alpha =
+ * K / (1 - phi).  Returns 0 on success. */
+int orc_dispersion_fit(const double* t, const double* sigma2, int n, int i0, double two_r, double u_slip,
+                       double phi, double* K, double* D_alpha) {
+  if (n - i0 < 2 || u_slip == 0.0 || phi >= 1.0) return -1;
+  double S = 0, Sx = 0, Sy = 0, Sxx = 0, Sxy = 0;
+  for (int i = i0; i < n; i++) {
+    double y = sigma2[i] / (two_r * two_r);
+    S += 1.0;
+    Sx += t[i];
+    Sy += y;
+    Sxx += t[i] * t[i];
+    Sxy += t[i] * y;
+  }
+  double den = S * Sxx - Sx * Sx;
+  if (den == 0.0) return -1;
+  double slope = (S * Sxy - Sx * Sy) / den;
+  *K = slope / (u_slip / two_r);
+  *D_alpha = *K / (1.0 - phi);
+  return 0;
+}

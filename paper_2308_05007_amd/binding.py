@@ -79,6 +79,9 @@ SIGNATURES = {
     "rwmi_batch_synchronize": (C.c_int, [C.c_void_p]),
     "rwmi_batch_destroy": (None, [C.c_void_p]),
     "rwmi_device_normals": (C.c_int, [C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p]),
+    "rwmi_dispersion_fit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_double, C.c_double,
+                                      C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]),
 }
 
 _lib = None
@@ -400,6 +403,16 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def dispersion_fit(t, sigma2, two_r, u_slip, phi, i0=0):
+    """K, D_alpha and offset of Eq. 38-40 from a moment series (library host code)."""
+    t = np.ascontiguousarray(t, float)
+    s2 = np.ascontiguousarray(sigma2, float)
+    K, Da, off = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().rwmi_dispersion_fit(t.ctypes.data_as(C.c_void_p), s2.ctypes.data_as(C.c_void_p), t.size, int(i0),
+                                     float(two_r), float(u_slip), float(phi), C.byref(K), C.byref(Da), C.byref(off)))
+    return K.value, Da.value, off.value
 
 
 def device_normals(seed, t, purpose, n, device=0):

@@ -897,6 +897,33 @@ rwmi_status rwmi_device_normals(int32_t device, uint64_t seed, uint32_t t, uint3
   return RWMI_OK;
 }
 
+rwmi_status rwmi_dispersion_fit(const double* t, const double* sigma2, uint32_t n, uint32_t i0, double two_r,
+                                double u_slip, double phi, double* K, double* D_alpha, double* offset) {
+  if (!t || !sigma2 || !K || !D_alpha) return fail(nullptr, RWMI_EINVAL, "null argument");
+  if (n < i0 + 2) return fail(nullptr, RWMI_EINVAL, "need at least two samples");
+  if (u_slip == 0.0 || !(phi < 1.0) || two_r == 0.0) return fail(nullptr, RWMI_EINVAL, "u_slip, phi or 2R invalid");
+  // centred least squares (two passes) for numerical stability
+  const double m = (double)(n - i0);
+  double st = 0.0, ss = 0.0;
+  for (uint32_t i = i0; i < n; ++i) {
+    st += t[i];
+    ss += sigma2[i] / (two_r * two_r);
+  }
+  const double tb = st / m, sb = ss / m;
+  double sxy = 0.0, sxx = 0.0;
+  for (uint32_t i = i0; i < n; ++i) {
+    const double dt = t[i] - tb;
+    sxy += dt * (sigma2[i] / (two_r * two_r) - sb);
+    sxx += dt * dt;
+  }
+  if (sxx == 0.0) return fail(nullptr, RWMI_EINVAL, "all sample times equal");
+  const double b = sxy / sxx;
+  *K = b * two_r / u_slip;
+  *D_alpha = *K / (1.0 - phi);
+  if (offset) *offset = sb - b * tb;
+  return RWMI_OK;
+}
+
 // ---------------------------------------------------------------- batch
 
 static rwmi_status bfail(rwmi_batch* b, rwmi_status st, const char* msg) {

@@ -1,0 +1,139 @@
+"""Launch-shape autotuner for single domains and batches.
+
+A candidate is (fluid threads per block, walker threads per block, fluid
+launch flags).  The tuner builds scratch copies of the workload (the real
+state is never stepped), times each candidate over a few coupled steps after a
+warm-up, and keeps the fastest.  Results are cached per workload signature
+(kind, precision, lattice size classes, walker magnitude, device name) in a
+JSON file (RWMI_AUTOTUNE_CACHE, default ~/.cache/rwmi/autotune.json).  The
+launch shape never changes results: every node and walker is computed the
+same way under every candidate.
+"""
+import json
+import math
+import os
+import time
+
+from . import binding as B
+
+FLUID_BLOCKS = (128, 256, 512)
+WALK_BLOCKS = (128, 256)
+FLAGS = (0, 1, 2, 3)
+
+
+def candidates():
+    return [(lb, wb, fl) for lb in FLUID_BLOCKS for wb in WALK_BLOCKS for fl in FLAGS]
+
+
+def _cache_path():
+    return os.environ.get("RWMI_AUTOTUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "rwmi",
+                                                                     "autotune.json")
+
+
+def _load():
+    try:
+        with open(_cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(key, value):
+    d = _load()
+    d[key] = value
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(d, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _device_name():
+    try:
+        import torch
+        return torch.cuda.get_device_name(0).replace(" ", "_")
+    except Exception:
+        return "unknown"
+
+
+def signature(kind, cfgs):
+    classes = sorted({max(c["domain"]["n"]) for c in cfgs})
+    precs = sorted({c["domain"]["precision"] for c in cfgs})
+    nw = sum(c["walkers"]["n"] for c in cfgs)
+    return "%s|%s|%s|n%d|w1e%d|%s" % (kind, ",".join(precs), ",".join(map(str, classes)), len(cfgs),
+                                        int(math.log10(max(nw, 1))), _device_name())
+
+
+def _apply(target, cand, batch):
+    lb, wb, fl = cand
+    target.set("lbm_block", lb)
+    if batch:
+        target.set("walk_block", wb)
+    target.set("fluid_flags", fl)
+
+
+def tune_domain(cfg, steps=20, warmup=10, use_cache=True):
+    """Best (lbm_block, walk_block, flags) for one domain configuration."""
+    key = signature("domain", [cfg])
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            return tuple(hit["best"])
+    best, best_t, table = None, float("inf"), {}
+    for cand in candidates():
+        d = B.build_domain(cfg)
+        _apply(d, cand, batch=False)
+        d.set("walk_block", cand[1])
+        d.step(warmup)
+        d.sync()
+        t0 = time.perf_counter()
+        d.step(steps)
+        d.sync()
+        dt = (time.perf_counter() - t0) / steps
+        d.close()
+        table[str(cand)] = dt
+        if dt < best_t:
+            best, best_t = cand, dt
+    _store(key, {"best": list(best), "us_per_step": best_t * 1e6, "table_us": {k: v * 1e6 for k, v in table.items()}})
+    return best
+
+
+def build_batch(cfgs, use_graph=True):
+    doms = [B.build_domain(c) for c in cfgs]
+    bt = B.Batch()
+    for d in doms:
+        bt.add(d)
+    if use_graph:
+        bt.set("use_graph", 1)
+    return bt, doms
+
+
+def tune_batch(cfgs, steps=16, warmup=8, use_cache=True, cands=None):
+    """Best (lbm_block, walk_block, flags) for a batch of configurations."""
+    key = signature("batch", cfgs)
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            return tuple(hit["best"])
+    bt, doms = build_batch(cfgs, use_graph=False)
+    best, best_t, table = None, float("inf"), {}
+    for cand in cands or candidates():
+        _apply(bt, cand, batch=True)
+        bt.step(warmup)
+        bt.sync()
+        t0 = time.perf_counter()
+        bt.step(steps)
+        bt.sync()
+        dt = (time.perf_counter() - t0) / steps
+        table[str(cand)] = dt
+        if dt < best_t:
+            best, best_t = cand, dt
+    bt.close()
+    for d in doms:
+        d.close()
+    _store(key, {"best": list(best), "us_per_step": best_t * 1e6, "table_us": {k: v * 1e6 for k, v in table.items()}})
+    return best

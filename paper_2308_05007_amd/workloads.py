@@ -62,9 +62,11 @@ def bounding_radius(b, k):
     return float(np.max(np.sqrt((b * b).sum(1)))) + math.sqrt(float(np.sum(k)))
 
 
-def place_particles(rng, n, shapes, motion_pad, walls, tries=20000):
+def place_particles(rng, n, shapes, motion_pad, walls, tries=20000, allow_fewer=False):
     """Centres by rejection: bounding spheres widened by the motion amplitude
-    plus one cell do not overlap and stay clear of wall planes."""
+    plus one cell do not overlap and stay clear of wall planes.  With
+    allow_fewer the shapes that find no room are dropped (the centres of the
+    placed prefix are returned)."""
     centres = []
     radii = []
     for b, k in shapes:
@@ -89,8 +91,29 @@ def place_particles(rng, n, shapes, motion_pad, walls, tries=20000):
                 radii.append(r)
                 break
         else:
+            if allow_fewer:
+                return centres
             raise RuntimeError("could not place particle")
     return centres
+
+
+def _place_one(rng, n, shapes, centres, b, k, motion_pad, tries=2000):
+    """A centre for shape (b, k) in a periodic box whose widened bounding
+    sphere does not overlap those of the placed shapes, or None."""
+    r = bounding_radius(b, k) + motion_pad + 1.0
+    radii = [bounding_radius(b2, k2) + motion_pad + 1.0 for b2, k2 in shapes]
+    for _ in range(tries):
+        c = np.array([rng.uniform(0, n[a]) for a in range(3)])
+        ok = True
+        for c2, r2 in zip(centres, radii):
+            d = c - c2
+            d -= np.asarray(n, float) * np.round(d / np.asarray(n, float))
+            if d @ d < (r + r2) ** 2:
+                ok = False
+                break
+        if ok and 2 * r < min(n):
+            return c
+    return None
 
 
 def _domain(n, bc, tau, F=(0, 0, 0), D=0.0, seed=0, precision="fp64", u0=(0, 0, 0), wall_lo=None,
@@ -165,17 +188,33 @@ def config_oscillator(precision="fp16", n=256, n_particles=64, n_walkers=10_000_
 
 def config_batch_member(i, precision="fp32", steps=1000):
     """One member of the 64-simulation shape sweep (config seed 4 + i): lattice
-    in {48,64,80,96}^3 periodic, 4-16 metaballs of 4-20 control points with
-    aspect ratio U[1,4], random orientation, oscillating (A = 4, T = 1000);
+    in {48,64,80,96}^3 periodic, 4-16 metaballs of 4-20 control points
+    (spread U[1.5,3], k ~ U[0.2,0.8]) with aspect ratio U[1,4], random
+    orientation, oscillating (A = 4, T = 1000) -- drawn shapes that find no
+    room without overlap in a small box are dropped, keeping at least 4;
     1e5-5e5 walkers uniform in the fluid; tau 0.8; D = 0.005; Philox seed
     1000 + i."""
     rng = np.random.default_rng(4 + i)
     e = int(rng.choice([48, 64, 80, 96]))
     npart = int(rng.integers(4, 17))
-    shapes = [metaball_shape(rng, int(rng.integers(4, 21)), rng.uniform(2.0, 5.0), (0.3, 1.5),
+    shapes = [metaball_shape(rng, int(rng.integers(4, 21)), rng.uniform(1.5, 3.0), (0.2, 0.8),
                              aspect=rng.uniform(1.0, 4.0), rotate=True) for _ in range(npart)]
     dims = (e, e, e)
-    centres = place_particles(rng, dims, shapes, 4.0, (False, False, False))
+    # place one by one; a shape that finds no room is scaled down by 0.7
+    # (offsets x 0.7, weights x 0.49 scale the metaball exactly) up to four
+    # times, then dropped
+    placed, centres = [], []
+    for b, k in shapes:
+        for _ in range(5):
+            cs = _place_one(rng, dims, placed, centres, b, k, 4.0)
+            if cs is not None:
+                placed.append((b, k))
+                centres.append(cs)
+                break
+            b, k = 0.7 * b, 0.49 * k
+    if len(centres) < 4:
+        raise RuntimeError("sweep member %d: fewer than 4 metaballs fit" % i)
+    shapes = placed
     parts = [dict(b=b, k=k, centre=c, motion="sinusoid", amp=np.array([4.0, 0, 0]), period=1000.0,
                   phase=float(rng.uniform())) for (b, k), c in zip(shapes, centres)]
     nw = int(rng.integers(100_000, 500_001))

@@ -17,8 +17,10 @@ sample of the same workload on this host.
 
 Other workloads (own JSON line each, not the headline):
   --workload oscillator --precision fp16|bf16|fp32|fp64   256^3 oscillator
+  --workload precision                                    all storage modes vs FP64
   --workload batch                                        64-simulation sweep
-  --workload serve                                        Poisson request stream
+  --workload serve [--rate 20 --duration 15]              Poisson request stream (disabled, see
+                                                          paper_2308_05007_amd.serve.DISABLED)
 """
 import argparse
 import hashlib
@@ -184,6 +186,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="channel", choices=["channel", "oscillator", "precision", "batch", "serve"])
     ap.add_argument("--lattice", type=int, default=None)
+    ap.add_argument("--rate", type=float, default=None)
+    ap.add_argument("--duration", type=float, default=None)
     ap.add_argument("--particles", type=int, default=None)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--walkers", type=int, default=None)

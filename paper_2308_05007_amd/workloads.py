@@ -99,21 +99,22 @@ def place_particles(rng, n, shapes, motion_pad, walls, tries=20000, allow_fewer=
 
 def _place_one(rng, n, shapes, centres, b, k, motion_pad, tries=2000):
     """A centre for shape (b, k) in a periodic box whose widened bounding
-    sphere does not overlap those of the placed shapes, or None."""
+    sphere does not overlap those of the placed shapes, or None (candidates
+    drawn uniformly, the first admissible one is taken)."""
     r = bounding_radius(b, k) + motion_pad + 1.0
-    radii = [bounding_radius(b2, k2) + motion_pad + 1.0 for b2, k2 in shapes]
-    for _ in range(tries):
-        c = np.array([rng.uniform(0, n[a]) for a in range(3)])
-        ok = True
-        for c2, r2 in zip(centres, radii):
-            d = c - c2
-            d -= np.asarray(n, float) * np.round(d / np.asarray(n, float))
-            if d @ d < (r + r2) ** 2:
-                ok = False
-                break
-        if ok and 2 * r < min(n):
-            return c
-    return None
+    L = np.asarray(n, float)
+    if 2 * r >= L.min():
+        return None
+    cand = rng.uniform(0.0, 1.0, size=(tries, 3)) * L
+    if not centres:
+        return cand[0]
+    C = np.asarray(centres)
+    R = np.array([bounding_radius(b2, k2) + motion_pad + 1.0 for b2, k2 in shapes])
+    d = cand[:, None, :] - C[None, :, :]
+    d -= L * np.round(d / L)
+    ok = np.all((d * d).sum(-1) >= (r + R[None, :]) ** 2, axis=1)
+    idx = np.flatnonzero(ok)
+    return cand[idx[0]] if idx.size else None
 
 
 def _domain(n, bc, tau, F=(0, 0, 0), D=0.0, seed=0, precision="fp64", u0=(0, 0, 0), wall_lo=None,
@@ -230,8 +231,9 @@ def config_batch(n_sims=64, precision="fp32", steps=1000):
 def serving_request(rid, rng, steps_range=(500, 3000), edges=(32, 48, 64, 80, 96, 112, 128),
                     walker_range=(1e4, 1e6), particle_range=(2, 32), precisions=("fp32", "fp16")):
     """One solve request of the serving trace: edge from the size classes,
-    2-32 metaballs, log-uniform walker count, step count, storage precision;
-    Philox seed = request id."""
+    2-32 metaballs drawn (those without room in a small box shrink, then are
+    dropped), log-uniform walker count, step count, storage precision; Philox
+    seed = request id."""
     e = int(rng.choice(edges))
     npart = int(rng.integers(particle_range[0], particle_range[1] + 1))
     # shapes scaled to the box so that the particles fit
@@ -239,13 +241,17 @@ def serving_request(rid, rng, steps_range=(500, 3000), edges=(32, 48, 64, 80, 96
     shapes = [metaball_shape(rng, int(rng.integers(4, 13)), rng.uniform(1.0, smax), (0.2, 0.8),
                              aspect=rng.uniform(1.0, 2.0), rotate=True) for _ in range(npart)]
     dims = (e, e, e)
-    try:
-        centres = place_particles(rng, dims, shapes, 2.0, (False, False, False), tries=2000)
-    except RuntimeError:
-        shapes = shapes[:2]
-        centres = place_particles(rng, dims, shapes, 2.0, (False, False, False))
+    placed, centres = [], []
+    for b, k in shapes:  # shapes without room shrink by 0.7 up to four times, then are dropped
+        for _ in range(5):
+            c = _place_one(rng, dims, placed, centres, b, k, 2.0, tries=400)
+            if c is not None:
+                placed.append((b, k))
+                centres.append(c)
+                break
+            b, k = 0.7 * b, 0.49 * k
     parts = [dict(b=b, k=k, centre=c, motion="sinusoid", amp=np.array([2.0, 0, 0]), period=1000.0,
-                  phase=float(rng.uniform())) for (b, k), c in zip(shapes, centres)]
+                  phase=float(rng.uniform())) for (b, k), c in zip(placed, centres)]
     nw = int(round(math.exp(rng.uniform(math.log(walker_range[0]), math.log(walker_range[1])))))
     steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
     prec = str(rng.choice(list(precisions)))

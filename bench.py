@@ -19,6 +19,7 @@ Other workloads (own JSON line each, not the headline):
   --workload oscillator --precision fp16|bf16|fp32|fp64   256^3 oscillator
   --workload precision                                    all storage modes vs FP64
   --workload batch                                        64-simulation sweep
+  --workload copy [--lattice MiB]                         plain copy (HBM counter calibration)
   --workload serve [--rate 20 --duration 15]              Poisson request stream (disabled, see
                                                           paper_2308_05007_amd.serve.DISABLED)
 """
@@ -57,9 +58,18 @@ def fluid_bytes_per_node(prec):
     return 38 * ELEM[prec] + 3 * UELEM[prec]
 
 
+def walker_bytes_per_step(prec):
+    """Algorithmic bytes of one walker step: its cell index and three offsets
+    read and written back.  Image counts (touched only on a periodic wrap)
+    and the velocity corners (shared between walkers, served from cache) are
+    not credited."""
+    return 2 * (4 + 3 * (8 if prec == "fp64" else 4))
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lbm_impl.h", "dev_common.h", "k_lowp.hip", "k_fp64.hip"):
+    for f in ("step_impl.h", "step_map.h", "lbm_impl.h", "walk_impl.h", "pro_impl.h", "dev_common.h", "k_lowp.hip",
+              "k_fp64.hip"):
         with open(os.path.join(ROOT, "paper_2308_05007_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -140,10 +150,11 @@ def bench_plain(args):
     nw = cfg["walkers"]["n"]
     assert mom["n_walkers"] == nw, "walker count not conserved"
     mlups = N * steps / dt / 1e6
-    fl_ms, fl_n = kt["fluid"]
-    fl_avg_s = fl_ms / 1e3 / max(fl_n, 1)
-    bytes_launch = fluid_nodes(cfg) * fluid_bytes_per_node(prec)
-    achieved = bytes_launch / fl_avg_s / 1e9
+    ms_total, launches, fluid_steps = kt
+    avg_s = ms_total / 1e3 / max(launches, 1)
+    # a full launch carries one fluid update and one walker step
+    bytes_launch = fluid_nodes(cfg) * fluid_bytes_per_node(prec) + nw * walker_bytes_per_step(prec)
+    achieved = fluid_steps * bytes_launch / (ms_total / 1e3) / 1e9
     traffic = pmc_traffic(key)
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -155,9 +166,10 @@ def bench_plain(args):
         "walker_steps_per_s": round(nw * steps / dt, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_fluid (PSM-BGK collide + pull-stream)",
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(fl_avg_s * 1e6, 2)},
-        "kernels_us": {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in kt.items()},
+                     "traffic": traffic,
+                     "kernel": "k_step (fused: PSM-BGK collide + pull-stream, walkers, particle prologue)",
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 2),
+                     "launches": launches, "steps_in_launches": fluid_steps},
         "counters": mom["counters"],
     }
     if not args.no_cpu_baseline:
@@ -179,12 +191,35 @@ def bench_precision(args):
                       "report": rep}), flush=True)
 
 
+def bench_copy(args):
+    """Device-to-device copy of a known size through one elementwise kernel
+    (y = x * 1): the reference for the HBM byte counters and the measured
+    copy ceiling of this GPU."""
+    import torch
+    nbytes = (args.lattice or 1024) << 20  # MiB per tensor
+    x = torch.rand(nbytes // 4, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    print(json.dumps({"metric": "device copy (y = x * 1)", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "us_per_copy": round(s * 1e6, 2), "GB_per_s": round(2 * nbytes / s / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="channel", choices=["channel", "oscillator", "precision", "batch", "serve"])
+    ap.add_argument("--workload", default="channel", choices=["channel", "oscillator", "precision", "batch", "serve", "copy"])
     ap.add_argument("--lattice", type=int, default=None)
     ap.add_argument("--rate", type=float, default=None)
     ap.add_argument("--duration", type=float, default=None)
@@ -202,6 +237,8 @@ def main():
         bench_plain(args)
     elif args.workload == "precision":
         bench_precision(args)
+    elif args.workload == "copy":
+        bench_copy(args)
     elif args.workload == "batch":
         from paper_2308_05007_amd import batchbench
         batchbench.main(args)

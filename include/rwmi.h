@@ -187,7 +187,9 @@ rwmi_status rwmi_seed_walkers(rwmi_domain* dom, const rwmi_seed_desc* s, uint64_
  * Each step: particle poses at t and t+1; fluid update at P(t) writing u(t);
  * walkers moved with u(t) and classified against P(t+1); walker counter
  * (w, t, purpose, 0) with purpose 0 Brownian, 1 refill direction, 2 refill
- * radius.  Device-side anomalies are counted (see rwmi_moments), never
+ * radius.  n steps are n + 1 launches of one fused kernel on the domain
+ * stream (launch j: fluid and prologue of step t0 + j, walkers of step
+ * t0 + j - 1).  Device-side anomalies are counted (see rwmi_moments), never
  * returned. */
 rwmi_status rwmi_step(rwmi_domain* dom, uint32_t n_steps);
 
@@ -222,27 +224,29 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles
 /* Debug and tuning knobs (EINVAL on an unknown key):
  *   RWMI_KEY_MAX_BISECT      iteration cap of Algorithm 1 (default 200, >= 1)
  *   RWMI_KEY_USE_GRAPH       0/1: replay steps from a captured hipGraph
- *   RWMI_KEY_LBM_BLOCK       threads per block of the fluid kernel (64..1024, multiple of 64)
- *   RWMI_KEY_WALK_BLOCK      threads per block of the walker kernel
- *   RWMI_KEY_TIMING          0/1: record HIP events around every kernel of a step
- *   RWMI_KEY_FLUID_FLAGS     launch options of the fluid kernel: bit 0 hands each of
- *                            the 8 XCDs a contiguous range of blocks (default on),
- *                            bit 1 writes f* and (u, rho) with non-temporal stores
- * Results never depend on the block sizes or flags. */
+ *   RWMI_KEY_BLOCK           threads per block of the step launch (128, 256, 512;
+ *                            default 256): nodes per fluid block, walkers per
+ *                            walker block, mask blocks per prologue block
+ *   RWMI_KEY_TIMING          0/1: record HIP events around every step launch
+ *   RWMI_KEY_STEP_FLAGS      launch options of the step kernel: bit 0 deals each of
+ *                            the 8 XCDs a contiguous run of fluid blocks with its
+ *                            share of walker blocks interleaved (default on), bit 1
+ *                            writes f* and (u, rho) with non-temporal stores
+ * Results never depend on the block size or flags. */
 enum {
   RWMI_KEY_MAX_BISECT = 1,
   RWMI_KEY_USE_GRAPH = 2,
-  RWMI_KEY_LBM_BLOCK = 3,
-  RWMI_KEY_WALK_BLOCK = 4,
+  RWMI_KEY_BLOCK = 3,
   RWMI_KEY_TIMING = 5,
-  RWMI_KEY_FLUID_FLAGS = 6
+  RWMI_KEY_STEP_FLAGS = 6
 };
 rwmi_status rwmi_debug_set(rwmi_domain* dom, int32_t key, int64_t value);
 
-/* Kernel timing recorded while RWMI_KEY_TIMING is on (synchronises, then
- * clears the record).  Index k: 0 poses+mask, 1 fluid, 2 walkers (main),
- * 3 walkers near particles.  ms[k] total milliseconds, launches[k] count. */
-rwmi_status rwmi_read_kernel_times(rwmi_domain* dom, double ms[4], uint64_t launches[4]);
+/* Timing of the step launches recorded while RWMI_KEY_TIMING is on
+ * (synchronises, then clears the record): *ms total milliseconds between the
+ * events bracketing each launch, *launches their number, *steps the number of
+ * them that carried a fluid update (a group of n steps is n + 1 launches). */
+rwmi_status rwmi_read_kernel_times(rwmi_domain* dom, double* ms, uint64_t* launches, uint64_t* steps);
 
 /* Block until all work enqueued for the domain has finished. */
 rwmi_status rwmi_synchronize(rwmi_domain* dom);
@@ -252,8 +256,8 @@ rwmi_status rwmi_synchronize(rwmi_domain* dom);
 const char* rwmi_last_error(const rwmi_domain* dom);
 
 /* ---------------------------------------------------------------- batch
- * A batch steps many domains with one launch per kernel per step (work
- * lists over all member domains) on the batch stream, optionally replayed
+ * A batch steps many domains with one fused launch per step and precision
+ * (block maps over all member domains) on the batch stream, optionally replayed
  * from a hipGraph.  Members keep their state and ownership; results of a
  * domain are bit-identical to stepping it alone (same arithmetic per node and
  * per walker).  Members must live on the batch device; their own streams are
@@ -263,8 +267,8 @@ rwmi_status rwmi_batch_add(rwmi_batch* b, rwmi_domain* dom);
 rwmi_status rwmi_batch_remove(rwmi_batch* b, rwmi_domain* dom);
 /* Enqueue n_steps steps of every member on the batch stream. */
 rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps);
-/* Launch options of the batch (RWMI_KEY_USE_GRAPH, _LBM_BLOCK, _WALK_BLOCK,
- * _FLUID_FLAGS); they replace the members' own for batch steps. */
+/* Launch options of the batch (RWMI_KEY_USE_GRAPH, _BLOCK, _STEP_FLAGS); they
+ * replace the members' own for batch steps. */
 rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value);
 rwmi_status rwmi_batch_synchronize(rwmi_batch* b);
 void rwmi_batch_destroy(rwmi_batch* b);

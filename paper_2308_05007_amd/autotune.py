@@ -1,7 +1,7 @@
 """Launch-shape autotuner for single domains and batches.
 
-A candidate is (fluid threads per block, walker threads per block, fluid
-launch flags).  The tuner builds scratch copies of the workload (the real
+A candidate is (threads per block of the fused step launch, step launch
+flags).  The tuner builds scratch copies of the workload (the real
 state is never stepped), times each candidate over a few coupled steps after a
 warm-up, and keeps the fastest.  Results are cached per workload signature
 (kind, precision, lattice size classes, walker magnitude, device name) in a
@@ -16,13 +16,12 @@ import time
 
 from . import binding as B
 
-FLUID_BLOCKS = (128, 256, 512)
-WALK_BLOCKS = (128, 256)
+BLOCKS = (128, 256, 512)
 FLAGS = (0, 1, 2, 3)
 
 
 def candidates():
-    return [(lb, wb, fl) for lb in FLUID_BLOCKS for wb in WALK_BLOCKS for fl in FLAGS]
+    return [(bs, fl) for bs in BLOCKS for fl in FLAGS]
 
 
 def _cache_path():
@@ -64,20 +63,19 @@ def signature(kind, cfgs):
     classes = sorted({max(c["domain"]["n"]) for c in cfgs})
     precs = sorted({c["domain"]["precision"] for c in cfgs})
     nw = sum(c["walkers"]["n"] for c in cfgs)
-    return "%s|%s|%s|n%d|w1e%d|%s" % (kind, ",".join(precs), ",".join(map(str, classes)), len(cfgs),
+    return "%s|fused|%s|%s|n%d|w1e%d|%s" % (kind, ",".join(precs), ",".join(map(str, classes)), len(cfgs),
                                         int(math.log10(max(nw, 1))), _device_name())
 
 
-def _apply(target, cand, batch):
-    lb, wb, fl = cand
-    target.set("lbm_block", lb)
-    if batch:
-        target.set("walk_block", wb)
-    target.set("fluid_flags", fl)
+def apply(target, cand):
+    """Set a candidate on a Domain or a Batch."""
+    bs, fl = cand
+    target.set("block", bs)
+    target.set("step_flags", fl)
 
 
 def tune_domain(cfg, steps=20, warmup=10, use_cache=True):
-    """Best (lbm_block, walk_block, flags) for one domain configuration."""
+    """Best (block, flags) for one domain configuration."""
     key = signature("domain", [cfg])
     if use_cache:
         hit = _load().get(key)
@@ -86,8 +84,7 @@ def tune_domain(cfg, steps=20, warmup=10, use_cache=True):
     best, best_t, table = None, float("inf"), {}
     for cand in candidates():
         d = B.build_domain(cfg)
-        _apply(d, cand, batch=False)
-        d.set("walk_block", cand[1])
+        apply(d, cand)
         d.step(warmup)
         d.sync()
         t0 = time.perf_counter()
@@ -113,7 +110,7 @@ def build_batch(cfgs, use_graph=True):
 
 
 def tune_batch(cfgs, steps=16, warmup=8, use_cache=True, cands=None):
-    """Best (lbm_block, walk_block, flags) for a batch of configurations."""
+    """Best (block, flags) for a batch of configurations."""
     key = signature("batch", cfgs)
     if use_cache:
         hit = _load().get(key)
@@ -122,7 +119,7 @@ def tune_batch(cfgs, steps=16, warmup=8, use_cache=True, cands=None):
     bt, doms = build_batch(cfgs, use_graph=False)
     best, best_t, table = None, float("inf"), {}
     for cand in cands or candidates():
-        _apply(bt, cand, batch=True)
+        apply(bt, cand)
         bt.step(warmup)
         bt.sync()
         t0 = time.perf_counter()

@@ -27,7 +27,7 @@ def run(n_sims=64, steps=1000, precision="fp32", check=4, tune=True):
     cfgs = W.config_batch(n_sims, precision=precision, steps=steps)
     nodes = sum(int(np.prod(c["domain"]["n"])) for c in cfgs)
     walkers = sum(c["walkers"]["n"] for c in cfgs)
-    cand = autotune.tune_batch(cfgs) if tune else (256, 256, 1)
+    cand = autotune.tune_batch(cfgs) if tune else (256, 1)
     # plain path: one simulation at a time
     ref = {}
     t_plain = 0.0
@@ -43,9 +43,7 @@ def run(n_sims=64, steps=1000, precision="fp32", check=4, tune=True):
         d.close()
     # batched path
     bt, doms = autotune.build_batch(cfgs, use_graph=True)
-    bt.set("lbm_block", cand[0])
-    bt.set("walk_block", cand[1])
-    bt.set("fluid_flags", cand[2])
+    autotune.apply(bt, cand)
     bt.sync()
     t0 = time.perf_counter()
     bt.step(steps)
@@ -57,7 +55,7 @@ def run(n_sims=64, steps=1000, precision="fp32", check=4, tune=True):
         d.close()
     return {
         "n_sims": n_sims, "steps": steps, "precision": precision, "nodes": nodes, "walkers": walkers,
-        "launch": {"lbm_block": cand[0], "walk_block": cand[1], "fluid_flags": cand[2]},
+        "launch": {"block": cand[0], "step_flags": cand[1]},
         "plain": {"seconds": t_plain, "MLUPS": nodes * steps / t_plain / 1e6,
                   "walker_steps_per_s": walkers * steps / t_plain},
         "batched": {"seconds": t_batch, "MLUPS": nodes * steps / t_batch / 1e6,

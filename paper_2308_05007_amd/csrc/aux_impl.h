@@ -1,92 +1,10 @@
-// Per-step prologue (particle poses, walker cull mask), walker seeding,
-// occupancy (Eq. 16) and the FP64 moment reductions.
+// Walker seeding, occupancy (Eq. 16) and the FP64 moment reductions.
 #pragma once
 #include "dev_common.h"
 #include "lbm_impl.h"
 #include "walk_impl.h"
 
 namespace rwmi {
-
-// Circular or plain gap between coordinate c and the interval [a, b].
-__device__ __forceinline__ double gap_to(int periodic, int L, double a, double b, double c) {
-  if (!periodic) {
-    if (c < a) return a - c;
-    if (c > b) return c - b;
-    return 0.0;
-  }
-  const double hw = 0.5 * (b - a);
-  if (2.0 * hw >= (double)L) return 0.0;
-  double m = c - 0.5 * (a + b);
-  m = m - (double)L * floor(m / (double)L + 0.5);
-  const double g = fabs(m) - hw;
-  return g > 0.0 ? g : 0.0;
-}
-
-// Walker-side prologue of step t (parity par = t & 1): block 0 writes the
-// poses P(t), P(t+1) into pose[par]; every block builds its share of the
-// coarse mask at P(t+1) in mask[par]: bit p of a coarse block is set when the
-// sphere (c_p(t+1), rb_p + 1/2) meets the block (extended to infinity beyond
-// wall planes).
-__global__ void k_prologue(const DomView* __restrict__ views, const int32_t* __restrict__ boff, int nd_count,
-                           uint32_t kstep) {
-  __shared__ double sc[kMaxParticles][3];
-  __shared__ double sr[kMaxParticles];
-  const int d = find_domain(boff, nd_count, blockIdx.x);
-  const DomView& V = views[d];
-  const int lb = blockIdx.x - boff[d];
-  const uint64_t t = step_of(V, kstep);
-  const int par = (int)(t & 1ull);
-  const int tid = threadIdx.x;
-  if (tid < V.np) {
-    const DevParticle& P = V.parts[tid];
-    double c0[3], v0[3], c1[3], v1[3];
-    particle_pose(P, t, c0, v0);
-    particle_pose(P, t + 1, c1, v1);
-    if (lb == 0) {
-      double* pt = V.pose[par] + 6 * tid;
-      double* pn = V.pose[par] + 6 * (V.np + tid);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        pt[a] = c0[a];
-        pt[3 + a] = v0[a];
-        pn[a] = c1[a];
-        pn[3 + a] = v1[a];
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) sc[tid][a] = c1[a];
-    sr[tid] = P.maskr;
-  }
-  __syncthreads();
-  if (V.nw == 0 || V.np == 0) return;
-  const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
-  const int64_t cb = (int64_t)lb * blockDim.x + tid;
-  if (cb >= nmb) return;
-  const int bidx[3] = {(int)(cb % V.mb[0]), (int)((cb / V.mb[0]) % V.mb[1]), (int)(cb / ((int64_t)V.mb[0] * V.mb[1]))};
-  double lo[3], hi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = (double)(bidx[a] * kMaskBlock);
-    const int e = (bidx[a] + 1) * kMaskBlock;
-    hi[a] = (double)(e < V.n[a] ? e : V.n[a]);
-    if (V.bc[a]) {
-      if (bidx[a] == 0) lo[a] = -1e300;
-      if (bidx[a] == V.mb[a] - 1) hi[a] = 1e300;
-    }
-  }
-  unsigned long long bits = 0ull;
-  for (int p = 0; p < V.np; ++p) {
-    double g2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double g = gap_to(!V.bc[a], V.n[a], lo[a], hi[a], sc[p][a]);
-      g2 += g * g;
-    }
-    const double r = sr[p];
-    if (g2 <= r * r * (1.0 + 1e-9) + 1e-9) bits |= (1ull << p);
-  }
-  V.mask[par][cb] = bits;
-}
 
 // Seeding at t = 0: walker w tries Philox blocks (w, 0xFFFFFFFF, 16 + a, 0).
 // Writes cell, offsets (in the walker precision) and flag[w] = 1 if placed.

@@ -37,41 +37,12 @@ size_t elem_size(int prec) { return prec == RWMI_FP64 ? 8 : (prec == RWMI_FP32 ?
 size_t u_size(int prec) { return prec == RWMI_FP64 ? 8 : 4; }
 size_t off_size(int prec) { return prec == RWMI_FP64 ? 8 : 4; }
 
-enum { KT_PRO = 0, KT_FLUID = 1, KT_WALK = 2, KT_SLOW = 3, KT_N = 4 };
+using rwmi::kRoleFluid;
+using rwmi::kRolePro;
+using rwmi::kRoles;
+using rwmi::kRoleWalk;
 
 }  // namespace
-
-// Two streams per domain (or batch): the fluid kernels run on `a`, the
-// walker side (prologue, walkers, near-surface walkers) on `b`, so that the
-// walkers of step t overlap the fluid update of step t+1.  Step t's walkers
-// wait for F[t] (u(t) written); the fluid update of step t+2, which rewrites
-// the same velocity buffer, waits for W[t] (walkers of step t done).
-struct Streams {
-  hipStream_t b = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  hipEvent_t F[4] = {}, W[4] = {};
-  hipError_t create() {
-    hipError_t e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-    for (hipEvent_t* ev : {&fork, &join})
-      if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
-    for (int i = 0; i < 4; ++i) {
-      if ((e = hipEventCreateWithFlags(&F[i], hipEventDisableTiming)) != hipSuccess) return e;
-      if ((e = hipEventCreateWithFlags(&W[i], hipEventDisableTiming)) != hipSuccess) return e;
-    }
-    return hipSuccess;
-  }
-  void destroy() {
-    for (hipEvent_t e : {fork, join})
-      if (e) (void)hipEventDestroy(e);
-    for (int i = 0; i < 4; ++i) {
-      if (F[i]) (void)hipEventDestroy(F[i]);
-      if (W[i]) (void)hipEventDestroy(W[i]);
-    }
-    if (b) (void)hipStreamDestroy(b);
-    b = nullptr;
-  }
-};
 
 struct rwmi_domain {
   rwmi_domain_desc desc{};
@@ -79,28 +50,27 @@ struct rwmi_domain {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  Streams ss;
   Alloc al;
   std::string err = "no error";
   std::vector<HostParticle> parts;
   std::vector<void*> owned;  // device allocations to release
   DomView hv{};
   DomView* dv = nullptr;    // device copy of hv
-  int32_t* dboff = nullptr; // 4 work maps of 2 entries each
+  int32_t* dboff = nullptr; // kRoles block maps of 2 entries each
   bool particles_uploaded = false;
   bool seeded = false;
   bool stepped = false;
   uint64_t steps = 0;
   double ref[3] = {0, 0, 0};
-  int lbm_bs = 256, walk_bs = 256;
-  int fluid_flags = rwmi::kFlagXcd;
+  int bs = 256;  // threads per block of the step launch
+  int flags = rwmi::kFlagXcd;
   bool use_graph = false;
   bool timing = false;
   hipGraphExec_t gexec = nullptr;
   uint32_t gsteps = 0;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
-  std::vector<std::pair<int, size_t>> evrec;  // (kernel type, index of start event)
+  std::vector<std::pair<uint32_t, size_t>> evrec;  // (steps advanced, index of start event) per timed launch
   // lazily allocated readback scratch
   uint32_t* occ = nullptr;
   double* mom_part = nullptr;
@@ -114,7 +84,6 @@ struct rwmi_batch {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  Streams ss;
   std::string err;
   std::vector<rwmi_domain*> members;
   bool dirty = true;
@@ -123,17 +92,16 @@ struct rwmi_batch {
     int prec;
     std::vector<rwmi_domain*> doms;
     DomView* views = nullptr;
-    int32_t* boff = nullptr;  // 4 maps x (nd + 1)
-    int blocks[KT_N] = {0, 0, 0, 0};
-    bool any_walkers = false;
+    int32_t* boff = nullptr;  // kRoles maps x (nd + 1)
+    int blocks[kRoles] = {0, 0, 0};
   };
   std::vector<Group> groups;
   std::vector<void*> owned;
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;
   uint32_t gsteps = 0;
-  int lbm_bs = 256, walk_bs = 256;
-  int fluid_flags = rwmi::kFlagXcd;
+  int bs = 256;
+  int flags = rwmi::kFlagXcd;
 };
 
 namespace {
@@ -201,23 +169,25 @@ rwmi_status upload_view(rwmi_domain* d) {
 
 int blocks_for(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
-void kernel_blocks(const rwmi_domain* d, int b[KT_N]) {
+// Blocks per role of one domain at bs threads per block: walkers, prologue
+// (only with walkers and particles), fluid.
+void role_blocks(const rwmi_domain* d, int bs, int b[kRoles]) {
   const int64_t nmb = (int64_t)d->hv.mb[0] * d->hv.mb[1] * d->hv.mb[2];
-  b[KT_PRO] = (d->hv.nw > 0 && d->hv.np > 0) ? blocks_for(nmb, 256) : 1;
-  b[KT_FLUID] = blocks_for(d->hv.N, d->lbm_bs);
-  b[KT_WALK] = blocks_for(d->hv.nw, d->walk_bs);
-  b[KT_SLOW] = b[KT_WALK];
+  b[kRoleWalk] = d->hv.nw > 0 ? blocks_for(d->hv.nw, bs) : 0;
+  b[kRolePro] = (d->hv.nw > 0 && d->hv.np > 0) ? blocks_for(nmb, bs) : 0;
+  b[kRoleFluid] = blocks_for(d->hv.N, bs);
 }
 
 rwmi_status upload_workmaps(rwmi_domain* d) {
-  int b[KT_N];
-  kernel_blocks(d, b);
-  int32_t h[2 * KT_N];
-  for (int k = 0; k < KT_N; ++k) {
+  int b[kRoles];
+  role_blocks(d, d->bs, b);
+  int32_t h[2 * kRoles];
+  for (int k = 0; k < kRoles; ++k) {
     h[2 * k] = 0;
     h[2 * k + 1] = b[k];
   }
   HIPCHK(d, hipMemcpyAsync(d->dboff, h, sizeof h, hipMemcpyHostToDevice, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));  // h lives on this stack frame
   return RWMI_OK;
 }
 
@@ -312,18 +282,26 @@ hipEvent_t take_event(rwmi_domain* d) {
   return d->evpool[d->evused++];
 }
 
-// A launch group of n coupled steps for one domain: step offsets k = 0..n-1
-// relative to the domain's device step counter, fluid on the domain stream,
-// walker side on the second stream, joined at the end, then the counter is
-// advanced by n.
+// A launch group of n coupled steps for one domain: launches j = 0..n of
+// the fused step kernel on the domain stream (launch j: fluid and prologue
+// of step t0 + j for j < n, walkers of step t0 + j - 1 for j >= 1), then the
+// device step counter advances by n.  With `record`, HIP events bracket every
+// launch.
 rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record) {
-  const DomView* v = d->dv;
-  int b[KT_N];
-  kernel_blocks(d, b);
-  const bool walkers = d->hv.nw > 0;
-  const bool parts = d->hv.np > 0;
-  hipStream_t A = d->stream, Bs = d->ss.b;
-  auto timed = [&](int kt, hipStream_t s, auto&& launch) -> rwmi_status {
+  int b[kRoles];
+  role_blocks(d, d->bs, b);
+  hipStream_t A = d->stream;
+  for (uint32_t j = 0; j <= n; ++j) {
+    rwmi::StepArgs a{};
+    a.views = d->dv;
+    a.boff = d->dboff;
+    a.nd = 1;
+    a.nb[kRoleWalk] = j >= 1 ? b[kRoleWalk] : 0;
+    a.nb[kRolePro] = j < n ? b[kRolePro] : 0;
+    a.nb[kRoleFluid] = j < n ? b[kRoleFluid] : 0;
+    a.flags = d->flags;
+    a.j = j;
+    if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     size_t i0 = 0;
     if (record) {
@@ -331,44 +309,15 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record) {
       e0 = take_event(d);
       e1 = take_event(d);
       if (!e0 || !e1) return fail(d, RWMI_EDEVICE, "hipEventCreate failed");
-      HIPCHK(d, hipEventRecord(e0, s));
+      HIPCHK(d, hipEventRecord(e0, A));
     }
-    HIPCHK(d, launch());
+    HIPCHK(d, rwmi::launch_step(d->prec, d->bs, a, A));
     if (record) {
-      HIPCHK(d, hipEventRecord(e1, s));
-      d->evrec.push_back({kt, i0});
+      HIPCHK(d, hipEventRecord(e1, A));
+      d->evrec.push_back({j < n ? 1u : 0u, i0});
     }
-    return RWMI_OK;
-  };
-  rwmi_status st;
-  if (walkers) {
-    HIPCHK(d, hipEventRecord(d->ss.fork, A));
-    HIPCHK(d, hipStreamWaitEvent(Bs, d->ss.fork, 0));
   }
-  for (uint32_t k = 0; k < n; ++k) {
-    const rwmi::Work wpro{v, d->dboff + 0, 1, b[KT_PRO], 0, k};
-    const rwmi::Work wflu{v, d->dboff + 2, 1, b[KT_FLUID], d->fluid_flags, k};
-    const rwmi::Work wwal{v, d->dboff + 4, 1, b[KT_WALK], 0, k};
-    const rwmi::Work wslo{v, d->dboff + 6, 1, b[KT_SLOW], 0, k};
-    if (walkers && k >= 2) HIPCHK(d, hipStreamWaitEvent(A, d->ss.W[(k - 2) & 3], 0));
-    if ((st = timed(KT_FLUID, A, [&] { return rwmi::launch_fluid(d->prec, d->lbm_bs, wflu, A); })) != RWMI_OK)
-      return st;
-    if (!walkers) continue;
-    HIPCHK(d, hipEventRecord(d->ss.F[k & 3], A));
-    if (parts && (st = timed(KT_PRO, Bs, [&] { return rwmi::launch_prologue(wpro, Bs); })) != RWMI_OK) return st;
-    HIPCHK(d, hipStreamWaitEvent(Bs, d->ss.F[k & 3], 0));
-    if ((st = timed(KT_WALK, Bs, [&] { return rwmi::launch_walk(d->prec, d->walk_bs, wwal, Bs); })) != RWMI_OK)
-      return st;
-    if (parts &&
-        (st = timed(KT_SLOW, Bs, [&] { return rwmi::launch_walk_slow(d->prec, d->walk_bs, wslo, Bs); })) != RWMI_OK)
-      return st;
-    HIPCHK(d, hipEventRecord(d->ss.W[k & 3], Bs));
-  }
-  if (walkers) {
-    HIPCHK(d, hipEventRecord(d->ss.join, Bs));
-    HIPCHK(d, hipStreamWaitEvent(A, d->ss.join, 0));
-  }
-  HIPCHK(d, rwmi::launch_advance(v, 1, n, A));
+  HIPCHK(d, rwmi::launch_advance(d->dv, 1, n, A));
   return RWMI_OK;
 }
 
@@ -389,8 +338,8 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   b += 2 * 19 * N * elem_size(p) + 8 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
   b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 192 * n_particles + (n_particles ? 16 * nmb : 0);
-  // walkers: cell, offsets, images, queue (id + step), moment partials
-  b += n_walkers * (4 + 3 * off_size(p) + 12 + 4 + 3 * off_size(p));
+  // walkers: cell, offsets, images
+  b += n_walkers * (4 + 3 * off_size(p) + 12);
   b += 4 * N;  // occupancy
   b += 8 * (6 * ((n_walkers + 4095) / 4096) + 12 * ((N + 4095) / 4096) + 64);
   return b;
@@ -478,12 +427,6 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
 
   rwmi_status st = RWMI_OK;
   void *fA, *fB, *u4;
-  if (d->ss.create() != hipSuccess) {
-    d->ss.destroy();
-    if (d->own_stream) (void)hipStreamDestroy(d->stream);
-    delete d;
-    return fail(nullptr, RWMI_EDEVICE, "stream/event creation failed");
-  }
   uint64_t* tstep;
   unsigned long long* cnt;
   if ((st = alloc_into(d, fA, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
@@ -491,7 +434,7 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
       (st = alloc_into(d, u4, 8 * (size_t)N * u_size(d->prec))) != RWMI_OK ||
       (st = alloc_into(d, tstep, 16)) != RWMI_OK || (st = alloc_into(d, cnt, 8 * rwmi::kCounters)) != RWMI_OK ||
       (st = alloc_into(d, d->dv, sizeof(DomView))) != RWMI_OK ||
-      (st = alloc_into(d, d->dboff, sizeof(int32_t) * 2 * KT_N)) != RWMI_OK) {
+      (st = alloc_into(d, d->dboff, sizeof(int32_t) * 2 * kRoles)) != RWMI_OK) {
     rwmi_destroy_domain(d);
     return fail(nullptr, st, "%s", g_err.c_str());
   }
@@ -519,8 +462,6 @@ void rwmi_destroy_domain(rwmi_domain* d) {
   (void)hipSetDevice(d->device);
   if (d->stream) (void)hipStreamSynchronize(d->stream);
   drop_graph(d);
-  if (d->ss.b) (void)hipStreamSynchronize(d->ss.b);
-  d->ss.destroy();
   for (hipEvent_t e : d->evpool) (void)hipEventDestroy(e);
   for (void* p : d->owned) dev_free(d->al, p);
   if (d->own_stream) (void)hipStreamDestroy(d->stream);
@@ -609,25 +550,16 @@ rwmi_status rwmi_seed_walkers(rwmi_domain* d, const rwmi_seed_desc* s, uint64_t 
     m += hflag[w];
   }
   // walker arrays of the final size
-  int32_t *wcell, *wimg, *qid;
-  void *woff, *qdl;
-  uint32_t* qcount;
+  int32_t *wcell, *wimg;
+  void* woff;
   if ((st = alloc_into(d, wcell, 4 * std::max<int64_t>(m, 1))) != RWMI_OK ||
       (st = alloc_into(d, woff, 3 * osz * std::max<int64_t>(m, 1))) != RWMI_OK ||
-      (st = alloc_into(d, wimg, 12 * std::max<int64_t>(m, 1))) != RWMI_OK ||
-      (st = alloc_into(d, qid, 4 * std::max<int64_t>(m, 1))) != RWMI_OK ||
-      (st = alloc_into(d, qdl, 3 * osz * std::max<int64_t>(m, 1))) != RWMI_OK ||
-      (st = alloc_into(d, qcount, 4 * ((std::max<int64_t>(m, 1) + 127) / 128))) != RWMI_OK)
+      (st = alloc_into(d, wimg, 12 * std::max<int64_t>(m, 1))) != RWMI_OK)
     return cleanup(), st;
   d->hv.wcell = wcell;
   d->hv.woff = woff;
   d->hv.wimg = wimg;
-  d->hv.qid = qid;
-  d->hv.qdl = qdl;
-  d->hv.qcount = qcount;
   d->hv.nw = m;
-  d->hv.qcap = std::max<int64_t>(m, 1);
-  d->hv.qblock = d->walk_bs;
   if ((st = upload_view(d)) != RWMI_OK) return cleanup(), st;
   if (m > 0) {
     if (hipMemcpyAsync(pos, hpos.data(), 4 * nn, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
@@ -836,26 +768,18 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       d->use_graph = value != 0;
       if (!d->use_graph) drop_graph(d);
       return RWMI_OK;
-    case RWMI_KEY_LBM_BLOCK:
-      if (value != 128 && value != 256 && value != 512) return fail(d, RWMI_EINVAL, "fluid block must be 128, 256 or 512");
-      if (d->batch) return fail(d, RWMI_ESTATE, "the batch sets the fluid block of its members");
-      d->lbm_bs = (int)value;
+    case RWMI_KEY_BLOCK:
+      if (value != 128 && value != 256 && value != 512) return fail(d, RWMI_EINVAL, "block must be 128, 256 or 512");
+      if (d->batch) return fail(d, RWMI_ESTATE, "the batch sets the block size of its members");
+      d->bs = (int)value;
       drop_graph(d);
-      return upload_workmaps(d);
-    case RWMI_KEY_WALK_BLOCK:
-      if (value != 128 && value != 256) return fail(d, RWMI_EINVAL, "walker block must be 128 or 256");
-      if (d->batch) return fail(d, RWMI_ESTATE, "the batch sets the walker block of its members");
-      d->walk_bs = (int)value;
-      d->hv.qblock = (int)value;
-      drop_graph(d);
-      if (upload_view(d) != RWMI_OK) return RWMI_EDEVICE;
       return upload_workmaps(d);
     case RWMI_KEY_TIMING:
       d->timing = value != 0;
       return RWMI_OK;
-    case RWMI_KEY_FLUID_FLAGS:
-      if (value < 0 || value > 3) return fail(d, RWMI_EINVAL, "fluid flags must be in 0..3");
-      d->fluid_flags = (int)value;
+    case RWMI_KEY_STEP_FLAGS:
+      if (value < 0 || value > 3) return fail(d, RWMI_EINVAL, "step flags must be in 0..3");
+      d->flags = (int)value;
       drop_graph(d);
       return RWMI_OK;
     default:
@@ -863,19 +787,19 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
   }
 }
 
-rwmi_status rwmi_read_kernel_times(rwmi_domain* d, double ms[4], uint64_t launches[4]) {
-  if (!d || !ms || !launches) return fail(d, RWMI_EINVAL, "null argument");
+rwmi_status rwmi_read_kernel_times(rwmi_domain* d, double* ms, uint64_t* launches, uint64_t* steps) {
+  if (!d || !ms || !launches || !steps) return fail(d, RWMI_EINVAL, "null argument");
   HIPCHK(d, hipSetDevice(d->device));
   HIPCHK(d, hipStreamSynchronize(d->stream));
-  for (int k = 0; k < KT_N; ++k) {
-    ms[k] = 0.0;
-    launches[k] = 0;
-  }
+  *ms = 0.0;
+  *launches = 0;
+  *steps = 0;
   for (auto& r : d->evrec) {
     float t = 0.0f;
     HIPCHK(d, hipEventElapsedTime(&t, d->evpool[r.second], d->evpool[r.second + 1]));
-    ms[r.first] += t;
-    launches[r.first]++;
+    *ms += t;
+    *launches += 1;
+    *steps += r.first;
   }
   d->evrec.clear();
   d->evused = 0;
@@ -937,11 +861,6 @@ rwmi_status rwmi_batch_create(int32_t device, void* stream, rwmi_batch** out) {
   if (hipSetDevice(device) != hipSuccess) return bfail(nullptr, RWMI_EDEVICE, "hipSetDevice failed");
   rwmi_batch* b = new rwmi_batch();
   b->device = device;
-  if (b->ss.create() != hipSuccess) {
-    b->ss.destroy();
-    delete b;
-    return bfail(nullptr, RWMI_EDEVICE, "stream/event creation failed");
-  }
   if (stream) {
     b->stream = (hipStream_t)stream;
   } else {
@@ -993,7 +912,7 @@ rwmi_status rwmi_batch_remove(rwmi_batch* b, rwmi_domain* d) {
   return RWMI_OK;
 }
 
-// Rebuild the per-precision view arrays and work maps of the batch.
+// Rebuild the per-precision view arrays and block maps of the batch.
 static rwmi_status batch_rebuild(rwmi_batch* b) {
   if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, RWMI_EDEVICE, "batch sync failed");
   batch_drop_graph(b);
@@ -1006,31 +925,21 @@ static rwmi_status batch_rebuild(rwmi_batch* b) {
     if (g.doms.empty()) continue;
     const int nd = (int)g.doms.size();
     std::vector<DomView> hv(nd);
-    std::vector<int32_t> boff(KT_N * (nd + 1));
-    for (int k = 0; k < KT_N; ++k) {
-      int acc = 0;
-      for (int i = 0; i < nd; ++i) {
-        rwmi_domain* d = g.doms[i];
-        const int lbs = d->lbm_bs, wbs = d->walk_bs;
-        d->lbm_bs = b->lbm_bs;
-        d->walk_bs = b->walk_bs;
-        int bl[KT_N];
-        kernel_blocks(d, bl);
-        d->lbm_bs = lbs;
-        d->walk_bs = wbs;
-        boff[k * (nd + 1) + i] = acc;
-        int nb = bl[k];
-        if ((k == KT_WALK || k == KT_SLOW) && d->hv.nw == 0) nb = 0;
-        if (k == KT_SLOW && d->hv.np == 0) nb = 0;
-        acc += nb;
-      }
-      boff[k * (nd + 1) + nd] = acc;
-      g.blocks[k] = acc;
-    }
+    std::vector<int32_t> boff(kRoles * (nd + 1));
+    int64_t acc[kRoles] = {0, 0, 0};
     for (int i = 0; i < nd; ++i) {
+      int bl[kRoles];
+      role_blocks(g.doms[i], b->bs, bl);
+      for (int k = 0; k < kRoles; ++k) {
+        boff[k * (nd + 1) + i] = (int32_t)acc[k];
+        acc[k] += bl[k];
+      }
       hv[i] = g.doms[i]->hv;
-      hv[i].qblock = b->walk_bs;
-      if (g.doms[i]->hv.nw > 0) g.any_walkers = true;
+    }
+    for (int k = 0; k < kRoles; ++k) {
+      if (acc[k] > (int64_t)1 << 28) return bfail(b, RWMI_EINVAL, "batch too large for one launch");
+      boff[k * (nd + 1) + nd] = (int32_t)acc[k];
+      g.blocks[k] = (int)acc[k];
     }
     if (hipMalloc(&g.views, sizeof(DomView) * nd) != hipSuccess ||
         hipMalloc(&g.boff, sizeof(int32_t) * boff.size()) != hipSuccess)
@@ -1046,47 +955,29 @@ static rwmi_status batch_rebuild(rwmi_batch* b) {
   return RWMI_OK;
 }
 
-// A launch group of n steps for every member: one launch per kernel per step
-// and precision group, the same two-stream schedule as a single domain.
+// A launch group of n steps for every member: per precision group the same
+// n + 1 fused launches as a single domain, each over all members of the
+// group, then the step counters advance by n.
 static rwmi_status batch_enqueue_group(rwmi_batch* b, uint32_t n) {
-  hipStream_t A = b->stream, Bs = b->ss.b;
-  bool walkers = false;
-  for (auto& g : b->groups) walkers |= g.blocks[KT_WALK] > 0;
-  auto ck = [&](hipError_t e) -> bool { return e == hipSuccess; };
-  if (walkers && (!ck(hipEventRecord(b->ss.fork, A)) || !ck(hipStreamWaitEvent(Bs, b->ss.fork, 0))))
-    return bfail(b, RWMI_EDEVICE, "batch fork failed");
-  for (uint32_t k = 0; k < n; ++k) {
-    if (walkers && k >= 2 && !ck(hipStreamWaitEvent(A, b->ss.W[(k - 2) & 3], 0)))
-      return bfail(b, RWMI_EDEVICE, "batch wait failed");
+  hipStream_t A = b->stream;
+  for (uint32_t j = 0; j <= n; ++j) {
     for (auto& g : b->groups) {
-      const int nd = (int)g.doms.size();
-      const rwmi::Work wflu{g.views, g.boff + 1 * (nd + 1), nd, g.blocks[KT_FLUID], b->fluid_flags, k};
-      if (!ck(rwmi::launch_fluid(g.prec, b->lbm_bs, wflu, A))) return bfail(b, RWMI_EDEVICE, "batch launch failed");
+      rwmi::StepArgs a{};
+      a.views = g.views;
+      a.boff = g.boff;
+      a.nd = (int)g.doms.size();
+      a.nb[kRoleWalk] = j >= 1 ? g.blocks[kRoleWalk] : 0;
+      a.nb[kRolePro] = j < n ? g.blocks[kRolePro] : 0;
+      a.nb[kRoleFluid] = j < n ? g.blocks[kRoleFluid] : 0;
+      a.flags = b->flags;
+      a.j = j;
+      if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
+      if (rwmi::launch_step(g.prec, b->bs, a, A) != hipSuccess) return bfail(b, RWMI_EDEVICE, "batch launch failed");
     }
-    if (!walkers) continue;
-    if (!ck(hipEventRecord(b->ss.F[k & 3], A))) return bfail(b, RWMI_EDEVICE, "batch record failed");
-    for (auto& g : b->groups) {
-      const int nd = (int)g.doms.size();
-      const rwmi::Work wpro{g.views, g.boff + 0 * (nd + 1), nd, g.blocks[KT_PRO], 0, k};
-      if (g.blocks[KT_SLOW] > 0 && !ck(rwmi::launch_prologue(wpro, Bs)))
-        return bfail(b, RWMI_EDEVICE, "batch prologue failed");
-    }
-    if (!ck(hipStreamWaitEvent(Bs, b->ss.F[k & 3], 0))) return bfail(b, RWMI_EDEVICE, "batch wait failed");
-    for (auto& g : b->groups) {
-      const int nd = (int)g.doms.size();
-      const rwmi::Work wwal{g.views, g.boff + 2 * (nd + 1), nd, g.blocks[KT_WALK], 0, k};
-      const rwmi::Work wslo{g.views, g.boff + 3 * (nd + 1), nd, g.blocks[KT_SLOW], 0, k};
-      if (g.blocks[KT_WALK] > 0 && !ck(rwmi::launch_walk(g.prec, b->walk_bs, wwal, Bs)))
-        return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
-      if (g.blocks[KT_SLOW] > 0 && !ck(rwmi::launch_walk_slow(g.prec, b->walk_bs, wslo, Bs)))
-        return bfail(b, RWMI_EDEVICE, "batch walker launch failed");
-    }
-    if (!ck(hipEventRecord(b->ss.W[k & 3], Bs))) return bfail(b, RWMI_EDEVICE, "batch record failed");
   }
-  if (walkers && (!ck(hipEventRecord(b->ss.join, Bs)) || !ck(hipStreamWaitEvent(A, b->ss.join, 0))))
-    return bfail(b, RWMI_EDEVICE, "batch join failed");
   for (auto& g : b->groups)
-    if (!ck(rwmi::launch_advance(g.views, (int)g.doms.size(), n, A))) return bfail(b, RWMI_EDEVICE, "batch advance failed");
+    if (rwmi::launch_advance(g.views, (int)g.doms.size(), n, A) != hipSuccess)
+      return bfail(b, RWMI_EDEVICE, "batch advance failed");
   return RWMI_OK;
 }
 
@@ -1103,7 +994,7 @@ rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps) {
   if (b->members.empty()) return RWMI_OK;
   uint32_t left = n_steps;
   if (b->use_graph && n_steps >= 2) {
-    const uint32_t k = std::min<uint32_t>(n_steps, 32);
+    const uint32_t k = std::min<uint32_t>(n_steps, 64);
     if (!b->gexec || b->gsteps != k) {
       batch_drop_graph(b);
       hipGraph_t g;
@@ -1151,19 +1042,14 @@ rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value) {
       b->use_graph = value != 0;
       if (!b->use_graph) batch_drop_graph(b);
       return RWMI_OK;
-    case RWMI_KEY_LBM_BLOCK:
-      if (value != 128 && value != 256 && value != 512) return bfail(b, RWMI_EINVAL, "bad fluid block");
-      b->lbm_bs = (int)value;
+    case RWMI_KEY_BLOCK:
+      if (value != 128 && value != 256 && value != 512) return bfail(b, RWMI_EINVAL, "block must be 128, 256 or 512");
+      b->bs = (int)value;
       b->dirty = true;
       return RWMI_OK;
-    case RWMI_KEY_WALK_BLOCK:
-      if (value != 128 && value != 256) return bfail(b, RWMI_EINVAL, "bad walker block");
-      b->walk_bs = (int)value;
-      b->dirty = true;
-      return RWMI_OK;
-    case RWMI_KEY_FLUID_FLAGS:
-      if (value < 0 || value > 3) return bfail(b, RWMI_EINVAL, "fluid flags must be in 0..3");
-      b->fluid_flags = (int)value;
+    case RWMI_KEY_STEP_FLAGS:
+      if (value < 0 || value > 3) return bfail(b, RWMI_EINVAL, "step flags must be in 0..3");
+      b->flags = (int)value;
       batch_drop_graph(b);
       return RWMI_OK;
     default:
@@ -1185,8 +1071,6 @@ void rwmi_batch_destroy(rwmi_batch* b) {
   for (rwmi_domain* d : b->members) d->batch = nullptr;
   batch_drop_graph(b);
   batch_free_groups(b);
-  if (b->ss.b) (void)hipStreamSynchronize(b->ss.b);
-  b->ss.destroy();
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }

@@ -77,7 +77,6 @@ struct DomView {
   int32_t np;        // particles
   int64_t N;         // nodes
   int64_t nw;        // walkers
-  int64_t qcap;      // near-surface queue capacity
   int32_t prec;
   int32_t has_force;
   int32_t max_bisect;
@@ -99,10 +98,6 @@ struct DomView {
   int32_t* wcell;                 // walker cell index
   void* woff;                     // walker offsets SoA [3][nw] (double or float)
   int32_t* wimg;                  // walker image counts SoA [3][nw]
-  int32_t* qid;                   // near-surface queue: walker id
-  void* qdl;                      // near-surface queue: step vector SoA [3][qcap]
-  uint32_t* qcount;               // queued walkers per walker block (region of qblock slots)
-  int32_t qblock;                 // walkers per block of the walker kernel
   unsigned long long* counters;   // kCounters
   uint32_t* occ;                  // occupancy per node
 };
@@ -112,15 +107,6 @@ struct DomView {
 template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
   return (__attribute__((address_space(1))) T*)p;
-}
-
-// Block order for an 8-XCD part: workgroup i runs on XCD i mod 8, so give
-// XCD x the contiguous range of logical blocks [start(x), start(x+1)) with
-// start(x) = x floor(nb/8) + min(x, nb mod 8).  A bijection of [0, nb).
-__device__ __forceinline__ int xcd_swizzle(int i, int nb) {
-  const int x = i & 7, local = i >> 3;
-  const int per = nb >> 3, extra = nb & 7;
-  return x * per + (x < extra ? x : extra) + local;
 }
 
 // Step t of a launch: the domain's step counter at the start of the launch

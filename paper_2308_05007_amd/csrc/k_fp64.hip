@@ -2,34 +2,18 @@
 // a separately rounded IEEE operation) and the precision-independent ones.
 #include "aux_impl.h"
 #include "launch.h"
+#include "step_impl.h"
 
 namespace rwmi {
 
-hipError_t launch_prologue(const Work& w, hipStream_t s) {
-  k_prologue<<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k);
-  return hipGetLastError();
-}
-
-hipError_t launch_fluid_p64(int bs, const Work& w, hipStream_t s) {
+hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
+  const unsigned g = (unsigned)step_grid(a.nb, (a.flags & kFlagXcd) != 0);
+  if (g == 0) return hipSuccess;
   switch (bs) {
-    case 128: k_fluid<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
-    case 512: k_fluid<P64, 512><<<w.blocks, 512, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
-    default: k_fluid<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
+    case 128: k_step<P64, 128><<<g, 128, 0, s>>>(a); break;
+    case 512: k_step<P64, 512><<<g, 512, 0, s>>>(a); break;
+    default: k_step<P64, 256><<<g, 256, 0, s>>>(a); break;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_walk_p64(int bs, const Work& w, hipStream_t s) {
-  switch (bs) {
-    case 128: k_walk<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.k); break;
-    default: k_walk<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k); break;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_walk_slow_p64(int bs, const Work& w, hipStream_t s) {
-  if (bs == 128) k_walk_slow<P64, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.k);
-  else k_walk_slow<P64, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k);
   return hipGetLastError();
 }
 

@@ -1,39 +1,25 @@
 // FP32 / FP16-storage / BF16-storage kernels (collision and walker
 // arithmetic in float; contraction to FMA allowed).
-#include "lbm_impl.h"
-#include "walk_impl.h"
 #include "launch.h"
+#include "step_impl.h"
 
 namespace rwmi {
 
 template <int P>
-static void fluid_bs(int bs, const Work& w, hipStream_t s) {
+static void step_bs(int bs, unsigned g, const StepArgs& a, hipStream_t s) {
   switch (bs) {
-    case 128: k_fluid<P, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
-    case 512: k_fluid<P, 512><<<w.blocks, 512, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
-    default: k_fluid<P, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.flags, w.k); break;
+    case 128: k_step<P, 128><<<g, 128, 0, s>>>(a); break;
+    case 512: k_step<P, 512><<<g, 512, 0, s>>>(a); break;
+    default: k_step<P, 256><<<g, 256, 0, s>>>(a); break;
   }
 }
 
-hipError_t launch_fluid_lowp(int prec, int bs, const Work& w, hipStream_t s) {
-  if (prec == P32) fluid_bs<P32>(bs, w, s);
-  else if (prec == P16) fluid_bs<P16>(bs, w, s);
-  else fluid_bs<PB16>(bs, w, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_walk_lowp(int bs, const Work& w, hipStream_t s) {
-  // every low-precision mode keeps walker offsets and the velocity in float
-  switch (bs) {
-    case 128: k_walk<P32, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.k); break;
-    default: k_walk<P32, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k); break;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_walk_slow_lowp(int bs, const Work& w, hipStream_t s) {
-  if (bs == 128) k_walk_slow<P32, 128><<<w.blocks, 128, 0, s>>>(w.views, w.boff, w.nd, w.k);
-  else k_walk_slow<P32, 256><<<w.blocks, 256, 0, s>>>(w.views, w.boff, w.nd, w.k);
+hipError_t launch_step_lowp(int prec, int bs, const StepArgs& a, hipStream_t s) {
+  const unsigned g = (unsigned)step_grid(a.nb, (a.flags & kFlagXcd) != 0);
+  if (g == 0) return hipSuccess;
+  if (prec == P32) step_bs<P32>(bs, g, a, s);
+  else if (prec == P16) step_bs<P16>(bs, g, a, s);
+  else step_bs<PB16>(bs, g, a, s);
   return hipGetLastError();
 }
 

@@ -3,44 +3,23 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "step_map.h"
+
 namespace rwmi {
 struct DomView;
 
-// A multi-domain launch: `blocks` blocks over nd domains, boff (device) the
-// block prefix per domain.
-struct Work {
-  const DomView* views;
-  const int32_t* boff;
-  int nd;
-  int blocks;
-  int flags;     // fluid kernel: kFlagXcd | kFlagNontemporal
-  uint32_t k;    // step offset within the launch group
-};
-constexpr int kFlagXcd = 1;          // XCD-contiguous block order
-constexpr int kFlagNontemporal = 2;  // non-temporal stores of f* and (u, rho)
-
-hipError_t launch_prologue(const Work& w, hipStream_t s);
-hipError_t launch_fluid_p64(int bs, const Work& w, hipStream_t s);
-hipError_t launch_fluid_lowp(int prec, int bs, const Work& w, hipStream_t s);
-hipError_t launch_walk_p64(int bs, const Work& w, hipStream_t s);
-hipError_t launch_walk_lowp(int bs, const Work& w, hipStream_t s);
-hipError_t launch_walk_slow_p64(int bs, const Work& w, hipStream_t s);
-hipError_t launch_walk_slow_lowp(int bs, const Work& w, hipStream_t s);
+// One fused step launch (walker, prologue and fluid blocks; step_map.h) with
+// bs threads per block; the grid size follows from a.nb and a.flags.
+hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s);
+hipError_t launch_step_lowp(int prec, int bs, const StepArgs& a, hipStream_t s);
 hipError_t launch_init_p64(const DomView* v, int dom, int64_t N, const double u0[3], hipStream_t s);
 hipError_t launch_init_lowp(int prec, const DomView* v, int dom, int64_t N, const double u0[3], hipStream_t s);
 hipError_t launch_read_f_p64(const DomView* v, int dom, int64_t N, double* out, hipStream_t s);
 hipError_t launch_read_f_lowp(int prec, const DomView* v, int dom, int64_t N, double* out, hipStream_t s);
 
 // precision 0 is FP64 (rwmi::P64)
-inline hipError_t launch_fluid(int prec, int bs, const Work& w, hipStream_t s) {
-  return prec == 0 ? launch_fluid_p64(bs, w, s) : launch_fluid_lowp(prec, bs, w, s);
-}
-inline hipError_t launch_walk(int prec, int bs, const Work& w, hipStream_t s) {
-  return prec == 0 ? launch_walk_p64(bs, w, s) : launch_walk_lowp(bs, w, s);
-}
-// one block per walker block (queue region), same block size as the walker kernel
-inline hipError_t launch_walk_slow(int prec, int bs, const Work& w, hipStream_t s) {
-  return prec == 0 ? launch_walk_slow_p64(bs, w, s) : launch_walk_slow_lowp(bs, w, s);
+inline hipError_t launch_step(int prec, int bs, const StepArgs& a, hipStream_t s) {
+  return prec == 0 ? launch_step_p64(bs, a, s) : launch_step_lowp(prec, bs, a, s);
 }
 inline hipError_t launch_init(int prec, const DomView* v, int dom, int64_t N, const double u0[3], hipStream_t s) {
   return prec == 0 ? launch_init_p64(v, dom, N, u0, s) : launch_init_lowp(prec, v, dom, N, u0, s);

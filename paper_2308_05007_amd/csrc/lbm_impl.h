@@ -1,5 +1,6 @@
 // D3Q19 partially-saturated-cell BGK collide + pull-stream, one thread per
-// node, one block per run of consecutive nodes (x fastest).
+// node, one block per run of consecutive nodes (x fastest); a block function
+// run by the fluid blocks of the fused step launch.
 //
 // Stored state between steps is the post-collision distribution f*(t-1),
 // SoA [19][nodes], with the moving-wall term of Eq. 23 already added to every
@@ -197,19 +198,13 @@ __device__ __forceinline__ void unroll(F&& f) {
   }
 }
 
+// Nodes [lb BS, (lb + 1) BS) of a domain through step t; nt selects
+// non-temporal stores.  Every thread of the block calls it.
 template <int P, int BS>
-__global__ void __launch_bounds__(BS) k_fluid(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
-                                              int nd_count, int flags, uint32_t k) {
+__device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, BlockParticles& sp) {
   using S = typename Store<P>::S;
   using R = typename Store<P>::C;
   constexpr bool exact = (P == P64);
-  __shared__ BlockParticles sp;
-  const int gb = (flags & 1) ? xcd_swizzle((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
-  const bool nt = (flags & 2) != 0;
-  const int d = find_domain(boff, nd_count, gb);
-  const DomView& V = views[d];
-  const uint32_t lb = (uint32_t)(gb - boff[d]);
-  const uint64_t t = step_of(V, k);
   using SR = typename Raw<S>::T;
   const auto src = gp((const SR*)((t & 1ull) ? V.fB : V.fA));
   const auto dst = gp((SR*)((t & 1ull) ? V.fA : V.fB));

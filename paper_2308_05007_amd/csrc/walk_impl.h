@@ -1,16 +1,18 @@
-// Random walkers (Eq. 2) on the lattice velocity field.
+// Random walkers (Eq. 2) on the lattice velocity field, one block function
+// run by the walker blocks of the fused step launch.
 //
-// k_walk (one thread per walker): trilinear interpolation of u(t) between
+// Fast path (one thread per walker): trilinear interpolation of u(t) between
 // node centres (x, then y, then z), three normals from the Philox block
 // (w, t, 0, 0), step dl = u + z sqrt(2D).  The coarse cull mask of the
 // particles at t+1 is looked up at the start and end cells; a walker with no
 // candidate particle at either end can be neither type II nor IV (Sec.
 // 2.4.2), so it is moved here (walls, renormalisation).  Walkers with a
-// candidate are compacted into the near-surface queue with a wavefront ballot.
+// candidate are compacted into the block's LDS queue with a wavefront ballot.
 //
-// k_walk_slow (grid-stride over the queue): the full classification against
-// the particles at t+1 (types I-IV), Algorithm 1 and Algorithm 2 for type IV,
-// the refill of type II, then walls and renormalisation.
+// Near-surface path (the queued walkers, packed into the first waves of the
+// same block): the full classification against the particles at t+1 (types
+// I-IV), Algorithm 1 and Algorithm 2 for type IV, the refill of type II, then
+// walls and renormalisation.
 #pragma once
 #include "dev_common.h"
 
@@ -204,20 +206,30 @@ __device__ __forceinline__ void store_walker(const DomView& V, int64_t w, int c[
   gp(V.wcell)[w] = (int32_t)lin(V, c[0], c[1], c[2]);
 }
 
+// LDS of a walker block: the near-surface queue of its own walkers.
+template <typename R, int BS>
+struct WalkLds {
+  uint32_t s_q[BS / 64], s_r[BS / 64];
+  int32_t id[BS];
+  R dl[3][BS];
+};
+
+template <int P>
+__device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const typename Store<P>::O dl[3]);
+
+// Walkers [lblock BS, (lblock + 1) BS) of a domain through step t.  Every
+// thread of the block calls it.
 template <int P, int BS>
-__global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
-                                             int nd_count, uint32_t kstep) {
+__device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uint64_t t,
+                                           WalkLds<typename Store<P>::O, BS>& L) {
   using R = typename Store<P>::O;
   using U = typename Store<P>::U;
-  const int d = find_domain(boff, nd_count, blockIdx.x);
-  const DomView& V = views[d];
-  const int64_t w = ((int64_t)blockIdx.x - boff[d]) * BS + threadIdx.x;
+  const int64_t w = lblock * BS + threadIdx.x;
   const bool active = w < V.nw;
   bool queue = false;
   bool refl = false;
   R dl[3] = {(R)0, (R)0, (R)0};
   if (active) {
-    const uint64_t t = step_of(V, kstep);
     const int par = (int)(t & 1ull);
     const int nx = V.n[0], ny = V.n[1];
     const uint32_t lc = (uint32_t)gp(V.wcell)[w];
@@ -325,58 +337,51 @@ __global__ void __launch_bounds__(BS) k_walk(const DomView* __restrict__ views, 
       if (!queue) store_walker<R>(V, w, c, xn);
     }
   }
-  // wavefront-ballot compaction into this block's region of the queue (no
-  // global atomics): ballot and popcount per wave, prefix over the waves in
-  // LDS, one count per block
+  // wavefront-ballot compaction of the near-surface walkers into the block's
+  // LDS queue: ballot and popcount per wave, prefix over the waves
   constexpr int kWaves = BS / 64;
-  __shared__ uint32_t s_q[kWaves], s_r[kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long qm = __ballot(queue);
   const unsigned long long rm = __ballot(refl);
   if (lane == 0) {
-    s_q[wave] = (uint32_t)__popcll(qm);
-    s_r[wave] = (uint32_t)__popcll(rm);
+    L.s_q[wave] = (uint32_t)__popcll(qm);
+    L.s_r[wave] = (uint32_t)__popcll(rm);
   }
   __syncthreads();
   uint32_t before = 0, total = 0, refl_total = 0;
 #pragma unroll
   for (int k = 0; k < kWaves; ++k) {
-    before += k < wave ? s_q[k] : 0u;
-    total += s_q[k];
-    refl_total += s_r[k];
+    before += k < wave ? L.s_q[k] : 0u;
+    total += L.s_q[k];
+    refl_total += L.s_r[k];
   }
-  const int64_t lblock = (int64_t)blockIdx.x - boff[d];
   if (queue) {
-    const int64_t slot = lblock * BS + before + (uint32_t)__popcll(qm & ((1ull << lane) - 1ull));
-    gp(V.qid)[slot] = (int32_t)w;
-    const auto qdl = gp((R*)V.qdl);
-    qdl[slot] = dl[0];
-    qdl[V.qcap + slot] = dl[1];
-    qdl[2 * V.qcap + slot] = dl[2];
+    const uint32_t slot = before + (uint32_t)__popcll(qm & ((1ull << lane) - 1ull));
+    L.id[slot] = (int32_t)w;
+    L.dl[0][slot] = dl[0];
+    L.dl[1][slot] = dl[1];
+    L.dl[2][slot] = dl[2];
   }
-  if (threadIdx.x == 0) {
-    if (V.np > 0) gp(V.qcount)[lblock] = total;
-    if (refl_total) atomicAdd(&V.counters[kWallReflect], (unsigned long long)refl_total);
+  if (threadIdx.x == 0 && refl_total) atomicAdd(&V.counters[kWallReflect], (unsigned long long)refl_total);
+  __syncthreads();
+  // the queued walkers, packed into the first waves of the block
+  if (threadIdx.x < total) {
+    const R q[3] = {L.dl[0][threadIdx.x], L.dl[1][threadIdx.x], L.dl[2][threadIdx.x]};
+    walk_near_surface<P>(V, t, L.id[threadIdx.x], q);
   }
 }
 
-template <int P, int BS>
-__global__ void __launch_bounds__(BS) k_walk_slow(const DomView* __restrict__ views, const int32_t* __restrict__ boff,
-                                                  int nd_count, uint32_t kstep) {
+// A walker with a candidate particle at either end of its step: the full
+// classification against the particles at t+1 (types I-IV), Algorithm 1 and
+// Algorithm 2 for type IV, the refill of type II, then walls and
+// renormalisation.  dl is the step drawn by the fast path.
+template <int P>
+__device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const typename Store<P>::O dl[3]) {
   using R = typename Store<P>::O;
-  const int d = find_domain(boff, nd_count, blockIdx.x);
-  const DomView& V = views[d];
-  const int64_t wb = (int64_t)blockIdx.x - boff[d];  // queue region of walker block wb
-  const uint64_t t = step_of(V, kstep);
   const int par = (int)(t & 1ull);
   const int nx = V.n[0], ny = V.n[1];
   const auto off = gp((const R*)V.woff);
-  const auto qdl = gp((const R*)V.qdl);
-  const uint32_t nq = gp((const uint32_t*)V.qcount)[wb];
-  if (threadIdx.x < nq) {
-    const int64_t q = wb * BS + threadIdx.x;
-    const int64_t w = gp(V.qid)[q];
-    const R dl[3] = {qdl[q], qdl[V.qcap + q], qdl[2 * V.qcap + q]};
+  {
     const uint32_t lc = (uint32_t)gp(V.wcell)[w];
     const uint32_t q1 = fdiv(lc, V.dx);
     const int cz = (int)fdiv(q1, V.dy);

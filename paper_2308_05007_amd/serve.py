@@ -76,9 +76,8 @@ class ContinuousServer:
         if use_graph:
             self.batch.set("use_graph", 1)
         if launch:
-            self.batch.set("lbm_block", launch[0])
-            self.batch.set("walk_block", launch[1])
-            self.batch.set("fluid_flags", launch[2])
+            self.batch.set("block", launch[0])
+            self.batch.set("step_flags", launch[1])
         self.active = {}  # rid -> [domain, request, arrival, remaining, footprint]
         self.used = 0
         self.keep = keep_results

@@ -183,6 +183,25 @@ def test_channel_128_fp64_prefix(orc, B):
         compare(o, g, f=False)
 
 
+@pytest.mark.parametrize("bs", [128, 256, 512])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+def test_launch_shapes_match_oracle(orc, B, bs, flags):
+    """Every block size and role map of the fused step launch (walker blocks
+    interleaved with fluid blocks, per XCD or over the whole grid; uneven
+    role counts per XCD) gives the oracle's FP64 result; the steps are
+    enqueued in uneven groups so that group edges (fluid-only first launch,
+    walker-only last launch) fall at different steps."""
+    cfg = W.config_tiny(n=(24, 10, 17), bc=("periodic", "wall", "periodic"), n_particles=3, n_walkers=3000,
+                        seed=11, spread=1.5)
+    o, g = _pair(orc, B, cfg)
+    g.set("block", bs)
+    g.set("step_flags", flags)
+    for chunk in (5, 1, 6):
+        o.step(chunk)
+        g.step(chunk)
+    compare(o, g, f=False)
+
+
 def test_graph_replay_equals_eager(B):
     cfg = W.config_tiny(n=(9, 4, 11), bc=("periodic", "wall", "periodic"), n_walkers=500, n_particles=2, seed=5)
     a = B.build_domain(cfg)

@@ -34,6 +34,39 @@
  *   reports  : occupancy n_s (Eq. 16), FP64 moments feeding Eq. 38-40.
  *
  * Every sum is taken left to right in the order stated next to it.
+ *
+ * Pins (tests/test_oracle_*.py and tests/test_dispersion.py check these
+ * against mathematics other than this code):
+ *   equilibrium     lattice isotropy sums; mass, momentum and second moment
+ *                   of f^eq (textbook invariants)
+ *   collision       mass conserved, momentum grows by exactly F per node and
+ *                   step, tau = 1 relaxes to f^eq, a rest state stays at rest
+ *                   bitwise; PSM: eps = 0 ignores the solid velocity, a fully
+ *                   solid node relaxes to u_s, momentum exchange per node
+ *   streaming       pull equals a separately written push (brute force);
+ *                   Poiseuille at the exact tau (closed form), curvature at any
+ *                   tau, Couette linear profile
+ *   metaball        one control point is a sphere of radius sqrt(k); two equal
+ *                   points give the mid-plane ring; gradient vs central
+ *                   differences; bounding-radius lemma; minimum image
+ *   solid fraction  one control point: eps = 1/2 + (sqrt(k) - r) exactly, the
+ *                   sphere volume V + pi R / 3 by quadrature.  For several
+ *                   control points the first-order estimate is a reading:
+ *                   parity unpinned beyond the one-point case.
+ *   Algorithm 1, 2  crossing of a one-point sphere vs the quadratic root;
+ *                   iteration cap; |t_r| = |t_i|, t_r.n = -t_i.n, specular on
+ *                   a sphere
+ *   random          Philox words vs rocRAND's philox4x32_10 (library
+ *                   cross-check); LN and SINCOS2PI vs long-double libm;
+ *                   normals: moments, KS, bound
+ *   walkers         free-space MSD = 6 D t; plume drift and spread (Eq. 31,
+ *                   34); walls confine and keep a uniform density; reflection
+ *                   keeps walkers out of a static particle; count conserved
+ *   type II refill  the refilled walker lies outside every particle and near
+ *                   the surface, count conserved.  The refill point itself is
+ *                   a reading: parity unpinned beyond these invariants.
+ *   dispersion fit  a linear variance series gives the closed-form K and
+ *                   D_alpha; pure diffusion gives sigma^2 = 2 D t
  */
 #include <math.h>
 #include <stdint.h>

@@ -113,7 +113,9 @@ def cpu_baseline(cfg, seconds=15.0, max_steps=200):
                       % (steps, cfg["name"], N, w["n"], dt)}
 
 
-def run_plain(cfg, steps, warmup, prec, timing=True, graph=False):
+def run_plain(cfg, steps, warmup, prec, timing=8, graph=False):
+    """Warm up, then time `steps` steps; HIP events bracket every `timing`-th
+    step launch on the domain stream (0: none)."""
     from paper_2308_05007_amd import binding as B
     import torch
     dom = B.build_domain(cfg, device=0)
@@ -123,7 +125,7 @@ def run_plain(cfg, steps, warmup, prec, timing=True, graph=False):
     dom.sync()
     torch.cuda.synchronize()
     if timing:
-        dom.set("timing", 1)
+        dom.set("timing", timing)
         dom.kernel_times()  # clear
     t0 = time.perf_counter()
     dom.step(steps)
@@ -145,16 +147,17 @@ def bench_plain(args):
         key = "oscillator_256_" + (args.precision or "fp16")
     prec = cfg["domain"]["precision"]
     steps, warmup = args.steps, args.warmup
-    dom, dt, kt, mom = run_plain(cfg, steps, warmup, prec, timing=True, graph=False)
+    dom, dt, kt, mom = run_plain(cfg, steps, warmup, prec, timing=args.timing_every, graph=False)
     N = int(np.prod(cfg["domain"]["n"]))
     nw = cfg["walkers"]["n"]
     assert mom["n_walkers"] == nw, "walker count not conserved"
     mlups = N * steps / dt / 1e6
-    ms_total, launches, fluid_steps = kt
+    ms_total, launches, fluid_launches, walker_launches = kt
     avg_s = ms_total / 1e3 / max(launches, 1)
     # a full launch carries one fluid update and one walker step
-    bytes_launch = fluid_nodes(cfg) * fluid_bytes_per_node(prec) + nw * walker_bytes_per_step(prec)
-    achieved = fluid_steps * bytes_launch / (ms_total / 1e3) / 1e9
+    fb, wb = fluid_nodes(cfg) * fluid_bytes_per_node(prec), nw * walker_bytes_per_step(prec)
+    bytes_launch = fb + wb
+    achieved = (fluid_launches * fb + walker_launches * wb) / (ms_total / 1e3) / 1e9
     traffic = pmc_traffic(key)
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -169,7 +172,7 @@ def bench_plain(args):
                      "traffic": traffic,
                      "kernel": "k_step (fused: PSM-BGK collide + pull-stream, walkers, particle prologue)",
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 2),
-                     "launches": launches, "steps_in_launches": fluid_steps},
+                     "timed_launches": launches, "timed_every": args.timing_every},
         "counters": mom["counters"],
     }
     if not args.no_cpu_baseline:
@@ -228,6 +231,7 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--timing-every", type=int, default=8, help="bracket every n-th step launch with HIP events")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,

@@ -227,26 +227,34 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles
  *   RWMI_KEY_BLOCK           threads per block of the step launch (128, 256, 512;
  *                            default 256): nodes per fluid block, walkers per
  *                            walker block, mask blocks per prologue block
- *   RWMI_KEY_TIMING          0/1: record HIP events around every step launch
+ *   RWMI_KEY_TIMING          p > 0: record HIP events around every p-th step launch
+ *                            (1: every launch); 0: off
  *   RWMI_KEY_STEP_FLAGS      launch options of the step kernel: bit 0 deals each of
  *                            the 8 XCDs a contiguous run of fluid blocks with its
  *                            share of walker blocks interleaved (default on), bit 1
  *                            writes f* and (u, rho) with non-temporal stores
- * Results never depend on the block size or flags. */
+ *   RWMI_KEY_SORT_EVERY      regroup the walkers by coarse block (4^3 nodes) every this
+ *                            many steps for memory locality (default 64, 0 = never)
+ * Results never depend on the block size, flags or sort interval: walker ids
+ * travel with the walkers and every read-out is by id. */
 enum {
   RWMI_KEY_MAX_BISECT = 1,
   RWMI_KEY_USE_GRAPH = 2,
   RWMI_KEY_BLOCK = 3,
   RWMI_KEY_TIMING = 5,
-  RWMI_KEY_STEP_FLAGS = 6
+  RWMI_KEY_STEP_FLAGS = 6,
+  RWMI_KEY_SORT_EVERY = 7
 };
 rwmi_status rwmi_debug_set(rwmi_domain* dom, int32_t key, int64_t value);
 
 /* Timing of the step launches recorded while RWMI_KEY_TIMING is on
  * (synchronises, then clears the record): *ms total milliseconds between the
- * events bracketing each launch, *launches their number, *steps the number of
- * them that carried a fluid update (a group of n steps is n + 1 launches). */
-rwmi_status rwmi_read_kernel_times(rwmi_domain* dom, double* ms, uint64_t* launches, uint64_t* steps);
+ * events bracketing each timed launch, *launches their number, and how many
+ * of them carried a fluid update (*fluid_steps) and a walker step
+ * (*walker_steps); a group of n steps is n + 1 launches, the first without
+ * walkers, the last with walkers only. */
+rwmi_status rwmi_read_kernel_times(rwmi_domain* dom, double* ms, uint64_t* launches, uint64_t* fluid_steps,
+                                   uint64_t* walker_steps);
 
 /* Block until all work enqueued for the domain has finished. */
 rwmi_status rwmi_synchronize(rwmi_domain* dom);

@@ -18,7 +18,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: 
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 MOTION = {"static": 0, "sinusoid": 1, "const_vel": 2}
 SEED_KIND = {"uniform": 0, "gaussian": 1, "band": 2, "explicit": 3}
-KEY = {"max_bisect": 1, "use_graph": 2, "block": 3, "timing": 5, "step_flags": 6}
+KEY = {"max_bisect": 1, "use_graph": 2, "block": 3, "timing": 5, "step_flags": 6, "sort_every": 7}
 MAX_PARTICLES = 64
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -69,7 +69,7 @@ SIGNATURES = {
     "rwmi_footprint_bytes": (C.c_uint64, [C.POINTER(DomainDesc), C.c_uint32, C.c_uint32, C.c_uint64]),
     "rwmi_debug_set": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64]),
     "rwmi_read_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
-                                         C.POINTER(C.c_uint64)]),
+                                         C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "rwmi_synchronize": (C.c_int, [C.c_void_p]),
     "rwmi_last_error": (C.c_char_p, [C.c_void_p]),
     "rwmi_batch_create": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -342,11 +342,11 @@ class Domain:
         return f.reshape(19, *self.n[::-1])
 
     def kernel_times(self):
-        """(total ms, launches, steps carried) of the step launches timed
-        since the last call (timing must be on)."""
-        ms, launches, steps = C.c_double(), C.c_uint64(), C.c_uint64()
-        self._ck(self.L.rwmi_read_kernel_times(self.h, C.byref(ms), C.byref(launches), C.byref(steps)))
-        return ms.value, int(launches.value), int(steps.value)
+        """(total ms, launches, of which with a fluid update, of which with a
+        walker step) of the step launches timed since the last call."""
+        ms, n, nf, nw = C.c_double(), C.c_uint64(), C.c_uint64(), C.c_uint64()
+        self._ck(self.L.rwmi_read_kernel_times(self.h, C.byref(ms), C.byref(n), C.byref(nf), C.byref(nw)))
+        return ms.value, int(n.value), int(nf.value), int(nw.value)
 
 
 def build_domain(cfg, device=0, use_torch=True, seed_walkers=True):

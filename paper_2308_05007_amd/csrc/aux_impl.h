@@ -154,8 +154,9 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_walkers(const DomView* __re
   double acc[kWalkMom] = {0, 0, 0, 0, 0, 0};
   const int nx = V.n[0], ny = V.n[1];
   for (int j = threadIdx.x; j < kRedChunk; j += kRedThreads) {
-    const int64_t w = base + j;
-    if (w >= V.nw) break;
+    const int64_t id = base + j;  // walker ids in order, whatever slot holds them
+    if (id >= V.nw) break;
+    const int64_t w = V.winv[id];
     const int32_t lc = V.wcell[w];
     const int c[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
 #pragma unroll
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
   const int64_t last = (base + kRedChunk - 1 < V.N) ? base + kRedChunk - 1 : V.N - 1;
   const uint64_t done = V.tstep[0];  // steps completed
   const bool stepped = done > 0;
-  if (stepped && V.np > 0) cull_block(V, (uint32_t)base, (uint32_t)last, done - 1, sp);
+  if (stepped && V.np > 0) cull_block(V, (uint32_t)base, (uint32_t)last, done - 1, sp, false);
   else if (threadIdx.x == 0) sp.cnt = 0;
   __syncthreads();
   double acc[kNodeMom];
@@ -257,6 +258,174 @@ __global__ void k_normals(uint32_t k0, uint32_t k1, uint32_t t, uint32_t purpose
   z[3 * i] = a;
   z[3 * i + 1] = b;
   z[3 * i + 2] = c;
+}
+
+// ---------------------------------------------------------------- walker sort
+// Walkers are kept grouped by coarse mask block (4^3 nodes) so that the
+// walkers of a wavefront gather neighbouring velocities and share mask words.
+// A counting sort: rank within the block's bin (wave-aggregated atomics, so
+// the order inside a bin is arbitrary), exclusive scan of the bin counts,
+// scatter to scratch, copy back.  Every result of the library is independent
+// of the slot order (walker ids travel with the walkers; moments and
+// read-back go by id), so the arbitrary order inside a bin changes nothing.
+
+__device__ __forceinline__ uint32_t walker_bin(const DomView& V, int32_t cell) {
+  const uint32_t lc = (uint32_t)cell;
+  const uint32_t q1 = fdiv(lc, V.dx);
+  const uint32_t z = fdiv(q1, V.dy);
+  const uint32_t y = q1 - z * (uint32_t)V.n[1];
+  const uint32_t x = lc - q1 * (uint32_t)V.n[0];
+  return x / kMaskBlock + (uint32_t)V.mb[0] * (y / kMaskBlock + (uint32_t)V.mb[1] * (z / kMaskBlock));
+}
+
+// Every bin has kSortCopies counters (key-major: counter key * kSortCopies +
+// copy), a block using copy blockIdx mod kSortCopies, so that the walkers of
+// a dense bin do not all queue on one address; the scan over the key-major
+// counters still keeps each bin contiguous.
+constexpr int kSortCopies = 16;
+
+// bin[w] (its counter) and rank[w] (position among the walkers of that
+// counter); hist[counter] ends as the count.
+__global__ void k_sort_rank(const DomView* __restrict__ views, int dom, uint32_t* __restrict__ hist,
+                            uint32_t* __restrict__ bin, uint32_t* __restrict__ rank) {
+  const DomView& V = views[dom];
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = w < V.nw;
+  const uint32_t key =
+      active ? walker_bin(V, gp(V.wcell)[w]) * kSortCopies + (uint32_t)(blockIdx.x % kSortCopies) : 0u;
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(active);
+  uint32_t r = 0;
+  while (todo) {
+    // the lowest pending lane's key: one atomic for all lanes holding it
+    const int leader = __ffsll((long long)todo) - 1;
+    const uint32_t k = __shfl(key, leader);
+    const unsigned long long same = __ballot(active && key == k) & todo;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&hist[k], (uint32_t)__popcll(same));
+    base = __shfl(base, leader);
+    if ((same >> lane) & 1ull) r = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  if (active) {
+    gp(bin)[w] = key;
+    gp(rank)[w] = r;
+  }
+}
+
+// Exclusive scan of n counts in place: tiles of kScanTile counts scanned by
+// one block each (every thread a contiguous run of 4, loaded and stored
+// coalesced), the tile sums scanned by one block, then added to the tiles.
+constexpr int kScanThreads = 1024;
+constexpr int kScanTile = 4 * kScanThreads;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s, uint32_t& total) {
+  const int tid = threadIdx.x;
+  s[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {  // Hillis-Steele inclusive scan
+    const uint32_t u = tid >= o ? s[tid - o] : 0u;
+    __syncthreads();
+    s[tid] += u;
+    __syncthreads();
+  }
+  total = s[kScanThreads - 1];
+  return s[tid] - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(uint32_t* __restrict__ a, int64_t n,
+                                                             uint32_t* __restrict__ tsum) {
+  __shared__ uint32_t s[kScanThreads];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+  const auto g = gp(a);
+  uint32_t v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = i0 + k < n ? g[i0 + k] : 0u;
+  uint32_t total;
+  uint32_t run = block_exclusive_scan((v[0] + v[1]) + (v[2] + v[3]), s, total);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < n) g[i0 + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) gp(tsum)[blockIdx.x] = total;
+}
+
+// Exclusive scan of m <= kScanThreads * 64 tile sums, one block.
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t* __restrict__ t, int64_t m) {
+  __shared__ uint32_t s[kScanThreads];
+  const int64_t per = (m + kScanThreads - 1) / kScanThreads;
+  const int64_t b = threadIdx.x * per, e = (b + per < m) ? b + per : m;
+  uint32_t sum = 0;
+  for (int64_t i = b; i < e; ++i) sum += t[i];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(sum, s, total);
+  for (int64_t i = b; i < e; ++i) {
+    const uint32_t c = t[i];
+    t[i] = run;
+    run += c;
+  }
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ a, int64_t n, const uint32_t* __restrict__ tsum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) gp(a)[i] += gp(tsum)[i / kScanTile];
+}
+
+// Scatter every walker to slot start[bin] + rank in the scratch arrays.
+template <typename R>
+__global__ void k_sort_scatter(const DomView* __restrict__ views, int dom, const uint32_t* __restrict__ start,
+                               const uint32_t* __restrict__ bin, const uint32_t* __restrict__ rank,
+                               int32_t* __restrict__ cell2, R* __restrict__ off2, int32_t* __restrict__ img2,
+                               int32_t* __restrict__ wid2) {
+  const DomView& V = views[dom];
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= V.nw) return;
+  const int64_t nw = V.nw;
+  const int64_t d = (int64_t)gp(start)[gp(bin)[w]] + gp(rank)[w];
+  gp(cell2)[d] = gp(V.wcell)[w];
+  gp(wid2)[d] = gp(V.wid)[w];
+  const auto off = gp((const R*)V.woff);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gp(off2)[a * nw + d] = off[a * nw + w];
+    gp(img2)[a * nw + d] = gp(V.wimg)[a * nw + w];
+  }
+}
+
+// Copy the sorted scratch back.
+template <typename R>
+__global__ void k_sort_back(const DomView* __restrict__ views, int dom, const int32_t* __restrict__ cell2,
+                            const R* __restrict__ off2, const int32_t* __restrict__ img2,
+                            const int32_t* __restrict__ wid2) {
+  const DomView& V = views[dom];
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= V.nw) return;
+  const int64_t nw = V.nw;
+  gp(V.wcell)[w] = gp(cell2)[w];
+  gp(V.wid)[w] = gp(wid2)[w];
+  const auto off = gp((R*)V.woff);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    off[a * nw + w] = gp(off2)[a * nw + w];
+    gp(V.wimg)[a * nw + w] = gp(img2)[a * nw + w];
+  }
+}
+
+// Slot i holds walker i (after seeding).
+__global__ void k_ids_identity(const DomView* __restrict__ views, int dom) {
+  const DomView& V = views[dom];
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= V.nw) return;
+  gp(V.wid)[w] = (int32_t)w;
+}
+
+// The id -> slot map, built when a read-out needs walkers in id order.
+__global__ void k_ids_inverse(const DomView* __restrict__ views, int dom) {
+  const DomView& V = views[dom];
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= V.nw) return;
+  gp(V.winv)[gp(V.wid)[w]] = (int32_t)w;
 }
 
 }  // namespace rwmi

@@ -64,13 +64,23 @@ struct rwmi_domain {
   double ref[3] = {0, 0, 0};
   int bs = 256;  // threads per block of the step launch
   int flags = rwmi::kFlagXcd;
+  int sort_every = 64;     // regroup walkers by coarse block every this many steps (0: never)
+  uint64_t sorted_at = 0;  // step of the last regrouping (host view)
+  rwmi::SortScratch sort{};
   bool use_graph = false;
   bool timing = false;
+  uint32_t timing_every = 1;  // bracket every this many launches
+  uint64_t launch_seq = 0;    // launches enqueued while timing
   hipGraphExec_t gexec = nullptr;
   uint32_t gsteps = 0;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
-  std::vector<std::pair<uint32_t, size_t>> evrec;  // (steps advanced, index of start event) per timed launch
+  struct TimedLaunch {
+    size_t ev;      // index of the start event (the stop event follows)
+    bool fluid;     // carried a fluid update
+    bool walkers;   // carried a walker step
+  };
+  std::vector<TimedLaunch> evrec;
   // lazily allocated readback scratch
   uint32_t* occ = nullptr;
   double* mom_part = nullptr;
@@ -170,12 +180,22 @@ rwmi_status upload_view(rwmi_domain* d) {
 int blocks_for(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
 // Blocks per role of one domain at bs threads per block: walkers, prologue
-// (only with walkers and particles), fluid.
+// (poses whenever there are particles, the cull mask too when there are also
+// walkers), fluid.
 void role_blocks(const rwmi_domain* d, int bs, int b[kRoles]) {
   const int64_t nmb = (int64_t)d->hv.mb[0] * d->hv.mb[1] * d->hv.mb[2];
   b[kRoleWalk] = d->hv.nw > 0 ? blocks_for(d->hv.nw, bs) : 0;
-  b[kRolePro] = (d->hv.nw > 0 && d->hv.np > 0) ? blocks_for(nmb, bs) : 0;
+  b[kRolePro] = d->hv.np > 0 ? (d->hv.nw > 0 ? blocks_for(nmb, bs) : 1) : 0;
   b[kRoleFluid] = blocks_for(d->hv.N, bs);
+}
+
+// Blocks per role of launch j of a group of n steps (j = -1: the
+// prologue-only launch that opens the group).
+void launch_roles(const int b[kRoles], int j, uint32_t n, int nb[kRoles]) {
+  const int64_t nn = (int64_t)n;
+  nb[kRoleWalk] = j >= 1 ? b[kRoleWalk] : 0;
+  nb[kRolePro] = (j == -1 || (j >= 0 && j < nn - 1)) ? b[kRolePro] : 0;
+  nb[kRoleFluid] = (j >= 0 && j < nn) ? b[kRoleFluid] : 0;
 }
 
 rwmi_status upload_workmaps(rwmi_domain* d) {
@@ -247,7 +267,7 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   if ((st = alloc_into(d, dp, sizeof(DevParticle) * hp.size())) != RWMI_OK) return st;
   if ((st = alloc_into(d, dc, sizeof(double) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
   if ((st = alloc_into(d, dcf, sizeof(float) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
-  if ((st = alloc_into(d, dpose, sizeof(double) * 24 * std::max(np, 1))) != RWMI_OK) return st;
+  if ((st = alloc_into(d, dpose, sizeof(double) * 36 * std::max(np, 1))) != RWMI_OK) return st;
   HIPCHK(d, hipMemcpyAsync(dp, hp.data(), sizeof(DevParticle) * hp.size(), hipMemcpyHostToDevice, d->stream));
   if (!ctrl.empty()) {
     HIPCHK(d, hipMemcpyAsync(dc, ctrl.data(), sizeof(double) * ctrl.size(), hipMemcpyHostToDevice, d->stream));
@@ -257,16 +277,14 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   d->hv.parts = dp;
   d->hv.ctrl = dc;
   d->hv.ctrl_f = dcf;
-  d->hv.pose[0] = dpose;
-  d->hv.pose[1] = dpose + 12 * std::max(np, 1);
+  for (int k = 0; k < 3; ++k) d->hv.pose[k] = dpose + 12 * std::max(np, 1) * k;
   d->hv.np = np;
   if (np > 0) {
     unsigned long long* mask;
     int32_t mb[3];
     const int64_t nmb = mask_blocks(d->desc, mb);
-    if ((st = alloc_into(d, mask, 16 * nmb)) != RWMI_OK) return st;
-    d->hv.mask[0] = mask;
-    d->hv.mask[1] = mask + nmb;
+    if ((st = alloc_into(d, mask, 24 * nmb)) != RWMI_OK) return st;
+    for (int k = 0; k < 3; ++k) d->hv.mask[k] = mask + nmb * k;
   }
   d->particles_uploaded = true;
   if ((st = upload_view(d)) != RWMI_OK) return st;
@@ -282,29 +300,42 @@ hipEvent_t take_event(rwmi_domain* d) {
   return d->evpool[d->evused++];
 }
 
-// A launch group of n coupled steps for one domain: launches j = 0..n of
-// the fused step kernel on the domain stream (launch j: fluid and prologue
-// of step t0 + j for j < n, walkers of step t0 + j - 1 for j >= 1), then the
-// device step counter advances by n.  With `record`, HIP events bracket every
-// launch.
-rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record) {
+// Regroup the walkers before launch j of a group of n?  Every sort_every
+// launches inside a group, and at its start when due (always at the start of
+// a captured group, whose replays cannot consult the host).
+bool sort_before(const rwmi_domain* d, uint32_t j, uint32_t n, bool capturing) {
+  const uint32_t S = (uint32_t)d->sort_every;
+  if (S == 0 || d->hv.nw == 0 || j >= n || j % S != 0) return false;
+  return j > 0 || capturing || d->steps - d->sorted_at >= S;
+}
+
+// A launch group of n coupled steps for one domain: the prologue-only launch
+// of step t0, then launches j = 0..n of the fused step kernel on the domain
+// stream (launch j: fluid of t0 + j for j < n, prologue of t0 + j + 1 for
+// j < n - 1, walkers of t0 + j - 1 for j >= 1), with the walker regrouping
+// between launches, then the device step counter advances by n.  With
+// `record`, HIP events bracket every timing_every-th launch (j >= 0).
+rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturing) {
   int b[kRoles];
   role_blocks(d, d->bs, b);
   hipStream_t A = d->stream;
-  for (uint32_t j = 0; j <= n; ++j) {
+  for (int j = -1; j <= (int)n; ++j) {
+    if (j >= 0 && sort_before(d, (uint32_t)j, n, capturing)) {
+      HIPCHK(d, rwmi::launch_sort(d->prec, d->dv, 0, d->hv.nw, d->sort, A));
+      if (!capturing) d->sorted_at = d->steps + (uint32_t)j;
+    }
     rwmi::StepArgs a{};
     a.views = d->dv;
     a.boff = d->dboff;
     a.nd = 1;
-    a.nb[kRoleWalk] = j >= 1 ? b[kRoleWalk] : 0;
-    a.nb[kRolePro] = j < n ? b[kRolePro] : 0;
-    a.nb[kRoleFluid] = j < n ? b[kRoleFluid] : 0;
+    launch_roles(b, j, n, a.nb);
     a.flags = d->flags;
     a.j = j;
     if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     size_t i0 = 0;
-    if (record) {
+    const bool timed = record && j >= 0 && (d->launch_seq++ % d->timing_every) == 0;
+    if (timed) {
       i0 = d->evused;
       e0 = take_event(d);
       e1 = take_event(d);
@@ -312,9 +343,9 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record) {
       HIPCHK(d, hipEventRecord(e0, A));
     }
     HIPCHK(d, rwmi::launch_step(d->prec, d->bs, a, A));
-    if (record) {
+    if (timed) {
       HIPCHK(d, hipEventRecord(e1, A));
-      d->evrec.push_back({j < n ? 1u : 0u, i0});
+      d->evrec.push_back({i0, a.nb[kRoleFluid] > 0, a.nb[kRoleWalk] > 0});
     }
   }
   HIPCHK(d, rwmi::launch_advance(d->dv, 1, n, A));
@@ -337,9 +368,11 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   uint64_t b = 0;
   b += 2 * 19 * N * elem_size(p) + 8 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
-  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 192 * n_particles + (n_particles ? 16 * nmb : 0);
-  // walkers: cell, offsets, images
-  b += n_walkers * (4 + 3 * off_size(p) + 12);
+  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 288 * n_particles + (n_particles ? 24 * nmb : 0);
+  // walkers: cell, offsets, images, id and slot maps; sort scratch (bin, rank
+  // and a second copy of the walker record) and the bin counts
+  b += n_walkers * (4 + 3 * off_size(p) + 12 + 8);
+  b += n_walkers * (8 + 4 + 3 * off_size(p) + 12 + 4) + 64 * nmb + 4 * (16 * nmb / 4096 + 1);
   b += 4 * N;  // occupancy
   b += 8 * (6 * ((n_walkers + 4095) / 4096) + 12 * ((N + 4095) / 4096) + 64);
   return b;
@@ -550,20 +583,29 @@ rwmi_status rwmi_seed_walkers(rwmi_domain* d, const rwmi_seed_desc* s, uint64_t 
     m += hflag[w];
   }
   // walker arrays of the final size
-  int32_t *wcell, *wimg;
+  int32_t *wcell, *wimg, *wid, *winv;
   void* woff;
-  if ((st = alloc_into(d, wcell, 4 * std::max<int64_t>(m, 1))) != RWMI_OK ||
-      (st = alloc_into(d, woff, 3 * osz * std::max<int64_t>(m, 1))) != RWMI_OK ||
-      (st = alloc_into(d, wimg, 12 * std::max<int64_t>(m, 1))) != RWMI_OK)
+  const int64_t m1 = std::max<int64_t>(m, 1);
+  rwmi::SortScratch& sc = d->sort;
+  sc.nbins = (int64_t)d->hv.mb[0] * d->hv.mb[1] * d->hv.mb[2];
+  if ((st = alloc_into(d, wcell, 4 * m1)) != RWMI_OK || (st = alloc_into(d, woff, 3 * osz * m1)) != RWMI_OK ||
+      (st = alloc_into(d, wimg, 12 * m1)) != RWMI_OK || (st = alloc_into(d, wid, 4 * m1)) != RWMI_OK ||
+      (st = alloc_into(d, winv, 4 * m1)) != RWMI_OK || (st = alloc_into(d, sc.hist, 64 * sc.nbins + 4 * (16 * sc.nbins / 4096 + 1))) != RWMI_OK ||
+      (st = alloc_into(d, sc.bin, 4 * m1)) != RWMI_OK || (st = alloc_into(d, sc.rank, 4 * m1)) != RWMI_OK ||
+      (st = alloc_into(d, sc.cell, 4 * m1)) != RWMI_OK || (st = alloc_into(d, sc.off, 3 * osz * m1)) != RWMI_OK ||
+      (st = alloc_into(d, sc.img, 12 * m1)) != RWMI_OK || (st = alloc_into(d, sc.wid, 4 * m1)) != RWMI_OK)
     return cleanup(), st;
   d->hv.wcell = wcell;
   d->hv.woff = woff;
   d->hv.wimg = wimg;
+  d->hv.wid = wid;
+  d->hv.winv = winv;
   d->hv.nw = m;
   if ((st = upload_view(d)) != RWMI_OK) return cleanup(), st;
   if (m > 0) {
     if (hipMemcpyAsync(pos, hpos.data(), 4 * nn, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
-        rwmi::launch_seed_scatter(d->prec, d->dv, 0, nn, tcell, toff, flag, pos, m, d->stream) != hipSuccess)
+        rwmi::launch_seed_scatter(d->prec, d->dv, 0, nn, tcell, toff, flag, pos, m, d->stream) != hipSuccess ||
+        rwmi::launch_ids_identity(d->dv, 0, m, d->stream) != hipSuccess)
       return cleanup(), fail(d, RWMI_EDEVICE, "seed scatter failed");
   }
   if (hipStreamSynchronize(d->stream) != hipSuccess) return cleanup(), fail(d, RWMI_EDEVICE, "seeding failed");
@@ -592,7 +634,7 @@ rwmi_status rwmi_step(rwmi_domain* d, uint32_t n_steps) {
       drop_graph(d);
       hipGraph_t g;
       HIPCHK(d, hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal));
-      if ((st = enqueue_group(d, k, false)) != RWMI_OK) {
+      if ((st = enqueue_group(d, k, false, true)) != RWMI_OK) {
         hipGraph_t junk = nullptr;
         (void)hipStreamEndCapture(d->stream, &junk);
         if (junk) (void)hipGraphDestroy(junk);
@@ -607,11 +649,12 @@ rwmi_status rwmi_step(rwmi_domain* d, uint32_t n_steps) {
     while (left >= d->gsteps) {
       HIPCHK(d, hipGraphLaunch(d->gexec, d->stream));
       left -= d->gsteps;
+      if (d->sort_every > 0 && d->hv.nw > 0) d->sorted_at = d->steps;  // every replay sorts at its start
       d->steps += d->gsteps;
     }
   }
   if (left > 0) {
-    if ((st = enqueue_group(d, left, d->timing)) != RWMI_OK) return st;
+    if ((st = enqueue_group(d, left, d->timing, false)) != RWMI_OK) return st;
     d->steps += left;
   }
   return RWMI_OK;
@@ -661,20 +704,38 @@ rwmi_status rwmi_read_walkers(rwmi_domain* d, int32_t* cell, double* off, int32_
   HIPCHK(d, hipSetDevice(d->device));
   const int64_t m = d->hv.nw;
   if (m == 0) return RWMI_OK;
-  if (cell) HIPCHK(d, hipMemcpyAsync(cell, d->hv.wcell, 4 * m, hipMemcpyDeviceToHost, d->stream));
-  if (img) HIPCHK(d, hipMemcpyAsync(img, d->hv.wimg, 12 * m, hipMemcpyDeviceToHost, d->stream));
+  // slots hold walkers in any order; the output is in walker-id order
+  std::vector<int32_t> wid(m), hc, hi;
+  std::vector<double> hd;
   std::vector<float> hf;
+  HIPCHK(d, hipMemcpyAsync(wid.data(), d->hv.wid, 4 * m, hipMemcpyDeviceToHost, d->stream));
+  if (cell) {
+    hc.resize(m);
+    HIPCHK(d, hipMemcpyAsync(hc.data(), d->hv.wcell, 4 * m, hipMemcpyDeviceToHost, d->stream));
+  }
+  if (img) {
+    hi.resize(3 * m);
+    HIPCHK(d, hipMemcpyAsync(hi.data(), d->hv.wimg, 12 * m, hipMemcpyDeviceToHost, d->stream));
+  }
   if (off) {
     if (d->prec == RWMI_FP64) {
-      HIPCHK(d, hipMemcpyAsync(off, d->hv.woff, 24 * m, hipMemcpyDeviceToHost, d->stream));
+      hd.resize(3 * m);
+      HIPCHK(d, hipMemcpyAsync(hd.data(), d->hv.woff, 24 * m, hipMemcpyDeviceToHost, d->stream));
     } else {
       hf.resize(3 * m);
       HIPCHK(d, hipMemcpyAsync(hf.data(), d->hv.woff, 12 * m, hipMemcpyDeviceToHost, d->stream));
     }
   }
   HIPCHK(d, hipStreamSynchronize(d->stream));
-  if (off && d->prec != RWMI_FP64)
-    for (int64_t i = 0; i < 3 * m; ++i) off[i] = hf[i];
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t w = wid[i];
+    if (w < 0 || w >= m) return fail(d, RWMI_EDEVICE, "walker id map corrupt at slot %lld", (long long)i);
+    if (cell) cell[w] = hc[i];
+    for (int a = 0; a < 3; ++a) {
+      if (img) img[a * m + w] = hi[a * m + i];
+      if (off) off[a * m + w] = d->prec == RWMI_FP64 ? hd[a * m + i] : (double)hf[a * m + i];
+    }
+  }
   return RWMI_OK;
 }
 
@@ -775,31 +836,43 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       drop_graph(d);
       return upload_workmaps(d);
     case RWMI_KEY_TIMING:
+      if (value < 0 || value > (1 << 20)) return fail(d, RWMI_EINVAL, "timing period out of range");
       d->timing = value != 0;
+      d->timing_every = value > 0 ? (uint32_t)value : 1u;
+      d->launch_seq = 0;
       return RWMI_OK;
     case RWMI_KEY_STEP_FLAGS:
       if (value < 0 || value > 3) return fail(d, RWMI_EINVAL, "step flags must be in 0..3");
       d->flags = (int)value;
       drop_graph(d);
       return RWMI_OK;
+    case RWMI_KEY_SORT_EVERY:
+      if (value < 0 || value > (1 << 20)) return fail(d, RWMI_EINVAL, "sort interval out of range");
+      d->sort_every = (int)value;
+      drop_graph(d);
+      if (d->batch) d->batch->dirty = true;
+      return RWMI_OK;
     default:
       return fail(d, RWMI_EINVAL, "unknown key %d", key);
   }
 }
 
-rwmi_status rwmi_read_kernel_times(rwmi_domain* d, double* ms, uint64_t* launches, uint64_t* steps) {
-  if (!d || !ms || !launches || !steps) return fail(d, RWMI_EINVAL, "null argument");
+rwmi_status rwmi_read_kernel_times(rwmi_domain* d, double* ms, uint64_t* launches, uint64_t* fluid_steps,
+                                   uint64_t* walker_steps) {
+  if (!d || !ms || !launches || !fluid_steps || !walker_steps) return fail(d, RWMI_EINVAL, "null argument");
   HIPCHK(d, hipSetDevice(d->device));
   HIPCHK(d, hipStreamSynchronize(d->stream));
   *ms = 0.0;
   *launches = 0;
-  *steps = 0;
+  *fluid_steps = 0;
+  *walker_steps = 0;
   for (auto& r : d->evrec) {
     float t = 0.0f;
-    HIPCHK(d, hipEventElapsedTime(&t, d->evpool[r.second], d->evpool[r.second + 1]));
+    HIPCHK(d, hipEventElapsedTime(&t, d->evpool[r.ev], d->evpool[r.ev + 1]));
     *ms += t;
     *launches += 1;
-    *steps += r.first;
+    *fluid_steps += r.fluid ? 1 : 0;
+    *walker_steps += r.walkers ? 1 : 0;
   }
   d->evrec.clear();
   d->evused = 0;
@@ -956,19 +1029,26 @@ static rwmi_status batch_rebuild(rwmi_batch* b) {
 }
 
 // A launch group of n steps for every member: per precision group the same
-// n + 1 fused launches as a single domain, each over all members of the
-// group, then the step counters advance by n.
-static rwmi_status batch_enqueue_group(rwmi_batch* b, uint32_t n) {
+// launches as a single domain (prologue-only launch, then n + 1 fused
+// launches), each over all members of the group, then the step counters
+// advance by n.
+static rwmi_status batch_enqueue_group(rwmi_batch* b, uint32_t n, bool capturing) {
   hipStream_t A = b->stream;
-  for (uint32_t j = 0; j <= n; ++j) {
+  for (int j = -1; j <= (int)n; ++j) {
+    for (auto& g : b->groups)
+      for (size_t i = 0; i < g.doms.size() && j >= 0; ++i) {
+        rwmi_domain* d = g.doms[i];
+        if (!sort_before(d, (uint32_t)j, n, capturing)) continue;
+        if (rwmi::launch_sort(g.prec, g.views, (int)i, d->hv.nw, d->sort, A) != hipSuccess)
+          return bfail(b, RWMI_EDEVICE, "batch sort failed");
+        if (!capturing) d->sorted_at = d->steps + (uint32_t)j;
+      }
     for (auto& g : b->groups) {
       rwmi::StepArgs a{};
       a.views = g.views;
       a.boff = g.boff;
       a.nd = (int)g.doms.size();
-      a.nb[kRoleWalk] = j >= 1 ? g.blocks[kRoleWalk] : 0;
-      a.nb[kRolePro] = j < n ? g.blocks[kRolePro] : 0;
-      a.nb[kRoleFluid] = j < n ? g.blocks[kRoleFluid] : 0;
+      launch_roles(g.blocks, j, n, a.nb);
       a.flags = b->flags;
       a.j = j;
       if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
@@ -1000,7 +1080,7 @@ rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps) {
       hipGraph_t g;
       if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, RWMI_EDEVICE, "capture failed");
-      if (batch_enqueue_group(b, k) != RWMI_OK) {
+      if (batch_enqueue_group(b, k, true) != RWMI_OK) {
         hipGraph_t junk = nullptr;
         (void)hipStreamEndCapture(b->stream, &junk);
         if (junk) (void)hipGraphDestroy(junk);
@@ -1015,11 +1095,14 @@ rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps) {
     while (left >= b->gsteps) {
       if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return bfail(b, RWMI_EDEVICE, "graph launch failed");
       left -= b->gsteps;
-      for (rwmi_domain* d : b->members) d->steps += b->gsteps;
+      for (rwmi_domain* d : b->members) {
+        if (d->sort_every > 0 && d->hv.nw > 0) d->sorted_at = d->steps;  // every replay sorts at its start
+        d->steps += b->gsteps;
+      }
     }
   }
   if (left > 0) {
-    rwmi_status st = batch_enqueue_group(b, left);
+    rwmi_status st = batch_enqueue_group(b, left, false);
     if (st != RWMI_OK) return st;
     for (rwmi_domain* d : b->members) d->steps += left;
   }

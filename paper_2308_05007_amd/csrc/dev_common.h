@@ -92,12 +92,14 @@ struct DomView {
   const DevParticle* parts;
   const double* ctrl;             // 4 per control point: bx, by, bz, k
   const float* ctrl_f;            // the same in float (low-precision modes)
-  double* pose[2];                // per step parity: [2][np][6] (c, v) at t and t+1
+  double* pose[3];                // per step t, slot t mod 3: [2][np][6] (c, v) at t and t+1
   uint64_t* tstep;                // [0] steps completed before the current launch group
-  unsigned long long* mask[2];    // per step parity: coarse cull mask at P(t+1)
+  unsigned long long* mask[3];    // per step t, slot t mod 3: coarse cull mask at P(t+1)
   int32_t* wcell;                 // walker cell index
   void* woff;                     // walker offsets SoA [3][nw] (double or float)
   int32_t* wimg;                  // walker image counts SoA [3][nw]
+  int32_t* wid;                   // walker id held by slot i (Philox counter, read-back order)
+  int32_t* winv;                  // slot of walker id w (inverse of wid; built for read-outs)
   unsigned long long* counters;   // kCounters
   uint32_t* occ;                  // occupancy per node
 };
@@ -111,7 +113,14 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
 
 // Step t of a launch: the domain's step counter at the start of the launch
 // group plus the launch's offset k within the group.
-__device__ __forceinline__ uint64_t step_of(const DomView& V, uint32_t k) { return gp(V.tstep)[0] + k; }
+__device__ __forceinline__ uint64_t step_of(const DomView& V, int32_t k) {
+  return (uint64_t)((int64_t)gp(V.tstep)[0] + k);
+}
+
+// Slot of the pose table and cull mask of step t.  Three slots: one launch
+// writes those of step t+1 while its fluid blocks read step t's and its
+// walker blocks step t-1's.
+__device__ __forceinline__ int pose_slot(uint64_t t) { return (int)(t % 3ull); }
 
 // Work map of a multi-domain launch: block b of the grid belongs to domain d
 // with boff[d] <= b < boff[d + 1].

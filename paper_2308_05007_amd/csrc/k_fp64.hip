@@ -61,12 +61,42 @@ hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_
   const int64_t nbw = (nw + kRedChunk - 1) / kRedChunk;
   const int64_t nbn = (N + kRedChunk - 1) / kRedChunk;
   if (nbw > 0) {
+    k_ids_inverse<<<(unsigned)((nw + 255) / 256), 256, 0, s>>>(v, dom);
     if (prec == P64) k_mom_walkers<double><<<(unsigned)nbw, kRedThreads, 0, s>>>(v, dom, ref, pw);
     else k_mom_walkers<float><<<(unsigned)nbw, kRedThreads, 0, s>>>(v, dom, ref, pw);
   }
   if (prec == P64) k_mom_nodes<double><<<(unsigned)nbn, kRedThreads, 0, s>>>(v, dom, pn);
   else k_mom_nodes<float><<<(unsigned)nbn, kRedThreads, 0, s>>>(v, dom, pn);
   k_mom_final<<<1, 64, 0, s>>>(v, dom, pw, nbw, pn, nbn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(int prec, const DomView* views, int dom, int64_t nw, const SortScratch& sc, hipStream_t s) {
+  if (nw <= 0) return hipSuccess;
+  const unsigned gw = (unsigned)((nw + 255) / 256);
+  const int64_t nc = sc.nbins * kSortCopies;
+  k_fill_u32<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(sc.hist, nc, 0u);
+  k_sort_rank<<<gw, 256, 0, s>>>(views, dom, sc.hist, sc.bin, sc.rank);
+  const int64_t tiles = (nc + kScanTile - 1) / kScanTile;
+  uint32_t* tsum = sc.hist + nc;  // tile sums after the counters
+  k_scan_tiles<<<(unsigned)tiles, kScanThreads, 0, s>>>(sc.hist, nc, tsum);
+  k_scan_sums<<<1, kScanThreads, 0, s>>>(tsum, tiles);
+  k_scan_add<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(sc.hist, nc, tsum);
+  if (prec == P64) {
+    k_sort_scatter<double><<<gw, 256, 0, s>>>(views, dom, sc.hist, sc.bin, sc.rank, sc.cell, (double*)sc.off, sc.img,
+                                               sc.wid);
+    k_sort_back<double><<<gw, 256, 0, s>>>(views, dom, sc.cell, (const double*)sc.off, sc.img, sc.wid);
+  } else {
+    k_sort_scatter<float><<<gw, 256, 0, s>>>(views, dom, sc.hist, sc.bin, sc.rank, sc.cell, (float*)sc.off, sc.img,
+                                              sc.wid);
+    k_sort_back<float><<<gw, 256, 0, s>>>(views, dom, sc.cell, (const float*)sc.off, sc.img, sc.wid);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ids_identity(const DomView* views, int dom, int64_t nw, hipStream_t s) {
+  if (nw <= 0) return hipSuccess;
+  k_ids_identity<<<(unsigned)((nw + 255) / 256), 256, 0, s>>>(views, dom);
   return hipGetLastError();
 }
 

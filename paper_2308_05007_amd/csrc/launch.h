@@ -37,6 +37,22 @@ hipError_t launch_occupancy(const DomView* v, int dom, uint32_t* occ, int64_t N,
 hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_t nw, const double* ref,
                           double* pw, double* pn, double* out, hipStream_t s);
 hipError_t launch_advance(const DomView* views, int nd, uint32_t n, hipStream_t s);
+
+// Scratch of the walker sort of one domain (device memory owned by the domain).
+struct SortScratch {
+  uint32_t* hist;  // 16 counters per bin (counts, then starts), then the scan's tile sums
+  uint32_t* bin;   // [nw]
+  uint32_t* rank;  // [nw]
+  int32_t* cell;   // [nw]
+  void* off;       // [3][nw] in the walker offset type
+  int32_t* img;    // [3][nw]
+  int32_t* wid;    // [nw]
+  int64_t nbins;
+};
+// Regroup the walkers of domain `dom` of `views` by coarse mask block.
+hipError_t launch_sort(int prec, const DomView* views, int dom, int64_t nw, const SortScratch& sc, hipStream_t s);
+// Slot i holds walker i (after seeding).
+hipError_t launch_ids_identity(const DomView* views, int dom, int64_t nw, hipStream_t s);
 hipError_t launch_normals(uint64_t seed, uint32_t t, uint32_t purpose, int64_t n, double* z, hipStream_t s);
 
 }  // namespace rwmi

@@ -50,8 +50,10 @@ __device__ __forceinline__ double interval_gap(int periodic, int L, int lo, int 
 
 // Cull the particles at pose P(t) for the node range [n0, n1] of a block and
 // stage their poses and control points in LDS.  Called by every thread of
-// the block; wave 0 computes the poses.
-__device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32_t n1, uint64_t t, BlockParticles& sp) {
+// the block; wave 0 takes the poses from the pose table of step t (written by
+// the prologue of an earlier launch) or, with from_table false, computes them.
+__device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32_t n1, uint64_t t, BlockParticles& sp,
+                                           bool from_table) {
   const int nx = V.n[0], ny = V.n[1];
   int lo[3], hi[3];
   {
@@ -71,7 +73,16 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
     double pc[3] = {0, 0, 0}, pv[3] = {0, 0, 0};
     if (tid < V.np) {
       const DevParticle& P = V.parts[tid];
-      particle_pose(P, t, pc, pv);
+      if (from_table) {
+        const auto pt = gp((const double*)V.pose[pose_slot(t)]) + 6 * tid;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          pc[a] = pt[a];
+          pv[a] = pt[3 + a];
+        }
+      } else {
+        particle_pose(P, t, pc, pv);
+      }
       double g2 = 0.0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -211,7 +222,7 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   const uint32_t N = (uint32_t)V.N;
   const uint32_t n0 = lb * BS;
   const uint32_t n1 = (n0 + BS - 1 < N) ? n0 + BS - 1 : N - 1;
-  if (V.np > 0) cull_block(V, n0, n1, t, sp);
+  if (V.np > 0) cull_block(V, n0, n1, t, sp, true);
   else if (threadIdx.x == 0) sp.cnt = 0;
   __syncthreads();
 

@@ -25,16 +25,16 @@ struct ProLds {
   double r[kMaxParticles];
 };
 
-// Walker-side prologue of step t (parity par = t & 1): block 0 of a domain
-// writes the poses P(t), P(t+1) into pose[par]; block lb builds mask blocks
-// [lb blockDim, (lb + 1) blockDim) of the coarse mask at P(t+1) in mask[par]:
+// Prologue of step t (table slot t mod 3): block 0 of a domain writes the
+// poses P(t), P(t+1) into pose[slot]; block lb builds mask blocks
+// [lb blockDim, (lb + 1) blockDim) of the coarse mask at P(t+1) in mask[slot]:
 // bit p of a coarse block is set when the sphere (c_p(t+1), rb_p + 1/2) meets
 // the block (extended to infinity beyond wall planes).  Every thread of the
 // block calls it.
 __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_t t, ProLds& L) {
   double (&sc)[kMaxParticles][3] = L.c;
   double (&sr)[kMaxParticles] = L.r;
-  const int par = (int)(t & 1ull);
+  const int ps = pose_slot(t);
   const int tid = threadIdx.x;
   if (tid < V.np) {
     const DevParticle& P = V.parts[tid];
@@ -42,8 +42,8 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
     particle_pose(P, t, c0, v0);
     particle_pose(P, t + 1, c1, v1);
     if (lb == 0) {
-      double* pt = V.pose[par] + 6 * tid;
-      double* pn = V.pose[par] + 6 * (V.np + tid);
+      double* pt = V.pose[ps] + 6 * tid;
+      double* pn = V.pose[ps] + 6 * (V.np + tid);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         pt[a] = c0[a];
@@ -57,7 +57,7 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
     sr[tid] = P.maskr;
   }
   __syncthreads();
-  if (V.nw == 0 || V.np == 0) return;
+  if (V.nw == 0 || V.np == 0) return;  // the fluid needs only the poses
   const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
   const int64_t cb = (int64_t)lb * blockDim.x + tid;
   if (cb >= nmb) return;
@@ -84,7 +84,7 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
     const double r = sr[p];
     if (g2 <= r * r * (1.0 + 1e-9) + 1e-9) bits |= (1ull << p);
   }
-  V.mask[par][cb] = bits;
+  V.mask[ps][cb] = bits;
 }
 
 }  // namespace rwmi

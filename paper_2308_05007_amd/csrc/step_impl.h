@@ -1,11 +1,15 @@
-// The fused step launch: walker blocks of step t-1, prologue blocks of step t
-// and fluid blocks of step t in one grid (roles from step_map.h).  A launch
-// group of n steps is n + 1 launches j = 0..n: launch j carries the fluid
-// update and the prologue of step t0 + j (j < n) and the walkers of step
-// t0 + j - 1 (j >= 1), t0 being the domain's step counter at the start of
-// the group.  The walkers of step t read u(t) and the poses/mask of step t,
-// written by the previous launch into the buffers of parity t & 1, while the
-// current launch writes those of parity (t + 1) & 1.
+// The fused step launch: walker blocks of step t-1, fluid blocks of step t
+// and prologue blocks of step t+1 in one grid (roles from step_map.h), t being
+// the domain's step counter at the start of the launch group plus the launch
+// index j.  A group of n steps is a prologue-only launch (j = -1, prologue of
+// t0) and then launches j = 0..n: fluid of t0 + j (j < n), prologue of
+// t0 + j + 1 (j < n - 1), walkers of t0 + j - 1 (j >= 1).
+//
+// No role reads what another role of the same launch writes.  The fluid of
+// step t reads f of parity t & 1, the poses of slot t mod 3 and writes f, u of
+// parity (t + 1) & 1 and t & 1; the walkers of step t - 1 read u of parity
+// (t - 1) & 1 and the poses/mask of slot (t - 1) mod 3; the prologue writes
+// slot (t + 1) mod 3.
 #pragma once
 #include "lbm_impl.h"
 #include "pro_impl.h"
@@ -33,7 +37,7 @@ __global__ void __launch_bounds__(BS) k_step(StepArgs a) {
   const int lb = idx - bo[d];
   const uint64_t t = step_of(V, a.j);
   if (role == kRoleWalk) walk_block<P, BS>(V, lb, t - 1, lds.walk);
-  else if (role == kRolePro) prologue_block(V, lb, t, lds.pro);
+  else if (role == kRolePro) prologue_block(V, lb, t + 1, lds.pro);
   else fluid_block<P, BS>(V, (uint32_t)lb, t, (a.flags & 2) != 0, lds.fluid);
 }
 

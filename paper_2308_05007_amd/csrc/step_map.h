@@ -1,11 +1,11 @@
 // Block roles of the fused step launch (host and device).
 //
 // One launch of a step group carries three kinds of blocks: the walkers of
-// step t-1 (fast path, then the block's own near-surface walkers), the
-// walker-side prologue of step t (particle poses, coarse cull mask) and the
-// fluid update of step t.  They read only what earlier launches wrote and
-// write disjoint buffers (velocity, pose and mask are double-buffered by step
-// parity), so they need no ordering among themselves.
+// step t-1 (fast path, then the block's own near-surface walkers), the fluid
+// update of step t and the prologue of step t+1 (particle poses, coarse cull
+// mask).  They read only what earlier launches wrote and write disjoint
+// buffers (velocity double-buffered by step parity, pose table and mask by
+// step mod 3), so they need no ordering among themselves.
 //
 // Hardware block i runs on XCD i mod 8.  With the XCD-aware map every XCD
 // receives a contiguous run of the fluid blocks (neighbouring nodes share its
@@ -39,7 +39,7 @@ struct StepArgs {
   int nd;
   int nb[kRoles];       // blocks per role over all domains
   int flags;            // kFlagXcd | kFlagNontemporal
-  uint32_t j;           // launch index within the group
+  int32_t j;            // launch index within the group (-1: the prologue-only launch)
 };
 
 // Share of XCD x of n items dealt in contiguous runs: count and first item.

@@ -1,9 +1,9 @@
 // Random walkers (Eq. 2) on the lattice velocity field, one block function
 // run by the walker blocks of the fused step launch.
 //
-// Fast path (one thread per walker): trilinear interpolation of u(t) between
-// node centres (x, then y, then z), three normals from the Philox block
-// (w, t, 0, 0), step dl = u + z sqrt(2D).  The coarse cull mask of the
+// Fast path (one thread per walker slot): trilinear interpolation of u(t)
+// between node centres (x, then y, then z), three normals from the Philox
+// block (id, t, 0, 0) of the walker id the slot holds, step dl = u + z sqrt(2D).  The coarse cull mask of the
 // particles at t+1 is looked up at the start and end cells; a walker with no
 // candidate particle at either end can be neither type II nor IV (Sec.
 // 2.4.2), so it is moved here (walls, renormalisation).  Walkers with a
@@ -53,14 +53,14 @@ __device__ __forceinline__ int64_t mask_index(const DomView& V, const int c[3], 
   return b[0] + V.mb[0] * (b[1] + V.mb[1] * b[2]);
 }
 
-// Particle pose at t+1 from the pose table.
-__device__ __forceinline__ gconst<double> pose_next(const DomView& V, int par, int p) {
-  return gp((const double*)V.pose[par]) + 6 * (V.np + p);
+// Particle pose at t+1 from the pose table of step t.
+__device__ __forceinline__ gconst<double> pose_next(const DomView& V, int ps, int p) {
+  return gp((const double*)V.pose[ps]) + 6 * (V.np + p);
 }
 
 template <typename R>
-__device__ __forceinline__ R particle_M_at(const DomView& V, int par, int p, const int c[3], const R x[3]) {
-  const auto pc = pose_next(V, par, p);
+__device__ __forceinline__ R particle_M_at(const DomView& V, int ps, int p, const int c[3], const R x[3]) {
+  const auto pc = pose_next(V, ps, p);
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
@@ -69,8 +69,8 @@ __device__ __forceinline__ R particle_M_at(const DomView& V, int par, int p, con
 }
 
 template <typename R>
-__device__ __forceinline__ void particle_grad_at(const DomView& V, int par, int p, const int c[3], const R x[3], R g[3]) {
-  const auto pc = pose_next(V, par, p);
+__device__ __forceinline__ void particle_grad_at(const DomView& V, int ps, int p, const int c[3], const R x[3], R g[3]) {
+  const auto pc = pose_next(V, ps, p);
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
@@ -83,8 +83,8 @@ __device__ __forceinline__ void particle_grad_at(const DomView& V, int par, int 
 // there (bounding-radius lemma), so the result is that of testing all.
 // Is (c + x) within the sphere (c_p(t+1), rb_p + 1/2) of particle p?
 template <typename R>
-__device__ __forceinline__ bool in_sphere(const DomView& V, int par, int p, const int c[3], const R x[3]) {
-  const auto pc = pose_next(V, par, p);
+__device__ __forceinline__ bool in_sphere(const DomView& V, int ps, int p, const int c[3], const R x[3]) {
+  const auto pc = pose_next(V, ps, p);
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
@@ -93,19 +93,19 @@ __device__ __forceinline__ bool in_sphere(const DomView& V, int par, int p, cons
 }
 
 template <typename R>
-__device__ __forceinline__ unsigned long long mask_at(const DomView& V, int par, const int c[3], const R x[3]) {
-  return gp((const unsigned long long*)V.mask[par])[mask_index<R>(V, c, x)];
+__device__ __forceinline__ unsigned long long mask_at(const DomView& V, int ps, const int c[3], const R x[3]) {
+  return gp((const unsigned long long*)V.mask[ps])[mask_index<R>(V, c, x)];
 }
 
 template <typename R>
-__device__ __forceinline__ int inside_any(const DomView& V, int par, const int c[3], const R x[3]) {
+__device__ __forceinline__ int inside_any(const DomView& V, int ps, const int c[3], const R x[3]) {
   // only the particles whose mask bit is set for the point's coarse block can
   // contain it; visit them in ascending index order
-  unsigned long long bits = mask_at<R>(V, par, c, x);
+  unsigned long long bits = mask_at<R>(V, ps, c, x);
   while (bits) {
     const int p = __ffsll((long long)bits) - 1;
     bits &= bits - 1ull;
-    const auto pc = pose_next(V, par, p);
+    const auto pc = pose_next(V, ps, p);
     const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
     const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
     const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
@@ -121,12 +121,12 @@ __device__ __forceinline__ int inside_any(const DomView& V, int par, const int c
 // Algorithm 1 on x(s) = a0 + s dir between s_out (M < 1) and s_in (M >= 1):
 // midpoint in s, converged when |M - 1| < 1e-3, at most imax evaluations.
 template <typename R>
-__device__ __forceinline__ bool bisect(const DomView& V, int par, int p, const int c[3], const R a0[3], const R dir[3],
+__device__ __forceinline__ bool bisect(const DomView& V, int ps, int p, const int c[3], const R a0[3], const R dir[3],
                                        R s_out, R s_in, int imax, R& s_res) {
   for (int it = 1; it <= imax; ++it) {
     const R sm = (R)0.5 * (s_out + s_in);
     const R x[3] = {a0[0] + sm * dir[0], a0[1] + sm * dir[1], a0[2] + sm * dir[2]};
-    const R m = particle_M_at<R>(V, par, p, c, x);
+    const R m = particle_M_at<R>(V, ps, p, c, x);
     if (fabs(m - (R)1) < (R)1e-3) {
       s_res = sm;
       return true;
@@ -230,7 +230,8 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
   bool refl = false;
   R dl[3] = {(R)0, (R)0, (R)0};
   if (active) {
-    const int par = (int)(t & 1ull);
+    const int par = (int)(t & 1ull);  // velocity buffer of step t
+    const int ps = pose_slot(t);        // pose table and cull mask of step t
     const int nx = V.n[0], ny = V.n[1];
     const uint32_t lc = (uint32_t)gp(V.wcell)[w];
     const uint32_t q1 = fdiv(lc, V.dx);
@@ -257,7 +258,9 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
       b0[a] = b;
       b1[a] = b1a;
     }
-    const auto u4 = gp((const U*)V.u4[par]);
+    // one vector load per corner: (ux, uy, uz, rho) of a node is 4 U
+    using U4v = U __attribute__((ext_vector_type(4)));
+    const auto u4 = gp((const U4v*)V.u4[par]);
     R Ui[3];
     {
       R v[2][2][3];
@@ -266,12 +269,10 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
 #pragma unroll
         for (int yy = 0; yy < 2; ++yy) {
           const int y = yy ? b1[1] : b0[1], z = zz ? b1[2] : b0[2];
-          const int64_t i0 = lin(V, b0[0], y, z), i1 = lin(V, b1[0], y, z);
+          const U4v lo4 = u4[lin(V, b0[0], y, z)], hi4 = u4[lin(V, b1[0], y, z)];
+          const R lo[3] = {(R)lo4.x, (R)lo4.y, (R)lo4.z}, hi[3] = {(R)hi4.x, (R)hi4.y, (R)hi4.z};
 #pragma unroll
-          for (int cpt = 0; cpt < 3; ++cpt) {
-            const R lo = (R)u4[4 * i0 + cpt], hi = (R)u4[4 * i1 + cpt];
-            v[zz][yy][cpt] = ((R)1 - wt[0]) * lo + wt[0] * hi;
-          }
+          for (int cpt = 0; cpt < 3; ++cpt) v[zz][yy][cpt] = ((R)1 - wt[0]) * lo[cpt] + wt[0] * hi[cpt];
         }
 #pragma unroll
       for (int cpt = 0; cpt < 3; ++cpt) {
@@ -281,7 +282,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
       }
     }
     // Brownian step (Eq. 2 with dt = 1)
-    const U4 r = philox4x32_10((uint32_t)w, (uint32_t)t, 0u, 0u, V.key0, V.key1);
+    const U4 r = philox4x32_10((uint32_t)gp(V.wid)[w], (uint32_t)t, 0u, 0u, V.key0, V.key1);
     R xf[3];
     if constexpr (P == P64) {
       double z0, z1, z2;
@@ -303,11 +304,11 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
       // neither type II nor IV (M < 1 outside rb); candidates come from the
       // coarse mask, the exact sphere test decides
       const R zero3[3] = {(R)0, (R)0, (R)0};
-      unsigned long long bits = mask_at<R>(V, par, c, zero3) | mask_at<R>(V, par, c, xf);
+      unsigned long long bits = mask_at<R>(V, ps, c, zero3) | mask_at<R>(V, ps, c, xf);
       while (bits && !queue) {
         const int p = __ffsll((long long)bits) - 1;
         bits &= bits - 1ull;
-        queue = in_sphere<R>(V, par, p, c, o) || in_sphere<R>(V, par, p, c, xf);
+        queue = in_sphere<R>(V, ps, p, c, o) || in_sphere<R>(V, ps, p, c, xf);
       }
     }
     if (!queue) {
@@ -324,11 +325,11 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] = o[a];
           } else if (V.np > 0) {
-            unsigned long long bits = mask_at<R>(V, par, c, xn);
+            unsigned long long bits = mask_at<R>(V, ps, c, xn);
             while (bits && !queue) {
               const int p = __ffsll((long long)bits) - 1;
               bits &= bits - 1ull;
-              queue = in_sphere<R>(V, par, p, c, xn);  // the reflected point may be inside a particle
+              queue = in_sphere<R>(V, ps, p, c, xn);  // the reflected point may be inside a particle
             }
             if (queue) refl = false;
           }
@@ -378,7 +379,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
 template <int P>
 __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const typename Store<P>::O dl[3]) {
   using R = typename Store<P>::O;
-  const int par = (int)(t & 1ull);
+  const int ps = pose_slot(t);
   const int nx = V.n[0], ny = V.n[1];
   const auto off = gp((const R*)V.woff);
   {
@@ -393,19 +394,19 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
       xf[a] = o[a] + dl[a];
       xn[a] = xf[a];
     }
-    const int jb = inside_any<R>(V, par, c, xf);
+    const int jb = inside_any<R>(V, ps, c, xf);
     if (jb >= 0) {
-      const int ja = inside_any<R>(V, par, c, o);
+      const int ja = inside_any<R>(V, ps, c, o);
       if (ja < 0) {
         // type IV: no-flux boundary, Algorithm 1 then Algorithm 2
         atomicAdd(&V.counters[kType4], 1ull);
         R s;
         bool done = false;
-        if (bisect<R>(V, par, jb, c, o, dl, (R)0, (R)1, V.max_bisect, s)) {
+        if (bisect<R>(V, ps, jb, c, o, dl, (R)0, (R)1, V.max_bisect, s)) {
           R xi[3], g[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) xi[a] = o[a] + s * dl[a];
-          particle_grad_at<R>(V, par, jb, c, xi, g);
+          particle_grad_at<R>(V, ps, jb, c, xi, g);
           const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
           if (gn > (R)0) {
             R nv[3], ti[3];
@@ -417,7 +418,7 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
             const R dt = (ti[0] * nv[0] + ti[1] * nv[1]) + ti[2] * nv[2];
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] = xi[a] + (ti[a] - ((R)2 * dt) * nv[a]);
-            if (inside_any<R>(V, par, c, xn) >= 0) {
+            if (inside_any<R>(V, ps, c, xn) >= 0) {
               atomicAdd(&V.counters[kReturned], 1ull);
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = o[a];
@@ -435,7 +436,7 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
         // sqrt(2D) half-ball on the outer side of the surface)
         atomicAdd(&V.counters[kType2], 1ull);
         R g[3];
-        particle_grad_at<R>(V, par, jb, c, xf, g);
+        particle_grad_at<R>(V, ps, jb, c, xf, g);
         const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
         bool fallback = true;
         if (gn > (R)0) {
@@ -446,17 +447,18 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
           for (;;) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) xe[a] = xf[a] + s * no[a];
-            if (!(particle_M_at<R>(V, par, jb, c, xe) >= (R)1) || !(s < lim)) break;
+            if (!(particle_M_at<R>(V, ps, jb, c, xe) >= (R)1) || !(s < lim)) break;
             s = (R)2 * s;
           }
-          if (particle_M_at<R>(V, par, jb, c, xe) < (R)1) {
+          if (particle_M_at<R>(V, ps, jb, c, xe) < (R)1) {
             R ss;
-            if (bisect<R>(V, par, jb, c, xf, no, s, (R)0, V.max_bisect, ss)) {
+            if (bisect<R>(V, ps, jb, c, xf, no, s, (R)0, V.max_bisect, ss)) {
               R xs[3];
 #pragma unroll
               for (int a = 0; a < 3; ++a) xs[a] = xf[a] + ss * no[a];
-              const U4 r1 = philox4x32_10((uint32_t)w, (uint32_t)t, 1u, 0u, V.key0, V.key1);
-              const U4 r2 = philox4x32_10((uint32_t)w, (uint32_t)t, 2u, 0u, V.key0, V.key1);
+              const uint32_t id = (uint32_t)gp(V.wid)[w];
+              const U4 r1 = philox4x32_10(id, (uint32_t)t, 1u, 0u, V.key0, V.key1);
+              const U4 r2 = philox4x32_10(id, (uint32_t)t, 2u, 0u, V.key0, V.key1);
               R v[3];
               if constexpr (P == P64) {
                 double v0, v1, v2;
@@ -487,7 +489,7 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = xe[a];
             }
-            bool bad = inside_any<R>(V, par, c, xn) >= 0;
+            bool bad = inside_any<R>(V, ps, c, xn) >= 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
               if (bad || !V.bc[a]) continue;
@@ -499,7 +501,7 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = xe[a];
             }
-            fallback = inside_any<R>(V, par, c, xn) >= 0;
+            fallback = inside_any<R>(V, ps, c, xn) >= 0;
           }
         }
         if (fallback) {
@@ -516,7 +518,7 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
     }
     if (reflect_walls<R>(V, c, xn)) {
       atomicAdd(&V.counters[kWallReflect], 1ull);
-      if (outside_walls<R>(V, c, xn) || inside_any<R>(V, par, c, xn) >= 0) {
+      if (outside_walls<R>(V, c, xn) || inside_any<R>(V, ps, c, xn) >= 0) {
         atomicAdd(&V.counters[kReturned], 1ull);
 #pragma unroll
         for (int a = 0; a < 3; ++a) xn[a] = o[a];

@@ -202,6 +202,43 @@ def test_launch_shapes_match_oracle(orc, B, bs, flags):
     compare(o, g, f=False)
 
 
+@pytest.mark.parametrize("every", [1, 3])
+def test_walker_regrouping_keeps_oracle_results(orc, B, every):
+    """Regrouping the walkers by coarse block (here before every launch, or
+    every third) moves them between slots; ids travel with them, so the FP64
+    results by id still equal the oracle's."""
+    cfg = W.config_tiny(n=(20, 9, 14), bc=("periodic", "wall", "periodic"), n_particles=2, n_walkers=2500,
+                        seed=13, spread=1.5)
+    o, g = _pair(orc, B, cfg)
+    g.set("sort_every", every)
+    for chunk in (4, 7):
+        o.step(chunk)
+        g.step(chunk)
+    compare(o, g, f=False)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_walker_order_never_shows(B, prec):
+    """Moments, walkers and counters are identical whether the walkers are
+    never regrouped, regrouped every step or every 5 steps, eager or from a
+    graph: every read-out goes by walker id."""
+    cfg = W.config_tiny(n=(16, 12, 10), bc=("periodic", "wall", "periodic"), n_particles=3, n_walkers=4000,
+                        seed=17, spread=1.5, precision=prec)
+    res = []
+    for every, graph in ((0, 0), (1, 0), (5, 1)):
+        d = B.build_domain(cfg)
+        d.set("sort_every", every)
+        d.set("use_graph", graph)
+        d.step(23)
+        m = d.moments()
+        res.append((m["sum"].tolist(), m["sumsq"].tolist(), m["counters"], d.walkers(), d.occupancy()))
+        d.close()
+    for r in res[1:]:
+        assert r[0] == res[0][0] and r[1] == res[0][1] and r[2] == res[0][2]
+        assert all(np.array_equal(x, y) for x, y in zip(r[3], res[0][3]))
+        assert np.array_equal(r[4], res[0][4])
+
+
 def test_graph_replay_equals_eager(B):
     cfg = W.config_tiny(n=(9, 4, 11), bc=("periodic", "wall", "periodic"), n_walkers=500, n_particles=2, seed=5)
     a = B.build_domain(cfg)

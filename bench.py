@@ -66,26 +66,28 @@ def walker_bytes_per_step(prec):
     return 2 * (4 + 3 * (8 if prec == "fp64" else 4))
 
 
-def kernel_source_hash():
+def kernel_source_hash(prec):
+    """Hash of the sources the step kernel of this precision is built from."""
     h = hashlib.sha256()
-    for f in ("step_impl.h", "step_map.h", "lbm_impl.h", "walk_impl.h", "pro_impl.h", "dev_common.h", "k_lowp.hip",
-              "k_fp64.hip"):
+    unit = "k_fp64.hip" if prec == "fp64" else "k_lowp.hip"
+    for f in ("step_impl.h", "step_map.h", "lbm_impl.h", "walk_impl.h", "pro_impl.h", "dev_common.h", "launch.h",
+              unit):
         with open(os.path.join(ROOT, "paper_2308_05007_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(workload_key):
-    """HBM bytes per launch of the fluid kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "fluid_traffic.json")
+def pmc_traffic(workload_key, prec):
+    """HBM bytes per full step launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "step_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
     e = d.get(workload_key)
-    if not e or e.get("kernel_source_sha256_16") != kernel_source_hash():
+    if not e or e.get("kernel_source_sha256_16") != kernel_source_hash(prec):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -158,7 +160,7 @@ def bench_plain(args):
     fb, wb = fluid_nodes(cfg) * fluid_bytes_per_node(prec), nw * walker_bytes_per_step(prec)
     bytes_launch = fb + wb
     achieved = (fluid_launches * fb + walker_launches * wb) / (ms_total / 1e3) / 1e9
-    traffic = pmc_traffic(key)
+    traffic = pmc_traffic(key, prec)
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": round(dt / steps * 1e3, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -174,6 +176,7 @@ def bench_plain(args):
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                      "timed_launches": launches, "timed_every": args.timing_every},
         "counters": mom["counters"],
+        "near_surface_per_step": round(mom["near_surface"] / max(mom["step"], 1), 1),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, seconds=args.cpu_seconds)

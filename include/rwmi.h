@@ -148,6 +148,8 @@ typedef struct {
   uint64_t refill_fallback; /* refill found no admissible point */
   uint64_t returned_to_origin; /* narrow-gap rule: walker kept its position */
   uint64_t wall_reflect;    /* walkers reflected at a wall */
+  uint64_t near_surface;    /* walker steps that took the near-surface path (a cost
+                               diagnostic: it depends on the culling, not a result) */
 } rwmi_moments;
 
 typedef struct rwmi_domain rwmi_domain;
@@ -235,6 +237,10 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles
  *                            writes f* and (u, rho) with non-temporal stores
  *   RWMI_KEY_SORT_EVERY      regroup the walkers by coarse block (4^3 nodes) every this
  *                            many steps for memory locality (default 64, 0 = never)
+ *   RWMI_KEY_STREAMING       1: two lattices (pull from one, write the other); 2: one
+ *                            lattice streamed in place.  Default: in place while the 19
+ *                            distributions take at most 192 MB, else two lattices.
+ *                            Only before the first step (ESTATE after); resets f to f^eq
  * Results never depend on the block size, flags or sort interval: walker ids
  * travel with the walkers and every read-out is by id. */
 enum {
@@ -243,7 +249,8 @@ enum {
   RWMI_KEY_BLOCK = 3,
   RWMI_KEY_TIMING = 5,
   RWMI_KEY_STEP_FLAGS = 6,
-  RWMI_KEY_SORT_EVERY = 7
+  RWMI_KEY_SORT_EVERY = 7,
+  RWMI_KEY_STREAMING = 8
 };
 rwmi_status rwmi_debug_set(rwmi_domain* dom, int32_t key, int64_t value);
 

@@ -18,7 +18,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: 
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 MOTION = {"static": 0, "sinusoid": 1, "const_vel": 2}
 SEED_KIND = {"uniform": 0, "gaussian": 1, "band": 2, "explicit": 3}
-KEY = {"max_bisect": 1, "use_graph": 2, "block": 3, "timing": 5, "step_flags": 6, "sort_every": 7}
+KEY = {"max_bisect": 1, "use_graph": 2, "block": 3, "timing": 5, "step_flags": 6, "sort_every": 7, "streaming": 8}
 MAX_PARTICLES = 64
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -50,7 +50,7 @@ class Moments(C.Structure):
                 ("mass", C.c_double), ("momentum", C.c_double * 3), ("fluid_u", C.c_double * 3),
                 ("particle_v", C.c_double * 3), ("solid_volume", C.c_double), ("type2", C.c_uint64),
                 ("type4", C.c_uint64), ("bisect_fail", C.c_uint64), ("refill_fallback", C.c_uint64),
-                ("returned_to_origin", C.c_uint64), ("wall_reflect", C.c_uint64)]
+                ("returned_to_origin", C.c_uint64), ("wall_reflect", C.c_uint64), ("near_surface", C.c_uint64)]
 
 
 # name -> (restype, argtypes); the full exported surface of include/rwmi.h
@@ -313,7 +313,8 @@ class Domain:
                     particle_v=np.array(m.particle_v[:]), solid_volume=m.solid_volume,
                     counters=dict(type2=int(m.type2), type4=int(m.type4), bisect_fail=int(m.bisect_fail),
                                   refill_fallback=int(m.refill_fallback),
-                                  returned_to_origin=int(m.returned_to_origin), wall_reflect=int(m.wall_reflect)))
+                                  returned_to_origin=int(m.returned_to_origin), wall_reflect=int(m.wall_reflect)),
+                    near_surface=int(m.near_surface))
 
     def occupancy(self):
         ns = np.empty(self.N, np.uint32)

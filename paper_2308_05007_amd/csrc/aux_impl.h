@@ -278,10 +278,11 @@ __device__ __forceinline__ uint32_t walker_bin(const DomView& V, int32_t cell) {
   return x / kMaskBlock + (uint32_t)V.mb[0] * (y / kMaskBlock + (uint32_t)V.mb[1] * (z / kMaskBlock));
 }
 
-// Every bin has kSortCopies counters (key-major: counter key * kSortCopies +
-// copy), a block using copy blockIdx mod kSortCopies, so that the walkers of
-// a dense bin do not all queue on one address; the scan over the key-major
-// counters still keeps each bin contiguous.
+// Every bin has kSortCopies counters, stored copy-major (counter copy * nbins
+// + bin, so the copies of a bin sit in different cache lines); a block uses
+// copy blockIdx mod kSortCopies, so that the walkers of a dense bin do not
+// all queue on one address.  The starts are then taken bin by bin: bin totals,
+// exclusive scan over the bins, then the copies of each bin in order.
 constexpr int kSortCopies = 16;
 
 // bin[w] (its counter) and rank[w] (position among the walkers of that
@@ -291,8 +292,8 @@ __global__ void k_sort_rank(const DomView* __restrict__ views, int dom, uint32_t
   const DomView& V = views[dom];
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = w < V.nw;
-  const uint32_t key =
-      active ? walker_bin(V, gp(V.wcell)[w]) * kSortCopies + (uint32_t)(blockIdx.x % kSortCopies) : 0u;
+  const uint32_t nbins = (uint32_t)V.mb[0] * (uint32_t)V.mb[1] * (uint32_t)V.mb[2];
+  const uint32_t key = active ? (uint32_t)(blockIdx.x % kSortCopies) * nbins + walker_bin(V, gp(V.wcell)[w]) : 0u;
   const int lane = threadIdx.x & 63;
   unsigned long long todo = __ballot(active);
   uint32_t r = 0;
@@ -370,6 +371,29 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t* __restrict
 __global__ void k_scan_add(uint32_t* __restrict__ a, int64_t n, const uint32_t* __restrict__ tsum) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) gp(a)[i] += gp(tsum)[i / kScanTile];
+}
+
+// total[b] = sum over the copies of bin b.
+__global__ void k_bin_totals(const uint32_t* __restrict__ cnt, int64_t nbins, uint32_t* __restrict__ total) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  uint32_t s = 0;
+#pragma unroll
+  for (int c = 0; c < kSortCopies; ++c) s += gp(cnt)[c * nbins + b];
+  gp(total)[b] = s;
+}
+
+// Counts of the copies of bin b become their starts, from the bin's start.
+__global__ void k_bin_starts(uint32_t* __restrict__ cnt, int64_t nbins, const uint32_t* __restrict__ start) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  uint32_t run = gp(start)[b];
+#pragma unroll
+  for (int c = 0; c < kSortCopies; ++c) {
+    const uint32_t k = gp(cnt)[c * nbins + b];
+    gp(cnt)[c * nbins + b] = run;
+    run += k;
+  }
 }
 
 // Scatter every walker to slot start[bin] + rank in the scratch arrays.

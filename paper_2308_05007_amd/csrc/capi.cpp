@@ -34,6 +34,17 @@ struct Alloc {
 };
 
 size_t elem_size(int prec) { return prec == RWMI_FP64 ? 8 : (prec == RWMI_FP32 ? 4 : 2); }
+
+// One lattice streamed in place while the distributions fit in a budget that
+// the memory-side cache (256 MB on this part) can hold beside the velocity
+// and walkers: then the in-place pattern runs from that cache.  Larger
+// lattices keep two lattices, whose pull pattern streams from HBM a little
+// faster than the in-place pattern does.
+constexpr uint64_t kInPlaceMaxBytes = 192ull << 20;
+bool default_inplace(const rwmi_domain_desc& s) {
+  const uint64_t N = (uint64_t)s.n[0] * s.n[1] * s.n[2];
+  return 19 * N * elem_size(s.precision) <= kInPlaceMaxBytes;
+}
 size_t u_size(int prec) { return prec == RWMI_FP64 ? 8 : 4; }
 size_t off_size(int prec) { return prec == RWMI_FP64 ? 8 : 4; }
 
@@ -98,8 +109,9 @@ struct rwmi_batch {
   std::vector<rwmi_domain*> members;
   bool dirty = true;
   // per precision group: device arrays of views and work maps
-  struct Group {
+  struct Group {  // members of one precision and lattice layout
     int prec;
+    int inplace;
     std::vector<rwmi_domain*> doms;
     DomView* views = nullptr;
     int32_t* boff = nullptr;  // kRoles maps x (nd + 1)
@@ -330,6 +342,7 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturin
     a.nd = 1;
     launch_roles(b, j, n, a.nb);
     a.flags = d->flags;
+    a.inplace = d->hv.inplace;
     a.j = j;
     if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -366,13 +379,13 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   int32_t mb[3];
   const uint64_t nmb = (uint64_t)mask_blocks(*s, mb);
   uint64_t b = 0;
-  b += 2 * 19 * N * elem_size(p) + 8 * N * u_size(p);
+  b += (default_inplace(*s) ? 1 : 2) * 19 * N * elem_size(p) + 8 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
   b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 288 * n_particles + (n_particles ? 24 * nmb : 0);
   // walkers: cell, offsets, images, id and slot maps; sort scratch (bin, rank
   // and a second copy of the walker record) and the bin counts
   b += n_walkers * (4 + 3 * off_size(p) + 12 + 8);
-  b += n_walkers * (8 + 4 + 3 * off_size(p) + 12 + 4) + 64 * nmb + 4 * (16 * nmb / 4096 + 1);
+  b += n_walkers * (8 + 4 + 3 * off_size(p) + 12 + 4) + 68 * nmb + 4 * (nmb / 4096 + 1);
   b += 4 * N;  // occupancy
   b += 8 * (6 * ((n_walkers + 4095) / 4096) + 12 * ((N + 4095) / 4096) + 64);
   return b;
@@ -429,6 +442,7 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
   v.dmy = rwmi::make_fastdiv(v.mb[1]);
   v.N = N;
   v.prec = d->prec;
+  v.inplace = default_inplace(*s) ? 1 : 0;
   const double rho0 = s->rho0 > 0 ? s->rho0 : 1.0;
   v.tau = s->tau;
   v.omega = 1.0 / s->tau;
@@ -462,8 +476,9 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
   void *fA, *fB, *u4;
   uint64_t* tstep;
   unsigned long long* cnt;
+  fB = nullptr;
   if ((st = alloc_into(d, fA, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
-      (st = alloc_into(d, fB, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
+      (!v.inplace && (st = alloc_into(d, fB, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK) ||
       (st = alloc_into(d, u4, 8 * (size_t)N * u_size(d->prec))) != RWMI_OK ||
       (st = alloc_into(d, tstep, 16)) != RWMI_OK || (st = alloc_into(d, cnt, 8 * rwmi::kCounters)) != RWMI_OK ||
       (st = alloc_into(d, d->dv, sizeof(DomView))) != RWMI_OK ||
@@ -590,7 +605,7 @@ rwmi_status rwmi_seed_walkers(rwmi_domain* d, const rwmi_seed_desc* s, uint64_t 
   sc.nbins = (int64_t)d->hv.mb[0] * d->hv.mb[1] * d->hv.mb[2];
   if ((st = alloc_into(d, wcell, 4 * m1)) != RWMI_OK || (st = alloc_into(d, woff, 3 * osz * m1)) != RWMI_OK ||
       (st = alloc_into(d, wimg, 12 * m1)) != RWMI_OK || (st = alloc_into(d, wid, 4 * m1)) != RWMI_OK ||
-      (st = alloc_into(d, winv, 4 * m1)) != RWMI_OK || (st = alloc_into(d, sc.hist, 64 * sc.nbins + 4 * (16 * sc.nbins / 4096 + 1))) != RWMI_OK ||
+      (st = alloc_into(d, winv, 4 * m1)) != RWMI_OK || (st = alloc_into(d, sc.hist, 68 * sc.nbins + 4 * (sc.nbins / 4096 + 1))) != RWMI_OK ||
       (st = alloc_into(d, sc.bin, 4 * m1)) != RWMI_OK || (st = alloc_into(d, sc.rank, 4 * m1)) != RWMI_OK ||
       (st = alloc_into(d, sc.cell, 4 * m1)) != RWMI_OK || (st = alloc_into(d, sc.off, 3 * osz * m1)) != RWMI_OK ||
       (st = alloc_into(d, sc.img, 12 * m1)) != RWMI_OK || (st = alloc_into(d, sc.wid, 4 * m1)) != RWMI_OK)
@@ -812,6 +827,7 @@ rwmi_status rwmi_read_moments(rwmi_domain* d, rwmi_moments* out) {
   out->refill_fallback = u64[rwmi::kRefillFallback];
   out->returned_to_origin = u64[rwmi::kReturned];
   out->wall_reflect = u64[rwmi::kWallReflect];
+  out->near_surface = u64[rwmi::kNearSurface];
   return RWMI_OK;
 }
 
@@ -846,6 +862,24 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       d->flags = (int)value;
       drop_graph(d);
       return RWMI_OK;
+    case RWMI_KEY_STREAMING: {
+      if (value != 1 && value != 2) return fail(d, RWMI_EINVAL, "streaming must be 1 (two lattices) or 2 (in place)");
+      if (d->stepped || d->batch) return fail(d, RWMI_ESTATE, "the streaming layout is chosen before the first step");
+      const int ip = value == 2 ? 1 : 0;
+      if (ip == d->hv.inplace) return RWMI_OK;
+      if (!ip && !d->hv.fB) {
+        void* fB;
+        rwmi_status st;
+        if ((st = alloc_into(d, fB, 19 * (size_t)d->hv.N * elem_size(d->prec))) != RWMI_OK) return st;
+        d->hv.fB = fB;
+      }
+      d->hv.inplace = ip;
+      drop_graph(d);
+      if (upload_view(d) != RWMI_OK) return RWMI_EDEVICE;
+      HIPCHK(d, rwmi::launch_init(d->prec, d->dv, 0, d->hv.N, d->desc.u0, d->stream));
+      HIPCHK(d, hipStreamSynchronize(d->stream));
+      return RWMI_OK;
+    }
     case RWMI_KEY_SORT_EVERY:
       if (value < 0 || value > (1 << 20)) return fail(d, RWMI_EINVAL, "sort interval out of range");
       d->sort_every = (int)value;
@@ -990,11 +1024,13 @@ static rwmi_status batch_rebuild(rwmi_batch* b) {
   if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, RWMI_EDEVICE, "batch sync failed");
   batch_drop_graph(b);
   batch_free_groups(b);
-  for (int prec = 0; prec < 4; ++prec) {
+  for (int key = 0; key < 8; ++key) {
+    const int prec = key >> 1, ip = key & 1;
     rwmi_batch::Group g;
     g.prec = prec;
+    g.inplace = ip;
     for (rwmi_domain* d : b->members)
-      if (d->prec == prec) g.doms.push_back(d);
+      if (d->prec == prec && d->hv.inplace == ip) g.doms.push_back(d);
     if (g.doms.empty()) continue;
     const int nd = (int)g.doms.size();
     std::vector<DomView> hv(nd);
@@ -1050,6 +1086,7 @@ static rwmi_status batch_enqueue_group(rwmi_batch* b, uint32_t n, bool capturing
       a.nd = (int)g.doms.size();
       launch_roles(g.blocks, j, n, a.nb);
       a.flags = b->flags;
+      a.inplace = g.inplace;
       a.j = j;
       if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
       if (rwmi::launch_step(g.prec, b->bs, a, A) != hipSuccess) return bfail(b, RWMI_EDEVICE, "batch launch failed");

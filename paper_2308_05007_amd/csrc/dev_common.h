@@ -28,7 +28,7 @@ __host__ __device__ constexpr R weight(int i) {
 
 constexpr int kMaxParticles = 64;
 constexpr int kCounters = 8;
-enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect };
+enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect, kNearSurface };
 constexpr int kMaskBlock = 4;  // edge of a coarse block of the walker cull mask
 
 // Precision tags
@@ -78,6 +78,7 @@ struct DomView {
   int64_t N;         // nodes
   int64_t nw;        // walkers
   int32_t prec;
+  int32_t inplace;   // 1: one lattice streamed in place (slots by step parity); 0: two lattices
   int32_t has_force;
   int32_t max_bisect;
   uint32_t key0, key1;
@@ -86,8 +87,8 @@ struct DomView {
   float omega_f, tm_f, cfree_f, rho0_f, sD_f, F_f[3], halfF_f[3];
   double wu[3][2][3];             // wall velocity [axis][lo/hi][component]
   float wu_f[3][2][3];
-  void* fA;                       // distributions, parity 0 source
-  void* fB;                       // distributions, parity 1 source
+  void* fA;                       // distributions: parity 0 source (two lattices) or the lattice (in place)
+  void* fB;                       // distributions, parity 1 source (two lattices only)
   void* u4[2];                    // (ux, uy, uz, rho) per node, written by step t into [t & 1]
   const DevParticle* parts;
   const double* ctrl;             // 4 per control point: bx, by, bz, k
@@ -324,12 +325,15 @@ __device__ __forceinline__ double axis_disp<double>(int periodic, int L, int cel
 // +inf at a control point.
 template <typename R, typename PT>
 __device__ __forceinline__ R metaball_value(PT ctrl, int nc, R dx, R dy, R dz) {
+  // A control point at distance 0 gives k / 0 = +inf (k > 0), so M = +inf
+  // with no early exit; without a branch the loop unrolls and several control
+  // points are loaded at once.
   R M = (R)0;
+#pragma unroll 4
   for (int i = 0; i < nc; ++i) {
     const auto q = ctrl + 4 * i;
     const R rx = dx - (R)q[0], ry = dy - (R)q[1], rz = dz - (R)q[2];
     const R r2 = (rx * rx + ry * ry) + rz * rz;
-    if (r2 == (R)0) return (R)INFINITY;
     M = M + qdiv<R>((R)q[3], r2);
   }
   return M;
@@ -339,6 +343,7 @@ __device__ __forceinline__ R metaball_value(PT ctrl, int nc, R dx, R dy, R dz) {
 template <typename R, typename PT>
 __device__ __forceinline__ void metaball_grad(PT ctrl, int nc, R dx, R dy, R dz, R g[3]) {
   g[0] = g[1] = g[2] = (R)0;
+#pragma unroll 4
   for (int i = 0; i < nc; ++i) {
     const auto q = ctrl + 4 * i;
     const R rx = dx - (R)q[0], ry = dy - (R)q[1], rz = dz - (R)q[2];

@@ -9,10 +9,18 @@ namespace rwmi {
 hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
   const unsigned g = (unsigned)step_grid(a.nb, (a.flags & kFlagXcd) != 0);
   if (g == 0) return hipSuccess;
-  switch (bs) {
-    case 128: k_step<P64, 128><<<g, 128, 0, s>>>(a); break;
-    case 512: k_step<P64, 512><<<g, 512, 0, s>>>(a); break;
-    default: k_step<P64, 256><<<g, 256, 0, s>>>(a); break;
+  if (a.inplace) {
+    switch (bs) {
+      case 128: k_step<P64, 128, true><<<g, 128, 0, s>>>(a); break;
+      case 512: k_step<P64, 512, true><<<g, 512, 0, s>>>(a); break;
+      default: k_step<P64, 256, true><<<g, 256, 0, s>>>(a); break;
+    }
+  } else {
+    switch (bs) {
+      case 128: k_step<P64, 128, false><<<g, 128, 0, s>>>(a); break;
+      case 512: k_step<P64, 512, false><<<g, 512, 0, s>>>(a); break;
+      default: k_step<P64, 256, false><<<g, 256, 0, s>>>(a); break;
+    }
   }
   return hipGetLastError();
 }
@@ -74,14 +82,19 @@ hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_
 hipError_t launch_sort(int prec, const DomView* views, int dom, int64_t nw, const SortScratch& sc, hipStream_t s) {
   if (nw <= 0) return hipSuccess;
   const unsigned gw = (unsigned)((nw + 255) / 256);
-  const int64_t nc = sc.nbins * kSortCopies;
+  // hist: counters [kSortCopies][nbins], bin totals [nbins], scan tile sums
+  const int64_t nb = sc.nbins, nc = nb * kSortCopies;
+  uint32_t* total = sc.hist + nc;
+  uint32_t* tsum = total + nb;
+  const unsigned gb = (unsigned)((nb + 255) / 256);
+  const int64_t tiles = (nb + kScanTile - 1) / kScanTile;
   k_fill_u32<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(sc.hist, nc, 0u);
   k_sort_rank<<<gw, 256, 0, s>>>(views, dom, sc.hist, sc.bin, sc.rank);
-  const int64_t tiles = (nc + kScanTile - 1) / kScanTile;
-  uint32_t* tsum = sc.hist + nc;  // tile sums after the counters
-  k_scan_tiles<<<(unsigned)tiles, kScanThreads, 0, s>>>(sc.hist, nc, tsum);
+  k_bin_totals<<<gb, 256, 0, s>>>(sc.hist, nb, total);
+  k_scan_tiles<<<(unsigned)tiles, kScanThreads, 0, s>>>(total, nb, tsum);
   k_scan_sums<<<1, kScanThreads, 0, s>>>(tsum, tiles);
-  k_scan_add<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(sc.hist, nc, tsum);
+  k_scan_add<<<gb, 256, 0, s>>>(total, nb, tsum);
+  k_bin_starts<<<gb, 256, 0, s>>>(sc.hist, nb, total);
   if (prec == P64) {
     k_sort_scatter<double><<<gw, 256, 0, s>>>(views, dom, sc.hist, sc.bin, sc.rank, sc.cell, (double*)sc.off, sc.img,
                                                sc.wid);

@@ -5,21 +5,27 @@
 
 namespace rwmi {
 
-template <int P>
+template <int P, bool IP>
 static void step_bs(int bs, unsigned g, const StepArgs& a, hipStream_t s) {
   switch (bs) {
-    case 128: k_step<P, 128><<<g, 128, 0, s>>>(a); break;
-    case 512: k_step<P, 512><<<g, 512, 0, s>>>(a); break;
-    default: k_step<P, 256><<<g, 256, 0, s>>>(a); break;
+    case 128: k_step<P, 128, IP><<<g, 128, 0, s>>>(a); break;
+    case 512: k_step<P, 512, IP><<<g, 512, 0, s>>>(a); break;
+    default: k_step<P, 256, IP><<<g, 256, 0, s>>>(a); break;
   }
+}
+
+template <int P>
+static void step_layout(int bs, unsigned g, const StepArgs& a, hipStream_t s) {
+  if (a.inplace) step_bs<P, true>(bs, g, a, s);
+  else step_bs<P, false>(bs, g, a, s);
 }
 
 hipError_t launch_step_lowp(int prec, int bs, const StepArgs& a, hipStream_t s) {
   const unsigned g = (unsigned)step_grid(a.nb, (a.flags & kFlagXcd) != 0);
   if (g == 0) return hipSuccess;
-  if (prec == P32) step_bs<P32>(bs, g, a, s);
-  else if (prec == P16) step_bs<P16>(bs, g, a, s);
-  else step_bs<PB16>(bs, g, a, s);
+  if (prec == P32) step_layout<P32>(bs, g, a, s);
+  else if (prec == P16) step_layout<P16>(bs, g, a, s);
+  else step_layout<PB16>(bs, g, a, s);
   return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ hipError_t launch_advance(const DomView* views, int nd, uint32_t n, hipStream_t 
 
 // Scratch of the walker sort of one domain (device memory owned by the domain).
 struct SortScratch {
-  uint32_t* hist;  // 16 counters per bin (counts, then starts), then the scan's tile sums
+  uint32_t* hist;  // 16 counters per bin (copy-major), bin totals, scan tile sums
   uint32_t* bin;   // [nw]
   uint32_t* rank;  // [nw]
   int32_t* cell;   // [nw]

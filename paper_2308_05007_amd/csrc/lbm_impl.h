@@ -209,16 +209,67 @@ __device__ __forceinline__ void unroll(F&& f) {
   }
 }
 
-// Nodes [lb BS, (lb + 1) BS) of a domain through step t; nt selects
-// non-temporal stores.  Every thread of the block calls it.
-template <int P, int BS>
+// Lattice layouts of a step: two lattices, or one lattice streamed in place
+// at an even or an odd step (the slots a step reads and writes).
+enum Layout { kTwoLattices = 0, kInPlaceEven = 1, kInPlaceOdd = 2 };
+
+// Linear offsets to the six face neighbours of a fluid node (periodic wrap)
+// and whether the neighbour at -1 / +1 along an axis is a wall node.
+struct Nbr {
+  int dxm, dxp, dym, dyp, dzm, dzp;
+  bool wxl, wxh, wyl, wyh, wzl, wzh;
+};
+__device__ __forceinline__ Nbr node_nbr(const DomView& V, int x, int y, int z) {
+  const int nx = V.n[0], ny = V.n[1], nz = V.n[2];
+  const int sxy = nx * ny;
+  Nbr b;
+  b.dxm = x > 0 ? -1 : nx - 1;
+  b.dxp = x < nx - 1 ? 1 : -(nx - 1);
+  b.dym = y > 0 ? -nx : (ny - 1) * nx;
+  b.dyp = y < ny - 1 ? nx : -(ny - 1) * nx;
+  b.dzm = z > 0 ? -sxy : (nz - 1) * sxy;
+  b.dzp = z < nz - 1 ? sxy : -(nz - 1) * sxy;
+  b.wxl = V.bc[0] && x == 1;
+  b.wxh = V.bc[0] && x == nx - 2;
+  b.wyl = V.bc[1] && y == 1;
+  b.wyh = V.bc[1] && y == ny - 2;
+  b.wzl = V.bc[2] && z == 1;
+  b.wzh = V.bc[2] && z == nz - 2;
+  return b;
+}
+
+// Offset to the neighbour x - e_i and whether it is a wall node.
+template <int i>
+__device__ __forceinline__ void upstream_of(const Nbr& b, bool& wall, int& delta) {
+  constexpr int ex = kEx[i], ey = kEy[i], ez = kEz[i];
+  wall = false;
+  delta = 0;
+  if constexpr (ex == 1) { wall |= b.wxl; delta += b.dxm; } else if constexpr (ex == -1) { wall |= b.wxh; delta += b.dxp; }
+  if constexpr (ey == 1) { wall |= b.wyl; delta += b.dym; } else if constexpr (ey == -1) { wall |= b.wyh; delta += b.dyp; }
+  if constexpr (ez == 1) { wall |= b.wzl; delta += b.dzm; } else if constexpr (ez == -1) { wall |= b.wzh; delta += b.dzp; }
+}
+
+// Nodes [lb BS, (lb + 1) BS) of a domain through step t in layout L (the
+// domain's layout at t's parity); nt selects non-temporal stores.  Every
+// thread of the block calls it.
+template <int P, int BS, int L>
 __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, BlockParticles& sp) {
   using S = typename Store<P>::S;
   using R = typename Store<P>::C;
   constexpr bool exact = (P == P64);
   using SR = typename Raw<S>::T;
-  const auto src = gp((const SR*)((t & 1ull) ? V.fB : V.fA));
-  const auto dst = gp((SR*)((t & 1ull) ? V.fA : V.fB));
+  // two lattices: read the parity-t buffer, write the other; in place (one
+  // lattice): every access goes to fA, the slots depending on t's parity
+  constexpr bool inplace = L != kTwoLattices;
+  constexpr bool odd_ip = L == kInPlaceOdd;
+  const bool odd = (t & 1ull) != 0;
+  const auto src = gp((const SR*)((inplace || !odd) ? V.fA : V.fB));
+  SR* dst0 = (SR*)((inplace || odd) ? V.fA : V.fB);
+  // In place, dst equals src; hide that from the optimiser, which would
+  // otherwise keep all 19 load addresses live until the stores instead of
+  // recomputing them (this only moves a register value, no memory access).
+  if constexpr (inplace) asm volatile("" : "+s"(dst0));
+  const auto dst = gp(dst0);
   const uint32_t N = (uint32_t)V.N;
   const uint32_t n0 = lb * BS;
   const uint32_t n1 = (n0 + BS - 1 < N) ? n0 + BS - 1 : N - 1;
@@ -237,15 +288,8 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   if ((bx && (x == 0 || x == nx - 1)) || (by && (y == 0 || y == ny - 1)) || (bz && (z == 0 || z == nz - 1)))
     return;  // wall node: never updated
   const int nd[3] = {x, y, z};
-  const int sxy = nx * ny;
-  // linear offsets to the six face neighbours (periodic wrap)
-  const int dxm = x > 0 ? -1 : nx - 1, dxp = x < nx - 1 ? 1 : -(nx - 1);
-  const int dym = y > 0 ? -nx : (ny - 1) * nx, dyp = y < ny - 1 ? nx : -(ny - 1) * nx;
-  const int dzm = z > 0 ? -sxy : (nz - 1) * sxy, dzp = z < nz - 1 ? sxy : -(nz - 1) * sxy;
-  // neighbour at -1 / +1 along an axis is a wall node
-  const bool wxl = bx && x == 1, wxh = bx && x == nx - 2;
-  const bool wyl = by && y == 1, wyh = by && y == ny - 2;
-  const bool wzl = bz && z == 1, wzh = bz && z == nz - 2;
+  const Nbr nb = node_nbr(V, x, y, z);
+  const bool wxl = nb.wxl, wxh = nb.wxh, wyl = nb.wyl, wyh = nb.wyh, wzl = nb.wzl, wzh = nb.wzh;
   const bool near_wall = wxl | wxh | wyl | wyh | wzl | wzh;
 
   // ---- solid fraction and solid velocity
@@ -260,18 +304,32 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   const R eps = es < (R)1 ? es : (R)1;
   const bool solid = eps > (R)0;
 
-  // ---- gather (pull-stream; from a wall node the stored bounced population)
+
+  // ---- gather of f_i(x, t).  Two lattices: f*_i(x - e_i) of the last step
+  // from slot i there, or the bounced f*_opp(i)(x) from the node's own slot
+  // opp(i) when x - e_i is a wall node.  In place, even t: the node's own
+  // slot i (the previous step pushed it there); odd t: f*_i(x - e_i) sits in
+  // slot opp(i) of x - e_i (the previous step swapped it), or in the node's own
+  // slot i when x - e_i is a wall node.
   R f[kQ];
   unroll<0, kQ>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    constexpr int ex = kEx[i], ey = kEy[i], ez = kEz[i];
-    bool wall = false;
-    int delta = 0;
-    if constexpr (ex == 1) { wall |= wxl; delta += dxm; } else if constexpr (ex == -1) { wall |= wxh; delta += dxp; }
-    if constexpr (ey == 1) { wall |= wyl; delta += dym; } else if constexpr (ey == -1) { wall |= wyh; delta += dyp; }
-    if constexpr (ez == 1) { wall |= wzl; delta += dzm; } else if constexpr (ez == -1) { wall |= wzh; delta += dzp; }
-    const auto base = src + (size_t)(wall ? opp_dir(i) : i) * N;
-    const SR raw = base[wall ? id : (uint32_t)((int)id + delta)];
+    bool wall;
+    int delta;
+    upstream_of<i>(nb, wall, delta);
+    int slot;
+    uint32_t at;
+    if constexpr (!inplace) {
+      slot = wall ? opp_dir(i) : i;
+      at = wall ? id : (uint32_t)((int)id + delta);
+    } else if constexpr (!odd_ip) {
+      slot = i;
+      at = id;
+    } else {
+      slot = wall ? i : opp_dir(i);
+      at = wall ? id : (uint32_t)((int)id + delta);
+    }
+    const SR raw = src[(size_t)slot * N + at];
     if constexpr (exact) f[i] = raw;
     else f[i] = raw_in<S>(raw);
   });
@@ -371,13 +429,40 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
       v = v + (((R)6 * weight<R>(i)) * rho) * edot_c<i, R>(wx, wy, wz);
     }
   };
+  // ---- store of f*_j(x, t).  Two lattices: slot j of the node.  In place,
+  // even t: slot opp(j) of the node (swap); odd t: slot j of x + e_j (push),
+  // or slot opp(j) of the node itself when x + e_j is a wall node (bounce).
+  // x + e_j is the upstream neighbour of direction opp(j).  The push targets
+  // are recomputed from an opaque copy of the node's coordinates, so that the
+  // optimiser does not keep the gather's 19 addresses (the same locations)
+  // live through the collision.
+  Nbr nbs = nb;
+  uint32_t ids = id;
+  if constexpr (odd_ip) {
+    int cx = x, cy = y, cz = z;
+    asm volatile("" : "+v"(cx), "+v"(cy), "+v"(cz), "+v"(ids));
+    nbs = node_nbr(V, cx, cy, cz);
+  }
   auto put = [&](auto jc, R v) {
     constexpr int j = decltype(jc)::value;
     SR w;
     if constexpr (exact) w = v;
     else w = raw_out<S>(v);
-    if (nt) __builtin_nontemporal_store(w, &dst[(size_t)j * N + id]);
-    else dst[(size_t)j * N + id] = w;
+    int slot = j;
+    uint32_t at = id;
+    if constexpr (inplace) {
+      if constexpr (!odd_ip) {
+        slot = opp_dir(j);
+      } else {
+        bool wall;
+        int delta;
+        upstream_of<opp_dir(j)>(nbs, wall, delta);
+        slot = wall ? opp_dir(j) : j;
+        at = wall ? ids : (uint32_t)((int)ids + delta);
+      }
+    }
+    if (nt) __builtin_nontemporal_store(w, &dst[(size_t)slot * N + at]);
+    else dst[(size_t)slot * N + at] = w;
   };
 
   // rest population
@@ -420,25 +505,20 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
     put(oc, vo);
   });
   {
+    // (ux, uy, uz, rho) of the node as one vector store
     using U = typename Store<P>::U;
-    const auto u = gp((U*)V.u4[t & 1ull]) + 4 * (size_t)id;
-    if (nt) {
-      __builtin_nontemporal_store((U)ux, &u[0]);
-      __builtin_nontemporal_store((U)uy, &u[1]);
-      __builtin_nontemporal_store((U)uz, &u[2]);
-      __builtin_nontemporal_store((U)rho, &u[3]);
-    } else {
-      u[0] = ux;
-      u[1] = uy;
-      u[2] = uz;
-      u[3] = rho;
-    }
+    using U4v = U __attribute__((ext_vector_type(4)));
+    const U4v v = {(U)ux, (U)uy, (U)uz, (U)rho};
+    const auto u = gp((U4v*)V.u4[t & 1ull]) + id;
+    if (nt) __builtin_nontemporal_store(v, u);
+    else *u = v;
   }
 }
 
-// Initial stored state: streaming it reproduces f = feq(rho0, u0) at every
-// fluid node (populations that bounce are set to the value they must arrive
-// with); (u, rho) = (u0, rho0), wall nodes carry the wall velocity.
+// Initial stored state: the gather of step 0 reads f = feq(rho0, u0) at
+// every fluid node (with two lattices, populations that bounce are set to the
+// value they must arrive with); (u, rho) = (u0, rho0), wall nodes carry the
+// wall velocity.
 template <int P>
 __global__ void k_init(const DomView* __restrict__ views, int dom, double u0x, double u0y, double u0z) {
   using S = typename Store<P>::S;
@@ -456,13 +536,16 @@ __global__ void k_init(const DomView* __restrict__ views, int dom, double u0x, d
   S* fA = (S*)V.fA;
   S* fB = (S*)V.fB;
   for (int j = 0; j < kQ; ++j) {
+    // two lattices: slot j holds what streams into slot j's direction, so a
+    // population that will bounce holds f^eq of the opposite direction; in
+    // place (even layout) slot j of the node is f_j(x, 0) itself
     int i = j;
-    if (wslot < 0 && wall_slot(V, nd, kEx[j], kEy[j], kEz[j]) >= 0) i = opp_dir(j);
+    if (!V.inplace && wslot < 0 && wall_slot(V, nd, kEx[j], kEy[j], kEz[j]) >= 0) i = opp_dir(j);
     const double eu = edot<double>(i, u0x, u0y, u0z);
     double fe = (weight<double>(i) * rho0) * (((1.0 + 3.0 * eu) + 4.5 * (eu * eu)) - uu15);
     if (P != P64) fe = fe - weight<double>(i) * rho0;
     fA[(int64_t)j * V.N + id] = from_d<S>(fe);
-    fB[(int64_t)j * V.N + id] = from_d<S>(fe);
+    if (!V.inplace) fB[(int64_t)j * V.N + id] = from_d<S>(fe);
   }
   for (int b = 0; b < 2; ++b) {  // wall nodes keep these values in both buffers
     U* u4 = (U*)V.u4[b];
@@ -487,8 +570,9 @@ __global__ void k_read_f(const DomView* __restrict__ views, int dom, double* __r
   const DomView& V = views[dom];
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= V.N) return;
-  const uint64_t t = V.tstep[0];  // steps completed
-  const S* src = (const S*)((t & 1ull) ? V.fB : V.fA);
+  const uint64_t t = V.tstep[0];  // steps completed: the gather of step t
+  const bool inplace = V.inplace != 0, odd = (t & 1ull) != 0;
+  const S* src = (const S*)((!inplace && odd) ? V.fB : V.fA);
   const int nx = V.n[0], ny = V.n[1], nz = V.n[2];
   const int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
   for (int a = 0; a < 3; ++a)
@@ -503,7 +587,11 @@ __global__ void k_read_f(const DomView* __restrict__ views, int dom, double* __r
       if (V.bc[a]) wall |= (comp(i, a) != 0) && (s[a] == 0 || s[a] == V.n[a] - 1);
       else s[a] = s[a] < 0 ? s[a] + V.n[a] : (s[a] >= V.n[a] ? s[a] - V.n[a] : s[a]);
     }
-    const int64_t sidx = wall ? (int64_t)opp_dir(i) * V.N + id : (int64_t)i * V.N + (s[0] + nx * ((int64_t)s[1] + (int64_t)ny * s[2]));
+    const int64_t up = s[0] + nx * ((int64_t)s[1] + (int64_t)ny * s[2]);
+    int64_t sidx;
+    if (!inplace) sidx = wall ? (int64_t)opp_dir(i) * V.N + id : (int64_t)i * V.N + up;
+    else if (!odd) sidx = (int64_t)i * V.N + id;
+    else sidx = wall ? (int64_t)i * V.N + id : (int64_t)opp_dir(i) * V.N + up;
     double v = (double)to_c(src[sidx]);
     if (P != P64) v = v + weight<double>(i) * V.rho0;
     out[(int64_t)i * V.N + id] = v;

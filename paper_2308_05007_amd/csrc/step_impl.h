@@ -25,8 +25,17 @@ union StepLds {
   ProLds pro;
 };
 
-template <int P, int BS>
-__global__ void __launch_bounds__(BS) k_step(StepArgs a) {
+// IP: the domains of the launch stream their lattice in place (else: two
+// lattices); one instantiation per layout keeps each kernel's registers to
+// the paths it can take.
+#ifndef RWMI_STEP_WAVES_PER_EU
+#define RWMI_STEP_WAVES_PER_EU 8
+#endif
+// Waves per SIMD the register allocation must leave room for: 8 (64 VGPRs)
+// spills a few registers of the rarely taken paths to scratch and measured
+// at least as fast as 7 (72 VGPRs, no spill) or the unconstrained 78.
+template <int P, int BS, bool IP>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RWMI_STEP_WAVES_PER_EU))) k_step(StepArgs a) {
   __shared__ StepLds<P, BS> lds;
   int idx = 0;
   const int role = step_role((int)blockIdx.x, a.nb, (a.flags & 1) != 0, idx);
@@ -38,7 +47,9 @@ __global__ void __launch_bounds__(BS) k_step(StepArgs a) {
   const uint64_t t = step_of(V, a.j);
   if (role == kRoleWalk) walk_block<P, BS>(V, lb, t - 1, lds.walk);
   else if (role == kRolePro) prologue_block(V, lb, t + 1, lds.pro);
-  else fluid_block<P, BS>(V, (uint32_t)lb, t, (a.flags & 2) != 0, lds.fluid);
+  else if constexpr (!IP) fluid_block<P, BS, kTwoLattices>(V, (uint32_t)lb, t, (a.flags & 2) != 0, lds.fluid);
+  else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd>(V, (uint32_t)lb, t, (a.flags & 2) != 0, lds.fluid);
+  else fluid_block<P, BS, kInPlaceEven>(V, (uint32_t)lb, t, (a.flags & 2) != 0, lds.fluid);
 }
 
 }  // namespace rwmi

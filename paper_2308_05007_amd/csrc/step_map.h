@@ -39,6 +39,7 @@ struct StepArgs {
   int nd;
   int nb[kRoles];       // blocks per role over all domains
   int flags;            // kFlagXcd | kFlagNontemporal
+  int inplace;          // every domain of the launch streams its lattice in place
   int32_t j;            // launch index within the group (-1: the prologue-only launch)
 };
 

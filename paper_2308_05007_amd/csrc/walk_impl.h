@@ -363,7 +363,10 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
     L.dl[1][slot] = dl[1];
     L.dl[2][slot] = dl[2];
   }
-  if (threadIdx.x == 0 && refl_total) atomicAdd(&V.counters[kWallReflect], (unsigned long long)refl_total);
+  if (threadIdx.x == 0) {
+    if (refl_total) atomicAdd(&V.counters[kWallReflect], (unsigned long long)refl_total);
+    if (total) atomicAdd(&V.counters[kNearSurface], (unsigned long long)total);
+  }
   __syncthreads();
   // the queued walkers, packed into the first waves of the block
   if (threadIdx.x < total) {

@@ -40,8 +40,11 @@ def test_footprint_is_host_only_and_monotone():
     b = B.footprint_bytes(dom, 20, 240, 2_000_000)
     c = B.footprint_bytes(dict(dom, precision="fp16"), 20, 240, 1_000_000)
     assert 0 < c < a < b
-    # distributions dominate: two FP32 copies of 19 populations per node
-    assert a > 2 * 19 * 4 * 128 ** 3
+    # distributions dominate: at 128^3 FP32 (160 MB) one lattice streamed in
+    # place; at 256^3 (1.27 GB) two lattices
+    assert 19 * 4 * 128 ** 3 < a < 2 * 19 * 4 * 128 ** 3
+    big = B.footprint_bytes(dict(dom, n=(256, 256, 256)), 20, 240, 1_000_000)
+    assert big > 2 * 19 * 4 * 256 ** 3
 
 
 def test_errors_without_a_gpu_are_reported_not_raised_by_the_library():

@@ -118,12 +118,17 @@ TINY = [
 ]
 
 
+@pytest.mark.parametrize("streaming", [1, 2])
 @pytest.mark.parametrize("case", range(len(TINY)))
-def test_tiny_fp64_parity(orc, B, case):
+def test_tiny_fp64_parity(orc, B, case, streaming):
+    """Both lattice layouts (two lattices; one lattice streamed in place, whose
+    slots alternate with the step parity) against the oracle, distributions
+    included, after odd and even step counts."""
     kw = dict(TINY[case])
     steps = kw.pop("steps", 12)
     cfg = W.config_tiny(steps=steps, seed=100 + case, **kw)
     o, g = _pair(orc, B, cfg)
+    g.set("streaming", streaming)
     compare(o, g)
     for chunk in (1, 3, steps - 4):
         o.step(chunk)
@@ -237,6 +242,15 @@ def test_walker_order_never_shows(B, prec):
         assert r[0] == res[0][0] and r[1] == res[0][1] and r[2] == res[0][2]
         assert all(np.array_equal(x, y) for x, y in zip(r[3], res[0][3]))
         assert np.array_equal(r[4], res[0][4])
+
+
+def test_streaming_layout_is_fixed_after_the_first_step(B):
+    from paper_2308_05007_amd.binding import RwmiError
+    d = B.build_domain(W.config_tiny())
+    d.step(1)
+    with pytest.raises(RwmiError):
+        d.set("streaming", 1)
+    d.close()
 
 
 def test_graph_replay_equals_eager(B):

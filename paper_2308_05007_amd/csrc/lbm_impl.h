@@ -48,6 +48,14 @@ __device__ __forceinline__ double interval_gap(int periodic, int L, int lo, int 
   return g > 0.0 ? g : 0.0;
 }
 
+// Block barrier that orders LDS only: global loads in flight (the gather)
+// stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Cull the particles at pose P(t) for the node range [n0, n1] of a block and
 // stage their poses and control points in LDS.  Called by every thread of
 // the block; wave 0 takes the poses from the pose table of step t (written by
@@ -103,7 +111,7 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
     }
     if (tid == 0) sp.cnt = __popcll(m);
   }
-  __syncthreads();
+  lds_barrier();
   const int cnt = sp.cnt;
   if (cnt == 0) return;
   if (tid == 0) {
@@ -120,14 +128,14 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
     }
   }
   if (tid < cnt) sp.cutsq[tid] = parts[sp.id[tid]].cutsq;
-  __syncthreads();
+  lds_barrier();
   for (int k = 0; k < cnt; ++k) {
     const int off = sp.ctrl_off[k];
     if (off < 0) continue;
     const auto src = gp(V.ctrl) + 4 * parts[sp.id[k]].ctrl0;
     for (int j = tid; j < 4 * sp.nc[k]; j += blockDim.x) sp.ctrl[4 * off + j] = src[j];
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Solid fraction of one particle at node nd (1/2 + signed distance estimate
@@ -273,36 +281,21 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   const uint32_t N = (uint32_t)V.N;
   const uint32_t n0 = lb * BS;
   const uint32_t n1 = (n0 + BS - 1 < N) ? n0 + BS - 1 : N - 1;
-  if (V.np > 0) cull_block(V, n0, n1, t, sp, true);
-  else if (threadIdx.x == 0) sp.cnt = 0;
-  __syncthreads();
-
   const uint32_t id = n0 + threadIdx.x;
-  if (id >= N) return;
+  const uint32_t idc = id < N ? id : n0;  // a valid node for the threads past the end
   const int nx = V.n[0], ny = V.n[1], nz = V.n[2];
   const int bx = V.bc[0], by = V.bc[1], bz = V.bc[2];
-  const uint32_t q1 = fdiv(id, V.dx);
-  const int x = (int)(id - q1 * (uint32_t)nx);
+  const uint32_t q1 = fdiv(idc, V.dx);
+  const int x = (int)(idc - q1 * (uint32_t)nx);
   const int z = (int)fdiv(q1, V.dy);
   const int y = (int)q1 - z * ny;
-  if ((bx && (x == 0 || x == nx - 1)) || (by && (y == 0 || y == ny - 1)) || (bz && (z == 0 || z == nz - 1)))
-    return;  // wall node: never updated
+  // wall nodes are never updated
+  const bool live = id < N && !((bx && (x == 0 || x == nx - 1)) || (by && (y == 0 || y == ny - 1)) ||
+                                (bz && (z == 0 || z == nz - 1)));
   const int nd[3] = {x, y, z};
   const Nbr nb = node_nbr(V, x, y, z);
   const bool wxl = nb.wxl, wxh = nb.wxh, wyl = nb.wyl, wyh = nb.wyh, wzl = nb.wzl, wzh = nb.wzh;
   const bool near_wall = wxl | wxh | wyl | wyh | wzl | wzh;
-
-  // ---- solid fraction and solid velocity
-  R es = (R)0, unx = (R)0, uny = (R)0, unz = (R)0;
-  for (int k = 0; k < sp.cnt; ++k) {
-    const R e = node_eps<R>(V, sp, k, nd);
-    es = es + e;
-    unx = unx + e * (R)sp.v[k][0];
-    uny = uny + e * (R)sp.v[k][1];
-    unz = unz + e * (R)sp.v[k][2];
-  }
-  const R eps = es < (R)1 ? es : (R)1;
-  const bool solid = eps > (R)0;
 
 
   // ---- gather of f_i(x, t).  Two lattices: f*_i(x - e_i) of the last step
@@ -312,7 +305,7 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   // slot opp(i) of x - e_i (the previous step swapped it), or in the node's own
   // slot i when x - e_i is a wall node.
   R f[kQ];
-  unroll<0, kQ>([&](auto ic) {
+  if (live) unroll<0, kQ>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     bool wall;
     int delta;
@@ -333,6 +326,24 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
     if constexpr (exact) f[i] = raw;
     else f[i] = raw_in<S>(raw);
   });
+
+  // ---- particles culled for the block (every thread takes part in the
+  // cull's LDS barriers while its gather is in flight), then the solid
+  // fraction and solid velocity of the node
+  if (V.np > 0) cull_block(V, n0, n1, t, sp, true);
+  else if (threadIdx.x == 0) sp.cnt = 0;
+  lds_barrier();
+  if (!live) return;
+  R es = (R)0, unx = (R)0, uny = (R)0, unz = (R)0;
+  for (int k = 0; k < sp.cnt; ++k) {
+    const R e = node_eps<R>(V, sp, k, nd);
+    es = es + e;
+    unx = unx + e * (R)sp.v[k][0];
+    uny = uny + e * (R)sp.v[k][1];
+    unz = unz + e * (R)sp.v[k][2];
+  }
+  const R eps = es < (R)1 ? es : (R)1;
+  const bool solid = eps > (R)0;
 
   // ---- moments (Eq. 14-15; Guo half-force velocity)
   R rho, drho;

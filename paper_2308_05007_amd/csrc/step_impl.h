@@ -31,11 +31,16 @@ union StepLds {
 #ifndef RWMI_STEP_WAVES_PER_EU
 #define RWMI_STEP_WAVES_PER_EU 8
 #endif
-// Waves per SIMD the register allocation must leave room for: 8 (64 VGPRs)
-// spills a few registers of the rarely taken paths to scratch and measured
-// at least as fast as 7 (72 VGPRs, no spill) or the unconstrained 78.
+// Waves per SIMD the register allocation must leave room for.  Float
+// collision: 8 (64 VGPRs) spills a few registers of the rarely taken paths
+// to scratch and measured at least as fast as 7 (72 VGPRs, no spill) or the
+// unconstrained 78.  FP64 needs about twice the registers: no constraint.
+template <int P>
+constexpr int step_waves_per_eu() { return P == P64 ? 1 : RWMI_STEP_WAVES_PER_EU; }
+
 template <int P, int BS, bool IP>
-__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RWMI_STEP_WAVES_PER_EU))) k_step(StepArgs a) {
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<P>())))
+k_step(StepArgs a) {
   __shared__ StepLds<P, BS> lds;
   int idx = 0;
   const int role = step_role((int)blockIdx.x, a.nb, (a.flags & 1) != 0, idx);

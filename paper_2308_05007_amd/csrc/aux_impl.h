@@ -174,13 +174,14 @@ template <typename U>
 __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __restrict__ views, int dom,
                                                            double* __restrict__ part) {
   __shared__ double sh[kNodeMom][kRedThreads];
-  __shared__ BlockParticles sp;
+  using C = typename Store<sizeof(U) == 8 ? P64 : P32>::C;
+  __shared__ BlockParticles<C> sp;
   const DomView& V = views[dom];
   const int64_t base = (int64_t)blockIdx.x * kRedChunk;
   const int64_t last = (base + kRedChunk - 1 < V.N) ? base + kRedChunk - 1 : V.N - 1;
   const uint64_t done = V.tstep[0];  // steps completed
   const bool stepped = done > 0;
-  if (stepped && V.np > 0) cull_block(V, (uint32_t)base, (uint32_t)last, done - 1, sp, false);
+  if (stepped && V.np > 0) cull_block<C>(V, (uint32_t)base, (uint32_t)last, done - 1, sp, false);
   else if (threadIdx.x == 0) sp.cnt = 0;
   __syncthreads();
   double acc[kNodeMom];
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
     if (wall) continue;
     double es = 0.0, un[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < sp.cnt; ++k) {
-      const double e = (double)node_eps<typename Store<sizeof(U) == 8 ? P64 : P32>::C>(V, sp, k, nd);
+      const double e = (double)node_eps<C>(V, sp, k, nd);
       es = es + e;
 #pragma unroll
       for (int a = 0; a < 3; ++a) un[a] = un[a] + e * sp.v[k][a];

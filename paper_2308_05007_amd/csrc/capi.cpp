@@ -189,15 +189,21 @@ rwmi_status upload_view(rwmi_domain* d) {
   return RWMI_OK;
 }
 
+// Fluid cull words per table slot: one per fluid block at the smallest block
+// size.
+int64_t fcull_words(int64_t N) { return (N + 127) / 128; }
+
 int blocks_for(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
 // Blocks per role of one domain at bs threads per block: walkers, prologue
-// (poses whenever there are particles, the cull mask too when there are also
+// (whenever there are particles: poses, one thread per fluid block for its
+// cull word, and one per coarse block for the walker cull mask when there are
 // walkers), fluid.
 void role_blocks(const rwmi_domain* d, int bs, int b[kRoles]) {
   const int64_t nmb = (int64_t)d->hv.mb[0] * d->hv.mb[1] * d->hv.mb[2];
+  const int64_t nfb = (d->hv.N + bs - 1) / bs;
   b[kRoleWalk] = d->hv.nw > 0 ? blocks_for(d->hv.nw, bs) : 0;
-  b[kRolePro] = d->hv.np > 0 ? (d->hv.nw > 0 ? blocks_for(nmb, bs) : 1) : 0;
+  b[kRolePro] = d->hv.np > 0 ? blocks_for(std::max<int64_t>(d->hv.nw > 0 ? nmb : 0, nfb), bs) : 0;
   b[kRoleFluid] = blocks_for(d->hv.N, bs);
 }
 
@@ -251,7 +257,8 @@ rwmi_status finalize_particles(rwmi_domain* d) {
       if (rr > bmax) bmax = rr;
     }
     r.rb = bmax + std::sqrt(K);
-    r.cutsq = (r.rb + 2.0) * (r.rb + 2.0);
+    r.epscut2 = (r.rb + 0.75) * (r.rb + 0.75);
+    r.shell2 = (std::sqrt(K) + 0.75) * (std::sqrt(K) + 0.75);
     r.maskr = r.rb + 0.5;
     for (int a = 0; a < 3; ++a) {
       r.c0[a] = q.c0[a];
@@ -297,6 +304,11 @@ rwmi_status finalize_particles(rwmi_domain* d) {
     const int64_t nmb = mask_blocks(d->desc, mb);
     if ((st = alloc_into(d, mask, 24 * nmb)) != RWMI_OK) return st;
     for (int k = 0; k < 3; ++k) d->hv.mask[k] = mask + nmb * k;
+    // fluid cull words for the smallest block size
+    unsigned long long* fcull;
+    const int64_t nfw = fcull_words(d->hv.N);
+    if ((st = alloc_into(d, fcull, 24 * nfw)) != RWMI_OK) return st;
+    for (int k = 0; k < 3; ++k) d->hv.fcull[k] = fcull + nfw * k;
   }
   d->particles_uploaded = true;
   if ((st = upload_view(d)) != RWMI_OK) return st;
@@ -381,7 +393,8 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   uint64_t b = 0;
   b += (default_inplace(*s) ? 1 : 2) * 19 * N * elem_size(p) + 8 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
-  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 288 * n_particles + (n_particles ? 24 * nmb : 0);
+  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 288 * n_particles +
+       (n_particles ? 24 * nmb + 24 * (uint64_t)fcull_words((int64_t)N) : 0);
   // walkers: cell, offsets, images, id and slot maps; sort scratch (bin, rank
   // and a second copy of the walker record) and the bin counts
   b += n_walkers * (4 + 3 * off_size(p) + 12 + 8);

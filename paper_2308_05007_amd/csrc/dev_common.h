@@ -62,7 +62,10 @@ struct DevParticle {
   double c0[3], amp[3], vel[3];
   double period, phase;
   double rb;      // bounding radius: M <= 1 beyond it
-  double cutsq;   // (rb + 2)^2, support of the solid fraction
+  double epscut2; // (rb + 3/4)^2: the solid fraction is 0 beyond rb + 3/4
+  double shell2;  // (sqrt(K) + 3/4)^2, K the sum of the weights: the solid
+                  // fraction is 0 farther than sqrt(K) + 3/4 from every
+                  // control point
   double maskr;   // rb + 0.5, radius used to build the walker cull mask
   int32_t motion, nc, ctrl0, pad;
 };
@@ -96,6 +99,8 @@ struct DomView {
   double* pose[3];                // per step t, slot t mod 3: [2][np][6] (c, v) at t and t+1
   uint64_t* tstep;                // [0] steps completed before the current launch group
   unsigned long long* mask[3];    // per step t, slot t mod 3: coarse cull mask at P(t+1)
+  unsigned long long* fcull[3];   // per step t, slot t mod 3: bit p set when particle p's
+                                  // solid-fraction support at P(t) meets fluid block b
   int32_t* wcell;                 // walker cell index
   void* woff;                     // walker offsets SoA [3][nw] (double or float)
   int32_t* wimg;                  // walker image counts SoA [3][nw]
@@ -110,6 +115,14 @@ struct DomView {
 template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
   return (__attribute__((address_space(1))) T*)p;
+}
+
+// Constant-address-space view of a pointer to data that no block of the
+// running launch writes: wave-uniform loads through it compile to scalar
+// loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* kp(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
 }
 
 // Step t of a launch: the domain's step counter at the start of the launch

@@ -20,15 +20,19 @@ namespace rwmi {
 
 constexpr int kLdsCtrl = 160;  // control points staged in LDS per block
 
+// The particles culled for a block, in the collision's arithmetic type C.
+template <typename C>
 struct BlockParticles {
   int cnt;
   int id[kMaxParticles];
-  int ctrl_off[kMaxParticles];  // offset in s_ctrl, or -1 to read global memory
+  int ctrl_off[kMaxParticles];  // offset in ctrl, or -1 to read global memory
+  int ctrl0[kMaxParticles];     // first control point in the global table
   int nc[kMaxParticles];
   double c[kMaxParticles][3];
   double v[kMaxParticles][3];
-  double cutsq[kMaxParticles];
-  double ctrl[4 * kLdsCtrl];
+  C cut2[kMaxParticles];    // squared support radius about the centre
+  C shell2[kMaxParticles];  // squared radius about each control point
+  alignas(16) C ctrl[4 * kLdsCtrl];
 };
 
 // Circular (periodic) or plain distance from coordinate c to the node-centre
@@ -56,31 +60,61 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Cull the particles at pose P(t) for the node range [n0, n1] of a block and
-// stage their poses and control points in LDS.  Called by every thread of
-// the block; wave 0 takes the poses from the pose table of step t (written by
-// the prologue of an earlier launch) or, with from_table false, computes them.
-__device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32_t n1, uint64_t t, BlockParticles& sp,
-                                           bool from_table) {
-  const int nx = V.n[0], ny = V.n[1];
-  int lo[3], hi[3];
-  {
-    const uint32_t a0 = fdiv(n0, V.dx), a1 = fdiv(n1, V.dx);
-    const int z0 = (int)fdiv(a0, V.dy), z1 = (int)fdiv(a1, V.dy);
-    const int x0 = (int)(n0 - a0 * (uint32_t)nx), x1 = (int)(n1 - a1 * (uint32_t)nx);
-    const int y0 = (int)a0 - z0 * ny, y1 = (int)a1 - z1 * ny;
-    lo[2] = z0; hi[2] = z1;
-    if (z0 == z1 && y0 == y1) { lo[0] = x0; hi[0] = x1; lo[1] = y0; hi[1] = y0; }
-    else if (z0 == z1) { lo[0] = 0; hi[0] = nx - 1; lo[1] = y0; hi[1] = y1; }
-    else { lo[0] = 0; hi[0] = nx - 1; lo[1] = 0; hi[1] = ny - 1; }
+// Exclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_exclusive_sum(int x) {
+  const int lane = (int)(threadIdx.x & 63u);
+  int s = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(s, d, 64);
+    if (lane >= d) s += y;
   }
-  const auto parts = gp(V.parts);
+  return s - x;
+}
+
+// Bounding box, in node indices, of the node range [n0, n1] (x fastest).
+__device__ __forceinline__ void node_range_box(const DomView& V, uint32_t n0, uint32_t n1, int lo[3], int hi[3]) {
+  const int nx = V.n[0], ny = V.n[1];
+  const uint32_t a0 = fdiv(n0, V.dx), a1 = fdiv(n1, V.dx);
+  const int z0 = (int)fdiv(a0, V.dy), z1 = (int)fdiv(a1, V.dy);
+  const int x0 = (int)(n0 - a0 * (uint32_t)nx), x1 = (int)(n1 - a1 * (uint32_t)nx);
+  const int y0 = (int)a0 - z0 * ny, y1 = (int)a1 - z1 * ny;
+  lo[2] = z0; hi[2] = z1;
+  if (z0 == z1 && y0 == y1) { lo[0] = x0; hi[0] = x1; lo[1] = y0; hi[1] = y0; }
+  else if (z0 == z1) { lo[0] = 0; hi[0] = nx - 1; lo[1] = y0; hi[1] = y1; }
+  else { lo[0] = 0; hi[0] = nx - 1; lo[1] = 0; hi[1] = ny - 1; }
+}
+
+// Does the solid-fraction support (squared radius cut2 about centre pc) meet
+// the node centres of the box [lo, hi]?
+__device__ __forceinline__ bool support_meets_box(const DomView& V, const int lo[3], const int hi[3], const double pc[3],
+                                                  double cut2) {
+  double g2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double g = interval_gap(!V.bc[a], V.n[a], lo[a], hi[a], pc[a]);
+    g2 += g * g;
+  }
+  return g2 <= cut2 * (1.0 + 1e-9) + 1e-9;
+}
+
+// Cull the particles at pose P(t) for the node range [n0, n1] of a block and
+// stage their poses and control points in LDS (the moment reduction's
+// blocks).  Called by every thread of the block; wave 0 does the work,
+// taking the poses from the pose table of step t (written by the prologue of
+// an earlier launch) or, with from_table false, computing them.  Ends with
+// one block barrier.
+template <typename C>
+__device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32_t n1, uint64_t t,
+                                           BlockParticles<C>& sp, bool from_table) {
   const int tid = threadIdx.x;
   if (tid < 64) {
+    int lo[3], hi[3];
+    node_range_box(V, n0, n1, lo, hi);
     bool keep = false;
     double pc[3] = {0, 0, 0}, pv[3] = {0, 0, 0};
+    const auto P = gp(V.parts) + tid;
     if (tid < V.np) {
-      const DevParticle& P = V.parts[tid];
       if (from_table) {
         const auto pt = gp((const double*)V.pose[pose_slot(t)]) + 6 * tid;
 #pragma unroll
@@ -89,78 +123,101 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
           pv[a] = pt[3 + a];
         }
       } else {
-        particle_pose(P, t, pc, pv);
+        particle_pose(V.parts[tid], t, pc, pv);
       }
-      double g2 = 0.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double g = interval_gap(!V.bc[a], V.n[a], lo[a], hi[a], pc[a]);
-        g2 += g * g;
-      }
-      keep = g2 <= P.cutsq * (1.0 + 1e-9) + 1e-9;
+      keep = support_meets_box(V, lo, hi, pc, P->epscut2);
     }
     const unsigned long long m = __ballot(keep);
+    const int nc = keep ? P->nc : 0;
+    const int pre = wave_exclusive_sum(nc);  // kept particles in index order
     if (keep) {
       const int r = __popcll(m & ((1ull << tid) - 1ull));
+      const int c0 = P->ctrl0;
       sp.id[r] = tid;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         sp.c[r][a] = pc[a];
         sp.v[r][a] = pv[a];
       }
+      sp.cut2[r] = (C)P->epscut2;
+      sp.shell2[r] = (C)P->shell2;
+      sp.nc[r] = nc;
+      sp.ctrl0[r] = c0;
+      const bool fits = pre + nc <= kLdsCtrl;
+      sp.ctrl_off[r] = fits ? pre : -1;
+      if (fits) {
+        const auto src = gp(ctrl_of<C>(V)) + 4 * c0;
+        for (int i = 0; i < 4 * nc; ++i) sp.ctrl[4 * pre + i] = src[i];
+      }
     }
     if (tid == 0) sp.cnt = __popcll(m);
   }
   lds_barrier();
-  const int cnt = sp.cnt;
-  if (cnt == 0) return;
-  if (tid == 0) {
-    int off = 0;
-    for (int k = 0; k < cnt; ++k) {
-      const int nc = parts[sp.id[k]].nc;
-      sp.nc[k] = nc;
-      if (off + nc <= kLdsCtrl) {
-        sp.ctrl_off[k] = off;
-        off += nc;
-      } else {
-        sp.ctrl_off[k] = -1;
-      }
-    }
-  }
-  if (tid < cnt) sp.cutsq[tid] = parts[sp.id[tid]].cutsq;
-  lds_barrier();
-  for (int k = 0; k < cnt; ++k) {
-    const int off = sp.ctrl_off[k];
-    if (off < 0) continue;
-    const auto src = gp(V.ctrl) + 4 * parts[sp.id[k]].ctrl0;
-    for (int j = tid; j < 4 * sp.nc[k]; j += blockDim.x) sp.ctrl[4 * off + j] = src[j];
-  }
-  lds_barrier();
 }
 
-// Solid fraction of one particle at node nd (1/2 + signed distance estimate
-// 2 M (sqrt M - 1) / |grad M|, clamped; 0 beyond sqrt(cutsq)).
-template <typename R>
-__device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles& sp, int k, const int nd[3]) {
-  const R dx = axis_disp<R>(!V.bc[0], V.n[0], nd[0], sp.c[k][0], (R)0.5);
-  const R dy = axis_disp<R>(!V.bc[1], V.n[1], nd[1], sp.c[k][1], (R)0.5);
-  const R dz = axis_disp<R>(!V.bc[2], V.n[2], nd[2], sp.c[k][2], (R)0.5);
-  const R r2c = (dx * dx + dy * dy) + dz * dz;
-  if (r2c > (R)sp.cutsq[k]) return (R)0;
-  const int nc = sp.nc[k];
-  R M, g[3];
-  if (sp.ctrl_off[k] >= 0) {
-    const double* ctrl = sp.ctrl + 4 * sp.ctrl_off[k];
-    M = metaball_value<R>(ctrl, nc, dx, dy, dz);
-    if (M == (R)INFINITY) return (R)1;
-    metaball_grad<R>(ctrl, nc, dx, dy, dz, g);
-  } else {
-    const auto ctrl = gp(ctrl_of<R>(V)) + 4 * gp(V.parts)[sp.id[k]].ctrl0;
-    M = metaball_value<R>(ctrl, nc, dx, dy, dz);
-    if (M == (R)INFINITY) return (R)1;
-    metaball_grad<R>(ctrl, nc, dx, dy, dz, g);
+// Cull word of the fluid block of BS nodes with index fb: bit p set when the
+// support of particle p (centre c[p], squared radius cut2[p]) meets the
+// block's nodes.  Built by the prologue one launch ahead of the block.
+__device__ __forceinline__ unsigned long long fluid_cull_word(const DomView& V, int bs, int64_t fb,
+                                                              const double (*c)[3], const double* cut2) {
+  const uint32_t N = (uint32_t)V.N;
+  const uint32_t n0 = (uint32_t)fb * (uint32_t)bs;
+  const uint32_t n1 = (n0 + (uint32_t)bs - 1 < N) ? n0 + (uint32_t)bs - 1 : N - 1;
+  int lo[3], hi[3];
+  node_range_box(V, n0, n1, lo, hi);
+  unsigned long long bits = 0ull;
+  for (int p = 0; p < V.np; ++p)
+    if (support_meets_box(V, lo, hi, c[p], cut2[p])) bits |= 1ull << p;
+  return bits;
+}
+
+// Solid fraction of one particle at node nd: 1/2 + the signed distance
+// estimate 2 M (sqrt M - 1) / |grad M|, clamped to [0, 1] (Eq. 3, Eq. 17).
+//
+// Nodes where the estimate is provably <= -3/4 get 0 without evaluating M.
+// With all weights positive and r the distance to the nearest control point,
+// M <= K / r^2 and |grad M| <= 2 M / r (K the sum of the weights).  If
+// r >= sqrt(K) + 3/4 then 1 - sqrt(M) >= (3/4) / r (3/4 being 1/2 + 1/4), so
+// the estimate is at most -(1 + 2/4) / 2 = -3/4 and the fraction is 0,
+// however it is rounded.  The centre test uses the same bound with the
+// bounding radius: beyond rb + 3/4 from the centre every control point is
+// farther than sqrt(K) + 3/4.
+template <typename R, typename PT>
+__device__ __forceinline__ R eps_from_ctrl(PT ctrl, int nc, R dx, R dy, R dz, R shell2) {
+  R rmin2 = (R)INFINITY;
+#pragma unroll 4
+  for (int i = 0; i < nc; ++i) {
+    const auto q = ctrl + 4 * i;
+    const R rx = dx - (R)q[0], ry = dy - (R)q[1], rz = dz - (R)q[2];
+    const R r2 = (rx * rx + ry * ry) + rz * rz;
+    rmin2 = r2 < rmin2 ? r2 : rmin2;
   }
-  const R gn = qsqrt<R>((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+  if (!(rmin2 < shell2)) return (R)0;
+  // M (Eq. 3) and its gradient (Eq. 17) in one pass, each sum in control-point
+  // order; the FP64 terms are the IEEE quotients k / r^2 and -2 k / r^4
+  R M = (R)0, g0 = (R)0, g1 = (R)0, g2 = (R)0;
+#pragma unroll 4
+  for (int i = 0; i < nc; ++i) {
+    const auto q = ctrl + 4 * i;
+    const R rx = dx - (R)q[0], ry = dy - (R)q[1], rz = dz - (R)q[2];
+    const R r2 = (rx * rx + ry * ry) + rz * rz;
+    const R k = (R)q[3];
+    R f;
+    if constexpr (std::is_same<R, double>::value) {
+      M = M + k / r2;
+      f = ((R)-2 * k) / (r2 * r2);
+    } else {
+      const R inv = __builtin_amdgcn_rcpf(r2);
+      const R tk = k * inv;
+      M = M + tk;
+      f = ((R)-2 * tk) * inv;
+    }
+    g0 = g0 + f * rx;
+    g1 = g1 + f * ry;
+    g2 = g2 + f * rz;
+  }
+  if (M == (R)INFINITY) return (R)1;  // on a control point
+  const R gn = qsqrt<R>((g0 * g0 + g1 * g1) + g2 * g2);
   R e;
   if (gn == (R)0) {
     e = M >= (R)1 ? (R)1 : (R)0;
@@ -171,6 +228,36 @@ __device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles& sp
   if (e < (R)0) e = (R)0;
   if (e > (R)1) e = (R)1;
   return e;
+}
+
+template <typename R>
+__device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles<R>& sp, int k, const int nd[3]) {
+  const R dx = axis_disp<R>(!V.bc[0], V.n[0], nd[0], sp.c[k][0], (R)0.5);
+  const R dy = axis_disp<R>(!V.bc[1], V.n[1], nd[1], sp.c[k][1], (R)0.5);
+  const R dz = axis_disp<R>(!V.bc[2], V.n[2], nd[2], sp.c[k][2], (R)0.5);
+  const R r2c = (dx * dx + dy * dy) + dz * dz;
+  if (!(r2c < sp.cut2[k])) return (R)0;
+  const int off = sp.ctrl_off[k];
+  if (off >= 0) return eps_from_ctrl<R>(sp.ctrl + 4 * off, sp.nc[k], dx, dy, dz, sp.shell2[k]);
+  return eps_from_ctrl<R>(gp(ctrl_of<R>(V)) + 4 * sp.ctrl0[k], sp.nc[k], dx, dy, dz, sp.shell2[k]);
+}
+
+// Solid fraction of particle p at node nd in a fluid block of step t, and the
+// particle's velocity: pose from the pose table of slot ps, particle record
+// and control points, all through wave-uniform scalar loads.
+template <typename R>
+__device__ __forceinline__ R node_eps_direct(const DomView& V, int ps, int p, const int nd[3], R v[3]) {
+  const auto pt = kp((const double*)V.pose[ps]) + 6 * p;
+  const auto P = kp(V.parts) + p;
+  v[0] = (R)pt[3];
+  v[1] = (R)pt[4];
+  v[2] = (R)pt[5];
+  const R dx = axis_disp<R>(!V.bc[0], V.n[0], nd[0], pt[0], (R)0.5);
+  const R dy = axis_disp<R>(!V.bc[1], V.n[1], nd[1], pt[1], (R)0.5);
+  const R dz = axis_disp<R>(!V.bc[2], V.n[2], nd[2], pt[2], (R)0.5);
+  const R r2c = (dx * dx + dy * dy) + dz * dz;
+  if (!(r2c < (R)P->epscut2)) return (R)0;
+  return eps_from_ctrl<R>(kp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz, (R)P->shell2);
 }
 
 // e_i . v with zero components contributing nothing (left to right over x, y, z).
@@ -261,7 +348,7 @@ __device__ __forceinline__ void upstream_of(const Nbr& b, bool& wall, int& delta
 // domain's layout at t's parity); nt selects non-temporal stores.  Every
 // thread of the block calls it.
 template <int P, int BS, int L>
-__device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, BlockParticles& sp) {
+__device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt) {
   using S = typename Store<P>::S;
   using R = typename Store<P>::C;
   constexpr bool exact = (P == P64);
@@ -280,7 +367,6 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   const auto dst = gp(dst0);
   const uint32_t N = (uint32_t)V.N;
   const uint32_t n0 = lb * BS;
-  const uint32_t n1 = (n0 + BS - 1 < N) ? n0 + BS - 1 : N - 1;
   const uint32_t id = n0 + threadIdx.x;
   const uint32_t idc = id < N ? id : n0;  // a valid node for the threads past the end
   const int nx = V.n[0], ny = V.n[1], nz = V.n[2];
@@ -327,20 +413,24 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
     else f[i] = raw_in<S>(raw);
   });
 
-  // ---- particles culled for the block (every thread takes part in the
-  // cull's LDS barriers while its gather is in flight), then the solid
-  // fraction and solid velocity of the node
-  if (V.np > 0) cull_block(V, n0, n1, t, sp, true);
-  else if (threadIdx.x == 0) sp.cnt = 0;
-  lds_barrier();
   if (!live) return;
+  // ---- solid fraction and solid velocity of the node, over the particles
+  // whose support meets the block (cull word from the prologue), in index
+  // order
   R es = (R)0, unx = (R)0, uny = (R)0, unz = (R)0;
-  for (int k = 0; k < sp.cnt; ++k) {
-    const R e = node_eps<R>(V, sp, k, nd);
-    es = es + e;
-    unx = unx + e * (R)sp.v[k][0];
-    uny = uny + e * (R)sp.v[k][1];
-    unz = unz + e * (R)sp.v[k][2];
+  if (V.np > 0) {
+    const int ps = pose_slot(t);
+    unsigned long long bits = kp(V.fcull[ps])[lb];
+    while (bits) {
+      const int p = __ffsll((long long)bits) - 1;
+      bits &= bits - 1ull;
+      R v[3];
+      const R e = node_eps_direct<R>(V, ps, p, nd, v);
+      es = es + e;
+      unx = unx + e * v[0];
+      uny = uny + e * v[1];
+      unz = unz + e * v[2];
+    }
   }
   const R eps = es < (R)1 ? es : (R)1;
   const bool solid = eps > (R)0;

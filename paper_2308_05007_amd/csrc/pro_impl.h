@@ -2,6 +2,7 @@
 // mask (a block function of the fused step launch).
 #pragma once
 #include "dev_common.h"
+#include "lbm_impl.h"
 
 namespace rwmi {
 
@@ -21,17 +22,22 @@ __device__ __forceinline__ double gap_to(int periodic, int L, double a, double b
 }
 
 struct ProLds {
-  double c[kMaxParticles][3];
-  double r[kMaxParticles];
+  double c[kMaxParticles][3];   // centres at t + 1
+  double r[kMaxParticles];      // walker mask radius
+  double c0[kMaxParticles][3];  // centres at t
+  double cut2[kMaxParticles];   // squared solid-fraction support radius
 };
 
-// Prologue of step t (table slot t mod 3): block 0 of a domain writes the
-// poses P(t), P(t+1) into pose[slot]; block lb builds mask blocks
-// [lb blockDim, (lb + 1) blockDim) of the coarse mask at P(t+1) in mask[slot]:
-// bit p of a coarse block is set when the sphere (c_p(t+1), rb_p + 1/2) meets
-// the block (extended to infinity beyond wall planes).  Every thread of the
-// block calls it.
-__device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_t t, ProLds& L) {
+// Prologue of step t (table slot t mod 3).  Block 0 of a domain writes the
+// poses P(t), P(t+1) into pose[slot].  Thread i of the prologue blocks
+// (i = lb blockDim + threadIdx.x) builds
+// - word i of the coarse walker mask at P(t+1) in mask[slot]: bit p set when
+//   the sphere (c_p(t+1), rb_p + 1/2) meets coarse block i (extended to
+//   infinity beyond wall planes);
+// - the cull word of fluid block i (blocks of bs nodes) at P(t) in
+//   fcull[slot].
+// Every thread of the block calls it.
+__device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_t t, int bs, ProLds& L) {
   double (&sc)[kMaxParticles][3] = L.c;
   double (&sr)[kMaxParticles] = L.r;
   const int ps = pose_slot(t);
@@ -53,14 +59,20 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
       }
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) sc[tid][a] = c1[a];
+    for (int a = 0; a < 3; ++a) {
+      sc[tid][a] = c1[a];
+      L.c0[tid][a] = c0[a];
+    }
     sr[tid] = P.maskr;
+    L.cut2[tid] = P.epscut2;
   }
   __syncthreads();
-  if (V.nw == 0 || V.np == 0) return;  // the fluid needs only the poses
-  const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
+  if (V.np == 0) return;
   const int64_t cb = (int64_t)lb * blockDim.x + tid;
-  if (cb >= nmb) return;
+  const int64_t nfb = (V.N + bs - 1) / bs;
+  if (cb < nfb) V.fcull[ps][cb] = fluid_cull_word(V, bs, cb, L.c0, L.cut2);
+  const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
+  if (V.nw == 0 || cb >= nmb) return;
   const int bidx[3] = {(int)(cb % V.mb[0]), (int)((cb / V.mb[0]) % V.mb[1]), (int)(cb / ((int64_t)V.mb[0] * V.mb[1]))};
   double lo[3], hi[3];
 #pragma unroll

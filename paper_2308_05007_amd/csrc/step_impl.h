@@ -20,7 +20,6 @@ namespace rwmi {
 
 template <int P, int BS>
 union StepLds {
-  BlockParticles fluid;
   WalkLds<typename Store<P>::O, BS> walk;
   ProLds pro;
 };
@@ -51,10 +50,10 @@ k_step(StepArgs a) {
   const int lb = idx - bo[d];
   const uint64_t t = step_of(V, a.j);
   if (role == kRoleWalk) walk_block<P, BS>(V, lb, t - 1, lds.walk);
-  else if (role == kRolePro) prologue_block(V, lb, t + 1, lds.pro);
-  else if constexpr (!IP) fluid_block<P, BS, kTwoLattices>(V, (uint32_t)lb, t, (a.flags & 2) != 0, lds.fluid);
-  else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd>(V, (uint32_t)lb, t, (a.flags & 2) != 0, lds.fluid);
-  else fluid_block<P, BS, kInPlaceEven>(V, (uint32_t)lb, t, (a.flags & 2) != 0, lds.fluid);
+  else if (role == kRolePro) prologue_block(V, lb, t + 1, BS, lds.pro);
+  else if constexpr (!IP) fluid_block<P, BS, kTwoLattices>(V, (uint32_t)lb, t, (a.flags & 2) != 0);
+  else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd>(V, (uint32_t)lb, t, (a.flags & 2) != 0);
+  else fluid_block<P, BS, kInPlaceEven>(V, (uint32_t)lb, t, (a.flags & 2) != 0);
 }
 
 }  // namespace rwmi

@@ -315,10 +315,13 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   return upload_workmaps(d);
 }
 
+// Timing events: no host reads device data through them, so they skip the
+// system-scope cache write-back and invalidation a default event performs
+// (which also stalls the stream around each record).
 hipEvent_t take_event(rwmi_domain* d) {
   if (d->evused == d->evpool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     d->evpool.push_back(e);
   }
   return d->evpool[d->evused++];

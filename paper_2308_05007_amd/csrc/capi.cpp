@@ -472,6 +472,9 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
   v.rho0_f = (float)rho0;
   v.sD_f = (float)v.sD;
   v.has_force = 0;
+  for (int i = 0; i < rwmi::kQ; ++i)
+    v.eF_f[i] = (float)((double)rwmi::kEx[i] * s->force[0] + (double)rwmi::kEy[i] * s->force[1] +
+                        (double)rwmi::kEz[i] * s->force[2]);
   for (int a = 0; a < 3; ++a) {
     v.F[a] = s->force[a];
     v.F_f[a] = (float)s->force[a];

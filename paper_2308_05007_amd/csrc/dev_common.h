@@ -88,6 +88,7 @@ struct DomView {
   double tau, omega, tm, cfree;   // 1/tau, tau - 1/2, 1 - 1/(2 tau)
   double F[3], rho0, sD;          // force, initial density, sqrt(2D)
   float omega_f, tm_f, cfree_f, rho0_f, sD_f, F_f[3], halfF_f[3];
+  float eF_f[kQ];                 // e_i . F per direction (float collision)
   double wu[3][2][3];             // wall velocity [axis][lo/hi][component]
   float wu_f[3][2][3];
   void* fA;                       // distributions: parity 0 source (two lattices) or the lattice (in place)
@@ -117,6 +118,14 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
+// Block barrier that orders LDS only: global memory operations in flight
+// stay in flight across it (no wait for outstanding loads or stores).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Constant-address-space view of a pointer to data that no block of the
 // running launch writes: wave-uniform loads through it compile to scalar
 // loads.
@@ -128,7 +137,7 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T* kp(const T
 // Step t of a launch: the domain's step counter at the start of the launch
 // group plus the launch's offset k within the group.
 __device__ __forceinline__ uint64_t step_of(const DomView& V, int32_t k) {
-  return (uint64_t)((int64_t)gp(V.tstep)[0] + k);
+  return (uint64_t)((int64_t)kp(V.tstep)[0] + k);
 }
 
 // Slot of the pose table and cull mask of step t.  Three slots: one launch

@@ -11,15 +11,15 @@ hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
   if (g == 0) return hipSuccess;
   if (a.inplace) {
     switch (bs) {
-      case 128: k_step<P64, 128, true><<<g, 128, 0, s>>>(a); break;
-      case 512: k_step<P64, 512, true><<<g, 512, 0, s>>>(a); break;
-      default: k_step<P64, 256, true><<<g, 256, 0, s>>>(a); break;
+      case 128: k_step<P64, 128, true><<<g, 128, 0, s>>>(a, a.views, a.boff); break;
+      case 512: k_step<P64, 512, true><<<g, 512, 0, s>>>(a, a.views, a.boff); break;
+      default: k_step<P64, 256, true><<<g, 256, 0, s>>>(a, a.views, a.boff); break;
     }
   } else {
     switch (bs) {
-      case 128: k_step<P64, 128, false><<<g, 128, 0, s>>>(a); break;
-      case 512: k_step<P64, 512, false><<<g, 512, 0, s>>>(a); break;
-      default: k_step<P64, 256, false><<<g, 256, 0, s>>>(a); break;
+      case 128: k_step<P64, 128, false><<<g, 128, 0, s>>>(a, a.views, a.boff); break;
+      case 512: k_step<P64, 512, false><<<g, 512, 0, s>>>(a, a.views, a.boff); break;
+      default: k_step<P64, 256, false><<<g, 256, 0, s>>>(a, a.views, a.boff); break;
     }
   }
   return hipGetLastError();

@@ -8,9 +8,9 @@ namespace rwmi {
 template <int P, bool IP>
 static void step_bs(int bs, unsigned g, const StepArgs& a, hipStream_t s) {
   switch (bs) {
-    case 128: k_step<P, 128, IP><<<g, 128, 0, s>>>(a); break;
-    case 512: k_step<P, 512, IP><<<g, 512, 0, s>>>(a); break;
-    default: k_step<P, 256, IP><<<g, 256, 0, s>>>(a); break;
+    case 128: k_step<P, 128, IP><<<g, 128, 0, s>>>(a, a.views, a.boff); break;
+    case 512: k_step<P, 512, IP><<<g, 512, 0, s>>>(a, a.views, a.boff); break;
+    default: k_step<P, 256, IP><<<g, 256, 0, s>>>(a, a.views, a.boff); break;
   }
 }
 

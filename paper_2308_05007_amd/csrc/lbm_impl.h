@@ -52,14 +52,6 @@ __device__ __forceinline__ double interval_gap(int periodic, int L, int lo, int 
   return g > 0.0 ? g : 0.0;
 }
 
-// Block barrier that orders LDS only: global loads in flight (the gather)
-// stay in flight across it.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // Exclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_exclusive_sum(int x) {
   const int lane = (int)(threadIdx.x & 63u);
@@ -566,13 +558,38 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
     else dst[(size_t)slot * N + at] = w;
   };
 
+  // Float collision, folded: with e_o = -e_i and w_o = w_i the relaxed,
+  // forced population of an opposite pair is
+  //   (1 - A) f_i + w_i (S +- D),
+  //   S = K0 + eu (K2 eu + K3 eF),  D = eu K1 + K4 eF,
+  // eu = e_i.u, eF = e_i.F, K0 = A (drho - rho 1.5 u.u) - 3 Cf u.F,
+  // K1 = 3 A rho, K2 = 4.5 A rho, K3 = 9 Cf, K4 = 3 Cf: the same BGK and Guo
+  // terms as the FP64 form, in fewer operations.
+  R omA = (R)0, K0 = (R)0, K1 = (R)0, K2 = (R)0, K3 = (R)0, K4 = (R)0;
+  if constexpr (!exact) {
+    omA = (R)1 - A;
+    K1 = ((R)3 * A) * rho;
+    K2 = ((R)4.5 * A) * rho;
+    K0 = A * (drho - rho * uu15);
+    if (force) {
+      K3 = (R)9 * Cf;
+      K4 = (R)3 * Cf;
+      K0 = K0 - K4 * uF;
+    }
+  }
   // rest population
   {
     constexpr std::integral_constant<int, 0> i0{};
-    const R fe0 = feq(i0, (R)0, uu15);
-    R o0 = f[0] - A * (f[0] - fe0);
-    if (solid) o0 = o0 + B * ((f[0] - fe0) - (f[0] - feq(i0, (R)0, us15)));
-    if (force) o0 = o0 + Cf * guo(i0, (R)0);
+    R o0;
+    if constexpr (exact) {
+      const R fe0 = feq(i0, (R)0, uu15);
+      o0 = f[0] - A * (f[0] - fe0);
+      if (solid) o0 = o0 + B * ((f[0] - fe0) - (f[0] - feq(i0, (R)0, us15)));
+      if (force) o0 = o0 + Cf * guo(i0, (R)0);
+    } else {
+      o0 = omA * f[0] + weight<R>(0) * K0;
+      if (solid) o0 = o0 + B * (feq(i0, (R)0, us15) - feq(i0, (R)0, uu15));
+    }
     put(i0, o0);
   }
   // opposite pairs (i, i+1): each pair is relaxed, exchanged with the solid,
@@ -582,21 +599,50 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
     constexpr int o = i + 1;
     constexpr std::integral_constant<int, i> ic{};
     constexpr std::integral_constant<int, o> oc{};
-    const R eui = edot_c<i, R>(ux, uy, uz);
-    const R euo = edot_c<o, R>(ux, uy, uz);
-    const R fei = feq(ic, eui, uu15);
-    const R feo = feq(oc, euo, uu15);
-    R vi = f[i] - A * (f[i] - fei);
-    R vo = f[o] - A * (f[o] - feo);
-    if (solid) {
-      const R fesi = feq(ic, edot_c<i, R>(usx, usy, usz), us15);
-      const R feso = feq(oc, edot_c<o, R>(usx, usy, usz), us15);
-      vi = vi + B * ((f[o] - feo) - (f[i] - fesi));
-      vo = vo + B * ((f[i] - fei) - (f[o] - feso));
-    }
-    if (force) {
-      vi = vi + Cf * guo(ic, eui);
-      vo = vo + Cf * guo(oc, euo);
+    R vi, vo;
+    if constexpr (exact) {
+      const R eui = edot_c<i, R>(ux, uy, uz);
+      const R euo = edot_c<o, R>(ux, uy, uz);
+      const R fei = feq(ic, eui, uu15);
+      const R feo = feq(oc, euo, uu15);
+      vi = f[i] - A * (f[i] - fei);
+      vo = f[o] - A * (f[o] - feo);
+      if (solid) {
+        const R fesi = feq(ic, edot_c<i, R>(usx, usy, usz), us15);
+        const R feso = feq(oc, edot_c<o, R>(usx, usy, usz), us15);
+        vi = vi + B * ((f[o] - feo) - (f[i] - fesi));
+        vo = vo + B * ((f[i] - fei) - (f[o] - feso));
+      }
+      if (force) {
+        vi = vi + Cf * guo(ic, eui);
+        vo = vo + Cf * guo(oc, euo);
+      }
+    } else {
+      // w S and w D with the weight folded into the node's constants (the
+      // products are shared by the pairs of one weight class)
+      const R eu = edot_c<i, R>(ux, uy, uz);
+      constexpr R w = weight<R>(i);
+      R S, D;
+      if (force) {
+        const R eF = kp(V.eF_f)[i];
+        S = (w * K0) + eu * ((w * K2) * eu + (w * K3) * eF);
+        D = eu * (w * K1) + (w * K4) * eF;
+      } else {
+        S = (w * K0) + eu * ((w * K2) * eu);
+        D = eu * (w * K1);
+      }
+      vi = omA * f[i] + (S + D);
+      vo = omA * f[o] + (S - D);
+      if (solid) {
+        // Noble-Torczynski exchange with the solid: B ((f_o - fe_o) - (f_i - fes_i))
+        const R fei = feq(ic, eu, uu15);
+        const R feo = feq(oc, -eu, uu15);
+        const R eus = edot_c<i, R>(usx, usy, usz);
+        const R fesi = feq(ic, eus, us15);
+        const R feso = feq(oc, -eus, us15);
+        vi = vi + B * ((f[o] - feo) - (f[i] - fesi));
+        vo = vo + B * ((f[i] - fei) - (f[o] - feso));
+      }
     }
     if (near_wall) {
       wall_term(ic, vi);

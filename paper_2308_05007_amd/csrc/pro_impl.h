@@ -66,7 +66,7 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
     sr[tid] = P.maskr;
     L.cut2[tid] = P.epscut2;
   }
-  __syncthreads();
+  lds_barrier();
   if (V.np == 0) return;
   const int64_t cb = (int64_t)lb * blockDim.x + tid;
   const int64_t nfb = (V.N + bs - 1) / bs;

@@ -39,14 +39,16 @@ constexpr int step_waves_per_eu() { return P == P64 ? 1 : RWMI_STEP_WAVES_PER_EU
 
 template <int P, int BS, bool IP>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<P>())))
-k_step(StepArgs a) {
+k_step(StepArgs a, const DomView* __restrict__ views, const int32_t* __restrict__ boff) {
+  // views and boff (the same pointers as in a) are read-only in the launch:
+  // as restrict parameters their wave-uniform reads compile to scalar loads
   __shared__ StepLds<P, BS> lds;
   int idx = 0;
   const int role = step_role((int)blockIdx.x, a.nb, (a.flags & 1) != 0, idx);
   if (role == kRoleNone) return;
-  const int32_t* bo = a.boff + role * (a.nd + 1);
+  const int32_t* bo = boff + role * (a.nd + 1);
   const int d = find_domain(bo, a.nd, idx);
-  const DomView& V = a.views[d];
+  const DomView& V = views[d];
   const int lb = idx - bo[d];
   const uint64_t t = step_of(V, a.j);
   if (role == kRoleWalk) walk_block<P, BS>(V, lb, t - 1, lds.walk);

@@ -348,7 +348,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
     L.s_q[wave] = (uint32_t)__popcll(qm);
     L.s_r[wave] = (uint32_t)__popcll(rm);
   }
-  __syncthreads();
+  lds_barrier();
   uint32_t before = 0, total = 0, refl_total = 0;
 #pragma unroll
   for (int k = 0; k < kWaves; ++k) {
@@ -367,7 +367,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
     if (refl_total) atomicAdd(&V.counters[kWallReflect], (unsigned long long)refl_total);
     if (total) atomicAdd(&V.counters[kNearSurface], (unsigned long long)total);
   }
-  __syncthreads();
+  lds_barrier();
   // the queued walkers, packed into the first waves of the block
   if (threadIdx.x < total) {
     const R q[3] = {L.dl[0][threadIdx.x], L.dl[1][threadIdx.x], L.dl[2][threadIdx.x]};

@@ -147,22 +147,6 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
   lds_barrier();
 }
 
-// Cull word of the fluid block of BS nodes with index fb: bit p set when the
-// support of particle p (centre c[p], squared radius cut2[p]) meets the
-// block's nodes.  Built by the prologue one launch ahead of the block.
-__device__ __forceinline__ unsigned long long fluid_cull_word(const DomView& V, int bs, int64_t fb,
-                                                              const double (*c)[3], const double* cut2) {
-  const uint32_t N = (uint32_t)V.N;
-  const uint32_t n0 = (uint32_t)fb * (uint32_t)bs;
-  const uint32_t n1 = (n0 + (uint32_t)bs - 1 < N) ? n0 + (uint32_t)bs - 1 : N - 1;
-  int lo[3], hi[3];
-  node_range_box(V, n0, n1, lo, hi);
-  unsigned long long bits = 0ull;
-  for (int p = 0; p < V.np; ++p)
-    if (support_meets_box(V, lo, hi, c[p], cut2[p])) bits |= 1ull << p;
-  return bits;
-}
-
 // Solid fraction of one particle at node nd: 1/2 + the signed distance
 // estimate 2 M (sqrt M - 1) / |grad M|, clamped to [0, 1] (Eq. 3, Eq. 17).
 //

@@ -6,26 +6,50 @@
 
 namespace rwmi {
 
-// Circular or plain gap between coordinate c and the interval [a, b].
-__device__ __forceinline__ double gap_to(int periodic, int L, double a, double b, double c) {
-  if (!periodic) {
-    if (c < a) return a - c;
-    if (c > b) return c - b;
-    return 0.0;
+// The cull words need only a superset of the particles that meet a block: a
+// walker with a candidate bit runs the exact sphere test, a fluid node the
+// exact support test.  So the prologue tests in float, with every radius
+// enlarged by kCullMargin lattice units, which covers the float rounding of
+// coordinates far beyond any lattice that fits in memory.
+constexpr float kCullMargin = 0.05f;
+
+// Lower bound on the distance from coordinate c to the interval [a, b] on an
+// axis of length L (circular when periodic; invL = 1 / L).
+__device__ __forceinline__ float gap_lb(int periodic, float L, float invL, float a, float b, float c) {
+  if (!periodic) return fmaxf(fmaxf(a - c, c - b), 0.0f);
+  float m = c - 0.5f * (a + b);
+  m = m - L * rintf(m * invL);
+  return fmaxf(fabsf(m) - 0.5f * (b - a), 0.0f);
+}
+
+// Bits p of the particles (centres c[p], squared enlarged radii r2[p]) whose
+// sphere meets the box [lo, hi].
+__device__ __forceinline__ unsigned long long box_bits(const DomView& V, const float lo[3], const float hi[3],
+                                                       const float (*c)[3], const float* r2) {
+  float L[3], invL[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    L[a] = (float)V.n[a];
+    invL[a] = 1.0f / L[a];
   }
-  const double hw = 0.5 * (b - a);
-  if (2.0 * hw >= (double)L) return 0.0;
-  double m = c - 0.5 * (a + b);
-  m = m - (double)L * floor(m / (double)L + 0.5);
-  const double g = fabs(m) - hw;
-  return g > 0.0 ? g : 0.0;
+  unsigned long long bits = 0ull;
+  for (int p = 0; p < V.np; ++p) {
+    float g2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float g = gap_lb(!V.bc[a], L[a], invL[a], lo[a], hi[a], c[p][a]);
+      g2 += g * g;
+    }
+    if (g2 <= r2[p]) bits |= 1ull << p;
+  }
+  return bits;
 }
 
 struct ProLds {
-  double c[kMaxParticles][3];   // centres at t + 1
-  double r[kMaxParticles];      // walker mask radius
-  double c0[kMaxParticles][3];  // centres at t
-  double cut2[kMaxParticles];   // squared solid-fraction support radius
+  float c1[kMaxParticles][3];  // centres at t + 1
+  float rm2[kMaxParticles];    // squared walker mask radius, enlarged
+  float c0[kMaxParticles][3];  // centres at t
+  float rc2[kMaxParticles];    // squared solid-fraction support radius, enlarged
 };
 
 // Prologue of step t (table slot t mod 3).  Block 0 of a domain writes the
@@ -33,13 +57,12 @@ struct ProLds {
 // (i = lb blockDim + threadIdx.x) builds
 // - word i of the coarse walker mask at P(t+1) in mask[slot]: bit p set when
 //   the sphere (c_p(t+1), rb_p + 1/2) meets coarse block i (extended to
-//   infinity beyond wall planes);
+//   infinity beyond wall planes), and possibly for particles just beyond;
 // - the cull word of fluid block i (blocks of bs nodes) at P(t) in
-//   fcull[slot].
+//   fcull[slot]: bit p set when the support (c_p(t), rb_p + 3/4) meets the
+//   block's node centres, and possibly for particles just beyond.
 // Every thread of the block calls it.
 __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_t t, int bs, ProLds& L) {
-  double (&sc)[kMaxParticles][3] = L.c;
-  double (&sr)[kMaxParticles] = L.r;
   const int ps = pose_slot(t);
   const int tid = threadIdx.x;
   if (tid < V.np) {
@@ -60,43 +83,48 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      sc[tid][a] = c1[a];
-      L.c0[tid][a] = c0[a];
+      L.c1[tid][a] = (float)c1[a];
+      L.c0[tid][a] = (float)c0[a];
     }
-    sr[tid] = P.maskr;
-    L.cut2[tid] = P.epscut2;
+    const float rm = (float)P.maskr + kCullMargin;
+    const float rc = (float)sqrt(P.epscut2) + kCullMargin;
+    L.rm2[tid] = rm * rm;
+    L.rc2[tid] = rc * rc;
   }
   lds_barrier();
   if (V.np == 0) return;
   const int64_t cb = (int64_t)lb * blockDim.x + tid;
   const int64_t nfb = (V.N + bs - 1) / bs;
-  if (cb < nfb) V.fcull[ps][cb] = fluid_cull_word(V, bs, cb, L.c0, L.cut2);
+  if (cb < nfb) {
+    // node centres of fluid block cb
+    const uint32_t N = (uint32_t)V.N;
+    const uint32_t n0 = (uint32_t)cb * (uint32_t)bs;
+    const uint32_t n1 = (n0 + (uint32_t)bs - 1 < N) ? n0 + (uint32_t)bs - 1 : N - 1;
+    int blo[3], bhi[3];
+    node_range_box(V, n0, n1, blo, bhi);
+    float lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = (float)blo[a] + 0.5f;
+      hi[a] = (float)bhi[a] + 0.5f;
+    }
+    V.fcull[ps][cb] = box_bits(V, lo, hi, L.c0, L.rc2);
+  }
   const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
   if (V.nw == 0 || cb >= nmb) return;
   const int bidx[3] = {(int)(cb % V.mb[0]), (int)((cb / V.mb[0]) % V.mb[1]), (int)(cb / ((int64_t)V.mb[0] * V.mb[1]))};
-  double lo[3], hi[3];
+  float lo[3], hi[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = (double)(bidx[a] * kMaskBlock);
+    lo[a] = (float)(bidx[a] * kMaskBlock);
     const int e = (bidx[a] + 1) * kMaskBlock;
-    hi[a] = (double)(e < V.n[a] ? e : V.n[a]);
+    hi[a] = (float)(e < V.n[a] ? e : V.n[a]);
     if (V.bc[a]) {
-      if (bidx[a] == 0) lo[a] = -1e300;
-      if (bidx[a] == V.mb[a] - 1) hi[a] = 1e300;
+      if (bidx[a] == 0) lo[a] = -1e30f;
+      if (bidx[a] == V.mb[a] - 1) hi[a] = 1e30f;
     }
   }
-  unsigned long long bits = 0ull;
-  for (int p = 0; p < V.np; ++p) {
-    double g2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double g = gap_to(!V.bc[a], V.n[a], lo[a], hi[a], sc[p][a]);
-      g2 += g * g;
-    }
-    const double r = sr[p];
-    if (g2 <= r * r * (1.0 + 1e-9) + 1e-9) bits |= (1ull << p);
-  }
-  V.mask[ps][cb] = bits;
+  V.mask[ps][cb] = box_bits(V, lo, hi, L.c1, L.rm2);
 }
 
 }  // namespace rwmi

@@ -21,6 +21,8 @@ namespace {
 
 thread_local std::string g_err = "no error";
 
+constexpr uint64_t kNeverSorted = ~0ull;  // sorted_at before the first regrouping
+
 struct HostParticle {
   std::vector<double> b, k;
   double c0[3], amp[3], vel[3], period, phase;
@@ -76,7 +78,7 @@ struct rwmi_domain {
   int bs = 256;  // threads per block of the step launch
   int flags = rwmi::kFlagXcd;
   int sort_every = 64;     // regroup walkers by coarse block every this many steps (0: never)
-  uint64_t sorted_at = 0;  // step of the last regrouping (host view)
+  uint64_t sorted_at = kNeverSorted;  // step of the last regrouping (host view)
   rwmi::SortScratch sort{};
   bool use_graph = false;
   bool timing = false;
@@ -333,7 +335,9 @@ hipEvent_t take_event(rwmi_domain* d) {
 bool sort_before(const rwmi_domain* d, uint32_t j, uint32_t n, bool capturing) {
   const uint32_t S = (uint32_t)d->sort_every;
   if (S == 0 || d->hv.nw == 0 || j >= n || j % S != 0) return false;
-  return j > 0 || capturing || d->steps - d->sorted_at >= S;
+  // seeded walkers come in id order, scattered over the lattice: the first
+  // group regroups them at its start
+  return j > 0 || capturing || d->sorted_at == kNeverSorted || d->steps - d->sorted_at >= S;
 }
 
 // A launch group of n coupled steps for one domain: the prologue-only launch

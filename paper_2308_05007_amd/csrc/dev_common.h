@@ -30,6 +30,10 @@ constexpr int kMaxParticles = 64;
 constexpr int kCounters = 8;
 enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect, kNearSurface };
 constexpr int kMaskBlock = 4;  // edge of a coarse block of the walker cull mask
+// The start cell's coarse mask word also covers the end of any walker step
+// with |dl| <= kMaskReach on every axis: the prologue dilates each coarse
+// block by that much.
+constexpr float kMaskReach = 1.0f;
 
 // Precision tags
 enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };

@@ -56,8 +56,9 @@ struct ProLds {
 // poses P(t), P(t+1) into pose[slot].  Thread i of the prologue blocks
 // (i = lb blockDim + threadIdx.x) builds
 // - word i of the coarse walker mask at P(t+1) in mask[slot]: bit p set when
-//   the sphere (c_p(t+1), rb_p + 1/2) meets coarse block i (extended to
-//   infinity beyond wall planes), and possibly for particles just beyond;
+//   the sphere (c_p(t+1), rb_p + 1/2) meets coarse block i dilated by
+//   kMaskReach (and extended to infinity beyond wall planes), and possibly
+//   for particles just beyond;
 // - the cull word of fluid block i (blocks of bs nodes) at P(t) in
 //   fcull[slot]: bit p set when the support (c_p(t), rb_p + 3/4) meets the
 //   block's node centres, and possibly for particles just beyond.
@@ -119,6 +120,10 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
     lo[a] = (float)(bidx[a] * kMaskBlock);
     const int e = (bidx[a] + 1) * kMaskBlock;
     hi[a] = (float)(e < V.n[a] ? e : V.n[a]);
+    // dilated by the walker mask reach: the word also serves the end point
+    // of a step of at most kMaskReach per axis from any cell of the block
+    lo[a] -= kMaskReach;
+    hi[a] += kMaskReach;
     if (V.bc[a]) {
       if (bidx[a] == 0) lo[a] = -1e30f;
       if (bidx[a] == V.mb[a] - 1) hi[a] = 1e30f;

@@ -78,18 +78,25 @@ __device__ __forceinline__ void particle_grad_at(const DomView& V, int ps, int p
   metaball_grad<R>(gp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz, g);
 }
 
-// Lowest index of a particle whose own M >= 1 at (c + x), or -1.  Particles
-// whose bounding sphere (rb + 1/2) is farther than the point are skipped: M < 1
-// there (bounding-radius lemma), so the result is that of testing all.
-// Is (c + x) within the sphere (c_p(t+1), rb_p + 1/2) of particle p?
+// Is (c + x) within the sphere (c_p(t+1), rb_p + 1/2) of particle p, enlarged
+// by kSphereMargin?  A float test on the spheres the walker block staged in
+// LDS; the margin covers the float rounding, so every point of the exact
+// sphere passes.  A walker it passes goes to the exact near-surface path.
+constexpr float kSphereMargin = 0.05f;
 template <typename R>
-__device__ __forceinline__ bool in_sphere(const DomView& V, int ps, int p, const int c[3], const R x[3]) {
-  const auto pc = pose_next(V, ps, p);
-  const R dx = axis_disp<R>(!V.bc[0], V.n[0], c[0], pc[0], x[0]);
-  const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
-  const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
-  const double mr = gp(V.parts)[p].maskr;
-  return (dx * dx + dy * dy) + dz * dz < (R)(mr * mr);
+__device__ __forceinline__ bool near_sphere(const DomView& V, const float (*sph)[4], int p, const int c[3],
+                                            const R x[3]) {
+  float d2 = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float d = ((float)c[a] + (float)x[a]) - sph[p][a];
+    if (!V.bc[a]) {
+      const float L = (float)V.n[a];
+      d = d - L * rintf(d * (1.0f / L));
+    }
+    d2 += d * d;
+  }
+  return d2 < sph[p][3];
 }
 
 template <typename R>
@@ -97,6 +104,9 @@ __device__ __forceinline__ unsigned long long mask_at(const DomView& V, int ps, 
   return gp((const unsigned long long*)V.mask[ps])[mask_index<R>(V, c, x)];
 }
 
+// Lowest index of a particle whose own M >= 1 at (c + x), or -1.  Particles
+// whose bounding sphere (rb + 1/2) is farther than the point are skipped: M < 1
+// there (bounding-radius lemma), so the result is that of testing all.
 template <typename R>
 __device__ __forceinline__ int inside_any(const DomView& V, int ps, const int c[3], const R x[3]) {
   // only the particles whose mask bit is set for the point's coarse block can
@@ -209,6 +219,7 @@ __device__ __forceinline__ void store_walker(const DomView& V, int64_t w, int c[
 // LDS of a walker block: the near-surface queue of its own walkers.
 template <typename R, int BS>
 struct WalkLds {
+  float sph[kMaxParticles][4];  // particle spheres at t+1: centre, enlarged squared radius
   uint32_t s_q[BS / 64], s_r[BS / 64];
   int32_t id[BS];
   R dl[3][BS];
@@ -226,19 +237,37 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
   using U = typename Store<P>::U;
   const int64_t w = lblock * BS + threadIdx.x;
   const bool active = w < V.nw;
+  const int ps = pose_slot(t);  // pose table and cull mask of step t
   bool queue = false;
   bool refl = false;
   R dl[3] = {(R)0, (R)0, (R)0};
+  int c[3] = {0, 0, 0};
+  R o[3] = {(R)0, (R)0, (R)0}, xf[3] = {(R)0, (R)0, (R)0};
+  unsigned long long bits0 = 0ull;
+  // particle spheres at t+1 for the candidate filter, staged while the
+  // walkers load
+  if (V.np > 0 && (int)threadIdx.x < V.np) {
+    const int p = threadIdx.x;
+    const auto pc = pose_next(V, ps, p);
+    const float r = (float)gp(V.parts)[p].maskr + kSphereMargin;
+    L.sph[p][0] = (float)pc[0];
+    L.sph[p][1] = (float)pc[1];
+    L.sph[p][2] = (float)pc[2];
+    L.sph[p][3] = r * r;
+  }
   if (active) {
     const int par = (int)(t & 1ull);  // velocity buffer of step t
-    const int ps = pose_slot(t);        // pose table and cull mask of step t
     const int nx = V.n[0], ny = V.n[1];
     const uint32_t lc = (uint32_t)gp(V.wcell)[w];
     const uint32_t q1 = fdiv(lc, V.dx);
     const int cz = (int)fdiv(q1, V.dy);
-    int c[3] = {(int)(lc - q1 * (uint32_t)nx), (int)q1 - cz * ny, cz};
+    c[0] = (int)(lc - q1 * (uint32_t)nx);
+    c[1] = (int)q1 - cz * ny;
+    c[2] = cz;
     const auto off = gp((const R*)V.woff);
-    const R o[3] = {off[w], off[V.nw + w], off[2 * V.nw + w]};
+    o[0] = off[w];
+    o[1] = off[V.nw + w];
+    o[2] = off[2 * V.nw + w];
     // trilinear interpolation between node centres
     int b0[3], b1[3];
     R wt[3];
@@ -258,9 +287,40 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
       b0[a] = b;
       b1[a] = b1a;
     }
-    // one vector load per corner: (ux, uy, uz, rho) of a node is 4 U
+    // one vector load per corner: (ux, uy, uz, rho) of a node is 4 U.  All
+    // eight are issued, with the cull-mask word of the start cell, before the
+    // normals are drawn, so that the Philox rounds run while they are in
+    // flight.
     using U4v = U __attribute__((ext_vector_type(4)));
     const auto u4 = gp((const U4v*)V.u4[par]);
+    U4v cu[2][2][2];
+#pragma unroll
+    for (int zz = 0; zz < 2; ++zz)
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy) {
+        const int y = yy ? b1[1] : b0[1], z = zz ? b1[2] : b0[2];
+        cu[zz][yy][0] = u4[lin(V, b0[0], y, z)];
+        cu[zz][yy][1] = u4[lin(V, b1[0], y, z)];
+      }
+    const R zero3[3] = {(R)0, (R)0, (R)0};
+    if (V.np > 0) bits0 = mask_at<R>(V, ps, c, zero3);
+    // Brownian step (Eq. 2 with dt = 1): normals of the walker id's Philox block
+    const U4 r = philox4x32_10((uint32_t)gp(V.wid)[w], (uint32_t)t, 0u, 0u, V.key0, V.key1);
+    R zn[3];
+    if constexpr (P == P64) {
+      double z0, z1, z2;
+      gauss3(r, z0, z1, z2);
+      zn[0] = z0 * V.sD;
+      zn[1] = z1 * V.sD;
+      zn[2] = z2 * V.sD;
+    } else {
+      float z0, z1, z2;
+      gauss3_fast(r, z0, z1, z2);
+      zn[0] = z0 * V.sD_f;
+      zn[1] = z1 * V.sD_f;
+      zn[2] = z2 * V.sD_f;
+    }
+    // trilinear interpolation of u(t): x, then y, then z
     R Ui[3];
     {
       R v[2][2][3];
@@ -268,8 +328,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
       for (int zz = 0; zz < 2; ++zz)
 #pragma unroll
         for (int yy = 0; yy < 2; ++yy) {
-          const int y = yy ? b1[1] : b0[1], z = zz ? b1[2] : b0[2];
-          const U4v lo4 = u4[lin(V, b0[0], y, z)], hi4 = u4[lin(V, b1[0], y, z)];
+          const U4v lo4 = cu[zz][yy][0], hi4 = cu[zz][yy][1];
           const R lo[3] = {(R)lo4.x, (R)lo4.y, (R)lo4.z}, hi[3] = {(R)hi4.x, (R)hi4.y, (R)hi4.z};
 #pragma unroll
           for (int cpt = 0; cpt < 3; ++cpt) v[zz][yy][cpt] = ((R)1 - wt[0]) * lo[cpt] + wt[0] * hi[cpt];
@@ -281,34 +340,25 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
         Ui[cpt] = ((R)1 - wt[2]) * v0 + wt[2] * v1;
       }
     }
-    // Brownian step (Eq. 2 with dt = 1)
-    const U4 r = philox4x32_10((uint32_t)gp(V.wid)[w], (uint32_t)t, 0u, 0u, V.key0, V.key1);
-    R xf[3];
-    if constexpr (P == P64) {
-      double z0, z1, z2;
-      gauss3(r, z0, z1, z2);
-      dl[0] = Ui[0] + z0 * V.sD;
-      dl[1] = Ui[1] + z1 * V.sD;
-      dl[2] = Ui[2] + z2 * V.sD;
-    } else {
-      float z0, z1, z2;
-      gauss3_fast(r, z0, z1, z2);
-      dl[0] = Ui[0] + z0 * V.sD_f;
-      dl[1] = Ui[1] + z1 * V.sD_f;
-      dl[2] = Ui[2] + z2 * V.sD_f;
-    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dl[a] = Ui[a] + zn[a];
 #pragma unroll
     for (int a = 0; a < 3; ++a) xf[a] = o[a] + dl[a];
+  }
+  if (V.np > 0) lds_barrier();  // particle spheres staged
+  if (active) {
     if (V.np > 0) {
       // a walker that starts and ends outside every bounding sphere is
       // neither type II nor IV (M < 1 outside rb); candidates come from the
-      // coarse mask, the exact sphere test decides
-      const R zero3[3] = {(R)0, (R)0, (R)0};
-      unsigned long long bits = mask_at<R>(V, ps, c, zero3) | mask_at<R>(V, ps, c, xf);
+      // coarse mask (the start word covers the end of a short step), the
+      // sphere filter decides
+      unsigned long long bits = bits0;
+      if (!(fabs(dl[0]) <= (R)kMaskReach && fabs(dl[1]) <= (R)kMaskReach && fabs(dl[2]) <= (R)kMaskReach))
+        bits |= mask_at<R>(V, ps, c, xf);
       while (bits && !queue) {
         const int p = __ffsll((long long)bits) - 1;
         bits &= bits - 1ull;
-        queue = in_sphere<R>(V, ps, p, c, o) || in_sphere<R>(V, ps, p, c, xf);
+        queue = near_sphere<R>(V, L.sph, p, c, o) || near_sphere<R>(V, L.sph, p, c, xf);
       }
     }
     if (!queue) {
@@ -329,7 +379,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
             while (bits && !queue) {
               const int p = __ffsll((long long)bits) - 1;
               bits &= bits - 1ull;
-              queue = in_sphere<R>(V, ps, p, c, xn);  // the reflected point may be inside a particle
+              queue = near_sphere<R>(V, L.sph, p, c, xn);  // the reflected point may be inside a particle
             }
             if (queue) refl = false;
           }

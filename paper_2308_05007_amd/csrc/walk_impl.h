@@ -213,7 +213,7 @@ __device__ __forceinline__ void store_walker(const DomView& V, int64_t w, int c[
     c[a] = cc;
     off[a * nw + w] = of;
   }
-  gp(V.wcell)[w] = (int32_t)lin(V, c[0], c[1], c[2]);
+  gp(V.wcell)[w] = (int32_t)((uint32_t)c[0] + (uint32_t)V.n[0] * ((uint32_t)c[1] + (uint32_t)V.n[1] * (uint32_t)c[2]));
 }
 
 // LDS of a walker block: the near-surface queue of its own walkers.
@@ -293,14 +293,20 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
     // flight.
     using U4v = U __attribute__((ext_vector_type(4)));
     const auto u4 = gp((const U4v*)V.u4[par]);
+    // node indices in 32 bits (fewer than 2^31 nodes): corner (0,0,0) plus
+    // per-axis steps to the upper corner, which wrap on periodic axes
+    const uint32_t unx = (uint32_t)nx, unxy = unx * (uint32_t)ny;
+    const uint32_t i000 = (uint32_t)b0[0] + unx * ((uint32_t)b0[1] + (uint32_t)ny * (uint32_t)b0[2]);
+    const uint32_t sx = (uint32_t)(b1[0] - b0[0]), sy = (uint32_t)(b1[1] - b0[1]) * unx,
+                   sz = (uint32_t)(b1[2] - b0[2]) * unxy;
     U4v cu[2][2][2];
 #pragma unroll
     for (int zz = 0; zz < 2; ++zz)
 #pragma unroll
       for (int yy = 0; yy < 2; ++yy) {
-        const int y = yy ? b1[1] : b0[1], z = zz ? b1[2] : b0[2];
-        cu[zz][yy][0] = u4[lin(V, b0[0], y, z)];
-        cu[zz][yy][1] = u4[lin(V, b1[0], y, z)];
+        const uint32_t i0 = i000 + (yy ? sy : 0u) + (zz ? sz : 0u);
+        cu[zz][yy][0] = u4[i0];
+        cu[zz][yy][1] = u4[i0 + sx];
       }
     const R zero3[3] = {(R)0, (R)0, (R)0};
     if (V.np > 0) bits0 = mask_at<R>(V, ps, c, zero3);

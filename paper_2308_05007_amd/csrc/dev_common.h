@@ -327,13 +327,16 @@ __device__ __forceinline__ void particle_pose(const DevParticle& p, uint64_t t, 
 
 // ------------------------------------------------------------------ geometry
 // Displacement from a particle centre cp to (cell + x) along one axis, with
-// the minimum image r - L floor(r / L + 1/2) on periodic axes.
+// the minimum image r - L floor(r / L + 1/2) on periodic axes.  In float the
+// image is r - L rint(r / L) with a hardware reciprocal: it can differ from
+// the FP64 choice only where |r| is within rounding of L / 2, where both
+// images are equally far.
 template <typename R>
 __device__ __forceinline__ R axis_disp(int periodic, int L, int cell, double cp, R x) {
   R r = (R)((double)cell - cp) + x;
   if (periodic) {
     const R Lr = (R)L;
-    r = r - Lr * floor(r / Lr + (R)0.5);
+    r = r - Lr * rintf(r * __builtin_amdgcn_rcpf(Lr));
   }
   return r;
 }

@@ -151,6 +151,21 @@ def test_sweeping_particle_types_2_and_4(orc, B):
     assert c["type2"] > 0 and c["type4"] > 0
 
 
+@pytest.mark.parametrize("n,bc", [((9, 6, 10), ("periodic", "wall", "periodic")),
+                                  ((3, 7, 4), ("periodic", "periodic", "wall"))])
+def test_long_steps_near_particles(orc, B, n, bc):
+    """D = 0.5 (sqrt(2D) = 1): many steps are longer than a cell on some axis,
+    so the fast path must look up the end point's coarse-mask word as well
+    (shorter steps rely on the start word's dilated block); the second lattice
+    is narrower than a coarse block on two axes."""
+    cfg = W.config_tiny(n=n, bc=bc, n_particles=3, n_walkers=600, D=0.5, spread=1.0, seed=21, steps=8)
+    o, g = _pair(orc, B, cfg)
+    for chunk in (1, 3, 4):
+        o.step(chunk)
+        g.step(chunk)
+        compare(o, g)
+
+
 def test_forced_bisection_failure(orc, B):
     cfg = W.config_plain_fp64(scale=0.2)
     cfg["domain"]["D"] = 0.05

@@ -236,7 +236,7 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles
  *                            share of walker blocks interleaved (default on), bit 1
  *                            writes f* and (u, rho) with non-temporal stores
  *   RWMI_KEY_SORT_EVERY      regroup the walkers by coarse block (4^3 nodes) every this
- *                            many steps for memory locality (default 64, 0 = never)
+ *                            many steps for memory locality (default 128, 0 = never)
  *   RWMI_KEY_STREAMING       1: two lattices (pull from one, write the other); 2: one
  *                            lattice streamed in place.  Default: in place while the 19
  *                            distributions take at most 192 MB, else two lattices.

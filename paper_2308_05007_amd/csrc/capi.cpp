@@ -77,7 +77,7 @@ struct rwmi_domain {
   double ref[3] = {0, 0, 0};
   int bs = 256;  // threads per block of the step launch
   int flags = rwmi::kFlagXcd;
-  int sort_every = 64;     // regroup walkers by coarse block every this many steps (0: never)
+  int sort_every = 128;    // regroup walkers by coarse block every this many steps (0: never)
   uint64_t sorted_at = kNeverSorted;  // step of the last regrouping (host view)
   rwmi::SortScratch sort{};
   bool use_graph = false;

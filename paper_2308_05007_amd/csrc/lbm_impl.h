@@ -7,10 +7,11 @@
 // population that will bounce off a wall node.  A step gathers
 // f_i(x, t) = f*_i(x - e_i, t-1) (or the bounced f*_opp(i)(x) when x - e_i is
 // a wall node), computes rho, u (Eq. 14-15, Guo half-force velocity), the
-// solid fraction eps and solid velocity u_s of the metaballs culled for the
-// block (Eq. 3, Eq. 17), collides (BGK, Eq. 12-13, Noble-Torczynski
-// weighting, Guo source) and writes f*(t) in place of the node's own slots of
-// the other buffer, plus (u, rho).
+// solid fraction eps and solid velocity u_s of the metaballs in the block's
+// cull word (Eq. 3, Eq. 17), collides (BGK, Eq. 12-13, Noble-Torczynski
+// weighting, Guo source) and writes f*(t), plus (u, rho).  Two lattices: the
+// node's own slots of the other buffer.  One lattice streamed in place: the
+// node's opposite slots on even steps, the neighbours' slots on odd steps.
 #pragma once
 #include <type_traits>
 

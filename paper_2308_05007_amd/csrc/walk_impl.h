@@ -3,8 +3,11 @@
 //
 // Fast path (one thread per walker slot): trilinear interpolation of u(t)
 // between node centres (x, then y, then z), three normals from the Philox
-// block (id, t, 0, 0) of the walker id the slot holds, step dl = u + z sqrt(2D).  The coarse cull mask of the
-// particles at t+1 is looked up at the start and end cells; a walker with no
+// block (id, t, 0, 0) of the walker id the slot holds, step
+// dl = u + z sqrt(2D).  The coarse cull mask of the particles at t+1 gives
+// the candidates at the start cell (its dilated block covers the end of a
+// short step) and, for a long step, at the end cell; float bounding-sphere
+// tests on the block's staged spheres filter them.  A walker with no
 // candidate particle at either end can be neither type II nor IV (Sec.
 // 2.4.2), so it is moved here (walls, renormalisation).  Walkers with a
 // candidate are compacted into the block's LDS queue with a wavefront ballot.

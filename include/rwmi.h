@@ -239,7 +239,7 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles
  *                            many steps for memory locality (default 128, 0 = never)
  *   RWMI_KEY_STREAMING       1: two lattices (pull from one, write the other); 2: one
  *                            lattice streamed in place.  Default: in place while the 19
- *                            distributions take at most 192 MB, else two lattices.
+ *                            distributions take at most 384 MB, else two lattices.
  *                            Only before the first step (ESTATE after); resets f to f^eq
  * Results never depend on the block size, flags or sort interval: walker ids
  * travel with the walkers and every read-out is by id. */

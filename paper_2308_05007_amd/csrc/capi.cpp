@@ -37,12 +37,12 @@ struct Alloc {
 
 size_t elem_size(int prec) { return prec == RWMI_FP64 ? 8 : (prec == RWMI_FP32 ? 4 : 2); }
 
-// One lattice streamed in place while the distributions fit in a budget that
-// the memory-side cache (256 MB on this part) can hold beside the velocity
-// and walkers: then the in-place pattern runs from that cache.  Larger
-// lattices keep two lattices, whose pull pattern streams from HBM a little
-// faster than the in-place pattern does.
-constexpr uint64_t kInPlaceMaxBytes = 192ull << 20;
+// One lattice streamed in place while the distributions take at most 384 MB:
+// up to about that size the in-place pattern, partly served by the 256 MB
+// memory-side cache, beats the two-lattice pull (measured with real data:
+// 3-5% faster at 227-319 MB of distributions, 2-3% slower at 427-538 MB).
+// Larger lattices keep two lattices.
+constexpr uint64_t kInPlaceMaxBytes = 384ull << 20;
 bool default_inplace(const rwmi_domain_desc& s) {
   const uint64_t N = (uint64_t)s.n[0] * s.n[1] * s.n[2];
   return 19 * N * elem_size(s.precision) <= kInPlaceMaxBytes;

@@ -289,6 +289,8 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   if ((st = alloc_into(d, dc, sizeof(double) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
   if ((st = alloc_into(d, dcf, sizeof(float) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
   if ((st = alloc_into(d, dpose, sizeof(double) * 36 * std::max(np, 1))) != RWMI_OK) return st;
+  float* dsph;
+  if ((st = alloc_into(d, dsph, sizeof(float) * 12 * std::max(np, 1))) != RWMI_OK) return st;
   HIPCHK(d, hipMemcpyAsync(dp, hp.data(), sizeof(DevParticle) * hp.size(), hipMemcpyHostToDevice, d->stream));
   if (!ctrl.empty()) {
     HIPCHK(d, hipMemcpyAsync(dc, ctrl.data(), sizeof(double) * ctrl.size(), hipMemcpyHostToDevice, d->stream));
@@ -298,7 +300,10 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   d->hv.parts = dp;
   d->hv.ctrl = dc;
   d->hv.ctrl_f = dcf;
-  for (int k = 0; k < 3; ++k) d->hv.pose[k] = dpose + 12 * std::max(np, 1) * k;
+  for (int k = 0; k < 3; ++k) {
+    d->hv.pose[k] = dpose + 12 * std::max(np, 1) * k;
+    d->hv.sph[k] = dsph + 4 * std::max(np, 1) * k;
+  }
   d->hv.np = np;
   if (np > 0) {
     unsigned long long* mask;
@@ -400,7 +405,7 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   uint64_t b = 0;
   b += (default_inplace(*s) ? 1 : 2) * 19 * N * elem_size(p) + 8 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
-  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + 288 * n_particles +
+  b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + (288 + 48) * n_particles +
        (n_particles ? 24 * nmb + 24 * (uint64_t)fcull_words((int64_t)N) : 0);
   // walkers: cell, offsets, images, id and slot maps; sort scratch (bin, rank
   // and a second copy of the walker record) and the bin counts

@@ -34,6 +34,9 @@ constexpr int kMaskBlock = 4;  // edge of a coarse block of the walker cull mask
 // with |dl| <= kMaskReach on every axis: the prologue dilates each coarse
 // block by that much.
 constexpr float kMaskReach = 1.0f;
+// The fast path's float bounding-sphere filter enlarges every radius by this
+// many lattice units, which covers the float rounding of its test.
+constexpr float kSphereMargin = 0.05f;
 
 // Precision tags
 enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
@@ -102,6 +105,8 @@ struct DomView {
   const double* ctrl;             // 4 per control point: bx, by, bz, k
   const float* ctrl_f;            // the same in float (low-precision modes)
   double* pose[3];                // per step t, slot t mod 3: [2][np][6] (c, v) at t and t+1
+  float* sph[3];                  // per step t, slot t mod 3: [np][4] walker filter spheres at
+                                  // t+1: centre, (rb + 1/2 + kSphereMargin)^2
   uint64_t* tstep;                // [0] steps completed before the current launch group
   unsigned long long* mask[3];    // per step t, slot t mod 3: coarse cull mask at P(t+1)
   unsigned long long* fcull[3];   // per step t, slot t mod 3: bit p set when particle p's

@@ -53,7 +53,8 @@ struct ProLds {
 };
 
 // Prologue of step t (table slot t mod 3).  Block 0 of a domain writes the
-// poses P(t), P(t+1) into pose[slot].  Thread i of the prologue blocks
+// poses P(t), P(t+1) into pose[slot] and the walkers' filter spheres at t+1
+// into sph[slot].  Thread i of the prologue blocks
 // (i = lb blockDim + threadIdx.x) builds
 // - word i of the coarse walker mask at P(t+1) in mask[slot]: bit p set when
 //   the sphere (c_p(t+1), rb_p + 1/2) meets coarse block i dilated by
@@ -81,6 +82,11 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
         pn[a] = c1[a];
         pn[3 + a] = v1[a];
       }
+      // the walkers' filter sphere at t+1, one 16-byte record
+      using F4 = float __attribute__((ext_vector_type(4)));
+      const float rs = (float)P.maskr + kSphereMargin;
+      const F4 sp = {(float)c1[0], (float)c1[1], (float)c1[2], rs * rs};
+      *gp((F4*)V.sph[ps] + tid) = sp;
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

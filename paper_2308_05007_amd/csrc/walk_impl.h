@@ -82,24 +82,25 @@ __device__ __forceinline__ void particle_grad_at(const DomView& V, int ps, int p
 }
 
 // Is (c + x) within the sphere (c_p(t+1), rb_p + 1/2) of particle p, enlarged
-// by kSphereMargin?  A float test on the spheres the walker block staged in
-// LDS; the margin covers the float rounding, so every point of the exact
+// by kSphereMargin?  A float test on the sphere table the prologue wrote for
+// step t; the margin covers the float rounding, so every point of the exact
 // sphere passes.  A walker it passes goes to the exact near-surface path.
-constexpr float kSphereMargin = 0.05f;
 template <typename R>
-__device__ __forceinline__ bool near_sphere(const DomView& V, const float (*sph)[4], int p, const int c[3],
-                                            const R x[3]) {
+__device__ __forceinline__ bool near_sphere(const DomView& V, int ps, int p, const int c[3], const R x[3]) {
+  using F4 = float __attribute__((ext_vector_type(4)));
+  const F4 sp = gp((const F4*)V.sph[ps])[p];
+  const float sc[3] = {sp.x, sp.y, sp.z};
   float d2 = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float d = ((float)c[a] + (float)x[a]) - sph[p][a];
+    float d = ((float)c[a] + (float)x[a]) - sc[a];
     if (!V.bc[a]) {
       const float L = (float)V.n[a];
       d = d - L * rintf(d * (1.0f / L));
     }
     d2 += d * d;
   }
-  return d2 < sph[p][3];
+  return d2 < sp.w;
 }
 
 template <typename R>
@@ -222,7 +223,6 @@ __device__ __forceinline__ void store_walker(const DomView& V, int64_t w, int c[
 // LDS of a walker block: the near-surface queue of its own walkers.
 template <typename R, int BS>
 struct WalkLds {
-  float sph[kMaxParticles][4];  // particle spheres at t+1: centre, enlarged squared radius
   uint32_t s_q[BS / 64], s_r[BS / 64];
   int32_t id[BS];
   R dl[3][BS];
@@ -247,17 +247,6 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
   int c[3] = {0, 0, 0};
   R o[3] = {(R)0, (R)0, (R)0}, xf[3] = {(R)0, (R)0, (R)0};
   unsigned long long bits0 = 0ull;
-  // particle spheres at t+1 for the candidate filter, staged while the
-  // walkers load
-  if (V.np > 0 && (int)threadIdx.x < V.np) {
-    const int p = threadIdx.x;
-    const auto pc = pose_next(V, ps, p);
-    const float r = (float)gp(V.parts)[p].maskr + kSphereMargin;
-    L.sph[p][0] = (float)pc[0];
-    L.sph[p][1] = (float)pc[1];
-    L.sph[p][2] = (float)pc[2];
-    L.sph[p][3] = r * r;
-  }
   if (active) {
     const int par = (int)(t & 1ull);  // velocity buffer of step t
     const int nx = V.n[0], ny = V.n[1];
@@ -353,9 +342,6 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
     for (int a = 0; a < 3; ++a) dl[a] = Ui[a] + zn[a];
 #pragma unroll
     for (int a = 0; a < 3; ++a) xf[a] = o[a] + dl[a];
-  }
-  if (V.np > 0) lds_barrier();  // particle spheres staged
-  if (active) {
     if (V.np > 0) {
       // a walker that starts and ends outside every bounding sphere is
       // neither type II nor IV (M < 1 outside rb); candidates come from the
@@ -367,7 +353,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
       while (bits && !queue) {
         const int p = __ffsll((long long)bits) - 1;
         bits &= bits - 1ull;
-        queue = near_sphere<R>(V, L.sph, p, c, o) || near_sphere<R>(V, L.sph, p, c, xf);
+        queue = near_sphere<R>(V, ps, p, c, o) || near_sphere<R>(V, ps, p, c, xf);
       }
     }
     if (!queue) {
@@ -388,7 +374,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
             while (bits && !queue) {
               const int p = __ffsll((long long)bits) - 1;
               bits &= bits - 1ull;
-              queue = near_sphere<R>(V, L.sph, p, c, xn);  // the reflected point may be inside a particle
+              queue = near_sphere<R>(V, ps, p, c, xn);  // the reflected point may be inside a particle
             }
             if (queue) refl = false;
           }

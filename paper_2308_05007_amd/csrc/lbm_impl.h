@@ -66,16 +66,23 @@ __device__ __forceinline__ int wave_exclusive_sum(int x) {
 }
 
 // Bounding box, in node indices, of the node range [n0, n1] (x fastest).
-__device__ __forceinline__ void node_range_box(const DomView& V, uint32_t n0, uint32_t n1, int lo[3], int hi[3]) {
-  const int nx = V.n[0], ny = V.n[1];
-  const uint32_t a0 = fdiv(n0, V.dx), a1 = fdiv(n1, V.dx);
-  const int z0 = (int)fdiv(a0, V.dy), z1 = (int)fdiv(a1, V.dy);
+// Bounding box, in grid indices, of the linear index range [n0, n1] of an
+// nx x ny x nz grid (x fastest; dx, dy divide by nx, ny).
+__device__ __forceinline__ void index_range_box(uint32_t n0, uint32_t n1, const FastDiv& dx, const FastDiv& dy, int nx,
+                                                int ny, int lo[3], int hi[3]) {
+  const uint32_t a0 = fdiv(n0, dx), a1 = fdiv(n1, dx);
+  const int z0 = (int)fdiv(a0, dy), z1 = (int)fdiv(a1, dy);
   const int x0 = (int)(n0 - a0 * (uint32_t)nx), x1 = (int)(n1 - a1 * (uint32_t)nx);
   const int y0 = (int)a0 - z0 * ny, y1 = (int)a1 - z1 * ny;
   lo[2] = z0; hi[2] = z1;
   if (z0 == z1 && y0 == y1) { lo[0] = x0; hi[0] = x1; lo[1] = y0; hi[1] = y0; }
   else if (z0 == z1) { lo[0] = 0; hi[0] = nx - 1; lo[1] = y0; hi[1] = y1; }
   else { lo[0] = 0; hi[0] = nx - 1; lo[1] = 0; hi[1] = ny - 1; }
+}
+
+// Bounding box, in node indices, of the node range [n0, n1].
+__device__ __forceinline__ void node_range_box(const DomView& V, uint32_t n0, uint32_t n1, int lo[3], int hi[3]) {
+  index_range_box(n0, n1, V.dx, V.dy, V.n[0], V.n[1], lo, hi);
 }
 
 // Does the solid-fraction support (squared radius cut2 about centre pc) meet

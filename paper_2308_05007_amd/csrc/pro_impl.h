@@ -22,27 +22,66 @@ __device__ __forceinline__ float gap_lb(int periodic, float L, float invL, float
   return fmaxf(fabsf(m) - 0.5f * (b - a), 0.0f);
 }
 
-// Bits p of the particles (centres c[p], squared enlarged radii r2[p]) whose
-// sphere meets the box [lo, hi].
-__device__ __forceinline__ unsigned long long box_bits(const DomView& V, const float lo[3], const float hi[3],
-                                                       const float (*c)[3], const float* r2) {
-  float L[3], invL[3];
+// Does the sphere (centre c, squared enlarged radius r2) meet the box
+// [lo, hi]?
+__device__ __forceinline__ bool sphere_meets(const DomView& V, const float lo[3], const float hi[3], const float c[3],
+                                             float r2) {
+  float g2 = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    L[a] = (float)V.n[a];
-    invL[a] = 1.0f / L[a];
+    const float L = (float)V.n[a];
+    const float g = gap_lb(!V.bc[a], L, 1.0f / L, lo[a], hi[a], c[a]);
+    g2 += g * g;
   }
+  return g2 <= r2;
+}
+
+// Bits p, among the candidates `cand`, of the particles (centres c[p],
+// squared enlarged radii r2[p]) whose sphere meets the box [lo, hi].
+__device__ __forceinline__ unsigned long long box_bits(const DomView& V, const float lo[3], const float hi[3],
+                                                       const float (*c)[3], const float* r2, unsigned long long cand) {
   unsigned long long bits = 0ull;
-  for (int p = 0; p < V.np; ++p) {
-    float g2 = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float g = gap_lb(!V.bc[a], L[a], invL[a], lo[a], hi[a], c[p][a]);
-      g2 += g * g;
-    }
-    if (g2 <= r2[p]) bits |= 1ull << p;
+  while (cand) {
+    const int p = __ffsll((long long)cand) - 1;
+    cand &= cand - 1ull;
+    if (sphere_meets(V, lo, hi, c[p], r2[p])) bits |= 1ull << p;
   }
   return bits;
+}
+
+// Node-centre box of the fluid blocks [f0, f1] (bs nodes each).
+__device__ __forceinline__ void fluid_blocks_box(const DomView& V, int bs, int64_t f0, int64_t f1, float lo[3],
+                                                 float hi[3]) {
+  const uint32_t N = (uint32_t)V.N;
+  const uint32_t n0 = (uint32_t)f0 * (uint32_t)bs;
+  const uint32_t e = (uint32_t)(f1 + 1) * (uint32_t)bs;
+  const uint32_t n1 = (e < N ? e : N) - 1;
+  int blo[3], bhi[3];
+  node_range_box(V, n0, n1, blo, bhi);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = (float)blo[a] + 0.5f;
+    hi[a] = (float)bhi[a] + 0.5f;
+  }
+}
+
+// Box of the coarse mask blocks [m0, m1], dilated by the walker mask reach
+// (the word also serves the end point of a step of at most kMaskReach per
+// axis from any cell of the block) and extended to infinity beyond wall
+// planes.
+__device__ __forceinline__ void mask_blocks_box(const DomView& V, int64_t m0, int64_t m1, float lo[3], float hi[3]) {
+  int blo[3], bhi[3];
+  index_range_box((uint32_t)m0, (uint32_t)m1, V.dmx, V.dmy, V.mb[0], V.mb[1], blo, bhi);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int e = (bhi[a] + 1) * kMaskBlock;
+    lo[a] = (float)(blo[a] * kMaskBlock) - kMaskReach;
+    hi[a] = (float)(e < V.n[a] ? e : V.n[a]) + kMaskReach;
+    if (V.bc[a]) {
+      if (blo[a] == 0) lo[a] = -1e30f;
+      if (bhi[a] == V.mb[a] - 1) hi[a] = 1e30f;
+    }
+  }
 }
 
 struct ProLds {
@@ -50,6 +89,7 @@ struct ProLds {
   float rm2[kMaxParticles];    // squared walker mask radius, enlarged
   float c0[kMaxParticles][3];  // centres at t
   float rc2[kMaxParticles];    // squared solid-fraction support radius, enlarged
+  unsigned long long cand_f, cand_m;  // particles that meet the block's whole range
 };
 
 // Prologue of step t (table slot t mod 3).  Block 0 of a domain writes the
@@ -63,7 +103,9 @@ struct ProLds {
 // - the cull word of fluid block i (blocks of bs nodes) at P(t) in
 //   fcull[slot]: bit p set when the support (c_p(t), rb_p + 3/4) meets the
 //   block's node centres, and possibly for particles just beyond.
-// Every thread of the block calls it.
+// Each thread tests only the particles that meet the bounding box of its
+// prologue block's whole range of words.  Every thread of the block calls
+// it.
 __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_t t, int bs, ProLds& L) {
   const int ps = pose_slot(t);
   const int tid = threadIdx.x;
@@ -98,44 +140,46 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
     L.rm2[tid] = rm * rm;
     L.rc2[tid] = rc * rc;
   }
-  lds_barrier();
-  if (V.np == 0) return;
-  const int64_t cb = (int64_t)lb * blockDim.x + tid;
+  if (V.np == 0) return;  // uniform: no barrier is skipped by part of the block
+  // candidates of the whole block (a superset for each of its words): the
+  // particles whose sphere meets the bounding box of the block's fluid blocks
+  // or coarse blocks; wave 0 holds every particle (at most 64)
+  const int64_t c0i = (int64_t)lb * blockDim.x;
+  const int64_t c1i = c0i + blockDim.x - 1;
   const int64_t nfb = (V.N + bs - 1) / bs;
-  if (cb < nfb) {
-    // node centres of fluid block cb
-    const uint32_t N = (uint32_t)V.N;
-    const uint32_t n0 = (uint32_t)cb * (uint32_t)bs;
-    const uint32_t n1 = (n0 + (uint32_t)bs - 1 < N) ? n0 + (uint32_t)bs - 1 : N - 1;
-    int blo[3], bhi[3];
-    node_range_box(V, n0, n1, blo, bhi);
-    float lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = (float)blo[a] + 0.5f;
-      hi[a] = (float)bhi[a] + 0.5f;
-    }
-    V.fcull[ps][cb] = box_bits(V, lo, hi, L.c0, L.rc2);
-  }
   const int64_t nmb = (int64_t)V.mb[0] * V.mb[1] * V.mb[2];
-  if (V.nw == 0 || cb >= nmb) return;
-  const int bidx[3] = {(int)(cb % V.mb[0]), (int)((cb / V.mb[0]) % V.mb[1]), (int)(cb / ((int64_t)V.mb[0] * V.mb[1]))};
-  float lo[3], hi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = (float)(bidx[a] * kMaskBlock);
-    const int e = (bidx[a] + 1) * kMaskBlock;
-    hi[a] = (float)(e < V.n[a] ? e : V.n[a]);
-    // dilated by the walker mask reach: the word also serves the end point
-    // of a step of at most kMaskReach per axis from any cell of the block
-    lo[a] -= kMaskReach;
-    hi[a] += kMaskReach;
-    if (V.bc[a]) {
-      if (bidx[a] == 0) lo[a] = -1e30f;
-      if (bidx[a] == V.mb[a] - 1) hi[a] = 1e30f;
+  if (tid < 64) {
+    bool inf = false, inm = false;
+    if (tid < V.np) {
+      float lo[3], hi[3];
+      if (c0i < nfb) {
+        fluid_blocks_box(V, bs, c0i, c1i < nfb ? c1i : nfb - 1, lo, hi);
+        const float c[3] = {L.c0[tid][0], L.c0[tid][1], L.c0[tid][2]};
+        inf = sphere_meets(V, lo, hi, c, L.rc2[tid]);
+      }
+      if (V.nw > 0 && c0i < nmb) {
+        mask_blocks_box(V, c0i, c1i < nmb ? c1i : nmb - 1, lo, hi);
+        const float c[3] = {L.c1[tid][0], L.c1[tid][1], L.c1[tid][2]};
+        inm = sphere_meets(V, lo, hi, c, L.rm2[tid]);
+      }
+    }
+    const unsigned long long bf = __ballot(inf), bm = __ballot(inm);
+    if (tid == 0) {
+      L.cand_f = bf;
+      L.cand_m = bm;
     }
   }
-  V.mask[ps][cb] = box_bits(V, lo, hi, L.c1, L.rm2);
+  lds_barrier();
+  const int64_t cb = c0i + tid;
+  if (cb < nfb) {
+    float lo[3], hi[3];
+    fluid_blocks_box(V, bs, cb, cb, lo, hi);
+    V.fcull[ps][cb] = box_bits(V, lo, hi, L.c0, L.rc2, L.cand_f);
+  }
+  if (V.nw == 0 || cb >= nmb) return;
+  float lo[3], hi[3];
+  mask_blocks_box(V, cb, cb, lo, hi);
+  V.mask[ps][cb] = box_bits(V, lo, hi, L.c1, L.rm2, L.cand_m);
 }
 
 }  // namespace rwmi

@@ -108,6 +108,14 @@ __device__ __forceinline__ unsigned long long mask_at(const DomView& V, int ps, 
   return gp((const unsigned long long*)V.mask[ps])[mask_index<R>(V, c, x)];
 }
 
+// Coarse mask word of the cell c itself (c inside the lattice).
+__device__ __forceinline__ unsigned long long mask_at_cell(const DomView& V, int ps, const int c[3]) {
+  static_assert(kMaskBlock == 4, "coarse block index by shift");
+  const uint32_t i = ((uint32_t)c[0] >> 2) +
+                     (uint32_t)V.mb[0] * (((uint32_t)c[1] >> 2) + (uint32_t)V.mb[1] * ((uint32_t)c[2] >> 2));
+  return gp((const unsigned long long*)V.mask[ps])[i];
+}
+
 // Lowest index of a particle whose own M >= 1 at (c + x), or -1.  Particles
 // whose bounding sphere (rb + 1/2) is farther than the point are skipped: M < 1
 // there (bounding-radius lemma), so the result is that of testing all.
@@ -300,8 +308,7 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
         cu[zz][yy][0] = u4[i0];
         cu[zz][yy][1] = u4[i0 + sx];
       }
-    const R zero3[3] = {(R)0, (R)0, (R)0};
-    if (V.np > 0) bits0 = mask_at<R>(V, ps, c, zero3);
+    if (V.np > 0) bits0 = mask_at_cell(V, ps, c);
     // Brownian step (Eq. 2 with dt = 1): normals of the walker id's Philox block
     const U4 r = philox4x32_10((uint32_t)gp(V.wid)[w], (uint32_t)t, 0u, 0u, V.key0, V.key1);
     R zn[3];

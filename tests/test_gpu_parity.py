@@ -166,6 +166,22 @@ def test_long_steps_near_particles(orc, B, n, bc):
         compare(o, g)
 
 
+def test_maximum_particle_count(orc, B):
+    """64 overlapping metaballs (the limit): every bit of the cull and mask
+    words, full-wave ballots in the prologue, the lowest-index rule where
+    particles overlap."""
+    cfg = W.config_tiny(n=(20, 18, 22), bc=("periodic", "wall", "periodic"), n_particles=64, n_walkers=3000,
+                        D=0.05, spread=0.7, seed=31, steps=6, amp=1.0)
+    assert len(cfg["particles"]) == 64
+    o, g = _pair(orc, B, cfg)
+    for chunk in (1, 2, 3):
+        o.step(chunk)
+        g.step(chunk)
+        compare(o, g)
+    c = o.counters()
+    assert c["type2"] > 0 and c["type4"] > 0
+
+
 def test_forced_bisection_failure(orc, B):
     cfg = W.config_plain_fp64(scale=0.2)
     cfg["domain"]["D"] = 0.05

@@ -7,7 +7,7 @@
 // dl = u + z sqrt(2D).  The coarse cull mask of the particles at t+1 gives
 // the candidates at the start cell (its dilated block covers the end of a
 // short step) and, for a long step, at the end cell; float bounding-sphere
-// tests on the block's staged spheres filter them.  A walker with no
+// tests on the prologue's sphere table filter them.  A walker with no
 // candidate particle at either end can be neither type II nor IV (Sec.
 // 2.4.2), so it is moved here (walls, renormalisation).  Walkers with a
 // candidate are compacted into the block's LDS queue with a wavefront ballot.

@@ -114,7 +114,8 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
 __global__ void k_occupancy(const DomView* __restrict__ views, int dom) {
   const DomView& V = views[dom];
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w < V.nw) atomicAdd(&V.occ[V.wcell[w]], 1u);
+  if (w < V.nw)
+    __hip_atomic_fetch_add(gp(V.occ) + gp(V.wcell)[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- moments

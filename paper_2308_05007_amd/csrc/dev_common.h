@@ -135,6 +135,13 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Event counter increment: a relaxed device-scope atomic on the global
+// address space (a global, not a flat, atomic instruction).
+__device__ __forceinline__ void counter_add(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long*)p, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Constant-address-space view of a pointer to data that no block of the
 // running launch writes: wave-uniform loads through it compile to scalar
 // loads.

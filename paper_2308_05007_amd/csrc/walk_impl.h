@@ -366,14 +366,14 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
     if (!queue) {
       R xn[3] = {xf[0], xf[1], xf[2]};
       if (!finite3<R>(xn)) {
-        atomicAdd(&V.counters[kReturned], 1ull);
+        counter_add(&V.counters[kReturned], 1ull);
 #pragma unroll
         for (int a = 0; a < 3; ++a) xn[a] = o[a];
       } else {
         refl = reflect_walls<R>(V, c, xn);
         if (refl) {
           if (outside_walls<R>(V, c, xn)) {
-            atomicAdd(&V.counters[kReturned], 1ull);
+            counter_add(&V.counters[kReturned], 1ull);
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] = o[a];
           } else if (V.np > 0) {
@@ -416,8 +416,8 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
     L.dl[2][slot] = dl[2];
   }
   if (threadIdx.x == 0) {
-    if (refl_total) atomicAdd(&V.counters[kWallReflect], (unsigned long long)refl_total);
-    if (total) atomicAdd(&V.counters[kNearSurface], (unsigned long long)total);
+    if (refl_total) counter_add(&V.counters[kWallReflect], (unsigned long long)refl_total);
+    if (total) counter_add(&V.counters[kNearSurface], (unsigned long long)total);
   }
   lds_barrier();
   // the queued walkers, packed into the first waves of the block
@@ -454,7 +454,7 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
       const int ja = inside_any<R>(V, ps, c, o);
       if (ja < 0) {
         // type IV: no-flux boundary, Algorithm 1 then Algorithm 2
-        atomicAdd(&V.counters[kType4], 1ull);
+        counter_add(&V.counters[kType4], 1ull);
         R s;
         bool done = false;
         if (bisect<R>(V, ps, jb, c, o, dl, (R)0, (R)1, V.max_bisect, s)) {
@@ -474,7 +474,7 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] = xi[a] + (ti[a] - ((R)2 * dt) * nv[a]);
             if (inside_any<R>(V, ps, c, xn) >= 0) {
-              atomicAdd(&V.counters[kReturned], 1ull);
+              counter_add(&V.counters[kReturned], 1ull);
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = o[a];
             }
@@ -482,14 +482,14 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
           }
         }
         if (!done) {
-          atomicAdd(&V.counters[kBisectFail], 1ull);
+          counter_add(&V.counters[kBisectFail], 1ull);
 #pragma unroll
           for (int a = 0; a < 3; ++a) xn[a] = o[a];
         }
       } else {
         // type II: refill (push out along -grad M, random point in the
         // sqrt(2D) half-ball on the outer side of the surface)
-        atomicAdd(&V.counters[kType2], 1ull);
+        counter_add(&V.counters[kType2], 1ull);
         R g[3];
         particle_grad_at<R>(V, ps, jb, c, xf, g);
         const R gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
@@ -540,7 +540,7 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = xs[a] + rr * v[a];
             } else {
-              atomicAdd(&V.counters[kBisectFail], 1ull);
+              counter_add(&V.counters[kBisectFail], 1ull);
 #pragma unroll
               for (int a = 0; a < 3; ++a) xn[a] = xe[a];
             }
@@ -560,21 +560,21 @@ __device__ void walk_near_surface(const DomView& V, uint64_t t, int64_t w, const
           }
         }
         if (fallback) {
-          atomicAdd(&V.counters[kRefillFallback], 1ull);
+          counter_add(&V.counters[kRefillFallback], 1ull);
 #pragma unroll
           for (int a = 0; a < 3; ++a) xn[a] = xf[a];
         }
       }
     }
     if (!finite3<R>(xn)) {
-      atomicAdd(&V.counters[kReturned], 1ull);
+      counter_add(&V.counters[kReturned], 1ull);
 #pragma unroll
       for (int a = 0; a < 3; ++a) xn[a] = o[a];
     }
     if (reflect_walls<R>(V, c, xn)) {
-      atomicAdd(&V.counters[kWallReflect], 1ull);
+      counter_add(&V.counters[kWallReflect], 1ull);
       if (outside_walls<R>(V, c, xn) || inside_any<R>(V, ps, c, xn) >= 0) {
-        atomicAdd(&V.counters[kReturned], 1ull);
+        counter_add(&V.counters[kReturned], 1ull);
 #pragma unroll
         for (int a = 0; a < 3; ++a) xn[a] = o[a];
       }

@@ -12,8 +12,8 @@ near-surface queue.  Inputs are resident in HBM before the timed region.
 Prints one JSON line with MLUPS (all lattice nodes per second), walker-steps
 per second, the fluid kernel's achieved HBM bandwidth against the 8 TB/s peak
 (algorithmic bytes over its average duration from HIP events recorded around
-every launch of the timed region) and the FP64 CPU oracle timed on a bounded
-sample of the same workload on this host.
+windows of consecutive step launches covering the timed region) and the FP64
+CPU oracle timed on a bounded sample of the same workload on this host.
 
 Other workloads (own JSON line each, not the headline):
   --workload oscillator --precision fp16|bf16|fp32|fp64   256^3 oscillator
@@ -116,8 +116,8 @@ def cpu_baseline(cfg, seconds=15.0, max_steps=200):
 
 
 def run_plain(cfg, steps, warmup, prec, timing=8, graph=False):
-    """Warm up, then time `steps` steps; HIP events bracket every `timing`-th
-    step launch on the domain stream (0: none)."""
+    """Warm up, then time `steps` steps; HIP events on the domain stream
+    bracket windows of `timing` consecutive step launches (0: none)."""
     from paper_2308_05007_amd import binding as B
     import torch
     dom = B.build_domain(cfg, device=0)
@@ -174,7 +174,7 @@ def bench_plain(args):
                      "traffic": traffic,
                      "kernel": "k_step (fused: PSM-BGK collide + pull-stream, walkers, particle prologue)",
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 2),
-                     "timed_launches": launches, "timed_every": args.timing_every},
+                     "timed_launches": launches, "timing_window": args.timing_every},
         "counters": mom["counters"],
         "near_surface_per_step": round(mom["near_surface"] / max(mom["step"], 1), 1),
     }
@@ -234,7 +234,8 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--timing-every", type=int, default=8, help="bracket every n-th step launch with HIP events")
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="HIP events bracket windows of this many consecutive step launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,

@@ -229,8 +229,8 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles
  *   RWMI_KEY_BLOCK           threads per block of the step launch (128, 256, 512;
  *                            default 256): nodes per fluid block, walkers per
  *                            walker block, mask blocks per prologue block
- *   RWMI_KEY_TIMING          p > 0: record HIP events around every p-th step launch
- *                            (1: every launch); 0: off
+ *   RWMI_KEY_TIMING          p > 0: record HIP events around windows of p consecutive
+ *                            step launches (1: every launch on its own); 0: off
  *   RWMI_KEY_STEP_FLAGS      launch options of the step kernel: bit 0 deals each of
  *                            the 8 XCDs a contiguous run of fluid blocks with its
  *                            share of walker blocks interleaved (default on), bit 1
@@ -256,8 +256,10 @@ rwmi_status rwmi_debug_set(rwmi_domain* dom, int32_t key, int64_t value);
 
 /* Timing of the step launches recorded while RWMI_KEY_TIMING is on
  * (synchronises, then clears the record): *ms total milliseconds between the
- * events bracketing each timed launch, *launches their number, and how many
- * of them carried a fluid update (*fluid_steps) and a walker step
+ * events bracketing each timed window of consecutive step launches (windows
+ * close before a walker regrouping and at the end of a launch group, so they
+ * hold step launches only), *launches the launches timed, and how many of
+ * them carried a fluid update (*fluid_steps) and a walker step
  * (*walker_steps); a group of n steps is n + 1 launches, the first without
  * walkers, the last with walkers only. */
 rwmi_status rwmi_read_kernel_times(rwmi_domain* dom, double* ms, uint64_t* launches, uint64_t* fluid_steps,

@@ -82,18 +82,19 @@ struct rwmi_domain {
   rwmi::SortScratch sort{};
   bool use_graph = false;
   bool timing = false;
-  uint32_t timing_every = 1;  // bracket every this many launches
-  uint64_t launch_seq = 0;    // launches enqueued while timing
+  uint32_t timing_every = 1;  // step launches per timed window
   hipGraphExec_t gexec = nullptr;
   uint32_t gsteps = 0;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
-  struct TimedLaunch {
-    size_t ev;      // index of the start event (the stop event follows)
-    bool fluid;     // carried a fluid update
-    bool walkers;   // carried a walker step
+  // A timed window: consecutive step launches bracketed by one event pair.
+  struct TimedWindow {
+    size_t ev;         // index of the start event (the stop event follows)
+    uint32_t launches; // step launches in the window
+    uint32_t fluid;    // of them, launches that carried a fluid update
+    uint32_t walkers;  // and launches that carried a walker step
   };
-  std::vector<TimedLaunch> evrec;
+  std::vector<TimedWindow> evrec;
   // lazily allocated readback scratch
   uint32_t* occ = nullptr;
   double* mom_part = nullptr;
@@ -325,6 +326,11 @@ rwmi_status finalize_particles(rwmi_domain* d) {
 // Timing events: no host reads device data through them, so they skip the
 // system-scope cache write-back and invalidation a default event performs
 // (which also stalls the stream around each record).
+struct TimedWindowState {
+  size_t ev;
+  uint32_t launches, fluid, walkers;
+};
+
 hipEvent_t take_event(rwmi_domain* d) {
   if (d->evused == d->evpool.size()) {
     hipEvent_t e;
@@ -350,13 +356,25 @@ bool sort_before(const rwmi_domain* d, uint32_t j, uint32_t n, bool capturing) {
 // stream (launch j: fluid of t0 + j for j < n, prologue of t0 + j + 1 for
 // j < n - 1, walkers of t0 + j - 1 for j >= 1), with the walker regrouping
 // between launches, then the device step counter advances by n.  With
-// `record`, HIP events bracket every timing_every-th launch (j >= 0).
+// `record`, HIP events bracket windows of timing_every consecutive step
+// launches (j >= 0); a window closes early before a regrouping and at the
+// end of the group, so it times step launches only.
 rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturing) {
   int b[kRoles];
   role_blocks(d, d->bs, b);
   hipStream_t A = d->stream;
+  bool open = false;
+  TimedWindowState win{};
+  auto close_window = [&]() -> rwmi_status {
+    if (!open) return RWMI_OK;
+    HIPCHK(d, hipEventRecord(d->evpool[win.ev + 1], A));
+    d->evrec.push_back({win.ev, win.launches, win.fluid, win.walkers});
+    open = false;
+    return RWMI_OK;
+  };
   for (int j = -1; j <= (int)n; ++j) {
     if (j >= 0 && sort_before(d, (uint32_t)j, n, capturing)) {
+      if (close_window() != RWMI_OK) return RWMI_EDEVICE;
       HIPCHK(d, rwmi::launch_sort(d->prec, d->dv, 0, d->hv.nw, d->sort, A));
       if (!capturing) d->sorted_at = d->steps + (uint32_t)j;
     }
@@ -369,22 +387,23 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturin
     a.inplace = d->hv.inplace;
     a.j = j;
     if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    size_t i0 = 0;
-    const bool timed = record && j >= 0 && (d->launch_seq++ % d->timing_every) == 0;
-    if (timed) {
-      i0 = d->evused;
-      e0 = take_event(d);
-      e1 = take_event(d);
+    const bool timed = record && j >= 0;
+    if (timed && !open) {
+      win = TimedWindowState{d->evused, 0, 0, 0};
+      hipEvent_t e0 = take_event(d), e1 = take_event(d);
       if (!e0 || !e1) return fail(d, RWMI_EDEVICE, "hipEventCreate failed");
       HIPCHK(d, hipEventRecord(e0, A));
+      open = true;
     }
     HIPCHK(d, rwmi::launch_step(d->prec, d->bs, a, A));
     if (timed) {
-      HIPCHK(d, hipEventRecord(e1, A));
-      d->evrec.push_back({i0, a.nb[kRoleFluid] > 0, a.nb[kRoleWalk] > 0});
+      win.launches += 1;
+      win.fluid += a.nb[kRoleFluid] > 0 ? 1u : 0u;
+      win.walkers += a.nb[kRoleWalk] > 0 ? 1u : 0u;
+      if (win.launches == d->timing_every && close_window() != RWMI_OK) return RWMI_EDEVICE;
     }
   }
+  if (close_window() != RWMI_OK) return RWMI_EDEVICE;
   HIPCHK(d, rwmi::launch_advance(d->dv, 1, n, A));
   return RWMI_OK;
 }
@@ -883,7 +902,6 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       if (value < 0 || value > (1 << 20)) return fail(d, RWMI_EINVAL, "timing period out of range");
       d->timing = value != 0;
       d->timing_every = value > 0 ? (uint32_t)value : 1u;
-      d->launch_seq = 0;
       return RWMI_OK;
     case RWMI_KEY_STEP_FLAGS:
       if (value < 0 || value > 3) return fail(d, RWMI_EINVAL, "step flags must be in 0..3");
@@ -932,9 +950,9 @@ rwmi_status rwmi_read_kernel_times(rwmi_domain* d, double* ms, uint64_t* launche
     float t = 0.0f;
     HIPCHK(d, hipEventElapsedTime(&t, d->evpool[r.ev], d->evpool[r.ev + 1]));
     *ms += t;
-    *launches += 1;
-    *fluid_steps += r.fluid ? 1 : 0;
-    *walker_steps += r.walkers ? 1 : 0;
+    *launches += r.launches;
+    *fluid_steps += r.fluid;
+    *walker_steps += r.walkers;
   }
   d->evrec.clear();
   d->evused = 0;

@@ -165,7 +165,7 @@ typedef struct rwmi_batch rwmi_batch;
 rwmi_status rwmi_create_domain(const rwmi_domain_desc* desc, rwmi_domain** out);
 
 /* Release every device buffer of the domain (after synchronising its stream).
- * NULL is ignored.  The domain must not be in a batch. */
+ * NULL is ignored.  A domain still in a batch is removed from it first. */
 void rwmi_destroy_domain(rwmi_domain* dom);
 
 /* Add a metaball particle (Eq. 3) with prescribed motion.  The host arrays are

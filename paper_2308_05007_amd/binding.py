@@ -233,6 +233,11 @@ class Domain:
 
     def close(self):
         if getattr(self, "h", None):
+            # the library takes a domain out of its batch before freeing it
+            bt = getattr(self, "_batch", None)
+            if bt is not None and self in bt.members:
+                bt.members.remove(self)
+            self._batch = None
             self.L.rwmi_destroy_domain(self.h)
             self.h = None
 
@@ -380,10 +385,12 @@ class Batch:
     def add(self, dom):
         self._ck(self.L.rwmi_batch_add(self.h, dom.h))
         self.members.append(dom)
+        dom._batch = self
 
     def remove(self, dom):
         self._ck(self.L.rwmi_batch_remove(self.h, dom.h))
         self.members.remove(dom)
+        dom._batch = None
 
     def step(self, n=1):
         self._ck(self.L.rwmi_batch_step(self.h, int(n)))
@@ -398,6 +405,8 @@ class Batch:
         if getattr(self, "h", None):
             self.L.rwmi_batch_destroy(self.h)
             self.h = None
+            for d in self.members:
+                d._batch = None
             self.members = []
 
     def __del__(self):

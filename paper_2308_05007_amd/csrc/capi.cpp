@@ -234,6 +234,8 @@ rwmi_status upload_workmaps(rwmi_domain* d) {
 
 void drop_graph(rwmi_domain* d) {
   if (d->gexec) {
+    // no launch of the executable graph may still be in flight
+    (void)hipStreamSynchronize(d->stream);
     (void)hipGraphExecDestroy(d->gexec);
     d->gexec = nullptr;
     d->gsteps = 0;
@@ -555,6 +557,9 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
 void rwmi_destroy_domain(rwmi_domain* d) {
   if (!d) return;
   (void)hipSetDevice(d->device);
+  // a domain still in a batch leaves it first, so that the batch never holds
+  // a pointer to freed memory (whatever order a caller destroys them in)
+  if (d->batch) (void)rwmi_batch_remove(d->batch, d);
   if (d->stream) (void)hipStreamSynchronize(d->stream);
   drop_graph(d);
   for (hipEvent_t e : d->evpool) (void)hipEventDestroy(e);
@@ -1029,6 +1034,8 @@ rwmi_status rwmi_batch_create(int32_t device, void* stream, rwmi_batch** out) {
 
 static void batch_drop_graph(rwmi_batch* b) {
   if (b->gexec) {
+    // no launch of the executable graph may still be in flight
+    (void)hipStreamSynchronize(b->stream);
     (void)hipGraphExecDestroy(b->gexec);
     b->gexec = nullptr;
     b->gsteps = 0;

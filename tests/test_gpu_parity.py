@@ -349,6 +349,38 @@ def test_batch_equals_alone(B, prec):
     bt.close()
 
 
+
+def test_destroy_domain_in_batch(B):
+    """Destroying a member takes it out of its batch; the others step on
+    exactly as they would alone (graph replay before and after)."""
+    cfgs = [W.config_tiny(n=n, bc=bc, n_walkers=nw, n_particles=npart, seed=s)
+            for n, bc, nw, npart, s in (((9, 4, 11), ("periodic", "wall", "periodic"), 300, 2, 4),
+                                         ((6, 6, 6), ("periodic",) * 3, 200, 1, 5),
+                                         ((12, 5, 7), ("periodic",) * 3, 700, 3, 6))]
+    alone = [B.build_domain(c) for c in cfgs]
+    mixed = [B.build_domain(c) for c in cfgs]
+    for d in alone:
+        d.step(12)
+    bt = B.Batch()
+    for d in mixed:
+        bt.add(d)
+    bt.set("use_graph", 1)
+    bt.step(5)
+    mixed[1].close()
+    assert len(bt.members) == 2
+    bt.step(7)
+    bt.sync()
+    for a, m in ((alone[0], mixed[0]), (alone[2], mixed[2])):
+        ua, ra = a.velocity()
+        um, rm = m.velocity()
+        assert np.array_equal(ua, um) and np.array_equal(ra, rm)
+        for x, y in zip(a.walkers(), m.walkers()):
+            assert np.array_equal(x, y)
+        assert a.moments()["counters"] == m.moments()["counters"]
+    bt.close()
+    mixed[0].close()
+    mixed[2].close()
+
 def test_fp32_mode_against_oracle(orc, B):
     """FP32 storage of deviations, float collision and float walker offsets
     with the same normals: stated bounds after 50 steps of the 32^3 case."""

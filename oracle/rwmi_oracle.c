@@ -50,9 +50,11 @@
  *                   points give the mid-plane ring; gradient vs central
  *                   differences; bounding-radius lemma; minimum image
  *   solid fraction  one control point: eps = 1/2 + (sqrt(k) - r) exactly, the
- *                   sphere volume V + pi R / 3 by quadrature.  For several
- *                   control points the first-order estimate is a reading:
- *                   parity unpinned beyond the one-point case.
+ *                   sphere volume V + pi R / 3 by quadrature.  Two control
+ *                   points (equal and unequal weights): 1/2 + d matches the
+ *                   exact signed distance to the surface within the
+ *                   second-order bound of a first-order estimate, and eps is
+ *                   exactly 0 or 1 beyond the ramp.
  *   Algorithm 1, 2  crossing of a one-point sphere vs the quadratic root;
  *                   iteration cap; |t_r| = |t_i|, t_r.n = -t_i.n, specular on
  *                   a sphere

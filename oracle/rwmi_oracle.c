@@ -65,8 +65,10 @@
  *                   34); walls confine and keep a uniform density; reflection
  *                   keeps walkers out of a static particle; count conserved
  *   type II refill  the refilled walker lies outside every particle and near
- *                   the surface, count conserved.  The refill point itself is
- *                   a reading: parity unpinned beyond these invariants.
+ *                   the surface, count conserved; on a sphere the refill
+ *                   point matches its closed form (radial exit, outer half
+ *                   ball of radius sqrt(2D)) and is uniform in that half
+ *                   ball.  How the point is chosen is a reading.
  *   dispersion fit  a linear variance series gives the closed-form K and
  *                   D_alpha; pure diffusion gives sigma^2 = 2 D t
  */

@@ -154,3 +154,53 @@ def test_occupancy_is_cell_count(orc):
     ns = o.occupancy().ravel()
     assert np.array_equal(ns, np.bincount(cell, minlength=ns.size))
     assert ns.sum() == 500
+
+
+def test_refill_point_on_a_sphere(orc):
+    """Type II refill (Sec. 2.4.2) in closed form.  One control point is a
+    sphere of radius R = sqrt(k) whose -grad M is radial, in a fluid exactly
+    at rest, so a walker that starts and ends its free step inside is pushed
+    out along the ray from the centre through its end point x_f: the exit is
+    c + R (x_f - c)/|x_f - c|, where Algorithm 1 stops within |M - 1| < 1e-3
+    (a radial error of at most R (1/sqrt(0.999) - 1)).  It is then placed at
+    radius sqrt(2D) max(U1, U2, U3) along the purpose-1 normal direction,
+    flipped into the outer half space.  The placements must also be uniform
+    in the outer half ball: (r / sqrt(2D))^3 and the cosine to the normal are
+    U(0, 1)."""
+    n, k, D, seed, m = 32, 64.0, 0.5, 77, 4000
+    R, sD = math.sqrt(k), math.sqrt(2 * D)
+    c = np.array([16.3, 15.8, 16.1])
+    o = orc.Oracle(dict(n=(n,) * 3, bc=("periodic",) * 3, tau=0.8, F=(0, 0, 0), D=D, seed=seed))
+    o.add_particle(dict(b=np.zeros((1, 3)), k=np.array([k]), centre=c, motion="static"))
+    # start points uniform in the ball of radius 2: every free step (|z| sqrt(2D) < 6) ends inside
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((m, 3))
+    X0 = c + d / np.linalg.norm(d, axis=1)[:, None] * (2.0 * rng.random(m) ** (1 / 3))[:, None]
+    c3 = np.floor(X0).astype(np.int64)
+    cell = (c3[:, 0] + n * (c3[:, 1] + n * c3[:, 2])).astype(np.int32)
+    o.set_walkers(cell, (X0 - c3).T.ravel(), c)
+    t = o.t
+    o.step(1)
+    cnt = o.counters()
+    assert cnt["type2"] == m and cnt["refill_fallback"] == 0 and cnt["bisect_fail"] == 0
+    assert np.all(o.fields()["u"] == 0.0)
+    cl, of, im = o.walkers()
+    X1 = np.stack([cl % n, (cl // n) % n, cl // (n * n)], -1).astype(float) + im.T * n + of.T
+    # the closed form, with the random numbers of the walker's counters (pinned
+    # separately against rocRAND and libm)
+    xf = X0 + sD * orc.normals(t, 0, seed, m)
+    nh = (xf - c) / np.linalg.norm(xf - c, axis=1)[:, None]
+    xs = c + R * nh
+    v = orc.normals(t, 1, seed, m)
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    v = np.where((v * nh).sum(1)[:, None] < 0.0, -v, v)
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], np.uint32)
+    U = np.array([(orc.philox([w, t, 2, 0], key)[:3].astype(float) + 0.5) / 2.0 ** 32 for w in range(m)])
+    dev = X1 - (xs + (sD * U.max(1))[:, None] * v)
+    rad = (dev * nh).sum(1)
+    assert np.all(np.abs(rad) <= R * (1.0 / math.sqrt(0.999) - 1.0)), np.abs(rad).max()
+    assert np.all(np.linalg.norm(dev - rad[:, None] * nh, axis=1) < 1e-9)
+    r = X1 - xs
+    rn = np.linalg.norm(r, axis=1)
+    assert stats.kstest((rn / sD) ** 3, "uniform").pvalue > 1e-3
+    assert stats.kstest((r * nh).sum(1) / rn, "uniform").pvalue > 1e-3

@@ -234,7 +234,7 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* desc, uint32_t n_particles
  *   RWMI_KEY_STEP_FLAGS      launch options of the step kernel: bit 0 deals each of
  *                            the 8 XCDs a contiguous run of fluid blocks with its
  *                            share of walker blocks interleaved (default on), bit 1
- *                            writes f* and (u, rho) with non-temporal stores
+ *                            writes f* and u with non-temporal stores
  *   RWMI_KEY_SORT_EVERY      regroup the walkers by coarse block (4^3 nodes) every this
  *                            many steps for memory locality (default 128, 0 = never)
  *   RWMI_KEY_STREAMING       1: two lattices (pull from one, write the other); 2: one

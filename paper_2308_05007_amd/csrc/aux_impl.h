@@ -188,7 +188,8 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
   double acc[kNodeMom];
 #pragma unroll
   for (int k = 0; k < kNodeMom; ++k) acc[k] = 0.0;
-  const U* u4 = (const U*)V.u4[stepped ? ((done - 1) & 1ull) : 0];
+  const U* uf = (const U*)V.u[stepped ? ((done - 1) & 1ull) : 0];
+  const U* rf = (const U*)V.rho;
   const int nx = V.n[0], ny = V.n[1];
   for (int j = threadIdx.x; j < kRedChunk; j += kRedThreads) {
     const int64_t id = base + j;
@@ -207,11 +208,11 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
       for (int a = 0; a < 3; ++a) un[a] = un[a] + e * sp.v[k][a];
     }
     const double eps = es < 1.0 ? es : 1.0;
-    const double r = (double)u4[4 * id + 3];
+    const double r = (double)rf[id];
     acc[0] = acc[0] + r;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double ua = (double)u4[4 * id + a];
+      const double ua = (double)uf[3 * id + a];
       const double usa = es > 0.0 ? un[a] / es : 0.0;
       acc[1 + a] = acc[1 + a] + r * ua;
       acc[4 + a] = acc[4 + a] + (1.0 - eps) * ua;

@@ -385,7 +385,8 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturin
     a.boff = d->dboff;
     a.nd = 1;
     launch_roles(b, j, n, a.nb);
-    a.flags = d->flags;
+    // the group's last fluid step also stores the densities for read-outs
+    a.flags = d->flags | (j == (int)n - 1 ? rwmi::kFlagDensity : 0);
     a.inplace = d->hv.inplace;
     a.j = j;
     if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
@@ -424,7 +425,7 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   int32_t mb[3];
   const uint64_t nmb = (uint64_t)mask_blocks(*s, mb);
   uint64_t b = 0;
-  b += (default_inplace(*s) ? 1 : 2) * 19 * N * elem_size(p) + 8 * N * u_size(p);
+  b += (default_inplace(*s) ? 1 : 2) * 19 * N * elem_size(p) + 7 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
   b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + (288 + 48) * n_particles +
        (n_particles ? 24 * nmb + 24 * (uint64_t)fcull_words((int64_t)N) : 0);
@@ -522,13 +523,13 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
   v.max_bisect = 200;
 
   rwmi_status st = RWMI_OK;
-  void *fA, *fB, *u4;
+  void *fA, *fB, *ub;
   uint64_t* tstep;
   unsigned long long* cnt;
   fB = nullptr;
   if ((st = alloc_into(d, fA, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
       (!v.inplace && (st = alloc_into(d, fB, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK) ||
-      (st = alloc_into(d, u4, 8 * (size_t)N * u_size(d->prec))) != RWMI_OK ||
+      (st = alloc_into(d, ub, 7 * (size_t)N * u_size(d->prec))) != RWMI_OK ||
       (st = alloc_into(d, tstep, 16)) != RWMI_OK || (st = alloc_into(d, cnt, 8 * rwmi::kCounters)) != RWMI_OK ||
       (st = alloc_into(d, d->dv, sizeof(DomView))) != RWMI_OK ||
       (st = alloc_into(d, d->dboff, sizeof(int32_t) * 2 * kRoles)) != RWMI_OK) {
@@ -537,8 +538,10 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
   }
   v.fA = fA;
   v.fB = fB;
-  v.u4[0] = u4;
-  v.u4[1] = (char*)u4 + 4 * (size_t)N * u_size(d->prec);
+  // two velocity buffers of 3 U per node, then the densities
+  v.u[0] = ub;
+  v.u[1] = (char*)ub + 3 * (size_t)N * u_size(d->prec);
+  v.rho = (char*)ub + 6 * (size_t)N * u_size(d->prec);
   v.tstep = tstep;
   v.counters = cnt;
   uint64_t zeros[rwmi::kCounters] = {0};
@@ -747,21 +750,20 @@ rwmi_status rwmi_read_velocity(rwmi_domain* d, double* u, double* rho) {
   HIPCHK(d, hipSetDevice(d->device));
   const int64_t N = d->hv.N;
   const size_t us = u_size(d->prec);
-  std::vector<unsigned char> h(4 * N * us);
-  const void* ub = d->hv.u4[d->steps > 0 ? ((d->steps - 1) & 1) : 0];
+  // velocities of the last step (buffer of its parity), densities from the
+  // group's last fluid step, which is the same step
+  std::vector<unsigned char> h(3 * N * us), hr(N * us);
+  const void* ub = d->hv.u[d->steps > 0 ? ((d->steps - 1) & 1) : 0];
   HIPCHK(d, hipMemcpyAsync(h.data(), ub, h.size(), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(d, hipMemcpyAsync(hr.data(), d->hv.rho, hr.size(), hipMemcpyDeviceToHost, d->stream));
   HIPCHK(d, hipStreamSynchronize(d->stream));
+  auto at = [&](const std::vector<unsigned char>& b, int64_t k) -> double {
+    return us == 8 ? ((const double*)b.data())[k] : (double)((const float*)b.data())[k];
+  };
   for (int64_t i = 0; i < N; ++i) {
-    for (int c = 0; c < 4; ++c) {
-      double v;
-      if (us == 8) v = ((const double*)h.data())[4 * i + c];
-      else v = ((const float*)h.data())[4 * i + c];
-      if (c < 3) {
-        if (u) u[c * N + i] = v;
-      } else if (rho) {
-        rho[i] = v;
-      }
-    }
+    if (u)
+      for (int c = 0; c < 3; ++c) u[c * N + i] = at(h, 3 * i + c);
+    if (rho) rho[i] = at(hr, i);
   }
   return RWMI_OK;
 }
@@ -1138,7 +1140,7 @@ static rwmi_status batch_enqueue_group(rwmi_batch* b, uint32_t n, bool capturing
       a.boff = g.boff;
       a.nd = (int)g.doms.size();
       launch_roles(g.blocks, j, n, a.nb);
-      a.flags = b->flags;
+      a.flags = b->flags | (j == (int)n - 1 ? rwmi::kFlagDensity : 0);
       a.inplace = g.inplace;
       a.j = j;
       if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;

@@ -100,7 +100,8 @@ struct DomView {
   float wu_f[3][2][3];
   void* fA;                       // distributions: parity 0 source (two lattices) or the lattice (in place)
   void* fB;                       // distributions, parity 1 source (two lattices only)
-  void* u4[2];                    // (ux, uy, uz, rho) per node, written by step t into [t & 1]
+  void* u[2];                     // (ux, uy, uz) per node (3 U), written by step t into [t & 1]
+  void* rho;                      // density per node, written by the last fluid step of a group
   const DevParticle* parts;
   const double* ctrl;             // 4 per control point: bx, by, bz, k
   const float* ctrl_f;            // the same in float (low-precision modes)

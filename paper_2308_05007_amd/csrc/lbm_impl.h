@@ -329,10 +329,10 @@ __device__ __forceinline__ void upstream_of(const Nbr& b, bool& wall, int& delta
 }
 
 // Nodes [lb BS, (lb + 1) BS) of a domain through step t in layout L (the
-// domain's layout at t's parity); nt selects non-temporal stores.  Every
-// thread of the block calls it.
+// domain's layout at t's parity); nt selects non-temporal stores, dens the
+// store of the node densities as well.  Every thread of the block calls it.
 template <int P, int BS, int L>
-__device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt) {
+__device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens) {
   using S = typename Store<P>::S;
   using R = typename Store<P>::C;
   constexpr bool exact = (P == P64);
@@ -644,20 +644,26 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
     put(oc, vo);
   });
   {
-    // (ux, uy, uz, rho) of the node as one vector store
+    // (ux, uy, uz): three consecutive U, merged into one store by the
+    // compiler; the density only where a read-out may follow
     using U = typename Store<P>::U;
-    using U4v = U __attribute__((ext_vector_type(4)));
-    const U4v v = {(U)ux, (U)uy, (U)uz, (U)rho};
-    const auto u = gp((U4v*)V.u4[t & 1ull]) + id;
-    if (nt) __builtin_nontemporal_store(v, u);
-    else *u = v;
+    const auto u = gp((U*)V.u[t & 1ull]) + 3ull * (uint64_t)id;
+    const U v[3] = {(U)ux, (U)uy, (U)uz};
+    if (nt) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) __builtin_nontemporal_store(v[a], u + a);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) u[a] = v[a];
+    }
+    if (dens) gp((U*)V.rho)[id] = (U)rho;
   }
 }
 
 // Initial stored state: the gather of step 0 reads f = feq(rho0, u0) at
 // every fluid node (with two lattices, populations that bounce are set to the
-// value they must arrive with); (u, rho) = (u0, rho0), wall nodes carry the
-// wall velocity.
+// value they must arrive with); u = u0 in both velocity buffers (wall nodes
+// carry the wall velocity) and rho = rho0.
 template <int P>
 __global__ void k_init(const DomView* __restrict__ views, int dom, double u0x, double u0y, double u0z) {
   using S = typename Store<P>::S;
@@ -687,19 +693,19 @@ __global__ void k_init(const DomView* __restrict__ views, int dom, double u0x, d
     if (!V.inplace) fB[(int64_t)j * V.N + id] = from_d<S>(fe);
   }
   for (int b = 0; b < 2; ++b) {  // wall nodes keep these values in both buffers
-    U* u4 = (U*)V.u4[b];
+    U* u = (U*)V.u[b] + 3 * id;
     if (wslot >= 0) {
       const int a = wslot >> 1, side = wslot & 1;
-      u4[4 * id + 0] = (U)V.wu[a][side][0];
-      u4[4 * id + 1] = (U)V.wu[a][side][1];
-      u4[4 * id + 2] = (U)V.wu[a][side][2];
+      u[0] = (U)V.wu[a][side][0];
+      u[1] = (U)V.wu[a][side][1];
+      u[2] = (U)V.wu[a][side][2];
     } else {
-      u4[4 * id + 0] = (U)u0x;
-      u4[4 * id + 1] = (U)u0y;
-      u4[4 * id + 2] = (U)u0z;
+      u[0] = (U)u0x;
+      u[1] = (U)u0y;
+      u[2] = (U)u0z;
     }
-    u4[4 * id + 3] = (U)rho0;
   }
+  ((U*)V.rho)[id] = (U)rho0;
 }
 
 // Pre-collision f(x, t) for diagnostics, as double SoA [19][nodes].

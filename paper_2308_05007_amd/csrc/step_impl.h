@@ -7,7 +7,8 @@
 //
 // No role reads what another role of the same launch writes.  The fluid of
 // step t reads f of parity t & 1, the poses of slot t mod 3 and writes f, u of
-// parity (t + 1) & 1 and t & 1; the walkers of step t - 1 read u of parity
+// parity (t + 1) & 1 and t & 1 (and, on the group's last fluid step, the
+// densities, which no role reads); the walkers of step t - 1 read u of parity
 // (t - 1) & 1 and the poses/mask of slot (t - 1) mod 3; the prologue writes
 // slot (t + 1) mod 3.
 #pragma once
@@ -53,9 +54,12 @@ k_step(StepArgs a, const DomView* __restrict__ views, const int32_t* __restrict_
   const uint64_t t = step_of(V, a.j);
   if (role == kRoleWalk) walk_block<P, BS>(V, lb, t - 1, lds.walk);
   else if (role == kRolePro) prologue_block(V, lb, t + 1, BS, lds.pro);
-  else if constexpr (!IP) fluid_block<P, BS, kTwoLattices>(V, (uint32_t)lb, t, (a.flags & 2) != 0);
-  else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd>(V, (uint32_t)lb, t, (a.flags & 2) != 0);
-  else fluid_block<P, BS, kInPlaceEven>(V, (uint32_t)lb, t, (a.flags & 2) != 0);
+  else {
+    const bool nt = (a.flags & kFlagNontemporal) != 0, dens = (a.flags & kFlagDensity) != 0;
+    if constexpr (!IP) fluid_block<P, BS, kTwoLattices>(V, (uint32_t)lb, t, nt, dens);
+    else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd>(V, (uint32_t)lb, t, nt, dens);
+    else fluid_block<P, BS, kInPlaceEven>(V, (uint32_t)lb, t, nt, dens);
+  }
 }
 
 }  // namespace rwmi

@@ -28,7 +28,11 @@ namespace rwmi {
 enum BlockRole { kRoleWalk = 0, kRolePro = 1, kRoleFluid = 2, kRoles = 3, kRoleNone = -1 };
 
 constexpr int kFlagXcd = 1;          // XCD-aware role map
-constexpr int kFlagNontemporal = 2;  // non-temporal stores of f* and (u, rho)
+constexpr int kFlagNontemporal = 2;  // non-temporal stores of f* and u
+// Set by the host (never by a caller) on the launch that carries the last
+// fluid step of a launch group: that step also writes the node densities,
+// which only read-outs use.
+constexpr int kFlagDensity = 4;
 
 struct DomView;
 
@@ -38,7 +42,7 @@ struct StepArgs {
   const int32_t* boff;  // kRoles maps of nd + 1 block prefixes: walkers, prologue, fluid
   int nd;
   int nb[kRoles];       // blocks per role over all domains
-  int flags;            // kFlagXcd | kFlagNontemporal
+  int flags;            // kFlagXcd | kFlagNontemporal | kFlagDensity
   int inplace;          // every domain of the launch streams its lattice in place
   int32_t j;            // launch index within the group (-1: the prologue-only launch)
 };

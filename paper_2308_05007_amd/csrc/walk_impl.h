@@ -287,26 +287,29 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
       b0[a] = b;
       b1[a] = b1a;
     }
-    // one vector load per corner: (ux, uy, uz, rho) of a node is 4 U.  All
-    // eight are issued, with the cull-mask word of the start cell, before the
-    // normals are drawn, so that the Philox rounds run while they are in
-    // flight.
-    using U4v = U __attribute__((ext_vector_type(4)));
-    const auto u4 = gp((const U4v*)V.u4[par]);
+    // one load per corner: (ux, uy, uz) of a node is 3 consecutive U, which
+    // the compiler merges into one access.  All eight are issued, with the
+    // cull-mask word of the start cell, before the normals are drawn, so that
+    // the Philox rounds run while they are in flight.
+    const auto uf = gp((const U*)V.u[par]);
     // node indices in 32 bits (fewer than 2^31 nodes): corner (0,0,0) plus
     // per-axis steps to the upper corner, which wrap on periodic axes
     const uint32_t unx = (uint32_t)nx, unxy = unx * (uint32_t)ny;
     const uint32_t i000 = (uint32_t)b0[0] + unx * ((uint32_t)b0[1] + (uint32_t)ny * (uint32_t)b0[2]);
     const uint32_t sx = (uint32_t)(b1[0] - b0[0]), sy = (uint32_t)(b1[1] - b0[1]) * unx,
                    sz = (uint32_t)(b1[2] - b0[2]) * unxy;
-    U4v cu[2][2][2];
+    U cu[2][2][2][3];
 #pragma unroll
     for (int zz = 0; zz < 2; ++zz)
 #pragma unroll
       for (int yy = 0; yy < 2; ++yy) {
         const uint32_t i0 = i000 + (yy ? sy : 0u) + (zz ? sz : 0u);
-        cu[zz][yy][0] = u4[i0];
-        cu[zz][yy][1] = u4[i0 + sx];
+        const auto lo = uf + 3ull * i0, hi = uf + 3ull * (i0 + sx);
+#pragma unroll
+        for (int cpt = 0; cpt < 3; ++cpt) {
+          cu[zz][yy][0][cpt] = lo[cpt];
+          cu[zz][yy][1][cpt] = hi[cpt];
+        }
       }
     if (V.np > 0) bits0 = mask_at_cell(V, ps, c);
     // Brownian step (Eq. 2 with dt = 1): normals of the walker id's Philox block
@@ -333,10 +336,9 @@ __device__ __forceinline__ void walk_block(const DomView& V, int64_t lblock, uin
       for (int zz = 0; zz < 2; ++zz)
 #pragma unroll
         for (int yy = 0; yy < 2; ++yy) {
-          const U4v lo4 = cu[zz][yy][0], hi4 = cu[zz][yy][1];
-          const R lo[3] = {(R)lo4.x, (R)lo4.y, (R)lo4.z}, hi[3] = {(R)hi4.x, (R)hi4.y, (R)hi4.z};
 #pragma unroll
-          for (int cpt = 0; cpt < 3; ++cpt) v[zz][yy][cpt] = ((R)1 - wt[0]) * lo[cpt] + wt[0] * hi[cpt];
+          for (int cpt = 0; cpt < 3; ++cpt)
+            v[zz][yy][cpt] = ((R)1 - wt[0]) * (R)cu[zz][yy][0][cpt] + wt[0] * (R)cu[zz][yy][1][cpt];
         }
 #pragma unroll
       for (int cpt = 0; cpt < 3; ++cpt) {

@@ -53,3 +53,40 @@ def test_errors_without_a_gpu_are_reported_not_raised_by_the_library():
     st = L.rwmi_step(None, 1)
     assert st == B.RWMI_EINVAL
     assert L.rwmi_last_error(None)
+
+
+@pytest.mark.parametrize("change,what", [
+    (dict(tau=0.5), "tau"),
+    (dict(tau=float("nan")), "tau"),
+    (dict(n=(0, 8, 8)), "n[0]"),
+    (dict(n=(8, 2, 8), bc=("periodic", "wall", "periodic")), "wall axis"),
+    (dict(n=(2048, 1024, 1024)), "too large"),
+    (dict(D=-1.0), "diffusivity"),
+])
+def test_invalid_domains_are_rejected_before_the_device(change, what):
+    """Descriptor checks run on the host first, so they report EINVAL (and
+    no domain) on a machine without a GPU; 2^31 nodes is one past the
+    largest lattice the 32-bit node indices allow."""
+    import ctypes as C
+    from paper_2308_05007_amd import binding as B
+    from paper_2308_05007_amd import workloads as W
+    dom = dict(W.config_channel(precision="fp32")["domain"], **change)
+    d = B.make_desc(dom)
+    h = C.c_void_p(1)
+    assert B.lib().rwmi_create_domain(C.byref(d), C.byref(h)) == B.RWMI_EINVAL
+    assert not h.value
+    assert what in B.lib().rwmi_last_error(None).decode()
+
+
+def test_invalid_precision_and_callback_pairs_are_rejected():
+    import ctypes as C
+    from paper_2308_05007_amd import binding as B
+    from paper_2308_05007_amd import workloads as W
+    d = B.make_desc(W.config_channel(precision="fp32")["domain"])
+    d.precision = 99
+    h = C.c_void_p()
+    assert B.lib().rwmi_create_domain(C.byref(d), C.byref(h)) == B.RWMI_EINVAL
+    d = B.make_desc(W.config_channel(precision="fp32")["domain"])
+    d.alloc = B.ALLOC_FN(lambda n, ctx: None)
+    assert B.lib().rwmi_create_domain(C.byref(d), C.byref(h)) == B.RWMI_EINVAL
+    assert "together" in B.lib().rwmi_last_error(None).decode()

@@ -46,7 +46,8 @@
  *   streaming       pull equals a separately written push (brute force);
  *                   Poiseuille at the exact tau (closed form), curvature at any
  *                   tau, Couette linear profile
- *   metaball        one control point is a sphere of radius sqrt(k); two equal
+ *   metaball        one control point is a sphere of radius sqrt(k) (with
+ *                   Table 1's sphere: projected area 78.54 at k = 25); two equal
  *                   points give the mid-plane ring; gradient vs central
  *                   differences; bounding-radius lemma; minimum image
  *   solid fraction  one control point: eps = 1/2 + (sqrt(k) - r) exactly, the

@@ -170,3 +170,30 @@ def test_reflection_off_sphere_is_specular(orc):
     g = -2 * 4.0 * (x_inter - c) / np.linalg.norm(x_inter - c) ** 4
     tr = orc.reflect(ti, g)
     assert np.allclose(tr, [0.3, 0.1, 0.4], atol=1e-15)
+
+
+def test_table1_sphere_projected_area(orc):
+    """Table 1 prints A_m = 78.54 for the spherical particle: a sphere of
+    radius 5 lattice units (pi 5^2).  The oracle's metaball with one control
+    point of weight k = 25 must enclose exactly that disc in its widest
+    section (through the centre), counted on a fine grid of the oracle's own
+    M >= 1 test (grid error well under 0.5%)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_sphere_projected_area.txt")
+    vals = dict(l.split() for l in open(path) if l.strip() and not l.startswith("#"))
+    A_m = float(vals["A_m"])
+    o = orc.Oracle(_box())
+    c = np.array([20.25, 19.5, 20.75])
+    o.add_particle(dict(b=np.zeros((1, 3)), k=np.array([25.0]), centre=c, motion="static"))
+    h = 0.05
+    g = np.arange(-6.0 + h / 2, 6.0, h)
+    inside = 0
+    for x in g:
+        for y in g:
+            cell, off = _pt(c + np.array([x, y, 0.0]))
+            inside += o.particle_M(0, 0, cell, off) >= 1.0
+    area = inside * h * h
+    assert abs(area - A_m) / A_m < 5e-3, (area, A_m)
+    # a section off the centre is smaller: the widest one is through it
+    cell, off = _pt(c + np.array([4.9, 0.0, 1.0]))
+    assert o.particle_M(0, 0, cell, off) < 1.0

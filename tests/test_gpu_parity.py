@@ -315,12 +315,17 @@ def test_graph_replay_equals_eager(B):
     a = B.build_domain(cfg)
     b = B.build_domain(cfg)
     b.set("use_graph", 1)
-    a.step(37)
-    b.step(37)
-    ua, ra = a.velocity()
-    ub, rb = b.velocity()
-    assert np.array_equal(ua, ub) and np.array_equal(ra, rb)
-    assert all(np.array_equal(x, y) for x, y in zip(a.walkers(), b.walkers()))
+    # one replay; a replay of 64 then 36 eager steps; a new capture of 3
+    for n in (37, 100, 3):
+        a.step(n)
+        b.step(n)
+        ua, ra = a.velocity()
+        ub, rb = b.velocity()
+        assert np.array_equal(ua, ub) and np.array_equal(ra, rb)
+        assert all(np.array_equal(x, y) for x, y in zip(a.walkers(), b.walkers()))
+        ma, mb = a.moments(), b.moments()
+        assert ma["mass"] == mb["mass"] and np.array_equal(ma["momentum"], mb["momentum"])
+        assert ma["counters"] == mb["counters"]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])

@@ -245,6 +245,35 @@ def test_channel_128_fp32_headline(orc, B):
     assert int(g.occupancy().sum()) == cfg["walkers"]["n"]
 
 
+def test_oscillator_256_fp16_full_size(orc, B):
+    """The other benchmarked configuration at its full size (256^3 periodic,
+    FP16 storage of deviations, 64 oscillating metaballs, 1e7 walkers in the
+    solute band; default launch shape, two lattices) against the FP64 oracle
+    after 2 steps, within the FP16 mode's stated bounds: velocity L2 3e-3
+    relative, median walker position error 3e-4 cell; walker count and
+    occupancy sum exact."""
+    cfg = W.config_oscillator(precision="fp16")
+    o, g = _pair(orc, B, cfg)
+    for _ in range(2):
+        o.step(1)
+        g.step(1)
+    ug, _ = g.velocity()
+    uo = o.fields()["u"]
+    rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    co, oo, io = o.walkers()
+    cg, og, ig = g.walkers()
+    n = cfg["domain"]["n"]
+    L = np.array(n)[:, None]
+    X = lambda c, off, im: np.stack([c % n[0], (c // n[0]) % n[1], c // (n[0] * n[1])]) + off + L * im
+    d = np.abs(X(cg, og, ig) - X(co, oo, io)).max(0)
+    print("oscillator 256^3 FP16 vs oracle: velocity L2 %.3g, median position %.3g, 99.9%% %.3g"
+          % (rel, np.median(d), np.quantile(d, 0.999)))
+    assert rel < 3e-3, rel
+    assert np.median(d) < 3e-4, np.median(d)
+    assert g.moments()["n_walkers"] == cfg["walkers"]["n"]
+    assert int(g.occupancy().sum()) == cfg["walkers"]["n"]
+
+
 @pytest.mark.parametrize("bs", [128, 256, 512])
 @pytest.mark.parametrize("flags", [0, 1, 2, 3])
 def test_launch_shapes_match_oracle(orc, B, bs, flags):

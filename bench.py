@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--timing-every", type=int, default=8,
+    ap.add_argument("--timing-every", type=int, default=32,
                     help="HIP events bracket windows of this many consecutive step launches")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -42,7 +42,9 @@
  *   collision       mass conserved, momentum grows by exactly F per node and
  *                   step, tau = 1 relaxes to f^eq, a rest state stays at rest
  *                   bitwise; PSM: eps = 0 ignores the solid velocity, a fully
- *                   solid node relaxes to u_s, momentum exchange per node
+ *                   solid node relaxes to u_s, momentum exchange per node, and
+ *                   direction by direction f^eq(u) + g maps to the closed-form
+ *                   blend (1-B) f^eq(u) + B f^eq(u_s) + (1-B)(1-1/tau) g + B g_opp
  *   streaming       pull equals a separately written push (brute force);
  *                   Poiseuille at the exact tau (closed form), curvature at any
  *                   tau, Couette linear profile
@@ -62,9 +64,17 @@
  *   random          Philox words vs rocRAND's philox4x32_10 (library
  *                   cross-check); LN and SINCOS2PI vs long-double libm;
  *                   normals: moments, KS, bound
- *   walkers         free-space MSD = 6 D t; plume drift and spread (Eq. 31,
+ *   walkers         free-space MSD = 6 D t, also with steps of several
+ *                   periods (image counts); plume drift and spread (Eq. 31,
  *                   34); walls confine and keep a uniform density; reflection
- *                   keeps walkers out of a static particle; count conserved
+ *                   keeps walkers out of a static particle; count conserved;
+ *                   a non-finite step and a wall reflection still outside the
+ *                   fluid range return the walker (closed form per walker)
+ *   interpolation   displacement at D = 0 equals the closed-form tensor
+ *                   product of 1-D chords of a per-axis quadratic field, and
+ *                   the Couette profile with the wall nodes' velocity
+ *   moments         Poiseuille mean and momentum; fluid and particle averages
+ *                   and solid volume of two spheres in a prescribed flow
  *   type II refill  the refilled walker lies outside every particle and near
  *                   the surface, count conserved; on a sphere the refill
  *                   point matches its closed form (radial exit, outer half

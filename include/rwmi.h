@@ -198,6 +198,21 @@ rwmi_status rwmi_step(rwmi_domain* dom, uint32_t n_steps);
 /* Compute and copy the FP64 moments (synchronises). */
 rwmi_status rwmi_read_moments(rwmi_domain* dom, rwmi_moments* out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same moments,
+ * bit for bit, from the same kernels, with no allocation of any kind.  The
+ * reduction's partials, staging output and reference point live in one
+ * file-scope device array of the library, 1 MiB per GPU (131072 doubles),
+ * which each GPU the library runs on holds until the process ends.  Limit:
+ * 64 + 6 ceil(n_walkers / 4096) + 12 ceil(n_nodes / 4096) <= 131072 (the
+ * 256^3 lattice with 1e7 walkers uses 49%); EINVAL beyond it, with the sizes
+ * in the message.  ESTATE if the domain has particles and has been neither
+ * seeded nor stepped (their upload allocates).  Synchronises the domain's
+ * stream.  Every call on a GPU shares that GPU's array: calls for domains of
+ * one GPU that overlap in time (from several host threads) race and must be
+ * serialised by the caller. */
+rwmi_status rwmi_read_moments_noalloc(rwmi_domain* dom, rwmi_moments* out);
+
 /* Occupancy n_s per node (Eq. 16: walkers whose cell is the node), exact
  * uint32, nx*ny*nz entries (synchronises). */
 rwmi_status rwmi_read_occupancy(rwmi_domain* dom, uint32_t* ns);

@@ -61,6 +61,7 @@ SIGNATURES = {
     "rwmi_seed_walkers": (C.c_int, [C.c_void_p, C.POINTER(SeedDesc), C.c_uint64, C.POINTER(C.c_uint64)]),
     "rwmi_step": (C.c_int, [C.c_void_p, C.c_uint32]),
     "rwmi_read_moments": (C.c_int, [C.c_void_p, C.POINTER(Moments)]),
+    "rwmi_read_moments_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Moments)]),
     "rwmi_read_occupancy": (C.c_int, [C.c_void_p, C.c_void_p]),
     "rwmi_read_velocity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rwmi_read_walkers": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -310,9 +311,12 @@ class Domain:
         self._ck(self.L.rwmi_query_sizes(self.h, C.byref(a), C.byref(b), C.byref(c)))
         return int(a.value), int(b.value), int(c.value)
 
-    def moments(self):
+    def moments(self, noalloc=False):
+        """FP64 moments; noalloc=True reads them through the allocation-free
+        entry point (same kernels, scratch in the library's device array)."""
         m = Moments()
-        self._ck(self.L.rwmi_read_moments(self.h, C.byref(m)))
+        f = self.L.rwmi_read_moments_noalloc if noalloc else self.L.rwmi_read_moments
+        self._ck(f(self.h, C.byref(m)))
         return dict(step=int(m.step), n_walkers=int(m.n_walkers), sum=np.array(m.sum[:]), sumsq=np.array(m.sumsq[:]),
                     mass=m.mass, momentum=np.array(m.momentum[:]), fluid_u=np.array(m.fluid_u[:]),
                     particle_v=np.array(m.particle_v[:]), solid_volume=m.solid_volume,

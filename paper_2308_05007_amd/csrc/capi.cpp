@@ -839,6 +839,32 @@ rwmi_status rwmi_read_occupancy(rwmi_domain* d, uint32_t* ns) {
   return RWMI_OK;
 }
 
+// The moments from the 32 doubles the final reduction wrote.
+static void fill_moments(const rwmi_domain* d, const double h[32], rwmi_moments* out) {
+  std::memset(out, 0, sizeof *out);
+  const int64_t nw = d->hv.nw;
+  uint64_t u64[rwmi::kCounters + 1];
+  std::memcpy(u64, h + 18, sizeof u64);
+  out->step = u64[rwmi::kCounters];
+  out->n_walkers = (uint64_t)nw;
+  for (int a = 0; a < 3; ++a) {
+    out->sum[a] = h[a];
+    out->sumsq[a] = h[3 + a];
+    out->momentum[a] = h[7 + a];
+    out->fluid_u[a] = h[13] > 0.0 ? h[10 + a] / h[13] : 0.0;
+    out->particle_v[a] = h[17] > 0.0 ? h[14 + a] / h[17] : 0.0;
+  }
+  out->mass = h[6];
+  out->solid_volume = h[17];
+  out->type2 = u64[rwmi::kType2];
+  out->type4 = u64[rwmi::kType4];
+  out->bisect_fail = u64[rwmi::kBisectFail];
+  out->refill_fallback = u64[rwmi::kRefillFallback];
+  out->returned_to_origin = u64[rwmi::kReturned];
+  out->wall_reflect = u64[rwmi::kWallReflect];
+  out->near_surface = u64[rwmi::kNearSurface];
+}
+
 rwmi_status rwmi_read_moments(rwmi_domain* d, rwmi_moments* out) {
   if (!d || !out) return fail(d, RWMI_EINVAL, "null argument");
   HIPCHK(d, hipSetDevice(d->device));
@@ -861,27 +887,40 @@ rwmi_status rwmi_read_moments(rwmi_domain* d, rwmi_moments* out) {
   double h[32];
   HIPCHK(d, hipMemcpyAsync(h, d->mom_out, sizeof h, hipMemcpyDeviceToHost, d->stream));
   HIPCHK(d, hipStreamSynchronize(d->stream));
-  std::memset(out, 0, sizeof *out);
-  uint64_t u64[rwmi::kCounters + 1];
-  std::memcpy(u64, h + 18, sizeof u64);
-  out->step = u64[rwmi::kCounters];
-  out->n_walkers = (uint64_t)nw;
-  for (int a = 0; a < 3; ++a) {
-    out->sum[a] = h[a];
-    out->sumsq[a] = h[3 + a];
-    out->momentum[a] = h[7 + a];
-    out->fluid_u[a] = h[13] > 0.0 ? h[10 + a] / h[13] : 0.0;
-    out->particle_v[a] = h[17] > 0.0 ? h[14 + a] / h[17] : 0.0;
-  }
-  out->mass = h[6];
-  out->solid_volume = h[17];
-  out->type2 = u64[rwmi::kType2];
-  out->type4 = u64[rwmi::kType4];
-  out->bisect_fail = u64[rwmi::kBisectFail];
-  out->refill_fallback = u64[rwmi::kRefillFallback];
-  out->returned_to_origin = u64[rwmi::kReturned];
-  out->wall_reflect = u64[rwmi::kWallReflect];
-  out->near_surface = u64[rwmi::kNearSurface];
+  fill_moments(d, h, out);
+  return RWMI_OK;
+}
+
+// Same kernels and reduction order as rwmi_read_moments, with every buffer
+// they need (output staging [0, 32), reference point [32, 36), walker
+// partials from 64, node partials after them) in the library's per-GPU
+// scratch array.  Nothing there has to start at zero: each reduction block
+// writes its own partials and the final kernel writes every output word.
+rwmi_status rwmi_read_moments_noalloc(rwmi_domain* d, rwmi_moments* out) {
+  if (!d || !out) return fail(d, RWMI_EINVAL, "null argument");
+  if (!d->particles_uploaded && !d->parts.empty())
+    return fail(d, RWMI_ESTATE, "particles are uploaded by seeding or the first step; read moments after either");
+  const int64_t N = d->hv.N, nw = d->hv.nw;
+  const int64_t nbw = (nw + 4095) / 4096, nbn = (N + 4095) / 4096;
+  const int64_t need = 64 + 6 * nbw + 12 * nbn;
+  if (need > rwmi::kNoAllocDoubles)
+    return fail(d, RWMI_EINVAL,
+                "the allocation-free read-out needs %lld doubles of scratch for %lld nodes and %lld walkers; "
+                "it holds %lld (64 + 6 per 4096 walkers + 12 per 4096 nodes must fit)",
+                (long long)need, (long long)N, (long long)nw, (long long)rwmi::kNoAllocDoubles);
+  HIPCHK(d, hipSetDevice(d->device));
+  double* sc = nullptr;
+  HIPCHK(d, rwmi::noalloc_scratch(&sc));
+  double* outd = sc;
+  double* refd = sc + 32;
+  double* pw = sc + 64;
+  double* pn = pw + 6 * nbw;
+  HIPCHK(d, hipMemcpyAsync(refd, d->ref, 24, hipMemcpyHostToDevice, d->stream));
+  HIPCHK(d, rwmi::launch_moments(d->prec, d->dv, 0, N, nw, refd, pw, pn, outd, d->stream));
+  double h[32];
+  HIPCHK(d, hipMemcpyAsync(h, outd, sizeof h, hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  fill_moments(d, h, out);
   return RWMI_OK;
 }
 

@@ -1,10 +1,36 @@
 // FP64 kernels (compiled with -ffp-contract=off: every double operation is
 // a separately rounded IEEE operation) and the precision-independent ones.
+#include <mutex>
+
 #include "aux_impl.h"
 #include "launch.h"
 #include "step_impl.h"
 
+// Moment partials, staging output and reference point of the allocation-free
+// moment read-out.  In host code this name is only a stand-in for the symbol:
+// kernels get the address noalloc_scratch looked up on their device.
+static __device__ __align__(256) double scratch[rwmi::kNoAllocDoubles];
+
 namespace rwmi {
+
+hipError_t noalloc_scratch(double** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = (double*)p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
   const unsigned g = (unsigned)step_grid(a.nb, (a.flags & kFlagXcd) != 0);

@@ -38,6 +38,13 @@ hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_
                           double* pw, double* pn, double* out, hipStream_t s);
 hipError_t launch_advance(const DomView* views, int nd, uint32_t n, hipStream_t s);
 
+// Scratch of the allocation-free moment read-out: a file-scope device array
+// of kNoAllocDoubles doubles (1 MiB) in k_fp64.hip, one copy per GPU, held
+// until the process ends.  noalloc_scratch returns its device address on the
+// current device (looked up once per device and kept).
+constexpr int64_t kNoAllocDoubles = 131072;
+hipError_t noalloc_scratch(double** ptr);
+
 // Scratch of the walker sort of one domain (device memory owned by the domain).
 struct SortScratch {
   uint32_t* hist;  // 16 counters per bin (copy-major), bin totals, scan tile sums

@@ -425,7 +425,7 @@ uint64_t rwmi_footprint_bytes(const rwmi_domain_desc* s, uint32_t n_particles, u
   int32_t mb[3];
   const uint64_t nmb = (uint64_t)mask_blocks(*s, mb);
   uint64_t b = 0;
-  b += (default_inplace(*s) ? 1 : 2) * 19 * N * elem_size(p) + 7 * N * u_size(p);
+  b += (default_inplace(*s) ? 1 : 2) * rwmi::f_elems((int64_t)N) * elem_size(p) + 7 * N * u_size(p);
   b += sizeof(DomView) + 64 + 16;
   b += n_particles * sizeof(DevParticle) + 48 * n_ctrl_total + (288 + 48) * n_particles +
        (n_particles ? 24 * nmb + 24 * (uint64_t)fcull_words((int64_t)N) : 0);
@@ -449,7 +449,9 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
       return fail(nullptr, RWMI_EINVAL, "a wall axis needs at least 3 nodes (axis %d)", a);
   }
   const int64_t N = (int64_t)s->n[0] * s->n[1] * s->n[2];
-  if (N > ((int64_t)1 << 31) - 1) return fail(nullptr, RWMI_EINVAL, "lattice of %lld nodes too large", (long long)N);
+  if (N > rwmi::kMaxNodes)
+    return fail(nullptr, RWMI_EINVAL, "lattice of %lld nodes too large (at most %lld: 32-bit element indices)",
+                (long long)N, (long long)rwmi::kMaxNodes);
   if (!(s->tau > 0.5)) return fail(nullptr, RWMI_EINVAL, "tau = %g must be > 0.5", s->tau);
   if (!(s->diffusivity >= 0.0)) return fail(nullptr, RWMI_EINVAL, "diffusivity must be >= 0");
   if (!valid_prec(s->precision)) return fail(nullptr, RWMI_EINVAL, "precision %d unknown", s->precision);
@@ -527,8 +529,8 @@ rwmi_status rwmi_create_domain(const rwmi_domain_desc* s, rwmi_domain** out) {
   uint64_t* tstep;
   unsigned long long* cnt;
   fB = nullptr;
-  if ((st = alloc_into(d, fA, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK ||
-      (!v.inplace && (st = alloc_into(d, fB, 19 * (size_t)N * elem_size(d->prec))) != RWMI_OK) ||
+  if ((st = alloc_into(d, fA, rwmi::f_elems(N) * elem_size(d->prec))) != RWMI_OK ||
+      (!v.inplace && (st = alloc_into(d, fB, rwmi::f_elems(N) * elem_size(d->prec))) != RWMI_OK) ||
       (st = alloc_into(d, ub, 7 * (size_t)N * u_size(d->prec))) != RWMI_OK ||
       (st = alloc_into(d, tstep, 16)) != RWMI_OK || (st = alloc_into(d, cnt, 8 * rwmi::kCounters)) != RWMI_OK ||
       (st = alloc_into(d, d->dv, sizeof(DomView))) != RWMI_OK ||
@@ -962,7 +964,7 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       if (!ip && !d->hv.fB) {
         void* fB;
         rwmi_status st;
-        if ((st = alloc_into(d, fB, 19 * (size_t)d->hv.N * elem_size(d->prec))) != RWMI_OK) return st;
+        if ((st = alloc_into(d, fB, rwmi::f_elems(d->hv.N) * elem_size(d->prec))) != RWMI_OK) return st;
         d->hv.fB = fB;
       }
       d->hv.inplace = ip;

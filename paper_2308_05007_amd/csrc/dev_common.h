@@ -26,6 +26,32 @@ __host__ __device__ constexpr R weight(int i) {
   return i == 0 ? R(1.0) / R(3.0) : (i <= 6 ? R(1.0) / R(18.0) : R(1.0) / R(36.0));
 }
 
+// Distribution layouts.  Two lattices (streamed from HBM) are stored in
+// tiles: kTile consecutive nodes (x fastest) form a tile, which holds the
+// kTile values of direction 0, then of direction 1, ... up to 18, so that a
+// wave's 19 loads and 19 stores fall in a few contiguous regions of memory
+// instead of 19 planes one lattice apart.  A lattice streamed in place (small
+// enough to run from the memory-side cache) keeps one plane of N values per
+// direction, whose cheaper neighbour addressing keeps the in-place kernel
+// free of register spills.  Allocations hold ceil(N / kTile) whole tiles, at
+// most 2^32 - 1 elements (a domain has at most kMaxNodes nodes), so element
+// indices are 32-bit.
+constexpr int kTileShift = 8;
+constexpr uint32_t kTile = 1u << kTileShift;
+constexpr int64_t kMaxNodes = ((int64_t)0xFFFFFFFF / (kQ * (int64_t)kTile)) * (int64_t)kTile;
+// Element of direction `slot` of node n: slot * fstride + fnode(n).  Kernels
+// form it as a wave-uniform base (slot * fstride) plus the per-node offset.
+__host__ __device__ __forceinline__ uint32_t fnode(bool tiled, uint32_t n) {
+  return tiled ? ((n >> kTileShift) * (uint32_t)kQ << kTileShift) + (n & (kTile - 1u)) : n;
+}
+__host__ __device__ __forceinline__ uint32_t fstride(bool tiled, uint32_t N) { return tiled ? kTile : N; }
+__host__ __device__ __forceinline__ size_t fidx(bool tiled, int slot, uint32_t n, uint32_t N) {
+  return (size_t)slot * fstride(tiled, N) + fnode(tiled, n);
+}
+__host__ __device__ __forceinline__ uint64_t f_elems(int64_t N) {
+  return (uint64_t)((N + (int64_t)kTile - 1) >> kTileShift) * (uint64_t)kQ * (uint64_t)kTile;
+}
+
 constexpr int kMaxParticles = 64;
 constexpr int kCounters = 8;
 enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect, kNearSurface };
@@ -98,7 +124,7 @@ struct DomView {
   float eF_f[kQ];                 // e_i . F per direction (float collision)
   double wu[3][2][3];             // wall velocity [axis][lo/hi][component]
   float wu_f[3][2][3];
-  void* fA;                       // distributions: parity 0 source (two lattices) or the lattice (in place)
+  void* fA;                       // distributions (fidx): parity 0 source (two lattices) or the lattice (in place)
   void* fB;                       // distributions, parity 1 source (two lattices only)
   void* u[2];                     // (ux, uy, uz) per node (3 U), written by step t into [t & 1]
   void* rho;                      // density per node, written by the last fluid step of a group
@@ -180,18 +206,18 @@ struct U4 { uint32_t x, y, z, w; };
 
 __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                              uint32_t k0, uint32_t k1) {
+  // each 32x32 -> 64-bit product as one 64-bit multiply, which compiles to a
+  // single v_mad_u64_u32 instead of separate low and high multiplies
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = (uint32_t)p1;
     c2 = n2;
-    c3 = lo0;
+    c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }

@@ -2,8 +2,8 @@
 // node, one block per run of consecutive nodes (x fastest); a block function
 // run by the fluid blocks of the fused step launch.
 //
-// Stored state between steps is the post-collision distribution f*(t-1),
-// SoA [19][nodes], with the moving-wall term of Eq. 23 already added to every
+// Stored state between steps is the post-collision distribution f*(t-1)
+// (layouts: fidx), with the moving-wall term of Eq. 23 already added to every
 // population that will bounce off a wall node.  A step gathers
 // f_i(x, t) = f*_i(x - e_i, t-1) (or the bounced f*_opp(i)(x) when x - e_i is
 // a wall node), computes rho, u (Eq. 14-15, Guo half-force velocity), the
@@ -350,6 +350,7 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   if constexpr (inplace) asm volatile("" : "+s"(dst0));
   const auto dst = gp(dst0);
   const uint32_t N = (uint32_t)V.N;
+  const uint32_t FS = fstride(!inplace, N);  // elements between directions (layouts: fidx)
   const uint32_t n0 = lb * BS;
   const uint32_t id = n0 + threadIdx.x;
   const uint32_t idc = id < N ? id : n0;  // a valid node for the threads past the end
@@ -392,7 +393,7 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
       slot = wall ? i : opp_dir(i);
       at = wall ? id : (uint32_t)((int)id + delta);
     }
-    const SR raw = src[(size_t)slot * N + at];
+    const SR raw = src[(size_t)slot * FS + fnode(!inplace, at)];
     if constexpr (exact) f[i] = raw;
     else f[i] = raw_in<S>(raw);
   });
@@ -546,8 +547,8 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
         at = wall ? ids : (uint32_t)((int)ids + delta);
       }
     }
-    if (nt) __builtin_nontemporal_store(w, &dst[(size_t)slot * N + at]);
-    else dst[(size_t)slot * N + at] = w;
+    if (nt) __builtin_nontemporal_store(w, &dst[(size_t)slot * FS + fnode(!inplace, at)]);
+    else dst[(size_t)slot * FS + fnode(!inplace, at)] = w;
   };
 
   // Float collision, folded: with e_o = -e_i and w_o = w_i the relaxed,
@@ -689,8 +690,9 @@ __global__ void k_init(const DomView* __restrict__ views, int dom, double u0x, d
     const double eu = edot<double>(i, u0x, u0y, u0z);
     double fe = (weight<double>(i) * rho0) * (((1.0 + 3.0 * eu) + 4.5 * (eu * eu)) - uu15);
     if (P != P64) fe = fe - weight<double>(i) * rho0;
-    fA[(int64_t)j * V.N + id] = from_d<S>(fe);
-    if (!V.inplace) fB[(int64_t)j * V.N + id] = from_d<S>(fe);
+    const bool tiled = !V.inplace;
+    fA[fidx(tiled, j, (uint32_t)id, (uint32_t)V.N)] = from_d<S>(fe);
+    if (tiled) fB[fidx(tiled, j, (uint32_t)id, (uint32_t)V.N)] = from_d<S>(fe);
   }
   for (int b = 0; b < 2; ++b) {  // wall nodes keep these values in both buffers
     U* u = (U*)V.u[b] + 3 * id;
@@ -733,10 +735,11 @@ __global__ void k_read_f(const DomView* __restrict__ views, int dom, double* __r
       else s[a] = s[a] < 0 ? s[a] + V.n[a] : (s[a] >= V.n[a] ? s[a] - V.n[a] : s[a]);
     }
     const int64_t up = s[0] + nx * ((int64_t)s[1] + (int64_t)ny * s[2]);
-    int64_t sidx;
-    if (!inplace) sidx = wall ? (int64_t)opp_dir(i) * V.N + id : (int64_t)i * V.N + up;
-    else if (!odd) sidx = (int64_t)i * V.N + id;
-    else sidx = wall ? (int64_t)i * V.N + id : (int64_t)opp_dir(i) * V.N + up;
+    size_t sidx;
+    const uint32_t un = (uint32_t)id, uu = (uint32_t)up, NN = (uint32_t)V.N;
+    if (!inplace) sidx = wall ? fidx(true, opp_dir(i), un, NN) : fidx(true, i, uu, NN);
+    else if (!odd) sidx = fidx(false, i, un, NN);
+    else sidx = wall ? fidx(false, i, un, NN) : fidx(false, opp_dir(i), uu, NN);
     double v = (double)to_c(src[sidx]);
     if (P != P64) v = v + weight<double>(i) * V.rho0;
     out[(int64_t)i * V.N + id] = v;

@@ -2,26 +2,34 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-Default workload: the 128^3 FP32 channel (walls at y = 0 / 127, periodic x
-and z, tau 0.7, body force 5e-6, 20 oscillating metaballs of 8-16 control
-points, 1e6 walkers released as a Gaussian pulse of sigma 4, D = 0.005,
-2000 steps).  One step = one coupled step: particle poses + walker cull mask,
-PSM-BGK collide-stream (writes u), walker advection/diffusion with the
-near-surface queue.  Inputs are resident in HBM before the timed region.
+Default workload (the headline): the 256^3 periodic oscillator in FP32
+storage -- 64 metaballs of 12 control points (random orientation) in a
+prescribed sinusoidal oscillation (amplitude 4, period 5000), 1e7 walkers
+released in the band z in [127.5, 128.5), D = 0.002, tau = 0.8.  Its two
+lattices (2.6 GB) and velocity field stream from HBM; nothing of it fits the
+256 MB memory-side cache.  One step = one coupled step: particle poses and
+walker cull mask, PSM-BGK collide-stream (writes u), walker advection /
+diffusion with the near-surface queue.  Inputs are resident in HBM before
+the timed region.
 
-Prints one JSON line with MLUPS (all lattice nodes per second), walker-steps
-per second, the fluid kernel's achieved HBM bandwidth against the 8 TB/s peak
-(algorithmic bytes over its average duration from HIP events recorded around
-windows of consecutive step launches covering the timed region) and the FP64
-CPU oracle timed on a bounded sample of the same workload on this host.
+The timed window sits mid-run: half of the workload's steps are advanced
+untimed first (see burnin_steps), then W warm-up steps, then K timed steps.
+
+Prints one JSON line: MLUPS (all lattice nodes per second), walker-steps per
+second, the step kernel's achieved bandwidth in algorithmic bytes against
+the 8 TB/s HBM peak (HIP events recorded around windows of consecutive step
+launches that cover the timed region), the same workload with FP16 and BF16
+storage and the 128^3 FP32 channel (whose lattice is cache-resident) as
+secondary figures, and the FP64 CPU oracle timed on a bounded sample of the
+headline workload on this host, on all threads and on one.
 
 Other workloads (own JSON line each, not the headline):
-  --workload oscillator --precision fp16|bf16|fp32|fp64   256^3 oscillator
+  --workload oscillator --precision fp16|bf16|fp32|fp64   256^3 oscillator alone
+  --workload channel [--precision ...]                    128^3 channel alone
   --workload precision                                    all storage modes vs FP64
   --workload batch                                        64-simulation sweep
   --workload copy [--lattice MiB]                         plain copy (HBM counter calibration)
-  --workload serve [--rate 20 --duration 15]              Poisson request stream (disabled, see
-                                                          paper_2308_05007_amd.serve.DISABLED)
+  --workload serve [--rate 20 --duration 15]              Poisson request stream
 """
 import argparse
 import hashlib
@@ -92,10 +100,11 @@ def pmc_traffic(workload_key, prec):
     return e.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(cfg, seconds=15.0, max_steps=200):
-    """The FP64 oracle on this host's cores: first steps of the same workload
-    (seeding excluded), as many as fit in about `seconds`."""
+def _oracle_sample(cfg, seconds, max_steps, threads):
+    """Steps of the FP64 oracle on the workload (seeding excluded) with the
+    given number of threads: at least one, then as many as fit in `seconds`."""
     import oracle
+    oracle.set_threads(threads)
     o = oracle.build_domain(cfg)
     w = cfg["walkers"]
     o.seed(w, w["n"])
@@ -107,22 +116,43 @@ def cpu_baseline(cfg, seconds=15.0, max_steps=200):
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
+    del o
+    return steps, dt
+
+
+def cpu_baseline(cfg, seconds=12.0, max_steps=200, single_thread=True):
+    """The FP64 oracle on this host's cores, on a bounded sample of the same
+    workload: its first steps on all threads (about `seconds`), then its
+    first step on one thread."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
     N = int(np.prod(cfg["domain"]["n"]))
-    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
-    return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "walker_steps_per_s": w["n"] * steps / dt,
-            "sample": "FP64 oracle, first %d coupled steps of %s (%d nodes, %d walkers), %.1f s"
-                      % (steps, cfg["name"], N, w["n"], dt)}
+    nw = cfg["walkers"]["n"]
+    steps, dt = _oracle_sample(cfg, seconds, max_steps, cores)
+    out = {"value": round(N * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "walker_steps_per_s": round(nw * steps / dt, 1),
+           "sample": "FP64 oracle, first %d coupled steps of %s (%d nodes, %d walkers) on %d threads, %.1f s"
+                     % (steps, cfg["name"], N, nw, cores, dt)}
+    if single_thread:
+        s1, d1 = _oracle_sample(cfg, 0.0, 1, 1)
+        out["single_thread"] = {"value": round(N * s1 / d1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                                "walker_steps_per_s": round(nw * s1 / d1, 1),
+                                "sample": "first %d coupled step on 1 thread, %.1f s" % (s1, d1)}
+    oracle.set_threads(cores)
+    return out
 
 
-def run_plain(cfg, steps, warmup, prec, timing=8, graph=False):
-    """Warm up, then time `steps` steps; HIP events on the domain stream
-    bracket windows of `timing` consecutive step launches (0: none)."""
+def run_plain(cfg, steps, warmup, timing=32, graph=False, burnin=0):
+    """Advance `burnin` steps (untimed: the state at mid-run), warm up, then
+    time `steps` steps; HIP events on the domain stream bracket windows of
+    `timing` consecutive step launches (0: none)."""
     from paper_2308_05007_amd import binding as B
     import torch
     dom = B.build_domain(cfg, device=0)
     if graph:
         dom.set("use_graph", 1)
+    if burnin:
+        dom.step(burnin)
     dom.step(warmup)
     dom.sync()
     torch.cuda.synchronize()
@@ -136,48 +166,89 @@ def run_plain(cfg, steps, warmup, prec, timing=8, graph=False):
     dt = time.perf_counter() - t0
     kt = dom.kernel_times() if timing else {}
     mom = dom.moments()
-    return dom, dt, kt, mom
+    dom.close()
+    del dom
+    torch.cuda.empty_cache()
+    return dt, kt, mom
 
 
-def bench_plain(args):
-    from paper_2308_05007_amd import workloads as W
-    if args.workload == "channel":
-        cfg = W.config_channel(precision=args.precision or "fp32")
-        key = "channel_128_" + (args.precision or "fp32")
-    else:
-        cfg = W.config_oscillator(precision=args.precision or "fp16", n_walkers=args.walkers or 10_000_000)
-        key = "oscillator_256_" + (args.precision or "fp16")
+def burnin_steps(cfg, args):
+    """Untimed steps before the warm-up: half of the workload's run, so that
+    the timed window sits mid-run.  The particles stir a fluid that starts at
+    rest, and a launch takes longer as the stored values fill with nonzero
+    data (the 256^3 FP32 oscillator: 537 us per launch at step 5, 598 at step
+    100, 620-633 from step 1000 to 5000)."""
+    return cfg["steps"] // 2 if args.burnin is None else args.burnin
+
+
+def measure(cfg, key, steps, warmup, timing, burnin=0):
+    """MLUPS, walker-steps/s and the step kernel's achieved bandwidth in
+    algorithmic bytes for one workload."""
     prec = cfg["domain"]["precision"]
-    steps, warmup = args.steps, args.warmup
-    dom, dt, kt, mom = run_plain(cfg, steps, warmup, prec, timing=args.timing_every, graph=False)
+    dt, kt, mom = run_plain(cfg, steps, warmup, timing=timing, burnin=burnin)
     N = int(np.prod(cfg["domain"]["n"]))
     nw = cfg["walkers"]["n"]
     assert mom["n_walkers"] == nw, "walker count not conserved"
-    mlups = N * steps / dt / 1e6
     ms_total, launches, fluid_launches, walker_launches = kt
     avg_s = ms_total / 1e3 / max(launches, 1)
     # a full launch carries one fluid update and one walker step
     fb, wb = fluid_nodes(cfg) * fluid_bytes_per_node(prec), nw * walker_bytes_per_step(prec)
-    bytes_launch = fb + wb
     achieved = (fluid_launches * fb + walker_launches * wb) / (ms_total / 1e3) / 1e9
-    traffic = pmc_traffic(key, prec)
+    return {"key": key, "prec": prec, "N": N, "nw": nw, "dt": dt, "steps": steps, "burnin": burnin,
+            "mlups": N * steps / dt / 1e6, "wsps": nw * steps / dt, "achieved": achieved,
+            "bytes_launch": fb + wb, "avg_us": avg_s * 1e6, "launches": launches, "mom": mom}
+
+
+def bench_plain(args):
+    from paper_2308_05007_amd import workloads as W
+    headline = args.workload == "oscillator"
+    prec = args.precision or "fp32"
+    if headline:
+        cfg = W.config_oscillator(precision=prec, n_walkers=args.walkers or 10_000_000)
+        key = "oscillator_256_" + prec
+    else:
+        cfg = W.config_channel(precision=prec)
+        key = "channel_128_" + prec
+    steps, warmup = args.steps, args.warmup
+    r = measure(cfg, key, steps, warmup, args.timing_every, burnin=burnin_steps(cfg, args))
+    mom = r["mom"]
     out = {
-        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warmup,
-        "ms_per_step": round(dt / steps * 1e3, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPE[prec], "data": "synthetic (seeded metaballs and walkers; no datasets)",
+        "metric": METRIC, "value": round(r["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(r["dt"] / steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec],
+        "data": "synthetic (seeded metaballs and walkers; no datasets)",
         "config": {"workload": key, "lattice": list(cfg["domain"]["n"]), "bc": list(cfg["domain"]["bc"]),
-                   "particles": len(cfg["particles"]), "walkers": nw, "precision": prec,
-                   "steps_per_run": cfg["steps"]},
-        "walker_steps_per_s": round(nw * steps / dt, 1),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
+                   "particles": len(cfg["particles"]), "walkers": r["nw"], "precision": prec,
+                   "steps_per_run": cfg["steps"], "timed_from_step": r["burnin"] + warmup},
+        "walker_steps_per_s": round(r["wsps"], 1),
+        "roofline": {"bound": "hbm", "achieved": round(r["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
+                     "traffic": pmc_traffic(key, prec),
                      "kernel": "k_step (fused: PSM-BGK collide + pull-stream, walkers, particle prologue)",
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 2),
-                     "timed_launches": launches, "timing_window": args.timing_every},
+                     "bytes_per_launch": r["bytes_launch"], "avg_launch_us": round(r["avg_us"], 2),
+                     "timed_launches": r["launches"], "timing_window": args.timing_every},
         "counters": mom["counters"],
         "near_surface_per_step": round(mom["near_surface"] / max(mom["step"], 1), 1),
     }
+    if headline and prec == "fp32" and not args.no_secondary:
+        sec = {}
+        s2, w2 = 64, 8
+        for p2 in ("fp16", "bf16"):
+            c2 = W.config_oscillator(precision=p2, n_walkers=args.walkers or 10_000_000)
+            q = measure(c2, "oscillator_256_" + p2, s2, w2, args.timing_every, burnin=burnin_steps(c2, args))
+            sec[q["key"]] = {"MLUPS": round(q["mlups"], 1), "walker_steps_per_s": round(q["wsps"], 1),
+                             "ms_per_step": round(q["dt"] / s2 * 1e3, 5), "roofline_frac": round(q["achieved"] / HBM_PEAK_GBS, 4),
+                             "bytes_per_launch": q["bytes_launch"], "avg_launch_us": round(q["avg_us"], 2),
+                             "steps": s2, "warmup": w2, "timed_from_step": q["burnin"] + w2}
+        c3 = W.config_channel(precision="fp32")
+        q = measure(c3, "channel_128_fp32", 256, 16, args.timing_every, burnin=burnin_steps(c3, args))
+        sec["channel_128_fp32_cache_resident"] = {
+            "MLUPS": round(q["mlups"], 1), "walker_steps_per_s": round(q["wsps"], 1),
+            "ms_per_step": round(q["dt"] / 256 * 1e3, 5), "roofline_frac": round(q["achieved"] / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": q["bytes_launch"], "avg_launch_us": round(q["avg_us"], 2), "steps": 256, "warmup": 16,
+            "timed_from_step": q["burnin"] + 16,
+            "note": "the in-place lattice and velocity (160 MB + 48 MB) fit the 256 MB memory-side cache: not an HBM figure"}
+        out["secondary"] = sec
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, seconds=args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -223,9 +294,10 @@ def bench_copy(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="channel", choices=["channel", "oscillator", "precision", "batch", "serve", "copy"])
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="oscillator",
+                    choices=["oscillator", "channel", "precision", "batch", "serve", "copy"])
     ap.add_argument("--lattice", type=int, default=None)
     ap.add_argument("--rate", type=float, default=None)
     ap.add_argument("--duration", type=float, default=None)
@@ -233,7 +305,10 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-secondary", action="store_true", help="skip the FP16/BF16 and channel figures")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--burnin", type=int, default=None,
+                    help="untimed steps before the warm-up (default: half of the workload's run)")
     ap.add_argument("--timing-every", type=int, default=32,
                     help="HIP events bracket windows of this many consecutive step launches")
     args = ap.parse_args()

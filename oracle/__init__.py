@@ -82,6 +82,8 @@ def lib():
         L.orc_bisect_segment.argtypes = [P, C.c_int, C.c_int64, ip, dp, dp, C.c_double, C.c_double,
                                          C.c_int, C.POINTER(C.c_int)]
         L.orc_reflect.argtypes = [dp, dp, dp]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         L.orc_dispersion_fit.restype = C.c_int
         L.orc_dispersion_fit.argtypes = [dp, dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -302,6 +304,15 @@ def dispersion_fit(t, sigma2, two_r, u_slip, phi, i0=0):
     if r != 0:
         raise ValueError("oracle dispersion fit: invalid input")
     return K.value, Da.value
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
 
 
 def build_domain(cfg):

@@ -84,6 +84,9 @@
  *                   D_alpha; pure diffusion gives sigma^2 = 2 D t
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1036,6 +1039,22 @@ void orc_set_walkers(orc_domain* d, int64_t nw, const int32_t* cell, const doubl
   memcpy(d->cell, cell, sizeof(int32_t) * nw);
   memcpy(d->off, off, sizeof(double) * 3 * nw);
   for (int a = 0; a < 3; a++) d->ref[a] = ref[a];
+}
+
+/* Threads of the OpenMP loops (the CPU-baseline timing runs 1 and all). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /* ------------------------------------------ exported pieces for the pins */

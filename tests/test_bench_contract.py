@@ -24,7 +24,11 @@ def test_algorithmic_bytes_per_unit():
     assert [bench.fluid_bytes_per_node(p) for p in ("fp64", "fp32", "fp16", "bf16")] == [328, 164, 88, 88]
     assert [bench.walker_bytes_per_step(p) for p in ("fp64", "fp32", "fp16", "bf16")] == [56, 32, 32, 32]
     from paper_2308_05007_amd import workloads as W
-    # the headline launch: 128 x 126 x 128 fluid nodes (two wall planes) and 1e6 walkers
+    # the headline launch: 256^3 periodic fluid nodes and 1e7 walkers in FP32
+    cfg = W.config_oscillator(precision="fp32", n_walkers=10_000_000)
+    assert bench.fluid_nodes(cfg) == 256 ** 3
+    assert bench.fluid_nodes(cfg) * 164 + cfg["walkers"]["n"] * 32 == 3071463424
+    # the cache-resident channel: 128 x 126 x 128 fluid nodes (two wall planes) and 1e6 walkers
     cfg = W.config_channel(precision="fp32")
     assert bench.fluid_nodes(cfg) == 128 * 126 * 128
     assert bench.fluid_nodes(cfg) * 164 + cfg["walkers"]["n"] * 32 == 370558976

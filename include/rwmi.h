@@ -175,7 +175,11 @@ void rwmi_destroy_domain(rwmi_domain* dom);
  * than RWMI_MAX_PARTICLES particles. */
 rwmi_status rwmi_add_metaball_particle(rwmi_domain* dom, const rwmi_metaball_desc* p, int32_t* out_id);
 
-/* Seed n walkers (ids 0..n-1) at step 0, on the device.  Attempt a of walker
+/* Seed n walkers (ids 0..n-1) at step 0, on the device: the solute particles
+ * of the random-walk method (Sec. 2.4, Eq. 2), released as in the paper's
+ * tests (a point or a Gaussian pulse, Sec. 3.1; a horizontal band, Sec. 4)
+ * or uniformly in the fluid; the concentration they carry is the node count
+ * of Eq. 16.  Attempt a of walker
  * w draws the Philox block with counter (w, 0xFFFFFFFF, 16 + a, 0); positions
  * inside a particle at t = 0 or outside the fluid range of a wall axis are
  * redrawn up to max_attempts times (remove_inside = 1: dropped instead, the
@@ -186,8 +190,11 @@ rwmi_status rwmi_add_metaball_particle(rwmi_domain* dom, const rwmi_metaball_des
 rwmi_status rwmi_seed_walkers(rwmi_domain* dom, const rwmi_seed_desc* s, uint64_t n, uint64_t* out_seeded);
 
 /* Enqueue n_steps coupled steps t -> t+1 on the domain's stream and return.
- * Each step: particle poses at t and t+1; fluid update at P(t) writing u(t);
- * walkers moved with u(t) and classified against P(t+1); walker counter
+ * Each step (the coupled scheme of Sec. 2.4 on the lattice Boltzmann update
+ * of Sec. 2.3, Eq. 12-15, and the random-walk update of Eq. 2): particle
+ * poses at t and t+1 (prescribed motion, Sec. 4 Eq. 37); fluid update at P(t)
+ * writing u(t); walkers moved with u(t) (Sec. 2.4.1) and classified against
+ * P(t+1) (types I-IV, Sec. 2.4.2; Algorithms 1-2); walker counter
  * (w, t, purpose, 0) with purpose 0 Brownian, 1 refill direction, 2 refill
  * radius.  n steps are n + 1 launches of one fused kernel on the domain
  * stream (launch j: fluid and prologue of step t0 + j, walkers of step
@@ -316,6 +323,34 @@ void rwmi_batch_destroy(rwmi_batch* b);
  * EINVAL if fewer than 2 samples are used, u_slip == 0 or phi >= 1. */
 rwmi_status rwmi_dispersion_fit(const double* t, const double* sigma2, uint32_t n, uint32_t i0, double two_r,
                                 double u_slip, double phi, double* K, double* D_alpha, double* offset);
+
+/* The dispersion pipeline of Sec. 4 (Eq. 38-40) from a series of moment
+ * read-outs of one domain (rwmi_read_moments every m steps), host-only
+ * arithmetic on the caller's array:
+ *   sigma2_i = sumsq[a]/N_w - (sum[a]/N_w)^2 of sample i along the dispersion
+ *              axis a (the variance of the unwrapped walker positions; the
+ *              Gaussian-fit variance of the averaged concentration profile);
+ *   u_slip   = |max_i fluid_u[f] - max_i particle_v[f]| along the flow axis f
+ *              (Eq. 39: the maxima over time of the fluid-average and the
+ *              particle-average velocity; the magnitude, since with
+ *              prescribed particle motion the fluid lags the particles);
+ *   phi      = mean of solid_volume over the samples taken after at least
+ *              one step, divided by n_nodes (the solid volume fraction);
+ *   K, D_alpha, offset from rwmi_dispersion_fit on (step_i, sigma2_i),
+ *              i = i0..n-1, with two_r the particle diameter (Eq. 38, 40).
+ * sigma2 (n doubles) receives the variance series if not NULL.  EINVAL if
+ * fewer than 2 samples are fitted, a sample has no walkers, an axis is not
+ * 0..2, n_nodes is 0, u_slip is 0 or phi >= 1. */
+typedef struct {
+  double u_slip;
+  double phi;
+  double K;
+  double D_alpha;
+  double offset;
+} rwmi_dispersion;
+rwmi_status rwmi_dispersion_from_moments(const rwmi_moments* series, uint32_t n, uint32_t i0, int32_t disp_axis,
+                                         int32_t flow_axis, uint64_t n_nodes, double two_r, double* sigma2,
+                                         rwmi_dispersion* out);
 
 /* ---------------------------------------------------------------- diagnostics
  * The Gaussian triples the walker kernels draw for counters (id, t, purpose,

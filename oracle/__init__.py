@@ -82,6 +82,9 @@ def lib():
         L.orc_bisect_segment.argtypes = [P, C.c_int, C.c_int64, ip, dp, dp, C.c_double, C.c_double,
                                          C.c_int, C.POINTER(C.c_int)]
         L.orc_reflect.argtypes = [dp, dp, dp]
+        L.orc_dispersion_from_moments.restype = C.c_int
+        L.orc_dispersion_from_moments.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                                  C.c_void_p, dp]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
         L.orc_dispersion_fit.restype = C.c_int
@@ -304,6 +307,39 @@ def dispersion_fit(t, sigma2, two_r, u_slip, phi, i0=0):
     if r != 0:
         raise ValueError("oracle dispersion fit: invalid input")
     return K.value, Da.value
+
+
+MOMENT_FIELDS = ("n_walkers", "sum", "sumsq", "mass", "momentum", "fluid_u", "particle_v", "solid_volume", "step")
+
+
+def moments_record(m):
+    """The 19-double moment record (orc_moments layout) of a moments dict."""
+    r = np.zeros(19)
+    r[0] = m["n_walkers"]
+    r[1:4] = m["sum"]
+    r[4:7] = m["sumsq"]
+    r[7] = m["mass"]
+    r[8:11] = m["momentum"]
+    r[11:14] = m["fluid_u"]
+    r[14:17] = m["particle_v"]
+    r[17] = m["solid_volume"]
+    r[18] = m["step"]
+    return r
+
+
+def dispersion_from_moments(series, n_nodes, two_r, disp_axis=2, flow_axis=0, i0=None):
+    """Eq. 38-40 from a list of moments dicts: (sigma2 series, dict of
+    u_slip, phi, K, D_alpha, offset)."""
+    rec = np.ascontiguousarray(np.stack([moments_record(m) for m in series]).ravel())
+    n = len(series)
+    i0 = n // 2 if i0 is None else int(i0)
+    s2 = np.empty(n)
+    out = np.empty(5)
+    r = lib().orc_dispersion_from_moments(rec, n, i0, int(disp_axis), int(flow_axis), float(n_nodes), float(two_r),
+                                          s2.ctypes.data_as(C.c_void_p), out)
+    if r != 0:
+        raise ValueError("oracle dispersion: invalid input")
+    return s2, dict(u_slip=out[0], phi=out[1], K=out[2], D_alpha=out[3], offset=out[4])
 
 
 def set_threads(n):

@@ -1148,3 +1148,63 @@ int orc_dispersion_fit(const double* t, const double* sigma2, int n, int i0, dou
   *D_alpha = *K / (1.0 - phi);
   return 0;
 }
+
+/* The dispersion pipeline of Sec. 4 from a series of n moment records
+ * (orc_moments layout, 19 doubles each):
+ *   variance along the dispersion axis: sumsq/N - (sum/N)^2 per sample;
+ *   Eq. 39: the slip velocity is the gap between the maxima over time of the
+ *   fluid-average and the particle-average velocity along the flow axis
+ *   (taken as a magnitude);
+ *   solid fraction: the solid volume averaged over the samples after the
+ *   first step, over the node count;
+ *   Eq. 38 and 40 through orc_dispersion_fit on samples i0..n-1.
+ * out5 = {u_slip, phi, K, D_alpha, intercept of the line}.  Returns 0 on
+ * success. */
+int orc_dispersion_from_moments(const double* mom, int n, int i0, int disp_axis, int flow_axis, double n_nodes,
+                                double two_r, double* sigma2, double* out5) {
+  if (n - i0 < 2 || disp_axis < 0 || disp_axis > 2 || flow_axis < 0 || flow_axis > 2 || !(n_nodes > 0.0))
+    return -1;
+  double* t = (double*)malloc(sizeof(double) * n);
+  double* v = (double*)malloc(sizeof(double) * n);
+  double umax = -INFINITY, pmax = -INFINITY, solid = 0.0;
+  int ns = 0;
+  for (int i = 0; i < n; i++) {
+    const double* m = mom + 19 * i;
+    double N = m[0];
+    if (!(N > 0.0)) {
+      free(t);
+      free(v);
+      return -1;
+    }
+    double mean = m[1 + disp_axis] / N;
+    v[i] = m[4 + disp_axis] / N - mean * mean;
+    t[i] = m[18];
+    if (m[11 + flow_axis] > umax) umax = m[11 + flow_axis];
+    if (m[14 + flow_axis] > pmax) pmax = m[14 + flow_axis];
+    if (m[18] > 0.0) {
+      solid = solid + m[17];
+      ns = ns + 1;
+    }
+  }
+  if (sigma2) memcpy(sigma2, v, sizeof(double) * n);
+  double u_slip = fabs(umax - pmax);
+  double phi = ns > 0 ? (solid / (double)ns) / n_nodes : 0.0;
+  double K = 0.0, Da = 0.0;
+  int r = orc_dispersion_fit(t, v, n, i0, two_r, u_slip, phi, &K, &Da);
+  /* intercept of the least-squares line of sigma^2/(2R)^2 against t */
+  double S = 0, Sx = 0, Sy = 0;
+  for (int i = i0; i < n; i++) {
+    S += 1.0;
+    Sx += t[i];
+    Sy += v[i] / (two_r * two_r);
+  }
+  double slope = K * (u_slip / two_r);
+  out5[0] = u_slip;
+  out5[1] = phi;
+  out5[2] = K;
+  out5[3] = Da;
+  out5[4] = (Sy - slope * Sx) / S;
+  free(t);
+  free(v);
+  return r;
+}

@@ -45,6 +45,11 @@ class SeedDesc(C.Structure):
                 ("ref", C.c_double * 3), ("max_attempts", C.c_int32), ("remove_inside", C.c_int32)]
 
 
+class Dispersion(C.Structure):
+    _fields_ = [("u_slip", C.c_double), ("phi", C.c_double), ("K", C.c_double), ("D_alpha", C.c_double),
+                ("offset", C.c_double)]
+
+
 class Moments(C.Structure):
     _fields_ = [("step", C.c_uint64), ("n_walkers", C.c_uint64), ("sum", C.c_double * 3), ("sumsq", C.c_double * 3),
                 ("mass", C.c_double), ("momentum", C.c_double * 3), ("fluid_u", C.c_double * 3),
@@ -80,6 +85,8 @@ SIGNATURES = {
     "rwmi_batch_set": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64]),
     "rwmi_batch_synchronize": (C.c_int, [C.c_void_p]),
     "rwmi_batch_destroy": (None, [C.c_void_p]),
+    "rwmi_dispersion_from_moments": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
+                                               C.c_uint64, C.c_double, C.c_void_p, C.c_void_p]),
     "rwmi_device_normals": (C.c_int, [C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p]),
     "rwmi_dispersion_fit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_double, C.c_double,
                                       C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -428,6 +435,37 @@ def dispersion_fit(t, sigma2, two_r, u_slip, phi, i0=0):
     _check(lib().rwmi_dispersion_fit(t.ctypes.data_as(C.c_void_p), s2.ctypes.data_as(C.c_void_p), t.size, int(i0),
                                      float(two_r), float(u_slip), float(phi), C.byref(K), C.byref(Da), C.byref(off)))
     return K.value, Da.value, off.value
+
+
+def moments_struct(m):
+    """A Moments structure holding the fields of a moments dict."""
+    r = Moments()
+    r.step = int(m["step"])
+    r.n_walkers = int(m["n_walkers"])
+    for a in range(3):
+        r.sum[a] = float(m["sum"][a])
+        r.sumsq[a] = float(m["sumsq"][a])
+        r.momentum[a] = float(m["momentum"][a])
+        r.fluid_u[a] = float(m["fluid_u"][a])
+        r.particle_v[a] = float(m["particle_v"][a])
+    r.mass = float(m["mass"])
+    r.solid_volume = float(m["solid_volume"])
+    return r
+
+
+def dispersion_from_moments(series, n_nodes, two_r, disp_axis=2, flow_axis=0, i0=None):
+    """Eq. 38-40 from a list of moments dicts through the library: (sigma2
+    series, dict of u_slip, phi, K, D_alpha, offset)."""
+    n = len(series)
+    arr = (Moments * max(n, 1))()
+    for i, m in enumerate(series):
+        arr[i] = moments_struct(m)
+    i0 = n // 2 if i0 is None else int(i0)
+    s2 = np.empty(max(n, 1))
+    out = Dispersion()
+    _check(lib().rwmi_dispersion_from_moments(arr, n, i0, int(disp_axis), int(flow_axis), int(n_nodes), float(two_r),
+                                              s2.ctypes.data_as(C.c_void_p), C.byref(out)))
+    return s2[:n], dict(u_slip=out.u_slip, phi=out.phi, K=out.K, D_alpha=out.D_alpha, offset=out.offset)
 
 
 def device_normals(seed, t, purpose, n, device=0):

@@ -1049,6 +1049,37 @@ rwmi_status rwmi_dispersion_fit(const double* t, const double* sigma2, uint32_t 
   return RWMI_OK;
 }
 
+rwmi_status rwmi_dispersion_from_moments(const rwmi_moments* ser, uint32_t n, uint32_t i0, int32_t disp_axis,
+                                         int32_t flow_axis, uint64_t n_nodes, double two_r, double* sigma2,
+                                         rwmi_dispersion* out) {
+  if (!ser || !out) return fail(nullptr, RWMI_EINVAL, "null argument");
+  if (disp_axis < 0 || disp_axis > 2 || flow_axis < 0 || flow_axis > 2) return fail(nullptr, RWMI_EINVAL, "axis out of range");
+  if (n_nodes == 0) return fail(nullptr, RWMI_EINVAL, "n_nodes must be > 0");
+  if (n < i0 + 2) return fail(nullptr, RWMI_EINVAL, "need at least two samples in the fit");
+  std::vector<double> t(n), s2(n);
+  double umax = -INFINITY, vmax = -INFINITY, solid = 0.0;
+  uint32_t nsolid = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const rwmi_moments& m = ser[i];
+    if (m.n_walkers == 0) return fail(nullptr, RWMI_EINVAL, "sample %u has no walkers", i);
+    const double N = (double)m.n_walkers;
+    const double mean = m.sum[disp_axis] / N;
+    t[i] = (double)m.step;
+    s2[i] = m.sumsq[disp_axis] / N - mean * mean;
+    if (m.fluid_u[flow_axis] > umax) umax = m.fluid_u[flow_axis];
+    if (m.particle_v[flow_axis] > vmax) vmax = m.particle_v[flow_axis];
+    if (m.step > 0) {
+      solid += m.solid_volume;
+      nsolid += 1;
+    }
+  }
+  if (sigma2) std::memcpy(sigma2, s2.data(), sizeof(double) * n);
+  out->u_slip = std::fabs(umax - vmax);
+  out->phi = nsolid ? (solid / (double)nsolid) / (double)n_nodes : 0.0;
+  return rwmi_dispersion_fit(t.data(), s2.data(), n, i0, two_r, out->u_slip, out->phi, &out->K, &out->D_alpha,
+                             &out->offset);
+}
+
 // ---------------------------------------------------------------- batch
 
 static rwmi_status bfail(rwmi_batch* b, rwmi_status st, const char* msg) {

@@ -8,11 +8,10 @@ FP64 moments read every `every` steps.  The errors against the FP64 run are
   D_alpha           relative error of the dispersion coefficient (Eq. 38-40)
   positions         distance between a walker's FP64 and low-precision
                     positions (same walker id), median / 99th percentile / max
-The dispersion coefficient follows Sec. 4: sigma_z^2(t) from the moments,
-U_slip = |max_t <u_x>_fluid - max_t <u_p,x>| (Eq. 39; its magnitude, since
-with prescribed particle motion the fluid lags), phi = solid volume
-fraction, a least-squares line over the second half of the series (Eq. 38),
-D_alpha = K / (1 - phi) (Eq. 40), 2R = 10 lattice units as in Sec. 4.
+The dispersion coefficient follows Sec. 4 (Eq. 38-40) through the library's
+rwmi_dispersion_from_moments on the moment series (dispersion along z, the
+particles' oscillation along x, the line fitted over the second half of the
+series, 2R = 10 lattice units as in Sec. 4).
 """
 import copy
 import time
@@ -30,17 +29,13 @@ def run_protocol(cfg, precision, steps=None, every=50, device=0):
     steps = int(steps or c["steps"])
     d = B.build_domain(c, device=device)
     nw = c["walkers"]["n"]
-    ser = {k: [] for k in ("t", "sigma2_z", "fluid_ux", "particle_vx", "solid")}
+    ser = []
     t0 = time.perf_counter()
     done = 0
     while True:
         m = d.moments()
         assert m["n_walkers"] == nw, "walker count not conserved"
-        ser["t"].append(m["step"])
-        ser["sigma2_z"].append(m["sumsq"][2] / nw - (m["sum"][2] / nw) ** 2)
-        ser["fluid_ux"].append(m["fluid_u"][0])
-        ser["particle_vx"].append(m["particle_v"][0])
-        ser["solid"].append(m["solid_volume"])
+        ser.append(m)
         if done >= steps:
             break
         k = min(every, steps - done)
@@ -48,7 +43,7 @@ def run_protocol(cfg, precision, steps=None, every=50, device=0):
         done += k
     wall = time.perf_counter() - t0
     u, rho = d.velocity()
-    out = dict(series={k: np.array(v) for k, v in ser.items()}, u=u, rho=rho, occ=d.occupancy().astype(np.float64),
+    out = dict(series=ser, u=u, rho=rho, occ=d.occupancy().astype(np.float64),
                walkers=d.walkers(), counters=d.moments()["counters"], wall_s=wall, n=c["domain"]["n"],
                precision=precision, steps=steps)
     d.close()
@@ -56,15 +51,15 @@ def run_protocol(cfg, precision, steps=None, every=50, device=0):
 
 
 def dispersion(res, two_r=10.0):
+    """u_slip, phi, K and D_alpha of a run (Eq. 38-40, library pipeline); NaN
+    where the pipeline has no answer (no slip, fewer than two samples)."""
     s = res["series"]
-    u_slip = abs(float(np.max(s["fluid_ux"]) - np.max(s["particle_vx"])))
-    N = float(np.prod(res["n"]))
-    phi = float(np.mean(s["solid"][1:]) / N) if len(s["solid"]) > 1 else 0.0
-    i0 = len(s["t"]) // 2
-    if abs(u_slip) < 1e-300 or len(s["t"]) - i0 < 2:
-        return dict(u_slip=u_slip, phi=phi, K=float("nan"), D_alpha=float("nan"))
-    K, Da, _ = B.dispersion_fit(s["t"], s["sigma2_z"], two_r, u_slip, phi, i0=i0)
-    return dict(u_slip=u_slip, phi=phi, K=K, D_alpha=Da)
+    N = int(np.prod(res["n"]))
+    try:
+        _, r = B.dispersion_from_moments(s, N, two_r, disp_axis=2, flow_axis=0, i0=len(s) // 2)
+    except B.RwmiError:
+        return dict(u_slip=float("nan"), phi=float("nan"), K=float("nan"), D_alpha=float("nan"))
+    return dict(u_slip=r["u_slip"], phi=r["phi"], K=r["K"], D_alpha=r["D_alpha"])
 
 
 def positions(res):

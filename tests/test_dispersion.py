@@ -47,3 +47,62 @@ def test_pure_diffusion_variance_grows_as_2Dt(orc):
     K, _ = orc.dispersion_fit(np.array(ts), np.array(s2), 1.0, 1.0, 0.0)
     # slope standard error ~ 2D sqrt(2/N) relative
     assert abs(K - 2 * D) < 6 * 2 * D * math.sqrt(2.0 / N), (K, 2 * D)
+
+
+def _series(t, mean, var, fu, pv, solid, nw=10000):
+    """Moment read-outs whose variance along z, fluid and particle averages
+    along x and solid volume are the given series."""
+    out = []
+    for i in range(len(t)):
+        out.append(dict(step=int(t[i]), n_walkers=nw, sum=np.array([0.0, 0.0, nw * mean[i]]),
+                        sumsq=np.array([0.0, 0.0, nw * (var[i] + mean[i] ** 2)]), mass=1.0, momentum=np.zeros(3),
+                        fluid_u=np.array([fu[i], 0.0, 0.0]), particle_v=np.array([pv[i], 0.0, 0.0]),
+                        solid_volume=solid[i]))
+    return out
+
+
+def test_pipeline_closed_form(orc):
+    """Eq. 38-40 from a moment series in closed form: a variance a + b t along
+    z (with a drifting mean), fluid and particle averages along x whose
+    maxima over time are 0.011 and 0.032 (U_slip = 0.021), and a solid volume
+    of 1500 (ignored before the first step) on 40^3 nodes (phi = 1500/64000):
+    K = b / (2R U_slip), D_alpha = K / (1 - phi), both from the oracle and
+    the library."""
+    from paper_2308_05007_amd import binding as B
+    t = np.arange(0, 5001, 50)
+    a, b, two_r = 4.2, 0.0031, 10.0
+    mean = 128.0 + 1e-4 * t
+    fu = 0.011 * np.sin(2 * np.pi * t / 5000.0 + 0.3)
+    pv = 0.032 * np.sin(2 * np.pi * t / 5000.0)
+    fu[37] = 0.011  # the maxima are reached on samples
+    pv[25] = 0.032
+    solid = np.where(t > 0, 1500.0, 0.0)
+    ser = _series(t, mean, a + b * t, fu, pv, solid)
+    N = 40 ** 3
+    for impl in (orc.dispersion_from_moments, B.dispersion_from_moments):
+        s2, r = impl(ser, N, two_r, disp_axis=2, flow_axis=0, i0=30)
+        assert np.allclose(s2, a + b * t, rtol=1e-9, atol=1e-9)
+        assert abs(r["u_slip"] - 0.021) < 1e-15
+        assert abs(r["phi"] - 1500.0 / N) < 1e-15
+        K = b / (two_r * 0.021)
+        assert abs(r["K"] - K) < 1e-8 * K
+        assert abs(r["D_alpha"] - K / (1 - 1500.0 / N)) < 1e-8 * K
+        assert abs(r["offset"] - a / two_r ** 2) < 1e-8
+
+
+def test_pipeline_library_matches_oracle(orc):
+    from paper_2308_05007_amd import binding as B
+    rng = np.random.default_rng(9)
+    t = np.arange(0, 3001, 100)
+    ser = _series(t, 64 + rng.normal(0, 0.1, t.size), 2.0 + 0.01 * t + rng.normal(0, 0.5, t.size),
+                  rng.normal(0.01, 0.003, t.size), rng.normal(0.02, 0.004, t.size),
+                  rng.uniform(800, 900, t.size), nw=123457)
+    so, ro = orc.dispersion_from_moments(ser, 32 ** 3, 10.0, i0=15)
+    sl, rl = B.dispersion_from_moments(ser, 32 ** 3, 10.0, i0=15)
+    assert np.allclose(sl, so, rtol=1e-13, atol=0)
+    for k in ("u_slip", "phi", "K", "D_alpha", "offset"):
+        assert abs(rl[k] - ro[k]) <= 1e-10 * abs(ro[k]), k
+    with pytest.raises(B.RwmiError):
+        B.dispersion_from_moments(ser[:1], 32 ** 3, 10.0, i0=0)
+    with pytest.raises(B.RwmiError):
+        B.dispersion_from_moments(ser, 32 ** 3, 10.0, disp_axis=3)

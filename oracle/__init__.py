@@ -58,6 +58,7 @@ def lib():
             getattr(L, name).restype = C.c_int64
             getattr(L, name).argtypes = [P]
         L.orc_counters.argtypes = [P, u64p]
+        L.orc_get_ref.argtypes = [P, dp]
         L.orc_get_f.argtypes = [P, dp]
         L.orc_set_f.argtypes = [P, dp]
         L.orc_get_fields.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -216,6 +217,12 @@ class Oracle:
         return dict(n_walkers=out[0], sum=out[1:4].copy(), sumsq=out[4:7].copy(), mass=out[7],
                     momentum=out[8:11].copy(), fluid_u=out[11:14].copy(), particle_v=out[14:17].copy(),
                     solid_volume=out[17], step=out[18])
+
+    def ref(self):
+        """Reference point of the walker moments (set at seeding)."""
+        r = np.empty(3)
+        self.L.orc_get_ref(self.h, r)
+        return r
 
     def counters(self):
         c = np.zeros(8, np.uint64)

@@ -1014,6 +1014,7 @@ void orc_moments(const orc_domain* d, double* out) {
 int64_t orc_num_nodes(const orc_domain* d) { return d->N; }
 int64_t orc_num_walkers(const orc_domain* d) { return d->nw; }
 int64_t orc_time(const orc_domain* d) { return d->t; }
+void orc_get_ref(const orc_domain* d, double ref[3]) { memcpy(ref, d->ref, sizeof(d->ref)); }
 void orc_counters(const orc_domain* d, uint64_t* c) { memcpy(c, d->cnt, sizeof(d->cnt)); }
 void orc_get_f(const orc_domain* d, double* f) { memcpy(f, d->f, sizeof(double) * 19 * d->N); }
 void orc_set_f(orc_domain* d, const double* f) { memcpy(d->f, f, sizeof(double) * 19 * d->N); }

@@ -1,20 +1,20 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-FP64 mode: walker counts, cells, image counts and occupancy must match
-exactly; velocities, densities, distributions and walker offsets within 1e-10
-(relative to the field's scale), as the FP64 contract states.  The kernels
-follow the oracle's operation order, so in practice they agree bit for bit;
-the tests report the number of non-identical elements.
-"""
+FP64 mode: walker counts, cells, image counts, occupancy and event counters
+must match exactly.  The kernels follow the oracle's operation order with
+contraction off, so velocities, densities, distributions and walker offsets
+must match bit for bit as well (stricter than the 1e-10 relative the FP64
+contract allows); a failure reports how many elements differ and by how
+much.  The FP64 moments are sums the GPU takes in fixed chunks and the
+oracle sequentially: they must agree within the error bound of recursive
+summation, gamma_k times the sum of the absolute values of their terms
+(_sum_close)."""
 import numpy as np
 import pytest
 
 from paper_2308_05007_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-
-TOL = 1e-10
-
 
 @pytest.fixture(scope="module")
 def B():
@@ -34,14 +34,50 @@ def _pair(orc, B, cfg, seed=True):
     return o, g
 
 
-def _close(a, b, tol, what):
+def _same(a, b, what):
+    """Bitwise equality of two FP64 arrays (NaNs compare equal)."""
     a = np.asarray(a)
     b = np.asarray(b)
     assert a.shape == b.shape, what
-    scale = max(1.0, float(np.max(np.abs(b)))) if b.size else 1.0
-    err = float(np.max(np.abs(a - b))) if a.size else 0.0
-    assert err <= tol * scale, "%s: max diff %.3e (scale %.3e, %d of %d differ)" % (
-        what, err, scale, int(np.count_nonzero(a != b)), a.size)
+    if not np.array_equal(a, b, equal_nan=True):
+        d = np.abs(a - b)
+        raise AssertionError("%s: %d of %d elements differ, max diff %.3e (max |ref| %.3e)" % (
+            what, int(np.count_nonzero(a != b)), a.size, float(np.nanmax(d)), float(np.max(np.abs(b)))))
+
+
+def _sum_close(got, ref, abs_sum, n_terms, what, ratio=False):
+    """A sum of n_terms FP64 terms that the oracle adds one after another and
+    the GPU in chunks of 4096 (then the chunk partials in order): each result
+    is within gamma_k sum |x_i| of the exact sum, gamma_k = k u / (1 - k u),
+    u = 2^-53, k the longest chain of additions (n_terms for the oracle, at
+    most 4096 + n_terms / 4096 for the GPU); a ratio of two such sums with a
+    positive denominator (the fluid and particle averages) at most twice
+    that, relative to the ratio's |numerator terms| / denominator."""
+    got, ref, abs_sum = (np.atleast_1d(np.asarray(v, float)) for v in (got, ref, abs_sum))
+    k = n_terms + 4096 + n_terms / 4096.0 + 2
+    gamma = k * 2.0 ** -53 / (1 - k * 2.0 ** -53)
+    bound = (2.0 if ratio else 1.0) * gamma * abs_sum
+    err = np.abs(got - ref)
+    assert np.all(err <= bound), "%s: diff %s, bound %s" % (what, err, bound)
+
+
+def _moment_scales(o):
+    """Sums of the absolute values of the terms of every FP64 moment, from the
+    oracle's own state (fields, walkers)."""
+    fo = o.fields()
+    fluid = _fluid_mask(o.n, o_bc(o))
+    rho, u, eps, us = fo["rho"][fluid], fo["u"][:, fluid], fo["eps"][fluid], fo["us"][:, fluid]
+    cell, off, img = o.walkers()
+    n = np.asarray(o.n)
+    X = np.stack([cell % n[0], (cell // n[0]) % n[1], cell // (n[0] * n[1])]).astype(float) + img * n[:, None] + off
+    dx = X - o.ref()[:, None]
+    se, s1e = eps.sum(), (1.0 - eps).sum()
+    return dict(n_walkers=cell.size, n_fluid=int(rho.size),
+                sum=np.abs(dx).sum(1), sumsq=(dx * dx).sum(1), mass=np.abs(rho).sum(),
+                momentum=np.abs(rho * u).sum(1),
+                fluid_u=np.abs((1.0 - eps) * u).sum(1) / s1e if s1e > 0 else np.zeros(3),
+                particle_v=np.abs(eps * us).sum(1) / se if se > 0 else np.zeros(3),
+                solid_volume=np.abs(eps).sum())
 
 
 def o_bc(o):
@@ -60,32 +96,35 @@ def _fluid_mask(n, bc):
     return m
 
 
-def compare(o, g, fields=True, f=True, walkers=True, mom=True, tol=TOL):
+def compare(o, g, fields=True, f=True, walkers=True, mom=True):
     if fields:
         fo = o.fields()
         ug, rg = g.velocity()
-        _close(ug, fo["u"], tol, "velocity")
-        _close(rg, fo["rho"], tol, "density")
+        _same(ug, fo["u"], "velocity")
+        _same(rg, fo["rho"], "density")
     if f:
         # wall nodes hold no distributions (unspecified by the ABI)
         fluid = _fluid_mask(o.n, o_bc(o))
-        _close(g.distributions()[:, fluid], o.f()[:, fluid], tol, "distributions")
+        _same(g.distributions()[:, fluid], o.f()[:, fluid], "distributions")
     if walkers:
         co, oo, io = o.walkers()
         cg, og, ig = g.walkers()
         assert cg.size == co.size
         assert np.array_equal(cg, co), "cells differ for %d walkers" % int(np.count_nonzero(cg != co))
         assert np.array_equal(ig, io), "image counts differ"
-        _close(og, oo, tol, "offsets")
+        _same(og, oo, "offsets")
         assert np.array_equal(g.occupancy(), o.occupancy()), "occupancy differs"
     if mom:
         mo = o.moments()
         mg = g.moments()
         assert mg["n_walkers"] == int(mo["n_walkers"])
-        for k in ("sum", "sumsq", "momentum", "fluid_u", "particle_v"):
-            _close(mg[k], mo[k], 1e-9, "moment " + k)
-        for k in ("mass", "solid_volume"):
-            assert abs(mg[k] - mo[k]) <= 1e-9 * max(1.0, abs(mo[k])), k
+        sc = _moment_scales(o)
+        for k in ("sum", "sumsq"):
+            _sum_close(mg[k], mo[k], sc[k], sc["n_walkers"], "moment " + k)
+        for k in ("momentum", "mass", "solid_volume"):
+            _sum_close(mg[k], mo[k], sc[k], sc["n_fluid"], "moment " + k)
+        for k in ("fluid_u", "particle_v"):
+            _sum_close(mg[k], mo[k], sc[k], sc["n_fluid"], "moment " + k, ratio=True)
         assert mg["counters"] == o.counters()
 
 
@@ -245,33 +284,105 @@ def test_channel_128_fp32_headline(orc, B):
     assert int(g.occupancy().sum()) == cfg["walkers"]["n"]
 
 
-def test_oscillator_256_fp16_full_size(orc, B):
-    """The other benchmarked configuration at its full size (256^3 periodic,
-    FP16 storage of deviations, 64 oscillating metaballs, 1e7 walkers in the
-    solute band; default launch shape, two lattices) against the FP64 oracle
-    after 2 steps, within the FP16 mode's stated bounds: velocity L2 3e-3
-    relative, median walker position error 3e-4 cell; walker count and
-    occupancy sum exact."""
-    cfg = W.config_oscillator(precision="fp16")
-    o, g = _pair(orc, B, cfg)
-    for _ in range(2):
-        o.step(1)
-        g.step(1)
+# Stated bounds of the storage modes against FP64 (tests/test_gpu_precision.py
+# holds the same values for the 500-step comparison): velocity L2 relative,
+# 99th percentile of the walker position error (cells); and, element by
+# element, the velocity error relative to max |u|: at most 19 populations of
+# magnitude |delta f| <= 1e-3 each carry half an ulp of the storage format
+# (2^-11 relative for FP16, 2^-8 for BF16), which gives 1.5e-3 and 1.2e-2 of a
+# velocity of 5e-3 (the particles' peak speed); the bounds are three times that.
+# FP32 storage rounds at 2^-24: 19 x 1e-3 x 2^-24 is 2.3e-7 of that velocity,
+# and the float collision adds rounding of the same order; the bound is 1e-5.
+LOWP_BOUNDS = {"fp32": dict(vel_l2=5e-5, pos_p99=2e-5, vel_max=1e-5),
+               "fp16": dict(vel_l2=3e-3, pos_p99=3e-4, vel_max=5e-3),
+               "bf16": dict(vel_l2=1.5e-2, pos_p99=3e-3, vel_max=4e-2)}
+
+
+@pytest.fixture(scope="module")
+def oscillator_oracle_2steps(orc):
+    """The FP64 oracle of the 256^3 oscillator (64 oscillating metaballs, 1e7
+    walkers in the solute band) after 2 steps: velocity and walker positions."""
+    from paper_2308_05007_amd import workloads as W2
+    cfg = W2.config_oscillator(precision="fp64")
+    o = orc.build_domain(cfg)
+    w = cfg["walkers"]
+    assert o.seed(w, w["n"]) == w["n"]
+    o.step(2)
+    out = dict(u=o.fields()["u"], walkers=o.walkers(), n=cfg["domain"]["n"])
+    del o
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_oscillator_256_lowp_full_size(oscillator_oracle_2steps, B, prec):
+    """The benchmarked 256^3 oscillator at its full size (the headline FP32
+    storage, and 16-bit storage of deviations; default launch shape, two
+    lattices) against the FP64 oracle after 2 steps, within the mode's stated
+    bounds: velocity L2, velocity element by element, the 99th percentile of
+    the walker position error; walker count and occupancy sum exact."""
+    ref = oscillator_oracle_2steps
+    cfg = W.config_oscillator(precision=prec)
+    g = B.build_domain(cfg)
+    g.step(1)
+    g.step(1)
     ug, _ = g.velocity()
-    uo = o.fields()["u"]
+    uo = ref["u"]
     rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
-    co, oo, io = o.walkers()
+    vmax = float(np.max(np.abs(ug - uo)) / np.max(np.abs(uo)))
+    co, oo, io = ref["walkers"]
     cg, og, ig = g.walkers()
-    n = cfg["domain"]["n"]
+    n = ref["n"]
     L = np.array(n)[:, None]
     X = lambda c, off, im: np.stack([c % n[0], (c // n[0]) % n[1], c // (n[0] * n[1])]) + off + L * im
-    d = np.abs(X(cg, og, ig) - X(co, oo, io)).max(0)
-    print("oscillator 256^3 FP16 vs oracle: velocity L2 %.3g, median position %.3g, 99.9%% %.3g"
-          % (rel, np.median(d), np.quantile(d, 0.999)))
-    assert rel < 3e-3, rel
-    assert np.median(d) < 3e-4, np.median(d)
+    d = np.sqrt(((X(cg, og, ig) - X(co, oo, io)) ** 2).sum(0))
+    bd = LOWP_BOUNDS[prec]
+    print("oscillator 256^3 %s vs oracle: velocity L2 %.3g, max |du|/max|u| %.3g, position p50 %.3g p99 %.3g max %.3g"
+          % (prec, rel, vmax, np.median(d), np.quantile(d, 0.99), d.max()))
+    assert rel < bd["vel_l2"], rel
+    assert vmax < bd["vel_max"], vmax
+    assert np.quantile(d, 0.99) < bd["pos_p99"], np.quantile(d, 0.99)
     assert g.moments()["n_walkers"] == cfg["walkers"]["n"]
     assert int(g.occupancy().sum()) == cfg["walkers"]["n"]
+    g.close()
+
+
+def test_batch_fp64_against_oracle(orc, B):
+    """Nine uneven FP64 simulations stepped as one batch (members of the
+    48^3-96^3 shape sweep with fewer walkers, ragged and wall-bounded small
+    lattices; four of them on two lattices, the rest in place, so the batch
+    runs both layout groups), the steps replayed from captured graphs of 7
+    and 13 steps: every member equals its own oracle run bit for bit."""
+    cfgs = []
+    for i in (0, 3, 5):
+        c = W.config_batch_member(i, precision="fp64", steps=20)
+        c["walkers"]["n"] = 20_000
+        cfgs.append(c)
+    for k, (n, bc, npart, nw) in enumerate((((33, 47, 29), ("periodic",) * 3, 2, 3000),
+                                           ((50, 40, 44), ("periodic", "wall", "periodic"), 3, 4000),
+                                           ((40, 36, 52), ("wall", "periodic", "wall"), 2, 2500),
+                                           ((17, 9, 11), ("periodic", "wall", "periodic"), 1, 700),
+                                           ((56, 48, 40), ("periodic",) * 3, 0, 1500),
+                                           ((48, 56, 48), ("periodic",) * 3, 2, 0))):
+        cfgs.append(W.config_tiny(n=n, bc=bc, n_particles=npart, n_walkers=nw, seed=200 + k, spread=1.5, amp=2.0,
+                                  period=30.0, D=0.02, precision="fp64"))
+    pairs = [_pair(orc, B, c) for c in cfgs]
+    for k, (o, g) in enumerate(pairs):
+        if k % 2 == 1:
+            g.set("streaming", 1)  # two lattices
+    bt = B.Batch()
+    for _, g in pairs:
+        bt.add(g)
+    bt.set("use_graph", 1)
+    for chunk in (7, 13):
+        bt.step(chunk)
+        bt.sync()
+        for o, g in pairs:
+            o.step(chunk)
+    for k, (o, g) in enumerate(pairs):
+        compare(o, g)
+    bt.close()
+    for _, g in pairs:
+        g.close()
 
 
 @pytest.mark.parametrize("bs", [128, 256, 512])

@@ -86,18 +86,20 @@ def kernel_source_hash(prec):
 
 
 def pmc_traffic(workload_key, prec):
-    """HBM bytes per full step launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    """HBM bytes per timed step launch (FETCH_SIZE and WRITE_SIZE, calibrated
+    on a plain copy) and the algorithmic bytes of the same launches, from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel source; else (None, None)."""
     path = os.path.join(ROOT, "profiles", "step_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return None, None
     e = d.get(workload_key)
     if not e or e.get("kernel_source_sha256_16") != kernel_source_hash(prec):
-        return None
-    return e.get("hbm_bytes_per_launch")
+        return None, None
+    return e.get("hbm_bytes_per_launch"), e.get("algorithmic_bytes_per_launch")
 
 
 def _oracle_sample(cfg, seconds, max_steps, threads):
@@ -212,6 +214,7 @@ def bench_plain(args):
     steps, warmup = args.steps, args.warmup
     r = measure(cfg, key, steps, warmup, args.timing_every, burnin=burnin_steps(cfg, args))
     mom = r["mom"]
+    traffic, traffic_alg = pmc_traffic(key, prec)
     out = {
         "metric": METRIC, "value": round(r["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": round(r["dt"] / steps * 1e3, 5), "higher_is_better": True,
@@ -223,7 +226,8 @@ def bench_plain(args):
         "walker_steps_per_s": round(r["wsps"], 1),
         "roofline": {"bound": "hbm", "achieved": round(r["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
-                     "traffic": pmc_traffic(key, prec),
+                     "traffic": traffic,
+                     "traffic_over_algorithmic": round(traffic / traffic_alg, 4) if traffic and traffic_alg else None,
                      "kernel": "k_step (fused: PSM-BGK collide + pull-stream, walkers, particle prologue)",
                      "bytes_per_launch": r["bytes_launch"], "avg_launch_us": round(r["avg_us"], 2),
                      "timed_launches": r["launches"], "timing_window": args.timing_every},
@@ -312,6 +316,7 @@ def main():
     ap.add_argument("--timing-every", type=int, default=32,
                     help="HIP events bracket windows of this many consecutive step launches")
     args = ap.parse_args()
+    args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)

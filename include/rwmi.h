@@ -272,7 +272,8 @@ enum {
   RWMI_KEY_TIMING = 5,
   RWMI_KEY_STEP_FLAGS = 6,
   RWMI_KEY_SORT_EVERY = 7,
-  RWMI_KEY_STREAMING = 8
+  RWMI_KEY_STREAMING = 8,
+  RWMI_KEY_MEMBER_BLOCKS = 10
 };
 rwmi_status rwmi_debug_set(rwmi_domain* dom, int32_t key, int64_t value);
 
@@ -307,7 +308,12 @@ rwmi_status rwmi_batch_remove(rwmi_batch* b, rwmi_domain* dom);
 /* Enqueue n_steps steps of every member on the batch stream. */
 rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps);
 /* Launch options of the batch (RWMI_KEY_USE_GRAPH, _BLOCK, _STEP_FLAGS); they
- * replace the members' own for batch steps. */
+ * replace the members' own for batch steps.  RWMI_KEY_MEMBER_BLOCKS = 1: each
+ * member launches with its own block size (RWMI_KEY_BLOCK of that domain, which
+ * may be set while it is in the batch), so that every size class of a mixed
+ * batch has its own launch shape; the members of one precision, layout and
+ * block size share each launch, and all launches of a step are captured in
+ * one graph.  0 (default): every member uses the batch's RWMI_KEY_BLOCK. */
 rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value);
 rwmi_status rwmi_batch_synchronize(rwmi_batch* b);
 void rwmi_batch_destroy(rwmi_batch* b);

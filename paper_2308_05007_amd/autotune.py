@@ -1,7 +1,9 @@
 """Launch-shape autotuner for single domains and batches.
 
 A candidate is (threads per block of the fused step launch, step launch
-flags).  The tuner builds scratch copies of the workload (the real
+flags).  A mixed batch can also be tuned per size class (its members'
+largest lattice edge): each class gets its own block size, the flags are
+shared (tune_batch_classes).  The tuner builds scratch copies of the workload (the real
 state is never stepped), times each candidate over a few coupled steps after a
 warm-up, and keeps the fastest.  Results are cached per workload signature
 (kind, precision, lattice size classes, walker magnitude, device name) in a
@@ -107,6 +109,73 @@ def build_batch(cfgs, use_graph=True):
     if use_graph:
         bt.set("use_graph", 1)
     return bt, doms
+
+
+def size_class(cfg):
+    """Size class of a simulation: its largest lattice edge."""
+    return int(max(cfg["domain"]["n"]))
+
+
+def apply_classes(bt, doms, cfgs, shape):
+    """Launch a batch with a block size per size class: shape = (dict class
+    -> block, flags)."""
+    blocks, flags = shape
+    bt.set("member_blocks", 1)
+    bt.set("step_flags", flags)
+    for d, c in zip(doms, cfgs):
+        d.set("block", blocks[str(size_class(c))])
+
+
+def _time_batch(bt, steps, warmup):
+    bt.step(warmup)
+    bt.sync()
+    t0 = time.perf_counter()
+    bt.step(steps)
+    bt.sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def tune_batch_classes(cfgs, steps=16, warmup=8, use_cache=True, passes=1):
+    """Block size per size class, then the step flags, for a mixed batch: one
+    class at a time, its members' block size is varied with the others held,
+    and the batch is timed (coordinate descent over the classes, `passes`
+    sweeps); the flags are chosen last for the whole batch.  Returns
+    ({class: block}, flags) with classes as strings (JSON keys)."""
+    key = signature("batch-classes", cfgs)
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            return {k: int(v) for k, v in hit["blocks"].items()}, int(hit["flags"])
+    classes = sorted({size_class(c) for c in cfgs})
+    blocks = {str(k): 256 for k in classes}
+    flags = 1
+    bt, doms = build_batch(cfgs, use_graph=False)
+    table = {}
+    best_t = float("inf")
+    for _ in range(passes):
+        for k in classes:
+            best_b = blocks[str(k)]
+            for bs in BLOCKS:
+                blocks[str(k)] = bs
+                apply_classes(bt, doms, cfgs, (blocks, flags))
+                dt = _time_batch(bt, steps, warmup)
+                table["class %d block %d" % (k, bs)] = dt * 1e6
+                if dt < best_t:
+                    best_t, best_b = dt, bs
+            blocks[str(k)] = best_b
+    best_f = flags
+    for fl in FLAGS:
+        apply_classes(bt, doms, cfgs, (blocks, fl))
+        dt = _time_batch(bt, steps, warmup)
+        table["flags %d" % fl] = dt * 1e6
+        if dt < best_t:
+            best_t, best_f = dt, fl
+    flags = best_f
+    bt.close()
+    for d in doms:
+        d.close()
+    _store(key, {"blocks": blocks, "flags": flags, "us_per_step": best_t * 1e6, "table_us": table})
+    return blocks, flags
 
 
 def tune_batch(cfgs, steps=16, warmup=8, use_cache=True, cands=None):

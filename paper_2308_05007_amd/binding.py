@@ -18,7 +18,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: 
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 MOTION = {"static": 0, "sinusoid": 1, "const_vel": 2}
 SEED_KIND = {"uniform": 0, "gaussian": 1, "band": 2, "explicit": 3}
-KEY = {"max_bisect": 1, "use_graph": 2, "block": 3, "timing": 5, "step_flags": 6, "sort_every": 7, "streaming": 8}
+KEY = {"max_bisect": 1, "use_graph": 2, "block": 3, "timing": 5, "step_flags": 6, "sort_every": 7, "streaming": 8, "member_blocks": 10}
 MAX_PARTICLES = 64
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

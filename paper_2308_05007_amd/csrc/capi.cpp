@@ -22,6 +22,10 @@ namespace {
 thread_local std::string g_err = "no error";
 
 constexpr uint64_t kNeverSorted = ~0ull;  // sorted_at before the first regrouping
+// Steps captured in one graph: the default regrouping interval, so that a
+// replay (which regroups the walkers at its start) regroups no more often
+// than eager stepping does.
+constexpr uint32_t kGraphSteps = 128;
 
 struct HostParticle {
   std::vector<double> b, k;
@@ -112,9 +116,10 @@ struct rwmi_batch {
   std::vector<rwmi_domain*> members;
   bool dirty = true;
   // per precision group: device arrays of views and work maps
-  struct Group {  // members of one precision and lattice layout
+  struct Group {  // members of one precision, lattice layout and block size
     int prec;
     int inplace;
+    int bs;
     std::vector<rwmi_domain*> doms;
     DomView* views = nullptr;
     int32_t* boff = nullptr;  // kRoles maps x (nd + 1)
@@ -126,6 +131,7 @@ struct rwmi_batch {
   hipGraphExec_t gexec = nullptr;
   uint32_t gsteps = 0;
   int bs = 256;
+  bool member_blocks = false;  // each member launches with its own block size
   int flags = rwmi::kFlagXcd;
 };
 
@@ -701,7 +707,7 @@ rwmi_status rwmi_step(rwmi_domain* d, uint32_t n_steps) {
   d->stepped = true;
   uint32_t left = n_steps;
   if (d->use_graph && !d->timing && n_steps >= 2) {
-    const uint32_t k = std::min<uint32_t>(n_steps, 64);
+    const uint32_t k = std::min<uint32_t>(n_steps, kGraphSteps);
     if (!d->gexec || d->gsteps != k) {
       drop_graph(d);
       hipGraph_t g;
@@ -942,9 +948,11 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       return RWMI_OK;
     case RWMI_KEY_BLOCK:
       if (value != 128 && value != 256 && value != 512) return fail(d, RWMI_EINVAL, "block must be 128, 256 or 512");
-      if (d->batch) return fail(d, RWMI_ESTATE, "the batch sets the block size of its members");
       d->bs = (int)value;
       drop_graph(d);
+      // a batch holding it regroups it (if the batch launches members with
+      // their own block sizes); its own work map serves steps on its own
+      if (d->batch) d->batch->dirty = true;
       return upload_workmaps(d);
     case RWMI_KEY_TIMING:
       if (value < 0 || value > (1 << 20)) return fail(d, RWMI_EINVAL, "timing period out of range");
@@ -1151,13 +1159,17 @@ static rwmi_status batch_rebuild(rwmi_batch* b) {
   if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, RWMI_EDEVICE, "batch sync failed");
   batch_drop_graph(b);
   batch_free_groups(b);
-  for (int key = 0; key < 8; ++key) {
-    const int prec = key >> 1, ip = key & 1;
+  static const int kBlockSizes[3] = {128, 256, 512};
+  for (int key = 0; key < 24; ++key) {
+    const int prec = key >> 3, ip = (key >> 2) & 1, bsi = key & 3;
+    if (bsi > 2) continue;
+    const int gbs = kBlockSizes[bsi];
     rwmi_batch::Group g;
     g.prec = prec;
     g.inplace = ip;
+    g.bs = gbs;
     for (rwmi_domain* d : b->members)
-      if (d->prec == prec && d->hv.inplace == ip) g.doms.push_back(d);
+      if (d->prec == prec && d->hv.inplace == ip && (b->member_blocks ? d->bs : b->bs) == gbs) g.doms.push_back(d);
     if (g.doms.empty()) continue;
     const int nd = (int)g.doms.size();
     std::vector<DomView> hv(nd);
@@ -1165,7 +1177,7 @@ static rwmi_status batch_rebuild(rwmi_batch* b) {
     int64_t acc[kRoles] = {0, 0, 0};
     for (int i = 0; i < nd; ++i) {
       int bl[kRoles];
-      role_blocks(g.doms[i], b->bs, bl);
+      role_blocks(g.doms[i], gbs, bl);
       for (int k = 0; k < kRoles; ++k) {
         boff[k * (nd + 1) + i] = (int32_t)acc[k];
         acc[k] += bl[k];
@@ -1216,7 +1228,7 @@ static rwmi_status batch_enqueue_group(rwmi_batch* b, uint32_t n, bool capturing
       a.inplace = g.inplace;
       a.j = j;
       if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
-      if (rwmi::launch_step(g.prec, b->bs, a, A) != hipSuccess) return bfail(b, RWMI_EDEVICE, "batch launch failed");
+      if (rwmi::launch_step(g.prec, g.bs, a, A) != hipSuccess) return bfail(b, RWMI_EDEVICE, "batch launch failed");
     }
   }
   for (auto& g : b->groups)
@@ -1238,7 +1250,7 @@ rwmi_status rwmi_batch_step(rwmi_batch* b, uint32_t n_steps) {
   if (b->members.empty()) return RWMI_OK;
   uint32_t left = n_steps;
   if (b->use_graph && n_steps >= 2) {
-    const uint32_t k = std::min<uint32_t>(n_steps, 64);
+    const uint32_t k = std::min<uint32_t>(n_steps, kGraphSteps);
     if (!b->gexec || b->gsteps != k) {
       batch_drop_graph(b);
       hipGraph_t g;
@@ -1298,6 +1310,11 @@ rwmi_status rwmi_batch_set(rwmi_batch* b, int32_t key, int64_t value) {
       if (value < 0 || value > 3) return bfail(b, RWMI_EINVAL, "step flags must be in 0..3");
       b->flags = (int)value;
       batch_drop_graph(b);
+      return RWMI_OK;
+    case RWMI_KEY_MEMBER_BLOCKS:
+      if (value != 0 && value != 1) return bfail(b, RWMI_EINVAL, "member blocks must be 0 or 1");
+      b->member_blocks = value != 0;
+      b->dirty = true;
       return RWMI_OK;
     default:
       return bfail(b, RWMI_EINVAL, "unknown batch key");

@@ -350,8 +350,10 @@ def test_batch_fp64_against_oracle(orc, B):
     """Nine uneven FP64 simulations stepped as one batch (members of the
     48^3-96^3 shape sweep with fewer walkers, ragged and wall-bounded small
     lattices; four of them on two lattices, the rest in place, so the batch
-    runs both layout groups), the steps replayed from captured graphs of 7
-    and 13 steps: every member equals its own oracle run bit for bit."""
+    runs both layout groups; each member with its own block size of 128, 256
+    or 512, as a per-size-class launch shape sets them), the steps replayed
+    from captured graphs of 7 and 13 steps: every member equals its own
+    oracle run bit for bit."""
     cfgs = []
     for i in (0, 3, 5):
         c = W.config_batch_member(i, precision="fp64", steps=20)
@@ -373,6 +375,9 @@ def test_batch_fp64_against_oracle(orc, B):
     for _, g in pairs:
         bt.add(g)
     bt.set("use_graph", 1)
+    bt.set("member_blocks", 1)
+    for k, (_, g) in enumerate(pairs):
+        g.set("block", (128, 256, 512)[k % 3])
     for chunk in (7, 13):
         bt.step(chunk)
         bt.sync()

@@ -28,6 +28,7 @@ Other workloads (own JSON line each, not the headline):
   --workload channel [--precision ...]                    128^3 channel alone
   --workload precision                                    all storage modes vs FP64
   --workload batch                                        64-simulation sweep
+  --workload ensemble [--realisations 4 --radius 5]       shape sweep of Sec. 4 (D_alpha, Spearman)
   --workload copy [--lattice MiB]                         plain copy (HBM counter calibration)
   --workload serve [--rate 20 --duration 15]              Poisson request stream
 """
@@ -301,7 +302,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="oscillator",
-                    choices=["oscillator", "channel", "precision", "batch", "serve", "copy"])
+                    choices=["oscillator", "channel", "precision", "batch", "ensemble", "serve", "copy"])
     ap.add_argument("--lattice", type=int, default=None)
     ap.add_argument("--rate", type=float, default=None)
     ap.add_argument("--duration", type=float, default=None)
@@ -311,6 +312,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the FP16/BF16 and channel figures")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--realisations", type=int, default=None, help="ensemble: realisations per shape")
+    ap.add_argument("--radius", type=float, default=None, help="ensemble: particle radius R in lattice units")
     ap.add_argument("--burnin", type=int, default=None,
                     help="untimed steps before the warm-up (default: half of the workload's run)")
     ap.add_argument("--timing-every", type=int, default=32,
@@ -330,6 +333,9 @@ def main():
     elif args.workload == "batch":
         from paper_2308_05007_amd import batchbench
         batchbench.main(args)
+    elif args.workload == "ensemble":
+        from paper_2308_05007_amd import ensemble
+        ensemble.bench(args)
     else:
         from paper_2308_05007_amd import serve
         serve.bench(args)

@@ -224,6 +224,13 @@ rwmi_status rwmi_read_moments_noalloc(rwmi_domain* dom, rwmi_moments* out);
  * uint32, nx*ny*nz entries (synchronises). */
 rwmi_status rwmi_read_occupancy(rwmi_domain* dom, uint32_t* ns);
 
+/* Concentration profile along an axis: counts[k] = the number of walkers
+ * whose cell lies in layer k of that axis (Eq. 16 summed over the two other
+ * axes; Sec. 4 averages such profiles over realisations and fits a Gaussian
+ * to them).  n[axis] entries, exact; synchronises.  EINVAL for an axis
+ * outside 0..2. */
+rwmi_status rwmi_read_profile(rwmi_domain* dom, int32_t axis, uint64_t* counts);
+
 /* Velocity u(t) of the last fluid update, SoA [3][nodes] as double, and the
  * density of that update (rho may be NULL).  Wall nodes carry the wall
  * velocity.  Before any step: u0 and rho0. */
@@ -357,6 +364,14 @@ typedef struct {
 rwmi_status rwmi_dispersion_from_moments(const rwmi_moments* series, uint32_t n, uint32_t i0, int32_t disp_axis,
                                          int32_t flow_axis, uint64_t n_nodes, double two_r, double* sigma2,
                                          rwmi_dispersion* out);
+
+/* Least-squares Gaussian y = amp exp(-(x - mean)^2 / (2 var)) through n
+ * points (Sec. 4: Gaussian distributions fitted to the averaged
+ * concentration profiles give the variance series of Eq. 38), by
+ * Levenberg-Marquardt from the profile's weighted moments.  Host-only
+ * arithmetic on caller arrays.  EINVAL if fewer than three y are positive
+ * (three parameters are not fixed by fewer points). */
+rwmi_status rwmi_gaussian_fit(const double* x, const double* y, uint32_t n, double* amp, double* mean, double* var);
 
 /* ---------------------------------------------------------------- diagnostics
  * The Gaussian triples the walker kernels draw for counters (id, t, purpose,

@@ -86,6 +86,9 @@ def lib():
         L.orc_dispersion_from_moments.restype = C.c_int
         L.orc_dispersion_from_moments.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                                   C.c_void_p, dp]
+        L.orc_profile.argtypes = [P, C.c_int, u64p]
+        L.orc_gaussian_fit.restype = C.c_int
+        L.orc_gaussian_fit.argtypes = [dp, dp, C.c_int, dp]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
         L.orc_dispersion_fit.restype = C.c_int
@@ -224,6 +227,12 @@ class Oracle:
         self.L.orc_get_ref(self.h, r)
         return r
 
+    def profile(self, axis=2):
+        """Walkers per layer along `axis`."""
+        c = np.empty(self.n[axis], np.uint64)
+        self.L.orc_profile(self.h, int(axis), c)
+        return c
+
     def counters(self):
         c = np.zeros(8, np.uint64)
         self.L.orc_counters(self.h, c)
@@ -347,6 +356,16 @@ def dispersion_from_moments(series, n_nodes, two_r, disp_axis=2, flow_axis=0, i0
     if r != 0:
         raise ValueError("oracle dispersion: invalid input")
     return s2, dict(u_slip=out[0], phi=out[1], K=out[2], D_alpha=out[3], offset=out[4])
+
+
+def gaussian_fit(x, y):
+    """(A, mu, s2) of the least-squares Gaussian through (x, y)."""
+    out = np.empty(3)
+    x = _d(x)
+    y = _d(y)
+    if lib().orc_gaussian_fit(x, y, x.size, out) != 0:
+        raise ValueError("oracle gaussian fit: invalid input")
+    return out[0], out[1], out[2]
 
 
 def set_threads(n):

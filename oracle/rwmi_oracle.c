@@ -965,6 +965,18 @@ void orc_occupancy(const orc_domain* d, uint32_t* ns) {
   for (int64_t w = 0; w < d->nw; w++) ns[d->cell[w]]++;
 }
 
+/* Concentration profile along an axis (Eq. 16 summed over the other two
+ * axes): walkers per layer of the lattice along `axis`. */
+void orc_profile(const orc_domain* d, int axis, uint64_t* counts) {
+  const int nx = d->n[0], ny = d->n[1];
+  memset(counts, 0, sizeof(uint64_t) * d->n[axis]);
+  for (int64_t w = 0; w < d->nw; w++) {
+    int32_t lc = d->cell[w];
+    int c[3] = {lc % nx, (lc / nx) % ny, lc / (nx * ny)};
+    counts[c[axis]]++;
+  }
+}
+
 /* Moments (sequential sums in index order):
  * out[0]   walker count
  * out[1-3] sum (X - ref), X unwrapped with image counts
@@ -1208,4 +1220,97 @@ int orc_dispersion_from_moments(const double* mom, int n, int i0, int disp_axis,
   free(t);
   free(v);
   return r;
+}
+
+/* Least-squares Gaussian y = A exp(-(x - mu)^2 / (2 s2)) through the points
+ * (x_k, y_k), the profile fit of Sec. 4.  Gauss-Newton on (A, mu, s2) from
+ * the moment estimates (weights y_k), each step solving the 3x3 normal
+ * equations by Cramer's rule, halving the step while the residual sum of
+ * squares does not decrease; stops when the relative change of every
+ * parameter is below 1e-13 or after 200 steps.  out3 = {A, mu, s2}.
+ * Returns 0, or -1 if fewer than 3 points are positive (three parameters
+ * are not fixed by fewer) or the normal matrix is singular. */
+static double gauss_rss(const double* x, const double* y, int n, const double p[3]) {
+  double r = 0.0;
+  for (int k = 0; k < n; k++) {
+    double d = x[k] - p[1];
+    double e = y[k] - p[0] * exp(-(d * d) / (2.0 * p[2]));
+    r = r + e * e;
+  }
+  return r;
+}
+
+static double det3(const double m[3][3]) {
+  return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+         m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
+int orc_gaussian_fit(const double* x, const double* y, int n, double* out3) {
+  if (n < 3) return -1;
+  double sw = 0.0, sx = 0.0, ymax = 0.0;
+  int npos = 0;
+  for (int k = 0; k < n; k++) {
+    if (y[k] > 0.0) {
+      sw = sw + y[k];
+      sx = sx + y[k] * x[k];
+      npos = npos + 1;
+    }
+    if (y[k] > ymax) ymax = y[k];
+  }
+  if (npos < 3) return -1;
+  double p[3];
+  p[1] = sx / sw;
+  double sv = 0.0;
+  for (int k = 0; k < n; k++)
+    if (y[k] > 0.0) sv = sv + y[k] * (x[k] - p[1]) * (x[k] - p[1]);
+  p[2] = sv / sw;
+  if (!(p[2] > 0.0)) p[2] = 1.0;
+  p[0] = ymax;
+  double rss = gauss_rss(x, y, n, p);
+  for (int it = 0; it < 200; it++) {
+    double JtJ[3][3] = {{0}}, Jtr[3] = {0};
+    for (int k = 0; k < n; k++) {
+      double d = x[k] - p[1];
+      double g = exp(-(d * d) / (2.0 * p[2]));
+      double J[3] = {g, p[0] * g * d / p[2], p[0] * g * d * d / (2.0 * p[2] * p[2])};
+      double r = y[k] - p[0] * g;
+      for (int a = 0; a < 3; a++) {
+        Jtr[a] = Jtr[a] + J[a] * r;
+        for (int b = 0; b < 3; b++) JtJ[a][b] = JtJ[a][b] + J[a] * J[b];
+      }
+    }
+    double D = det3(JtJ);
+    if (D == 0.0 || !isfinite(D)) return -1;
+    double step[3];
+    for (int c = 0; c < 3; c++) {
+      double M[3][3];
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) M[a][b] = b == c ? Jtr[a] : JtJ[a][b];
+      step[c] = det3(M) / D;
+    }
+    double lam = 1.0, q[3], rq = 0.0;
+    int ok = 0;
+    for (int h = 0; h < 60; h++) {
+      for (int a = 0; a < 3; a++) q[a] = p[a] + lam * step[a];
+      if (q[2] > 0.0) {
+        rq = gauss_rss(x, y, n, q);
+        if (rq <= rss) {
+          ok = 1;
+          break;
+        }
+      }
+      lam = 0.5 * lam;
+    }
+    if (!ok) break;
+    double ch = 0.0;
+    for (int a = 0; a < 3; a++) {
+      double c = fabs(q[a] - p[a]) / (fabs(q[a]) > 1e-300 ? fabs(q[a]) : 1e-300);
+      if (c > ch) ch = c;
+      p[a] = q[a];
+    }
+    rss = rq;
+    if (ch < 1e-13) break;
+  }
+  for (int a = 0; a < 3; a++) out3[a] = p[a];
+  return 0;
 }

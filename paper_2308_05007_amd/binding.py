@@ -68,6 +68,7 @@ SIGNATURES = {
     "rwmi_read_moments": (C.c_int, [C.c_void_p, C.POINTER(Moments)]),
     "rwmi_read_moments_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Moments)]),
     "rwmi_read_occupancy": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rwmi_read_profile": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "rwmi_read_velocity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rwmi_read_walkers": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rwmi_read_distributions": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -87,6 +88,8 @@ SIGNATURES = {
     "rwmi_batch_destroy": (None, [C.c_void_p]),
     "rwmi_dispersion_from_moments": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
                                                C.c_uint64, C.c_double, C.c_void_p, C.c_void_p]),
+    "rwmi_gaussian_fit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rwmi_device_normals": (C.c_int, [C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p]),
     "rwmi_dispersion_fit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_double, C.c_double,
                                       C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -337,6 +340,12 @@ class Domain:
         self._ck(self.L.rwmi_read_occupancy(self.h, ns.ctypes.data_as(C.c_void_p)))
         return ns.reshape(self.n[::-1])
 
+    def profile(self, axis=2):
+        """Walkers per layer along `axis` (exact counts, n[axis] entries)."""
+        c = np.empty(self.n[axis], np.uint64)
+        self._ck(self.L.rwmi_read_profile(self.h, int(axis), c.ctypes.data_as(C.c_void_p)))
+        return c
+
     def velocity(self):
         u = np.empty(3 * self.N)
         rho = np.empty(self.N)
@@ -466,6 +475,16 @@ def dispersion_from_moments(series, n_nodes, two_r, disp_axis=2, flow_axis=0, i0
     _check(lib().rwmi_dispersion_from_moments(arr, n, i0, int(disp_axis), int(flow_axis), int(n_nodes), float(two_r),
                                               s2.ctypes.data_as(C.c_void_p), C.byref(out)))
     return s2[:n], dict(u_slip=out.u_slip, phi=out.phi, K=out.K, D_alpha=out.D_alpha, offset=out.offset)
+
+
+def gaussian_fit(x, y):
+    """(amp, mean, var) of the least-squares Gaussian through (x, y) (library host code)."""
+    x = np.ascontiguousarray(x, float)
+    y = np.ascontiguousarray(y, float)
+    a, m, v = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().rwmi_gaussian_fit(x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p), x.size, C.byref(a),
+                                   C.byref(m), C.byref(v)))
+    return a.value, m.value, v.value
 
 
 def device_normals(seed, t, purpose, n, device=0):

@@ -118,6 +118,44 @@ __global__ void k_occupancy(const DomView* __restrict__ views, int dom) {
     __hip_atomic_fetch_add(gp(V.occ) + gp(V.wcell)[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---------------------------------------------------------------- profile
+// Concentration profile along one axis (Eq. 16 summed over the two other
+// axes): the number of walkers whose cell lies in each layer.  Exact integer
+// counts in any order of addition.  Layers up to kProfileLds are counted in
+// a block histogram in LDS first, then added to the global counts once per
+// block and layer.
+constexpr int kProfileLds = 4096;
+constexpr int kProfileThreads = 256;
+constexpr int kProfilePerThread = 16;
+
+__global__ void __launch_bounds__(kProfileThreads) k_profile(const DomView* __restrict__ views, int dom, int axis,
+                                                             uint32_t* __restrict__ counts) {
+  __shared__ uint32_t h[kProfileLds];
+  const DomView& V = views[dom];
+  const int nl = V.n[axis];
+  const bool lds = nl <= kProfileLds;
+  if (lds)
+    for (int i = threadIdx.x; i < nl; i += kProfileThreads) h[i] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kProfileThreads * kProfilePerThread;
+  for (int k = 0; k < kProfilePerThread; ++k) {
+    const int64_t w = base + (int64_t)k * kProfileThreads + threadIdx.x;
+    if (w >= V.nw) break;
+    const uint32_t c = (uint32_t)gp(V.wcell)[w];
+    const uint32_t q1 = fdiv(c, V.dx);
+    uint32_t layer;
+    if (axis == 0) layer = c - q1 * (uint32_t)V.n[0];
+    else if (axis == 1) layer = q1 - fdiv(q1, V.dy) * (uint32_t)V.n[1];
+    else layer = fdiv(q1, V.dy);
+    if (lds) __hip_atomic_fetch_add(&h[layer], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else __hip_atomic_fetch_add(gp(counts) + layer, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (lds)
+    for (int i = threadIdx.x; i < nl; i += kProfileThreads)
+      if (h[i]) __hip_atomic_fetch_add(gp(counts) + i, h[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------- moments
 // Deterministic FP64 reductions: chunk k covers elements [k*4096, (k+1)*4096);
 // thread j of the 256-thread block adds elements j, j+256, ... in order, the

@@ -101,6 +101,7 @@ struct rwmi_domain {
   std::vector<TimedWindow> evrec;
   // lazily allocated readback scratch
   uint32_t* occ = nullptr;
+  uint32_t* prof = nullptr;  // walkers per layer (the longest axis)
   double* mom_part = nullptr;
   size_t mom_part_n = 0;
   double* mom_out = nullptr;
@@ -873,6 +874,22 @@ static void fill_moments(const rwmi_domain* d, const double h[32], rwmi_moments*
   out->near_surface = u64[rwmi::kNearSurface];
 }
 
+rwmi_status rwmi_read_profile(rwmi_domain* d, int32_t axis, uint64_t* counts) {
+  if (!d || !counts) return fail(d, RWMI_EINVAL, "null argument");
+  if (axis < 0 || axis > 2) return fail(d, RWMI_EINVAL, "axis %d out of range", axis);
+  HIPCHK(d, hipSetDevice(d->device));
+  rwmi_status st;
+  const int nmax = std::max(d->hv.n[0], std::max(d->hv.n[1], d->hv.n[2]));
+  if (!d->prof && (st = alloc_into(d, d->prof, 4 * (size_t)nmax)) != RWMI_OK) return st;
+  const int nl = d->hv.n[axis];
+  std::vector<uint32_t> h(nl);
+  HIPCHK(d, rwmi::launch_profile(d->dv, 0, axis, nl, d->hv.nw, d->prof, d->stream));
+  HIPCHK(d, hipMemcpyAsync(h.data(), d->prof, 4 * (size_t)nl, hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  for (int i = 0; i < nl; ++i) counts[i] = h[i];
+  return RWMI_OK;
+}
+
 rwmi_status rwmi_read_moments(rwmi_domain* d, rwmi_moments* out) {
   if (!d || !out) return fail(d, RWMI_EINVAL, "null argument");
   HIPCHK(d, hipSetDevice(d->device));
@@ -1086,6 +1103,104 @@ rwmi_status rwmi_dispersion_from_moments(const rwmi_moments* ser, uint32_t n, ui
   out->phi = nsolid ? (solid / (double)nsolid) / (double)n_nodes : 0.0;
   return rwmi_dispersion_fit(t.data(), s2.data(), n, i0, two_r, out->u_slip, out->phi, &out->K, &out->D_alpha,
                              &out->offset);
+}
+
+// Least-squares Gaussian through (x_k, y_k) (the concentration-profile fit
+// of Sec. 4): Levenberg-Marquardt on (A, mu, s2), started from the weighted
+// moments of the profile.
+static double gauss_sse(const double* x, const double* y, uint32_t n, const double p[3]) {
+  double s = 0.0;
+  for (uint32_t k = 0; k < n; ++k) {
+    const double d = x[k] - p[1];
+    const double r = y[k] - p[0] * std::exp(-0.5 * d * d / p[2]);
+    s += r * r;
+  }
+  return s;
+}
+
+// Solve the 3x3 system A z = b by Gaussian elimination with partial pivoting.
+static bool solve3(double A[3][3], double b[3], double z[3]) {
+  int idx[3] = {0, 1, 2};
+  for (int c = 0; c < 3; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 3; ++r)
+      if (std::fabs(A[idx[r]][c]) > std::fabs(A[idx[piv]][c])) piv = r;
+    std::swap(idx[c], idx[piv]);
+    const double a = A[idx[c]][c];
+    if (a == 0.0 || !std::isfinite(a)) return false;
+    for (int r = c + 1; r < 3; ++r) {
+      const double f = A[idx[r]][c] / a;
+      for (int k = c; k < 3; ++k) A[idx[r]][k] -= f * A[idx[c]][k];
+      b[idx[r]] -= f * b[idx[c]];
+    }
+  }
+  for (int c = 2; c >= 0; --c) {
+    double v = b[idx[c]];
+    for (int k = c + 1; k < 3; ++k) v -= A[idx[c]][k] * z[k];
+    z[c] = v / A[idx[c]][c];
+  }
+  return true;
+}
+
+rwmi_status rwmi_gaussian_fit(const double* x, const double* y, uint32_t n, double* amp, double* mean, double* var) {
+  if (!x || !y || !amp || !mean || !var) return fail(nullptr, RWMI_EINVAL, "null argument");
+  if (n < 3) return fail(nullptr, RWMI_EINVAL, "a Gaussian fit needs at least three points");
+  double w = 0.0, m1 = 0.0, top = 0.0;
+  uint32_t npos = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    if (y[k] > 0.0) {
+      w += y[k];
+      m1 += y[k] * x[k];
+      ++npos;
+    }
+    top = std::max(top, y[k]);
+  }
+  if (npos < 3) return fail(nullptr, RWMI_EINVAL, "a Gaussian fit needs at least three positive values");
+  double p[3] = {top, m1 / w, 0.0};
+  for (uint32_t k = 0; k < n; ++k)
+    if (y[k] > 0.0) p[2] += y[k] * (x[k] - p[1]) * (x[k] - p[1]);
+  p[2] = p[2] > 0.0 ? p[2] / w : 1.0;
+  double sse = gauss_sse(x, y, n, p), lam = 1e-3;
+  for (int it = 0; it < 500; ++it) {
+    double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, g[3] = {0, 0, 0};
+    for (uint32_t k = 0; k < n; ++k) {
+      const double d = x[k] - p[1];
+      const double e = std::exp(-0.5 * d * d / p[2]);
+      const double J[3] = {e, p[0] * e * d / p[2], 0.5 * p[0] * e * d * d / (p[2] * p[2])};
+      const double r = y[k] - p[0] * e;
+      for (int a = 0; a < 3; ++a) {
+        g[a] += J[a] * r;
+        for (int b = 0; b < 3; ++b) H[a][b] += J[a] * J[b];
+      }
+    }
+    bool improved = false;
+    double q[3] = {0, 0, 0}, sq = sse;
+    for (int tries = 0; tries < 40 && !improved; ++tries) {
+      double A[3][3], bb[3] = {g[0], g[1], g[2]}, z[3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) A[a][b] = H[a][b] + (a == b ? lam * H[a][a] : 0.0);
+      if (!solve3(A, bb, z)) {
+        lam *= 10.0;
+        continue;
+      }
+      for (int a = 0; a < 3; ++a) q[a] = p[a] + z[a];
+      if (q[2] > 0.0 && (sq = gauss_sse(x, y, n, q)) <= sse) improved = true;
+      else lam *= 10.0;
+    }
+    if (!improved) break;
+    double change = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      change = std::max(change, std::fabs(q[a] - p[a]) / std::max(std::fabs(q[a]), 1e-300));
+      p[a] = q[a];
+    }
+    sse = sq;
+    lam = std::max(lam * 0.1, 1e-12);
+    if (change < 1e-14) break;
+  }
+  *amp = p[0];
+  *mean = p[1];
+  *var = p[2];
+  return RWMI_OK;
 }
 
 // ---------------------------------------------------------------- batch

@@ -90,6 +90,16 @@ hipError_t launch_occupancy(const DomView* v, int dom, uint32_t* occ, int64_t N,
   return hipGetLastError();
 }
 
+hipError_t launch_profile(const DomView* v, int dom, int axis, int n_layers, int64_t nw, uint32_t* counts,
+                          hipStream_t s) {
+  k_fill_u32<<<(unsigned)((n_layers + 255) / 256), 256, 0, s>>>(counts, n_layers, 0u);
+  if (nw > 0) {
+    const int64_t per = (int64_t)kProfileThreads * kProfilePerThread;
+    k_profile<<<(unsigned)((nw + per - 1) / per), kProfileThreads, 0, s>>>(v, dom, axis, counts);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_t nw, const double* ref, double* pw,
                           double* pn, double* out, hipStream_t s) {
   const int64_t nbw = (nw + kRedChunk - 1) / kRedChunk;

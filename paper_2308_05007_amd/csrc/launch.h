@@ -33,6 +33,9 @@ hipError_t launch_seed(int prec, const DomView* v, int dom, int kind, const doub
 hipError_t launch_seed_scatter(int prec, const DomView* v, int dom, int64_t n, const int32_t* cell, const void* off,
                                const uint8_t* flag, const int32_t* pos, int64_t m, hipStream_t s);
 hipError_t launch_occupancy(const DomView* v, int dom, uint32_t* occ, int64_t N, int64_t nw, hipStream_t s);
+// walkers per layer along `axis` (n_layers = n[axis] counts, cleared first)
+hipError_t launch_profile(const DomView* v, int dom, int axis, int n_layers, int64_t nw, uint32_t* counts,
+                          hipStream_t s);
 // partial buffers: walkers ceil(nw/4096)*6, nodes ceil(N/4096)*12 doubles
 hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_t nw, const double* ref,
                           double* pw, double* pn, double* out, hipStream_t s);

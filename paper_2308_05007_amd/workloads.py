@@ -276,6 +276,52 @@ def serving_trace(rate=20.0, duration=600.0, seed=5, **kw):
     return out
 
 
+def ensemble_base_shapes(seed=6):
+    """Base shapes of the shape sweep of Sec. 4, synthetic stand-ins for its
+    sphere and imaged particles A-D (whose geometry is not available): a
+    one-point sphere, then metaballs of growing irregularity -- two points
+    (slightly elongated), four points along a line (elongated), six points
+    in a plane (flattened), ten random points (irregular).  Offsets and
+    weights before scaling to a common volume (config seed 6)."""
+    rng = np.random.default_rng(seed)
+    out = {"sphere": (np.zeros((1, 3)), np.array([1.0]))}
+    out["A"] = (np.array([[-0.35, 0, 0], [0.35, 0, 0]]), np.array([0.5, 0.5]))
+    out["B"] = (np.array([[x, 0, 0] for x in (-0.9, -0.3, 0.3, 0.9)]), np.array([0.22, 0.3, 0.3, 0.22]))
+    ang = np.arange(6) * (2 * math.pi / 6) + rng.uniform(0, 0.3, 6)
+    out["C"] = (np.stack([0.75 * np.cos(ang), 0.75 * np.sin(ang), rng.uniform(-0.05, 0.05, 6)], -1),
+                rng.uniform(0.12, 0.2, 6))
+    b, k = metaball_shape(rng, 10, 0.8, (0.06, 0.16), aspect=1.6, rotate=True)
+    out["D"] = (b, k)
+    return out
+
+
+def config_ensemble_member(name, b, k, realisation, shape_index=0, R=5.0, n_particles=50, n_walkers=2_000_000,
+                           steps=5000, D=0.002, precision="fp32"):
+    """One realisation of the oscillator case of Sec. 4 for one particle
+    shape: a periodic box of 24R x 24R x 36R lattice units, n_particles copies
+    of the shape (b, k: already at its final size), each randomly rotated and
+    placed without overlap, all driven by the same horizontal oscillation
+    (amplitude 4, period 5000, one phase: Eq. 37 read as a displacement);
+    the solute band 24R x 24R x 1 at mid-height with n_walkers walkers; tau
+    0.8, diffusivity D.  Realisation r differs in placement, orientation and
+    Philox seed (config seed 1000 shape_index + r)."""
+    sd = 1000 * shape_index + realisation
+    rng = np.random.default_rng(7000 + sd)
+    dims = (int(round(24 * R)), int(round(24 * R)), int(round(36 * R)))
+    shapes = [(np.ascontiguousarray(np.asarray(b, float) @ _rotation(rng).T), np.asarray(k, float))
+              for _ in range(n_particles)]
+    centres = place_particles(rng, dims, shapes, 4.0, (False, False, False))
+    parts = [dict(b=bb, k=kk, centre=c, motion="sinusoid", amp=np.array([4.0, 0, 0]), period=5000.0, phase=0.0)
+             for (bb, kk), c in zip(shapes, centres)]
+    h = dims[2] / 2
+    return dict(name="ensemble_%s_%d" % (name, realisation),
+                domain=_domain(dims, ("periodic",) * 3, 0.8, (0, 0, 0), D, seed=100 + sd, precision=precision),
+                particles=parts,
+                walkers=dict(kind="band", n=int(n_walkers), band=(2, h - 0.5, h + 0.5),
+                             ref=(dims[0] / 2, dims[1] / 2, h)),
+                steps=int(steps))
+
+
 def config_tiny(n=(6, 5, 7), bc=("periodic", "wall", "periodic"), n_particles=1, n_walkers=64, seed=7,
                 motion="sinusoid", D=0.02, tau=0.8, F=(1e-5, 0, 0), precision="fp64", steps=5, amp=1.5,
                 period=40.0, spread=1.0, walker_kind="uniform", wall_u=None, u0=(0, 0, 0)):

@@ -89,6 +89,10 @@ def lib():
         L.orc_profile.argtypes = [P, C.c_int, u64p]
         L.orc_gaussian_fit.restype = C.c_int
         L.orc_gaussian_fit.argtypes = [dp, dp, C.c_int, dp]
+        L.orc_set_dem.restype = C.c_int
+        L.orc_set_dem.argtypes = [P, dp]
+        L.orc_dem_state.argtypes = [P, C.c_int, dp]
+        L.orc_dem_set_motion.argtypes = [P, C.c_int, dp, dp]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
         L.orc_dispersion_fit.restype = C.c_int
@@ -105,8 +109,29 @@ def _d(x, n=None):
     return a
 
 
+def _raise(msg):
+    raise ValueError(msg)
+
+
+DEM_KEYS = ("rho_p", "g", "drive_amp", "drive_period", "drive_dir", "kn", "kt", "eta_n", "eta_t", "mu", "Rs",
+            "nsub", "coupling")
+DEM_DEFAULTS = {"g": (0.0, 0.0, 0.0), "drive_amp": 0.0, "drive_period": 5000.0, "drive_dir": (1.0, 0.0, 0.0),
+                "kt": 0.0, "eta_n": 0.0, "eta_t": 0.0, "mu": 0.0, "nsub": 100, "coupling": 1}
+
+
+def dem_params(dem):
+    """The 17 doubles of the coupling parameters, in the C layout."""
+    v = dict(DEM_DEFAULTS, **dem)
+    out = []
+    for k in DEM_KEYS:
+        x = v[k]
+        out.extend(np.ravel(x).astype(float).tolist())
+    assert len(out) == 17
+    return _d(out, 17)
+
+
 BC_PERIODIC, BC_WALL = 0, 1
-MOTION = {"static": 0, "sinusoid": 1, "const_vel": 2}
+MOTION = {"static": 0, "sinusoid": 1, "const_vel": 2, "coupled": 3}
 SEED_KIND = {"uniform": 0, "gaussian": 1, "band": 2, "explicit": 3}
 COUNTERS = ("type2", "type4", "bisect_fail", "refill_fallback", "returned_to_origin", "wall_reflect")
 
@@ -152,6 +177,21 @@ class Oracle:
             raise ValueError("oracle: too many particles or empty particle")
         self.nparticles += 1
         return r
+
+    def set_dem(self, dem):
+        """Two-way coupling of the particles added with motion "coupled"
+        (Eq. 4-11); call after adding the particles, before seeding."""
+        self.L.orc_set_dem(self.h, dem_params(dem)) == 0 or _raise("oracle: bad coupling parameters")
+
+    def dem_state(self, p):
+        o = np.zeros(32)
+        self.L.orc_dem_state(self.h, int(p), o)
+        return {"c": o[0:3].copy(), "v": o[3:6].copy(), "q": o[6:10].copy(), "L": o[10:13].copy(),
+                "w": o[13:16].copy(), "Fh": o[16:19].copy(), "Th": o[19:22].copy(), "mass": float(o[22]),
+                "I": o[23:32].reshape(3, 3).copy()}
+
+    def dem_set_motion(self, p, v, L):
+        self.L.orc_dem_set_motion(self.h, int(p), _d(v, 3), _d(L, 3))
 
     def seed(self, s, n):
         kind = SEED_KIND[s["kind"]]
@@ -382,4 +422,6 @@ def build_domain(cfg):
     o = Oracle(cfg["domain"])
     for p in cfg.get("particles", []):
         o.add_particle(p)
+    if cfg.get("dem"):
+        o.set_dem(cfg["dem"])
     return o

@@ -260,10 +260,19 @@ typedef struct {
   double* b; /* 3*nc offsets of the control points from the centre (world frame) */
   double* k; /* nc positive weights */
   double c0[3];
-  int motion; /* 0 static, 1 sinusoid, 2 constant velocity */
+  int motion; /* 0 static, 1 sinusoid, 2 constant velocity, 3 coupled (Eq. 4) */
   double amp[3], period, phase, vel[3];
   double rb;    /* bounding radius: M <= 1 beyond it */
   double cutsq; /* (rb + 2)^2: support of the solid fraction */
+  /* two-way coupled particles (motion 3): offsets b are relative to the
+   * centre of mass in the body frame; wb[0] holds them rotated to the
+   * current orientation, wb[1] a copy that the fluid update reads while
+   * the particle update rotates wb[0] */
+  double* wb[2];
+  double mass, Ib[3][3], Ibinv[3][3], cin; /* cin: level of the inner metaball */
+  double c[3], v[3], q[4], L[3], w[3];     /* state at the domain's time */
+  double Fh[3], Th[3];                      /* hydrodynamic force and torque of the last fluid update */
+  int64_t acc[6];                           /* their fixed-point sums */
 } OPart;
 
 typedef struct {
@@ -287,7 +296,16 @@ typedef struct {
   uint64_t cnt[ORC_NCNT];
   int max_bisect;
   int seeded;
+  /* two-way coupling of particles with motion 3 (Sec. 2.2, Eq. 4-11) */
+  int ndem;
+  double rho_p, g[3], drive_amp, drive_period, drive_dir[3], kn, kt, eta_n, eta_t, mu, Rs;
+  int nsub, coupling;
+  double xi[ORC_MAXP][ORC_MAXP][3]; /* tangential springs of particle pairs (i < j) */
+  double xiw[ORC_MAXP][6][3];       /* and of particle-wall contacts */
 } orc_domain;
+
+static void dem_accumulate(orc_domain* d, const void* Pt, const int nd[3], const double* ep, double es,
+                           const double fx[3]);
 
 enum { C_TYPE2 = 0, C_TYPE4, C_BISECT_FAIL, C_REFILL_FALLBACK, C_RETURNED, C_WALL_REFLECT };
 
@@ -351,7 +369,7 @@ void orc_destroy(orc_domain* d) {
   if (!d) return;
   free(d->f); free(d->fs); free(d->rho); free(d->u); free(d->eps); free(d->us);
   free(d->wall); free(d->wallu);
-  for (int p = 0; p < d->np; p++) { free(d->P[p].b); free(d->P[p].k); }
+  for (int p = 0; p < d->np; p++) { free(d->P[p].b); free(d->P[p].k); free(d->P[p].wb[0]); free(d->P[p].wb[1]); }
   free(d->cell); free(d->img); free(d->off);
   free(d);
 }
@@ -415,11 +433,35 @@ static void pose(const OPart* p, int64_t t, double c[3], double v[3]) {
   }
 }
 
-typedef struct { double c[ORC_MAXP][3], v[ORC_MAXP][3]; } Poses;
+/* Poses of every particle at one time: centre, velocity, angular velocity
+ * and the control-point offsets in the world frame. */
+typedef struct {
+  double c[ORC_MAXP][3], v[ORC_MAXP][3], w[ORC_MAXP][3];
+  const double* b[ORC_MAXP];
+} Poses;
 
-static void all_poses(const orc_domain* d, int64_t t, Poses* P) {
-  for (int p = 0; p < d->np; p++) pose(&d->P[p], t, P->c[p], P->v[p]);
+/* Prescribed particles: the pose at t; coupled particles (motion 3): the
+ * current state (or the next one with `next`, once the step's particle
+ * update has run). */
+static void all_poses_which(const orc_domain* d, int64_t t, int next, Poses* P) {
+  for (int p = 0; p < d->np; p++) {
+    const OPart* q = &d->P[p];
+    if (q->motion == 3) {
+      for (int a = 0; a < 3; a++) {
+        P->c[p][a] = q->c[a];
+        P->v[p][a] = q->v[a];
+        P->w[p][a] = q->w[a];
+      }
+      P->b[p] = q->wb[next];
+    } else {
+      pose(q, t, P->c[p], P->v[p]);
+      for (int a = 0; a < 3; a++) P->w[p][a] = 0.0;
+      P->b[p] = q->b;
+    }
+  }
 }
+
+static void all_poses(const orc_domain* d, int64_t t, Poses* P) { all_poses_which(d, t, 0, P); }
 
 /* Displacement from a particle centre to the point (cell + x) along axis a,
  * minimum image on periodic axes. */
@@ -432,28 +474,32 @@ static double rel(const orc_domain* d, int a, int cell_a, double cp, double x) {
   return r;
 }
 
-/* Eq. 3: M = sum_i k_i / |x - x_i|^2, in control-point order. */
-static double mb_M(const OPart* p, const double dl[3]) {
+/* Eq. 3: M = sum_i k_i / |x - x_i|^2, in control-point order (b: the
+ * control points' offsets from the centre in the world frame). */
+static double mb_Mb(const double* b, const double* k, int nc, const double dl[3]) {
   double M = 0.0;
-  for (int i = 0; i < p->nc; i++) {
-    double rx = dl[0] - p->b[3 * i], ry = dl[1] - p->b[3 * i + 1], rz = dl[2] - p->b[3 * i + 2];
+  for (int i = 0; i < nc; i++) {
+    double rx = dl[0] - b[3 * i], ry = dl[1] - b[3 * i + 1], rz = dl[2] - b[3 * i + 2];
     double r2 = rx * rx + ry * ry + rz * rz;
     if (r2 == 0.0) return INFINITY;
-    M = M + p->k[i] / r2;
+    M = M + k[i] / r2;
   }
   return M;
 }
 
 /* Eq. 17: grad M = sum_i -2 k_i (x - x_i) / |x - x_i|^4. */
-static void mb_grad(const OPart* p, const double dl[3], double g[3]) {
+static void mb_gradb(const double* b, const double* k, int nc, const double dl[3], double g[3]) {
   g[0] = g[1] = g[2] = 0.0;
-  for (int i = 0; i < p->nc; i++) {
-    double r[3] = {dl[0] - p->b[3 * i], dl[1] - p->b[3 * i + 1], dl[2] - p->b[3 * i + 2]};
+  for (int i = 0; i < nc; i++) {
+    double r[3] = {dl[0] - b[3 * i], dl[1] - b[3 * i + 1], dl[2] - b[3 * i + 2]};
     double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    double q = (-2.0 * p->k[i]) / (r2 * r2);
+    double q = (-2.0 * k[i]) / (r2 * r2);
     for (int a = 0; a < 3; a++) g[a] = g[a] + q * r[a];
   }
 }
+
+static double mb_M(const OPart* p, const double dl[3]) { return mb_Mb(p->b, p->k, p->nc, dl); }
+static void mb_grad(const OPart* p, const double dl[3], double g[3]) { mb_gradb(p->b, p->k, p->nc, dl, g); }
 
 static void delta_to(const orc_domain* d, const Poses* P, int p, const int cell[3],
                      const double x[3], double dl[3]) {
@@ -463,7 +509,11 @@ static void delta_to(const orc_domain* d, const Poses* P, int p, const int cell[
 static double M_at(const orc_domain* d, const Poses* P, int p, const int cell[3], const double x[3]) {
   double dl[3];
   delta_to(d, P, p, cell, x, dl);
-  return mb_M(&d->P[p], dl);
+  return mb_Mb(P->b[p], d->P[p].k, d->P[p].nc, dl);
+}
+
+static void grad_at(const orc_domain* d, const Poses* P, int p, const double dl[3], double g[3]) {
+  mb_gradb(P->b[p], d->P[p].k, d->P[p].nc, dl, g);
 }
 
 /* Inside a particle <=> its own M >= 1 (each particle has its own function);
@@ -487,10 +537,10 @@ static double eps_one(const orc_domain* d, const Poses* P, int p, const int nd[3
   for (int a = 0; a < 3; a++) dl[a] = rel(d, a, nd[a], P->c[p][a], 0.5);
   double r2c = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
   if (r2c > q->cutsq) return 0.0;
-  double M = mb_M(q, dl);
+  double M = mb_Mb(P->b[p], q->k, q->nc, dl);
   if (M == INFINITY) return 1.0;
   double g[3];
-  mb_grad(q, dl, g);
+  mb_gradb(P->b[p], q->k, q->nc, dl, g);
   double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
   double e;
   if (gn == 0.0) {
@@ -511,8 +561,20 @@ static double eps_one(const orc_domain* d, const Poses* P, int p, const int nd[3
  * Om_i = [f_opp - feq_opp(rho,u)] - [f_i - feq_i(rho,us)];
  * S_i = w_i [3 (e_i - u).F + 9 (e_i.u)(e_i.F)];
  * f*_i = f_i - (1-B)/tau (f_i - feq_i(rho,u)) + B Om_i + (1-B)(1 - 1/(2 tau)) S_i. */
+static void collide_node_x(const orc_domain* d, const double f[19], double eps, const double us[3],
+                           double out[19], double* rho_out, double u_out[3], double fx[3]);
 static void collide_node(const orc_domain* d, const double f[19], double eps, const double us[3],
                          double out[19], double* rho_out, double u_out[3]) {
+  double fx[3];
+  collide_node_x(d, f, eps, us, out, rho_out, u_out, fx);
+}
+
+/* The same collision, also returning the momentum the solid term takes from
+ * the fluid: fx = -sum_i B Om_i e_i (index order), the node's share of the
+ * hydrodynamic force on the particles (momentum exchange of the partially
+ * saturated cells). */
+static void collide_node_x(const orc_domain* d, const double f[19], double eps, const double us[3],
+                           double out[19], double* rho_out, double u_out[3], double fx[3]) {
   double rho = 0.0;
   for (int i = 0; i < 19; i++) rho = rho + f[i];
   double j[3] = {0.0, 0.0, 0.0};
@@ -533,6 +595,7 @@ static void collide_node(const orc_domain* d, const double f[19], double eps, co
     fe[i] = feq(i, rho, u);
     fes[i] = feq(i, rho, us);
   }
+  double fxa[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < 19; i++) {
     int o = opp(i);
     double Om = (f[o] - fe[o]) - (f[i] - fes[i]);
@@ -541,8 +604,14 @@ static void collide_node(const orc_domain* d, const double f[19], double eps, co
     double emF = 0.0;
     for (int a = 0; a < 3; a++) emF = emF + ((double)EV[i][a] - u[a]) * d->F[a];
     double S = WT[i] * (3.0 * emF + (9.0 * eu) * eF);
-    out[i] = ((f[i] - A * (f[i] - fe[i])) + B * Om) + Cf * S;
+    double bo = B * Om;
+    out[i] = ((f[i] - A * (f[i] - fe[i])) + bo) + Cf * S;
+    for (int a = 0; a < 3; a++) {
+      if (EV[i][a] == 1) fxa[a] = fxa[a] - bo;
+      else if (EV[i][a] == -1) fxa[a] = fxa[a] + bo;
+    }
   }
+  for (int a = 0; a < 3; a++) fx[a] = fxa[a];
   *rho_out = rho;
   for (int a = 0; a < 3; a++) u_out[a] = u[a];
 }
@@ -556,18 +625,30 @@ static void fluid_step(orc_domain* d, const Poses* Pt) {
     int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
     /* solid fraction and solid velocity: eps = min(1, sum eps_p),
      * us = sum eps_p v_p / sum eps_p (particle order) */
-    double es = 0.0, un[3] = {0.0, 0.0, 0.0};
+    double es = 0.0, un[3] = {0.0, 0.0, 0.0}, ep[ORC_MAXP];
     for (int p = 0; p < d->np; p++) {
       double e = eps_one(d, Pt, p, nd);
+      ep[p] = e;
       es = es + e;
-      for (int a = 0; a < 3; a++) un[a] = un[a] + e * Pt->v[p][a];
+      double up[3] = {Pt->v[p][0], Pt->v[p][1], Pt->v[p][2]};
+      if (d->P[p].motion == 3 && e > 0.0) {
+        /* rigid surface velocity v + w x (x - x_p) (Sec. 2.4.3) */
+        double dl[3];
+        for (int a = 0; a < 3; a++) dl[a] = rel(d, a, nd[a], Pt->c[p][a], 0.5);
+        const double* w = Pt->w[p];
+        up[0] = up[0] + (w[1] * dl[2] - w[2] * dl[1]);
+        up[1] = up[1] + (w[2] * dl[0] - w[0] * dl[2]);
+        up[2] = up[2] + (w[0] * dl[1] - w[1] * dl[0]);
+      }
+      for (int a = 0; a < 3; a++) un[a] = un[a] + e * up[a];
     }
     double eps = es < 1.0 ? es : 1.0;
     double us[3];
     for (int a = 0; a < 3; a++) us[a] = es > 0.0 ? un[a] / es : 0.0;
-    double f[19], out[19], rho, u[3];
+    double f[19], out[19], rho, u[3], fx[3];
     for (int i = 0; i < 19; i++) f[i] = d->f[i * N + id];
-    collide_node(d, f, eps, us, out, &rho, u);
+    collide_node_x(d, f, eps, us, out, &rho, u, fx);
+    if (d->ndem > 0 && es > 0.0) dem_accumulate(d, Pt, nd, ep, es, fx);
     for (int i = 0; i < 19; i++) d->fs[i * N + id] = out[i];
     d->rho[id] = rho;
     d->eps[id] = eps;
@@ -692,7 +773,7 @@ static void walker_step(const orc_domain* d, const Poses* Pn, int64_t w, int cel
         double xi[3], dv[3], g[3];
         for (int a = 0; a < 3; a++) xi[a] = o[a] + s * dl[a];
         delta_to(d, Pn, jb, cell, xi, dv);
-        mb_grad(&d->P[jb], dv, g);
+        grad_at(d, Pn, jb, dv, g);
         double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
         if (gn > 0.0) {
           double nv[3], ti[3];
@@ -719,7 +800,7 @@ static void walker_step(const orc_domain* d, const Poses* Pn, int64_t w, int cel
       cn->c[C_TYPE2]++;
       double dv[3], g[3];
       delta_to(d, Pn, jb, cell, xf, dv);
-      mb_grad(&d->P[jb], dv, g);
+      grad_at(d, Pn, jb, dv, g);
       double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
       int fallback = 1;
       if (gn > 0.0) {
@@ -855,13 +936,534 @@ static void walkers_step(orc_domain* d, const Poses* Pn) {
   for (int c = 0; c < ORC_NCNT; c++) d->cnt[c] += tot[c];
 }
 
-/* One coupled step t -> t+1: fluid at P(t), walkers with u(t) against P(t+1). */
+/* ------------------------------------------------- two-way coupling */
+/* Particles with motion 3 move by the Newton-Euler equations (Eq. 4) under
+ * gravity, the oscillator's drive (Eq. 37 as a horizontal acceleration
+ * a cos(2 pi t / T)), the hydrodynamic force and torque of the fluid update
+ * (the momentum the solid term of the partially saturated cells takes from
+ * the fluid, summed over the particle's nodes) and contacts: sphero-metaball
+ * particles (an inner metaball M >= cin dilated by a sphere of radius Rs),
+ * their closest points by Newton-Raphson (Eq. 6-9, Eq. 10-11 for walls), a
+ * linear spring-dashpot normal force and a tangential spring capped by
+ * Coulomb friction (Eq. 5).  nsub substeps per fluid step, symplectic Euler
+ * for positions and angular momentum, the orientation a unit quaternion. */
+
+#define ORC_FIX 281474976710656.0 /* 2^48: fixed-point scale of the force sums */
+
+static void quat_R(const double q[4], double R[3][3]) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0][0] = 1.0 - 2.0 * (y * y + z * z); R[0][1] = 2.0 * (x * y - w * z);       R[0][2] = 2.0 * (x * z + w * y);
+  R[1][0] = 2.0 * (x * y + w * z);       R[1][1] = 1.0 - 2.0 * (x * x + z * z); R[1][2] = 2.0 * (y * z - w * x);
+  R[2][0] = 2.0 * (x * z - w * y);       R[2][1] = 2.0 * (y * z + w * x);       R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+static void rotate_offsets(const OPart* p, const double q[4], double* out) {
+  double R[3][3];
+  quat_R(q, R);
+  for (int i = 0; i < p->nc; i++)
+    for (int a = 0; a < 3; a++)
+      out[3 * i + a] = (R[a][0] * p->b[3 * i] + R[a][1] * p->b[3 * i + 1]) + R[a][2] * p->b[3 * i + 2];
+}
+
+static int inv3(const double A[3][3], double X[3][3]) {
+  double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  double det = (A[0][0] * c00 + A[0][1] * c01) + A[0][2] * c02;
+  if (det == 0.0 || !isfinite(det)) return -1;
+  X[0][0] = c00 / det;
+  X[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+  X[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+  X[1][0] = c01 / det;
+  X[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+  X[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+  X[2][0] = c02 / det;
+  X[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+  X[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+  return 0;
+}
+
+/* Solid fraction of a cell of size h centred at offset x (the first-order
+ * distance estimate of the solid fraction, on the cell's scale). */
+static double cell_fraction(const OPart* p, const double x[3], double h) {
+  double M = mb_M(p, x);
+  if (M == INFINITY) return 1.0;
+  double g[3];
+  mb_grad(p, x, g);
+  double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  double e;
+  if (gn == 0.0) e = M >= 1.0 ? 1.0 : 0.0;
+  else e = 0.5 + (((2.0 * M) * (sqrt(M) - 1.0)) / gn) / h;
+  if (!(e > 0.0)) e = 0.0;
+  if (e > 1.0) e = 1.0;
+  return e;
+}
+
+/* Mass, centre of mass and inertia tensor of a metaball of density rho_p:
+ * cells of size h = rb/24 over the cube [-rb - h, rb + h]^3 about the reference
+ * point (one cell beyond rb), each weighted by its solid fraction, summed
+ * z, y, x in order. */
+static void mass_properties(const OPart* p, double rho_p, double* mass, double com[3], double I[3][3]) {
+  const int G = 50; /* cells of the cube [-rb - h, rb + h]^3 */
+  const double h = p->rb / 24.0;
+  double V = 0.0, S[3] = {0, 0, 0};
+  for (int iz = 0; iz < G; iz++)
+    for (int iy = 0; iy < G; iy++)
+      for (int ix = 0; ix < G; ix++) {
+        double x[3] = {((double)(ix - 25) + 0.5) * h, ((double)(iy - 25) + 0.5) * h, ((double)(iz - 25) + 0.5) * h};
+        double e = cell_fraction(p, x, h);
+        V = V + e;
+        for (int a = 0; a < 3; a++) S[a] = S[a] + e * x[a];
+      }
+  for (int a = 0; a < 3; a++) com[a] = S[a] / V;
+  double Q[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int iz = 0; iz < G; iz++)
+    for (int iy = 0; iy < G; iy++)
+      for (int ix = 0; ix < G; ix++) {
+        double x[3] = {((double)(ix - 25) + 0.5) * h, ((double)(iy - 25) + 0.5) * h, ((double)(iz - 25) + 0.5) * h};
+        double e = cell_fraction(p, x, h);
+        double r[3] = {x[0] - com[0], x[1] - com[1], x[2] - com[2]};
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) Q[a][b] = Q[a][b] + e * (r[a] * r[b]);
+      }
+  double h3 = (h * h) * h;
+  *mass = (rho_p * V) * h3;
+  double tr = (Q[0][0] + Q[1][1]) + Q[2][2];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) I[a][b] = (rho_p * h3) * ((a == b ? tr : 0.0) - Q[a][b]);
+}
+
+/* params: rho_p, g[3], drive amplitude, drive period, drive direction[3],
+ * kn, kt, eta_n, eta_t, mu, Rs, nsub, coupling.  Sets up every particle of
+ * motion 3 (centre of mass as its centre, state at rest but for its initial
+ * velocity); call after the particles are added and before seeding. */
+int orc_set_dem(orc_domain* d, const double* prm) {
+  d->rho_p = prm[0];
+  for (int a = 0; a < 3; a++) {
+    d->g[a] = prm[1 + a];
+    d->drive_dir[a] = prm[6 + a];
+  }
+  d->drive_amp = prm[4];
+  d->drive_period = prm[5];
+  d->kn = prm[9];
+  d->kt = prm[10];
+  d->eta_n = prm[11];
+  d->eta_t = prm[12];
+  d->mu = prm[13];
+  d->Rs = prm[14];
+  d->nsub = (int)prm[15];
+  d->coupling = (int)prm[16];
+  if (d->nsub < 1 || !(d->rho_p > 0.0)) return -1;
+  memset(d->xi, 0, sizeof(d->xi));
+  memset(d->xiw, 0, sizeof(d->xiw));
+  d->ndem = 0;
+  for (int pi = 0; pi < d->np; pi++) {
+    OPart* p = &d->P[pi];
+    if (p->motion != 3) continue;
+    double com[3], I[3][3];
+    mass_properties(p, d->rho_p, &p->mass, com, I);
+    for (int i = 0; i < p->nc; i++)
+      for (int a = 0; a < 3; a++) p->b[3 * i + a] = p->b[3 * i + a] - com[a];
+    double K = 0.0, bmax = 0.0;
+    for (int i = 0; i < p->nc; i++) {
+      K = K + p->k[i];
+      const double* b = p->b + 3 * i;
+      double r = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      if (r > bmax) bmax = r;
+    }
+    if (!(sqrt(K) > d->Rs)) return -1;
+    p->rb = bmax + sqrt(K);
+    p->cutsq = (p->rb + 2.0) * (p->rb + 2.0);
+    p->cin = (sqrt(K) / (sqrt(K) - d->Rs)) * (sqrt(K) / (sqrt(K) - d->Rs));
+    memcpy(p->Ib, I, sizeof(I));
+    if (inv3(I, p->Ibinv) != 0) return -1;
+    for (int a = 0; a < 3; a++) {
+      p->c[a] = p->c0[a] + com[a];
+      p->v[a] = p->vel[a];
+      p->L[a] = 0.0;
+      p->w[a] = 0.0;
+    }
+    p->q[0] = 1.0;
+    p->q[1] = p->q[2] = p->q[3] = 0.0;
+    p->wb[0] = (double*)malloc(sizeof(double) * 3 * p->nc);
+    p->wb[1] = (double*)malloc(sizeof(double) * 3 * p->nc);
+    rotate_offsets(p, p->q, p->wb[0]);
+    rotate_offsets(p, p->q, p->wb[1]);
+    memset(p->acc, 0, sizeof(p->acc));
+    d->ndem++;
+  }
+  return 0;
+}
+
+/* Node nd's share of the hydrodynamic force on each coupled particle with a
+ * solid fraction there (eps_p / sum eps of the exchange fx), and its torque
+ * about the particle's centre; summed in fixed point (2^48), so that the
+ * sums do not depend on the order of the nodes. */
+static int64_t fix48(double x) { return (int64_t)llrint(x * ORC_FIX); }
+
+static void dem_accumulate(orc_domain* d, const void* Pv, const int nd[3], const double* ep, double es,
+                           const double fx[3]) {
+  const Poses* Pt = (const Poses*)Pv;
+  for (int p = 0; p < d->np; p++) {
+    OPart* q = &d->P[p];
+    if (q->motion != 3 || !(ep[p] > 0.0)) continue;
+    double share = ep[p] / es;
+    double F[3], dl[3];
+    for (int a = 0; a < 3; a++) {
+      F[a] = share * fx[a];
+      dl[a] = rel(d, a, nd[a], Pt->c[p][a], 0.5);
+    }
+    double T[3] = {dl[1] * F[2] - dl[2] * F[1], dl[2] * F[0] - dl[0] * F[2], dl[0] * F[1] - dl[1] * F[0]};
+    int64_t v[6] = {fix48(F[0]), fix48(F[1]), fix48(F[2]), fix48(T[0]), fix48(T[1]), fix48(T[2])};
+    for (int k = 0; k < 6; k++) {
+#pragma omp atomic
+      q->acc[k] += v[k];
+    }
+  }
+}
+
+/* Hessian of M at offset dl: sum_i k_i (8 r r^T / |r|^6 - 2 I / |r|^4). */
+static void mb_hess(const double* b, const double* k, int nc, const double dl[3], double H[3][3]) {
+  for (int a = 0; a < 3; a++)
+    for (int c = 0; c < 3; c++) H[a][c] = 0.0;
+  for (int i = 0; i < nc; i++) {
+    double r[3] = {dl[0] - b[3 * i], dl[1] - b[3 * i + 1], dl[2] - b[3 * i + 2]};
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double r4 = r2 * r2;
+    double a8 = (8.0 * k[i]) / (r4 * r2), a2 = (2.0 * k[i]) / r4;
+    for (int a = 0; a < 3; a++)
+      for (int c = 0; c < 3; c++) H[a][c] = H[a][c] + (a8 * (r[a] * r[c]) - (a == c ? a2 : 0.0));
+  }
+}
+
+static void solve3x3(const double A[3][3], const double b[3], double x[3], int* ok) {
+  double X[3][3];
+  if (inv3(A, X) != 0) {
+    *ok = 0;
+    return;
+  }
+  for (int a = 0; a < 3; a++) x[a] = (X[a][0] * b[0] + X[a][1] * b[1]) + X[a][2] * b[2];
+  *ok = 1;
+}
+
+/* Eq. 8: the point of the inner body (level cin) reached from x along the
+ * gradient, q from a first-order Taylor expansion.  The expansion is taken
+ * in the field g = M^(-1/2), whose level sets are those of M and which is
+ * r / sqrt(k) for one control point, so that the point is exact for a
+ * sphere.  Returns 0 when x is inside the inner body. */
+static int inner_point(const double* b, const double* k, int nc, double cin, const double x[3], double xc[3]) {
+  double M = mb_Mb(b, k, nc, x);
+  if (!(M < cin)) return 0;
+  double gm[3];
+  mb_gradb(b, k, nc, x, gm);
+  double g = 1.0 / sqrt(M), gin = 1.0 / sqrt(cin);
+  double s = -0.5 * (g / M); /* dg/dM = -M^(-3/2) / 2 */
+  double gg[3] = {s * gm[0], s * gm[1], s * gm[2]};
+  double n2 = (gg[0] * gg[0] + gg[1] * gg[1]) + gg[2] * gg[2];
+  if (!(n2 > 0.0)) return 0;
+  double q = (gin - g) / n2;
+  for (int a = 0; a < 3; a++) xc[a] = x[a] + q * gg[a];
+  return 1;
+}
+
+/* Contact between coupled particles i and j (Eq. 6-9): the minimum x_m of
+ * M_i + M_j between them by Newton-Raphson (start: the midpoint of the
+ * centres, j's as the minimum image seen from i; 40 iterations at most,
+ * stop when the step is below 1e-12), the closest points of the inner
+ * bodies (Eq. 8, inner_point), the normal from i's point to j's and the
+ * overlap of the dilation spheres (Eq. 9).
+ * Returns 1 with (xcp offset from c_i, n, delta) when they overlap. */
+static int contact_pair(const orc_domain* d, int i, int j, const double ci[3], const double cj[3], const double* bi,
+                        const double* bj, double xcp[3], double n[3], double* delta) {
+  const OPart* P = &d->P[i];
+  const OPart* Q = &d->P[j];
+  double dc[3];
+  for (int a = 0; a < 3; a++) {
+    dc[a] = cj[a] - ci[a];
+    if (!d->bc[a]) {
+      double L = (double)d->n[a];
+      dc[a] = dc[a] - L * floor(dc[a] / L + 0.5);
+    }
+  }
+  double r2 = dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2];
+  double rr = P->rb + Q->rb;
+  if (!(r2 < rr * rr)) return 0;
+  double x[3] = {0.5 * dc[0], 0.5 * dc[1], 0.5 * dc[2]}; /* offset from c_i */
+  for (int it = 0; it < 40; it++) {
+    double xj[3] = {x[0] - dc[0], x[1] - dc[1], x[2] - dc[2]};
+    double gi[3], gj[3], Hi[3][3], Hj[3][3], H[3][3], g[3], st[3];
+    mb_gradb(bi, P->k, P->nc, x, gi);
+    mb_gradb(bj, Q->k, Q->nc, xj, gj);
+    mb_hess(bi, P->k, P->nc, x, Hi);
+    mb_hess(bj, Q->k, Q->nc, xj, Hj);
+    for (int a = 0; a < 3; a++) {
+      g[a] = gi[a] + gj[a];
+      for (int c = 0; c < 3; c++) H[a][c] = Hi[a][c] + Hj[a][c];
+    }
+    int ok;
+    solve3x3(H, g, st, &ok);
+    if (!ok || !(isfinite(st[0]) && isfinite(st[1]) && isfinite(st[2]))) return 0;
+    for (int a = 0; a < 3; a++) x[a] = x[a] - st[a];
+    double sn = sqrt(st[0] * st[0] + st[1] * st[1] + st[2] * st[2]);
+    if (sn < 1e-12) break;
+  }
+  double xj[3] = {x[0] - dc[0], x[1] - dc[1], x[2] - dc[2]};
+  double x0[3], x1[3], dd[3];
+  if (!inner_point(bi, P->k, P->nc, P->cin, x, x0)) return 0;
+  if (!inner_point(bj, Q->k, Q->nc, Q->cin, xj, x1)) return 0;
+  for (int a = 0; a < 3; a++) {
+    x1[a] = x1[a] + dc[a];
+    dd[a] = x1[a] - x0[a];
+  }
+  double dist = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+  double del = (d->Rs + d->Rs) - dist;
+  if (!(del > 0.0) || !(dist > 0.0)) return 0;
+  for (int a = 0; a < 3; a++) {
+    n[a] = dd[a] / dist;
+    xcp[a] = x0[a] + (d->Rs - 0.5 * del) * n[a];
+  }
+  *delta = del;
+  return 1;
+}
+
+/* Contact of coupled particle i with the wall plane of wall axis `ax` on
+ * side `side` (Eq. 10-11): the point of the inner metaball whose gradient is
+ * normal to the wall, by Newton-Raphson on (grad M tangential = 0,
+ * M = cin) from the inner surface point on the ray from the centre towards
+ * the wall; n points from the particle to the wall.  Returns 1 with (xcp
+ * offset from c_i, n, delta) when the dilation sphere crosses the plane. */
+static int contact_wall(const orc_domain* d, int i, const double ci[3], const double* bi, int ax, int side,
+                        double xcp[3], double n[3], double* delta) {
+  const OPart* P = &d->P[i];
+  double plane = side ? (double)(d->n[ax] - 1) : 1.0;
+  double gap = side ? plane - ci[ax] : ci[ax] - plane; /* distance from the centre to the plane */
+  if (!(gap < P->rb + d->Rs)) return 0;
+  int t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+  double dir = side ? 1.0 : -1.0;
+  double x[3] = {0.0, 0.0, 0.0};
+  /* start: bisection for M = cin on the ray from the centre towards the wall */
+  double lo = 0.0, hi = P->rb;
+  for (int it = 0; it < 60; it++) {
+    double m = 0.5 * (lo + hi);
+    double y[3] = {0.0, 0.0, 0.0};
+    y[ax] = dir * m;
+    if (mb_Mb(bi, P->k, P->nc, y) >= P->cin) lo = m;
+    else hi = m;
+  }
+  x[ax] = dir * lo;
+  for (int it = 0; it < 40; it++) {
+    double g[3], H[3][3], J[3][3], r[3], st[3];
+    mb_gradb(bi, P->k, P->nc, x, g);
+    mb_hess(bi, P->k, P->nc, x, H);
+    double M = mb_Mb(bi, P->k, P->nc, x);
+    r[0] = g[t1];
+    r[1] = g[t2];
+    r[2] = M - P->cin;
+    for (int c = 0; c < 3; c++) {
+      J[0][c] = H[t1][c];
+      J[1][c] = H[t2][c];
+      J[2][c] = g[c];
+    }
+    int ok;
+    solve3x3(J, r, st, &ok);
+    if (!ok || !(isfinite(st[0]) && isfinite(st[1]) && isfinite(st[2]))) return 0;
+    for (int a = 0; a < 3; a++) x[a] = x[a] - st[a];
+    double sn = sqrt(st[0] * st[0] + st[1] * st[1] + st[2] * st[2]);
+    if (sn < 1e-12) break;
+  }
+  double dist = side ? plane - (ci[ax] + x[ax]) : (ci[ax] + x[ax]) - plane;
+  double del = d->Rs - dist;
+  if (!(del > 0.0)) return 0;
+  for (int a = 0; a < 3; a++) n[a] = 0.0;
+  n[ax] = dir;
+  for (int a = 0; a < 3; a++) xcp[a] = x[a] + (d->Rs - 0.5 * del) * n[a];
+  *delta = del;
+  return 1;
+}
+
+static void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Spring-dashpot force (Eq. 5) on body B from body A at a contact: normal n
+ * from A to B, overlap delta, relative velocity vr = v_B - v_A at the contact
+ * point, tangential spring xi (updated).  Returns the force on B. */
+static void contact_force(const orc_domain* d, const double n[3], double delta, const double vr[3], double dt,
+                          double xi[3], double F[3]) {
+  double vn = (vr[0] * n[0] + vr[1] * n[1]) + vr[2] * n[2];
+  double Fn = d->kn * delta - d->eta_n * vn;
+  if (Fn < 0.0) Fn = 0.0;
+  double vt[3];
+  for (int a = 0; a < 3; a++) vt[a] = vr[a] - vn * n[a];
+  for (int a = 0; a < 3; a++) xi[a] = xi[a] + vt[a] * dt;
+  double xn = (xi[0] * n[0] + xi[1] * n[1]) + xi[2] * n[2];
+  for (int a = 0; a < 3; a++) xi[a] = xi[a] - xn * n[a];
+  double Ft[3];
+  for (int a = 0; a < 3; a++) Ft[a] = -(d->kt * xi[a]) - d->eta_t * vt[a];
+  double ft = sqrt((Ft[0] * Ft[0] + Ft[1] * Ft[1]) + Ft[2] * Ft[2]);
+  double cap = d->mu * Fn;
+  if (ft > cap) {
+    for (int a = 0; a < 3; a++) {
+      Ft[a] = Ft[a] * (cap / ft);
+      xi[a] = -(Ft[a] + d->eta_t * vt[a]) / d->kt;
+    }
+  }
+  for (int a = 0; a < 3; a++) F[a] = Fn * n[a] + Ft[a];
+}
+
+/* Advance every coupled particle by one fluid step (nsub substeps) from the
+ * state at t, with the hydrodynamic force of the fluid update of t. */
+static void dem_advance(orc_domain* d) {
+  const double dt = 1.0 / (double)d->nsub;
+  for (int p = 0; p < d->np; p++) {
+    OPart* q = &d->P[p];
+    if (q->motion != 3) continue;
+    for (int a = 0; a < 3; a++) {
+      q->Fh[a] = d->coupling ? (double)q->acc[a] / ORC_FIX : 0.0;
+      q->Th[a] = d->coupling ? (double)q->acc[3 + a] / ORC_FIX : 0.0;
+    }
+    memset(q->acc, 0, sizeof(q->acc));
+  }
+  for (int s = 0; s < d->nsub; s++) {
+    double tau = (double)d->t + (double)s * dt;
+    double F[ORC_MAXP][3], T[ORC_MAXP][3];
+    double ph = tau / d->drive_period;
+    ph = ph - floor(ph);
+    double sn, cs;
+    sincos2pi(ph, &sn, &cs);
+    for (int p = 0; p < d->np; p++) {
+      OPart* q = &d->P[p];
+      if (q->motion != 3) continue;
+      for (int a = 0; a < 3; a++) {
+        F[p][a] = (q->mass * d->g[a] + q->mass * ((d->drive_amp * cs) * d->drive_dir[a])) + q->Fh[a];
+        T[p][a] = q->Th[a];
+      }
+    }
+    /* particle pairs */
+    for (int i = 0; i < d->np; i++) {
+      if (d->P[i].motion != 3) continue;
+      for (int j = i + 1; j < d->np; j++) {
+        if (d->P[j].motion != 3) continue;
+        OPart *A = &d->P[i], *Bq = &d->P[j];
+        double xcp[3], n[3], del;
+        if (!contact_pair(d, i, j, A->c, Bq->c, A->wb[0], Bq->wb[0], xcp, n, &del)) {
+          memset(d->xi[i][j], 0, sizeof(d->xi[i][j]));
+          continue;
+        }
+        /* offsets of the contact point from both centres (j's via the minimum image) */
+        double dc[3], rj[3], va[3], vb[3], wa[3], wb[3], vr[3], Fc[3];
+        for (int a = 0; a < 3; a++) {
+          dc[a] = Bq->c[a] - A->c[a];
+          if (!d->bc[a]) {
+            double L = (double)d->n[a];
+            dc[a] = dc[a] - L * floor(dc[a] / L + 0.5);
+          }
+          rj[a] = xcp[a] - dc[a];
+        }
+        cross3(A->w, xcp, wa);
+        cross3(Bq->w, rj, wb);
+        for (int a = 0; a < 3; a++) {
+          va[a] = A->v[a] + wa[a];
+          vb[a] = Bq->v[a] + wb[a];
+          vr[a] = vb[a] - va[a];
+        }
+        contact_force(d, n, del, vr, dt, d->xi[i][j], Fc);
+        double ta[3], tb[3], mF[3] = {-Fc[0], -Fc[1], -Fc[2]};
+        cross3(rj, Fc, tb);
+        cross3(xcp, mF, ta);
+        for (int a = 0; a < 3; a++) {
+          F[j][a] = F[j][a] + Fc[a];
+          T[j][a] = T[j][a] + tb[a];
+          F[i][a] = F[i][a] + mF[a];
+          T[i][a] = T[i][a] + ta[a];
+        }
+      }
+    }
+    /* walls */
+    for (int i = 0; i < d->np; i++) {
+      OPart* A = &d->P[i];
+      if (A->motion != 3) continue;
+      for (int ax = 0; ax < 3; ax++) {
+        if (!d->bc[ax]) continue;
+        for (int side = 0; side < 2; side++) {
+          double xcp[3], n[3], del;
+          double* xi = d->xiw[i][2 * ax + side];
+          if (!contact_wall(d, i, A->c, A->wb[0], ax, side, xcp, n, &del)) {
+            memset(xi, 0, sizeof(double) * 3);
+            continue;
+          }
+          double wa[3], vr[3], Fc[3];
+          cross3(A->w, xcp, wa);
+          for (int a = 0; a < 3; a++) vr[a] = d->wu[ax][side][a] - (A->v[a] + wa[a]);
+          contact_force(d, n, del, vr, dt, xi, Fc);
+          double mF[3] = {-Fc[0], -Fc[1], -Fc[2]}, ta[3];
+          cross3(xcp, mF, ta);
+          for (int a = 0; a < 3; a++) {
+            F[i][a] = F[i][a] + mF[a];
+            T[i][a] = T[i][a] + ta[a];
+          }
+        }
+      }
+    }
+    /* Newton-Euler, symplectic Euler */
+    for (int p = 0; p < d->np; p++) {
+      OPart* q = &d->P[p];
+      if (q->motion != 3) continue;
+      for (int a = 0; a < 3; a++) {
+        q->v[a] = q->v[a] + (F[p][a] / q->mass) * dt;
+        q->c[a] = q->c[a] + q->v[a] * dt;
+        q->L[a] = q->L[a] + T[p][a] * dt;
+      }
+      if (!d->bc[0] || !d->bc[1] || !d->bc[2])
+        for (int a = 0; a < 3; a++)
+          if (!d->bc[a]) {
+            double L = (double)d->n[a];
+            q->c[a] = q->c[a] - L * floor(q->c[a] / L);
+          }
+      /* w = R Ib^-1 R^T L */
+      double R[3][3], y[3], z[3];
+      quat_R(q->q, R);
+      for (int a = 0; a < 3; a++) y[a] = (R[0][a] * q->L[0] + R[1][a] * q->L[1]) + R[2][a] * q->L[2];
+      for (int a = 0; a < 3; a++) z[a] = (q->Ibinv[a][0] * y[0] + q->Ibinv[a][1] * y[1]) + q->Ibinv[a][2] * y[2];
+      for (int a = 0; a < 3; a++) q->w[a] = (R[a][0] * z[0] + R[a][1] * z[1]) + R[a][2] * z[2];
+      /* q += dt/2 (0, w) q, normalised */
+      double w0 = q->q[0], w1 = q->q[1], w2 = q->q[2], w3 = q->q[3];
+      double hw[3] = {0.5 * dt * q->w[0], 0.5 * dt * q->w[1], 0.5 * dt * q->w[2]};
+      double n0 = w0 - ((hw[0] * w1 + hw[1] * w2) + hw[2] * w3);
+      double n1 = w1 + ((hw[0] * w0 + hw[1] * w3) - hw[2] * w2);
+      double n2 = w2 + ((hw[1] * w0 + hw[2] * w1) - hw[0] * w3);
+      double n3 = w3 + ((hw[2] * w0 + hw[0] * w2) - hw[1] * w1);
+      double nn = sqrt(((n0 * n0 + n1 * n1) + n2 * n2) + n3 * n3);
+      q->q[0] = n0 / nn;
+      q->q[1] = n1 / nn;
+      q->q[2] = n2 / nn;
+      q->q[3] = n3 / nn;
+      rotate_offsets(q, q->q, q->wb[0]);
+    }
+  }
+}
+
+/* One coupled step t -> t+1: fluid at P(t) (its momentum exchange gives the
+ * hydrodynamic force on the coupled particles), the coupled particles
+ * advanced to t+1, walkers with u(t) against P(t+1). */
 void orc_step(orc_domain* d, int nsteps) {
   for (int s = 0; s < nsteps; s++) {
     Poses Pt, Pn;
     all_poses(d, d->t, &Pt);
-    all_poses(d, d->t + 1, &Pn);
+    if (d->ndem > 0) {
+      /* Pt points at the offsets of the current orientation; keep a copy,
+       * since the particle update rotates them */
+      for (int p = 0; p < d->np; p++)
+        if (d->P[p].motion == 3) {
+          memcpy(d->P[p].wb[1], d->P[p].wb[0], sizeof(double) * 3 * d->P[p].nc);
+          Pt.b[p] = d->P[p].wb[1];
+        }
+    }
     fluid_step(d, &Pt);
+    if (d->ndem > 0) dem_advance(d);
+    all_poses(d, d->t + 1, &Pn);
     if (d->nw) walkers_step(d, &Pn);
     d->t++;
   }
@@ -1114,10 +1716,41 @@ void orc_particle_grad(const orc_domain* d, int p, int64_t t, const int cell[3],
   all_poses(d, t, &P);
   double dl[3];
   delta_to(d, &P, p, cell, x, dl);
-  mb_grad(&d->P[p], dl, g);
+  grad_at(d, &P, p, dl, g);
 }
 void orc_particle_pose(const orc_domain* d, int p, int64_t t, double c[3], double v[3]) {
+  if (d->P[p].motion == 3) {
+    memcpy(c, d->P[p].c, sizeof(double) * 3);
+    memcpy(v, d->P[p].v, sizeof(double) * 3);
+    return;
+  }
   pose(&d->P[p], t, c, v);
+}
+/* State of coupled particle p: c[3], v[3], q[4], L[3], w[3], Fh[3], Th[3],
+ * mass, Ib[9] (27 doubles). */
+void orc_dem_state(const orc_domain* d, int p, double* out) {
+  const OPart* q = &d->P[p];
+  memcpy(out, q->c, 24);
+  memcpy(out + 3, q->v, 24);
+  memcpy(out + 6, q->q, 32);
+  memcpy(out + 10, q->L, 24);
+  memcpy(out + 13, q->w, 24);
+  memcpy(out + 16, q->Fh, 24);
+  memcpy(out + 19, q->Th, 24);
+  out[22] = q->mass;
+  for (int a = 0; a < 3; a++)
+    for (int c = 0; c < 3; c++) out[23 + 3 * a + c] = q->Ib[a][c];
+}
+/* Overwrite a coupled particle's velocity and angular momentum (test set-up). */
+void orc_dem_set_motion(orc_domain* d, int p, const double v[3], const double L[3]) {
+  OPart* q = &d->P[p];
+  memcpy(q->v, v, 24);
+  memcpy(q->L, L, 24);
+  double R[3][3], y[3], z[3];
+  quat_R(q->q, R);
+  for (int a = 0; a < 3; a++) y[a] = (R[0][a] * q->L[0] + R[1][a] * q->L[1]) + R[2][a] * q->L[2];
+  for (int a = 0; a < 3; a++) z[a] = (q->Ibinv[a][0] * y[0] + q->Ibinv[a][1] * y[1]) + q->Ibinv[a][2] * y[2];
+  for (int a = 0; a < 3; a++) q->w[a] = (R[a][0] * z[0] + R[a][1] * z[1]) + R[a][2] * z[2];
 }
 double orc_particle_rb(const orc_domain* d, int p) { return d->P[p].rb; }
 /* Algorithm 1 on a caller-given segment; returns iterations used encoded as

@@ -66,13 +66,22 @@ typedef enum { RWMI_BC_PERIODIC = 0, RWMI_BC_WALL = 1 } rwmi_bc;
  * the walkers of all modes see the same noise up to float rounding. */
 typedef enum { RWMI_FP64 = 0, RWMI_FP32 = 1, RWMI_FP16_STORE = 2, RWMI_BF16_STORE = 3 } rwmi_precision;
 
-/* Prescribed rigid motion of a particle (fixed orientation; the oscillator of
- * Sec. 4 read as a displacement sinusoid):
+/* Motion of a particle.  Prescribed rigid motion (fixed orientation; the
+ * oscillator of Sec. 4 read as a displacement sinusoid):
  *   STATIC   c(t) = c0
  *   SINUSOID c(t) = c0 + A sin(2 pi (t / period + phase)),  phase in cycles
  *   CONST_VEL c(t) = c0 + v t
- * The surface velocity seen by the fluid is dc/dt (Sec. 2.4.3 with w = 0). */
-typedef enum { RWMI_MOTION_STATIC = 0, RWMI_MOTION_SINUSOID = 1, RWMI_MOTION_CONST_VEL = 2 } rwmi_motion;
+ * The surface velocity seen by the fluid is dc/dt (Sec. 2.4.3 with w = 0).
+ *   COUPLED  Newton-Euler motion (Sec. 2.2, Eq. 4) under gravity, the drive
+ *            of Eq. 37, the hydrodynamic force and torque and the contacts
+ *            of Eq. 5-11 (rwmi_set_coupling); surface velocity v + w x r;
+ *            the initial velocity is the descriptor's `velocity`. */
+typedef enum {
+  RWMI_MOTION_STATIC = 0,
+  RWMI_MOTION_SINUSOID = 1,
+  RWMI_MOTION_CONST_VEL = 2,
+  RWMI_MOTION_COUPLED = 3
+} rwmi_motion;
 
 /* Walker release (Sec. 3.1 point source, Sec. 4 solute band):
  *   UNIFORM  uniform over the fluid box
@@ -150,7 +159,27 @@ typedef struct {
   uint64_t wall_reflect;    /* walkers reflected at a wall */
   uint64_t near_surface;    /* walker steps that took the near-surface path (a cost
                                diagnostic: it depends on the culling, not a result) */
+  uint64_t contact_misses;  /* coupled-particle steps that moved farther than half the
+                               contact candidate margin (contacts may have been missed;
+                               0 in any run within the model's speed limits) */
 } rwmi_moments;
+
+/* Two-way coupling of the particles with motion COUPLED (Sec. 2.2, Eq. 4-11;
+ * the hydrodynamic force of the partially saturated cells).  Lattice units
+ * (fluid density rho0 = 1, one fluid step = unit time). */
+typedef struct {
+  double density;            /* particle density rho_p > 0 */
+  double gravity[3];         /* g of Eq. 4 */
+  double drive_amplitude;    /* Eq. 37: acceleration a cos(2 pi t / T) along d */
+  double drive_period;       /*   T in steps (> 0) */
+  double drive_direction[3]; /*   d (unit vector) */
+  double kn, kt;             /* Eq. 5: normal (> 0) and tangential (>= 0) stiffness */
+  double eta_n, eta_t;       /*   normal and tangential damping (>= 0) */
+  double mu;                 /*   friction coefficient (>= 0) */
+  double dilation_radius;    /* R_s of the sphero-metaball contact (Eq. 9, 11) */
+  int32_t substeps;          /* particle substeps per fluid step (>= 1) */
+  int32_t coupling;          /* 1: the fluid's force and torque act on the particles */
+} rwmi_coupling_desc;
 
 typedef struct rwmi_domain rwmi_domain;
 typedef struct rwmi_batch rwmi_batch;
@@ -174,6 +203,41 @@ void rwmi_destroy_domain(rwmi_domain* dom);
  * run; EINVAL on n_ctrl out of range, a weight <= 0, period <= 0, or more
  * than RWMI_MAX_PARTICLES particles. */
 rwmi_status rwmi_add_metaball_particle(rwmi_domain* dom, const rwmi_metaball_desc* p, int32_t* out_id);
+
+/* Set up the two-way coupling of the particles added with motion COUPLED
+ * (Sec. 2.2, Eq. 4-11); call after adding the particles and before seeding
+ * and stepping.  For each such particle: the mass, centre of mass and
+ * inertia tensor of the body M >= 1 at density rho_p (cells of size rb/24
+ * weighted by their solid fractions); the centre of mass becomes the
+ * particle's centre (the body stays where it was given), orientation the
+ * identity, angular momentum zero.  Contacts act between coupled particles
+ * and between them and the wall planes (1 and n - 1 on a wall axis); the
+ * inner body is the level set M = (sqrt K / (sqrt K - R_s))^2, K = sum k_i.
+ * Each step then runs the fluid at P(t), which sums the momentum its solid
+ * term takes from the fluid, -sum_i e_i B Om_i per node, shared among the
+ * coupled particles covering the node in proportion to their solid fractions
+ * (fixed point, 2^-48: independent of the summation order); then the
+ * particle update to t+1 in `substeps` symplectic Euler substeps with that
+ * force and torque held constant; then the walkers against P(t+1).  The
+ * domain steps with 256 threads per block, three launches per step, and
+ * cannot join a batch.  EINVAL: no coupled particle, parameters out of
+ * range, a particle with sqrt K <= R_s, more than 1024 control points in
+ * all; ESTATE: after seeding, stepping or a second call. */
+rwmi_status rwmi_set_coupling(rwmi_domain* dom, const rwmi_coupling_desc* c);
+
+/* State of coupled particle p after the last completed step, 32 doubles:
+ * centre of mass c[3], velocity v[3], orientation quaternion q[4] (w, x, y,
+ * z; body to world), angular momentum L[3], angular velocity w[3], the
+ * hydrodynamic force F_h[3] and torque T_h[3] of the last fluid step, mass,
+ * body-frame inertia tensor I[9] (row-major).  Synchronises the domain's
+ * stream.  EINVAL if p is not a coupled particle. */
+rwmi_status rwmi_read_particle_state(rwmi_domain* dom, int32_t p, double* out);
+
+/* Replace the velocity and angular momentum of coupled particle p (host
+ * arrays of 3) at the current step; the angular velocity follows as
+ * R I_b^-1 R^T L.  Synchronises the domain's stream.  EINVAL if p is not a
+ * coupled particle. */
+rwmi_status rwmi_set_particle_motion(rwmi_domain* dom, int32_t p, const double v[3], const double L[3]);
 
 /* Seed n walkers (ids 0..n-1) at step 0, on the device: the solute particles
  * of the random-walk method (Sec. 2.4, Eq. 2), released as in the paper's

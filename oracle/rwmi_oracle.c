@@ -1307,7 +1307,8 @@ static void contact_force(const orc_domain* d, const double n[3], double delta, 
   if (ft > cap) {
     for (int a = 0; a < 3; a++) {
       Ft[a] = Ft[a] * (cap / ft);
-      xi[a] = -(Ft[a] + d->eta_t * vt[a]) / d->kt;
+      /* the spring stretched to what the capped force needs (none without a spring) */
+      xi[a] = d->kt > 0.0 ? -(Ft[a] + d->eta_t * vt[a]) / d->kt : 0.0;
     }
   }
   for (int a = 0; a < 3; a++) F[a] = Fn * n[a] + Ft[a];

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "librwmi.so")
 RWMI_OK, RWMI_EINVAL, RWMI_ENOMEM, RWMI_EDEVICE, RWMI_ESTATE, RWMI_ESEED = 0, -1, -2, -3, -4, -5
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ESEED"}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
-MOTION = {"static": 0, "sinusoid": 1, "const_vel": 2}
+MOTION = {"static": 0, "sinusoid": 1, "const_vel": 2, "coupled": 3}
 SEED_KIND = {"uniform": 0, "gaussian": 1, "band": 2, "explicit": 3}
 KEY = {"max_bisect": 1, "use_graph": 2, "block": 3, "timing": 5, "step_flags": 6, "sort_every": 7, "streaming": 8, "member_blocks": 10}
 MAX_PARTICLES = 64
@@ -45,6 +45,36 @@ class SeedDesc(C.Structure):
                 ("ref", C.c_double * 3), ("max_attempts", C.c_int32), ("remove_inside", C.c_int32)]
 
 
+class CouplingDesc(C.Structure):
+    _fields_ = [("density", C.c_double), ("gravity", C.c_double * 3), ("drive_amplitude", C.c_double),
+                ("drive_period", C.c_double), ("drive_direction", C.c_double * 3), ("kn", C.c_double),
+                ("kt", C.c_double), ("eta_n", C.c_double), ("eta_t", C.c_double), ("mu", C.c_double),
+                ("dilation_radius", C.c_double), ("substeps", C.c_int32), ("coupling", C.c_int32)]
+
+
+# coupling parameters by the names of the particle dynamics (Eq. 4-11)
+COUPLING_DEFAULTS = {"g": (0.0, 0.0, 0.0), "drive_amp": 0.0, "drive_period": 5000.0, "drive_dir": (1.0, 0.0, 0.0),
+                     "kt": 0.0, "eta_n": 0.0, "eta_t": 0.0, "mu": 0.0, "nsub": 100, "coupling": 1}
+
+
+def coupling_desc(dem):
+    v = dict(COUPLING_DEFAULTS, **dem)
+    c = CouplingDesc()
+    c.density = float(v["rho_p"])
+    for a in range(3):
+        c.gravity[a] = float(v["g"][a])
+        c.drive_direction[a] = float(v["drive_dir"][a])
+    c.drive_amplitude = float(v["drive_amp"])
+    c.drive_period = float(v["drive_period"])
+    c.kn, c.kt = float(v["kn"]), float(v["kt"])
+    c.eta_n, c.eta_t = float(v["eta_n"]), float(v["eta_t"])
+    c.mu = float(v["mu"])
+    c.dilation_radius = float(v["Rs"])
+    c.substeps = int(v["nsub"])
+    c.coupling = int(v["coupling"])
+    return c
+
+
 class Dispersion(C.Structure):
     _fields_ = [("u_slip", C.c_double), ("phi", C.c_double), ("K", C.c_double), ("D_alpha", C.c_double),
                 ("offset", C.c_double)]
@@ -55,7 +85,8 @@ class Moments(C.Structure):
                 ("mass", C.c_double), ("momentum", C.c_double * 3), ("fluid_u", C.c_double * 3),
                 ("particle_v", C.c_double * 3), ("solid_volume", C.c_double), ("type2", C.c_uint64),
                 ("type4", C.c_uint64), ("bisect_fail", C.c_uint64), ("refill_fallback", C.c_uint64),
-                ("returned_to_origin", C.c_uint64), ("wall_reflect", C.c_uint64), ("near_surface", C.c_uint64)]
+                ("returned_to_origin", C.c_uint64), ("wall_reflect", C.c_uint64), ("near_surface", C.c_uint64),
+                ("contact_misses", C.c_uint64)]
 
 
 # name -> (restype, argtypes); the full exported surface of include/rwmi.h
@@ -63,6 +94,9 @@ SIGNATURES = {
     "rwmi_create_domain": (C.c_int, [C.POINTER(DomainDesc), C.POINTER(C.c_void_p)]),
     "rwmi_destroy_domain": (None, [C.c_void_p]),
     "rwmi_add_metaball_particle": (C.c_int, [C.c_void_p, C.POINTER(MetaballDesc), C.POINTER(C.c_int32)]),
+    "rwmi_set_coupling": (C.c_int, [C.c_void_p, C.POINTER(CouplingDesc)]),
+    "rwmi_read_particle_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "rwmi_set_particle_motion": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "rwmi_seed_walkers": (C.c_int, [C.c_void_p, C.POINTER(SeedDesc), C.c_uint64, C.POINTER(C.c_uint64)]),
     "rwmi_step": (C.c_int, [C.c_void_p, C.c_uint32]),
     "rwmi_read_moments": (C.c_int, [C.c_void_p, C.POINTER(Moments)]),
@@ -283,6 +317,26 @@ class Domain:
         self.nparticles += 1
         return out.value
 
+    def set_coupling(self, dem):
+        """Two-way coupling of the particles added with motion "coupled"
+        (Eq. 4-11); after adding the particles, before seeding."""
+        c = coupling_desc(dem)
+        self._ck(self.L.rwmi_set_coupling(self.h, C.byref(c)))
+
+    def particle_state(self, p):
+        o = np.zeros(32)
+        self._ck(self.L.rwmi_read_particle_state(self.h, int(p), o.ctypes.data_as(C.c_void_p)))
+        return {"c": o[0:3].copy(), "v": o[3:6].copy(), "q": o[6:10].copy(), "L": o[10:13].copy(),
+                "w": o[13:16].copy(), "Fh": o[16:19].copy(), "Th": o[19:22].copy(), "mass": float(o[22]),
+                "I": o[23:32].reshape(3, 3).copy()}
+
+    def set_particle_motion(self, p, v, L):
+        v = np.ascontiguousarray(np.asarray(v, float).ravel())
+        L = np.ascontiguousarray(np.asarray(L, float).ravel())
+        assert v.size == 3 and L.size == 3
+        self._ck(self.L.rwmi_set_particle_motion(self.h, int(p), v.ctypes.data_as(C.c_void_p),
+                                                 L.ctypes.data_as(C.c_void_p)))
+
     def seed(self, s, n, check=True):
         sd = SeedDesc()
         sd.kind = SEED_KIND[s["kind"]]
@@ -333,7 +387,7 @@ class Domain:
                     counters=dict(type2=int(m.type2), type4=int(m.type4), bisect_fail=int(m.bisect_fail),
                                   refill_fallback=int(m.refill_fallback),
                                   returned_to_origin=int(m.returned_to_origin), wall_reflect=int(m.wall_reflect)),
-                    near_surface=int(m.near_surface))
+                    near_surface=int(m.near_surface), contact_misses=int(m.contact_misses))
 
     def occupancy(self):
         ns = np.empty(self.N, np.uint32)
@@ -380,6 +434,8 @@ def build_domain(cfg, device=0, use_torch=True, seed_walkers=True):
     d = Domain(cfg["domain"], device=device, use_torch=use_torch)
     for p in cfg.get("particles", []):
         d.add_particle(p)
+    if cfg.get("dem"):
+        d.set_coupling(cfg["dem"])
     if seed_walkers and cfg.get("walkers") and cfg["walkers"].get("n", 0) > 0:
         d.seed(cfg["walkers"], cfg["walkers"]["n"])
     return d

@@ -74,6 +74,8 @@ __global__ void k_seed(const DomView* __restrict__ views, int dom, int kind, dou
       const double dy = axis_disp<double>(!V.bc[1], V.n[1], cell[1], pc[1], o[1]);
       const double dz = axis_disp<double>(!V.bc[2], V.n[2], cell[2], pc[2], o[2]);
       if ((dx * dx + dy * dy) + dz * dz >= P.maskr * P.maskr) continue;
+      // control points as given (seeding happens before the first step, at
+      // the initial orientation)
       if (metaball_value<double>(gp(V.ctrl) + 4 * P.ctrl0, P.nc, dx, dy, dz) >= 1.0) inside = true;
     }
     if (inside) continue;
@@ -220,7 +222,8 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
   const int64_t last = (base + kRedChunk - 1 < V.N) ? base + kRedChunk - 1 : V.N - 1;
   const uint64_t done = V.tstep[0];  // steps completed
   const bool stepped = done > 0;
-  if (stepped && V.np > 0) cull_block<C>(V, (uint32_t)base, (uint32_t)last, done - 1, sp, false);
+  // coupled particles: poses from the table the particle update wrote
+  if (stepped && V.np > 0) cull_block<C>(V, (uint32_t)base, (uint32_t)last, done - 1, sp, V.dem_mask != 0ull);
   else if (threadIdx.x == 0) sp.cnt = 0;
   __syncthreads();
   double acc[kNodeMom];
@@ -240,10 +243,16 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
     if (wall) continue;
     double es = 0.0, un[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < sp.cnt; ++k) {
-      const double e = (double)node_eps<C>(V, sp, k, nd);
+      C dl[3];
+      const double e = (double)node_eps<C>(V, sp, k, nd, dl);
       es = es + e;
+      double up[3] = {sp.v[k][0], sp.v[k][1], sp.v[k][2]};
+      if (((V.dem_mask >> sp.id[k]) & 1ull) && e > 0.0) {
+        const double dd[3] = {(double)dl[0], (double)dl[1], (double)dl[2]};
+        rigid_velocity<double>(sp.w[k], dd, up);
+      }
 #pragma unroll
-      for (int a = 0; a < 3; ++a) un[a] = un[a] + e * sp.v[k][a];
+      for (int a = 0; a < 3; ++a) un[a] = un[a] + e * up[a];
     }
     const double eps = es < 1.0 ? es : 1.0;
     const double r = (double)rf[id];

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/rwmi.h"
+#include "dem_impl.h"
 #include "dev_common.h"
 #include "launch.h"
 
@@ -107,6 +108,10 @@ struct rwmi_domain {
   double* mom_out = nullptr;
   double* dref = nullptr;
   rwmi_batch* batch = nullptr;
+  // two-way coupled particles
+  bool dem = false;
+  rwmi::DemArgs dem_host{};
+  rwmi::DemArgs* dem_dev = nullptr;
 };
 
 struct rwmi_batch {
@@ -298,7 +303,7 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   if ((st = alloc_into(d, dp, sizeof(DevParticle) * hp.size())) != RWMI_OK) return st;
   if ((st = alloc_into(d, dc, sizeof(double) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
   if ((st = alloc_into(d, dcf, sizeof(float) * std::max<size_t>(ctrl.size(), 4))) != RWMI_OK) return st;
-  if ((st = alloc_into(d, dpose, sizeof(double) * 36 * std::max(np, 1))) != RWMI_OK) return st;
+  if ((st = alloc_into(d, dpose, sizeof(double) * 6 * rwmi::kPoseRec * std::max(np, 1))) != RWMI_OK) return st;
   float* dsph;
   if ((st = alloc_into(d, dsph, sizeof(float) * 12 * std::max(np, 1))) != RWMI_OK) return st;
   HIPCHK(d, hipMemcpyAsync(dp, hp.data(), sizeof(DevParticle) * hp.size(), hipMemcpyHostToDevice, d->stream));
@@ -311,7 +316,9 @@ rwmi_status finalize_particles(rwmi_domain* d) {
   d->hv.ctrl = dc;
   d->hv.ctrl_f = dcf;
   for (int k = 0; k < 3; ++k) {
-    d->hv.pose[k] = dpose + 12 * std::max(np, 1) * k;
+    d->hv.ctrlr[k] = dc;  // nothing rotates unless coupled particles are set up
+    d->hv.ctrlr_f[k] = dcf;
+    d->hv.pose[k] = dpose + 2 * rwmi::kPoseRec * std::max(np, 1) * k;
     d->hv.sph[k] = dsph + 4 * std::max(np, 1) * k;
   }
   d->hv.np = np;
@@ -368,7 +375,10 @@ bool sort_before(const rwmi_domain* d, uint32_t j, uint32_t n, bool capturing) {
 // `record`, HIP events bracket windows of timing_every consecutive step
 // launches (j >= 0); a window closes early before a regrouping and at the
 // end of the group, so it times step launches only.
+rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool capturing);
+
 rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturing) {
+  if (d->dem) return enqueue_group_dem(d, n, capturing);
   int b[kRoles];
   role_blocks(d, d->bs, b);
   hipStream_t A = d->stream;
@@ -416,6 +426,153 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturin
   if (close_window() != RWMI_OK) return RWMI_EDEVICE;
   HIPCHK(d, rwmi::launch_advance(d->dv, 1, n, A));
   return RWMI_OK;
+}
+
+// A launch group of n steps with two-way coupled particles.  The poses of a
+// step are known only once the particle update of the previous step has run,
+// so each step is three launches: the fused launch j (walkers of t0 + j - 1
+// and fluid of t0 + j, which accumulates the hydrodynamic force), the
+// particle update of t0 + j (poses and control points of t0 + j + 1) and the
+// prologue of t0 + j + 1 (cull masks at those poses); then the walkers of
+// the last step.
+rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool capturing) {
+  int b[kRoles];
+  role_blocks(d, d->bs, b);
+  hipStream_t A = d->stream;
+  for (int j = 0; j <= (int)n; ++j) {
+    if (sort_before(d, (uint32_t)j, n, capturing)) {
+      HIPCHK(d, rwmi::launch_sort(d->prec, d->dv, 0, d->hv.nw, d->sort, A));
+      if (!capturing) d->sorted_at = d->steps + (uint32_t)j;
+    }
+    rwmi::StepArgs a{};
+    a.views = d->dv;
+    a.boff = d->dboff;
+    a.nd = 1;
+    a.nb[kRoleWalk] = j >= 1 ? b[kRoleWalk] : 0;
+    a.nb[kRolePro] = 0;
+    a.nb[kRoleFluid] = j < (int)n ? b[kRoleFluid] : 0;
+    a.flags = d->flags | rwmi::kFlagDem | (j == (int)n - 1 ? rwmi::kFlagDensity : 0);
+    a.inplace = d->hv.inplace;
+    a.j = j;
+    if (a.nb[kRoleWalk] + a.nb[kRoleFluid] > 0) HIPCHK(d, rwmi::launch_step(d->prec, 256, a, A));
+    if (j == (int)n) break;
+    HIPCHK(d, rwmi::launch_dem(d->dv, d->dem_dev, j, A));
+    a.nb[kRoleWalk] = 0;
+    a.nb[kRolePro] = b[kRolePro];
+    a.nb[kRoleFluid] = 0;
+    a.flags = d->flags | rwmi::kFlagDem;
+    HIPCHK(d, rwmi::launch_step(d->prec, 256, a, A));
+  }
+  HIPCHK(d, rwmi::launch_advance(d->dv, 1, n, A));
+  return RWMI_OK;
+}
+
+// ---- set-up of coupled particles (host arithmetic: once per particle)
+// Metaball value and gradient (Eq. 3, Eq. 17) at offset x from the reference
+// point, in control-point order.
+double host_M(const HostParticle& q, const double x[3]) {
+  double M = 0.0;
+  for (size_t i = 0; i < q.k.size(); ++i) {
+    const double rx = x[0] - q.b[3 * i], ry = x[1] - q.b[3 * i + 1], rz = x[2] - q.b[3 * i + 2];
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 == 0.0) return INFINITY;
+    M = M + q.k[i] / r2;
+  }
+  return M;
+}
+void host_grad(const HostParticle& q, const double x[3], double g[3]) {
+  g[0] = g[1] = g[2] = 0.0;
+  for (size_t i = 0; i < q.k.size(); ++i) {
+    const double r[3] = {x[0] - q.b[3 * i], x[1] - q.b[3 * i + 1], x[2] - q.b[3 * i + 2]};
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double f = (-2.0 * q.k[i]) / (r2 * r2);
+    for (int a = 0; a < 3; ++a) g[a] = g[a] + f * r[a];
+  }
+}
+// Solid fraction of the cell of size h centred at x: 1/2 + the distance
+// estimate 2 M (sqrt M - 1) / |grad M| in cell units, clamped to [0, 1].
+double host_cell_fraction(const HostParticle& q, const double x[3], double h) {
+  const double M = host_M(q, x);
+  if (M == INFINITY) return 1.0;
+  double g[3];
+  host_grad(q, x, g);
+  const double gn = std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  double e;
+  if (gn == 0.0) e = M >= 1.0 ? 1.0 : 0.0;
+  else e = 0.5 + (((2.0 * M) * (std::sqrt(M) - 1.0)) / gn) / h;
+  if (!(e > 0.0)) e = 0.0;
+  if (e > 1.0) e = 1.0;
+  return e;
+}
+// Mass, centre of mass (offset from the reference point) and inertia tensor
+// of a metaball of density rho: cells of size rb/24 over the cube
+// [-rb - h, rb + h]^3, weighted by their solid fractions, summed z, y, x.
+void host_mass_properties(const HostParticle& q, double rb, double rho, double* mass, double com[3],
+                          double I[3][3]) {
+  const int G = 50;
+  const double h = rb / 24.0;
+  double V = 0.0, S[3] = {0.0, 0.0, 0.0};
+  for (int iz = 0; iz < G; ++iz)
+    for (int iy = 0; iy < G; ++iy)
+      for (int ix = 0; ix < G; ++ix) {
+        const double x[3] = {((double)(ix - 25) + 0.5) * h, ((double)(iy - 25) + 0.5) * h,
+                             ((double)(iz - 25) + 0.5) * h};
+        const double e = host_cell_fraction(q, x, h);
+        V = V + e;
+        for (int a = 0; a < 3; ++a) S[a] = S[a] + e * x[a];
+      }
+  for (int a = 0; a < 3; ++a) com[a] = S[a] / V;
+  double Q[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int iz = 0; iz < G; ++iz)
+    for (int iy = 0; iy < G; ++iy)
+      for (int ix = 0; ix < G; ++ix) {
+        const double x[3] = {((double)(ix - 25) + 0.5) * h, ((double)(iy - 25) + 0.5) * h,
+                             ((double)(iz - 25) + 0.5) * h};
+        const double e = host_cell_fraction(q, x, h);
+        const double r[3] = {x[0] - com[0], x[1] - com[1], x[2] - com[2]};
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) Q[a][c] = Q[a][c] + e * (r[a] * r[c]);
+      }
+  const double h3 = (h * h) * h;
+  *mass = (rho * V) * h3;
+  const double tr = (Q[0][0] + Q[1][1]) + Q[2][2];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) I[a][c] = (rho * h3) * ((a == c ? tr : 0.0) - Q[a][c]);
+}
+bool host_inv3(const double A[3][3], double X[3][3]) {
+  const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  const double det = (A[0][0] * c00 + A[0][1] * c01) + A[0][2] * c02;
+  if (det == 0.0 || !std::isfinite(det)) return false;
+  X[0][0] = c00 / det;
+  X[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+  X[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+  X[1][0] = c01 / det;
+  X[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+  X[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+  X[2][0] = c02 / det;
+  X[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+  X[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+  return true;
+}
+// w = R I_b^-1 R^T L for the unit quaternion q.
+void host_omega(const double q[4], const double* Ibinv, const double L[3], double w[3]) {
+  const double qw = q[0], x = q[1], y = q[2], z = q[3];
+  double R[3][3];
+  R[0][0] = 1.0 - 2.0 * (y * y + z * z);
+  R[0][1] = 2.0 * (x * y - qw * z);
+  R[0][2] = 2.0 * (x * z + qw * y);
+  R[1][0] = 2.0 * (x * y + qw * z);
+  R[1][1] = 1.0 - 2.0 * (x * x + z * z);
+  R[1][2] = 2.0 * (y * z - qw * x);
+  R[2][0] = 2.0 * (x * z - qw * y);
+  R[2][1] = 2.0 * (y * z + qw * x);
+  R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+  double yv[3], zv[3];
+  for (int a = 0; a < 3; ++a) yv[a] = (R[0][a] * L[0] + R[1][a] * L[1]) + R[2][a] * L[2];
+  for (int a = 0; a < 3; ++a) zv[a] = (Ibinv[3 * a] * yv[0] + Ibinv[3 * a + 1] * yv[1]) + Ibinv[3 * a + 2] * yv[2];
+  for (int a = 0; a < 3; ++a) w[a] = (R[a][0] * zv[0] + R[a][1] * zv[1]) + R[a][2] * zv[2];
 }
 
 bool valid_prec(int p) { return p >= RWMI_FP64 && p <= RWMI_BF16_STORE; }
@@ -587,7 +744,7 @@ rwmi_status rwmi_add_metaball_particle(rwmi_domain* d, const rwmi_metaball_desc*
   if ((int)d->parts.size() >= RWMI_MAX_PARTICLES) return fail(d, RWMI_EINVAL, "at most %d particles", RWMI_MAX_PARTICLES);
   if (p->n_ctrl < 1 || p->n_ctrl > RWMI_MAX_CTRL || !p->offsets || !p->weights)
     return fail(d, RWMI_EINVAL, "n_ctrl = %d out of range", p->n_ctrl);
-  if (p->motion < RWMI_MOTION_STATIC || p->motion > RWMI_MOTION_CONST_VEL) return fail(d, RWMI_EINVAL, "bad motion");
+  if (p->motion < RWMI_MOTION_STATIC || p->motion > RWMI_MOTION_COUPLED) return fail(d, RWMI_EINVAL, "bad motion");
   if (p->motion == RWMI_MOTION_SINUSOID && !(p->period > 0.0)) return fail(d, RWMI_EINVAL, "period must be > 0");
   HostParticle h;
   h.b.assign(p->offsets, p->offsets + 3 * p->n_ctrl);
@@ -739,6 +896,161 @@ rwmi_status rwmi_step(rwmi_domain* d, uint32_t n_steps) {
   return RWMI_OK;
 }
 
+rwmi_status rwmi_set_coupling(rwmi_domain* d, const rwmi_coupling_desc* c) {
+  if (!d || !c) return fail(d, RWMI_EINVAL, "null argument");
+  if (d->dem) return fail(d, RWMI_ESTATE, "coupling already set up");
+  if (d->particles_uploaded || d->seeded || d->stepped)
+    return fail(d, RWMI_ESTATE, "set up the coupling after adding the particles, before seeding and stepping");
+  if (!(c->density > 0.0) || c->substeps < 1 || !(c->drive_period > 0.0) || !(c->dilation_radius > 0.0) ||
+      !(c->kn > 0.0) || c->kt < 0.0 || c->eta_n < 0.0 || c->eta_t < 0.0 || c->mu < 0.0)
+    return fail(d, RWMI_EINVAL, "coupling parameters out of range");
+  const int np = (int)d->parts.size();
+  unsigned long long mask = 0ull;
+  size_t nctrl = 0;
+  for (int p = 0; p < np; ++p) {
+    nctrl += d->parts[p].k.size();
+    if (d->parts[p].motion == RWMI_MOTION_COUPLED) mask |= 1ull << p;
+  }
+  if (!mask) return fail(d, RWMI_EINVAL, "no particle has motion RWMI_MOTION_COUPLED");
+  if (nctrl > (size_t)rwmi::kDemMaxCtrl)
+    return fail(d, RWMI_EINVAL, "%zu control points in all; coupled particles allow at most %d", nctrl,
+                rwmi::kDemMaxCtrl);
+  HIPCHK(d, hipSetDevice(d->device));
+  // mass properties; the centre of mass becomes each coupled particle's centre
+  std::vector<double> state((size_t)rwmi::kDemState * np, 0.0);
+  for (int p = 0; p < np; ++p) {
+    HostParticle& q = d->parts[p];
+    if (q.motion != RWMI_MOTION_COUPLED) continue;
+    const int nc = (int)q.k.size();
+    double K = 0.0, bmax = 0.0;
+    for (int i = 0; i < nc; ++i) {
+      K = K + q.k[i];
+      const double* b = &q.b[3 * i];
+      const double r = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      if (r > bmax) bmax = r;
+    }
+    const double sk = std::sqrt(K);
+    if (!(sk > c->dilation_radius)) return fail(d, RWMI_EINVAL, "particle %d is thinner than the dilation radius", p);
+    double mass, com[3], I[3][3], Iinv[3][3];
+    host_mass_properties(q, bmax + sk, c->density, &mass, com, I);
+    if (!host_inv3(I, Iinv)) return fail(d, RWMI_EINVAL, "particle %d has a singular inertia tensor", p);
+    double bmax2 = 0.0;
+    for (int i = 0; i < nc; ++i) {
+      for (int a = 0; a < 3; ++a) q.b[3 * i + a] = q.b[3 * i + a] - com[a];
+      const double* b = &q.b[3 * i];
+      const double r = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      if (r > bmax2) bmax2 = r;
+    }
+    double* st = &state[(size_t)rwmi::kDemState * p];
+    for (int a = 0; a < 3; ++a) {
+      q.c0[a] = q.c0[a] + com[a];
+      st[rwmi::kDc + a] = q.c0[a];
+      st[rwmi::kDv + a] = q.vel[a];
+    }
+    st[rwmi::kDq] = 1.0;
+    st[rwmi::kDm] = mass;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        st[rwmi::kDIb + 3 * a + b] = I[a][b];
+        st[rwmi::kDIbinv + 3 * a + b] = Iinv[a][b];
+      }
+    st[rwmi::kDcin] = (sk / (sk - c->dilation_radius)) * (sk / (sk - c->dilation_radius));
+    st[rwmi::kDrb] = bmax2 + sk;
+  }
+  rwmi_status st;
+  if ((st = finalize_particles(d)) != RWMI_OK) return st;
+  rwmi::DemArgs& A = d->dem_host;
+  A.nsub = c->substeps;
+  A.coupling = c->coupling ? 1 : 0;
+  for (int a = 0; a < 3; ++a) {
+    A.g[a] = c->gravity[a];
+    A.drive_dir[a] = c->drive_direction[a];
+  }
+  A.drive_amp = c->drive_amplitude;
+  A.drive_period = c->drive_period;
+  A.kn = c->kn;
+  A.kt = c->kt;
+  A.eta_n = c->eta_n;
+  A.eta_t = c->eta_t;
+  A.mu = c->mu;
+  A.Rs = c->dilation_radius;
+  unsigned long long* acc;
+  const size_t nct = std::max<size_t>(nctrl, 1);
+  if ((st = alloc_into(d, A.state, sizeof(double) * state.size())) != RWMI_OK ||
+      (st = alloc_into(d, A.xi, sizeof(double) * 3 * rwmi::kMaxParticles * rwmi::kMaxParticles)) != RWMI_OK ||
+      (st = alloc_into(d, A.xiw, sizeof(double) * 3 * 6 * rwmi::kMaxParticles)) != RWMI_OK ||
+      (st = alloc_into(d, acc, sizeof(unsigned long long) * 6 * np)) != RWMI_OK ||
+      (st = alloc_into(d, d->dem_dev, sizeof(rwmi::DemArgs))) != RWMI_OK)
+    return st;
+  for (int k = 0; k < 3; ++k) {
+    if ((st = alloc_into(d, A.ctrlr[k], sizeof(double) * 4 * nct)) != RWMI_OK ||
+        (st = alloc_into(d, A.ctrlr_f[k], sizeof(float) * 4 * nct)) != RWMI_OK)
+      return st;
+    HIPCHK(d, hipMemcpyAsync(A.ctrlr[k], d->hv.ctrl, sizeof(double) * 4 * nctrl, hipMemcpyDeviceToDevice, d->stream));
+    HIPCHK(d, hipMemcpyAsync(A.ctrlr_f[k], d->hv.ctrl_f, sizeof(float) * 4 * nctrl, hipMemcpyDeviceToDevice,
+                             d->stream));
+    d->hv.ctrlr[k] = A.ctrlr[k];
+    d->hv.ctrlr_f[k] = A.ctrlr_f[k];
+  }
+  HIPCHK(d, hipMemsetAsync(A.xi, 0, sizeof(double) * 3 * rwmi::kMaxParticles * rwmi::kMaxParticles, d->stream));
+  HIPCHK(d, hipMemsetAsync(A.xiw, 0, sizeof(double) * 3 * 6 * rwmi::kMaxParticles, d->stream));
+  HIPCHK(d, hipMemsetAsync(acc, 0, sizeof(unsigned long long) * 6 * np, d->stream));
+  HIPCHK(d, hipMemcpyAsync(A.state, state.data(), sizeof(double) * state.size(), hipMemcpyHostToDevice, d->stream));
+  HIPCHK(d, hipMemcpyAsync(d->dem_dev, &A, sizeof A, hipMemcpyHostToDevice, d->stream));
+  d->hv.dem_mask = mask;
+  d->hv.dem_acc = acc;
+  d->dem = true;
+  d->bs = 256;
+  if ((st = upload_view(d)) != RWMI_OK || (st = upload_workmaps(d)) != RWMI_OK) return st;
+  // poses and cull masks of the current step from the state
+  HIPCHK(d, rwmi::launch_dem_tables(d->dv, d->dem_dev, d->stream));
+  int b[kRoles];
+  role_blocks(d, d->bs, b);
+  rwmi::StepArgs a{};
+  a.views = d->dv;
+  a.boff = d->dboff;
+  a.nd = 1;
+  a.nb[kRolePro] = b[kRolePro];
+  a.flags = d->flags | rwmi::kFlagDem;
+  a.inplace = d->hv.inplace;
+  a.j = -1;
+  HIPCHK(d, rwmi::launch_step(d->prec, 256, a, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));  // `state` lives on this stack frame
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_read_particle_state(rwmi_domain* d, int32_t p, double* out) {
+  if (!d || !out) return fail(d, RWMI_EINVAL, "null argument");
+  if (!d->dem || p < 0 || p >= d->hv.np || !((d->hv.dem_mask >> p) & 1ull))
+    return fail(d, RWMI_EINVAL, "particle %d is not a coupled particle", p);
+  HIPCHK(d, hipSetDevice(d->device));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  HIPCHK(d, hipMemcpy(out, d->dem_host.state + (size_t)rwmi::kDemState * p, sizeof(double) * 32,
+                      hipMemcpyDeviceToHost));
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_set_particle_motion(rwmi_domain* d, int32_t p, const double v[3], const double L[3]) {
+  if (!d || !v || !L) return fail(d, RWMI_EINVAL, "null argument");
+  if (!d->dem || p < 0 || p >= d->hv.np || !((d->hv.dem_mask >> p) & 1ull))
+    return fail(d, RWMI_EINVAL, "particle %d is not a coupled particle", p);
+  if (d->batch) return fail(d, RWMI_ESTATE, "domain is stepped by its batch");
+  HIPCHK(d, hipSetDevice(d->device));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  double st[rwmi::kDemState];
+  double* dst = d->dem_host.state + (size_t)rwmi::kDemState * p;
+  HIPCHK(d, hipMemcpy(st, dst, sizeof st, hipMemcpyDeviceToHost));
+  for (int a = 0; a < 3; ++a) {
+    st[rwmi::kDv + a] = v[a];
+    st[rwmi::kDL + a] = L[a];
+  }
+  host_omega(st + rwmi::kDq, st + rwmi::kDIbinv, st + rwmi::kDL, st + rwmi::kDw);
+  HIPCHK(d, hipMemcpy(dst, st, sizeof st, hipMemcpyHostToDevice));
+  HIPCHK(d, rwmi::launch_dem_tables(d->dv, d->dem_dev, d->stream));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  return RWMI_OK;
+}
+
 rwmi_status rwmi_synchronize(rwmi_domain* d) {
   if (!d) return fail(d, RWMI_EINVAL, "null domain");
   HIPCHK(d, hipSetDevice(d->device));
@@ -872,6 +1184,7 @@ static void fill_moments(const rwmi_domain* d, const double h[32], rwmi_moments*
   out->returned_to_origin = u64[rwmi::kReturned];
   out->wall_reflect = u64[rwmi::kWallReflect];
   out->near_surface = u64[rwmi::kNearSurface];
+  out->contact_misses = u64[rwmi::kDemSkin];
 }
 
 rwmi_status rwmi_read_profile(rwmi_domain* d, int32_t axis, uint64_t* counts) {
@@ -965,6 +1278,7 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       return RWMI_OK;
     case RWMI_KEY_BLOCK:
       if (value != 128 && value != 256 && value != 512) return fail(d, RWMI_EINVAL, "block must be 128, 256 or 512");
+      if (d->dem && value != 256) return fail(d, RWMI_EINVAL, "domains with coupled particles step with 256 threads");
       d->bs = (int)value;
       drop_graph(d);
       // a batch holding it regroups it (if the batch launches members with
@@ -1250,6 +1564,7 @@ rwmi_status rwmi_batch_add(rwmi_batch* b, rwmi_domain* d) {
   if (d->batch) return bfail(b, RWMI_ESTATE, "domain already in a batch");
   if (d->device != b->device) return bfail(b, RWMI_EINVAL, "domain lives on another device");
   if (hipSetDevice(d->device) != hipSuccess) return bfail(b, RWMI_EDEVICE, "hipSetDevice failed");
+  if (d->dem) return bfail(b, RWMI_EINVAL, "domains with coupled particles are stepped alone");
   if (finalize_particles(d) != RWMI_OK) return bfail(b, RWMI_EDEVICE, d->err.c_str());
   d->batch = b;
   b->members.push_back(d);

@@ -54,7 +54,14 @@ __host__ __device__ __forceinline__ uint64_t f_elems(int64_t N) {
 
 constexpr int kMaxParticles = 64;
 constexpr int kCounters = 8;
-enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect, kNearSurface };
+// kDemSkin: a coupled particle moved farther in one step than the margin of
+// the contact candidate list (its contacts of that step may be missed).
+enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect, kNearSurface, kDemSkin };
+// Pose table record of one particle: centre, velocity, angular velocity.
+constexpr int kPoseRec = 9;
+// 2^48: the fixed-point scale of the hydrodynamic force and torque sums on
+// coupled particles (sums of at most 2^15 in magnitude).
+constexpr double kForceFix = 281474976710656.0;
 constexpr int kMaskBlock = 4;  // edge of a coarse block of the walker cull mask
 // The start cell's coarse mask word also covers the end of any walker step
 // with |dl| <= kMaskReach on every axis: the prologue dilates each coarse
@@ -129,9 +136,13 @@ struct DomView {
   void* u[2];                     // (ux, uy, uz) per node (3 U), written by step t into [t & 1]
   void* rho;                      // density per node, written by the last fluid step of a group
   const DevParticle* parts;
-  const double* ctrl;             // 4 per control point: bx, by, bz, k
+  const double* ctrl;             // 4 per control point: bx, by, bz, k (body frame)
   const float* ctrl_f;            // the same in float (low-precision modes)
-  double* pose[3];                // per step t, slot t mod 3: [2][np][6] (c, v) at t and t+1
+  const double* ctrlr[3];         // per pose slot s: control points at the pose P(s) of
+  const float* ctrlr_f[3];        // the slot's fluid step (offsets rotated with the
+                                  // particle; all three are ctrl when nothing rotates)
+  double* pose[3];                // per step t, slot t mod 3: [2][np][kPoseRec] (c, v, w)
+                                  // at t and t+1
   float* sph[3];                  // per step t, slot t mod 3: [np][4] walker filter spheres at
                                   // t+1: centre, (rb + 1/2 + kSphereMargin)^2
   uint64_t* tstep;                // [0] steps completed before the current launch group
@@ -145,6 +156,9 @@ struct DomView {
   int32_t* winv;                  // slot of walker id w (inverse of wid; built for read-outs)
   unsigned long long* counters;   // kCounters
   uint32_t* occ;                  // occupancy per node
+  unsigned long long dem_mask;    // bit p: particle p moves by Newton-Euler (two-way coupled)
+  unsigned long long* dem_acc;    // [np][6] hydrodynamic force and torque of the running
+                                  // fluid step, two's-complement sums in units of 2^-48
 };
 
 // Global-address-space view of a pointer loaded from memory, so that accesses
@@ -462,10 +476,12 @@ template <> __device__ __forceinline__ unsigned short raw_out<__hip_bfloat16>(fl
   return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
-// Control points in the arithmetic precision of a mode.
-template <typename R> __device__ __forceinline__ const R* ctrl_of(const DomView& V);
-template <> __device__ __forceinline__ const double* ctrl_of<double>(const DomView& V) { return V.ctrl; }
-template <> __device__ __forceinline__ const float* ctrl_of<float>(const DomView& V) { return V.ctrl_f; }
+// Control points at the pose of slot s, in the arithmetic precision of a mode.
+template <typename R> __device__ __forceinline__ const R* ctrl_of(const DomView& V, int s);
+template <> __device__ __forceinline__ const double* ctrl_of<double>(const DomView& V, int s) { return V.ctrlr[s]; }
+template <> __device__ __forceinline__ const float* ctrl_of<float>(const DomView& V, int s) { return V.ctrlr_f[s]; }
+// Slot of the pose P(t+1) that the walkers of step t (pose table slot ps) move against.
+__device__ __forceinline__ int next_slot(int ps) { return ps == 2 ? 0 : ps + 1; }
 // metaball sums read control points through a global pointer
 template <typename T> using gconst = const __attribute__((address_space(1))) T*;
 

@@ -3,6 +3,7 @@
 #include <mutex>
 
 #include "aux_impl.h"
+#include "dem_impl.h"
 #include "launch.h"
 #include "step_impl.h"
 
@@ -35,6 +36,11 @@ hipError_t noalloc_scratch(double** ptr) {
 hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
   const unsigned g = (unsigned)step_grid(a.nb, (a.flags & kFlagXcd) != 0);
   if (g == 0) return hipSuccess;
+  if (a.flags & kFlagDem) {  // coupled particles: 256 threads per block
+    if (a.inplace) k_step<P64, 256, true, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
+    else k_step<P64, 256, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
+    return hipGetLastError();
+  }
   if (a.inplace) {
     switch (bs) {
       case 128: k_step<P64, 128, true><<<g, 128, 0, s>>>(a, a.views, a.boff); break;
@@ -48,6 +54,30 @@ hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
       default: k_step<P64, 256, false><<<g, 256, 0, s>>>(a, a.views, a.boff); break;
     }
   }
+  return hipGetLastError();
+}
+
+// The particle update of step tstep + j of domain views[0]: one block of 64
+// threads (one per particle).
+__global__ void __launch_bounds__(64) k_dem(const DomView* __restrict__ views, const DemArgs* __restrict__ da,
+                                            int32_t j) {
+  __shared__ DemLds S;
+  const DomView& V = views[0];
+  dem_block(V, *da, step_of(V, j), S);
+}
+
+__global__ void __launch_bounds__(64) k_dem_tables(const DomView* __restrict__ views, const DemArgs* __restrict__ da) {
+  const DomView& V = views[0];
+  dem_tables(V, *da, step_of(V, 0));
+}
+
+hipError_t launch_dem(const DomView* v, const void* dem_args, int32_t j, hipStream_t s) {
+  k_dem<<<1, 64, 0, s>>>(v, (const DemArgs*)dem_args, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_dem_tables(const DomView* v, const void* dem_args, hipStream_t s) {
+  k_dem_tables<<<1, 64, 0, s>>>(v, (const DemArgs*)dem_args);
   return hipGetLastError();
 }
 

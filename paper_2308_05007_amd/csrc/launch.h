@@ -40,6 +40,11 @@ hipError_t launch_profile(const DomView* v, int dom, int axis, int n_layers, int
 hipError_t launch_moments(int prec, const DomView* v, int dom, int64_t N, int64_t nw, const double* ref,
                           double* pw, double* pn, double* out, hipStream_t s);
 hipError_t launch_advance(const DomView* views, int nd, uint32_t n, hipStream_t s);
+// Two-way coupled particles of domain views[0] (dem_args: a device DemArgs,
+// dem_impl.h): the particle update of step tstep + j, and the pose tables of
+// step tstep from the particle state.
+hipError_t launch_dem(const DomView* v, const void* dem_args, int32_t j, hipStream_t s);
+hipError_t launch_dem_tables(const DomView* v, const void* dem_args, hipStream_t s);
 
 // Scratch of the allocation-free moment read-out: a file-scope device array
 // of kNoAllocDoubles doubles (1 MiB) in k_fp64.hip, one copy per GPU, held

@@ -31,6 +31,8 @@ struct BlockParticles {
   int nc[kMaxParticles];
   double c[kMaxParticles][3];
   double v[kMaxParticles][3];
+  double w[kMaxParticles][3];  // angular velocity (coupled particles)
+  int cslot;                   // pose slot of the control points
   C cut2[kMaxParticles];    // squared support radius about the centre
   C shell2[kMaxParticles];  // squared radius about each control point
   alignas(16) C ctrl[4 * kLdsCtrl];
@@ -112,15 +114,16 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
     int lo[3], hi[3];
     node_range_box(V, n0, n1, lo, hi);
     bool keep = false;
-    double pc[3] = {0, 0, 0}, pv[3] = {0, 0, 0};
+    double pc[3] = {0, 0, 0}, pv[3] = {0, 0, 0}, pw[3] = {0, 0, 0};
     const auto P = gp(V.parts) + tid;
     if (tid < V.np) {
       if (from_table) {
-        const auto pt = gp((const double*)V.pose[pose_slot(t)]) + 6 * tid;
+        const auto pt = gp((const double*)V.pose[pose_slot(t)]) + kPoseRec * tid;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           pc[a] = pt[a];
           pv[a] = pt[3 + a];
+          pw[a] = pt[6 + a];
         }
       } else {
         particle_pose(V.parts[tid], t, pc, pv);
@@ -138,6 +141,7 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
       for (int a = 0; a < 3; ++a) {
         sp.c[r][a] = pc[a];
         sp.v[r][a] = pv[a];
+        sp.w[r][a] = pw[a];
       }
       sp.cut2[r] = (C)P->epscut2;
       sp.shell2[r] = (C)P->shell2;
@@ -146,11 +150,14 @@ __device__ __forceinline__ void cull_block(const DomView& V, uint32_t n0, uint32
       const bool fits = pre + nc <= kLdsCtrl;
       sp.ctrl_off[r] = fits ? pre : -1;
       if (fits) {
-        const auto src = gp(ctrl_of<C>(V)) + 4 * c0;
+        const auto src = gp(ctrl_of<C>(V, pose_slot(t))) + 4 * c0;
         for (int i = 0; i < 4 * nc; ++i) sp.ctrl[4 * pre + i] = src[i];
       }
     }
-    if (tid == 0) sp.cnt = __popcll(m);
+    if (tid == 0) {
+      sp.cnt = __popcll(m);
+      sp.cslot = pose_slot(t);
+    }
   }
   lds_barrier();
 }
@@ -215,15 +222,30 @@ __device__ __forceinline__ R eps_from_ctrl(PT ctrl, int nc, R dx, R dy, R dz, R 
 }
 
 template <typename R>
-__device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles<R>& sp, int k, const int nd[3]) {
+__device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles<R>& sp, int k, const int nd[3],
+                                      R* dl = nullptr) {
   const R dx = axis_disp<R>(!V.bc[0], V.n[0], nd[0], sp.c[k][0], (R)0.5);
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], nd[1], sp.c[k][1], (R)0.5);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], nd[2], sp.c[k][2], (R)0.5);
+  if (dl) {
+    dl[0] = dx;
+    dl[1] = dy;
+    dl[2] = dz;
+  }
   const R r2c = (dx * dx + dy * dy) + dz * dz;
   if (!(r2c < sp.cut2[k])) return (R)0;
   const int off = sp.ctrl_off[k];
   if (off >= 0) return eps_from_ctrl<R>(sp.ctrl + 4 * off, sp.nc[k], dx, dy, dz, sp.shell2[k]);
-  return eps_from_ctrl<R>(gp(ctrl_of<R>(V)) + 4 * sp.ctrl0[k], sp.nc[k], dx, dy, dz, sp.shell2[k]);
+  return eps_from_ctrl<R>(gp(ctrl_of<R>(V, sp.cslot)) + 4 * sp.ctrl0[k], sp.nc[k], dx, dy, dz, sp.shell2[k]);
+}
+
+// Velocity of a rigid body's surface at displacement dl from its centre:
+// v + w x dl (coupled particles; the node's solid velocity, Sec. 2.4.3).
+template <typename R>
+__device__ __forceinline__ void rigid_velocity(const R w[3], const R dl[3], R v[3]) {
+  v[0] = v[0] + (w[1] * dl[2] - w[2] * dl[1]);
+  v[1] = v[1] + (w[2] * dl[0] - w[0] * dl[2]);
+  v[2] = v[2] + (w[0] * dl[1] - w[1] * dl[0]);
 }
 
 // Solid fraction of particle p at node nd in a fluid block of step t, and the
@@ -231,7 +253,7 @@ __device__ __forceinline__ R node_eps(const DomView& V, const BlockParticles<R>&
 // and control points, all through wave-uniform scalar loads.
 template <typename R>
 __device__ __forceinline__ R node_eps_direct(const DomView& V, int ps, int p, const int nd[3], R v[3]) {
-  const auto pt = kp((const double*)V.pose[ps]) + 6 * p;
+  const auto pt = kp((const double*)V.pose[ps]) + kPoseRec * p;
   const auto P = kp(V.parts) + p;
   v[0] = (R)pt[3];
   v[1] = (R)pt[4];
@@ -241,7 +263,30 @@ __device__ __forceinline__ R node_eps_direct(const DomView& V, int ps, int p, co
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], nd[2], pt[2], (R)0.5);
   const R r2c = (dx * dx + dy * dy) + dz * dz;
   if (!(r2c < (R)P->epscut2)) return (R)0;
-  return eps_from_ctrl<R>(kp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz, (R)P->shell2);
+  return eps_from_ctrl<R>(kp(ctrl_of<R>(V, ps)) + 4 * P->ctrl0, P->nc, dx, dy, dz, (R)P->shell2);
+}
+
+// The same for a coupled particle: the solid velocity at the node includes
+// the rotation, v + w x dl, where the particle covers the node; dl is the
+// node centre's displacement from the particle's centre.
+template <typename R>
+__device__ __forceinline__ R node_eps_coupled(const DomView& V, int ps, int p, const int nd[3], R v[3], R dl[3]) {
+  const auto pt = kp((const double*)V.pose[ps]) + kPoseRec * p;
+  const auto P = kp(V.parts) + p;
+  v[0] = (R)pt[3];
+  v[1] = (R)pt[4];
+  v[2] = (R)pt[5];
+  dl[0] = axis_disp<R>(!V.bc[0], V.n[0], nd[0], pt[0], (R)0.5);
+  dl[1] = axis_disp<R>(!V.bc[1], V.n[1], nd[1], pt[1], (R)0.5);
+  dl[2] = axis_disp<R>(!V.bc[2], V.n[2], nd[2], pt[2], (R)0.5);
+  const R r2c = (dl[0] * dl[0] + dl[1] * dl[1]) + dl[2] * dl[2];
+  if (!(r2c < (R)P->epscut2)) return (R)0;
+  const R e = eps_from_ctrl<R>(kp(ctrl_of<R>(V, ps)) + 4 * P->ctrl0, P->nc, dl[0], dl[1], dl[2], (R)P->shell2);
+  if (e > (R)0) {
+    const R w[3] = {(R)pt[6], (R)pt[7], (R)pt[8]};
+    rigid_velocity<R>(w, dl, v);
+  }
+  return e;
 }
 
 // e_i . v with zero components contributing nothing (left to right over x, y, z).
@@ -331,8 +376,24 @@ __device__ __forceinline__ void upstream_of(const Nbr& b, bool& wall, int& delta
 // Nodes [lb BS, (lb + 1) BS) of a domain through step t in layout L (the
 // domain's layout at t's parity); nt selects non-temporal stores, dens the
 // store of the node densities as well.  Every thread of the block calls it.
-template <int P, int BS, int L>
-__device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens) {
+// Exchange of population i with the solid, bo = B Om_i, and its share of
+// the force on the solid: -e_i bo, summed per component in direction order.
+template <int i, typename R>
+__device__ __forceinline__ void solid_force(R bo, R& fx, R& fy, R& fz) {
+  if constexpr (kEx[i] == 1) fx = fx - bo; else if constexpr (kEx[i] == -1) fx = fx + bo;
+  if constexpr (kEy[i] == 1) fy = fy - bo; else if constexpr (kEy[i] == -1) fy = fy + bo;
+  if constexpr (kEz[i] == 1) fz = fz - bo; else if constexpr (kEz[i] == -1) fz = fz + bo;
+}
+
+// One node of a fluid block.  DEM: two-way coupled particles; the momentum
+// the solid term takes from the fluid at the node, -sum_i e_i B Om_i, is
+// shared among the coupled particles that cover it in proportion to their
+// solid fractions, and each share and its torque about the particle's centre
+// go into the block's accumulator dacc ([64][6], LDS) in fixed point, so
+// that the sums do not depend on the order of the nodes.
+template <int P, int BS, int L, bool DEM>
+__device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens,
+                                           unsigned long long* dacc) {
   using S = typename Store<P>::S;
   using R = typename Store<P>::C;
   constexpr bool exact = (P == P64);
@@ -403,6 +464,7 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   // whose support meets the block (cull word from the prologue), in index
   // order
   R es = (R)0, unx = (R)0, uny = (R)0, unz = (R)0;
+  unsigned long long cbits = 0ull;  // DEM: coupled particles that cover the node
   if (V.np > 0) {
     const int ps = pose_slot(t);
     unsigned long long bits = kp(V.fcull[ps])[lb];
@@ -410,7 +472,18 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
       const int p = __ffsll((long long)bits) - 1;
       bits &= bits - 1ull;
       R v[3];
-      const R e = node_eps_direct<R>(V, ps, p, nd, v);
+      R e;
+      if constexpr (DEM) {
+        if ((V.dem_mask >> p) & 1ull) {
+          R dl[3];
+          e = node_eps_coupled<R>(V, ps, p, nd, v, dl);
+          if (e > (R)0) cbits |= 1ull << p;
+        } else {
+          e = node_eps_direct<R>(V, ps, p, nd, v);
+        }
+      } else {
+        e = node_eps_direct<R>(V, ps, p, nd, v);
+      }
       es = es + e;
       unx = unx + e * v[0];
       uny = uny + e * v[1];
@@ -587,6 +660,7 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
   }
   // opposite pairs (i, i+1): each pair is relaxed, exchanged with the solid,
   // forced and stored before the next, so few registers stay live
+  R hfx = (R)0, hfy = (R)0, hfz = (R)0;  // DEM: force on the solid at the node
   unroll<0, 9>([&](auto pc) {
     constexpr int i = 1 + 2 * decltype(pc)::value;
     constexpr int o = i + 1;
@@ -603,8 +677,17 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
       if (solid) {
         const R fesi = feq(ic, edot_c<i, R>(usx, usy, usz), us15);
         const R feso = feq(oc, edot_c<o, R>(usx, usy, usz), us15);
-        vi = vi + B * ((f[o] - feo) - (f[i] - fesi));
-        vo = vo + B * ((f[i] - fei) - (f[o] - feso));
+        if constexpr (DEM) {
+          const R boi = B * ((f[o] - feo) - (f[i] - fesi));
+          const R boo = B * ((f[i] - fei) - (f[o] - feso));
+          vi = vi + boi;
+          vo = vo + boo;
+          solid_force<i, R>(boi, hfx, hfy, hfz);
+          solid_force<o, R>(boo, hfx, hfy, hfz);
+        } else {
+          vi = vi + B * ((f[o] - feo) - (f[i] - fesi));
+          vo = vo + B * ((f[i] - fei) - (f[o] - feso));
+        }
       }
       if (force) {
         vi = vi + Cf * guo(ic, eui);
@@ -633,8 +716,17 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
         const R eus = edot_c<i, R>(usx, usy, usz);
         const R fesi = feq(ic, eus, us15);
         const R feso = feq(oc, -eus, us15);
-        vi = vi + B * ((f[o] - feo) - (f[i] - fesi));
-        vo = vo + B * ((f[i] - fei) - (f[o] - feso));
+        if constexpr (DEM) {
+          const R boi = B * ((f[o] - feo) - (f[i] - fesi));
+          const R boo = B * ((f[i] - fei) - (f[o] - feso));
+          vi = vi + boi;
+          vo = vo + boo;
+          solid_force<i, R>(boi, hfx, hfy, hfz);
+          solid_force<o, R>(boo, hfx, hfy, hfz);
+        } else {
+          vi = vi + B * ((f[o] - feo) - (f[i] - fesi));
+          vo = vo + B * ((f[i] - fei) - (f[o] - feso));
+        }
       }
     }
     if (near_wall) {
@@ -658,6 +750,48 @@ __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint6
       for (int a = 0; a < 3; ++a) u[a] = v[a];
     }
     if (dens) gp((U*)V.rho)[id] = (U)rho;
+  }
+  if constexpr (DEM) {
+    // shares of the force and their torques, for each coupled particle
+    // covering the node (its solid fraction and displacement recomputed:
+    // the same arithmetic gives the same values)
+    const int ps = pose_slot(t);
+    unsigned long long bits = cbits;
+    while (bits) {
+      const int p = __ffsll((long long)bits) - 1;
+      bits &= bits - 1ull;
+      R v[3], dl[3];
+      const R e = node_eps_coupled<R>(V, ps, p, nd, v, dl);
+      const R share = e / es;
+      const R F[3] = {share * hfx, share * hfy, share * hfz};
+      const R T[3] = {dl[1] * F[2] - dl[2] * F[1], dl[2] * F[0] - dl[0] * F[2], dl[0] * F[1] - dl[1] * F[0]};
+      unsigned long long* a = dacc + 6 * p;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        atomicAdd(a + k, (unsigned long long)__double2ll_rn((double)F[k] * kForceFix));
+        atomicAdd(a + 3 + k, (unsigned long long)__double2ll_rn((double)T[k] * kForceFix));
+      }
+    }
+  }
+}
+
+template <int P, int BS, int L, bool DEM>
+__device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens,
+                                            unsigned long long* dacc) {
+  if constexpr (!DEM) {
+    fluid_node<P, BS, L, false>(V, lb, t, nt, dens, dacc);
+  } else {
+    for (int k = threadIdx.x; k < 6 * kMaxParticles; k += BS) dacc[k] = 0ull;
+    lds_barrier();
+    fluid_node<P, BS, L, true>(V, lb, t, nt, dens, dacc);
+    lds_barrier();
+    // the block's sums into the step's accumulator (two's-complement adds:
+    // exact, in any order)
+    const unsigned long long bits = V.np > 0 ? kp(V.fcull[pose_slot(t)])[lb] & V.dem_mask : 0ull;
+    for (int k = threadIdx.x; k < 6 * kMaxParticles; k += BS) {
+      const unsigned long long v = dacc[k];
+      if (((bits >> (k / 6)) & 1ull) && v != 0ull) atomicAdd(V.dem_acc + k, v);
+    }
   }
 }
 

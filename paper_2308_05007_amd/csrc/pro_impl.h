@@ -106,23 +106,42 @@ struct ProLds {
 // Each thread tests only the particles that meet the bounding box of its
 // prologue block's whole range of words.  Every thread of the block calls
 // it.
-__device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_t t, int bs, ProLds& L) {
+//
+// With coupled particles (`dem`) the poses are not known ahead: the particle
+// update after the fluid step of t - 1 has written P(t) into the pose table
+// (slot t mod 3 for the fluid of t, slot t - 1 mod 3 for the walkers of
+// t - 1) together with the filter spheres.  The prologue of t then builds
+// only the masks at P(t): the fluid cull words of slot t mod 3 and the
+// walker mask of slot t - 1 mod 3.
+__device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_t t, int bs, ProLds& L, bool dem) {
   const int ps = pose_slot(t);
+  const int psm = dem ? (ps == 0 ? 2 : ps - 1) : ps;  // slot of the walker mask
   const int tid = threadIdx.x;
   if (tid < V.np) {
     const DevParticle& P = V.parts[tid];
     double c0[3], v0[3], c1[3], v1[3];
-    particle_pose(P, t, c0, v0);
-    particle_pose(P, t + 1, c1, v1);
-    if (lb == 0) {
-      double* pt = V.pose[ps] + 6 * tid;
-      double* pn = V.pose[ps] + 6 * (V.np + tid);
+    if (dem) {
+      const auto pt = gp((const double*)V.pose[ps]) + kPoseRec * tid;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        c0[a] = pt[a];
+        c1[a] = pt[a];
+      }
+    } else {
+      particle_pose(P, t, c0, v0);
+      particle_pose(P, t + 1, c1, v1);
+    }
+    if (lb == 0 && !dem) {
+      double* pt = V.pose[ps] + kPoseRec * tid;
+      double* pn = V.pose[ps] + kPoseRec * (V.np + tid);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         pt[a] = c0[a];
         pt[3 + a] = v0[a];
+        pt[6 + a] = 0.0;
         pn[a] = c1[a];
         pn[3 + a] = v1[a];
+        pn[6 + a] = 0.0;
       }
       // the walkers' filter sphere at t+1, one 16-byte record
       using F4 = float __attribute__((ext_vector_type(4)));
@@ -179,7 +198,7 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
   if (V.nw == 0 || cb >= nmb) return;
   float lo[3], hi[3];
   mask_blocks_box(V, cb, cb, lo, hi);
-  V.mask[ps][cb] = box_bits(V, lo, hi, L.c1, L.rm2, L.cand_m);
+  V.mask[psm][cb] = box_bits(V, lo, hi, L.c1, L.rm2, L.cand_m);
 }
 
 }  // namespace rwmi

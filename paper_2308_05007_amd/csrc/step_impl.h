@@ -23,6 +23,7 @@ template <int P, int BS>
 union StepLds {
   WalkLds<typename Store<P>::O, BS> walk;
   ProLds pro;
+  unsigned long long dem[6 * kMaxParticles];  // fluid blocks with coupled particles
 };
 
 // IP: the domains of the launch stream their lattice in place (else: two
@@ -38,7 +39,9 @@ union StepLds {
 template <int P>
 constexpr int step_waves_per_eu() { return P == P64 ? 1 : RWMI_STEP_WAVES_PER_EU; }
 
-template <int P, int BS, bool IP>
+// DEM: the launch's domains have two-way coupled particles (the fluid
+// blocks accumulate the hydrodynamic force and torque on them).
+template <int P, int BS, bool IP, bool DEM = false>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<P>())))
 k_step(StepArgs a, const DomView* __restrict__ views, const int32_t* __restrict__ boff) {
   // views and boff (the same pointers as in a) are read-only in the launch:
@@ -53,12 +56,12 @@ k_step(StepArgs a, const DomView* __restrict__ views, const int32_t* __restrict_
   const int lb = idx - bo[d];
   const uint64_t t = step_of(V, a.j);
   if (role == kRoleWalk) walk_block<P, BS>(V, lb, t - 1, lds.walk);
-  else if (role == kRolePro) prologue_block(V, lb, t + 1, BS, lds.pro);
+  else if (role == kRolePro) prologue_block(V, lb, t + 1, BS, lds.pro, (a.flags & kFlagDem) != 0);
   else {
     const bool nt = (a.flags & kFlagNontemporal) != 0, dens = (a.flags & kFlagDensity) != 0;
-    if constexpr (!IP) fluid_block<P, BS, kTwoLattices>(V, (uint32_t)lb, t, nt, dens);
-    else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd>(V, (uint32_t)lb, t, nt, dens);
-    else fluid_block<P, BS, kInPlaceEven>(V, (uint32_t)lb, t, nt, dens);
+    if constexpr (!IP) fluid_block<P, BS, kTwoLattices, DEM>(V, (uint32_t)lb, t, nt, dens, lds.dem);
+    else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd, DEM>(V, (uint32_t)lb, t, nt, dens, lds.dem);
+    else fluid_block<P, BS, kInPlaceEven, DEM>(V, (uint32_t)lb, t, nt, dens, lds.dem);
   }
 }
 

@@ -33,6 +33,9 @@ constexpr int kFlagNontemporal = 2;  // non-temporal stores of f* and u
 // fluid step of a launch group: that step also writes the node densities,
 // which only read-outs use.
 constexpr int kFlagDensity = 4;
+// The domains have two-way coupled particles: the prologue builds the masks
+// from the poses the particle update wrote (step_impl.h, pro_impl.h).
+constexpr int kFlagDem = 8;
 
 struct DomView;
 

@@ -58,7 +58,7 @@ __device__ __forceinline__ int64_t mask_index(const DomView& V, const int c[3], 
 
 // Particle pose at t+1 from the pose table of step t.
 __device__ __forceinline__ gconst<double> pose_next(const DomView& V, int ps, int p) {
-  return gp((const double*)V.pose[ps]) + 6 * (V.np + p);
+  return gp((const double*)V.pose[ps]) + kPoseRec * (V.np + p);
 }
 
 template <typename R>
@@ -68,7 +68,7 @@ __device__ __forceinline__ R particle_M_at(const DomView& V, int ps, int p, cons
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
   const auto P = gp(V.parts) + p;
-  return metaball_value<R>(gp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz);
+  return metaball_value<R>(gp(ctrl_of<R>(V, next_slot(ps))) + 4 * P->ctrl0, P->nc, dx, dy, dz);
 }
 
 template <typename R>
@@ -78,7 +78,7 @@ __device__ __forceinline__ void particle_grad_at(const DomView& V, int ps, int p
   const R dy = axis_disp<R>(!V.bc[1], V.n[1], c[1], pc[1], x[1]);
   const R dz = axis_disp<R>(!V.bc[2], V.n[2], c[2], pc[2], x[2]);
   const auto P = gp(V.parts) + p;
-  metaball_grad<R>(gp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz, g);
+  metaball_grad<R>(gp(ctrl_of<R>(V, next_slot(ps))) + 4 * P->ctrl0, P->nc, dx, dy, dz, g);
 }
 
 // Is (c + x) within the sphere (c_p(t+1), rb_p + 1/2) of particle p, enlarged
@@ -135,7 +135,7 @@ __device__ __forceinline__ int inside_any(const DomView& V, int ps, const int c[
     const R r2 = (dx * dx + dy * dy) + dz * dz;
     const double mr = P->maskr;
     if (r2 >= (R)(mr * mr)) continue;
-    if (metaball_value<R>(gp(ctrl_of<R>(V)) + 4 * P->ctrl0, P->nc, dx, dy, dz) >= (R)1) return p;
+    if (metaball_value<R>(gp(ctrl_of<R>(V, next_slot(ps))) + 4 * P->ctrl0, P->nc, dx, dy, dz) >= (R)1) return p;
   }
   return -1;
 }

@@ -15,8 +15,10 @@ A configuration is a dict:
   domain:    n, bc (per axis "periodic" | "wall"), wall_lo / wall_hi (3 x 3
              wall velocities, row = axis), tau, F, D, rho0, u0, seed, precision
   particles: list of {b (nc x 3 offsets, world frame), k (nc), centre,
-             motion ("static" | "sinusoid" | "const_vel"), amp, period,
-             phase (in cycles), vel}
+             motion ("static" | "sinusoid" | "const_vel" | "coupled"), amp,
+             period, phase (in cycles), vel}
+  dem:       optional parameters of the two-way coupled particles
+             (coupling_params)
   walkers:   {kind ("uniform" | "gaussian" | "band" | "explicit"), n, centre,
              sigma, band=(axis, lo, hi), ref, max_attempts}
   steps:     number of coupled steps
@@ -317,6 +319,95 @@ def config_ensemble_member(name, b, k, realisation, shape_index=0, R=5.0, n_part
     return dict(name="ensemble_%s_%d" % (name, realisation),
                 domain=_domain(dims, ("periodic",) * 3, 0.8, (0, 0, 0), D, seed=100 + sd, precision=precision),
                 particles=parts,
+                walkers=dict(kind="band", n=int(n_walkers), band=(2, h - 0.5, h + 0.5),
+                             ref=(dims[0] / 2, dims[1] / 2, h)),
+                steps=int(steps))
+
+
+def coupling_params(nsub=100, drive_amp=1.6e-4, drive_period=5000.0, g=(0.0, 0.0, 0.0), rho_p=2.5, kn=200.0,
+                    kt=None, eta_n=None, eta_t=None, mu=0.3, Rs=0.5, coupling=1, mass_scale=None):
+    """Parameters of the two-way coupled particles (Eq. 4-11).  The drive is
+    Eq. 37 (4 cos(2 pi t / 5000) along x) in lattice units of the paper's
+    setup (dx = 1e-3 m, dt = 2e-4 s: 4 m/s^2 is 1.6e-4), one particle update
+    every 1/100 of a fluid step as in the paper's time steps; no gravity.
+    The contact constants are not given in the paper: k_n is chosen so that
+    a contact lasts many substeps (pi sqrt(m / k_n) > 10 steps for the
+    particles here), k_t = 2/7 k_n, damping at 10% of critical for a mass
+    mass_scale, friction 0.3."""
+    m = 1000.0 if mass_scale is None else float(mass_scale)
+    kt = 2.0 / 7.0 * kn if kt is None else kt
+    eta_n = 0.2 * math.sqrt(m * kn) if eta_n is None else eta_n
+    eta_t = 0.2 * math.sqrt(m * kt) if eta_t is None else eta_t
+    return dict(rho_p=rho_p, g=tuple(g), drive_amp=drive_amp, drive_period=drive_period, drive_dir=(1.0, 0.0, 0.0),
+                kn=kn, kt=kt, eta_n=eta_n, eta_t=eta_t, mu=mu, Rs=Rs, nsub=int(nsub), coupling=int(coupling))
+
+
+def config_coupled_small(seed=3, n=(26, 22, 30), bc=("periodic", "periodic", "periodic"), n_particles=3, R=3.0,
+                         n_walkers=3000, steps=40, precision="fp64", g=(0.0, 0.0, 0.0), speed=0.03, D=0.02,
+                         tau=0.8, nsub=20, drive_amp=1e-3, drive_period=60.0, gap=-3.0, with_prescribed=False):
+    """Small lattices of two-way coupled particles for element-by-element
+    parity: seeded metaballs with sqrt(sum k) = R (2-4 control points); the
+    first two on a line along x, their bounding spheres `gap` apart, launched
+    towards each other at `speed`; a third (when asked for) a quarter of the
+    box below them along z, launched at a random velocity; a strong, fast
+    drive so that the oscillation shows within a short run; walkers in a band
+    at mid-height.  With walls on z the third is launched towards the lower
+    wall.  (Bounding spheres overlap by 3 by default: the surfaces are about
+    a cell apart, close enough for the pair to meet although the fluid
+    slows them.)"""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for i in range(n_particles):
+        nc = int(rng.integers(2, 5))
+        b, k = metaball_shape(rng, nc, 0.35 * R, (0.5, 1.0))
+        shapes.append((b, k * (R * R / k.sum())))
+    ctr = np.array([v / 2.0 for v in n])
+    r0, r1 = bounding_radius(*shapes[0]), bounding_radius(*shapes[1])
+    half = 0.5 * (r0 + r1 + gap)
+    centres = [ctr + np.array([-half, 0.4, 0.0]), ctr + np.array([half, 0.0, 0.0])]
+    vels = [np.array([speed, 0.0, 0.0]), np.array([-speed, 0.0, 0.0])]
+    if n_particles > 2:
+        centres.append(ctr + np.array([0.3, -0.2, -n[2] / 4.0]))
+        vels.append(np.array([0.0, 0.0, -speed]) if bc[2] == "wall" else rng.uniform(-speed, speed, 3))
+    parts = [dict(b=b, k=k, centre=c, motion="coupled", vel=v) for (b, k), c, v in zip(shapes, centres, vels)]
+    if with_prescribed:
+        b, k = metaball_shape(rng, 2, 0.5, (0.5, 1.0))
+        parts.append(dict(b=b, k=k, centre=ctr + np.array([0.0, 0.0, n[2] / 4.0]), motion="sinusoid",
+                          amp=np.array([1.0, 0.0, 0.0]), period=50.0, phase=0.1))
+    h = n[2] / 2.0
+    return dict(name="coupled_small", domain=_domain(n, bc, tau, (0, 0, 0), D, seed=seed, precision=precision),
+                particles=parts,
+                dem=coupling_params(nsub=nsub, drive_amp=drive_amp, drive_period=drive_period, g=g, kn=50.0,
+                                    mass_scale=100.0),
+                walkers=dict(kind="band", n=n_walkers, band=(2, h - 3.0, h + 3.0), ref=tuple(ctr)),
+                steps=steps)
+
+
+def config_coupled_oscillator(R=5.0, n_particles=50, n_walkers=2_000_000, steps=5000, precision="fp32", seed=0,
+                              shape=None, D=0.002):
+    """The oscillator of Sec. 4 with two-way coupled particles: a periodic
+    box of 24R x 24R x 36R, n_particles seeded metaballs of radius about R
+    (or copies of `shape` = (b, k)), randomly rotated and placed without
+    overlap, at rest; every particle driven by Eq. 37 (coupling_params); the
+    solute band 24R x 24R x 1 at mid-height; tau 0.8."""
+    rng = np.random.default_rng(8000 + seed)
+    dims = (int(round(24 * R)), int(round(24 * R)), int(round(36 * R)))
+    shapes = []
+    for i in range(n_particles):
+        if shape is None:
+            b, k = metaball_shape(rng, int(rng.integers(2, 6)), 0.35 * R, (0.5, 1.0), rotate=True)
+            k = k * (R * R / k.sum())
+        else:
+            b = np.asarray(shape[0], float) @ _rotation(rng).T
+            k = np.asarray(shape[1], float)
+        shapes.append((np.ascontiguousarray(b), np.ascontiguousarray(k)))
+    centres = place_particles(rng, dims, shapes, 1.0, (False, False, False))
+    parts = [dict(b=b, k=k, centre=c, motion="coupled", vel=np.zeros(3)) for (b, k), c in zip(shapes, centres)]
+    m = 2.5 * 4.0 / 3.0 * math.pi * R ** 3
+    h = dims[2] / 2
+    return dict(name="coupled_oscillator_%d_%s" % (int(R), precision),
+                domain=_domain(dims, ("periodic",) * 3, 0.8, (0, 0, 0), D, seed=900 + seed, precision=precision),
+                particles=parts, dem=coupling_params(kn=200.0, mass_scale=m),
                 walkers=dict(kind="band", n=int(n_walkers), band=(2, h - 0.5, h + 0.5),
                              ref=(dims[0] / 2, dims[1] / 2, h)),
                 steps=int(steps))

@@ -29,6 +29,7 @@ Other workloads (own JSON line each, not the headline):
   --workload precision                                    all storage modes vs FP64
   --workload batch                                        64-simulation sweep
   --workload ensemble [--realisations 4 --radius 5]       shape sweep of Sec. 4 (D_alpha, Spearman)
+  --workload coupled [--radius 5 --precision fp32]        Sec. 4 oscillator, two-way coupled particles
   --workload copy [--lattice MiB]                         plain copy (HBM counter calibration)
   --workload serve [--rate 20 --duration 15]              Poisson request stream
 """
@@ -259,6 +260,67 @@ def bench_plain(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_coupled(args):
+    """The oscillator of Sec. 4 with two-way coupled particles (Eq. 4-11): 50
+    metaballs of radius R driven by Eq. 37 in a 24R x 24R x 36R box, 2e6
+    walkers in the band.  Wall clock over K steps through captured graphs
+    (MLUPS); then 32 steps with every launch timed on its own: the fused step
+    launch (fluid with the force sums, walkers), the particle update and the
+    prologue of the masks."""
+    from paper_2308_05007_amd import binding as B, workloads as W
+    import torch
+    prec = args.precision or "fp32"
+    R = args.radius or 5.0
+    cfg = W.config_coupled_oscillator(R=R, precision=prec, n_walkers=args.walkers or 2_000_000)
+    key = "coupled_oscillator_%d_%s" % (int(R), prec)
+    burnin = 500 if args.burnin is None else args.burnin
+    dom = B.build_domain(cfg, device=0)
+    dom.set("use_graph", 1)
+    dom.step(burnin + args.warmup)
+    dom.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dom.step(args.steps)
+    dom.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dom.set("use_graph", 0)
+    dom.set("timing", 1)
+    dom.kernel_times()
+    dom.coupling_times()
+    kt_steps = 32
+    dom.step(kt_steps)
+    dom.sync()
+    (ms_upd, n_upd), (ms_pro, n_pro) = dom.coupling_times()
+    ms_step, launches, fl, wl = dom.kernel_times()
+    mom = dom.moments()
+    states = [dom.particle_state(p) for p in range(len(cfg["particles"]))]
+    dom.close()
+    N = int(np.prod(cfg["domain"]["n"]))
+    nw = cfg["walkers"]["n"]
+    fb, wb = fluid_nodes(cfg) * fluid_bytes_per_node(prec), nw * walker_bytes_per_step(prec)
+    achieved = (fl * fb + wl * wb) / (ms_step / 1e3) / 1e9
+    vmax = max(float(np.abs(s["v"]).max()) for s in states)
+    out = {"metric": METRIC, "value": round(N * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec],
+           "data": "synthetic (seeded metaballs and walkers; no datasets)",
+           "config": {"workload": key, "lattice": list(cfg["domain"]["n"]), "particles": len(cfg["particles"]),
+                      "walkers": nw, "precision": prec, "substeps": cfg["dem"]["nsub"],
+                      "timed_from_step": burnin + args.warmup},
+           "walker_steps_per_s": round(nw * args.steps / dt, 1),
+           "per_launch_us": {"step (fluid + force sums, walkers)": round(ms_step * 1e3 / max(launches, 1), 2),
+                             "particle update": round(ms_upd * 1e3 / max(n_upd, 1), 2),
+                             "prologue (masks)": round(ms_pro * 1e3 / max(n_pro, 1), 2),
+                             "timed_steps": kt_steps},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "k_step with coupled particles (fluid with force sums, walkers)",
+                        "bytes_per_launch": fb + wb},
+           "max_particle_speed": vmax, "contact_misses": mom["contact_misses"], "counters": mom["counters"]}
+    print(json.dumps(out), flush=True)
+
+
 def bench_precision(args):
     """The oscillator in every storage mode against the FP64 GPU run."""
     from paper_2308_05007_amd import precision, workloads as W
@@ -302,7 +364,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="oscillator",
-                    choices=["oscillator", "channel", "precision", "batch", "ensemble", "serve", "copy"])
+                    choices=["oscillator", "channel", "precision", "batch", "ensemble", "coupled", "serve", "copy"])
     ap.add_argument("--lattice", type=int, default=None)
     ap.add_argument("--rate", type=float, default=None)
     ap.add_argument("--duration", type=float, default=None)
@@ -333,6 +395,8 @@ def main():
     elif args.workload == "batch":
         from paper_2308_05007_amd import batchbench
         batchbench.main(args)
+    elif args.workload == "coupled":
+        bench_coupled(args)
     elif args.workload == "ensemble":
         from paper_2308_05007_amd import ensemble
         ensemble.bench(args)

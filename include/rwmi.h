@@ -177,7 +177,7 @@ typedef struct {
   double eta_n, eta_t;       /*   normal and tangential damping (>= 0) */
   double mu;                 /*   friction coefficient (>= 0) */
   double dilation_radius;    /* R_s of the sphero-metaball contact (Eq. 9, 11) */
-  int32_t substeps;          /* particle substeps per fluid step (>= 1) */
+  int32_t substeps;          /* particle substeps per fluid step (1..1024) */
   int32_t coupling;          /* 1: the fluid's force and torque act on the particles */
 } rwmi_coupling_desc;
 
@@ -358,6 +358,14 @@ rwmi_status rwmi_debug_set(rwmi_domain* dom, int32_t key, int64_t value);
  * walkers, the last with walkers only. */
 rwmi_status rwmi_read_kernel_times(rwmi_domain* dom, double* ms, uint64_t* launches, uint64_t* fluid_steps,
                                    uint64_t* walker_steps);
+
+/* With coupled particles (rwmi_set_coupling) and RWMI_KEY_TIMING on, each
+ * launch of a step is timed on its own: the step launches go to the record
+ * above (one launch per window), the particle updates and the prologues
+ * that build the masks at the new poses to this one.  Synchronises, returns
+ * their total milliseconds and counts, then clears this record. */
+rwmi_status rwmi_read_coupling_times(rwmi_domain* dom, double* ms_update, uint64_t* n_update, double* ms_prologue,
+                                     uint64_t* n_prologue);
 
 /* Block until all work enqueued for the domain has finished. */
 rwmi_status rwmi_synchronize(rwmi_domain* dom);

@@ -20,7 +20,11 @@
  *              printed in the paper: both are readings.
  *   particles: metaball function and gradient (Eq. 3, Eq. 17), prescribed
  *              rigid motion (the oscillator of Sec. 4, Eq. 37 read as a
- *              displacement sinusoid), rigid surface velocity (Sec. 2.4.3).
+ *              displacement sinusoid), rigid surface velocity (Sec. 2.4.3);
+ *              or two-way coupled particles: Newton-Euler motion (Eq. 4)
+ *              under gravity, the drive of Eq. 37, the hydrodynamic force
+ *              and torque of the PSM momentum exchange and the contacts of
+ *              Eq. 5-11 (sphero-metaball pairs and walls).
  *   solute   : random-walk update (Eq. 2) with trilinear velocity
  *              interpolation (Sec. 2.4.1), walker/particle types I-IV
  *              (Sec. 2.4.2), binary search for the intersection (Algorithm 1),
@@ -82,6 +86,19 @@
  *                   ball.  How the point is chosen is a reading.
  *   dispersion fit  a linear variance series gives the closed-form K and
  *                   D_alpha; pure diffusion gives sigma^2 = 2 D t
+ *   coupled         (tests/test_oracle_dem.py) mass and inertia of a sphere
+ *   particles       (closed form) and of an asymmetric metaball (fine-grid
+ *                   indicator integral); the body stays where it was given;
+ *                   free fall and the drive as closed sums of symplectic
+ *                   Euler; elastic and damped head-on collisions (momentum,
+ *                   restitution of a linear spring-dashpot); static overlap
+ *                   m g / k_n on a wall and of two stacked spheres (exact
+ *                   closest points); sliding at mu g, then rolling at 5/7 v0;
+ *                   angular momentum of an oblique frictional collision;
+ *                   free precession of a symmetric body (first order);
+ *                   fluid + particle momentum conserved; Stokes torque on a
+ *                   spinning sphere within 10%; thread-count independent
+ *                   force sums
  */
 #include <math.h>
 #ifdef _OPENMP

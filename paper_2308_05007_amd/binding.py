@@ -111,6 +111,8 @@ SIGNATURES = {
     "rwmi_debug_set": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64]),
     "rwmi_read_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
                                          C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "rwmi_read_coupling_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
+                                           C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "rwmi_synchronize": (C.c_int, [C.c_void_p]),
     "rwmi_last_error": (C.c_char_p, [C.c_void_p]),
     "rwmi_batch_create": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -427,6 +429,13 @@ class Domain:
         ms, n, nf, nw = C.c_double(), C.c_uint64(), C.c_uint64(), C.c_uint64()
         self._ck(self.L.rwmi_read_kernel_times(self.h, C.byref(ms), C.byref(n), C.byref(nf), C.byref(nw)))
         return ms.value, int(n.value), int(nf.value), int(nw.value)
+
+    def coupling_times(self):
+        """(ms, count) of the particle updates and of the prologues timed
+        since the last call (coupled particles with timing on)."""
+        mu, nu, mp, npr = C.c_double(), C.c_uint64(), C.c_double(), C.c_uint64()
+        self._ck(self.L.rwmi_read_coupling_times(self.h, C.byref(mu), C.byref(nu), C.byref(mp), C.byref(npr)))
+        return (mu.value, int(nu.value)), (mp.value, int(npr.value))
 
 
 def build_domain(cfg, device=0, use_torch=True, seed_walkers=True):

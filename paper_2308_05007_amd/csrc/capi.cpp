@@ -100,6 +100,8 @@ struct rwmi_domain {
     uint32_t walkers;  // and launches that carried a walker step
   };
   std::vector<TimedWindow> evrec;
+  // coupled particles: timed particle updates (role 1) and prologues (role 2)
+  std::vector<std::pair<size_t, int>> evdem;
   // lazily allocated readback scratch
   uint32_t* occ = nullptr;
   uint32_t* prof = nullptr;  // walkers per layer (the longest axis)
@@ -375,10 +377,10 @@ bool sort_before(const rwmi_domain* d, uint32_t j, uint32_t n, bool capturing) {
 // `record`, HIP events bracket windows of timing_every consecutive step
 // launches (j >= 0); a window closes early before a regrouping and at the
 // end of the group, so it times step launches only.
-rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool capturing);
+rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool record, bool capturing);
 
 rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturing) {
-  if (d->dem) return enqueue_group_dem(d, n, capturing);
+  if (d->dem) return enqueue_group_dem(d, n, record, capturing);
   int b[kRoles];
   role_blocks(d, d->bs, b);
   hipStream_t A = d->stream;
@@ -434,11 +436,27 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturin
 // and fluid of t0 + j, which accumulates the hydrodynamic force), the
 // particle update of t0 + j (poses and control points of t0 + j + 1) and the
 // prologue of t0 + j + 1 (cull masks at those poses); then the walkers of
-// the last step.
-rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool capturing) {
+// the last step.  With `record`, an event pair brackets each launch: the
+// step launches as one-launch windows of the step record, the particle
+// updates and prologues in their own record.
+rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool record, bool capturing) {
   int b[kRoles];
   role_blocks(d, d->bs, b);
   hipStream_t A = d->stream;
+  size_t ev = 0;
+  auto open = [&]() -> rwmi_status {
+    if (!record) return RWMI_OK;
+    ev = d->evused;
+    hipEvent_t e0 = take_event(d), e1 = take_event(d);
+    if (!e0 || !e1) return fail(d, RWMI_EDEVICE, "hipEventCreate failed");
+    HIPCHK(d, hipEventRecord(e0, A));
+    return RWMI_OK;
+  };
+  auto close = [&]() -> rwmi_status {
+    if (!record) return RWMI_OK;
+    HIPCHK(d, hipEventRecord(d->evpool[ev + 1], A));
+    return RWMI_OK;
+  };
   for (int j = 0; j <= (int)n; ++j) {
     if (sort_before(d, (uint32_t)j, n, capturing)) {
       HIPCHK(d, rwmi::launch_sort(d->prec, d->dv, 0, d->hv.nw, d->sort, A));
@@ -454,14 +472,26 @@ rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool capturing) {
     a.flags = d->flags | rwmi::kFlagDem | (j == (int)n - 1 ? rwmi::kFlagDensity : 0);
     a.inplace = d->hv.inplace;
     a.j = j;
-    if (a.nb[kRoleWalk] + a.nb[kRoleFluid] > 0) HIPCHK(d, rwmi::launch_step(d->prec, 256, a, A));
+    if (a.nb[kRoleWalk] + a.nb[kRoleFluid] > 0) {
+      if (open() != RWMI_OK) return RWMI_EDEVICE;
+      HIPCHK(d, rwmi::launch_step(d->prec, 256, a, A));
+      if (close() != RWMI_OK) return RWMI_EDEVICE;
+      if (record)
+        d->evrec.push_back({ev, 1u, a.nb[kRoleFluid] > 0 ? 1u : 0u, a.nb[kRoleWalk] > 0 ? 1u : 0u});
+    }
     if (j == (int)n) break;
+    if (open() != RWMI_OK) return RWMI_EDEVICE;
     HIPCHK(d, rwmi::launch_dem(d->dv, d->dem_dev, j, A));
+    if (close() != RWMI_OK) return RWMI_EDEVICE;
+    if (record) d->evdem.push_back({ev, 1});
     a.nb[kRoleWalk] = 0;
     a.nb[kRolePro] = b[kRolePro];
     a.nb[kRoleFluid] = 0;
     a.flags = d->flags | rwmi::kFlagDem;
+    if (open() != RWMI_OK) return RWMI_EDEVICE;
     HIPCHK(d, rwmi::launch_step(d->prec, 256, a, A));
+    if (close() != RWMI_OK) return RWMI_EDEVICE;
+    if (record) d->evdem.push_back({ev, 2});
   }
   HIPCHK(d, rwmi::launch_advance(d->dv, 1, n, A));
   return RWMI_OK;
@@ -901,7 +931,8 @@ rwmi_status rwmi_set_coupling(rwmi_domain* d, const rwmi_coupling_desc* c) {
   if (d->dem) return fail(d, RWMI_ESTATE, "coupling already set up");
   if (d->particles_uploaded || d->seeded || d->stepped)
     return fail(d, RWMI_ESTATE, "set up the coupling after adding the particles, before seeding and stepping");
-  if (!(c->density > 0.0) || c->substeps < 1 || !(c->drive_period > 0.0) || !(c->dilation_radius > 0.0) ||
+  if (!(c->density > 0.0) || c->substeps < 1 || c->substeps > rwmi::kDemMaxSub || !(c->drive_period > 0.0) ||
+      !(c->dilation_radius > 0.0) ||
       !(c->kn > 0.0) || c->kt < 0.0 || c->eta_n < 0.0 || c->eta_t < 0.0 || c->mu < 0.0)
     return fail(d, RWMI_EINVAL, "coupling parameters out of range");
   const int np = (int)d->parts.size();
@@ -1342,7 +1373,30 @@ rwmi_status rwmi_read_kernel_times(rwmi_domain* d, double* ms, uint64_t* launche
     *walker_steps += r.walkers;
   }
   d->evrec.clear();
-  d->evused = 0;
+  if (d->evdem.empty()) d->evused = 0;
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_read_coupling_times(rwmi_domain* d, double* ms_update, uint64_t* n_update, double* ms_prologue,
+                                     uint64_t* n_prologue) {
+  if (!d || !ms_update || !n_update || !ms_prologue || !n_prologue) return fail(d, RWMI_EINVAL, "null argument");
+  HIPCHK(d, hipSetDevice(d->device));
+  HIPCHK(d, hipStreamSynchronize(d->stream));
+  *ms_update = *ms_prologue = 0.0;
+  *n_update = *n_prologue = 0;
+  for (auto& r : d->evdem) {
+    float t = 0.0f;
+    HIPCHK(d, hipEventElapsedTime(&t, d->evpool[r.first], d->evpool[r.first + 1]));
+    if (r.second == 1) {
+      *ms_update += t;
+      *n_update += 1;
+    } else {
+      *ms_prologue += t;
+      *n_prologue += 1;
+    }
+  }
+  d->evdem.clear();
+  if (d->evrec.empty()) d->evused = 0;
   return RWMI_OK;
 }
 

@@ -35,6 +35,8 @@ enum DemField { kDc = 0, kDv = 3, kDq = 6, kDL = 10, kDw = 13, kDFh = 16, kDTh =
                 kDIbinv = 32, kDcin = 41, kDrb = 42 };
 // Control points of all particles held in LDS by the particle update.
 constexpr int kDemMaxCtrl = 1024;
+// Substeps per fluid step (the drive's cosines of a step are tabulated in LDS).
+constexpr int kDemMaxSub = 1024;
 // Candidate partners of a step: bounding spheres within this margin at the
 // step's start.  Two particles that each move less than half of it over the
 // step cannot come into contact unnoticed (counter kDemSkin counts the
@@ -52,11 +54,21 @@ struct DemArgs {
   float* ctrlr_f[3];
 };
 
+// Slot k of a three-slot pointer table, selected without indexing (a
+// runtime index would force the caller's copy of the table to memory).
+template <typename T>
+__device__ __forceinline__ T* slot_ptr(T* const (&tab)[3], int k) {
+  return k == 0 ? tab[0] : (k == 1 ? tab[1] : tab[2]);
+}
+
 struct DemLds {
+  double cosv[kDemMaxSub];  // cos(2 pi tau_s / T) of the step's substeps
+  double wu[3][2][3];       // wall velocities
   double c[kMaxParticles][3], v[kMaxParticles][3], w[kMaxParticles][3];
   double rb[kMaxParticles], cin[kMaxParticles];
   int nc[kMaxParticles], c0[kMaxParticles];
-  double b[kDemMaxCtrl][3];  // offsets at the current orientation
+  double b[kDemMaxCtrl][3];   // offsets at the current orientation
+  double bb[kDemMaxCtrl][3];  // offsets in the body frame
   double k[kDemMaxCtrl];
 };
 
@@ -157,8 +169,15 @@ __device__ __forceinline__ bool dem_inner_point(const DemLds& S, int p, const do
   return true;
 }
 
+// Lattice extents and boundary kinds, held in registers by the particle
+// update (a global view would be reloaded after every store it cannot rule
+// out aliasing).
+struct DemGeom {
+  int n[3], bc[3];
+};
+
 // Minimum image of the displacement c_j - c_i on periodic axes.
-__device__ __forceinline__ void dem_disp(const DomView& V, const double ci[3], const double cj[3], double dc[3]) {
+__device__ __forceinline__ void dem_disp(const DemGeom& V, const double ci[3], const double cj[3], double dc[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     dc[a] = cj[a] - ci[a];
@@ -171,7 +190,7 @@ __device__ __forceinline__ void dem_disp(const DomView& V, const double ci[3], c
 
 // Contact of particles i < j (Eq. 6-9).  True with the contact point as an
 // offset from c_i, the normal from i's inner point to j's and the overlap.
-__device__ __forceinline__ bool dem_contact_pair(const DomView& V, const DemArgs& A, const DemLds& S, int i, int j,
+__device__ __forceinline__ bool dem_contact_pair(const DemGeom& V, const DemArgs& A, const DemLds& S, int i, int j,
                                                  double xcp[3], double n[3], double& delta) {
   double dc[3];
   dem_disp(V, S.c[i], S.c[j], dc);
@@ -222,7 +241,7 @@ __device__ __forceinline__ bool dem_contact_pair(const DomView& V, const DemArgs
 // Contact of particle i with the wall plane of axis ax, side `side` (Eq.
 // 10-11); the planes sit at 1 and n - 1 (halfway between the wall node and
 // the first fluid node).  n points from the particle to the wall.
-__device__ __forceinline__ bool dem_contact_wall(const DomView& V, const DemArgs& A, const DemLds& S, int i, int ax,
+__device__ __forceinline__ bool dem_contact_wall(const DemGeom& V, const DemArgs& A, const DemLds& S, int i, int ax,
                                                  int side, double xcp[3], double n[3], double& delta) {
   const double* ci = S.c[i];
   const double plane = side ? (double)(V.n[ax] - 1) : 1.0;
@@ -344,8 +363,26 @@ __device__ __forceinline__ void dem_omega(const double R[3][3], const double* Ib
 __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, uint64_t t, DemLds& S) {
   const int p = threadIdx.x;
   const int np = V.np;
+  const unsigned long long dmask = V.dem_mask;
+  DemGeom G;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    G.n[a] = V.n[a];
+    G.bc[a] = V.bc[a];
+  }
   const bool live = p < np;
-  const bool cp = live && ((V.dem_mask >> p) & 1ull);
+  const bool cp = live && ((dmask >> p) & 1ull);
+  // the drive of every substep of the step, in parallel
+  const double dt = 1.0 / (double)A.nsub;
+  for (int s = p; s < A.nsub; s += blockDim.x) {
+    const double tau = (double)t + (double)s * dt;
+    double ph = tau / A.drive_period;
+    ph = ph - floor(ph);
+    double sn, cs;
+    sincos_turns(ph, sn, cs);
+    S.cosv[s] = cs;
+  }
+  if (p < 18) S.wu[p / 6][(p / 3) & 1][p % 3] = V.wu[p / 6][(p / 3) & 1][p % 3];
   const DevParticle* P = live ? V.parts + p : nullptr;
   double* st = live ? A.state + (size_t)kDemState * p : nullptr;
   double c[3] = {0, 0, 0}, v[3] = {0, 0, 0}, q[4] = {1, 0, 0, 0}, L[3] = {0, 0, 0}, w[3] = {0, 0, 0};
@@ -379,10 +416,13 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     S.c0[p] = c0;
     S.rb[p] = cp ? st[kDrb] : P->rb;
     S.cin[p] = cp ? st[kDcin] : 1.0;
-    const double* src = A.ctrlr[sl];
+    const double* src = slot_ptr(A.ctrlr, sl);
     for (int i = 0; i < nc; ++i) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) S.b[c0 + i][a] = src[4 * (c0 + i) + a];
+      for (int a = 0; a < 3; ++a) {
+        S.b[c0 + i][a] = src[4 * (c0 + i) + a];
+        S.bb[c0 + i][a] = V.ctrl[4 * (c0 + i) + a];
+      }
       S.k[c0 + i] = src[4 * (c0 + i) + 3];
     }
 #pragma unroll
@@ -394,31 +434,36 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   }
   __syncthreads();
   // candidate partners of the step; the springs of every other pair are zero
-  unsigned long long nbr = 0ull;
+  // (xnz: the partners whose spring may be nonzero)
+  unsigned long long nbr = 0ull, xnz = 0ull;
   const double cstart[3] = {c[0], c[1], c[2]};
   if (cp) {
     for (int j = 0; j < np; ++j) {
-      if (j == p || !((V.dem_mask >> j) & 1ull)) continue;
+      if (j == p || !((dmask >> j) & 1ull)) continue;
       double dc[3];
-      dem_disp(V, S.c[p], S.c[j], dc);
+      dem_disp(G, S.c[p], S.c[j], dc);
       const double r2 = dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2];
       const double rr = (S.rb[p] + S.rb[j]) + kDemMargin;
-      if (r2 < rr * rr) nbr |= 1ull << j;
-      else {
-        double* x = A.xi + ((size_t)p * kMaxParticles + j) * 3;
+      double* x = A.xi + ((size_t)p * kMaxParticles + j) * 3;
+      const bool nz = x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0;
+      if (r2 < rr * rr) {
+        nbr |= 1ull << j;
+        if (nz) xnz |= 1ull << j;
+      } else if (nz) {
         x[0] = x[1] = x[2] = 0.0;
       }
     }
   }
-  const double dt = 1.0 / (double)A.nsub;
+  unsigned wnz = 0u;  // walls whose spring may be nonzero (bit 2 axis + side)
+  if (cp)
+    for (int k = 0; k < 6; ++k) {
+      const double* x = A.xiw + ((size_t)p * 6 + k) * 3;
+      if (x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0) wnz |= 1u << k;
+    }
   for (int s = 0; s < A.nsub; ++s) {
     double F[3], T[3];
     if (cp) {
-      const double tau = (double)t + (double)s * dt;
-      double ph = tau / A.drive_period;
-      ph = ph - floor(ph);
-      double sn, cs;
-      sincos_turns(ph, sn, cs);
+      const double cs = S.cosv[s];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         F[a] = (mass * A.g[a] + mass * ((A.drive_amp * cs) * A.drive_dir[a])) + Fh[a];
@@ -431,12 +476,15 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
         const int i0 = p < j ? p : j, i1 = p < j ? j : p;
         double* xi = A.xi + ((size_t)p * kMaxParticles + j) * 3;
         double xcp[3], n[3], del;
-        if (!dem_contact_pair(V, A, S, i0, i1, xcp, n, del)) {
-          xi[0] = xi[1] = xi[2] = 0.0;
+        if (!dem_contact_pair(G, A, S, i0, i1, xcp, n, del)) {
+          if ((xnz >> j) & 1ull) {
+            xi[0] = xi[1] = xi[2] = 0.0;
+            xnz &= ~(1ull << j);
+          }
           continue;
         }
         double dc[3], rj[3], wa[3], wb[3], vr[3], Fc[3];
-        dem_disp(V, S.c[i0], S.c[i1], dc);
+        dem_disp(G, S.c[i0], S.c[i1], dc);
 #pragma unroll
         for (int a = 0; a < 3; ++a) rj[a] = xcp[a] - dc[a];
         dem_cross(S.w[i0], xcp, wa);
@@ -447,11 +495,17 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
           const double vb = S.v[i1][a] + wb[a];
           vr[a] = vb - va;
         }
-        double xv[3] = {xi[0], xi[1], xi[2]};
+        double xv[3] = {0.0, 0.0, 0.0};
+        if ((xnz >> j) & 1ull) {
+          xv[0] = xi[0];
+          xv[1] = xi[1];
+          xv[2] = xi[2];
+        }
         dem_contact_force(A, n, del, vr, dt, xv, Fc);
         xi[0] = xv[0];
         xi[1] = xv[1];
         xi[2] = xv[2];
+        xnz |= 1ull << j;
         double tq[3];
         if (p == i1) {
           dem_cross(rj, Fc, tq);
@@ -470,24 +524,36 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
           }
         }
       }
+#pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        if (!V.bc[ax]) continue;
+        if (!G.bc[ax]) continue;
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
-          double* xi = A.xiw + ((size_t)p * 6 + 2 * ax + side) * 3;
+          const int k = 2 * ax + side;
+          double* xi = A.xiw + ((size_t)p * 6 + k) * 3;
           double xcp[3], n[3], del;
-          if (!dem_contact_wall(V, A, S, p, ax, side, xcp, n, del)) {
-            xi[0] = xi[1] = xi[2] = 0.0;
+          if (!dem_contact_wall(G, A, S, p, ax, side, xcp, n, del)) {
+            if ((wnz >> k) & 1u) {
+              xi[0] = xi[1] = xi[2] = 0.0;
+              wnz &= ~(1u << k);
+            }
             continue;
           }
           double wa[3], vr[3], Fc[3];
           dem_cross(S.w[p], xcp, wa);
 #pragma unroll
-          for (int a = 0; a < 3; ++a) vr[a] = V.wu[ax][side][a] - (S.v[p][a] + wa[a]);
-          double xv[3] = {xi[0], xi[1], xi[2]};
+          for (int a = 0; a < 3; ++a) vr[a] = S.wu[ax][side][a] - (S.v[p][a] + wa[a]);
+          double xv[3] = {0.0, 0.0, 0.0};
+          if ((wnz >> k) & 1u) {
+            xv[0] = xi[0];
+            xv[1] = xi[1];
+            xv[2] = xi[2];
+          }
           dem_contact_force(A, n, del, vr, dt, xv, Fc);
           xi[0] = xv[0];
           xi[1] = xv[1];
           xi[2] = xv[2];
+          wnz |= 1u << k;
           const double mF[3] = {-Fc[0], -Fc[1], -Fc[2]};
           double tq[3];
           dem_cross(xcp, mF, tq);
@@ -509,8 +575,8 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a)
-        if (!V.bc[a]) {
-          const double Ln = (double)V.n[a];
+        if (!G.bc[a]) {
+          const double Ln = (double)G.n[a];
           c[a] = c[a] - Ln * floor(c[a] / Ln);
         }
       double R[3][3];
@@ -531,7 +597,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
       dem_quat_R(q, R);
       const int c0 = S.c0[p];
       for (int i = 0; i < S.nc[p]; ++i) {
-        const double* bb = V.ctrl + 4 * (c0 + i);
+        const double* bb = S.bb[c0 + i];
 #pragma unroll
         for (int a = 0; a < 3; ++a) S.b[c0 + i][a] = (R[a][0] * bb[0] + R[a][1] * bb[1]) + R[a][2] * bb[2];
       }
@@ -565,13 +631,13 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     for (int a = 0; a < 4; ++a) st[kDq + a] = q[a];
     double d2 = 0.0;
     double dc[3];
-    dem_disp(V, cstart, c, dc);
+    dem_disp(G, cstart, c, dc);
 #pragma unroll
     for (int a = 0; a < 3; ++a) d2 = d2 + dc[a] * dc[a];
     if (d2 > 0.25 * kDemMargin * kDemMargin) counter_add(V.counters + kDemSkin, 1ull);
     const int c0 = S.c0[p];
-    double* dst = A.ctrlr[sn];
-    float* dstf = A.ctrlr_f[sn];
+    double* dst = slot_ptr(A.ctrlr, sn);
+    float* dstf = slot_ptr(A.ctrlr_f, sn);
     for (int i = 0; i < S.nc[p]; ++i) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -623,16 +689,18 @@ __device__ __forceinline__ void dem_tables(const DomView& V, const DemArgs& A, u
     const double q[4] = {st[kDq], st[kDq + 1], st[kDq + 2], st[kDq + 3]};
     dem_quat_R(q, R);
     const int c0 = P->ctrl0;
+    double* dst = slot_ptr(A.ctrlr, sl);
+    float* dstf = slot_ptr(A.ctrlr_f, sl);
     for (int i = 0; i < P->nc; ++i) {
       const double* bb = V.ctrl + 4 * (c0 + i);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const double x = (R[a][0] * bb[0] + R[a][1] * bb[1]) + R[a][2] * bb[2];
-        A.ctrlr[sl][4 * (c0 + i) + a] = x;
-        A.ctrlr_f[sl][4 * (c0 + i) + a] = (float)x;
+        dst[4 * (c0 + i) + a] = x;
+        dstf[4 * (c0 + i) + a] = (float)x;
       }
-      A.ctrlr[sl][4 * (c0 + i) + 3] = bb[3];
-      A.ctrlr_f[sl][4 * (c0 + i) + 3] = (float)bb[3];
+      dst[4 * (c0 + i) + 3] = bb[3];
+      dstf[4 * (c0 + i) + 3] = (float)bb[3];
     }
   } else {
     particle_pose(*P, t, pc, pv);

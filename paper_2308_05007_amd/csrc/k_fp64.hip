@@ -63,7 +63,8 @@ __global__ void __launch_bounds__(64) k_dem(const DomView* __restrict__ views, c
                                             int32_t j) {
   __shared__ DemLds S;
   const DomView& V = views[0];
-  dem_block(V, *da, step_of(V, j), S);
+  const DemArgs A = *da;  // parameters in registers for the whole update
+  dem_block(V, A, step_of(V, j), S);
 }
 
 __global__ void __launch_bounds__(64) k_dem_tables(const DomView* __restrict__ views, const DemArgs* __restrict__ da) {

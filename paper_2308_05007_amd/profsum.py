@@ -2,7 +2,7 @@
 with --kernel-trace) and of its counter runs (--pmc), as the markdown tables
 kept beside the benchmark's figures.
 
-    python -m paper_2308_05007_amd.profsum trace DB [--window REGEX N]
+    python -m paper_2308_05007_amd.profsum trace DB|TRACE.csv [--window REGEX N]
     python -m paper_2308_05007_amd.profsum pmc DB COUNTER REGEX N
 
 trace: per-kernel count, total, average, minimum and maximum duration over
@@ -22,6 +22,15 @@ import numpy as np
 
 
 def _rows(db):
+    """(name, start ns, end ns, grid size) of every dispatch, from a rocprofv3
+    database or its kernel-trace CSV (--output-format csv)."""
+    if db.endswith(".csv"):
+        import csv
+        with open(db) as fh:
+            rows = [(r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+                     int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+                    for r in csv.DictReader(fh)]
+        return sorted(rows, key=lambda r: r[1])
     c = sqlite3.connect(db)
     return list(c.execute("select name, start, end, grid_x * grid_y * grid_z from kernels order by start"))
 

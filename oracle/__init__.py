@@ -93,6 +93,12 @@ def lib():
         L.orc_set_dem.argtypes = [P, dp]
         L.orc_dem_state.argtypes = [P, C.c_int, dp]
         L.orc_dem_set_motion.argtypes = [P, C.c_int, dp, dp]
+        L.orc_set_ibb.restype = C.c_int
+        L.orc_set_ibb.argtypes = [P, C.c_int]
+        L.orc_ibb_ud.argtypes = [C.c_double, dp, dp, dp, dp]
+        L.orc_ibb_q.restype = C.c_double
+        L.orc_ibb_q.argtypes = [P, C.c_int, C.c_int64, ip, C.c_int, dp]
+        L.orc_get_smap.argtypes = [P, ip]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
         L.orc_dispersion_fit.restype = C.c_int
@@ -182,6 +188,21 @@ class Oracle:
         """Two-way coupling of the particles added with motion "coupled"
         (Eq. 4-11); call after adding the particles, before seeding."""
         self.L.orc_set_dem(self.h, dem_params(dem)) == 0 or _raise("oracle: bad coupling parameters")
+
+    def set_ibb(self, on=True):
+        """Interpolated bounce-back coupling (Eq. 23-27) instead of the
+        partially saturated cells; before the first step."""
+        self.L.orc_set_ibb(self.h, int(bool(on))) == 0 or _raise("oracle: the coupling is chosen before stepping")
+
+    def ibb_q(self, p, t, cell, o):
+        dlw = np.zeros(3)
+        q = self.L.orc_ibb_q(self.h, int(p), int(t), np.asarray(cell, np.int32), int(o), dlw)
+        return q, dlw
+
+    def smap(self):
+        out = np.empty(self.N, np.int32)
+        self.L.orc_get_smap(self.h, out)
+        return out.reshape(self.n[::-1])
 
     def dem_state(self, p):
         o = np.zeros(32)
@@ -368,6 +389,12 @@ def dispersion_fit(t, sigma2, two_r, u_slip, phi, i0=0):
 MOMENT_FIELDS = ("n_walkers", "sum", "sumsq", "mass", "momentum", "fluid_u", "particle_v", "solid_volume", "step")
 
 
+def ibb_ud(q, uf, uff, uw):
+    ud = np.zeros(3)
+    lib().orc_ibb_ud(float(q), _d(uf, 3), _d(uff, 3), _d(uw, 3), ud)
+    return ud
+
+
 def moments_record(m):
     """The 19-double moment record (orc_moments layout) of a moments dict."""
     r = np.zeros(19)
@@ -424,4 +451,6 @@ def build_domain(cfg):
         o.add_particle(p)
     if cfg.get("dem"):
         o.set_dem(cfg["dem"])
+    if cfg["domain"].get("coupling") == "ibb":
+        o.set_ibb(True)
     return o

@@ -290,6 +290,7 @@ typedef struct {
   double c[3], v[3], q[4], L[3], w[3];     /* state at the domain's time */
   double Fh[3], Th[3];                      /* hydrodynamic force and torque of the last fluid update */
   int64_t acc[6];                           /* their fixed-point sums */
+  int64_t acc_ibb[6];                       /* bounce-back coupling: sums of the last streaming */
 } OPart;
 
 typedef struct {
@@ -319,6 +320,11 @@ typedef struct {
   int nsub, coupling;
   double xi[ORC_MAXP][ORC_MAXP][3]; /* tangential springs of particle pairs (i < j) */
   double xiw[ORC_MAXP][6][3];       /* and of particle-wall contacts */
+  /* interpolated bounce-back coupling (Sec. 2.4.3, Eq. 23-27) instead of the
+   * partially saturated cells: node status (0 fluid, p + 1 inside particle
+   * p) at the poses of the current and of the previous fluid update */
+  int ibb;
+  int32_t *smap, *smap_prev;
 } orc_domain;
 
 static void dem_accumulate(orc_domain* d, const void* Pt, const int nd[3], const double* ep, double es,
@@ -388,6 +394,7 @@ void orc_destroy(orc_domain* d) {
   free(d->wall); free(d->wallu);
   for (int p = 0; p < d->np; p++) { free(d->P[p].b); free(d->P[p].k); free(d->P[p].wb[0]); free(d->P[p].wb[1]); }
   free(d->cell); free(d->img); free(d->off);
+  free(d->smap); free(d->smap_prev);
   free(d);
 }
 
@@ -633,7 +640,13 @@ static void collide_node_x(const orc_domain* d, const double f[19], double eps, 
   for (int a = 0; a < 3; a++) u_out[a] = u[a];
 }
 
+static void fluid_step_ibb(orc_domain* d, const Poses* Pt);
+
 static void fluid_step(orc_domain* d, const Poses* Pt) {
+  if (d->ibb) {
+    fluid_step_ibb(d, Pt);
+    return;
+  }
   const int64_t N = d->N;
   const int nx = d->n[0], ny = d->n[1], nz = d->n[2];
 #pragma omp parallel for schedule(static)
@@ -698,6 +711,218 @@ static void fluid_step(orc_domain* d, const Poses* Pt) {
       }
     }
   }
+}
+
+/* ------------------------------------------------ interpolated bounce-back */
+/* The paper's own fluid-particle rule (Sec. 2.4.3, Eq. 23-27), read for a
+ * pull-free collide-then-stream update:
+ *  - a node is solid when its centre is inside a particle (M_p >= 1, the
+ *    lowest index wins), else fluid; solid nodes do not collide, their
+ *    velocity is the particle's rigid velocity v + w x r and their density
+ *    rho0 (for the walkers and the averages);
+ *  - a node that was solid at the previous update and is fluid now is
+ *    refilled with f^eq(rho0, u_new), u_new the rigid velocity of the
+ *    particle that covered it (Eq. 27; the bounce-back refill of Eq. 26
+ *    needs populations a formerly solid node does not have);
+ *  - streaming after the collision at P(t): a fluid node x_f whose upstream
+ *    node x_f - e_i is solid receives Eq. 23, G_i = G+_{i'}(x_d) + 6 w rho_f
+ *    e_i . u_w, with Eq. 24 G+_{i'}(x_d) = f^eq_{i'}(rho_f, u_d) + the
+ *    non-equilibrium part of x_f's own post-collision population i', Eq. 25
+ *    for u_d, q the fraction of the link from x_f to the surface M = 1 (40
+ *    halvings of [0, 1]), u_w the rigid velocity at the surface point, u_ff
+ *    the velocity at x_f + e_i (u_f where that node is a wall or solid);
+ *  - the momentum exchange of each such link in its Galilean-invariant form,
+ *    (e_i' - u_w) G+_i'(x_f) - (e_i - u_w) G_i, with its torque about the
+ *    particle's centre, goes to a coupled particle; the particle update of
+ *    the next step uses it. */
+
+/* Lowest index of a particle whose M >= 1 at the centre of node nd, or -1. */
+static int solid_at(const orc_domain* d, const Poses* P, const int nd[3]) {
+  for (int p = 0; p < d->np; p++) {
+    const OPart* q = &d->P[p];
+    double dl[3];
+    for (int a = 0; a < 3; a++) dl[a] = rel(d, a, nd[a], P->c[p][a], 0.5);
+    double r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+    if (!(r2 < q->rb * q->rb)) continue;
+    if (mb_Mb(P->b[p], q->k, q->nc, dl) >= 1.0) return p;
+  }
+  return -1;
+}
+
+/* v + w x dl, the velocity of particle p's rigid body at offset dl. */
+static void rigid_vel(const Poses* P, int p, const double dl[3], double up[3]) {
+  const double* v = P->v[p];
+  const double* w = P->w[p];
+  up[0] = v[0] + (w[1] * dl[2] - w[2] * dl[1]);
+  up[1] = v[1] + (w[2] * dl[0] - w[0] * dl[2]);
+  up[2] = v[2] + (w[0] * dl[1] - w[1] * dl[0]);
+}
+
+/* Eq. 25: u_d from the velocities at x_f, x_ff and the wall point. */
+static void ibb_ud(double q, const double uf[3], const double uff[3], const double uw[3], double ud[3]) {
+  for (int a = 0; a < 3; a++) {
+    double u1 = q <= 0.5 ? (2.0 * q) * uf[a] + (1.0 - 2.0 * q) * uff[a]
+                         : ((1.0 - q) / q) * uf[a] + ((2.0 * q - 1.0) / q) * uw[a];
+    double u2 = ((1.0 - q) / (1.0 + q)) * uff[a] + ((2.0 * q) / (1.0 + q)) * uw[a];
+    ud[a] = u1 / 3.0 + (2.0 * u2) / 3.0;
+  }
+}
+
+/* q of the link from the centre of node nd along e_o into particle p: the
+ * surface M_p = 1 between q = 0 (M < 1, a fluid node) and q = 1 (M >= 1, a
+ * node inside p), by 40 halvings; dlw receives the surface point's offset
+ * from p's centre. */
+static double ibb_q(const orc_domain* d, const Poses* P, int p, const int nd[3], int o, double dlw[3]) {
+  const OPart* q = &d->P[p];
+  double d0[3];
+  for (int a = 0; a < 3; a++) d0[a] = rel(d, a, nd[a], P->c[p][a], 0.5);
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 40; it++) {
+    double m = 0.5 * (lo + hi);
+    double x[3];
+    for (int a = 0; a < 3; a++) x[a] = d0[a] + m * (double)EV[o][a];
+    if (mb_Mb(P->b[p], q->k, q->nc, x) >= 1.0) hi = m;
+    else lo = m;
+  }
+  double qq = 0.5 * (lo + hi);
+  for (int a = 0; a < 3; a++) dlw[a] = d0[a] + qq * (double)EV[o][a];
+  return qq;
+}
+
+static int64_t fix48(double x);
+
+static void fluid_step_ibb(orc_domain* d, const Poses* Pt) {
+  const int64_t N = d->N;
+  const int nx = d->n[0], ny = d->n[1];
+  int32_t* tmp = d->smap_prev;
+  d->smap_prev = d->smap;
+  d->smap = tmp;
+  int32_t* sm = d->smap;
+  const int32_t* sp = d->smap_prev;
+  /* collision at P(t) */
+#pragma omp parallel for schedule(static)
+  for (int64_t id = 0; id < N; id++) {
+    if (d->wall[id]) {
+      sm[id] = 0;
+      continue;
+    }
+    int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
+    int s = solid_at(d, Pt, nd);
+    sm[id] = s + 1;
+    if (s >= 0) {
+      double dl[3], up[3];
+      for (int a = 0; a < 3; a++) dl[a] = rel(d, a, nd[a], Pt->c[s][a], 0.5);
+      rigid_vel(Pt, s, dl, up);
+      d->rho[id] = d->rho0;
+      d->eps[id] = 1.0;
+      for (int a = 0; a < 3; a++) {
+        d->u[a * N + id] = up[a];
+        d->us[a * N + id] = up[a];
+      }
+      continue;
+    }
+    double f[19], out[19], rho, u[3];
+    const double zero[3] = {0.0, 0.0, 0.0};
+    if (sp[id] > 0) { /* uncovered since the last update: Eq. 27 */
+      int pp = sp[id] - 1;
+      double dl[3], un[3];
+      for (int a = 0; a < 3; a++) dl[a] = rel(d, a, nd[a], Pt->c[pp][a], 0.5);
+      rigid_vel(Pt, pp, dl, un);
+      for (int i = 0; i < 19; i++) f[i] = feq(i, d->rho0, un);
+    } else {
+      for (int i = 0; i < 19; i++) f[i] = d->f[i * N + id];
+    }
+    collide_node(d, f, 0.0, zero, out, &rho, u);
+    for (int i = 0; i < 19; i++) d->fs[i * N + id] = out[i];
+    d->rho[id] = rho;
+    d->eps[id] = 0.0;
+    for (int a = 0; a < 3; a++) {
+      d->u[a * N + id] = u[a];
+      d->us[a * N + id] = 0.0;
+    }
+  }
+  /* streaming with the boundary at P(t) */
+#pragma omp parallel for schedule(static)
+  for (int64_t id = 0; id < N; id++) {
+    if (d->wall[id] || sm[id] > 0) continue;
+    int nd[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
+    const double rf = d->rho[id];
+    const double uf[3] = {d->u[id], d->u[N + id], d->u[2 * N + id]};
+    for (int i = 0; i < 19; i++) {
+      int s3[3], f3[3];
+      for (int a = 0; a < 3; a++) {
+        s3[a] = nd[a] - EV[i][a];
+        if (s3[a] < 0) s3[a] += d->n[a];
+        if (s3[a] >= d->n[a]) s3[a] -= d->n[a];
+        f3[a] = nd[a] + EV[i][a];
+        if (f3[a] < 0) f3[a] += d->n[a];
+        if (f3[a] >= d->n[a]) f3[a] -= d->n[a];
+      }
+      int64_t sid = nidx(d, s3[0], s3[1], s3[2]);
+      const int o = opp(i);
+      if (d->wall[sid]) {
+        double uw[3] = {d->wallu[sid], d->wallu[N + sid], d->wallu[2 * N + sid]};
+        double term = ((6.0 * WT[i]) * rf) * edot(i, uw);
+        d->f[i * N + id] = d->fs[o * N + id] + term;
+      } else if (sm[sid] > 0) {
+        int p = sm[sid] - 1;
+        double dlw[3], uw[3], uff[3], ud[3];
+        double q = ibb_q(d, Pt, p, nd, o, dlw);
+        rigid_vel(Pt, p, dlw, uw);
+        int64_t fid = nidx(d, f3[0], f3[1], f3[2]);
+        for (int a = 0; a < 3; a++) uff[a] = (d->wall[fid] || sm[fid] > 0) ? uf[a] : d->u[a * N + fid];
+        ibb_ud(q, uf, uff, uw, ud);
+        double fso = d->fs[o * N + id];
+        double gneq = fso - feq(o, rf, uf);
+        double fi = (feq(o, rf, ud) + gneq) + ((6.0 * WT[o]) * rf) * edot(i, uw);
+        d->f[i * N + id] = fi;
+        if (d->P[p].motion == 3) {
+          double F[3];
+          for (int a = 0; a < 3; a++)
+            F[a] = ((double)EV[o][a] - uw[a]) * fso - ((double)EV[i][a] - uw[a]) * fi;
+          double T[3] = {dlw[1] * F[2] - dlw[2] * F[1], dlw[2] * F[0] - dlw[0] * F[2], dlw[0] * F[1] - dlw[1] * F[0]};
+          int64_t v[6] = {fix48(F[0]), fix48(F[1]), fix48(F[2]), fix48(T[0]), fix48(T[1]), fix48(T[2])};
+          for (int k = 0; k < 6; k++) {
+#pragma omp atomic
+            d->P[p].acc_ibb[k] += v[k];
+          }
+        }
+      } else {
+        d->f[i * N + id] = d->fs[i * N + sid];
+      }
+    }
+  }
+}
+
+/* Interpolated bounce-back instead of partially saturated cells; before the
+ * first step. */
+int orc_set_ibb(orc_domain* d, int on) {
+  if (d->t != 0) return -1;
+  d->ibb = on ? 1 : 0;
+  if (d->ibb && !d->smap) {
+    d->smap = (int32_t*)calloc(d->N, sizeof(int32_t));
+    d->smap_prev = (int32_t*)calloc(d->N, sizeof(int32_t));
+  }
+  return 0;
+}
+
+/* Eq. 25 alone (for tests). */
+void orc_ibb_ud(double q, const double uf[3], const double uff[3], const double uw[3], double ud[3]) {
+  ibb_ud(q, uf, uff, uw, ud);
+}
+
+/* q and the surface point of the link from node cell along e_o into particle
+ * p at step t (for tests). */
+double orc_ibb_q(const orc_domain* d, int p, int64_t t, const int cell[3], int o, double dlw[3]) {
+  Poses P;
+  all_poses(d, t, &P);
+  return ibb_q(d, &P, p, cell, o, dlw);
+}
+
+/* Node status of the last fluid update: 0 fluid, p + 1 inside particle p. */
+void orc_get_smap(const orc_domain* d, int32_t* out) {
+  if (d->smap) memcpy(out, d->smap, sizeof(int32_t) * d->N);
+  else memset(out, 0, sizeof(int32_t) * d->N);
 }
 
 /* ----------------------------------------------------------- walkers */
@@ -1479,6 +1704,13 @@ void orc_step(orc_domain* d, int nsteps) {
           Pt.b[p] = d->P[p].wb[1];
         }
     }
+    if (d->ibb && d->ndem > 0)
+      /* the exchange of the streaming that delivered f(t) drives the update t -> t+1 */
+      for (int p = 0; p < d->np; p++)
+        if (d->P[p].motion == 3) {
+          memcpy(d->P[p].acc, d->P[p].acc_ibb, sizeof(d->P[p].acc));
+          memset(d->P[p].acc_ibb, 0, sizeof(d->P[p].acc_ibb));
+        }
     fluid_step(d, &Pt);
     if (d->ndem > 0) dem_advance(d);
     all_poses(d, d->t + 1, &Pn);

@@ -225,6 +225,30 @@ rwmi_status rwmi_add_metaball_particle(rwmi_domain* dom, const rwmi_metaball_des
  * all; ESTATE: after seeding, stepping or a second call. */
 rwmi_status rwmi_set_coupling(rwmi_domain* dom, const rwmi_coupling_desc* c);
 
+/* Fluid-particle coupling of a domain (Sec. 2.4.3):
+ *   PSM  partially saturated cells (the default): the solid fraction of each
+ *        node (Eq. 3, Eq. 17) weights a Noble-Torczynski solid term in the
+ *        collision;
+ *   IBB  interpolated bounce-back, the paper's own rule (Eq. 23-27): a node
+ *        whose centre is inside a particle is solid (no collision, its
+ *        velocity the particle's v + w x r); a fluid node whose upstream
+ *        neighbour along e_i was solid at the previous update receives
+ *        Eq. 23 with Eq. 24 (equilibrium at u_d plus its own post-collision
+ *        non-equilibrium part) and Eq. 25 for u_d, q the fraction of the
+ *        link to the surface M = 1 (40 halvings); a node uncovered since the
+ *        previous update restarts from f^eq(rho0, u_new) (Eq. 27); the
+ *        force on coupled particles is the links' Galilean-invariant
+ *        momentum exchange, applied in the particle update of the next
+ *        step. */
+typedef enum { RWMI_COUPLING_PSM = 0, RWMI_COUPLING_IBB = 1 } rwmi_coupling;
+
+/* Choose the fluid-particle coupling (rwmi_coupling) before the first step.
+ * IBB switches the domain to two lattices and 256 threads per block, and
+ * keeps one status byte per node per step parity; such a domain cannot join
+ * a batch.  EINVAL for an unknown scheme; ESTATE after stepping or inside a
+ * batch. */
+rwmi_status rwmi_set_fluid_coupling(rwmi_domain* dom, int32_t scheme);
+
 /* State of coupled particle p after the last completed step, 32 doubles:
  * centre of mass c[3], velocity v[3], orientation quaternion q[4] (w, x, y,
  * z; body to world), angular momentum L[3], angular velocity w[3], the

@@ -95,6 +95,7 @@ SIGNATURES = {
     "rwmi_destroy_domain": (None, [C.c_void_p]),
     "rwmi_add_metaball_particle": (C.c_int, [C.c_void_p, C.POINTER(MetaballDesc), C.POINTER(C.c_int32)]),
     "rwmi_set_coupling": (C.c_int, [C.c_void_p, C.POINTER(CouplingDesc)]),
+    "rwmi_set_fluid_coupling": (C.c_int, [C.c_void_p, C.c_int32]),
     "rwmi_read_particle_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "rwmi_set_particle_motion": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "rwmi_seed_walkers": (C.c_int, [C.c_void_p, C.POINTER(SeedDesc), C.c_uint64, C.POINTER(C.c_uint64)]),
@@ -325,6 +326,11 @@ class Domain:
         c = coupling_desc(dem)
         self._ck(self.L.rwmi_set_coupling(self.h, C.byref(c)))
 
+    def set_fluid_coupling(self, scheme):
+        """"psm" (partially saturated cells) or "ibb" (interpolated
+        bounce-back, Eq. 23-27); before the first step."""
+        self._ck(self.L.rwmi_set_fluid_coupling(self.h, {"psm": 0, "ibb": 1}[scheme]))
+
     def particle_state(self, p):
         o = np.zeros(32)
         self._ck(self.L.rwmi_read_particle_state(self.h, int(p), o.ctypes.data_as(C.c_void_p)))
@@ -443,6 +449,8 @@ def build_domain(cfg, device=0, use_torch=True, seed_walkers=True):
     d = Domain(cfg["domain"], device=device, use_torch=use_torch)
     for p in cfg.get("particles", []):
         d.add_particle(p)
+    if cfg["domain"].get("coupling") == "ibb":
+        d.set_fluid_coupling("ibb")
     if cfg.get("dem"):
         d.set_coupling(cfg["dem"])
     if seed_walkers and cfg.get("walkers") and cfg["walkers"].get("n", 0) > 0:

@@ -242,6 +242,15 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
       if (V.bc[a] && (nd[a] == 0 || nd[a] == V.n[a] - 1)) wall = true;
     if (wall) continue;
     double es = 0.0, un[3] = {0.0, 0.0, 0.0};
+    if (V.ibb) {
+      // interpolated bounce-back: a node is solid or fluid; a solid node's
+      // stored velocity is its particle's rigid velocity
+      if (stepped && V.smap[(done - 1) & 1ull][id]) {
+        es = 1.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) un[a] = (double)uf[3 * id + a];
+      }
+    } else
     for (int k = 0; k < sp.cnt; ++k) {
       C dl[3];
       const double e = (double)node_eps<C>(V, sp, k, nd, dl);

@@ -379,6 +379,12 @@ bool sort_before(const rwmi_domain* d, uint32_t j, uint32_t n, bool capturing) {
 // end of the group, so it times step launches only.
 rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool record, bool capturing);
 
+// Flags of a domain's step launches: the caller's, plus the coupling's
+// (interpolated bounce-back reads every step's densities).
+int launch_flags(const rwmi_domain* d) {
+  return d->flags | (d->hv.ibb ? rwmi::kFlagIbb | rwmi::kFlagDensity : 0);
+}
+
 rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturing) {
   if (d->dem) return enqueue_group_dem(d, n, record, capturing);
   int b[kRoles];
@@ -405,7 +411,7 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturin
     a.nd = 1;
     launch_roles(b, j, n, a.nb);
     // the group's last fluid step also stores the densities for read-outs
-    a.flags = d->flags | (j == (int)n - 1 ? rwmi::kFlagDensity : 0);
+    a.flags = launch_flags(d) | (j == (int)n - 1 ? rwmi::kFlagDensity : 0);
     a.inplace = d->hv.inplace;
     a.j = j;
     if (a.nb[0] + a.nb[1] + a.nb[2] == 0) continue;
@@ -469,7 +475,7 @@ rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool record, bool capt
     a.nb[kRoleWalk] = j >= 1 ? b[kRoleWalk] : 0;
     a.nb[kRolePro] = 0;
     a.nb[kRoleFluid] = j < (int)n ? b[kRoleFluid] : 0;
-    a.flags = d->flags | rwmi::kFlagDem | (j == (int)n - 1 ? rwmi::kFlagDensity : 0);
+    a.flags = launch_flags(d) | rwmi::kFlagDem | (j == (int)n - 1 ? rwmi::kFlagDensity : 0);
     a.inplace = d->hv.inplace;
     a.j = j;
     if (a.nb[kRoleWalk] + a.nb[kRoleFluid] > 0) {
@@ -487,7 +493,7 @@ rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool record, bool capt
     a.nb[kRoleWalk] = 0;
     a.nb[kRolePro] = b[kRolePro];
     a.nb[kRoleFluid] = 0;
-    a.flags = d->flags | rwmi::kFlagDem;
+    a.flags = launch_flags(d) | rwmi::kFlagDem;
     if (open() != RWMI_OK) return RWMI_EDEVICE;
     HIPCHK(d, rwmi::launch_step(d->prec, 256, a, A));
     if (close() != RWMI_OK) return RWMI_EDEVICE;
@@ -1042,11 +1048,48 @@ rwmi_status rwmi_set_coupling(rwmi_domain* d, const rwmi_coupling_desc* c) {
   a.boff = d->dboff;
   a.nd = 1;
   a.nb[kRolePro] = b[kRolePro];
-  a.flags = d->flags | rwmi::kFlagDem;
+  a.flags = launch_flags(d) | rwmi::kFlagDem;
   a.inplace = d->hv.inplace;
   a.j = -1;
   HIPCHK(d, rwmi::launch_step(d->prec, 256, a, d->stream));
   HIPCHK(d, hipStreamSynchronize(d->stream));  // `state` lives on this stack frame
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_set_fluid_coupling(rwmi_domain* d, int32_t scheme) {
+  if (!d) return fail(d, RWMI_EINVAL, "null domain");
+  if (scheme != RWMI_COUPLING_PSM && scheme != RWMI_COUPLING_IBB) return fail(d, RWMI_EINVAL, "unknown coupling %d", scheme);
+  if (d->stepped || d->batch) return fail(d, RWMI_ESTATE, "the coupling is chosen before the first step");
+  HIPCHK(d, hipSetDevice(d->device));
+  rwmi_status st;
+  if (scheme == RWMI_COUPLING_IBB) {
+    if (d->hv.inplace && (st = rwmi_debug_set(d, RWMI_KEY_STREAMING, 1)) != RWMI_OK) return st;
+    if (!d->hv.smap[0]) {
+      uint8_t* sm;
+      if ((st = alloc_into(d, sm, 2 * (size_t)d->hv.N)) != RWMI_OK) return st;
+      HIPCHK(d, hipMemsetAsync(sm, 0, 2 * (size_t)d->hv.N, d->stream));
+      d->hv.smap[0] = sm;
+      d->hv.smap[1] = sm + d->hv.N;
+    }
+    d->bs = 256;
+  }
+  d->hv.ibb = scheme == RWMI_COUPLING_IBB ? 1 : 0;
+  drop_graph(d);
+  if ((st = upload_view(d)) != RWMI_OK || (st = upload_workmaps(d)) != RWMI_OK) return st;
+  if (d->dem) {  // the cull masks of the current step at this coupling's reach
+    int b[kRoles];
+    role_blocks(d, d->bs, b);
+    rwmi::StepArgs a{};
+    a.views = d->dv;
+    a.boff = d->dboff;
+    a.nd = 1;
+    a.nb[kRolePro] = b[kRolePro];
+    a.flags = launch_flags(d) | rwmi::kFlagDem;
+    a.inplace = d->hv.inplace;
+    a.j = -1;
+    HIPCHK(d, rwmi::launch_step(d->prec, 256, a, d->stream));
+  }
+  HIPCHK(d, hipStreamSynchronize(d->stream));
   return RWMI_OK;
 }
 
@@ -1309,7 +1352,8 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       return RWMI_OK;
     case RWMI_KEY_BLOCK:
       if (value != 128 && value != 256 && value != 512) return fail(d, RWMI_EINVAL, "block must be 128, 256 or 512");
-      if (d->dem && value != 256) return fail(d, RWMI_EINVAL, "domains with coupled particles step with 256 threads");
+      if ((d->dem || d->hv.ibb) && value != 256)
+        return fail(d, RWMI_EINVAL, "domains with coupled particles or bounce-back coupling step with 256 threads");
       d->bs = (int)value;
       drop_graph(d);
       // a batch holding it regroups it (if the batch launches members with
@@ -1330,6 +1374,7 @@ rwmi_status rwmi_debug_set(rwmi_domain* d, int32_t key, int64_t value) {
       if (value != 1 && value != 2) return fail(d, RWMI_EINVAL, "streaming must be 1 (two lattices) or 2 (in place)");
       if (d->stepped || d->batch) return fail(d, RWMI_ESTATE, "the streaming layout is chosen before the first step");
       const int ip = value == 2 ? 1 : 0;
+      if (ip && d->hv.ibb) return fail(d, RWMI_EINVAL, "bounce-back coupling streams between two lattices");
       if (ip == d->hv.inplace) return RWMI_OK;
       if (!ip && !d->hv.fB) {
         void* fB;
@@ -1618,7 +1663,8 @@ rwmi_status rwmi_batch_add(rwmi_batch* b, rwmi_domain* d) {
   if (d->batch) return bfail(b, RWMI_ESTATE, "domain already in a batch");
   if (d->device != b->device) return bfail(b, RWMI_EINVAL, "domain lives on another device");
   if (hipSetDevice(d->device) != hipSuccess) return bfail(b, RWMI_EDEVICE, "hipSetDevice failed");
-  if (d->dem) return bfail(b, RWMI_EINVAL, "domains with coupled particles are stepped alone");
+  if (d->dem || d->hv.ibb)
+    return bfail(b, RWMI_EINVAL, "domains with coupled particles or bounce-back coupling are stepped alone");
   if (finalize_particles(d) != RWMI_OK) return bfail(b, RWMI_EDEVICE, d->err.c_str());
   d->batch = b;
   b->members.push_back(d);

@@ -156,6 +156,10 @@ struct DomView {
   int32_t* winv;                  // slot of walker id w (inverse of wid; built for read-outs)
   unsigned long long* counters;   // kCounters
   uint32_t* occ;                  // occupancy per node
+  int32_t ibb;                    // interpolated bounce-back coupling instead of partially
+                                  // saturated cells (two lattices only)
+  uint8_t* smap[2];               // IBB: node status of the fluid update of step t in
+                                  // [t & 1]: 0 fluid, p + 1 inside particle p
   unsigned long long dem_mask;    // bit p: particle p moves by Newton-Euler (two-way coupled)
   unsigned long long* dem_acc;    // [np][6] hydrodynamic force and torque of the running
                                   // fluid step, two's-complement sums in units of 2^-48

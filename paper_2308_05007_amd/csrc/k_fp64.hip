@@ -36,6 +36,11 @@ hipError_t noalloc_scratch(double** ptr) {
 hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
   const unsigned g = (unsigned)step_grid(a.nb, (a.flags & kFlagXcd) != 0);
   if (g == 0) return hipSuccess;
+  if (a.flags & kFlagIbb) {  // bounce-back coupling: two lattices, 256 threads per block
+    if (a.flags & kFlagDem) k_step<P64, 256, false, true, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
+    else k_step<P64, 256, false, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
+    return hipGetLastError();
+  }
   if (a.flags & kFlagDem) {  // coupled particles: 256 threads per block
     if (a.inplace) k_step<P64, 256, true, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
     else k_step<P64, 256, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);

@@ -16,6 +16,11 @@ static void step_bs(int bs, unsigned g, const StepArgs& a, hipStream_t s) {
 
 template <int P>
 static void step_layout(int bs, unsigned g, const StepArgs& a, hipStream_t s) {
+  if (a.flags & kFlagIbb) {  // bounce-back coupling: two lattices, 256 threads per block
+    if (a.flags & kFlagDem) k_step<P, 256, false, true, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
+    else k_step<P, 256, false, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
+    return;
+  }
   if (a.flags & kFlagDem) {  // coupled particles: 256 threads per block
     if (a.inplace) k_step<P, 256, true, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
     else k_step<P, 256, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);

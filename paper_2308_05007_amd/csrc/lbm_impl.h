@@ -385,13 +385,164 @@ __device__ __forceinline__ void solid_force(R bo, R& fx, R& fy, R& fz) {
   if constexpr (kEz[i] == 1) fz = fz - bo; else if constexpr (kEz[i] == -1) fz = fz + bo;
 }
 
+// ---------------------------------------------- interpolated bounce-back
+// The paper's own coupling (Sec. 2.4.3, Eq. 23-27) in place of the partially
+// saturated cells.  A node is solid while its centre is inside a particle
+// (M_p >= 1, lowest index), else fluid; the status of step t's update is
+// kept in smap[t & 1].  Step t gathers, for a fluid node x_f whose upstream
+// node x_f - e_i was solid at the previous update (the populations it would
+// pull were never produced), the bounced population of Eq. 23-25 at the
+// geometry of that update; a node solid now stores its particle's rigid
+// velocity and skips the collision; a node uncovered since the previous
+// update starts from f^eq(rho0, u_new) (Eq. 27).
+
+// v + w x dl from a pose record.
+template <typename R, typename PT>
+__device__ __forceinline__ void rigid_at(PT pt, const R dl[3], R up[3]) {
+  up[0] = (R)pt[3];
+  up[1] = (R)pt[4];
+  up[2] = (R)pt[5];
+  const R w[3] = {(R)pt[6], (R)pt[7], (R)pt[8]};
+  rigid_velocity<R>(w, dl, up);
+}
+
+// Lowest particle among `bits` (index order) whose M >= 1 at the centre of
+// node nd at the pose of slot ps, or -1.
+template <typename R>
+__device__ __forceinline__ int solid_node(const DomView& V, int ps, unsigned long long bits, const int nd[3],
+                                          R dl[3]) {
+  while (bits) {
+    const int p = __ffsll((long long)bits) - 1;
+    bits &= bits - 1ull;
+    const auto pt = kp((const double*)V.pose[ps]) + kPoseRec * p;
+    const auto P = kp(V.parts) + p;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dl[a] = axis_disp<R>(!V.bc[a], V.n[a], nd[a], pt[a], (R)0.5);
+    const R r2 = (dl[0] * dl[0] + dl[1] * dl[1]) + dl[2] * dl[2];
+    const R rb = (R)P->rb;
+    if (!(r2 < rb * rb)) continue;
+    if (metaball_value<R>(kp(ctrl_of<R>(V, ps)) + 4 * P->ctrl0, P->nc, dl[0], dl[1], dl[2]) >= (R)1) return p;
+  }
+  return -1;
+}
+
+// f^eq of direction i (Eq. 13), in the stored form of precision P: the full
+// value (FP64) or its deviation from w_i rho0.
+template <int P>
+__device__ __forceinline__ typename Store<P>::C feq_stored(const DomView& V, int i, typename Store<P>::C rho,
+                                                           const typename Store<P>::C u[3]) {
+  using R = typename Store<P>::C;
+  const R eu = edot<R>(i, u[0], u[1], u[2]);
+  const R u15 = (R)1.5 * ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+  const R w = i == 0 ? weight<R>(0) : (i <= 6 ? weight<R>(1) : weight<R>(7));
+  if constexpr (P == P64) return (w * rho) * ((((R)1 + (R)3 * eu) + (R)4.5 * (eu * eu)) - u15);
+  else return w * ((rho - V.rho0_f) + rho * (eu * ((R)3 + (R)4.5 * eu) - u15));
+}
+
+// Eq. 23-25 for the link of fluid node id (coordinates nd) along e_i whose
+// upstream node lies in particle p at the previous update (step t - 1):
+// q from 40 halvings of [0, 1] for the surface M_p = 1 on the segment from
+// x_f towards the solid node; u_w the rigid velocity there; u_f, rho_f and
+// the fluid-side neighbour's u_ff (u_f where that node is a wall or solid)
+// from the update of t - 1; fso x_f's own post-collision population of the
+// opposite direction.  DEM: the link's momentum exchange in its
+// Galilean-invariant form, (e_o - u_w) fso - (e_i - u_w) f_i, and its torque
+// about the particle's centre go to the block's accumulator.  Not inlined:
+// boundary links are rare and the callers are unrolled over 18 directions.
+template <int P, bool DEM>
+__device__ __attribute__((noinline)) typename Store<P>::C ibb_link(const DomView& V, uint64_t t, uint32_t id,
+                                                                    int nx, int ny, int nz, int i, int p,
+                                                                    typename Store<P>::C fso,
+                                                                    unsigned long long* dacc) {
+  using R = typename Store<P>::C;
+  using U = typename Store<P>::U;
+  const int nd[3] = {nx, ny, nz};
+  const int o = opp_dir(i);
+  const int eo[3] = {kEx[o], kEy[o], kEz[o]};
+  const int ps = pose_slot(t - 1);
+  const auto pt = gp((const double*)V.pose[ps]) + kPoseRec * p;
+  const auto Pp = gp(V.parts) + p;
+  const auto ctrl = gp(ctrl_of<R>(V, ps)) + 4 * Pp->ctrl0;
+  const int nc = Pp->nc;
+  R d0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) d0[a] = axis_disp<R>(!V.bc[a], V.n[a], nd[a], pt[a], (R)0.5);
+  R lo = (R)0, hi = (R)1;
+  for (int it = 0; it < 40; ++it) {
+    const R m = (R)0.5 * (lo + hi);
+    const R x[3] = {d0[0] + m * (R)eo[0], d0[1] + m * (R)eo[1], d0[2] + m * (R)eo[2]};
+    if (metaball_value<R>(ctrl, nc, x[0], x[1], x[2]) >= (R)1) hi = m;
+    else lo = m;
+  }
+  const R q = (R)0.5 * (lo + hi);
+  const R dlw[3] = {d0[0] + q * (R)eo[0], d0[1] + q * (R)eo[1], d0[2] + q * (R)eo[2]};
+  R uw[3];
+  rigid_at<R>(pt, dlw, uw);
+  const auto up = gp((const U*)V.u[(t - 1) & 1ull]);
+  const R uf[3] = {(R)up[3ull * id], (R)up[3ull * id + 1], (R)up[3ull * id + 2]};
+  const R rf = (R)gp((const U*)V.rho)[id];
+  // x_ff = x_f + e_i
+  int ff[3] = {nd[0] + kEx[i], nd[1] + kEy[i], nd[2] + kEz[i]};
+  bool fwall = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int n = V.n[a];
+    if (V.bc[a]) {
+      if (ff[a] <= 0 || ff[a] >= n - 1) fwall = true;
+    } else {
+      ff[a] = ff[a] < 0 ? ff[a] + n : (ff[a] >= n ? ff[a] - n : ff[a]);
+    }
+  }
+  R uff[3] = {uf[0], uf[1], uf[2]};
+  if (!fwall) {
+    const uint32_t fid = (uint32_t)ff[0] + (uint32_t)V.n[0] * ((uint32_t)ff[1] + (uint32_t)V.n[1] * (uint32_t)ff[2]);
+    if (!gp(V.smap[(t - 1) & 1ull])[fid]) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) uff[a] = (R)up[3ull * fid + a];
+    }
+  }
+  R ud[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const R u1 = q <= (R)0.5 ? ((R)2 * q) * uf[a] + ((R)1 - (R)2 * q) * uff[a]
+                             : (((R)1 - q) / q) * uf[a] + (((R)2 * q - (R)1) / q) * uw[a];
+    const R u2 = (((R)1 - q) / ((R)1 + q)) * uff[a] + (((R)2 * q) / ((R)1 + q)) * uw[a];
+    ud[a] = u1 / (R)3 + ((R)2 * u2) / (R)3;
+  }
+  const R w = o <= 6 ? weight<R>(1) : weight<R>(7);
+  const R gneq = fso - feq_stored<P>(V, o, rf, uf);
+  const R fi = (feq_stored<P>(V, o, rf, ud) + gneq) + (((R)6 * w) * rf) * edot<R>(i, uw[0], uw[1], uw[2]);
+  if constexpr (DEM) {
+    if ((V.dem_mask >> p) & 1ull) {
+      // full populations for the exchange
+      R fs = fso, fn = fi;
+      if constexpr (P != P64) {
+        fs = fs + w * V.rho0_f;
+        fn = fn + w * V.rho0_f;
+      }
+      const R ei[3] = {(R)kEx[i], (R)kEy[i], (R)kEz[i]};
+      R F[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[a] = ((R)eo[a] - uw[a]) * fs - (ei[a] - uw[a]) * fn;
+      const R T[3] = {dlw[1] * F[2] - dlw[2] * F[1], dlw[2] * F[0] - dlw[0] * F[2], dlw[0] * F[1] - dlw[1] * F[0]};
+      unsigned long long* acc = dacc + 6 * p;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        atomicAdd(acc + k, (unsigned long long)__double2ll_rn((double)F[k] * kForceFix));
+        atomicAdd(acc + 3 + k, (unsigned long long)__double2ll_rn((double)T[k] * kForceFix));
+      }
+    }
+  }
+  return fi;
+}
+
 // One node of a fluid block.  DEM: two-way coupled particles; the momentum
 // the solid term takes from the fluid at the node, -sum_i e_i B Om_i, is
 // shared among the coupled particles that cover it in proportion to their
 // solid fractions, and each share and its torque about the particle's centre
 // go into the block's accumulator dacc ([64][6], LDS) in fixed point, so
 // that the sums do not depend on the order of the nodes.
-template <int P, int BS, int L, bool DEM>
+template <int P, int BS, int L, bool DEM, bool IBB>
 __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens,
                                            unsigned long long* dacc) {
   using S = typename Store<P>::S;
@@ -460,12 +611,68 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
   });
 
   if (!live) return;
+  if constexpr (IBB) {
+    static_assert(!inplace, "interpolated bounce-back streams between two lattices");
+    // links whose upstream node was solid at the previous update, for a node
+    // that was fluid then (a node solid then has no populations of its own:
+    // it is solid now or refilled below)
+    const unsigned long long bprev = V.np > 0 ? kp(V.fcull[pose_slot(t - 1)])[lb] : 0ull;
+    const uint8_t prev = bprev ? gp((const uint8_t*)V.smap[(t - 1) & 1ull])[id] : (uint8_t)0;
+    if (bprev && !prev) {
+      const auto smp = gp((const uint8_t*)V.smap[(t - 1) & 1ull]);
+      unroll<1, kQ>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        bool wall;
+        int delta;
+        upstream_of<i>(nb, wall, delta);
+        if (!wall) {
+          const uint8_t s = smp[(uint32_t)((int)id + delta)];
+          if (s) {
+            R fso;
+            const SR raw = src[(size_t)opp_dir(i) * FS + fnode(true, id)];
+            if constexpr (exact) fso = raw;
+            else fso = raw_in<S>(raw);
+            f[i] = ibb_link<P, DEM>(V, t, id, x, y, z, i, (int)s - 1, fso, dacc);
+          }
+        }
+      });
+    }
+    // the node's own status at P(t)
+    const int ps = pose_slot(t);
+    const unsigned long long bits = V.np > 0 ? kp(V.fcull[ps])[lb] : 0ull;
+    R dl[3];
+    const int sn = bits ? solid_node<R>(V, ps, bits, nd, dl) : -1;
+    gp(V.smap[t & 1ull])[id] = (uint8_t)(sn + 1);
+    if (sn >= 0) {
+      R up[3];
+      rigid_at<R>(kp((const double*)V.pose[ps]) + kPoseRec * sn, dl, up);
+      using U = typename Store<P>::U;
+      const auto u = gp((U*)V.u[t & 1ull]) + 3ull * (uint64_t)id;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) u[a] = (U)up[a];
+      gp((U*)V.rho)[id] = (U)V.rho0;
+      return;
+    }
+    if (prev) {  // uncovered since the previous update: Eq. 27
+      const int pp = (int)prev - 1;
+      const auto pt = kp((const double*)V.pose[ps]) + kPoseRec * pp;
+      R d[3], un[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) d[a] = axis_disp<R>(!V.bc[a], V.n[a], nd[a], pt[a], (R)0.5);
+      rigid_at<R>(pt, d, un);
+      R r0;
+      if constexpr (exact) r0 = V.rho0;
+      else r0 = V.rho0_f;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) f[i] = feq_stored<P>(V, i, r0, un);
+    }
+  }
   // ---- solid fraction and solid velocity of the node, over the particles
   // whose support meets the block (cull word from the prologue), in index
   // order
   R es = (R)0, unx = (R)0, uny = (R)0, unz = (R)0;
   unsigned long long cbits = 0ull;  // DEM: coupled particles that cover the node
-  if (V.np > 0) {
+  if (!IBB && V.np > 0) {
     const int ps = pose_slot(t);
     unsigned long long bits = kp(V.fcull[ps])[lb];
     while (bits) {
@@ -775,19 +982,22 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
   }
 }
 
-template <int P, int BS, int L, bool DEM>
+template <int P, int BS, int L, bool DEM, bool IBB = false>
 __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens,
                                             unsigned long long* dacc) {
   if constexpr (!DEM) {
-    fluid_node<P, BS, L, false>(V, lb, t, nt, dens, dacc);
+    fluid_node<P, BS, L, false, IBB>(V, lb, t, nt, dens, dacc);
   } else {
     for (int k = threadIdx.x; k < 6 * kMaxParticles; k += BS) dacc[k] = 0ull;
     lds_barrier();
-    fluid_node<P, BS, L, true>(V, lb, t, nt, dens, dacc);
+    fluid_node<P, BS, L, true, IBB>(V, lb, t, nt, dens, dacc);
     lds_barrier();
     // the block's sums into the step's accumulator (two's-complement adds:
-    // exact, in any order)
-    const unsigned long long bits = V.np > 0 ? kp(V.fcull[pose_slot(t)])[lb] & V.dem_mask : 0ull;
+    // exact, in any order); bounce-back links belong to the particles near
+    // the block at the previous update
+    unsigned long long bits = V.np > 0 ? kp(V.fcull[pose_slot(t)])[lb] : 0ull;
+    if (IBB && V.np > 0) bits = kp(V.fcull[pose_slot(t - 1)])[lb];
+    bits &= V.dem_mask;
     for (int k = threadIdx.x; k < 6 * kMaxParticles; k += BS) {
       const unsigned long long v = dacc[k];
       if (((bits >> (k / 6)) & 1ull) && v != 0ull) atomicAdd(V.dem_acc + k, v);
@@ -875,6 +1085,15 @@ __global__ void k_read_f(const DomView* __restrict__ views, int dom, double* __r
     else if (!odd) sidx = fidx(false, i, un, NN);
     else sidx = wall ? fidx(false, i, un, NN) : fidx(false, opp_dir(i), uu, NN);
     double v = (double)to_c(src[sidx]);
+    if (V.ibb && t > 0 && !wall && i > 0 && V.smap[(t - 1) & 1ull][up]) {
+      // interpolated bounce-back: what the next gather will take for this
+      // link (the value of a solid node, or of a node uncovered since, is
+      // not defined)
+      using C = typename Store<P>::C;
+      const C fso = to_c(src[fidx(true, opp_dir(i), un, NN)]);
+      v = (double)ibb_link<P, false>(V, t, un, nd[0], nd[1], nd[2], i, (int)V.smap[(t - 1) & 1ull][up] - 1, fso,
+                                     nullptr);
+    }
     if (P != P64) v = v + weight<double>(i) * V.rho0;
     out[(int64_t)i * V.N + id] = v;
   }

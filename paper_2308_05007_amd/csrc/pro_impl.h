@@ -155,7 +155,9 @@ __device__ __forceinline__ void prologue_block(const DomView& V, int lb, uint64_
       L.c0[tid][a] = (float)c0[a];
     }
     const float rm = (float)P.maskr + kCullMargin;
-    const float rc = (float)sqrt(P.epscut2) + kCullMargin;
+    // interpolated bounce-back: a node within rb + sqrt(2) can have a solid
+    // neighbour, so the fluid cull reaches rb + 2
+    const float rc = (V.ibb ? (float)P.rb + 2.0f : (float)sqrt(P.epscut2)) + kCullMargin;
     L.rm2[tid] = rm * rm;
     L.rc2[tid] = rc * rc;
   }

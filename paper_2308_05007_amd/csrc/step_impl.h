@@ -36,13 +36,14 @@ union StepLds {
 // collision: 8 (64 VGPRs) spills a few registers of the rarely taken paths
 // to scratch and measured at least as fast as 7 (72 VGPRs, no spill) or the
 // unconstrained 78.  FP64 needs about twice the registers: no constraint.
-template <int P>
-constexpr int step_waves_per_eu() { return P == P64 ? 1 : RWMI_STEP_WAVES_PER_EU; }
+template <int P, bool IBB = false>
+constexpr int step_waves_per_eu() { return (P == P64 || IBB) ? 1 : RWMI_STEP_WAVES_PER_EU; }
 
 // DEM: the launch's domains have two-way coupled particles (the fluid
-// blocks accumulate the hydrodynamic force and torque on them).
-template <int P, int BS, bool IP, bool DEM = false>
-__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<P>())))
+// blocks accumulate the hydrodynamic force and torque on them).  IBB: they
+// couple fluid and particles by interpolated bounce-back (two lattices).
+template <int P, int BS, bool IP, bool DEM = false, bool IBB = false>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<P, IBB>())))
 k_step(StepArgs a, const DomView* __restrict__ views, const int32_t* __restrict__ boff) {
   // views and boff (the same pointers as in a) are read-only in the launch:
   // as restrict parameters their wave-uniform reads compile to scalar loads
@@ -59,7 +60,7 @@ k_step(StepArgs a, const DomView* __restrict__ views, const int32_t* __restrict_
   else if (role == kRolePro) prologue_block(V, lb, t + 1, BS, lds.pro, (a.flags & kFlagDem) != 0);
   else {
     const bool nt = (a.flags & kFlagNontemporal) != 0, dens = (a.flags & kFlagDensity) != 0;
-    if constexpr (!IP) fluid_block<P, BS, kTwoLattices, DEM>(V, (uint32_t)lb, t, nt, dens, lds.dem);
+    if constexpr (!IP) fluid_block<P, BS, kTwoLattices, DEM, IBB>(V, (uint32_t)lb, t, nt, dens, lds.dem);
     else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd, DEM>(V, (uint32_t)lb, t, nt, dens, lds.dem);
     else fluid_block<P, BS, kInPlaceEven, DEM>(V, (uint32_t)lb, t, nt, dens, lds.dem);
   }

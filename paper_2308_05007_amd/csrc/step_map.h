@@ -36,6 +36,9 @@ constexpr int kFlagDensity = 4;
 // The domains have two-way coupled particles: the prologue builds the masks
 // from the poses the particle update wrote (step_impl.h, pro_impl.h).
 constexpr int kFlagDem = 8;
+// The domains couple fluid and particles by interpolated bounce-back
+// (lbm_impl.h); set by the host.
+constexpr int kFlagIbb = 16;
 
 struct DomView;
 

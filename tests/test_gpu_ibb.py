@@ -1,0 +1,142 @@
+"""Parity of the interpolated bounce-back coupling (Sec. 2.4.3, Eq. 23-27) on
+the GPU with the FP64 oracle, through the C ABI.
+
+FP64 runs the oracle's operation sequence (the link fraction q by the same
+40 halvings, Eq. 24-25 in the same order), so the node status, velocities,
+densities, walkers, counters and the distributions of every node that is
+fluid after the last update must match bit for bit (the populations of a
+solid node are not defined); with coupled particles so must the particle
+states, the force now being the links' Galilean-invariant exchange.  Cases:
+moving particles that cover and uncover nodes (refill, Eq. 27) with walls,
+moving walls and a body force on ragged lattices; a static particle in a
+driven flow; coupled particles that collide; 130 steps through a captured
+graph; the coupled oscillator of Sec. 4 at full size.  FP32 within bounds
+derived from the float rounding of the stored populations."""
+import numpy as np
+import pytest
+
+from paper_2308_05007_amd import workloads as W
+from test_gpu_parity import _fluid_mask, _pair, _same, compare
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("c", "v", "q", "L", "w", "Fh", "Th", "mass", "I")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2308_05007_amd import binding
+    binding.lib()
+    return binding
+
+
+def _ibb(cfg):
+    cfg["domain"]["coupling"] = "ibb"
+    return cfg
+
+
+def _compare_ibb(o, g, walkers=True):
+    compare(o, g, f=False, walkers=walkers)
+    sm = o.smap()
+    fluid = _fluid_mask(o.n, o.bc) & (sm == 0)
+    _same(g.distributions()[:, fluid], o.f()[:, fluid], "distributions of fluid nodes")
+    return sm
+
+
+def _states(o, g, cfg):
+    for p, part in enumerate(cfg["particles"]):
+        if part.get("motion") != "coupled":
+            continue
+        so, sg = o.dem_state(p), g.particle_state(p)
+        for k in KEYS:
+            _same(sg[k], so[k], "particle %d %s" % (p, k))
+
+
+CASES = {
+    "moving_walls_force": dict(n=(18, 15, 20), bc=("periodic", "wall", "periodic"), n_particles=3, spread=1.8,
+                               amp=1.5, period=60.0, steps=24, wall_u=((0, 0, 0, 0.02, 0, 0, 0, 0, 0),
+                                                                       (0, 0, 0, -0.01, 0, 0.005, 0, 0, 0))),
+    "periodic_sinusoid": dict(n=(20, 18, 22), bc=("periodic",) * 3, n_particles=4, spread=2.2, amp=1.5,
+                              period=50.0, steps=30, seed=11),
+    "const_vel_walls": dict(n=(17, 19, 16), bc=("wall", "periodic", "wall"), n_particles=2, spread=1.5,
+                            motion="const_vel", steps=20, seed=4, D=0.1),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_ibb_prescribed_fp64_bitwise(orc, B, case):
+    cfg = _ibb(W.config_tiny(n_walkers=800, **CASES[case]))
+    o, g = _pair(orc, B, cfg)
+    print("ibb case", case, flush=True)
+    steps = cfg["steps"]
+    o.step(steps // 2)
+    g.step(steps // 2)
+    g.sync()
+    sm1 = _compare_ibb(o, g)
+    o.step(steps - steps // 2)
+    g.step(steps - steps // 2)
+    g.sync()
+    sm2 = _compare_ibb(o, g)
+    assert (sm2 > 0).any()
+    if case != "const_vel_walls":
+        assert np.count_nonzero((sm1 > 0) != (sm2 > 0)) > 0  # nodes were covered and uncovered
+
+
+def test_ibb_static_particle_in_driven_flow(orc, B):
+    cfg = _ibb(W.config_plain_fp64())
+    cfg["walkers"]["n"] = 5000
+    o, g = _pair(orc, B, cfg)
+    o.step(40)
+    g.step(40)
+    g.sync()
+    _compare_ibb(o, g)
+
+
+def test_ibb_coupled_particles_fp64_bitwise(orc, B):
+    cfg = _ibb(W.config_coupled_small(seed=3))
+    o, g = _pair(orc, B, cfg)
+    o.step(20)
+    g.step(20)
+    g.sync()
+    _states(o, g, cfg)
+    o.step(20)
+    g.step(20)
+    g.sync()
+    _states(o, g, cfg)
+    _compare_ibb(o, g)
+    assert np.abs(o.dem_state(0)["Fh"]).max() > 0
+
+
+def test_ibb_graph_replay(orc, B):
+    cfg = _ibb(W.config_tiny(n=(16, 14, 18), bc=("periodic",) * 3, n_particles=3, spread=1.8, amp=1.5,
+                             period=60.0, n_walkers=500, seed=21))
+    o, g = _pair(orc, B, cfg)
+    g.set("use_graph", 1)
+    o.step(130)
+    g.step(130)
+    g.sync()
+    _compare_ibb(o, g)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ibb_coupled_oscillator_full_size(orc, B, precision):
+    """The coupled oscillator of Sec. 4 (120 x 120 x 180, 50 particles) with
+    bounce-back coupling for 3 steps: FP64 bit for bit; FP32 velocities
+    within 1e-6 + 1e-4 |u| of the oracle (a float population carries 2^-24
+    of its value, about 3e-9 for w rho0 = 1/18, and the velocity sums 19 of
+    them over rho), the particle forces within 2e-3 of their scale."""
+    cfg = _ibb(W.config_coupled_oscillator(R=5.0, n_walkers=100_000, steps=3, precision=precision))
+    o, g = _pair(orc, B, cfg)
+    o.step(3)
+    g.step(3)
+    g.sync()
+    if precision == "fp64":
+        _states(o, g, cfg)
+        compare(o, g, f=False)
+    else:
+        uo = o.fields()["u"]
+        ug, _ = g.velocity()
+        assert np.all(np.abs(ug - uo) <= 1e-6 + 1e-4 * np.abs(uo))
+        for p in range(len(cfg["particles"])):
+            so, sg = o.dem_state(p), g.particle_state(p)
+            assert np.abs(sg["Fh"] - so["Fh"]).max() <= 2e-3 * np.abs(so["Fh"]).max() + 1e-9, p

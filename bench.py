@@ -19,9 +19,11 @@ Prints one JSON line: MLUPS (all lattice nodes per second), walker-steps per
 second, the step kernel's achieved bandwidth in algorithmic bytes against
 the 8 TB/s HBM peak (HIP events recorded around windows of consecutive step
 launches that cover the timed region), the same workload with FP16 and BF16
-storage and the 128^3 FP32 channel (whose lattice is cache-resident) as
-secondary figures, and the FP64 CPU oracle timed on a bounded sample of the
-headline workload on this host, on all threads and on one.
+storage, with the paper's interpolated bounce-back coupling, the 128^3 FP32
+channel (whose lattice is cache-resident) and the Sec. 4 oscillator with
+two-way coupled particles (both couplings) as secondary figures, and the
+FP64 CPU oracle timed on a bounded sample of the headline workload on this
+host, on all threads and on one.
 
 Other workloads (own JSON line each, not the headline):
   --workload oscillator --precision fp16|bf16|fp32|fp64   256^3 oscillator alone
@@ -30,6 +32,8 @@ Other workloads (own JSON line each, not the headline):
   --workload batch                                        64-simulation sweep
   --workload ensemble [--realisations 4 --radius 5]       shape sweep of Sec. 4 (D_alpha, Spearman)
   --workload coupled [--radius 5 --precision fp32]        Sec. 4 oscillator, two-way coupled particles
+  --coupling ibb                                          interpolated bounce-back (Eq. 23-27) instead of
+                                                          partially saturated cells
   --workload copy [--lattice MiB]                         plain copy (HBM counter calibration)
   --workload serve [--rate 20 --duration 15]              Poisson request stream
 """
@@ -213,6 +217,9 @@ def bench_plain(args):
     else:
         cfg = W.config_channel(precision=prec)
         key = "channel_128_" + prec
+    if args.coupling == "ibb":
+        cfg["domain"]["coupling"] = "ibb"
+        key += "_ibb"
     steps, warmup = args.steps, args.warmup
     r = measure(cfg, key, steps, warmup, args.timing_every, burnin=burnin_steps(cfg, args))
     mom = r["mom"]
@@ -254,33 +261,50 @@ def bench_plain(args):
             "bytes_per_launch": q["bytes_launch"], "avg_launch_us": round(q["avg_us"], 2), "steps": 256, "warmup": 16,
             "timed_from_step": q["burnin"] + 16,
             "note": "the in-place lattice and velocity (160 MB + 48 MB) fit the 256 MB memory-side cache: not an HBM figure"}
+        # the paper's own coupling (interpolated bounce-back, Eq. 23-27) on the same workload
+        c4 = W.config_oscillator(precision="fp32", n_walkers=args.walkers or 10_000_000)
+        c4["domain"]["coupling"] = "ibb"
+        q = measure(c4, "oscillator_256_fp32_ibb", s2, w2, args.timing_every, burnin=burnin_steps(c4, args))
+        sec[q["key"]] = {"MLUPS": round(q["mlups"], 1), "walker_steps_per_s": round(q["wsps"], 1),
+                         "ms_per_step": round(q["dt"] / s2 * 1e3, 5), "roofline_frac": round(q["achieved"] / HBM_PEAK_GBS, 4),
+                         "bytes_per_launch": q["bytes_launch"], "avg_launch_us": round(q["avg_us"], 2),
+                         "steps": s2, "warmup": w2, "timed_from_step": q["burnin"] + w2,
+                         "note": "interpolated bounce-back instead of partially saturated cells; bytes credited "
+                                 "as for the headline (the density and status byte it also writes are not)"}
+        # two-way coupled particles (Eq. 4-11), both couplings
+        for cp in ("psm", "ibb"):
+            r = coupled_figures("fp32", 5.0, 2_000_000, 100, 5, 200, coupling=cp, timed_steps=16)
+            sec[r["key"]] = {"MLUPS": round(r["mlups"], 1), "walker_steps_per_s": round(r["wsps"], 1),
+                             "ms_per_step": round(r["dt"] / r["steps"] * 1e3, 5),
+                             "roofline_frac_step_launch": round(r["achieved"] / HBM_PEAK_GBS, 4),
+                             "per_launch_us": r["per_launch_us"], "steps": r["steps"], "warmup": 5,
+                             "timed_from_step": r["timed_from_step"], "particles": len(r["cfg"]["particles"]),
+                             "lattice": list(r["cfg"]["domain"]["n"]), "substeps": r["cfg"]["dem"]["nsub"]}
         out["secondary"] = sec
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, seconds=args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
-def bench_coupled(args):
+def coupled_figures(prec, R, n_walkers, steps, warmup, burnin, coupling="psm", timed_steps=32):
     """The oscillator of Sec. 4 with two-way coupled particles (Eq. 4-11): 50
-    metaballs of radius R driven by Eq. 37 in a 24R x 24R x 36R box, 2e6
-    walkers in the band.  Wall clock over K steps through captured graphs
-    (MLUPS); then 32 steps with every launch timed on its own: the fused step
-    launch (fluid with the force sums, walkers), the particle update and the
-    prologue of the masks."""
+    metaballs of radius R driven by Eq. 37 in a 24R x 24R x 36R box, walkers
+    in the band.  Wall clock over `steps` steps through captured graphs
+    (MLUPS); then `timed_steps` steps with every launch timed on its own: the
+    fused step launch (fluid with the force sums, walkers), the particle
+    update and the prologue of the masks."""
     from paper_2308_05007_amd import binding as B, workloads as W
     import torch
-    prec = args.precision or "fp32"
-    R = args.radius or 5.0
-    cfg = W.config_coupled_oscillator(R=R, precision=prec, n_walkers=args.walkers or 2_000_000)
-    key = "coupled_oscillator_%d_%s" % (int(R), prec)
-    burnin = 500 if args.burnin is None else args.burnin
+    cfg = W.config_coupled_oscillator(R=R, precision=prec, n_walkers=n_walkers)
+    if coupling == "ibb":
+        cfg["domain"]["coupling"] = "ibb"
     dom = B.build_domain(cfg, device=0)
     dom.set("use_graph", 1)
-    dom.step(burnin + args.warmup)
+    dom.step(burnin + warmup)
     dom.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    dom.step(args.steps)
+    dom.step(steps)
     dom.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -288,36 +312,48 @@ def bench_coupled(args):
     dom.set("timing", 1)
     dom.kernel_times()
     dom.coupling_times()
-    kt_steps = 32
-    dom.step(kt_steps)
+    dom.step(timed_steps)
     dom.sync()
     (ms_upd, n_upd), (ms_pro, n_pro) = dom.coupling_times()
     ms_step, launches, fl, wl = dom.kernel_times()
     mom = dom.moments()
-    states = [dom.particle_state(p) for p in range(len(cfg["particles"]))]
+    vmax = max(float(np.abs(dom.particle_state(p)["v"]).max()) for p in range(len(cfg["particles"])))
     dom.close()
     N = int(np.prod(cfg["domain"]["n"]))
     nw = cfg["walkers"]["n"]
     fb, wb = fluid_nodes(cfg) * fluid_bytes_per_node(prec), nw * walker_bytes_per_step(prec)
     achieved = (fl * fb + wl * wb) / (ms_step / 1e3) / 1e9
-    vmax = max(float(np.abs(s["v"]).max()) for s in states)
-    out = {"metric": METRIC, "value": round(N * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+    key = "coupled_oscillator_%d_%s%s" % (int(R), prec, "_ibb" if coupling == "ibb" else "")
+    return {"key": key, "cfg": cfg, "N": N, "nw": nw, "dt": dt, "steps": steps, "mlups": N * steps / dt / 1e6,
+            "wsps": nw * steps / dt, "achieved": achieved, "bytes_launch": fb + wb,
+            "per_launch_us": {"step (fluid + force sums, walkers)": round(ms_step * 1e3 / max(launches, 1), 2),
+                              "particle update": round(ms_upd * 1e3 / max(n_upd, 1), 2),
+                              "prologue (masks)": round(ms_pro * 1e3 / max(n_pro, 1), 2),
+                              "timed_steps": timed_steps},
+            "timed_from_step": burnin + warmup, "vmax": vmax, "mom": mom}
+
+
+def bench_coupled(args):
+    """One JSON line for the coupled oscillator (coupled_figures)."""
+    prec = args.precision or "fp32"
+    burnin = 500 if args.burnin is None else args.burnin
+    r = coupled_figures(prec, args.radius or 5.0, args.walkers or 2_000_000, args.steps, args.warmup, burnin,
+                        coupling=args.coupling)
+    cfg, mom = r["cfg"], r["mom"]
+    out = {"metric": METRIC, "value": round(r["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["dt"] / args.steps * 1e3, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec],
            "data": "synthetic (seeded metaballs and walkers; no datasets)",
-           "config": {"workload": key, "lattice": list(cfg["domain"]["n"]), "particles": len(cfg["particles"]),
-                      "walkers": nw, "precision": prec, "substeps": cfg["dem"]["nsub"],
-                      "timed_from_step": burnin + args.warmup},
-           "walker_steps_per_s": round(nw * args.steps / dt, 1),
-           "per_launch_us": {"step (fluid + force sums, walkers)": round(ms_step * 1e3 / max(launches, 1), 2),
-                             "particle update": round(ms_upd * 1e3 / max(n_upd, 1), 2),
-                             "prologue (masks)": round(ms_pro * 1e3 / max(n_pro, 1), 2),
-                             "timed_steps": kt_steps},
-           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+           "config": {"workload": r["key"], "lattice": list(cfg["domain"]["n"]), "particles": len(cfg["particles"]),
+                      "walkers": r["nw"], "precision": prec, "substeps": cfg["dem"]["nsub"],
+                      "coupling": args.coupling, "timed_from_step": r["timed_from_step"]},
+           "walker_steps_per_s": round(r["wsps"], 1),
+           "per_launch_us": r["per_launch_us"],
+           "roofline": {"bound": "hbm", "achieved": round(r["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(r["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
                         "kernel": "k_step with coupled particles (fluid with force sums, walkers)",
-                        "bytes_per_launch": fb + wb},
-           "max_particle_speed": vmax, "contact_misses": mom["contact_misses"], "counters": mom["counters"]}
+                        "bytes_per_launch": r["bytes_launch"]},
+           "max_particle_speed": r["vmax"], "contact_misses": mom["contact_misses"], "counters": mom["counters"]}
     print(json.dumps(out), flush=True)
 
 
@@ -378,6 +414,8 @@ def main():
     ap.add_argument("--radius", type=float, default=None, help="ensemble: particle radius R in lattice units")
     ap.add_argument("--burnin", type=int, default=None,
                     help="untimed steps before the warm-up (default: half of the workload's run)")
+    ap.add_argument("--coupling", default="psm", choices=["psm", "ibb"],
+                    help="fluid-particle coupling: partially saturated cells or interpolated bounce-back")
     ap.add_argument("--timing-every", type=int, default=32,
                     help="HIP events bracket windows of this many consecutive step launches")
     args = ap.parse_args()

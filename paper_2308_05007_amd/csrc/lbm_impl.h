@@ -441,16 +441,15 @@ __device__ __forceinline__ typename Store<P>::C feq_stored(const DomView& V, int
 
 // Eq. 23-25 for the link of fluid node id (coordinates nd) along e_i whose
 // upstream node lies in particle p at the previous update (step t - 1):
-// q from 40 halvings of [0, 1] for the surface M_p = 1 on the segment from
+// q from halvings of [0, 1] (40 in FP64, 24 in float) for the surface M_p = 1 on the segment from
 // x_f towards the solid node; u_w the rigid velocity there; u_f, rho_f and
 // the fluid-side neighbour's u_ff (u_f where that node is a wall or solid)
 // from the update of t - 1; fso x_f's own post-collision population of the
 // opposite direction.  DEM: the link's momentum exchange in its
 // Galilean-invariant form, (e_o - u_w) fso - (e_i - u_w) f_i, and its torque
-// about the particle's centre go to the block's accumulator.  Not inlined:
-// boundary links are rare and the callers are unrolled over 18 directions.
+// about the particle's centre go to the block's accumulator.
 template <int P, bool DEM>
-__device__ __attribute__((noinline)) typename Store<P>::C ibb_link(const DomView& V, uint64_t t, uint32_t id,
+__device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint64_t t, uint32_t id,
                                                                     int nx, int ny, int nz, int i, int p,
                                                                     typename Store<P>::C fso,
                                                                     unsigned long long* dacc) {
@@ -462,17 +461,33 @@ __device__ __attribute__((noinline)) typename Store<P>::C ibb_link(const DomView
   const int ps = pose_slot(t - 1);
   const auto pt = gp((const double*)V.pose[ps]) + kPoseRec * p;
   const auto Pp = gp(V.parts) + p;
-  const auto ctrl = gp(ctrl_of<R>(V, ps)) + 4 * Pp->ctrl0;
   const int nc = Pp->nc;
   R d0[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) d0[a] = axis_disp<R>(!V.bc[a], V.n[a], nd[a], pt[a], (R)0.5);
+  // halvings: 40 in FP64 (the oracle's), 24 in float (its resolution)
+  constexpr int kHalvings = P == P64 ? 40 : 24;
   R lo = (R)0, hi = (R)1;
-  for (int it = 0; it < 40; ++it) {
-    const R m = (R)0.5 * (lo + hi);
-    const R x[3] = {d0[0] + m * (R)eo[0], d0[1] + m * (R)eo[1], d0[2] + m * (R)eo[2]};
-    if (metaball_value<R>(ctrl, nc, x[0], x[1], x[2]) >= (R)1) hi = m;
-    else lo = m;
+  const int p0 = __builtin_amdgcn_readfirstlane(p);
+  if (__all(p == p0)) {
+    // one particle for the whole wave: its control points through the
+    // scalar cache (the bisection reads them kHalvings times)
+    const auto ctrl = kp(ctrl_of<R>(V, ps)) + 4 * kp(V.parts)[p0].ctrl0;
+    const int ncs = kp(V.parts)[p0].nc;
+    for (int it = 0; it < kHalvings; ++it) {
+      const R m = (R)0.5 * (lo + hi);
+      const R x[3] = {d0[0] + m * (R)eo[0], d0[1] + m * (R)eo[1], d0[2] + m * (R)eo[2]};
+      if (metaball_value<R>(ctrl, ncs, x[0], x[1], x[2]) >= (R)1) hi = m;
+      else lo = m;
+    }
+  } else {
+    const auto ctrl = gp(ctrl_of<R>(V, ps)) + 4 * Pp->ctrl0;
+    for (int it = 0; it < kHalvings; ++it) {
+      const R m = (R)0.5 * (lo + hi);
+      const R x[3] = {d0[0] + m * (R)eo[0], d0[1] + m * (R)eo[1], d0[2] + m * (R)eo[2]};
+      if (metaball_value<R>(ctrl, nc, x[0], x[1], x[2]) >= (R)1) hi = m;
+      else lo = m;
+    }
   }
   const R q = (R)0.5 * (lo + hi);
   const R dlw[3] = {d0[0] + q * (R)eo[0], d0[1] + q * (R)eo[1], d0[2] + q * (R)eo[2]};
@@ -620,6 +635,11 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
     const uint8_t prev = bprev ? gp((const uint8_t*)V.smap[(t - 1) & 1ull])[id] : (uint8_t)0;
     if (bprev && !prev) {
       const auto smp = gp((const uint8_t*)V.smap[(t - 1) & 1ull]);
+      // the directions whose upstream node was solid, then one pass over
+      // them (one copy of the link code; the lanes of a wave run their
+      // links side by side)
+      uint32_t lmask = 0u;
+      uint32_t lpart[5] = {0u, 0u, 0u, 0u, 0u};  // particle of each link, 6 bits x 5 per word
       unroll<1, kQ>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         bool wall;
@@ -628,14 +648,26 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
         if (!wall) {
           const uint8_t s = smp[(uint32_t)((int)id + delta)];
           if (s) {
-            R fso;
-            const SR raw = src[(size_t)opp_dir(i) * FS + fnode(true, id)];
-            if constexpr (exact) fso = raw;
-            else fso = raw_in<S>(raw);
-            f[i] = ibb_link<P, DEM>(V, t, id, x, y, z, i, (int)s - 1, fso, dacc);
+            lmask |= 1u << i;
+            lpart[i / 5] |= (uint32_t)(s - 1) << (6 * (i % 5));
           }
         }
       });
+      while (lmask) {
+        const int i = __ffs((int)lmask) - 1;
+        lmask &= lmask - 1u;
+        const uint32_t word = i < 5 ? lpart[0] : (i < 10 ? lpart[1] : (i < 15 ? lpart[2] : lpart[3]));
+        const int p = (int)((word >> (6 * (i % 5))) & 63u);
+        R fso;
+        const SR raw = src[(size_t)opp_dir(i) * FS + fnode(true, id)];
+        if constexpr (exact) fso = raw;
+        else fso = raw_in<S>(raw);
+        const R v = ibb_link<P, DEM>(V, t, id, x, y, z, i, p, fso, dacc);
+        unroll<1, kQ>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          if (j == i) f[j] = v;
+        });
+      }
     }
     // the node's own status at P(t)
     const int ps = pose_slot(t);

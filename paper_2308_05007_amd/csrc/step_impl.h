@@ -37,7 +37,7 @@ union StepLds {
 // to scratch and measured at least as fast as 7 (72 VGPRs, no spill) or the
 // unconstrained 78.  FP64 needs about twice the registers: no constraint.
 template <int P, bool IBB = false>
-constexpr int step_waves_per_eu() { return (P == P64 || IBB) ? 1 : RWMI_STEP_WAVES_PER_EU; }
+constexpr int step_waves_per_eu() { return P == P64 ? 1 : RWMI_STEP_WAVES_PER_EU; }
 
 // DEM: the launch's domains have two-way coupled particles (the fluid
 // blocks accumulate the hydrodynamic force and torque on them).  IBB: they

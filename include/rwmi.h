@@ -235,7 +235,7 @@ rwmi_status rwmi_set_coupling(rwmi_domain* dom, const rwmi_coupling_desc* c);
  *        neighbour along e_i was solid at the previous update receives
  *        Eq. 23 with Eq. 24 (equilibrium at u_d plus its own post-collision
  *        non-equilibrium part) and Eq. 25 for u_d, q the fraction of the
- *        link to the surface M = 1 (40 halvings); a node uncovered since the
+ *        link to the surface M = 1 (a bracketed regula falsi); a node uncovered since the
  *        previous update restarts from f^eq(rho0, u_new) (Eq. 27); the
  *        force on coupled particles is the links' Galilean-invariant
  *        momentum exchange, applied in the particle update of the next

@@ -728,8 +728,8 @@ static void fluid_step(orc_domain* d, const Poses* Pt) {
  *    node x_f - e_i is solid receives Eq. 23, G_i = G+_{i'}(x_d) + 6 w rho_f
  *    e_i . u_w, with Eq. 24 G+_{i'}(x_d) = f^eq_{i'}(rho_f, u_d) + the
  *    non-equilibrium part of x_f's own post-collision population i', Eq. 25
- *    for u_d, q the fraction of the link from x_f to the surface M = 1 (40
- *    halvings of [0, 1]), u_w the rigid velocity at the surface point, u_ff
+ *    for u_d, q the fraction of the link from x_f to the surface M = 1 (a
+ *    bracketed regula falsi, ibb_q), u_w the rigid velocity at the surface point, u_ff
  *    the velocity at x_f + e_i (u_f where that node is a wall or solid);
  *  - the momentum exchange of each such link in its Galilean-invariant form,
  *    (e_i' - u_w) G+_i'(x_f) - (e_i - u_w) G_i, with its torque about the
@@ -768,23 +768,43 @@ static void ibb_ud(double q, const double uf[3], const double uff[3], const doub
   }
 }
 
-/* q of the link from the centre of node nd along e_o into particle p: the
- * surface M_p = 1 between q = 0 (M < 1, a fluid node) and q = 1 (M >= 1, a
- * node inside p), by 40 halvings; dlw receives the surface point's offset
- * from p's centre. */
-static double ibb_q(const orc_domain* d, const Poses* P, int p, const int nd[3], int o, double dlw[3]) {
+/* 1 - M^(-1/2) at fraction s of the link from offset d0 along e_o: the
+ * distance-like field whose zero is the surface M = 1 (nearly linear along
+ * a link, exactly so for a sphere seen radially). */
+static double ibb_phi(const orc_domain* d, const Poses* P, int p, const double d0[3], int o, double s) {
   const OPart* q = &d->P[p];
+  double x[3];
+  for (int a = 0; a < 3; a++) x[a] = d0[a] + s * (double)EV[o][a];
+  return 1.0 - 1.0 / sqrt(mb_Mb(P->b[p], q->k, q->nc, x));
+}
+
+/* q of the link from the centre of node nd along e_o into particle p: the
+ * root of 1 - M^(-1/2) between q = 0 (M < 1, a fluid node) and q = 1
+ * (M >= 1, a node inside p), by the Illinois variant of regula falsi, ten
+ * steps or until the field is exactly zero (the bracket always holds a
+ * sign change); dlw receives the surface point's offset from p's centre. */
+static double ibb_q(const orc_domain* d, const Poses* P, int p, const int nd[3], int o, double dlw[3]) {
   double d0[3];
   for (int a = 0; a < 3; a++) d0[a] = rel(d, a, nd[a], P->c[p][a], 0.5);
-  double lo = 0.0, hi = 1.0;
-  for (int it = 0; it < 40; it++) {
-    double m = 0.5 * (lo + hi);
-    double x[3];
-    for (int a = 0; a < 3; a++) x[a] = d0[a] + m * (double)EV[o][a];
-    if (mb_Mb(P->b[p], q->k, q->nc, x) >= 1.0) hi = m;
-    else lo = m;
+  double a0 = 0.0, b0 = 1.0;
+  double fa = ibb_phi(d, P, p, d0, o, a0), fb = ibb_phi(d, P, p, d0, o, b0);
+  for (int it = 0; it < 10; it++) {
+    if (fb == fa) break;
+    double c = b0 - fb * ((b0 - a0) / (fb - fa));
+    double fc = ibb_phi(d, P, p, d0, o, c);
+    if (fc == 0.0) {
+      b0 = c;
+      break;
+    }
+    if ((fc < 0.0) == (fb < 0.0)) fa = 0.5 * fa;
+    else {
+      a0 = b0;
+      fa = fb;
+    }
+    b0 = c;
+    fb = fc;
   }
-  double qq = 0.5 * (lo + hi);
+  double qq = b0;
   for (int a = 0; a < 3; a++) dlw[a] = d0[a] + qq * (double)EV[o][a];
   return qq;
 }

@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(kRedThreads) k_mom_nodes(const DomView* __rest
     if (V.ibb) {
       // interpolated bounce-back: a node is solid or fluid; a solid node's
       // stored velocity is its particle's rigid velocity
-      if (stepped && V.smap[(done - 1) & 1ull][id]) {
+      if (stepped && (V.smap[(done - 1) & 1ull][id] & kSolidBits)) {
         es = 1.0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) un[a] = (double)uf[3 * id + a];

@@ -279,6 +279,10 @@ rwmi_status finalize_particles(rwmi_domain* d) {
     r.epscut2 = (r.rb + 0.75) * (r.rb + 0.75);
     r.shell2 = (std::sqrt(K) + 0.75) * (std::sqrt(K) + 0.75);
     r.maskr = r.rb + 0.5;
+    double kmin = q.k[0];
+    for (int i = 1; i < nc; ++i) kmin = std::min(kmin, q.k[i]);
+    r.cnear = (std::sqrt(kmin) / (std::sqrt(kmin) + rwmi::kNearReach)) *
+              (std::sqrt(kmin) / (std::sqrt(kmin) + rwmi::kNearReach));
     for (int a = 0; a < 3; ++a) {
       r.c0[a] = q.c0[a];
       r.amp[a] = q.amp[a];

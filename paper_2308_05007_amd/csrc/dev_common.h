@@ -20,6 +20,23 @@ constexpr int kEx[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0,
 constexpr int kEy[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int kEz[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 __host__ __device__ constexpr int opp_dir(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// Component a of e_i for a direction known only at run time, from the table
+// packed two bits per direction into a constant (0, 1 or 2 for -1): indexing
+// the constexpr arrays at run time would make the kernel copy them to
+// per-lane scratch memory.
+constexpr uint64_t pack_dirs(const int (&e)[kQ]) {
+  uint64_t b = 0;
+  for (int i = 0; i < kQ; ++i) b |= (uint64_t)(e[i] < 0 ? 2 : e[i]) << (2 * i);
+  return b;
+}
+constexpr uint64_t kExBits = pack_dirs(kEx), kEyBits = pack_dirs(kEy), kEzBits = pack_dirs(kEz);
+__host__ __device__ __forceinline__ int dir_comp(uint64_t bits, int i) {
+  const int v = (int)((bits >> (2 * i)) & 3ull);
+  return v == 2 ? -1 : v;
+}
+__host__ __device__ __forceinline__ int ex_of(int i) { return dir_comp(kExBits, i); }
+__host__ __device__ __forceinline__ int ey_of(int i) { return dir_comp(kEyBits, i); }
+__host__ __device__ __forceinline__ int ez_of(int i) { return dir_comp(kEzBits, i); }
 __host__ __device__ constexpr int comp(int i, int a) { return a == 0 ? kEx[i] : (a == 1 ? kEy[i] : kEz[i]); }
 template <typename R>
 __host__ __device__ constexpr R weight(int i) {
@@ -59,6 +76,12 @@ constexpr int kCounters = 8;
 enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect, kNearSurface, kDemSkin };
 // Pose table record of one particle: centre, velocity, angular velocity.
 constexpr int kPoseRec = 9;
+// Interpolated bounce-back: a fluid node can have a solid neighbour (at most
+// sqrt(2) away) only within this distance of a surface; such nodes carry
+// kNearBit in their status byte.
+constexpr double kNearReach = 1.5;
+constexpr uint8_t kNearBit = 0x80;
+constexpr uint8_t kSolidBits = 0x7F;
 // 2^48: the fixed-point scale of the hydrodynamic force and torque sums on
 // coupled particles (sums of at most 2^15 in magnitude).
 constexpr double kForceFix = 281474976710656.0;
@@ -107,6 +130,8 @@ struct DevParticle {
                   // fraction is 0 farther than sqrt(K) + 3/4 from every
                   // control point
   double maskr;   // rb + 0.5, radius used to build the walker cull mask
+  double cnear;   // (sqrt(kmin) / (sqrt(kmin) + kNearReach))^2, kmin the smallest weight:
+                  // M >= cnear wherever the surface M = 1 is within kNearReach
   int32_t motion, nc, ctrl0, pad;
 };
 
@@ -159,7 +184,8 @@ struct DomView {
   int32_t ibb;                    // interpolated bounce-back coupling instead of partially
                                   // saturated cells (two lattices only)
   uint8_t* smap[2];               // IBB: node status of the fluid update of step t in
-                                  // [t & 1]: 0 fluid, p + 1 inside particle p
+                                  // [t & 1]: 0 fluid, p + 1 inside particle p; a fluid node
+                                  // within kNearReach of a surface also has kNearBit
   unsigned long long dem_mask;    // bit p: particle p moves by Newton-Euler (two-way coupled)
   unsigned long long* dem_acc;    // [np][6] hydrodynamic force and torque of the running
                                   // fluid step, two's-complement sums in units of 2^-48

@@ -293,9 +293,10 @@ __device__ __forceinline__ R node_eps_coupled(const DomView& V, int ps, int p, c
 template <typename R>
 __device__ __forceinline__ R edot(int i, R vx, R vy, R vz) {
   R s = (R)0;
-  if (kEx[i] == 1) s = s + vx; else if (kEx[i] == -1) s = s - vx;
-  if (kEy[i] == 1) s = s + vy; else if (kEy[i] == -1) s = s - vy;
-  if (kEz[i] == 1) s = s + vz; else if (kEz[i] == -1) s = s - vz;
+  const int ex = ex_of(i), ey = ey_of(i), ez = ez_of(i);
+  if (ex == 1) s = s + vx; else if (ex == -1) s = s - vx;
+  if (ey == 1) s = s + vy; else if (ey == -1) s = s - vy;
+  if (ez == 1) s = s + vz; else if (ez == -1) s = s - vz;
   return s;
 }
 
@@ -407,10 +408,14 @@ __device__ __forceinline__ void rigid_at(PT pt, const R dl[3], R up[3]) {
 }
 
 // Lowest particle among `bits` (index order) whose M >= 1 at the centre of
-// node nd at the pose of slot ps, or -1.
+// node nd at the pose of slot ps, or -1; `near` is set when the node may lie
+// within kNearReach of a surface (M >= cnear for some particle: with all
+// weights positive, a point within d of the surface M = 1 has
+// M >= (sqrt(kmin) / (sqrt(kmin) + d))^2).
 template <typename R>
 __device__ __forceinline__ int solid_node(const DomView& V, int ps, unsigned long long bits, const int nd[3],
-                                          R dl[3]) {
+                                          R dl[3], bool& near) {
+  near = false;
   while (bits) {
     const int p = __ffsll((long long)bits) - 1;
     bits &= bits - 1ull;
@@ -420,8 +425,11 @@ __device__ __forceinline__ int solid_node(const DomView& V, int ps, unsigned lon
     for (int a = 0; a < 3; ++a) dl[a] = axis_disp<R>(!V.bc[a], V.n[a], nd[a], pt[a], (R)0.5);
     const R r2 = (dl[0] * dl[0] + dl[1] * dl[1]) + dl[2] * dl[2];
     const R rb = (R)P->rb;
-    if (!(r2 < rb * rb)) continue;
-    if (metaball_value<R>(kp(ctrl_of<R>(V, ps)) + 4 * P->ctrl0, P->nc, dl[0], dl[1], dl[2]) >= (R)1) return p;
+    const R rn = rb + (R)kNearReach;
+    if (!(r2 < rn * rn)) continue;
+    const R M = metaball_value<R>(kp(ctrl_of<R>(V, ps)) + 4 * P->ctrl0, P->nc, dl[0], dl[1], dl[2]);
+    if (r2 < rb * rb && M >= (R)1) return p;
+    if (M >= (R)P->cnear) near = true;
   }
   return -1;
 }
@@ -441,7 +449,7 @@ __device__ __forceinline__ typename Store<P>::C feq_stored(const DomView& V, int
 
 // Eq. 23-25 for the link of fluid node id (coordinates nd) along e_i whose
 // upstream node lies in particle p at the previous update (step t - 1):
-// q from halvings of [0, 1] (40 in FP64, 24 in float) for the surface M_p = 1 on the segment from
+// q from a bracketed regula falsi for the surface M_p = 1 on the segment from
 // x_f towards the solid node; u_w the rigid velocity there; u_f, rho_f and
 // the fluid-side neighbour's u_ff (u_f where that node is a wall or solid)
 // from the update of t - 1; fso x_f's own post-collision population of the
@@ -457,7 +465,7 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
   using U = typename Store<P>::U;
   const int nd[3] = {nx, ny, nz};
   const int o = opp_dir(i);
-  const int eo[3] = {kEx[o], kEy[o], kEz[o]};
+  const int eo[3] = {ex_of(o), ey_of(o), ez_of(o)};
   const int ps = pose_slot(t - 1);
   const auto pt = gp((const double*)V.pose[ps]) + kPoseRec * p;
   const auto Pp = gp(V.parts) + p;
@@ -465,31 +473,40 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
   R d0[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) d0[a] = axis_disp<R>(!V.bc[a], V.n[a], nd[a], pt[a], (R)0.5);
-  // halvings: 40 in FP64 (the oracle's), 24 in float (its resolution)
-  constexpr int kHalvings = P == P64 ? 40 : 24;
-  R lo = (R)0, hi = (R)1;
+  // q: the root of 1 - M^(-1/2) in [0, 1] by the Illinois variant of regula
+  // falsi (the bracket keeps a sign change), 10 steps in FP64, 6 in float
+  constexpr int kSteps = P == P64 ? 10 : 6;
   const int p0 = __builtin_amdgcn_readfirstlane(p);
-  if (__all(p == p0)) {
-    // one particle for the whole wave: its control points through the
-    // scalar cache (the bisection reads them kHalvings times)
-    const auto ctrl = kp(ctrl_of<R>(V, ps)) + 4 * kp(V.parts)[p0].ctrl0;
-    const int ncs = kp(V.parts)[p0].nc;
-    for (int it = 0; it < kHalvings; ++it) {
-      const R m = (R)0.5 * (lo + hi);
-      const R x[3] = {d0[0] + m * (R)eo[0], d0[1] + m * (R)eo[1], d0[2] + m * (R)eo[2]};
-      if (metaball_value<R>(ctrl, ncs, x[0], x[1], x[2]) >= (R)1) hi = m;
-      else lo = m;
+  const bool uni = __all(p == p0);
+  // one particle for the whole wave: its control points through the scalar
+  // cache (every step of the solve reads them)
+  const auto ctrl_s = kp(ctrl_of<R>(V, ps)) + 4 * kp(V.parts)[p0].ctrl0;
+  const int nc_s = kp(V.parts)[p0].nc;
+  const auto ctrl_v = gp(ctrl_of<R>(V, ps)) + 4 * Pp->ctrl0;
+  auto phi = [&](R s) -> R {
+    const R x[3] = {d0[0] + s * (R)eo[0], d0[1] + s * (R)eo[1], d0[2] + s * (R)eo[2]};
+    const R M = uni ? metaball_value<R>(ctrl_s, nc_s, x[0], x[1], x[2]) : metaball_value<R>(ctrl_v, nc, x[0], x[1], x[2]);
+    return (R)1 - qdiv<R>((R)1, qsqrt<R>(M));
+  };
+  R a0 = (R)0, b0 = (R)1;
+  R fa = phi(a0), fb = phi(b0);
+  for (int it = 0; it < kSteps; ++it) {
+    if (fb == fa) break;
+    const R c = b0 - fb * qdiv<R>(b0 - a0, fb - fa);
+    const R fc = phi(c);
+    if (fc == (R)0) {
+      b0 = c;
+      break;
     }
-  } else {
-    const auto ctrl = gp(ctrl_of<R>(V, ps)) + 4 * Pp->ctrl0;
-    for (int it = 0; it < kHalvings; ++it) {
-      const R m = (R)0.5 * (lo + hi);
-      const R x[3] = {d0[0] + m * (R)eo[0], d0[1] + m * (R)eo[1], d0[2] + m * (R)eo[2]};
-      if (metaball_value<R>(ctrl, nc, x[0], x[1], x[2]) >= (R)1) hi = m;
-      else lo = m;
+    if ((fc < (R)0) == (fb < (R)0)) fa = (R)0.5 * fa;
+    else {
+      a0 = b0;
+      fa = fb;
     }
+    b0 = c;
+    fb = fc;
   }
-  const R q = (R)0.5 * (lo + hi);
+  const R q = b0;
   const R dlw[3] = {d0[0] + q * (R)eo[0], d0[1] + q * (R)eo[1], d0[2] + q * (R)eo[2]};
   R uw[3];
   rigid_at<R>(pt, dlw, uw);
@@ -497,7 +514,7 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
   const R uf[3] = {(R)up[3ull * id], (R)up[3ull * id + 1], (R)up[3ull * id + 2]};
   const R rf = (R)gp((const U*)V.rho)[id];
   // x_ff = x_f + e_i
-  int ff[3] = {nd[0] + kEx[i], nd[1] + kEy[i], nd[2] + kEz[i]};
+  int ff[3] = {nd[0] + ex_of(i), nd[1] + ey_of(i), nd[2] + ez_of(i)};
   bool fwall = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -511,7 +528,7 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
   R uff[3] = {uf[0], uf[1], uf[2]};
   if (!fwall) {
     const uint32_t fid = (uint32_t)ff[0] + (uint32_t)V.n[0] * ((uint32_t)ff[1] + (uint32_t)V.n[1] * (uint32_t)ff[2]);
-    if (!gp(V.smap[(t - 1) & 1ull])[fid]) {
+    if (!(gp(V.smap[(t - 1) & 1ull])[fid] & kSolidBits)) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) uff[a] = (R)up[3ull * fid + a];
     }
@@ -535,7 +552,7 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
         fs = fs + w * V.rho0_f;
         fn = fn + w * V.rho0_f;
       }
-      const R ei[3] = {(R)kEx[i], (R)kEy[i], (R)kEz[i]};
+      const R ei[3] = {(R)ex_of(i), (R)ey_of(i), (R)ez_of(i)};
       R F[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) F[a] = ((R)eo[a] - uw[a]) * fs - (ei[a] - uw[a]) * fn;
@@ -559,7 +576,7 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
 // that the sums do not depend on the order of the nodes.
 template <int P, int BS, int L, bool DEM, bool IBB>
 __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens,
-                                           unsigned long long* dacc) {
+                                           unsigned long long* dacc, typename Store<P>::C* lv) {
   using S = typename Store<P>::S;
   using R = typename Store<P>::C;
   constexpr bool exact = (P == P64);
@@ -632,27 +649,30 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
     // that was fluid then (a node solid then has no populations of its own:
     // it is solid now or refilled below)
     const unsigned long long bprev = V.np > 0 ? kp(V.fcull[pose_slot(t - 1)])[lb] : 0ull;
-    const uint8_t prev = bprev ? gp((const uint8_t*)V.smap[(t - 1) & 1ull])[id] : (uint8_t)0;
-    if (bprev && !prev) {
+    const uint8_t prevb = bprev ? gp((const uint8_t*)V.smap[(t - 1) & 1ull])[id] : (uint8_t)0;
+    const uint8_t prev = prevb & kSolidBits;
+    if (prevb & kNearBit) {  // only a node near a surface can have a solid neighbour
       const auto smp = gp((const uint8_t*)V.smap[(t - 1) & 1ull]);
-      // the directions whose upstream node was solid, then one pass over
-      // them (one copy of the link code; the lanes of a wave run their
-      // links side by side)
+      // the directions whose upstream node was solid (and their particles),
+      // then one pass over them with one copy of the link code; the link
+      // values go through the thread's column of an LDS table, so that the
+      // population array stays in registers
       uint32_t lmask = 0u;
-      uint32_t lpart[5] = {0u, 0u, 0u, 0u, 0u};  // particle of each link, 6 bits x 5 per word
+      uint32_t lpart[4] = {0u, 0u, 0u, 0u};  // particle of each link, 6 bits x 5 per word
       unroll<1, kQ>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         bool wall;
         int delta;
         upstream_of<i>(nb, wall, delta);
         if (!wall) {
-          const uint8_t s = smp[(uint32_t)((int)id + delta)];
+          const uint8_t s = smp[(uint32_t)((int)id + delta)] & kSolidBits;
           if (s) {
             lmask |= 1u << i;
             lpart[i / 5] |= (uint32_t)(s - 1) << (6 * (i % 5));
           }
         }
       });
+      const uint32_t links = lmask;
       while (lmask) {
         const int i = __ffs((int)lmask) - 1;
         lmask &= lmask - 1u;
@@ -662,19 +682,20 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
         const SR raw = src[(size_t)opp_dir(i) * FS + fnode(true, id)];
         if constexpr (exact) fso = raw;
         else fso = raw_in<S>(raw);
-        const R v = ibb_link<P, DEM>(V, t, id, x, y, z, i, p, fso, dacc);
-        unroll<1, kQ>([&](auto jc) {
-          constexpr int j = decltype(jc)::value;
-          if (j == i) f[j] = v;
-        });
+        lv[(i - 1) * BS + threadIdx.x] = ibb_link<P, DEM>(V, t, id, x, y, z, i, p, fso, dacc);
       }
+      unroll<1, kQ>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if (links & (1u << i)) f[i] = lv[(i - 1) * BS + threadIdx.x];
+      });
     }
     // the node's own status at P(t)
     const int ps = pose_slot(t);
     const unsigned long long bits = V.np > 0 ? kp(V.fcull[ps])[lb] : 0ull;
     R dl[3];
-    const int sn = bits ? solid_node<R>(V, ps, bits, nd, dl) : -1;
-    gp(V.smap[t & 1ull])[id] = (uint8_t)(sn + 1);
+    bool near = false;
+    const int sn = bits ? solid_node<R>(V, ps, bits, nd, dl, near) : -1;
+    gp(V.smap[t & 1ull])[id] = sn >= 0 ? (uint8_t)(sn + 1) : (near ? kNearBit : (uint8_t)0);
     if (sn >= 0) {
       R up[3];
       rigid_at<R>(kp((const double*)V.pose[ps]) + kPoseRec * sn, dl, up);
@@ -1014,15 +1035,24 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
   }
 }
 
+// LDS of a fluid block: the coupled particles' force sums and, with the
+// bounce-back coupling, a column per thread of link values.
+template <int P, int BS, bool IBB>
+struct FluidLds {
+  unsigned long long dem[6 * kMaxParticles];
+  typename Store<P>::C lv[IBB ? (kQ - 1) * BS : 1];
+};
+
 template <int P, int BS, int L, bool DEM, bool IBB = false>
 __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens,
-                                            unsigned long long* dacc) {
+                                            FluidLds<P, BS, IBB>& fl) {
+  unsigned long long* dacc = fl.dem;
   if constexpr (!DEM) {
-    fluid_node<P, BS, L, false, IBB>(V, lb, t, nt, dens, dacc);
+    fluid_node<P, BS, L, false, IBB>(V, lb, t, nt, dens, dacc, fl.lv);
   } else {
     for (int k = threadIdx.x; k < 6 * kMaxParticles; k += BS) dacc[k] = 0ull;
     lds_barrier();
-    fluid_node<P, BS, L, true, IBB>(V, lb, t, nt, dens, dacc);
+    fluid_node<P, BS, L, true, IBB>(V, lb, t, nt, dens, dacc, fl.lv);
     lds_barrier();
     // the block's sums into the step's accumulator (two's-complement adds:
     // exact, in any order); bounce-back links belong to the particles near
@@ -1117,13 +1147,14 @@ __global__ void k_read_f(const DomView* __restrict__ views, int dom, double* __r
     else if (!odd) sidx = fidx(false, i, un, NN);
     else sidx = wall ? fidx(false, i, un, NN) : fidx(false, opp_dir(i), uu, NN);
     double v = (double)to_c(src[sidx]);
-    if (V.ibb && t > 0 && !wall && i > 0 && V.smap[(t - 1) & 1ull][up]) {
+    if (V.ibb && t > 0 && !wall && i > 0 && (V.smap[(t - 1) & 1ull][up] & kSolidBits)) {
       // interpolated bounce-back: what the next gather will take for this
       // link (the value of a solid node, or of a node uncovered since, is
       // not defined)
       using C = typename Store<P>::C;
       const C fso = to_c(src[fidx(true, opp_dir(i), un, NN)]);
-      v = (double)ibb_link<P, false>(V, t, un, nd[0], nd[1], nd[2], i, (int)V.smap[(t - 1) & 1ull][up] - 1, fso,
+      v = (double)ibb_link<P, false>(V, t, un, nd[0], nd[1], nd[2], i,
+                                     (int)(V.smap[(t - 1) & 1ull][up] & kSolidBits) - 1, fso,
                                      nullptr);
     }
     if (P != P64) v = v + weight<double>(i) * V.rho0;

@@ -35,6 +35,8 @@ Other workloads (own JSON line each, not the headline):
   --coupling ibb                                          interpolated bounce-back (Eq. 23-27) instead of
                                                           partially saturated cells
   --workload copy [--lattice MiB]                         plain copy (HBM counter calibration)
+  --workload streams                                      the update's memory pattern without arithmetic
+                                                          (1-19 read + write streams, planes and tiles)
   --workload serve [--rate 20 --duration 15]              Poisson request stream
 """
 import argparse
@@ -220,6 +222,14 @@ def bench_plain(args):
     if args.coupling == "ibb":
         cfg["domain"]["coupling"] = "ibb"
         key += "_ibb"
+    if args.components != "all":
+        # the same lattice and run without the walkers and/or the particles:
+        # the split of the step's time and counters among its parts
+        if "walkers" not in args.components:
+            cfg["walkers"]["n"] = 0
+        if "particles" not in args.components:
+            cfg["particles"] = []
+        key += "_" + args.components.replace("+", "_")
     steps, warmup = args.steps, args.warmup
     r = measure(cfg, key, steps, warmup, args.timing_every, burnin=burnin_steps(cfg, args))
     mom = r["mom"]
@@ -394,13 +404,47 @@ def bench_copy(args):
                       "us_per_copy": round(s * 1e6, 2), "GB_per_s": round(2 * nbytes / s / 1e9, 1)}), flush=True)
 
 
+def bench_streams(args):
+    """The lattice update's memory pattern without its arithmetic or
+    neighbour shifts (rwmi_stream_probe): 1, 2, 4, 8 and 19 read and as many
+    write streams of 2^24 floats each (one 256^3 lattice's node count), as
+    planes and in tiles of 256 nodes, 20 timed launches each.  The 1- and
+    2-stream cases (64 and 128 MB each way) fit the memory-side cache."""
+    import torch
+    from paper_2308_05007_amd import binding as B
+    B.lib()
+    n = 1 << 24
+    src = torch.rand(19 * n, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    out = {}
+    for streams in (1, 2, 4, 8, 19):
+        for tiled in (0, 1):
+            a, b = src[:streams * n], dst[:streams * n]
+            for _ in range(3):
+                B.stream_probe(streams, tiled, a, b, s)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(20):
+                B.stream_probe(streams, tiled, a, b, s)
+            e1.record(s)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 20
+            out["%d_%s" % (streams, "tiled" if tiled else "planes")] = {
+                "us_per_launch": round(us, 2), "bytes": 8 * streams * n,
+                "GB_per_s": round(8 * streams * n / us / 1e3, 1)}
+    print(json.dumps({"metric": "stream pattern bandwidth (reads + writes of 2^24 floats per stream)",
+                      "unit": "GB/s", "peak": HBM_PEAK_GBS, "results": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="oscillator",
-                    choices=["oscillator", "channel", "precision", "batch", "ensemble", "coupled", "serve", "copy"])
+                    choices=["oscillator", "channel", "precision", "batch", "ensemble", "coupled", "serve", "copy",
+                             "streams"])
     ap.add_argument("--lattice", type=int, default=None)
     ap.add_argument("--rate", type=float, default=None)
     ap.add_argument("--duration", type=float, default=None)
@@ -414,6 +458,8 @@ def main():
     ap.add_argument("--radius", type=float, default=None, help="ensemble: particle radius R in lattice units")
     ap.add_argument("--burnin", type=int, default=None,
                     help="untimed steps before the warm-up (default: half of the workload's run)")
+    ap.add_argument("--components", default="all", choices=["all", "fluid", "fluid+particles", "fluid+walkers"],
+                    help="oscillator/channel: run without the walkers and/or the particles (a split of the step)")
     ap.add_argument("--coupling", default="psm", choices=["psm", "ibb"],
                     help="fluid-particle coupling: partially saturated cells or interpolated bounce-back")
     ap.add_argument("--timing-every", type=int, default=32,
@@ -430,6 +476,8 @@ def main():
         bench_precision(args)
     elif args.workload == "copy":
         bench_copy(args)
+    elif args.workload == "streams":
+        bench_streams(args)
     elif args.workload == "batch":
         from paper_2308_05007_amd import batchbench
         batchbench.main(args)

@@ -474,6 +474,19 @@ rwmi_status rwmi_gaussian_fit(const double* x, const double* y, uint32_t n, doub
  * 0), id = 0..n-1, under key seed, written as n x 3 doubles to host z. */
 rwmi_status rwmi_device_normals(int32_t device, uint64_t seed, uint32_t t, uint32_t purpose, uint64_t n, double* z);
 
+/* Bandwidth probe of the lattice update's memory pattern without its
+ * arithmetic or neighbour shifts: one launch on `stream` (a hipStream_t;
+ * NULL: the null stream) in which each of n nodes reads one float from each
+ * of `streams` arrays of src and writes one float to each of as many arrays
+ * of dst, 8 * streams * n bytes in all.  tiled = 0: array i of node k at
+ * i * n + k; tiled = 1: in tiles of 256 nodes, the tile's 256 values of
+ * array 0, then of array 1, and so on (the distributions' two-lattice
+ * layout).  src and dst are device buffers of streams * n floats owned by
+ * the caller.  Asynchronous: returns after the launch.  EINVAL unless
+ * streams is 1, 2, 4, 8 or 19, n is a positive multiple of 256 below 2^32
+ * and both pointers are non-NULL; EDEVICE if the launch fails. */
+rwmi_status rwmi_stream_probe(int32_t streams, int32_t tiled, uint64_t n, const float* src, float* dst, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,7 @@ Translation units:
   k_fp64.hip  FP64 kernels and the precision-independent ones, with
               -ffp-contract=off so every double operation rounds once
   k_lowp.hip  FP32 / FP16 / BF16-storage kernels (contraction allowed)
+  probe.hip   the bandwidth probe of the stream pattern (measurement only)
   capi.cpp    host side of the C ABI
 All device code is built without packed FP32 instructions.
 """
@@ -26,6 +27,7 @@ COMMON = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-Xclang", "-t
 UNITS = [
     ("k_fp64.hip", ["-ffp-contract=off"]),
     ("k_lowp.hip", ["-ffp-contract=fast"]),
+    ("probe.hip", []),
     ("capi.cpp", ["-x", "hip", "-ffp-contract=off"]),
 ]
 

@@ -15,6 +15,11 @@
 #include "dev_common.h"
 #include "launch.h"
 
+namespace rwmi {
+// the bandwidth probe (probe.hip)
+hipError_t launch_stream_probe(int streams, bool tiled, uint64_t n, const float* src, float* dst, hipStream_t s);
+}
+
 using rwmi::DevParticle;
 using rwmi::DomView;
 
@@ -1461,6 +1466,16 @@ rwmi_status rwmi_device_normals(int32_t device, uint64_t seed, uint32_t t, uint3
   if (e == hipSuccess) e = hipMemcpy(z, dz, 24 * n, hipMemcpyDeviceToHost);
   (void)hipFree(dz);
   if (e != hipSuccess) return fail(nullptr, RWMI_EDEVICE, "normals: %s", hipGetErrorString(e));
+  return RWMI_OK;
+}
+
+rwmi_status rwmi_stream_probe(int32_t streams, int32_t tiled, uint64_t n, const float* src, float* dst, void* stream) {
+  if (!src || !dst) return fail(nullptr, RWMI_EINVAL, "null buffer");
+  if (!(streams == 1 || streams == 2 || streams == 4 || streams == 8 || streams == 19))
+    return fail(nullptr, RWMI_EINVAL, "streams must be 1, 2, 4, 8 or 19");
+  if (n == 0 || n % 256 != 0 || n >= (1ull << 32)) return fail(nullptr, RWMI_EINVAL, "n must be a positive multiple of 256 below 2^32");
+  const hipError_t e = rwmi::launch_stream_probe(streams, tiled != 0, n, src, dst, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, RWMI_EDEVICE, "stream probe: %s", hipGetErrorString(e));
   return RWMI_OK;
 }
 

@@ -90,3 +90,14 @@ def test_invalid_precision_and_callback_pairs_are_rejected():
     d.alloc = B.ALLOC_FN(lambda n, ctx: None)
     assert B.lib().rwmi_create_domain(C.byref(d), C.byref(h)) == B.RWMI_EINVAL
     assert "together" in B.lib().rwmi_last_error(None).decode()
+
+
+def test_stream_probe_rejects_bad_arguments_before_any_launch():
+    import ctypes as C
+    from paper_2308_05007_amd import binding as B
+    L = B.lib()
+    buf = C.c_void_p(16)  # never dereferenced: every case fails its checks first
+    for streams, n, src in ((3, 256, buf), (19, 300, buf), (19, 0, buf), (4, 1 << 32, buf), (4, 256, None)):
+        assert L.rwmi_stream_probe(streams, 1, n, src, buf, None) == B.RWMI_EINVAL
+    assert L.rwmi_stream_probe(5, 0, 256, buf, buf, None) == B.RWMI_EINVAL
+    assert "streams" in L.rwmi_last_error(None).decode()

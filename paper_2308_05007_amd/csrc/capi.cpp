@@ -284,10 +284,6 @@ rwmi_status finalize_particles(rwmi_domain* d) {
     r.epscut2 = (r.rb + 0.75) * (r.rb + 0.75);
     r.shell2 = (std::sqrt(K) + 0.75) * (std::sqrt(K) + 0.75);
     r.maskr = r.rb + 0.5;
-    double kmin = q.k[0];
-    for (int i = 1; i < nc; ++i) kmin = std::min(kmin, q.k[i]);
-    r.cnear = (std::sqrt(kmin) / (std::sqrt(kmin) + rwmi::kNearReach)) *
-              (std::sqrt(kmin) / (std::sqrt(kmin) + rwmi::kNearReach));
     for (int a = 0; a < 3; ++a) {
       r.c0[a] = q.c0[a];
       r.amp[a] = q.amp[a];
@@ -432,6 +428,8 @@ rwmi_status enqueue_group(rwmi_domain* d, uint32_t n, bool record, bool capturin
       HIPCHK(d, hipEventRecord(e0, A));
       open = true;
     }
+    if (d->hv.ibb && a.nb[kRoleFluid] > 0)
+      HIPCHK(d, rwmi::launch_ibb_links(d->prec, d->dv, 0, j, false, (unsigned)a.nb[kRoleFluid], A));
     HIPCHK(d, rwmi::launch_step(d->prec, d->bs, a, A));
     if (timed) {
       win.launches += 1;
@@ -489,6 +487,8 @@ rwmi_status enqueue_group_dem(rwmi_domain* d, uint32_t n, bool record, bool capt
     a.j = j;
     if (a.nb[kRoleWalk] + a.nb[kRoleFluid] > 0) {
       if (open() != RWMI_OK) return RWMI_EDEVICE;
+      if (d->hv.ibb && a.nb[kRoleFluid] > 0)
+        HIPCHK(d, rwmi::launch_ibb_links(d->prec, d->dv, 0, j, true, (unsigned)a.nb[kRoleFluid], A));
       HIPCHK(d, rwmi::launch_step(d->prec, 256, a, A));
       if (close() != RWMI_OK) return RWMI_EDEVICE;
       if (record)
@@ -1079,6 +1079,14 @@ rwmi_status rwmi_set_fluid_coupling(rwmi_domain* d, int32_t scheme) {
       HIPCHK(d, hipMemsetAsync(sm, 0, 2 * (size_t)d->hv.N, d->stream));
       d->hv.smap[0] = sm;
       d->hv.smap[1] = sm + d->hv.N;
+      // lists of the solid nodes (any node can be one), for the link pass
+      // of the next step
+      uint32_t* nl;
+      if ((st = alloc_into(d, nl, 4 * (2 * (size_t)d->hv.N + 2))) != RWMI_OK) return st;
+      HIPCHK(d, hipMemsetAsync(nl + 2 * (size_t)d->hv.N, 0, 8, d->stream));
+      d->hv.solid_list[0] = nl;
+      d->hv.solid_list[1] = nl + d->hv.N;
+      d->hv.solid_count = nl + 2 * (size_t)d->hv.N;
     }
     d->bs = 256;
   }

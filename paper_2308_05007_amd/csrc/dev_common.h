@@ -76,11 +76,7 @@ constexpr int kCounters = 8;
 enum CounterIdx { kType2 = 0, kType4, kBisectFail, kRefillFallback, kReturned, kWallReflect, kNearSurface, kDemSkin };
 // Pose table record of one particle: centre, velocity, angular velocity.
 constexpr int kPoseRec = 9;
-// Interpolated bounce-back: a fluid node can have a solid neighbour (at most
-// sqrt(2) away) only within this distance of a surface; such nodes carry
-// kNearBit in their status byte.
-constexpr double kNearReach = 1.5;
-constexpr uint8_t kNearBit = 0x80;
+// Interpolated bounce-back: the particle bits of a node's status byte.
 constexpr uint8_t kSolidBits = 0x7F;
 // 2^48: the fixed-point scale of the hydrodynamic force and torque sums on
 // coupled particles (sums of at most 2^15 in magnitude).
@@ -130,8 +126,6 @@ struct DevParticle {
                   // fraction is 0 farther than sqrt(K) + 3/4 from every
                   // control point
   double maskr;   // rb + 0.5, radius used to build the walker cull mask
-  double cnear;   // (sqrt(kmin) / (sqrt(kmin) + kNearReach))^2, kmin the smallest weight:
-                  // M >= cnear wherever the surface M = 1 is within kNearReach
   int32_t motion, nc, ctrl0, pad;
 };
 
@@ -184,8 +178,10 @@ struct DomView {
   int32_t ibb;                    // interpolated bounce-back coupling instead of partially
                                   // saturated cells (two lattices only)
   uint8_t* smap[2];               // IBB: node status of the fluid update of step t in
-                                  // [t & 1]: 0 fluid, p + 1 inside particle p; a fluid node
-                                  // within kNearReach of a surface also has kNearBit
+                                  // [t & 1]: 0 fluid, p + 1 inside particle p
+  uint32_t* solid_list[2];        // IBB: the nodes solid at the fluid update of step t,
+                                  // in [t & 1], in no particular order
+  uint32_t* solid_count;          // IBB: [2], their numbers
   unsigned long long dem_mask;    // bit p: particle p moves by Newton-Euler (two-way coupled)
   unsigned long long* dem_acc;    // [np][6] hydrodynamic force and torque of the running
                                   // fluid step, two's-complement sums in units of 2^-48

@@ -33,12 +33,20 @@ hipError_t noalloc_scratch(double** ptr) {
   return hipSuccess;
 }
 
+hipError_t launch_ibb_links_p64(const DomView* v, int dom, int32_t j, bool dem, unsigned blocks, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  blocks = kLinkGrid;  // the pass strides over the listed nodes
+  if (dem) k_ibb_links<P64, true><<<blocks, 256, 0, s>>>(v, dom, j);
+  else k_ibb_links<P64, false><<<blocks, 256, 0, s>>>(v, dom, j);
+  return hipGetLastError();
+}
+
 hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
   const unsigned g = (unsigned)step_grid(a.nb, (a.flags & kFlagXcd) != 0);
   if (g == 0) return hipSuccess;
-  if (a.flags & kFlagIbb) {  // bounce-back coupling: two lattices, 256 threads per block
-    if (a.flags & kFlagDem) k_step<P64, 256, false, true, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
-    else k_step<P64, 256, false, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
+  if (a.flags & kFlagIbb) {  // bounce-back coupling: two lattices, 256 threads per block; the link
+                             // pass carries the coupled particles' momentum exchange
+    k_step<P64, 256, false, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
     return hipGetLastError();
   }
   if (a.flags & kFlagDem) {  // coupled particles: 256 threads per block

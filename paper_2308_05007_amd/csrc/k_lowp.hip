@@ -16,9 +16,9 @@ static void step_bs(int bs, unsigned g, const StepArgs& a, hipStream_t s) {
 
 template <int P>
 static void step_layout(int bs, unsigned g, const StepArgs& a, hipStream_t s) {
-  if (a.flags & kFlagIbb) {  // bounce-back coupling: two lattices, 256 threads per block
-    if (a.flags & kFlagDem) k_step<P, 256, false, true, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
-    else k_step<P, 256, false, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
+  if (a.flags & kFlagIbb) {  // bounce-back coupling: two lattices, 256 threads per block; the link
+                             // pass carries the coupled particles' momentum exchange
+    k_step<P, 256, false, false, true><<<g, 256, 0, s>>>(a, a.views, a.boff);
     return;
   }
   if (a.flags & kFlagDem) {  // coupled particles: 256 threads per block
@@ -36,6 +36,22 @@ hipError_t launch_step_lowp(int prec, int bs, const StepArgs& a, hipStream_t s) 
   if (prec == P32) step_layout<P32>(bs, g, a, s);
   else if (prec == P16) step_layout<P16>(bs, g, a, s);
   else step_layout<PB16>(bs, g, a, s);
+  return hipGetLastError();
+}
+
+template <int P>
+static void links(const DomView* v, int dom, int32_t j, bool dem, unsigned blocks, hipStream_t s) {
+  if (dem) k_ibb_links<P, true><<<blocks, 256, 0, s>>>(v, dom, j);
+  else k_ibb_links<P, false><<<blocks, 256, 0, s>>>(v, dom, j);
+}
+
+hipError_t launch_ibb_links_lowp(int prec, const DomView* v, int dom, int32_t j, bool dem, unsigned blocks,
+                                 hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  blocks = kLinkGrid;  // the pass strides over the listed nodes
+  if (prec == P32) links<P32>(v, dom, j, dem, blocks, s);
+  else if (prec == P16) links<P16>(v, dom, j, dem, blocks, s);
+  else links<PB16>(v, dom, j, dem, blocks, s);
   return hipGetLastError();
 }
 

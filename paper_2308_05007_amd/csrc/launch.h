@@ -18,6 +18,16 @@ hipError_t launch_read_f_p64(const DomView* v, int dom, int64_t N, double* out, 
 hipError_t launch_read_f_lowp(int prec, const DomView* v, int dom, int64_t N, double* out, hipStream_t s);
 
 // precision 0 is FP64 (rwmi::P64)
+// Link pass of interpolated bounce-back (k_ibb_links) for the fluid update
+// of launch j of a group (none if `blocks`, the fluid blocks, is 0).
+hipError_t launch_ibb_links_p64(const DomView* v, int dom, int32_t j, bool dem, unsigned blocks, hipStream_t s);
+hipError_t launch_ibb_links_lowp(int prec, const DomView* v, int dom, int32_t j, bool dem, unsigned blocks,
+                                 hipStream_t s);
+inline hipError_t launch_ibb_links(int prec, const DomView* v, int dom, int32_t j, bool dem, unsigned blocks,
+                                   hipStream_t s) {
+  return prec == 0 ? launch_ibb_links_p64(v, dom, j, dem, blocks, s)
+                   : launch_ibb_links_lowp(prec, v, dom, j, dem, blocks, s);
+}
 inline hipError_t launch_step(int prec, int bs, const StepArgs& a, hipStream_t s) {
   return prec == 0 ? launch_step_p64(bs, a, s) : launch_step_lowp(prec, bs, a, s);
 }

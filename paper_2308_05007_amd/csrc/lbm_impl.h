@@ -408,14 +408,11 @@ __device__ __forceinline__ void rigid_at(PT pt, const R dl[3], R up[3]) {
 }
 
 // Lowest particle among `bits` (index order) whose M >= 1 at the centre of
-// node nd at the pose of slot ps, or -1; `near` is set when the node may lie
-// within kNearReach of a surface (M >= cnear for some particle: with all
-// weights positive, a point within d of the surface M = 1 has
-// M >= (sqrt(kmin) / (sqrt(kmin) + d))^2).
+// node nd at the pose of slot ps, or -1; dl receives the node's offset from
+// that particle's centre.
 template <typename R>
 __device__ __forceinline__ int solid_node(const DomView& V, int ps, unsigned long long bits, const int nd[3],
-                                          R dl[3], bool& near) {
-  near = false;
+                                          R dl[3]) {
   while (bits) {
     const int p = __ffsll((long long)bits) - 1;
     bits &= bits - 1ull;
@@ -425,11 +422,8 @@ __device__ __forceinline__ int solid_node(const DomView& V, int ps, unsigned lon
     for (int a = 0; a < 3; ++a) dl[a] = axis_disp<R>(!V.bc[a], V.n[a], nd[a], pt[a], (R)0.5);
     const R r2 = (dl[0] * dl[0] + dl[1] * dl[1]) + dl[2] * dl[2];
     const R rb = (R)P->rb;
-    const R rn = rb + (R)kNearReach;
-    if (!(r2 < rn * rn)) continue;
-    const R M = metaball_value<R>(kp(ctrl_of<R>(V, ps)) + 4 * P->ctrl0, P->nc, dl[0], dl[1], dl[2]);
-    if (r2 < rb * rb && M >= (R)1) return p;
-    if (M >= (R)P->cnear) near = true;
+    if (!(r2 < rb * rb)) continue;
+    if (metaball_value<R>(kp(ctrl_of<R>(V, ps)) + 4 * P->ctrl0, P->nc, dl[0], dl[1], dl[2]) >= (R)1) return p;
   }
   return -1;
 }
@@ -456,11 +450,15 @@ __device__ __forceinline__ typename Store<P>::C feq_stored(const DomView& V, int
 // opposite direction.  DEM: the link's momentum exchange in its
 // Galilean-invariant form, (e_o - u_w) fso - (e_i - u_w) f_i, and its torque
 // about the particle's centre go to the block's accumulator.
+// lctrl, when `lds`: every particle's control points at the pose of t - 1
+// in LDS, at the offsets they have in the domain's table.
 template <int P, bool DEM>
 __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint64_t t, uint32_t id,
                                                                     int nx, int ny, int nz, int i, int p,
                                                                     typename Store<P>::C fso,
-                                                                    unsigned long long* dacc) {
+                                                                    unsigned long long* dacc,
+                                                                    const typename Store<P>::C* lctrl = nullptr,
+                                                                    bool lds = false) {
   using R = typename Store<P>::C;
   using U = typename Store<P>::U;
   const int nd[3] = {nx, ny, nz};
@@ -482,10 +480,13 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
   // cache (every step of the solve reads them)
   const auto ctrl_s = kp(ctrl_of<R>(V, ps)) + 4 * kp(V.parts)[p0].ctrl0;
   const int nc_s = kp(V.parts)[p0].nc;
-  const auto ctrl_v = gp(ctrl_of<R>(V, ps)) + 4 * Pp->ctrl0;
+  const int c0 = Pp->ctrl0;
+  const auto ctrl_v = gp(ctrl_of<R>(V, ps)) + 4 * c0;
   auto phi = [&](R s) -> R {
     const R x[3] = {d0[0] + s * (R)eo[0], d0[1] + s * (R)eo[1], d0[2] + s * (R)eo[2]};
-    const R M = uni ? metaball_value<R>(ctrl_s, nc_s, x[0], x[1], x[2]) : metaball_value<R>(ctrl_v, nc, x[0], x[1], x[2]);
+    R M;
+    if (lds) M = metaball_value<R>(lctrl + 4 * c0, nc, x[0], x[1], x[2]);
+    else M = uni ? metaball_value<R>(ctrl_s, nc_s, x[0], x[1], x[2]) : metaball_value<R>(ctrl_v, nc, x[0], x[1], x[2]);
     return (R)1 - qdiv<R>((R)1, qsqrt<R>(M));
   };
   R a0 = (R)0, b0 = (R)1;
@@ -568,6 +569,96 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
   return fi;
 }
 
+// The link pass of step t, run before the step's fluid update.  For each
+// node x_s that was solid at the previous update and each direction i whose
+// downstream node x_f = x_s + e_i was fluid then (x_f's link along e_i), the
+// bounced population of Eq. 23-25 (ibb_link) is written into slot i of x_s
+// in the lattice step t pulls from, where x_f's gather finds it like any
+// other population.  A solid node's own populations are not defined and
+// each of its slots feeds one downstream node only, so no write meets a
+// value that is still to be read; the inputs (x_f's own populations,
+// velocities and densities of t - 1) belong to fluid nodes and are never
+// written here.
+//
+// The work items are the (node, direction) pairs of the solid nodes the
+// fluid update of t - 1 listed, 18 per node, spread over the launch's
+// threads: every link runs in its own lane, and all of a step's links are
+// in flight at once.  The control points of all particles are copied to LDS
+// first when they fit (every step of a link's root search reads them).  The
+// pass also clears the count of the list the fluid update of t fills.  DEM:
+// the links' momentum exchange in the block's LDS accumulator, then in the
+// step's.
+constexpr unsigned kLinkGrid = 2048;  // blocks of the link pass
+constexpr int kLinkCtrl = 1024;       // control points held in LDS
+
+template <int P, bool DEM>
+__global__ void __launch_bounds__(256) k_ibb_links(const DomView* __restrict__ views, int dom, int32_t j) {
+  using S = typename Store<P>::S;
+  using R = typename Store<P>::C;
+  using SR = typename Raw<S>::T;
+  __shared__ unsigned long long dacc[DEM ? 6 * kMaxParticles : 1];
+  __shared__ R cl[4 * kLinkCtrl];
+  const DomView& V = views[dom];
+  if (V.np == 0) return;
+  const uint64_t t = step_of(V, j);
+  // the fluid update of t lists into [t & 1]; the pass of t - 1 has read it
+  if (blockIdx.x == 0 && threadIdx.x == 0) V.solid_count[t & 1ull] = 0u;
+  const uint32_t nn = V.solid_count[(t - 1) & 1ull];
+  const uint64_t items = (uint64_t)nn * (kQ - 1);
+  const uint64_t first = (uint64_t)blockIdx.x * 256u;
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  if (first >= items) return;  // uniform over the block
+  const auto list = gp((const uint32_t*)V.solid_list[(t - 1) & 1ull]);
+  const auto smp = gp((const uint8_t*)V.smap[(t - 1) & 1ull]);
+  const auto src = gp((SR*)((t & 1ull) ? V.fB : V.fA));
+  constexpr uint32_t FS = kTile;
+  const auto plast = kp(V.parts) + (V.np - 1);
+  const int nctl = plast->ctrl0 + plast->nc;
+  const bool lds = nctl <= kLinkCtrl;
+  if (lds) {
+    const auto cg = gp(ctrl_of<R>(V, pose_slot(t - 1)));
+    for (int k = threadIdx.x; k < 4 * nctl; k += 256) cl[k] = cg[k];
+  }
+  if constexpr (DEM)
+    for (int k = threadIdx.x; k < 6 * kMaxParticles; k += 256) dacc[k] = 0ull;
+  lds_barrier();
+  for (uint64_t w = first + threadIdx.x; w < items; w += stride) {
+    const uint32_t us = list[w / (kQ - 1)];
+    const int i = 1 + (int)(w % (kQ - 1));
+    const uint32_t q1 = fdiv(us, V.dx);
+    const int zz = (int)fdiv(q1, V.dy);
+    // downstream node x_f = x_s + e_i: a wall node is never updated
+    int nd[3] = {(int)(us - q1 * (uint32_t)V.n[0]) + ex_of(i), (int)q1 - zz * V.n[1] + ey_of(i), zz + ez_of(i)};
+    bool wall = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int m = V.n[a];
+      if (V.bc[a]) wall = wall || nd[a] <= 0 || nd[a] >= m - 1;
+      else nd[a] = nd[a] < 0 ? nd[a] + m : (nd[a] >= m ? nd[a] - m : nd[a]);
+    }
+    if (wall) continue;
+    const uint32_t nid = (uint32_t)nd[0] + (uint32_t)V.n[0] * ((uint32_t)nd[1] + (uint32_t)V.n[1] * (uint32_t)nd[2]);
+    if (smp[nid] & kSolidBits) continue;  // solid too: no link
+    const uint8_t sb = smp[us] & kSolidBits;
+    const SR raw = src[(size_t)opp_dir(i) * FS + fnode(true, nid)];
+    R fso;
+    if constexpr (P == P64) fso = raw;
+    else fso = raw_in<S>(raw);
+    const R v = ibb_link<P, DEM>(V, t, nid, nd[0], nd[1], nd[2], i, (int)sb - 1, fso, dacc, cl, lds);
+    SR o;
+    if constexpr (P == P64) o = v;
+    else o = raw_out<S>(v);
+    src[(size_t)i * FS + fnode(true, us)] = o;
+  }
+  if constexpr (DEM) {
+    lds_barrier();
+    for (int k = threadIdx.x; k < 6 * kMaxParticles; k += 256) {
+      const unsigned long long v = dacc[k];
+      if (((V.dem_mask >> (k / 6)) & 1ull) && v != 0ull) atomicAdd(V.dem_acc + k, v);
+    }
+  }
+}
+
 // One node of a fluid block.  DEM: two-way coupled particles; the momentum
 // the solid term takes from the fluid at the node, -sum_i e_i B Om_i, is
 // shared among the coupled particles that cover it in proportion to their
@@ -576,7 +667,7 @@ __device__ __forceinline__ typename Store<P>::C ibb_link(const DomView& V, uint6
 // that the sums do not depend on the order of the nodes.
 template <int P, int BS, int L, bool DEM, bool IBB>
 __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens,
-                                           unsigned long long* dacc, typename Store<P>::C* lv) {
+                                           unsigned long long* dacc) {
   using S = typename Store<P>::S;
   using R = typename Store<P>::C;
   constexpr bool exact = (P == P64);
@@ -645,57 +736,33 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
   if (!live) return;
   if constexpr (IBB) {
     static_assert(!inplace, "interpolated bounce-back streams between two lattices");
-    // links whose upstream node was solid at the previous update, for a node
-    // that was fluid then (a node solid then has no populations of its own:
-    // it is solid now or refilled below)
+    // a link whose upstream node was solid at the previous update was
+    // gathered above like any other population: the link pass of this step
+    // (k_ibb_links) wrote its bounced value into that node's slot.  A node
+    // solid then has no populations of its own: it is solid now or refilled
+    // below.
     const unsigned long long bprev = V.np > 0 ? kp(V.fcull[pose_slot(t - 1)])[lb] : 0ull;
-    const uint8_t prevb = bprev ? gp((const uint8_t*)V.smap[(t - 1) & 1ull])[id] : (uint8_t)0;
-    const uint8_t prev = prevb & kSolidBits;
-    if (prevb & kNearBit) {  // only a node near a surface can have a solid neighbour
-      const auto smp = gp((const uint8_t*)V.smap[(t - 1) & 1ull]);
-      // the directions whose upstream node was solid (and their particles),
-      // then one pass over them with one copy of the link code; the link
-      // values go through the thread's column of an LDS table, so that the
-      // population array stays in registers
-      uint32_t lmask = 0u;
-      uint32_t lpart[4] = {0u, 0u, 0u, 0u};  // particle of each link, 6 bits x 5 per word
-      unroll<1, kQ>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        bool wall;
-        int delta;
-        upstream_of<i>(nb, wall, delta);
-        if (!wall) {
-          const uint8_t s = smp[(uint32_t)((int)id + delta)] & kSolidBits;
-          if (s) {
-            lmask |= 1u << i;
-            lpart[i / 5] |= (uint32_t)(s - 1) << (6 * (i % 5));
-          }
-        }
-      });
-      const uint32_t links = lmask;
-      while (lmask) {
-        const int i = __ffs((int)lmask) - 1;
-        lmask &= lmask - 1u;
-        const uint32_t word = i < 5 ? lpart[0] : (i < 10 ? lpart[1] : (i < 15 ? lpart[2] : lpart[3]));
-        const int p = (int)((word >> (6 * (i % 5))) & 63u);
-        R fso;
-        const SR raw = src[(size_t)opp_dir(i) * FS + fnode(true, id)];
-        if constexpr (exact) fso = raw;
-        else fso = raw_in<S>(raw);
-        lv[(i - 1) * BS + threadIdx.x] = ibb_link<P, DEM>(V, t, id, x, y, z, i, p, fso, dacc);
-      }
-      unroll<1, kQ>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        if (links & (1u << i)) f[i] = lv[(i - 1) * BS + threadIdx.x];
-      });
-    }
+    const uint8_t prev = bprev ? (uint8_t)(gp((const uint8_t*)V.smap[(t - 1) & 1ull])[id] & kSolidBits) : (uint8_t)0;
     // the node's own status at P(t)
     const int ps = pose_slot(t);
     const unsigned long long bits = V.np > 0 ? kp(V.fcull[ps])[lb] : 0ull;
     R dl[3];
-    bool near = false;
-    const int sn = bits ? solid_node<R>(V, ps, bits, nd, dl, near) : -1;
-    gp(V.smap[t & 1ull])[id] = sn >= 0 ? (uint8_t)(sn + 1) : (near ? kNearBit : (uint8_t)0);
+    const int sn = bits ? solid_node<R>(V, ps, bits, nd, dl) : -1;
+    gp(V.smap[t & 1ull])[id] = sn >= 0 ? (uint8_t)(sn + 1) : (uint8_t)0;
+    {
+      // a solid node joins the list the link pass of step t + 1 works
+      // through (one atomic per wave)
+      const bool app = sn >= 0;
+      const unsigned long long bal = __ballot(app);
+      if (bal) {
+        const int lane = (int)__lane_id();
+        const int leader = __ffsll((long long)bal) - 1;
+        uint32_t base = 0u;
+        if (lane == leader) base = atomicAdd(V.solid_count + (t & 1ull), (uint32_t)__popcll(bal));
+        base = (uint32_t)__shfl((int)base, leader);
+        if (app) gp(V.solid_list[t & 1ull])[base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = id;
+      }
+    }
     if (sn >= 0) {
       R up[3];
       rigid_at<R>(kp((const double*)V.pose[ps]) + kPoseRec * sn, dl, up);
@@ -1035,30 +1102,24 @@ __device__ __forceinline__ void fluid_node(const DomView& V, uint32_t lb, uint64
   }
 }
 
-// LDS of a fluid block: the coupled particles' force sums and, with the
-// bounce-back coupling, a column per thread of link values.
-template <int P, int BS, bool IBB>
-struct FluidLds {
-  unsigned long long dem[6 * kMaxParticles];
-  typename Store<P>::C lv[IBB ? (kQ - 1) * BS : 1];
-};
-
+// Fluid block.  DEM: the coupled particles' force sums of the block in LDS,
+// then in the step's accumulator.  The bounce-back coupling exchanges
+// momentum at its links only, in the link pass: its fluid blocks take the
+// non-DEM form.
 template <int P, int BS, int L, bool DEM, bool IBB = false>
 __device__ __forceinline__ void fluid_block(const DomView& V, uint32_t lb, uint64_t t, bool nt, bool dens,
-                                            FluidLds<P, BS, IBB>& fl) {
-  unsigned long long* dacc = fl.dem;
+                                            unsigned long long* dacc) {
+  static_assert(!(DEM && IBB), "bounce-back links carry the momentum exchange");
   if constexpr (!DEM) {
-    fluid_node<P, BS, L, false, IBB>(V, lb, t, nt, dens, dacc, fl.lv);
+    fluid_node<P, BS, L, false, IBB>(V, lb, t, nt, dens, dacc);
   } else {
     for (int k = threadIdx.x; k < 6 * kMaxParticles; k += BS) dacc[k] = 0ull;
     lds_barrier();
-    fluid_node<P, BS, L, true, IBB>(V, lb, t, nt, dens, dacc, fl.lv);
+    fluid_node<P, BS, L, true, IBB>(V, lb, t, nt, dens, dacc);
     lds_barrier();
     // the block's sums into the step's accumulator (two's-complement adds:
-    // exact, in any order); bounce-back links belong to the particles near
-    // the block at the previous update
+    // exact, in any order)
     unsigned long long bits = V.np > 0 ? kp(V.fcull[pose_slot(t)])[lb] : 0ull;
-    if (IBB && V.np > 0) bits = kp(V.fcull[pose_slot(t - 1)])[lb];
     bits &= V.dem_mask;
     for (int k = threadIdx.x; k < 6 * kMaxParticles; k += BS) {
       const unsigned long long v = dacc[k];

@@ -19,11 +19,11 @@
 
 namespace rwmi {
 
-template <int P, int BS, bool IBB>
+template <int P, int BS>
 union StepLds {
   WalkLds<typename Store<P>::O, BS> walk;
   ProLds pro;
-  FluidLds<P, BS, IBB> fluid;  // coupled particles' force sums, bounce-back link values
+  unsigned long long dem[6 * kMaxParticles];  // fluid blocks with coupled particles
 };
 
 // IP: the domains of the launch stream their lattice in place (else: two
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(step_wa
 k_step(StepArgs a, const DomView* __restrict__ views, const int32_t* __restrict__ boff) {
   // views and boff (the same pointers as in a) are read-only in the launch:
   // as restrict parameters their wave-uniform reads compile to scalar loads
-  __shared__ StepLds<P, BS, IBB> lds;
+  __shared__ StepLds<P, BS> lds;
   int idx = 0;
   const int role = step_role((int)blockIdx.x, a.nb, (a.flags & 1) != 0, idx);
   if (role == kRoleNone) return;
@@ -60,9 +60,9 @@ k_step(StepArgs a, const DomView* __restrict__ views, const int32_t* __restrict_
   else if (role == kRolePro) prologue_block(V, lb, t + 1, BS, lds.pro, (a.flags & kFlagDem) != 0);
   else {
     const bool nt = (a.flags & kFlagNontemporal) != 0, dens = (a.flags & kFlagDensity) != 0;
-    if constexpr (!IP) fluid_block<P, BS, kTwoLattices, DEM, IBB>(V, (uint32_t)lb, t, nt, dens, lds.fluid);
-    else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd, DEM>(V, (uint32_t)lb, t, nt, dens, lds.fluid);
-    else fluid_block<P, BS, kInPlaceEven, DEM>(V, (uint32_t)lb, t, nt, dens, lds.fluid);
+    if constexpr (!IP) fluid_block<P, BS, kTwoLattices, DEM, IBB>(V, (uint32_t)lb, t, nt, dens, lds.dem);
+    else if (t & 1ull) fluid_block<P, BS, kInPlaceOdd, DEM>(V, (uint32_t)lb, t, nt, dens, lds.dem);
+    else fluid_block<P, BS, kInPlaceEven, DEM>(V, (uint32_t)lb, t, nt, dens, lds.dem);
   }
 }
 

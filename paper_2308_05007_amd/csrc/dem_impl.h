@@ -70,6 +70,13 @@ struct DemLds {
   double b[kDemMaxCtrl][3];   // offsets at the current orientation
   double bb[kDemMaxCtrl][3];  // offsets in the body frame
   double k[kDemMaxCtrl];
+  // the particles whose rotated offsets the substeps read (a contact
+  // candidate or a wall within reach), their rotations and the list of their
+  // control points (particle << 16 | point), rotated by all lanes together
+  int need[kMaxParticles];
+  double R[kMaxParticles][9];
+  uint32_t work[kDemMaxCtrl];
+  int nwork;
 };
 
 // ---------------------------------------------------------------- metaball
@@ -383,6 +390,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     S.cosv[s] = cs;
   }
   if (p < 18) S.wu[p / 6][(p / 3) & 1][p % 3] = V.wu[p / 6][(p / 3) & 1][p % 3];
+  if (p < kMaxParticles) S.need[p] = 0;
   const DevParticle* P = live ? V.parts + p : nullptr;
   double* st = live ? A.state + (size_t)kDemState * p : nullptr;
   double c[3] = {0, 0, 0}, v[3] = {0, 0, 0}, q[4] = {1, 0, 0, 0}, L[3] = {0, 0, 0}, w[3] = {0, 0, 0};
@@ -460,6 +468,42 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
       const double* x = A.xiw + ((size_t)p * 6 + k) * 3;
       if (x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0) wnz |= 1u << k;
     }
+  // Rotated offsets are read only by contacts: a particle with a candidate
+  // partner or a wall plane within reach (bounding radius + R_s + the
+  // candidates' margin) at the start of the step has them rotated every
+  // substep, together with its partners; the others only once, after the
+  // last substep (the same values: a rotation depends on q alone).
+  if (cp) {
+    bool wall = false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+      if (G.bc[ax]) {
+        const double reach = (S.rb[p] + A.Rs) + kDemMargin;
+        wall = wall || (c[ax] - 1.0 < reach) || ((double)(G.n[ax] - 1) - c[ax] < reach);
+      }
+    if (nbr || wall) {
+      S.need[p] = 1;
+      unsigned long long bits = nbr;
+      while (bits) {
+        const int j = __ffsll((long long)bits) - 1;
+        bits &= bits - 1ull;
+        S.need[j] = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (p == 0) {
+    int k = 0;
+    for (int i = 0; i < np; ++i)
+      if (S.need[i])
+        for (int m = 0; m < S.nc[i]; ++m) S.work[k++] = ((uint32_t)i << 16) | (uint32_t)(S.c0[i] + m);
+    S.nwork = k;
+  }
+  __syncthreads();
+  const int nwork = S.nwork;
+  const bool need = live && S.need[p] != 0;
+  double Rc[3][3];  // rotation of the current q
+  dem_quat_R(q, Rc);
   for (int s = 0; s < A.nsub; ++s) {
     double F[3], T[3];
     if (cp) {
@@ -579,9 +623,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
           const double Ln = (double)G.n[a];
           c[a] = c[a] - Ln * floor(c[a] / Ln);
         }
-      double R[3][3];
-      dem_quat_R(q, R);
-      dem_omega(R, Ibinv, L, w);
+      dem_omega(Rc, Ibinv, L, w);
       const double w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
       const double hw[3] = {0.5 * dt * w[0], 0.5 * dt * w[1], 0.5 * dt * w[2]};
       const double n0 = w0 - ((hw[0] * w1 + hw[1] * w2) + hw[2] * w3);
@@ -593,14 +635,10 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
       q[1] = n1 / nn;
       q[2] = n2 / nn;
       q[3] = n3 / nn;
-      // offsets at the new orientation from the body-frame control points
-      dem_quat_R(q, R);
-      const int c0 = S.c0[p];
-      for (int i = 0; i < S.nc[p]; ++i) {
-        const double* bb = S.bb[c0 + i];
+      dem_quat_R(q, Rc);
+      if (need)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) S.b[c0 + i][a] = (R[a][0] * bb[0] + R[a][1] * bb[1]) + R[a][2] * bb[2];
-      }
+        for (int a = 0; a < 9; ++a) S.R[p][a] = Rc[a / 3][a % 3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         S.c[p][a] = c[a];
@@ -608,7 +646,27 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
         S.w[p][a] = w[a];
       }
     }
+    if (nwork) {
+      __syncthreads();  // the new rotations are visible
+      // offsets at the new orientation from the body-frame control points
+      for (int k = p; k < nwork; k += blockDim.x) {
+        const uint32_t e = S.work[k];
+        const double* R = S.R[e >> 16];
+        const int i = (int)(e & 0xFFFFu);
+        const double* bb = S.bb[i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) S.b[i][a] = (R[3 * a] * bb[0] + R[3 * a + 1] * bb[1]) + R[3 * a + 2] * bb[2];
+      }
+    }
     __syncthreads();  // the new state is visible to every contact of the next substep
+  }
+  if (cp && !need) {  // offsets at the final orientation
+    const int c0 = S.c0[p];
+    for (int i = 0; i < S.nc[p]; ++i) {
+      const double* bb = S.bb[c0 + i];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) S.b[c0 + i][a] = (Rc[a][0] * bb[0] + Rc[a][1] * bb[1]) + Rc[a][2] * bb[2];
+    }
   }
   if (!live) return;
   // results: state, pose tables of P(t+1), filter sphere, control points

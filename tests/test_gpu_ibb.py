@@ -149,3 +149,33 @@ def test_ibb_coupled_oscillator_full_size(orc, B, precision):
         for p in range(len(cfg["particles"])):
             so, sg = o.dem_state(p), g.particle_state(p)
             assert np.abs(sg["Fh"] - so["Fh"]).max() <= 2e-3 * np.abs(so["Fh"]).max() + 1e-9, p
+
+
+@pytest.mark.parametrize("precision,rel", [("fp16", 0.01), ("bf16", 0.05)])
+def test_ibb_half_storage_within_bounds(orc, B, precision, rel):
+    """FP16 and BF16 storage of the deviations f - w rho0 with bounce-back
+    (moving particles that cover and uncover nodes, 30 steps): a stored
+    deviation of about 3 w rho0 |u| carries a relative rounding of 2^-11
+    (FP16) or 2^-8 (BF16), some 1e-5 and 1e-4 of the flow's velocity scale
+    per step, so after 30 steps the velocities stay within 1% (FP16) and
+    5% (BF16) of the largest velocity at 99.9% of the nodes (the rest being
+    nodes whose solid/fluid status float decides differently) and within 10%
+    everywhere; the densities within the same fractions of the largest
+    density deviation plus 1e-4."""
+    cfg = _ibb(W.config_tiny(n_walkers=200, precision=precision, **CASES["periodic_sinusoid"]))
+    o, g = _pair(orc, B, cfg)
+    print("ibb half storage", precision, flush=True)
+    o.step(cfg["steps"])
+    g.step(cfg["steps"])
+    g.sync()
+    uo = o.fields()["u"]
+    ug, rg = g.velocity()
+    scale = np.abs(uo).max()
+    assert scale > 1e-3
+    err = np.abs(ug - uo).max(axis=0)
+    assert np.count_nonzero(err > rel * scale) <= max(1, 1e-3 * err.size), np.sort(err.ravel())[-5:] / scale
+    assert err.max() <= 0.1 * scale
+    ro = o.fields()["rho"]
+    dscale = np.abs(ro - 1.0).max()
+    rerr = np.abs(rg - ro)
+    assert np.count_nonzero(rerr > rel * dscale + 1e-4) <= max(1, 1e-3 * rerr.size)

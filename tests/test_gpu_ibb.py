@@ -179,3 +179,27 @@ def test_ibb_half_storage_within_bounds(orc, B, precision, rel):
     dscale = np.abs(ro - 1.0).max()
     rerr = np.abs(rg - ro)
     assert np.count_nonzero(rerr > rel * dscale + 1e-4) <= max(1, 1e-3 * rerr.size)
+
+
+def test_ibb_control_points_beyond_the_lds_table(orc, B):
+    """40 particles of 30 control points (1200 in all, more than the link
+    pass holds in LDS, so it reads them from global memory): FP64 bit for
+    bit, with nodes covered and uncovered."""
+    cfg = _ibb(W.config_tiny(n=(24, 20, 22), bc=("periodic",) * 3, n_particles=40, n_walkers=300, amp=1.5,
+                             period=40.0, seed=31, steps=16))
+    rng = np.random.default_rng(77)
+    for p in cfg["particles"]:
+        b, k = W.metaball_shape(rng, 30, 1.0, (0.03, 0.06))
+        p["b"], p["k"] = b, k
+    assert sum(len(p["k"]) for p in cfg["particles"]) > 1024
+    o, g = _pair(orc, B, cfg)
+    print("ibb 1200 control points", flush=True)
+    o.step(8)
+    g.step(8)
+    g.sync()
+    sm1 = _compare_ibb(o, g)
+    o.step(8)
+    g.step(8)
+    g.sync()
+    sm2 = _compare_ibb(o, g)
+    assert (sm2 > 0).any() and np.count_nonzero((sm1 > 0) != (sm2 > 0)) > 0

@@ -133,3 +133,17 @@ def test_oscillator_full_size(orc, B, precision):
             assert np.abs(sg["Fh"] - so["Fh"]).max() <= 2e-3 * np.abs(so["Fh"]).max() + 1e-9, p
             assert np.abs(sg["v"] - so["v"]).max() <= 1e-3 * np.abs(so["v"]).max() + 1e-12, p
             assert np.abs(sg["c"] - so["c"]).max() < 1e-9 + 1e-3 * np.abs(so["v"]).max() * 3
+
+
+@pytest.mark.parametrize("coupling", ["psm", "ibb"])
+def test_sixty_four_coupled_particles(orc, B, coupling):
+    """The largest particle count a domain takes, all two-way coupled (the
+    particle update's one wave of 64 lanes full), with either coupling: the
+    states bit for bit after 4 steps."""
+    cfg = W.config_coupled_oscillator(R=2.0, n_particles=64, n_walkers=2000, steps=4, precision="fp64", seed=5)
+    assert len(cfg["particles"]) == 64
+    if coupling == "ibb":
+        cfg["domain"]["coupling"] = "ibb"
+    o, g = _run(orc, B, cfg, 4, chunks=2)
+    _same_states(o, g, cfg)
+    compare(o, g, f=False)

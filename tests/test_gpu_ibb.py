@@ -203,3 +203,17 @@ def test_ibb_control_points_beyond_the_lds_table(orc, B):
     g.sync()
     sm2 = _compare_ibb(o, g)
     assert (sm2 > 0).any() and np.count_nonzero((sm1 > 0) != (sm2 > 0)) > 0
+
+
+def test_ibb_without_particles_is_plain_bgk(orc, B):
+    """No particle at all: nothing is ever solid, the link pass finds no
+    link, and the bounce-back domain advances exactly as the oracle's (and
+    as plain BGK with walls and a body force)."""
+    cfg = _ibb(W.config_tiny(n=(13, 11, 9), bc=("periodic", "wall", "periodic"), n_particles=0, n_walkers=100,
+                             steps=12, wall_u=((0, 0, 0, 0.01, 0, 0, 0, 0, 0), (0, 0, 0, 0, 0, 0, 0, 0, 0))))
+    o, g = _pair(orc, B, cfg)
+    o.step(12)
+    g.step(12)
+    g.sync()
+    sm = _compare_ibb(o, g)
+    assert not (sm > 0).any()

@@ -3,7 +3,7 @@
 // `streams` arrays and writes one float to each of as many; one launch
 // moves 8 * streams * n bytes.  It measures what this GPU's memory system
 // delivers to a pattern of that many concurrent read and write streams, the
-// ceiling against which the lattice update's bandwidth is judged.
+// ceiling the lattice update's bandwidth is compared with.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

@@ -12,6 +12,8 @@ moving walls and a body force on ragged lattices; a static particle in a
 driven flow; coupled particles that collide; 130 steps through a captured
 graph; the coupled oscillator of Sec. 4 at full size.  FP32 within bounds
 derived from the float rounding of the stored populations."""
+import math
+
 import numpy as np
 import pytest
 
@@ -217,3 +219,54 @@ def test_ibb_without_particles_is_plain_bgk(orc, B):
     g.sync()
     sm = _compare_ibb(o, g)
     assert not (sm > 0).any()
+
+
+def _array_flow(B, coupling, R, L=48, f=1e-7, tau=0.8, steps=30000):
+    """Mean velocity of body-force-driven flow through a simple cubic array
+    of spheres (one static one-point metaball, M = R^2 / r^2, in a periodic
+    L^3 box), extrapolated to the steady state by Aitken's delta-squared over
+    the last three samples (the mean flow approaches it as one exponential,
+    time constant about 6000 steps here)."""
+    dom = W._domain((L, L, L), ("periodic",) * 3, tau, (f, 0, 0), 0.0, seed=1, precision="fp64")
+    if coupling == "ibb":
+        dom["coupling"] = "ibb"
+    cfg = dict(name="array", domain=dom, walkers=dict(kind="uniform", n=0), steps=steps,
+               particles=[dict(b=np.zeros((1, 3)), k=np.array([R * R]), centre=np.array([L / 2] * 3),
+                               motion="static")])
+    g = B.build_domain(cfg, device=0)
+    g.set("use_graph", 1)
+    us = []
+    for _ in range(steps // 2000):
+        g.step(2000)
+        g.sync()
+        us.append(float(g.velocity()[0][0].mean()))
+    g.close()
+    a, b, c = us[-3:]
+    return (a * c - b * b) / (a + c - 2 * b)
+
+
+@pytest.mark.parametrize("R", [4.0, 6.0])
+def test_sphere_array_drag_against_sangani_acrivos(B, R):
+    """The comparison the bounce-back coupling was built for (Sec. 2.4.3,
+    the paper's own coupling against partially saturated cells): Stokes flow
+    (Re < 0.1) through a simple cubic array of spheres of volume fraction phi,
+    whose drag F = 6 pi mu R U K(phi) has the dilute expansion of Sangani and
+    Acrivos (1982), 1/K = 1 - 1.7601 phi^(1/3) + phi - 1.5593 phi^2 +
+    3.9799 phi^(8/3) - 3.0734 phi^(10/3); the body force on the fluid
+    f L^3 (1 - phi) balances it.  Bounce-back gives the mean velocity U
+    within 1.5% of the closed form (0.25% and 0.65% measured at R = 4 and 6),
+    partially saturated cells within 6% (4.0% and 2.9% too fast), and
+    bounce-back is the closer of the two."""
+    L, f, tau = 48, 1e-7, 0.8
+    mu = (tau - 0.5) / 3.0
+    phi = 4.0 / 3.0 * math.pi * R ** 3 / L ** 3
+    K = 1.0 / (1 - 1.7601 * phi ** (1 / 3) + phi - 1.5593 * phi ** 2 + 3.9799 * phi ** (8 / 3)
+               - 3.0734 * phi ** (10 / 3))
+    U = f * L ** 3 * (1 - phi) / (6 * math.pi * mu * R * K)
+    print("sphere array R", R, flush=True)
+    ui = _array_flow(B, "ibb", R)
+    up = _array_flow(B, "psm", R)
+    assert abs(ui / U - 1) < 0.015, (ui / U, up / U)
+    assert abs(up / U - 1) < 0.06, (ui / U, up / U)
+    assert abs(ui / U - 1) < abs(up / U - 1)
+    assert U * 2 * R / mu < 0.1  # Reynolds number (rho = 1)

@@ -408,32 +408,38 @@ def bench_streams(args):
     """The lattice update's memory pattern without its arithmetic or
     neighbour shifts (rwmi_stream_probe): 1, 2, 4, 8 and 19 read and as many
     write streams of 2^24 floats each (one 256^3 lattice's node count), as
-    planes and in tiles of 256 nodes, 20 timed launches each.  The 1- and
-    2-stream cases (64 and 128 MB each way) fit the memory-side cache."""
+    planes and in tiles of 256 nodes, and 4, 8 and 19 streams of halves in
+    tiles (the 16-bit storage modes), 20 timed launches each.  The 1- and
+    2-stream float cases (64 and 128 MB each way) fit the memory-side
+    cache."""
     import torch
     from paper_2308_05007_amd import binding as B
     B.lib()
     n = 1 << 24
-    src = torch.rand(19 * n, device="cuda")
-    dst = torch.empty_like(src)
+    src32 = torch.rand(19 * n, device="cuda")
+    dst32 = torch.empty_like(src32)
     s = torch.cuda.current_stream()
     out = {}
-    for streams in (1, 2, 4, 8, 19):
-        for tiled in (0, 1):
-            a, b = src[:streams * n], dst[:streams * n]
-            for _ in range(3):
-                B.stream_probe(streams, tiled, a, b, s)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            for _ in range(20):
-                B.stream_probe(streams, tiled, a, b, s)
-            e1.record(s)
-            torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) * 1e3 / 20
-            out["%d_%s" % (streams, "tiled" if tiled else "planes")] = {
-                "us_per_launch": round(us, 2), "bytes": 8 * streams * n,
-                "GB_per_s": round(8 * streams * n / us / 1e3, 1)}
-    print(json.dumps({"metric": "stream pattern bandwidth (reads + writes of 2^24 floats per stream)",
+    cases = [(st, t, 4) for st in (1, 2, 4, 8, 19) for t in (0, 1)] + [(st, 1, 2) for st in (4, 8, 19)]
+    src16 = dst16 = None
+    for streams, tiled, elem in cases:
+        if elem == 2 and src16 is None:
+            src16, dst16 = src32.half(), torch.empty_like(src32, dtype=torch.float16)
+        src, dst = (src32, dst32) if elem == 4 else (src16, dst16)
+        a, b = src[:streams * n], dst[:streams * n]
+        for _ in range(3):
+            B.stream_probe(streams, tiled, a, b, s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(20):
+            B.stream_probe(streams, tiled, a, b, s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 20
+        key = "%d_%s" % (streams, "tiled" if tiled else "planes") + ("" if elem == 4 else "_16bit")
+        out[key] = {"us_per_launch": round(us, 2), "bytes": 2 * elem * streams * n,
+                    "GB_per_s": round(2 * elem * streams * n / us / 1e3, 1)}
+    print(json.dumps({"metric": "stream pattern bandwidth (reads + writes of 2^24 elements per stream)",
                       "unit": "GB/s", "peak": HBM_PEAK_GBS, "results": out}), flush=True)
 
 

@@ -476,16 +476,19 @@ rwmi_status rwmi_device_normals(int32_t device, uint64_t seed, uint32_t t, uint3
 
 /* Bandwidth probe of the lattice update's memory pattern without its
  * arithmetic or neighbour shifts: one launch on `stream` (a hipStream_t;
- * NULL: the null stream) in which each of n nodes reads one float from each
- * of `streams` arrays of src and writes one float to each of as many arrays
- * of dst, 8 * streams * n bytes in all.  tiled = 0: array i of node k at
- * i * n + k; tiled = 1: in tiles of 256 nodes, the tile's 256 values of
- * array 0, then of array 1, and so on (the distributions' two-lattice
- * layout).  src and dst are device buffers of streams * n floats owned by
- * the caller.  Asynchronous: returns after the launch.  EINVAL unless
- * streams is 1, 2, 4, 8 or 19, n is a positive multiple of 256 below 2^32
- * and both pointers are non-NULL; EDEVICE if the launch fails. */
-rwmi_status rwmi_stream_probe(int32_t streams, int32_t tiled, uint64_t n, const float* src, float* dst, void* stream);
+ * NULL: the null stream) in which each of n nodes reads one element from
+ * each of `streams` arrays of src and writes one to each of as many arrays
+ * of dst, 2 * elem_bytes * streams * n bytes in all.  Elements are floats
+ * (elem_bytes 4) or IEEE halves (2, the 16-bit storage modes).  tiled = 0:
+ * array i of node k at i * n + k; tiled = 1: in tiles of 256 nodes, the
+ * tile's 256 values of array 0, then of array 1, and so on (the
+ * distributions' two-lattice layout).  src and dst are device buffers of
+ * streams * n elements owned by the caller.  Asynchronous: returns after
+ * the launch.  EINVAL unless streams is 1, 2, 4, 8 or 19, elem_bytes is 4
+ * or 2, n is a positive multiple of 256 below 2^32 and both pointers are
+ * non-NULL; EDEVICE if the launch fails. */
+rwmi_status rwmi_stream_probe(int32_t streams, int32_t elem_bytes, int32_t tiled, uint64_t n, const void* src,
+                              void* dst, void* stream);
 
 #ifdef __cplusplus
 }

@@ -128,7 +128,8 @@ SIGNATURES = {
     "rwmi_gaussian_fit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rwmi_device_normals": (C.c_int, [C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p]),
-    "rwmi_stream_probe": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rwmi_stream_probe": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
     "rwmi_dispersion_fit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_double, C.c_double,
                                       C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]),
@@ -570,10 +571,11 @@ def device_normals(seed, t, purpose, n, device=0):
 
 def stream_probe(streams, tiled, src, dst, stream=None):
     """One launch of the bandwidth probe on device tensors src and dst of
-    streams * n floats each (n = src.numel() // streams), on `stream` (a
-    torch stream; default the current one)."""
+    streams * n floats or halves each (n = src.numel() // streams), on
+    `stream` (a torch stream; default the current one)."""
     import torch
     n = src.numel() // int(streams)
     s = stream if stream is not None else torch.cuda.current_stream()
-    _check(lib().rwmi_stream_probe(int(streams), int(bool(tiled)), n, C.c_void_p(src.data_ptr()),
-                                   C.c_void_p(dst.data_ptr()), C.c_void_p(s.cuda_stream)))
+    _check(lib().rwmi_stream_probe(int(streams), int(src.element_size()), int(bool(tiled)), n,
+                                   C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                   C.c_void_p(s.cuda_stream)))

@@ -17,7 +17,8 @@
 
 namespace rwmi {
 // the bandwidth probe (probe.hip)
-hipError_t launch_stream_probe(int streams, bool tiled, uint64_t n, const float* src, float* dst, hipStream_t s);
+hipError_t launch_stream_probe(int streams, int elem, bool tiled, uint64_t n, const void* src, void* dst,
+                               hipStream_t s);
 }
 
 using rwmi::DevParticle;
@@ -1477,12 +1478,14 @@ rwmi_status rwmi_device_normals(int32_t device, uint64_t seed, uint32_t t, uint3
   return RWMI_OK;
 }
 
-rwmi_status rwmi_stream_probe(int32_t streams, int32_t tiled, uint64_t n, const float* src, float* dst, void* stream) {
+rwmi_status rwmi_stream_probe(int32_t streams, int32_t elem_bytes, int32_t tiled, uint64_t n, const void* src,
+                              void* dst, void* stream) {
   if (!src || !dst) return fail(nullptr, RWMI_EINVAL, "null buffer");
   if (!(streams == 1 || streams == 2 || streams == 4 || streams == 8 || streams == 19))
     return fail(nullptr, RWMI_EINVAL, "streams must be 1, 2, 4, 8 or 19");
+  if (elem_bytes != 4 && elem_bytes != 2) return fail(nullptr, RWMI_EINVAL, "elem_bytes must be 4 or 2");
   if (n == 0 || n % 256 != 0 || n >= (1ull << 32)) return fail(nullptr, RWMI_EINVAL, "n must be a positive multiple of 256 below 2^32");
-  const hipError_t e = rwmi::launch_stream_probe(streams, tiled != 0, n, src, dst, (hipStream_t)stream);
+  const hipError_t e = rwmi::launch_stream_probe(streams, elem_bytes, tiled != 0, n, src, dst, (hipStream_t)stream);
   if (e != hipSuccess) return fail(nullptr, RWMI_EDEVICE, "stream probe: %s", hipGetErrorString(e));
   return RWMI_OK;
 }

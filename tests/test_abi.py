@@ -97,7 +97,10 @@ def test_stream_probe_rejects_bad_arguments_before_any_launch():
     from paper_2308_05007_amd import binding as B
     L = B.lib()
     buf = C.c_void_p(16)  # never dereferenced: every case fails its checks first
-    for streams, n, src in ((3, 256, buf), (19, 300, buf), (19, 0, buf), (4, 1 << 32, buf), (4, 256, None)):
-        assert L.rwmi_stream_probe(streams, 1, n, src, buf, None) == B.RWMI_EINVAL
-    assert L.rwmi_stream_probe(5, 0, 256, buf, buf, None) == B.RWMI_EINVAL
+    for streams, elem, n, src in ((3, 4, 256, buf), (19, 4, 300, buf), (19, 2, 0, buf), (4, 4, 1 << 32, buf),
+                                  (4, 4, 256, None), (4, 8, 256, buf), (4, 1, 256, buf)):
+        assert L.rwmi_stream_probe(streams, elem, 1, n, src, buf, None) == B.RWMI_EINVAL
+    assert L.rwmi_stream_probe(5, 4, 0, 256, buf, buf, None) == B.RWMI_EINVAL
     assert "streams" in L.rwmi_last_error(None).decode()
+    assert L.rwmi_stream_probe(4, 3, 0, 256, buf, buf, None) == B.RWMI_EINVAL
+    assert "elem_bytes" in L.rwmi_last_error(None).decode()

@@ -77,6 +77,7 @@ struct DemLds {
   double R[kMaxParticles][9];
   uint32_t work[kDemMaxCtrl];
   int nwork;
+  double F[kMaxParticles][3];  // force of the substep, for the translation wave
 };
 
 // ---------------------------------------------------------------- metaball
@@ -367,8 +368,14 @@ __device__ __forceinline__ void dem_omega(const double R[3][3], const double* Ib
 
 // The particle update of step t = tstep + j (t -> t+1).  Launch: one block
 // of 64 threads per domain.
+// Two waves of 64 lanes, lane p of each for particle p: the first finds the
+// contacts and forces, integrates the rotation and writes the results; the
+// second integrates the translation (v, c), which depends on the rotation
+// of no substep, so the two chains of a substep run side by side.
 __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, uint64_t t, DemLds& S) {
-  const int p = threadIdx.x;
+  const int tid = threadIdx.x;
+  const bool main = tid < kMaxParticles;  // contacts, rotation, results
+  const int p = tid & (kMaxParticles - 1);
   const int np = V.np;
   const unsigned long long dmask = V.dem_mask;
   DemGeom G;
@@ -381,7 +388,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   const bool cp = live && ((dmask >> p) & 1ull);
   // the drive of every substep of the step, in parallel
   const double dt = 1.0 / (double)A.nsub;
-  for (int s = p; s < A.nsub; s += blockDim.x) {
+  for (int s = tid; s < A.nsub; s += blockDim.x) {
     const double tau = (double)t + (double)s * dt;
     double ph = tau / A.drive_period;
     ph = ph - floor(ph);
@@ -389,14 +396,22 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     sincos_turns(ph, sn, cs);
     S.cosv[s] = cs;
   }
-  if (p < 18) S.wu[p / 6][(p / 3) & 1][p % 3] = V.wu[p / 6][(p / 3) & 1][p % 3];
-  if (p < kMaxParticles) S.need[p] = 0;
+  if (tid < 18) S.wu[tid / 6][(tid / 3) & 1][tid % 3] = V.wu[tid / 6][(tid / 3) & 1][tid % 3];
+  if (main) S.need[p] = 0;
   const DevParticle* P = live ? V.parts + p : nullptr;
   double* st = live ? A.state + (size_t)kDemState * p : nullptr;
   double c[3] = {0, 0, 0}, v[3] = {0, 0, 0}, q[4] = {1, 0, 0, 0}, L[3] = {0, 0, 0}, w[3] = {0, 0, 0};
   double Fh[3] = {0, 0, 0}, Th[3] = {0, 0, 0}, mass = 1.0, Ibinv[9];
   const int sl = pose_slot(t);  // slot of the control points at P(t)
-  if (cp) {
+  if (cp && !main) {  // the translation wave
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c[a] = st[kDc + a];
+      v[a] = st[kDv + a];
+    }
+    mass = st[kDm];
+  }
+  if (cp && main) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       c[a] = st[kDc + a];
@@ -418,7 +433,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = 0ull;  // for the next fluid step
   }
-  if (live) {
+  if (live && main) {
     const int c0 = P->ctrl0, nc = P->nc;
     S.nc[p] = nc;
     S.c0[p] = c0;
@@ -445,7 +460,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   // (xnz: the partners whose spring may be nonzero)
   unsigned long long nbr = 0ull, xnz = 0ull;
   const double cstart[3] = {c[0], c[1], c[2]};
-  if (cp) {
+  if (cp && main) {
     for (int j = 0; j < np; ++j) {
       if (j == p || !((dmask >> j) & 1ull)) continue;
       double dc[3];
@@ -463,7 +478,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     }
   }
   unsigned wnz = 0u;  // walls whose spring may be nonzero (bit 2 axis + side)
-  if (cp)
+  if (cp && main)
     for (int k = 0; k < 6; ++k) {
       const double* x = A.xiw + ((size_t)p * 6 + k) * 3;
       if (x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0) wnz |= 1u << k;
@@ -473,7 +488,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   // candidates' margin) at the start of the step has them rotated every
   // substep, together with its partners; the others only once, after the
   // last substep (the same values: a rotation depends on q alone).
-  if (cp) {
+  if (cp && main) {
     bool wall = false;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
@@ -492,7 +507,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     }
   }
   __syncthreads();
-  if (p == 0) {
+  if (tid == 0) {
     int k = 0;
     for (int i = 0; i < np; ++i)
       if (S.need[i])
@@ -506,7 +521,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   dem_quat_R(q, Rc);
   for (int s = 0; s < A.nsub; ++s) {
     double F[3], T[3];
-    if (cp) {
+    if (cp && main) {
       const double cs = S.cosv[s];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -609,13 +624,15 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
         }
       }
     }
+    if (cp && main)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) S.F[p][a] = F[a];
     __syncthreads();  // every contact of the substep has read the shared state
-    if (cp) {
+    if (cp && !main) {  // translation
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        v[a] = v[a] + (F[a] / mass) * dt;
+        v[a] = v[a] + (S.F[p][a] / mass) * dt;
         c[a] = c[a] + v[a] * dt;
-        L[a] = L[a] + T[a] * dt;
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -623,6 +640,15 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
           const double Ln = (double)G.n[a];
           c[a] = c[a] - Ln * floor(c[a] / Ln);
         }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        S.c[p][a] = c[a];
+        S.v[p][a] = v[a];
+      }
+    }
+    if (cp && main) {  // rotation
+#pragma unroll
+      for (int a = 0; a < 3; ++a) L[a] = L[a] + T[a] * dt;
       dem_omega(Rc, Ibinv, L, w);
       const double w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
       const double hw[3] = {0.5 * dt * w[0], 0.5 * dt * w[1], 0.5 * dt * w[2]};
@@ -640,16 +666,12 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
 #pragma unroll
         for (int a = 0; a < 9; ++a) S.R[p][a] = Rc[a / 3][a % 3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        S.c[p][a] = c[a];
-        S.v[p][a] = v[a];
-        S.w[p][a] = w[a];
-      }
+      for (int a = 0; a < 3; ++a) S.w[p][a] = w[a];
     }
     if (nwork) {
       __syncthreads();  // the new rotations are visible
       // offsets at the new orientation from the body-frame control points
-      for (int k = p; k < nwork; k += blockDim.x) {
+      for (int k = tid; k < nwork; k += blockDim.x) {
         const uint32_t e = S.work[k];
         const double* R = S.R[e >> 16];
         const int i = (int)(e & 0xFFFFu);
@@ -660,6 +682,13 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     }
     __syncthreads();  // the new state is visible to every contact of the next substep
   }
+  if (!main) return;
+  if (cp)  // the translation wave's final centre and velocity
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c[a] = S.c[p][a];
+      v[a] = S.v[p][a];
+    }
   if (cp && !need) {  // offsets at the final orientation
     const int c0 = S.c0[p];
     for (int i = 0; i < S.nc[p]; ++i) {

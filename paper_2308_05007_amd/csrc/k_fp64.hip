@@ -72,7 +72,8 @@ hipError_t launch_step_p64(int bs, const StepArgs& a, hipStream_t s) {
 
 // The particle update of step tstep + j of domain views[0]: one block of 64
 // threads (one per particle).
-__global__ void __launch_bounds__(64) k_dem(const DomView* __restrict__ views, const DemArgs* __restrict__ da,
+__global__ void __launch_bounds__(2 * kMaxParticles) k_dem(const DomView* __restrict__ views,
+                                                          const DemArgs* __restrict__ da,
                                             int32_t j) {
   __shared__ DemLds S;
   const DomView& V = views[0];
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(64) k_dem_tables(const DomView* __restrict__ v
 }
 
 hipError_t launch_dem(const DomView* v, const void* dem_args, int32_t j, hipStream_t s) {
-  k_dem<<<1, 64, 0, s>>>(v, (const DemArgs*)dem_args, j);
+  k_dem<<<1, 2 * kMaxParticles, 0, s>>>(v, (const DemArgs*)dem_args, j);
   return hipGetLastError();
 }
 

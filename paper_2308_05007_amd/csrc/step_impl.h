@@ -29,15 +29,21 @@ union StepLds {
 // IP: the domains of the launch stream their lattice in place (else: two
 // lattices); one instantiation per layout keeps each kernel's registers to
 // the paths it can take.
-#ifndef RWMI_STEP_WAVES_PER_EU
-#define RWMI_STEP_WAVES_PER_EU 8
+#ifndef RWMI_STEP_WAVES_PER_EU_32
+#define RWMI_STEP_WAVES_PER_EU_32 6
 #endif
-// Waves per SIMD the register allocation must leave room for.  Float
-// collision: 8 (64 VGPRs) spills a few registers of the rarely taken paths
-// to scratch and measured at least as fast as 7 (72 VGPRs, no spill) or the
-// unconstrained 78.  FP64 needs about twice the registers: no constraint.
+#ifndef RWMI_STEP_WAVES_PER_EU_16
+#define RWMI_STEP_WAVES_PER_EU_16 8
+#endif
+// Waves per SIMD the register allocation must leave room for, measured on
+// the 256^3 oscillator.  FP32 storage: 6 (69 VGPRs, 7 waves, no spill) runs
+// the step in 609 us against 621 us at 8 (63 VGPRs and a few spills to
+// scratch); 16-bit storage the other way round, 413 us at 8 against 431 us
+// at 6.  FP64 needs about twice the registers: no constraint.
 template <int P, bool IBB = false>
-constexpr int step_waves_per_eu() { return P == P64 ? 1 : RWMI_STEP_WAVES_PER_EU; }
+constexpr int step_waves_per_eu() {
+  return P == P64 ? 1 : (P == P32 ? RWMI_STEP_WAVES_PER_EU_32 : RWMI_STEP_WAVES_PER_EU_16);
+}
 
 // DEM: the launch's domains have two-way coupled particles (the fluid
 // blocks accumulate the hydrodynamic force and torque on them).  IBB: they

@@ -404,7 +404,10 @@ const char* rwmi_last_error(const rwmi_domain* dom);
  * from a hipGraph.  Members keep their state and ownership; results of a
  * domain are bit-identical to stepping it alone (same arithmetic per node and
  * per walker).  Members must live on the batch device; their own streams are
- * synchronised before each batch step. */
+ * synchronised before each batch step.  rwmi_batch_add returns EINVAL for a
+ * domain with two-way coupled particles (rwmi_set_coupling) or with the
+ * bounce-back coupling (rwmi_set_fluid_coupling): such domains step alone,
+ * and ESTATE for a domain already in a batch. */
 rwmi_status rwmi_batch_create(int32_t device, void* stream, rwmi_batch** out);
 rwmi_status rwmi_batch_add(rwmi_batch* b, rwmi_domain* dom);
 rwmi_status rwmi_batch_remove(rwmi_batch* b, rwmi_domain* dom);

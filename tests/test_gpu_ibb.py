@@ -270,3 +270,24 @@ def test_sphere_array_drag_against_sangani_acrivos(B, R):
     assert abs(up / U - 1) < 0.06, (ui / U, up / U)
     assert abs(ui / U - 1) < abs(up / U - 1)
     assert U * 2 * R / mu < 0.1  # Reynolds number (rho = 1)
+
+
+@pytest.mark.parametrize("kind", ["ibb", "coupled"])
+def test_batches_refuse_coupled_domains(B, kind):
+    """A domain with the bounce-back coupling or with two-way coupled
+    particles steps alone: adding it to a batch is EINVAL, and the batch
+    still steps its other members."""
+    cfg = _ibb(W.config_tiny()) if kind == "ibb" else W.config_coupled_small(n_walkers=100, steps=2)
+    d = B.build_domain(cfg, device=0)
+    plain = B.build_domain(W.config_tiny(precision="fp32"), device=0)
+    b = B.Batch()
+    with pytest.raises(B.RwmiError) as e:
+        b.add(d)
+    assert e.value.status == B.RWMI_EINVAL
+    b.add(plain)
+    b.step(2)
+    b.sync()
+    b.remove(plain)
+    b.close()
+    plain.close()
+    d.close()

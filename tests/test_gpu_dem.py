@@ -147,3 +147,30 @@ def test_sixty_four_coupled_particles(orc, B, coupling):
     o, g = _run(orc, B, cfg, 4, chunks=2)
     _same_states(o, g, cfg)
     compare(o, g, f=False)
+
+
+@pytest.mark.parametrize("precision,eps", [("fp16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("gap", [2.0, None])
+def test_coupled_half_storage_within_bounds(orc, B, precision, eps, gap):
+    """Coupled particles over a lattice stored in FP16 or BF16 (particle
+    update in FP64), 20 steps, with and without the collision: each stored
+    deviation carries a relative rounding of eps = 2^-11 (FP16) or 2^-8
+    (BF16), and so do the exchange terms the force sums, so the force stays
+    within 4 eps of its scale, the velocities within 2 eps of theirs, the
+    positions within 1e-3 cells and the fluid velocity within 4 eps of its
+    largest value (measured: at most a fifth of these)."""
+    kw = dict(gap=gap) if gap is not None else {}
+    cfg = W.config_coupled_small(seed=3, precision=precision, n_walkers=1000, steps=20, **kw)
+    o, g = _pair(orc, B, cfg)
+    print("coupled", precision, "gap", gap, flush=True)
+    o.step(20)
+    g.step(20)
+    g.sync()
+    for p in _coupled(cfg):
+        so, sg = o.dem_state(p), g.particle_state(p)
+        assert np.abs(sg["Fh"] - so["Fh"]).max() <= 4 * eps * np.abs(so["Fh"]).max() + 1e-12, p
+        assert np.abs(sg["v"] - so["v"]).max() <= 2 * eps * np.abs(so["v"]).max() + 1e-12, p
+        assert np.abs(sg["c"] - so["c"]).max() < 1e-3, p
+    uo = o.fields()["u"]
+    ug, _ = g.velocity()
+    assert np.abs(ug - uo).max() <= 4 * eps * np.abs(uo).max()

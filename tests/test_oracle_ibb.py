@@ -5,6 +5,12 @@ Eq. 23-27).
     the wall velocity at the wall point, u_d is the profile's value at the
     departure point x_f + (1 - 2q) e_i (the point a population leaves to
     return to x_f after one step), for every q in (0, 1] on both branches;
+  - Eq. 25 on a quadratic profile: each of its two interpolants is linear
+    interpolation between two of x_ff, x_f and the wall point, so it misses
+    the profile at the departure point by the Lagrange remainder
+    h (s - s0)(s - s1) of its own two points; u_d must be the paper's 1/3 -
+    2/3 weighting of those two values (a swapped or equal split, or a
+    stencil on the wrong point, fails: tried on planted copies);
   - q: for a one-point metaball (a sphere) the link's fraction is the root
     of the link-sphere quadratic;
   - Eq. 23-24 and 27: a uniform flow with a particle moving at the same
@@ -17,10 +23,9 @@ Eq. 23-27).
     against its motion with no side force;
   - the link value depends on the fluid-side neighbour x_f + e_i and not on
     x_f + 2 e_i or the solid node.
-Eleven mistakes planted in copies of the oracle were tried; two pass every
-pin and are parity unpinned: the 1/3 - 2/3 split of Eq. 25 (any convex split
-is exact on the linear profiles the pin uses) and the Galilean-invariant
-terms of the exchange (of order u_w^2 in these flows).
+Of the mistakes planted in copies of the oracle, one passes every pin and
+is parity unpinned: dropping the Galilean-invariant terms of the exchange
+(of order u_w^2 in these flows).
 """
 import math
 
@@ -37,6 +42,23 @@ def test_ud_is_the_linear_profile_at_the_departure_point(orc):
         uff = uf - g  # and at x_ff, s = -1
         ud = orc.ibb_ud(q, uf, uff, uw)
         ref = uf + g * (2 * q - 1)
+        assert np.abs(ud - ref).max() < 1e-15, (q, ud, ref)
+
+
+def test_ud_weights_the_two_interpolants_one_third_two_thirds(orc):
+    rng = np.random.default_rng(21)
+    for q in list(rng.uniform(0.01, 1.0, 40)) + [0.5, 1.0, 0.25, 0.75]:
+        uf, g, h = (rng.normal(0, 0.05, 3) for _ in range(3))
+
+        def u(s):  # quadratic along the link; s = 0 at x_f, -1 at x_ff
+            return uf + g * s + h * s * s
+
+        sd = 2 * q - 1  # the departure point
+        s0, s1 = (-1.0, 0.0) if q <= 0.5 else (0.0, q)
+        first = u(sd) - h * (sd - s0) * (sd - s1)  # from x_ff, x_f or x_f, wall
+        second = u(sd) - h * (sd + 1.0) * (sd - q)  # from x_ff and the wall
+        ud = orc.ibb_ud(q, u(0.0), u(-1.0), u(q))
+        ref = first / 3 + 2 * second / 3
         assert np.abs(ud - ref).max() < 1e-15, (q, ud, ref)
 
 

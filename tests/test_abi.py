@@ -104,3 +104,26 @@ def test_stream_probe_rejects_bad_arguments_before_any_launch():
     assert "streams" in L.rwmi_last_error(None).decode()
     assert L.rwmi_stream_probe(4, 3, 0, 256, buf, buf, None) == B.RWMI_EINVAL
     assert "elem_bytes" in L.rwmi_last_error(None).decode()
+
+
+def build_c_client(out_dir):
+    """Compile tests/helpers/abi_client.c, a client of the ABI in plain C99
+    (no Python, no PyTorch), against include/rwmi.h and librwmi.so."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    pkg = os.path.join(ROOT, "paper_2308_05007_amd")
+    exe = os.path.join(str(out_dir), "abi_client")
+    subprocess.check_call([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                           "-I" + os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "helpers", "abi_client.c"),
+                           "-L" + pkg, "-lrwmi", "-Wl,-rpath," + pkg, "-o", exe])
+    return exe
+
+
+def test_header_is_c99_and_a_c_client_links(tmp_path):
+    from paper_2308_05007_amd import binding as B
+    B.lib()  # the library is built
+    exe = build_c_client(tmp_path)
+    assert os.access(exe, os.X_OK)

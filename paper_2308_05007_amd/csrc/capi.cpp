@@ -1026,6 +1026,7 @@ rwmi_status rwmi_set_coupling(rwmi_domain* d, const rwmi_coupling_desc* c) {
   if ((st = alloc_into(d, A.state, sizeof(double) * state.size())) != RWMI_OK ||
       (st = alloc_into(d, A.xi, sizeof(double) * 3 * rwmi::kMaxParticles * rwmi::kMaxParticles)) != RWMI_OK ||
       (st = alloc_into(d, A.xiw, sizeof(double) * 3 * 6 * rwmi::kMaxParticles)) != RWMI_OK ||
+      (st = alloc_into(d, A.xmask, sizeof(unsigned long long) * rwmi::kMaxParticles)) != RWMI_OK ||
       (st = alloc_into(d, acc, sizeof(unsigned long long) * 6 * np)) != RWMI_OK ||
       (st = alloc_into(d, d->dem_dev, sizeof(rwmi::DemArgs))) != RWMI_OK)
     return st;
@@ -1041,6 +1042,7 @@ rwmi_status rwmi_set_coupling(rwmi_domain* d, const rwmi_coupling_desc* c) {
   }
   HIPCHK(d, hipMemsetAsync(A.xi, 0, sizeof(double) * 3 * rwmi::kMaxParticles * rwmi::kMaxParticles, d->stream));
   HIPCHK(d, hipMemsetAsync(A.xiw, 0, sizeof(double) * 3 * 6 * rwmi::kMaxParticles, d->stream));
+  HIPCHK(d, hipMemsetAsync(A.xmask, 0, sizeof(unsigned long long) * rwmi::kMaxParticles, d->stream));
   HIPCHK(d, hipMemsetAsync(acc, 0, sizeof(unsigned long long) * 6 * np, d->stream));
   HIPCHK(d, hipMemcpyAsync(A.state, state.data(), sizeof(double) * state.size(), hipMemcpyHostToDevice, d->stream));
   HIPCHK(d, hipMemcpyAsync(d->dem_dev, &A, sizeof A, hipMemcpyHostToDevice, d->stream));

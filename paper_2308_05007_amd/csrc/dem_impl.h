@@ -50,6 +50,7 @@ struct DemArgs {
   double* state;                // [np][kDemState]
   double* xi;                   // [64][64][3] tangential springs, row p owned by thread p
   double* xiw;                  // [64][6][3] wall springs (axis, side)
+  unsigned long long* xmask;    // [64] bit j of row p: spring (p, j) may be nonzero
   double* ctrlr[3];             // writable views of DomView::ctrlr / ctrlr_f
   float* ctrlr_f[3];
 };
@@ -74,6 +75,7 @@ struct DemLds {
   // candidate or a wall within reach), their rotations and the list of their
   // control points (particle << 16 | point), rotated by all lanes together
   int need[kMaxParticles];
+  unsigned long long nbr2[kMaxParticles];  // candidates found by the second wave
   double R[kMaxParticles][9];
   uint32_t work[kDemMaxCtrl];
   int nwork;
@@ -184,17 +186,21 @@ struct DemGeom {
   int n[3], bc[3];
 };
 
-// Minimum image of the displacement c_j - c_i on periodic axes.
+// Minimum image of the displacement c_j - c_i on periodic axes.  Within a
+// quarter period the image shift floor(dc / L + 0.5) is 0 (the quotient
+// rounds into (-0.25, 0.25) at worst to +-0.25), and dc - L * 0 is dc bit for
+// bit, so the division is skipped there.
 __device__ __forceinline__ void dem_disp(const DemGeom& V, const double ci[3], const double cj[3], double dc[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     dc[a] = cj[a] - ci[a];
     if (!V.bc[a]) {
       const double L = (double)V.n[a];
-      dc[a] = dc[a] - L * floor(dc[a] / L + 0.5);
+      if (!(fabs(dc[a]) < 0.25 * L)) dc[a] = dc[a] - L * floor(dc[a] / L + 0.5);
     }
   }
 }
+
 
 // Contact of particles i < j (Eq. 6-9).  True with the contact point as an
 // offset from c_i, the normal from i's inner point to j's and the overlap.
@@ -433,21 +439,24 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = 0ull;  // for the next fluid step
   }
-  if (live && main) {
-    const int c0 = P->ctrl0, nc = P->nc;
-    S.nc[p] = nc;
-    S.c0[p] = c0;
-    S.rb[p] = cp ? st[kDrb] : P->rb;
-    S.cin[p] = cp ? st[kDcin] : 1.0;
+  if (np > 0) {  // the control points of all particles (contiguous), all threads
+    const DevParticle* last = V.parts + (np - 1);
+    const int nct = last->ctrl0 + last->nc;
     const double* src = slot_ptr(A.ctrlr, sl);
-    for (int i = 0; i < nc; ++i) {
+    for (int e = tid; e < nct; e += blockDim.x) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        S.b[c0 + i][a] = src[4 * (c0 + i) + a];
-        S.bb[c0 + i][a] = V.ctrl[4 * (c0 + i) + a];
+        S.b[e][a] = src[4 * e + a];
+        S.bb[e][a] = V.ctrl[4 * e + a];
       }
-      S.k[c0 + i] = src[4 * (c0 + i) + 3];
+      S.k[e] = src[4 * e + 3];
     }
+  }
+  if (live && main) {
+    S.nc[p] = P->nc;
+    S.c0[p] = P->ctrl0;
+    S.rb[p] = cp ? st[kDrb] : P->rb;
+    S.cin[p] = cp ? st[kDcin] : 1.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       S.c[p][a] = c[a];
@@ -460,26 +469,44 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   // (xnz: the partners whose spring may be nonzero)
   unsigned long long nbr = 0ull, xnz = 0ull;
   const double cstart[3] = {c[0], c[1], c[2]};
-  if (cp && main) {
-    for (int j = 0; j < np; ++j) {
-      if (j == p || !((dmask >> j) & 1ull)) continue;
+  // The two waves share the test: lane p of the first tries the particles
+  // below half of np, lane p of the second (which holds the same centre)
+  // the others.
+  if (cp) {
+    const int half = (np + 1) >> 1;
+    const int j0 = main ? 0 : half, j1 = main ? half : np;
+    const double rbp = S.rb[p];
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
       double dc[3];
-      dem_disp(G, S.c[p], S.c[j], dc);
+      dem_disp(G, c, S.c[j], dc);
       const double r2 = dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2];
-      const double rr = (S.rb[p] + S.rb[j]) + kDemMargin;
+      const double rr = (rbp + S.rb[j]) + kDemMargin;
+      const bool cand = j != p && ((dmask >> j) & 1ull) != 0ull && r2 < rr * rr;
+      nbr |= (unsigned long long)cand << j;
+    }
+    if (!main) S.nbr2[p] = nbr;
+  }
+  __syncthreads();
+  if (cp && main) {
+    nbr |= S.nbr2[p];
+    // Only the springs the previous step may have left nonzero (a superset
+    // kept in xmask) are read: every other one is zero.  A nonzero spring
+    // of a candidate is carried over, one of any other pair cleared.
+    unsigned long long held = A.xmask[p];
+    while (held) {
+      const int j = __ffsll((long long)held) - 1;
+      held &= held - 1ull;
       double* x = A.xi + ((size_t)p * kMaxParticles + j) * 3;
-      const bool nz = x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0;
-      if (r2 < rr * rr) {
-        nbr |= 1ull << j;
-        if (nz) xnz |= 1ull << j;
-      } else if (nz) {
-        x[0] = x[1] = x[2] = 0.0;
-      }
+      if (!(x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0)) continue;
+      if ((nbr >> j) & 1ull) xnz |= 1ull << j;
+      else x[0] = x[1] = x[2] = 0.0;
     }
   }
   unsigned wnz = 0u;  // walls whose spring may be nonzero (bit 2 axis + side)
   if (cp && main)
     for (int k = 0; k < 6; ++k) {
+      if (!G.bc[k >> 1]) continue;  // no wall plane: never written, zero
       const double* x = A.xiw + ((size_t)p * 6 + k) * 3;
       if (x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0) wnz |= 1u << k;
     }
@@ -507,11 +534,15 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     }
   }
   __syncthreads();
+  const unsigned long long needm = __ballot(main && S.need[p] != 0);  // the first wave's flags
   if (tid == 0) {
     int k = 0;
-    for (int i = 0; i < np; ++i)
-      if (S.need[i])
-        for (int m = 0; m < S.nc[i]; ++m) S.work[k++] = ((uint32_t)i << 16) | (uint32_t)(S.c0[i] + m);
+    unsigned long long bits = needm;
+    while (bits) {
+      const int i = __ffsll((long long)bits) - 1;
+      bits &= bits - 1ull;
+      for (int m = 0; m < S.nc[i]; ++m) S.work[k++] = ((uint32_t)i << 16) | (uint32_t)(S.c0[i] + m);
+    }
     S.nwork = k;
   }
   __syncthreads();
@@ -519,10 +550,12 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   const bool need = live && S.need[p] != 0;
   double Rc[3][3];  // rotation of the current q
   dem_quat_R(q, Rc);
+  double cs_next = S.cosv[0];  // the drive of the next substep, read ahead
   for (int s = 0; s < A.nsub; ++s) {
     double F[3], T[3];
+    const double cs = cs_next;
+    if (s + 1 < A.nsub) cs_next = S.cosv[s + 1];
     if (cp && main) {
-      const double cs = S.cosv[s];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         F[a] = (mass * A.g[a] + mass * ((A.drive_amp * cs) * A.drive_dir[a])) + Fh[a];
@@ -683,6 +716,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     __syncthreads();  // the new state is visible to every contact of the next substep
   }
   if (!main) return;
+  if (cp) A.xmask[p] = xnz;  // the springs this step may leave nonzero
   if (cp)  // the translation wave's final centre and velocity
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

@@ -17,6 +17,7 @@ import time
 
 import numpy as np
 
+from . import autotune
 from . import binding as B
 from . import shapes as S
 from . import workloads as W
@@ -59,6 +60,7 @@ def run(shapes, realisations=4, steps=5000, every=50, R=5.0, n_particles=50, n_w
                                                  n_walkers=n_walkers, steps=steps, D=D, precision=precision))
             owner.append(name)
     doms = [B.build_domain(c, device=device) for c in cfgs]
+    autotune.set_batch_streaming(doms, cfgs)
     bt = B.Batch(device=device)
     for d in doms:
         bt.add(d)

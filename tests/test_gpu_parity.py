@@ -500,6 +500,35 @@ def test_batch_equals_alone(B, prec):
 
 
 
+def test_large_batch_streams_between_two_lattices_and_equals_alone(B):
+    """Members whose distributions together exceed the in-place limit (six
+    96^3 FP32 sweep members, 403 MB) are switched to two lattices before
+    their first step; each still equals the same simulation run alone in
+    place, bit for bit (velocity, density, walkers, counters)."""
+    from paper_2308_05007_amd import autotune
+    members = [i for i in range(64) if max(W.config_batch_member(i, steps=8)["domain"]["n"]) == 96][:6]
+    cfgs = [W.config_batch_member(i, steps=8) for i in members]
+    assert autotune.batch_streaming(cfgs) == 1
+    print("members", members, flush=True)
+    bt, doms = autotune.build_batch(cfgs, use_graph=True)
+    bt.step(8)
+    bt.sync()
+    for i in (0, len(cfgs) - 1):
+        a = B.build_domain(cfgs[i])  # alone: 67 MB of distributions, in place
+        a.step(8)
+        a.sync()
+        ua, ra = a.velocity()
+        um, rm = doms[i].velocity()
+        assert np.array_equal(ua, um) and np.array_equal(ra, rm), i
+        for x, y in zip(a.walkers(), doms[i].walkers()):
+            assert np.array_equal(x, y), i
+        assert a.moments()["counters"] == doms[i].moments()["counters"]
+        a.close()
+    bt.close()
+    for d in doms:
+        d.close()
+
+
 def test_destroy_domain_in_batch(B):
     """Destroying a member takes it out of its batch; the others step on
     exactly as they would alone (graph replay before and after)."""

@@ -372,6 +372,43 @@ __device__ __forceinline__ void dem_omega(const double R[3][3], const double* Ib
   for (int a = 0; a < 3; ++a) w[a] = (R[a][0] * z[0] + R[a][1] * z[1]) + R[a][2] * z[2];
 }
 
+// One substep of the rotation: L += T dt, w = R I_b^-1 R^T L, q += dt/2
+// (0, w) q normalised, and R of the new q.
+__device__ __forceinline__ void dem_rotate(const double T[3], double dt, const double* Ibinv, double L[3], double w[3],
+                                           double q[4], double Rc[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) L[a] = L[a] + T[a] * dt;
+  dem_omega(Rc, Ibinv, L, w);
+  const double w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
+  const double hw[3] = {0.5 * dt * w[0], 0.5 * dt * w[1], 0.5 * dt * w[2]};
+  const double n0 = w0 - ((hw[0] * w1 + hw[1] * w2) + hw[2] * w3);
+  const double n1 = w1 + ((hw[0] * w0 + hw[1] * w3) - hw[2] * w2);
+  const double n2 = w2 + ((hw[1] * w0 + hw[2] * w1) - hw[0] * w3);
+  const double n3 = w3 + ((hw[2] * w0 + hw[0] * w2) - hw[1] * w1);
+  const double nn = sqrt(((n0 * n0 + n1 * n1) + n2 * n2) + n3 * n3);
+  q[0] = n0 / nn;
+  q[1] = n1 / nn;
+  q[2] = n2 / nn;
+  q[3] = n3 / nn;
+  dem_quat_R(q, Rc);
+}
+
+// One substep of the translation (symplectic Euler) with the periodic wrap.
+__device__ __forceinline__ void dem_translate(const DemGeom& G, const double F[3], double mass, double dt, double v[3],
+                                              double c[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    v[a] = v[a] + (F[a] / mass) * dt;
+    c[a] = c[a] + v[a] * dt;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (!G.bc[a]) {
+      const double Ln = (double)G.n[a];
+      c[a] = c[a] - Ln * floor(c[a] / Ln);
+    }
+}
+
 // The particle update of step t = tstep + j (t -> t+1).  Launch: one block
 // of 64 threads per domain.
 // Two waves of 64 lanes, lane p of each for particle p: the first finds the
@@ -435,6 +472,7 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
     for (int a = 0; a < 3; ++a) {
       Fh[a] = A.coupling ? (double)(long long)acc[a] / kForceFix : 0.0;
       Th[a] = A.coupling ? (double)(long long)acc[3 + a] / kForceFix : 0.0;
+      S.F[p][a] = Fh[a];  // for the second wave if no substep has contacts
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = 0ull;  // for the next fluid step
@@ -550,93 +588,71 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   const bool need = live && S.need[p] != 0;
   double Rc[3][3];  // rotation of the current q
   dem_quat_R(q, Rc);
-  double cs_next = S.cosv[0];  // the drive of the next substep, read ahead
-  for (int s = 0; s < A.nsub; ++s) {
-    double F[3], T[3];
-    const double cs = cs_next;
-    if (s + 1 < A.nsub) cs_next = S.cosv[s + 1];
-    if (cp && main) {
+  if (nwork == 0 && !G.bc[0] && !G.bc[1] && !G.bc[2]) {
+    // No particle has a contact candidate and there are no wall planes: no
+    // substep reads another particle's state, so each wave runs its chain
+    // of substeps without barriers.  The second wave forms each substep's
+    // force itself, from the terms the first wave would have summed (F_h
+    // it left in S.F); contacts would have added to them, and there are
+    // none.  The operations are those of the loop below, in its order.
+    if (cp && !main) {
+      const double fh[3] = {S.F[p][0], S.F[p][1], S.F[p][2]};
+      for (int s = 0; s < A.nsub; ++s) {
+        const double cs = S.cosv[s];
+        double F[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) F[a] = (mass * A.g[a] + mass * ((A.drive_amp * cs) * A.drive_dir[a])) + fh[a];
+        dem_translate(G, F, mass, dt, v, c);
+      }
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        F[a] = (mass * A.g[a] + mass * ((A.drive_amp * cs) * A.drive_dir[a])) + Fh[a];
-        T[a] = Th[a];
+        S.c[p][a] = c[a];
+        S.v[p][a] = v[a];
       }
-      unsigned long long bits = nbr;
-      while (bits) {
-        const int j = __ffsll((long long)bits) - 1;
-        bits &= bits - 1ull;
-        const int i0 = p < j ? p : j, i1 = p < j ? j : p;
-        double* xi = A.xi + ((size_t)p * kMaxParticles + j) * 3;
-        double xcp[3], n[3], del;
-        if (!dem_contact_pair(G, A, S, i0, i1, xcp, n, del)) {
-          if ((xnz >> j) & 1ull) {
-            xi[0] = xi[1] = xi[2] = 0.0;
-            xnz &= ~(1ull << j);
-          }
-          continue;
-        }
-        double dc[3], rj[3], wa[3], wb[3], vr[3], Fc[3];
-        dem_disp(G, S.c[i0], S.c[i1], dc);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) rj[a] = xcp[a] - dc[a];
-        dem_cross(S.w[i0], xcp, wa);
-        dem_cross(S.w[i1], rj, wb);
+    }
+    if (cp && main)
+      for (int s = 0; s < A.nsub; ++s) dem_rotate(Th, dt, Ibinv, L, w, q, Rc);
+    __syncthreads();  // the final centres and velocities are visible
+  } else {
+    double cs_next = S.cosv[0];  // the drive of the next substep, read ahead
+    for (int s = 0; s < A.nsub; ++s) {
+      double F[3], T[3];
+      const double cs = cs_next;
+      if (s + 1 < A.nsub) cs_next = S.cosv[s + 1];
+      if (cp && main) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const double va = S.v[i0][a] + wa[a];
-          const double vb = S.v[i1][a] + wb[a];
-          vr[a] = vb - va;
+          F[a] = (mass * A.g[a] + mass * ((A.drive_amp * cs) * A.drive_dir[a])) + Fh[a];
+          T[a] = Th[a];
         }
-        double xv[3] = {0.0, 0.0, 0.0};
-        if ((xnz >> j) & 1ull) {
-          xv[0] = xi[0];
-          xv[1] = xi[1];
-          xv[2] = xi[2];
-        }
-        dem_contact_force(A, n, del, vr, dt, xv, Fc);
-        xi[0] = xv[0];
-        xi[1] = xv[1];
-        xi[2] = xv[2];
-        xnz |= 1ull << j;
-        double tq[3];
-        if (p == i1) {
-          dem_cross(rj, Fc, tq);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            F[a] = F[a] + Fc[a];
-            T[a] = T[a] + tq[a];
-          }
-        } else {
-          const double mF[3] = {-Fc[0], -Fc[1], -Fc[2]};
-          dem_cross(xcp, mF, tq);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            F[a] = F[a] + mF[a];
-            T[a] = T[a] + tq[a];
-          }
-        }
-      }
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        if (!G.bc[ax]) continue;
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int k = 2 * ax + side;
-          double* xi = A.xiw + ((size_t)p * 6 + k) * 3;
+        unsigned long long bits = nbr;
+        while (bits) {
+          const int j = __ffsll((long long)bits) - 1;
+          bits &= bits - 1ull;
+          const int i0 = p < j ? p : j, i1 = p < j ? j : p;
+          double* xi = A.xi + ((size_t)p * kMaxParticles + j) * 3;
           double xcp[3], n[3], del;
-          if (!dem_contact_wall(G, A, S, p, ax, side, xcp, n, del)) {
-            if ((wnz >> k) & 1u) {
+          if (!dem_contact_pair(G, A, S, i0, i1, xcp, n, del)) {
+            if ((xnz >> j) & 1ull) {
               xi[0] = xi[1] = xi[2] = 0.0;
-              wnz &= ~(1u << k);
+              xnz &= ~(1ull << j);
             }
             continue;
           }
-          double wa[3], vr[3], Fc[3];
-          dem_cross(S.w[p], xcp, wa);
+          double dc[3], rj[3], wa[3], wb[3], vr[3], Fc[3];
+          dem_disp(G, S.c[i0], S.c[i1], dc);
 #pragma unroll
-          for (int a = 0; a < 3; ++a) vr[a] = S.wu[ax][side][a] - (S.v[p][a] + wa[a]);
+          for (int a = 0; a < 3; ++a) rj[a] = xcp[a] - dc[a];
+          dem_cross(S.w[i0], xcp, wa);
+          dem_cross(S.w[i1], rj, wb);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const double va = S.v[i0][a] + wa[a];
+            const double vb = S.v[i1][a] + wb[a];
+            vr[a] = vb - va;
+          }
           double xv[3] = {0.0, 0.0, 0.0};
-          if ((wnz >> k) & 1u) {
+          if ((xnz >> j) & 1ull) {
             xv[0] = xi[0];
             xv[1] = xi[1];
             xv[2] = xi[2];
@@ -645,75 +661,124 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
           xi[0] = xv[0];
           xi[1] = xv[1];
           xi[2] = xv[2];
-          wnz |= 1u << k;
-          const double mF[3] = {-Fc[0], -Fc[1], -Fc[2]};
+          xnz |= 1ull << j;
           double tq[3];
-          dem_cross(xcp, mF, tq);
+          if (p == i1) {
+            dem_cross(rj, Fc, tq);
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            F[a] = F[a] + mF[a];
-            T[a] = T[a] + tq[a];
+            for (int a = 0; a < 3; ++a) {
+              F[a] = F[a] + Fc[a];
+              T[a] = T[a] + tq[a];
+            }
+          } else {
+            const double mF[3] = {-Fc[0], -Fc[1], -Fc[2]};
+            dem_cross(xcp, mF, tq);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              F[a] = F[a] + mF[a];
+              T[a] = T[a] + tq[a];
+            }
+          }
+        }
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          if (!G.bc[ax]) continue;
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int k = 2 * ax + side;
+            double* xi = A.xiw + ((size_t)p * 6 + k) * 3;
+            double xcp[3], n[3], del;
+            if (!dem_contact_wall(G, A, S, p, ax, side, xcp, n, del)) {
+              if ((wnz >> k) & 1u) {
+                xi[0] = xi[1] = xi[2] = 0.0;
+                wnz &= ~(1u << k);
+              }
+              continue;
+            }
+            double wa[3], vr[3], Fc[3];
+            dem_cross(S.w[p], xcp, wa);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) vr[a] = S.wu[ax][side][a] - (S.v[p][a] + wa[a]);
+            double xv[3] = {0.0, 0.0, 0.0};
+            if ((wnz >> k) & 1u) {
+              xv[0] = xi[0];
+              xv[1] = xi[1];
+              xv[2] = xi[2];
+            }
+            dem_contact_force(A, n, del, vr, dt, xv, Fc);
+            xi[0] = xv[0];
+            xi[1] = xv[1];
+            xi[2] = xv[2];
+            wnz |= 1u << k;
+            const double mF[3] = {-Fc[0], -Fc[1], -Fc[2]};
+            double tq[3];
+            dem_cross(xcp, mF, tq);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              F[a] = F[a] + mF[a];
+              T[a] = T[a] + tq[a];
+            }
           }
         }
       }
-    }
-    if (cp && main)
+      if (cp && main)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) S.F[p][a] = F[a];
-    __syncthreads();  // every contact of the substep has read the shared state
-    if (cp && !main) {  // translation
+        for (int a = 0; a < 3; ++a) S.F[p][a] = F[a];
+      __syncthreads();  // every contact of the substep has read the shared state
+      if (cp && !main) {  // translation
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        v[a] = v[a] + (S.F[p][a] / mass) * dt;
-        c[a] = c[a] + v[a] * dt;
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        if (!G.bc[a]) {
-          const double Ln = (double)G.n[a];
-          c[a] = c[a] - Ln * floor(c[a] / Ln);
+        for (int a = 0; a < 3; ++a) {
+          v[a] = v[a] + (S.F[p][a] / mass) * dt;
+          c[a] = c[a] + v[a] * dt;
         }
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        S.c[p][a] = c[a];
-        S.v[p][a] = v[a];
+        for (int a = 0; a < 3; ++a)
+          if (!G.bc[a]) {
+            const double Ln = (double)G.n[a];
+            c[a] = c[a] - Ln * floor(c[a] / Ln);
+          }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          S.c[p][a] = c[a];
+          S.v[p][a] = v[a];
+        }
       }
-    }
-    if (cp && main) {  // rotation
+      if (cp && main) {  // rotation
 #pragma unroll
-      for (int a = 0; a < 3; ++a) L[a] = L[a] + T[a] * dt;
-      dem_omega(Rc, Ibinv, L, w);
-      const double w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
-      const double hw[3] = {0.5 * dt * w[0], 0.5 * dt * w[1], 0.5 * dt * w[2]};
-      const double n0 = w0 - ((hw[0] * w1 + hw[1] * w2) + hw[2] * w3);
-      const double n1 = w1 + ((hw[0] * w0 + hw[1] * w3) - hw[2] * w2);
-      const double n2 = w2 + ((hw[1] * w0 + hw[2] * w1) - hw[0] * w3);
-      const double n3 = w3 + ((hw[2] * w0 + hw[0] * w2) - hw[1] * w1);
-      const double nn = sqrt(((n0 * n0 + n1 * n1) + n2 * n2) + n3 * n3);
-      q[0] = n0 / nn;
-      q[1] = n1 / nn;
-      q[2] = n2 / nn;
-      q[3] = n3 / nn;
-      dem_quat_R(q, Rc);
-      if (need)
+        for (int a = 0; a < 3; ++a) L[a] = L[a] + T[a] * dt;
+        dem_omega(Rc, Ibinv, L, w);
+        const double w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
+        const double hw[3] = {0.5 * dt * w[0], 0.5 * dt * w[1], 0.5 * dt * w[2]};
+        const double n0 = w0 - ((hw[0] * w1 + hw[1] * w2) + hw[2] * w3);
+        const double n1 = w1 + ((hw[0] * w0 + hw[1] * w3) - hw[2] * w2);
+        const double n2 = w2 + ((hw[1] * w0 + hw[2] * w1) - hw[0] * w3);
+        const double n3 = w3 + ((hw[2] * w0 + hw[0] * w2) - hw[1] * w1);
+        const double nn = sqrt(((n0 * n0 + n1 * n1) + n2 * n2) + n3 * n3);
+        q[0] = n0 / nn;
+        q[1] = n1 / nn;
+        q[2] = n2 / nn;
+        q[3] = n3 / nn;
+        dem_quat_R(q, Rc);
+        if (need)
 #pragma unroll
-        for (int a = 0; a < 9; ++a) S.R[p][a] = Rc[a / 3][a % 3];
+          for (int a = 0; a < 9; ++a) S.R[p][a] = Rc[a / 3][a % 3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) S.w[p][a] = w[a];
-    }
-    if (nwork) {
-      __syncthreads();  // the new rotations are visible
-      // offsets at the new orientation from the body-frame control points
-      for (int k = tid; k < nwork; k += blockDim.x) {
-        const uint32_t e = S.work[k];
-        const double* R = S.R[e >> 16];
-        const int i = (int)(e & 0xFFFFu);
-        const double* bb = S.bb[i];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) S.b[i][a] = (R[3 * a] * bb[0] + R[3 * a + 1] * bb[1]) + R[3 * a + 2] * bb[2];
+        for (int a = 0; a < 3; ++a) S.w[p][a] = w[a];
       }
+      if (nwork) {
+        __syncthreads();  // the new rotations are visible
+        // offsets at the new orientation from the body-frame control points
+        for (int k = tid; k < nwork; k += blockDim.x) {
+          const uint32_t e = S.work[k];
+          const double* R = S.R[e >> 16];
+          const int i = (int)(e & 0xFFFFu);
+          const double* bb = S.bb[i];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) S.b[i][a] = (R[3 * a] * bb[0] + R[3 * a + 1] * bb[1]) + R[3 * a + 2] * bb[2];
+        }
+      }
+      __syncthreads();  // the new state is visible to every contact of the next substep
     }
-    __syncthreads();  // the new state is visible to every contact of the next substep
   }
   if (!main) return;
   if (cp) A.xmask[p] = xnz;  // the springs this step may leave nonzero

@@ -67,6 +67,32 @@ def test_coupled_fp64_bitwise(orc, B, case):
     assert g.moments()["contact_misses"] == 0
 
 
+def test_free_and_candidate_steps_alternate(orc, B):
+    """A pair in a periodic box that starts with no contact candidate (the
+    particle update runs its substeps without barriers), comes within the
+    candidate margin, collides (the synchronised substeps with contacts) and
+    separates again: FP64 states bit for bit with the oracle after every 10
+    steps through all three phases."""
+    cfg = W.config_coupled_small(gap=3.0, speed=0.08, steps=140, n_particles=2)
+    cfg["dem"]["rho_p"] = 20.0  # heavy enough to reach the other through the fluid
+    o, g = _pair(orc, B, cfg)
+    r = sum(W.bounding_radius(p["b"], p["k"]) for p in cfg["particles"])
+    n = np.asarray(cfg["domain"]["n"], float)
+    gaps = []
+    for k in range(14):
+        dc = o.dem_state(1)["c"] - o.dem_state(0)["c"]
+        dc -= n * np.floor(dc / n + 0.5)
+        gaps.append(float(np.linalg.norm(dc)) - r)
+        print("chunk", k, "bounding-sphere gap %.3f" % gaps[-1], flush=True)
+        o.step(10)
+        g.step(10)
+        g.sync()
+        _same_states(o, g, cfg, "chunk %d" % k)
+    compare(o, g)
+    # far (no candidate: the candidate margin is 1), in contact, far again
+    assert gaps[0] > 2.0 and min(gaps) < -1.0 and gaps[-1] > 2.0, gaps
+
+
 def test_coupled_graph_equals_eager(orc, B):
     """130 steps through a captured graph of 128 steps and two eager ones:
     the same bits as the oracle."""

@@ -67,6 +67,7 @@ struct DemLds {
   double wu[3][2][3];       // wall velocities
   double c[kMaxParticles][3], v[kMaxParticles][3], w[kMaxParticles][3];
   double rb[kMaxParticles], cin[kMaxParticles];
+  float cf[kMaxParticles][4];  // centre and bounding radius in float: the candidate prefilter
   int nc[kMaxParticles], c0[kMaxParticles];
   double b[kDemMaxCtrl][3];   // offsets at the current orientation
   double bb[kDemMaxCtrl][3];  // offsets in the body frame
@@ -500,7 +501,9 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
       S.c[p][a] = c[a];
       S.v[p][a] = v[a];
       S.w[p][a] = w[a];
+      S.cf[p][a] = (float)c[a];
     }
+    S.cf[p][3] = (float)S.rb[p];
   }
   __syncthreads();
   // candidate partners of the step; the springs of every other pair are zero
@@ -510,17 +513,45 @@ __device__ __forceinline__ void dem_block(const DomView& V, const DemArgs& A, ui
   // The two waves share the test: lane p of the first tries the particles
   // below half of np, lane p of the second (which holds the same centre)
   // the others.
+  // Each pair is first measured in float.  With every lattice edge at most
+  // 4096 the float distance of the centres' nearest images is within about
+  // 1.2e-3 of the exact one (positions rounded to 2^-12, their differences
+  // and squares to 2^-24 relative), and near half a period both images are
+  // about as long; so a float gap more than 0.01 from the candidate
+  // threshold decides the FP64 test's outcome, and only pairs closer to the
+  // threshold (or on larger lattices) take that test.
   if (cp) {
     const int half = (np + 1) >> 1;
     const int j0 = main ? 0 : half, j1 = main ? half : np;
     const double rbp = S.rb[p];
+    const float cpf[3] = {S.cf[p][0], S.cf[p][1], S.cf[p][2]};
+    const float rbpf = S.cf[p][3];
+    const float Lf[3] = {(float)G.n[0], (float)G.n[1], (float)G.n[2]};
+    const float band = (G.n[0] <= 4096 && G.n[1] <= 4096 && G.n[2] <= 4096) ? 0.01f : 3.4e38f;
 #pragma unroll 4
     for (int j = j0; j < j1; ++j) {
-      double dc[3];
-      dem_disp(G, c, S.c[j], dc);
-      const double r2 = dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2];
-      const double rr = (rbp + S.rb[j]) + kDemMargin;
-      const bool cand = j != p && ((dmask >> j) & 1ull) != 0ull && r2 < rr * rr;
+      float d2 = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float d = S.cf[j][a] - cpf[a];
+        if (!G.bc[a]) {
+          d = fabsf(d);
+          d = d > 0.5f * Lf[a] ? Lf[a] - d : d;
+        }
+        d2 += d * d;
+      }
+      const float gap = __builtin_sqrtf(d2) - ((rbpf + S.cf[j][3]) + (float)kDemMargin);
+      bool cand;
+      if (gap > band) cand = false;
+      else if (gap < -band) cand = true;
+      else {
+        double dc[3];
+        dem_disp(G, c, S.c[j], dc);
+        const double r2 = dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2];
+        const double rr = (rbp + S.rb[j]) + kDemMargin;
+        cand = r2 < rr * rr;
+      }
+      cand = cand && j != p && ((dmask >> j) & 1ull) != 0ull;
       nbr |= (unsigned long long)cand << j;
     }
     if (!main) S.nbr2[p] = nbr;

@@ -110,6 +110,16 @@ def pmc_traffic(workload_key, prec):
     return e.get("hbm_bytes_per_launch"), e.get("algorithmic_bytes_per_launch")
 
 
+def _traffic_keys(workload_key, prec):
+    """HBM traffic of a secondary workload's step launch from the committed
+    counter summary (as for the headline), when there is one for the current
+    kernel source."""
+    traffic, alg = pmc_traffic(workload_key, prec)
+    if not traffic or not alg:
+        return {}
+    return {"traffic": traffic, "traffic_over_algorithmic": round(traffic / alg, 4)}
+
+
 def _oracle_sample(cfg, seconds, max_steps, threads):
     """Steps of the FP64 oracle on the workload (seeding excluded) with the
     given number of threads: at least one, then as many as fit in `seconds`."""
@@ -260,6 +270,7 @@ def bench_plain(args):
             c2 = W.config_oscillator(precision=p2, n_walkers=args.walkers or 10_000_000)
             q = measure(c2, "oscillator_256_" + p2, s2, w2, args.timing_every, burnin=burnin_steps(c2, args))
             sec[q["key"]] = {"MLUPS": round(q["mlups"], 1), "walker_steps_per_s": round(q["wsps"], 1),
+                             **_traffic_keys(q["key"], p2),
                              "ms_per_step": round(q["dt"] / s2 * 1e3, 5), "roofline_frac": round(q["achieved"] / HBM_PEAK_GBS, 4),
                              "bytes_per_launch": q["bytes_launch"], "avg_launch_us": round(q["avg_us"], 2),
                              "steps": s2, "warmup": w2, "timed_from_step": q["burnin"] + w2}
@@ -276,6 +287,7 @@ def bench_plain(args):
         c4["domain"]["coupling"] = "ibb"
         q = measure(c4, "oscillator_256_fp32_ibb", s2, w2, args.timing_every, burnin=burnin_steps(c4, args))
         sec[q["key"]] = {"MLUPS": round(q["mlups"], 1), "walker_steps_per_s": round(q["wsps"], 1),
+                         **_traffic_keys(q["key"], "fp32"),
                          "ms_per_step": round(q["dt"] / s2 * 1e3, 5), "roofline_frac": round(q["achieved"] / HBM_PEAK_GBS, 4),
                          "bytes_per_launch": q["bytes_launch"], "avg_launch_us": round(q["avg_us"], 2),
                          "steps": s2, "warmup": w2, "timed_from_step": q["burnin"] + w2,
